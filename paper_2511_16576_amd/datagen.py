@@ -1,0 +1,309 @@
+"""Seeded synthetic polygon workloads.
+
+This module only produces inputs: integer-grid star-shaped simple polygons,
+jittered copies and near-duplicate clusters, with the sizes and distributions
+of the five workloads below.  It holds none of PolyMinHash's arithmetic (no
+point stream, no point-in-polygon test, no hashing, no areas), so both the
+CPU oracle and the GPU path can be fed from it.
+
+Polygons are returned in CSR form: ``xy`` int32[V, 2] holds vertices (x, y)
+and polygon p is ``xy[offsets[p]:offsets[p+1]]``; the ring is implicitly
+closed and every polygon is counter-clockwise, star-shaped about its integer
+centre and simple.
+
+Workloads (all on a W x W integer grid, sampling box [0, W-1]^2, hash seed 0):
+
+1. W=2^20, N=1,000, n ~ U{8..32}, R ~ U(0.05, 0.20) W, k=64, cap 2^20,
+   16 bands x 4 rows, 10 queries that are 2%-jittered copies.
+2. W=2^24, N=100,000, n = clip(round(LogNormal(ln 48, 1.0)), 8, 512),
+   R ~ U(0.02, 0.15) W, k=128, cap 2^22.
+3. W=2^20, N=1,000,000, n = clip(round(LogNormal(ln 48, 1.0)), 8, 1024),
+   R ~ U(0.05, 0.20) W, 20% of polygons in near-duplicate clusters of size
+   U{2..10} with per-cluster noise U[1%, 5%] of R, k=256, 32 x 8,
+   1,000 queries (2% jitter).
+4. pairs mined from workload 2's polygons (signed at k=256).
+5. W=2^24, N=4,000,000, n = clip(round(8 (1 + Lomax(1.5))), 8, 8192),
+   R ~ U(0.005, 0.03) W, k=256, cap 2^26, 32 x 8, 10,000 queries.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+@dataclasses.dataclass
+class PolySet:
+    xy: np.ndarray        # int32 [V, 2]
+    offsets: np.ndarray   # int64 [N + 1]
+    centre: np.ndarray    # int64 [N, 2]  (star centre of each polygon)
+    radius: np.ndarray    # float64 [N]   (outer radius R used to draw it)
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    def counts(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def poly(self, p: int) -> np.ndarray:
+        return self.xy[self.offsets[p]:self.offsets[p + 1]]
+
+    def subset(self, ids) -> "PolySet":
+        ids = np.asarray(ids, dtype=np.int64)
+        cnt = self.counts()[ids]
+        off = np.zeros(ids.shape[0] + 1, dtype=np.int64)
+        np.cumsum(cnt, out=off[1:])
+        src = np.repeat(self.offsets[ids], cnt) + (np.arange(off[-1]) - np.repeat(off[:-1], cnt))
+        return PolySet(np.ascontiguousarray(self.xy[src]), off, self.centre[ids].copy(),
+                       self.radius[ids].copy())
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    grid_bits: int
+    data: PolySet
+    queries: PolySet | None
+    query_source: np.ndarray | None   # dataset id each query was jittered from
+    k: int
+    cap: int
+    bands: int
+    rows: int
+    seed: int = 0
+    cluster: np.ndarray | None = None  # cluster id per dataset polygon (-1 = none)
+
+    @property
+    def box(self):
+        w = 1 << self.grid_bits
+        return (0, 0, w - 1, w - 1)
+
+
+def _segments(counts: np.ndarray):
+    off = np.zeros(counts.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    pid = np.repeat(np.arange(counts.shape[0], dtype=np.int64), counts)
+    return off, pid
+
+
+def _star_angles(rng, counts):
+    """Sorted angles per polygon, redrawn until every gap is below pi."""
+    off, pid = _segments(counts)
+    ang = np.empty(off[-1])
+    todo = np.arange(counts.shape[0])
+    while todo.size:
+        sub_cnt = counts[todo]
+        sub_off, sub_pid = _segments(sub_cnt)
+        a = rng.random(sub_off[-1]) * TWO_PI
+        a = a[np.lexsort((a, sub_pid))]
+        nxt = np.empty_like(a)
+        nxt[:-1] = a[1:]
+        last = sub_off[1:] - 1
+        gaps = nxt - a
+        gaps[last] = a[sub_off[:-1]] + TWO_PI - a[last]
+        bad = np.maximum.reduceat(gaps, sub_off[:-1]) >= math.pi
+        dst = np.repeat(off[todo], sub_cnt) + (np.arange(sub_off[-1]) - np.repeat(sub_off[:-1], sub_cnt))
+        ang[dst] = a
+        todo = todo[bad]
+    return ang
+
+
+def _star_valid(xy: np.ndarray, counts: np.ndarray, centre: np.ndarray) -> np.ndarray:
+    """Generator validity: every edge turns strictly counter-clockwise about the
+    centre and the ring winds once around it.  This makes the polygon simple
+    and star-shaped about its centre (input recipe only)."""
+    off, pid = _segments(counts)
+    v = xy.astype(np.int64)
+    nxt_idx = np.arange(off[-1]) + 1
+    nxt_idx[off[1:] - 1] = off[:-1]
+    c = centre[pid]
+    a = v - c
+    b = v[nxt_idx] - c
+    cr = a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]
+    ok = np.minimum.reduceat(cr, off[:-1]) > 0
+    turn = np.arctan2(cr.astype(np.float64), (a * b).sum(axis=1).astype(np.float64))
+    wind = np.add.reduceat(turn, off[:-1])
+    ok &= np.abs(wind - TWO_PI) < 1e-6
+    return ok
+
+
+def star_polygons(rng, counts, centres, radii) -> PolySet:
+    """Star-shaped simple polygons: sorted angles (max gap < pi), radii
+    U[0.5R, R], vertices rounded to the grid; invalid ones are redrawn."""
+    counts = np.asarray(counts, dtype=np.int64)
+    centres = np.asarray(centres, dtype=np.int64)
+    radii = np.asarray(radii, dtype=np.float64)
+    off, pid = _segments(counts)
+    xy = np.empty((off[-1], 2), dtype=np.int64)
+    todo = np.arange(counts.shape[0])
+    while todo.size:
+        sub_cnt = counts[todo]
+        sub_off, sub_pid = _segments(sub_cnt)
+        ang = _star_angles(rng, sub_cnt)
+        rad = rng.uniform(0.5, 1.0, sub_off[-1]) * radii[todo][sub_pid]
+        c = centres[todo][sub_pid]
+        sx = np.rint(c[:, 0] + rad * np.cos(ang)).astype(np.int64)
+        sy = np.rint(c[:, 1] + rad * np.sin(ang)).astype(np.int64)
+        sub_xy = np.stack([sx, sy], axis=1)
+        ok = _star_valid(sub_xy, sub_cnt, centres[todo])
+        dst = np.repeat(off[todo], sub_cnt) + (np.arange(sub_off[-1]) - np.repeat(sub_off[:-1], sub_cnt))
+        xy[dst] = sub_xy
+        todo = todo[~ok]
+    return PolySet(xy.astype(np.int32), off, centres.copy(), radii.copy())
+
+
+def _edge_ok(xy: np.ndarray, counts: np.ndarray, centre: np.ndarray) -> np.ndarray:
+    """Per-edge generator check: edge v_i -> v_{i+1} turns strictly
+    counter-clockwise about the polygon's centre (input recipe only)."""
+    off, pid = _segments(counts)
+    v = xy.astype(np.int64)
+    nxt_idx = np.arange(off[-1]) + 1
+    nxt_idx[off[1:] - 1] = off[:-1]
+    c = centre[pid]
+    a = v - c
+    b = v[nxt_idx] - c
+    return (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]) > 0, nxt_idx
+
+
+def jittered(rng, base: PolySet, ids, noise, grid_bits: int, max_rounds: int = 64) -> PolySet:
+    """Copies of base polygons ``ids`` with every coordinate moved by
+    round(U[-d, d]), d = noise * R, clipped to the grid.  The two vertices of
+    any edge that stops turning counter-clockwise about the source centre are
+    redrawn, so the copy stays star-shaped and simple; a copy still invalid
+    after ``max_rounds`` keeps its source vertices."""
+    ids = np.asarray(ids, dtype=np.int64)
+    noise = np.broadcast_to(np.asarray(noise, dtype=np.float64), ids.shape)
+    src = base.subset(ids)
+    counts = src.counts()
+    off, pid = _segments(counts)
+    hi = (1 << grid_bits) - 1
+    orig = src.xy.astype(np.int64)
+    d = (noise * src.radius)[pid]
+    out = orig.copy()
+    redo = np.arange(off[-1])
+    for _ in range(max_rounds):
+        if redo.size == 0:
+            break
+        j = np.rint(rng.uniform(-1.0, 1.0, (redo.size, 2)) * d[redo][:, None]).astype(np.int64)
+        out[redo] = np.clip(orig[redo] + j, 0, hi)
+        ok, nxt = _edge_ok(out, counts, src.centre)
+        bad = np.flatnonzero(~ok)
+        redo = np.unique(np.concatenate([bad, nxt[bad]]))
+    stuck = ~_star_valid(out, counts, src.centre)
+    if stuck.any():   # rare: such copies keep their source vertices
+        rows = np.flatnonzero(stuck[pid])
+        out[rows] = orig[rows]
+    return PolySet(out.astype(np.int32), off, src.centre.copy(), src.radius.copy())
+
+
+def _centres(rng, radii, grid_bits):
+    w = 1 << grid_bits
+    m = np.ceil(radii).astype(np.int64)
+    lo = m
+    hi = (w - 1) - m
+    cx = lo + np.floor(rng.random(radii.shape[0]) * (hi - lo + 1)).astype(np.int64)
+    cy = lo + np.floor(rng.random(radii.shape[0]) * (hi - lo + 1)).astype(np.int64)
+    return np.stack([cx, cy], axis=1)
+
+
+def _lognormal_counts(rng, n, cap):
+    return np.clip(np.rint(np.exp(rng.normal(math.log(48.0), 1.0, n))), 8, cap).astype(np.int64)
+
+
+def random_polygons(rng, n, grid_bits, count_fn, rfrac_lo, rfrac_hi) -> PolySet:
+    w = float(1 << grid_bits)
+    counts = count_fn(rng, n)
+    radii = rng.uniform(rfrac_lo, rfrac_hi, n) * w
+    centres = _centres(rng, radii, grid_bits)
+    return star_polygons(rng, counts, centres, radii)
+
+
+def concat(sets) -> PolySet:
+    xs = [s.xy for s in sets]
+    offs = [s.counts() for s in sets]
+    counts = np.concatenate(offs)
+    off = np.zeros(counts.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    return PolySet(np.concatenate(xs), off, np.concatenate([s.centre for s in sets]),
+                   np.concatenate([s.radius for s in sets]))
+
+
+def _rng(cfg: int, stream: int = 0):
+    return np.random.default_rng(np.random.SeedSequence([cfg, stream]))
+
+
+def workload(cfg: int, n: int | None = None, n_queries: int | None = None) -> Workload:
+    """Build workload ``cfg`` (1, 2, 3 or 5).  ``n`` / ``n_queries`` shrink it
+    (same distributions, fewer polygons) for tests and bounded samples."""
+    rng = _rng(cfg)
+    if cfg == 1:
+        N = 1000 if n is None else n
+        Q = 10 if n_queries is None else n_queries
+        data = random_polygons(rng, N, 20, lambda r, m: r.integers(8, 33, m), 0.05, 0.20)
+        src = rng.integers(0, N, Q)
+        q = jittered(rng, data, src, 0.02, 20)
+        return Workload("cfg1", 20, data, q, src, k=64, cap=1 << 20, bands=16, rows=4)
+    if cfg == 2:
+        N = 100_000 if n is None else n
+        Q = 10_000 if n_queries is None else n_queries
+        data = random_polygons(rng, N, 24, lambda r, m: _lognormal_counts(r, m, 512), 0.02, 0.15)
+        src = rng.integers(0, N, Q)
+        q = jittered(rng, data, src, 0.02, 24)
+        return Workload("cfg2", 24, data, q, src, k=128, cap=1 << 22, bands=32, rows=4)
+    if cfg == 3:
+        N = 1_000_000 if n is None else n
+        Q = 1000 if n_queries is None else n_queries
+        n_clu_target = int(round(0.2 * N))
+        sizes = []
+        while sum(sizes) < n_clu_target:
+            sizes.append(int(rng.integers(2, 11)))
+        sizes[-1] -= sum(sizes) - n_clu_target
+        if sizes and sizes[-1] < 1:
+            sizes.pop()
+        sizes = np.asarray(sizes, dtype=np.int64)
+        n_base = N - int(sizes.sum()) + sizes.shape[0]
+        base = random_polygons(rng, n_base, 20, lambda r, m: _lognormal_counts(r, m, 1024), 0.05, 0.20)
+        # the first len(sizes) base polygons seed the clusters
+        members = np.repeat(np.arange(sizes.shape[0]), sizes - 1)
+        noise = rng.uniform(0.01, 0.05, sizes.shape[0])[members]
+        copies = jittered(rng, base, members, noise, 20)
+        data = concat([base, copies])
+        cluster = np.concatenate([np.where(np.arange(n_base) < sizes.shape[0], np.arange(n_base), -1),
+                                  members])
+        perm = rng.permutation(data.n)
+        data = data.subset(perm)
+        cluster = cluster[perm]
+        src = rng.integers(0, data.n, Q)
+        q = jittered(rng, data, src, 0.02, 20)
+        return Workload("cfg3", 20, data, q, src, k=256, cap=1 << 20, bands=32, rows=8, cluster=cluster)
+    if cfg == 5:
+        N = 4_000_000 if n is None else n
+        Q = 10_000 if n_queries is None else n_queries
+
+        def pareto_counts(r, m):
+            return np.clip(np.rint(8.0 * (1.0 + r.pareto(1.5, m))), 8, 8192).astype(np.int64)
+        data = random_polygons(rng, N, 24, pareto_counts, 0.005, 0.03)
+        src = rng.integers(0, N, Q)
+        q = jittered(rng, data, src, 0.02, 24)
+        return Workload("cfg5", 24, data, q, src, k=256, cap=1 << 26, bands=32, rows=8)
+    raise ValueError(f"no workload {cfg}")
+
+
+def rectangle(x0, y0, x1, y1) -> np.ndarray:
+    """Counter-clockwise axis-aligned rectangle with corners (x0,y0), (x1,y1)."""
+    return np.array([[x0, y0], [x1, y0], [x1, y1], [x0, y1]], dtype=np.int32)
+
+
+def from_list(polys) -> PolySet:
+    """CSR PolySet from a list of (n_i, 2) integer arrays."""
+    polys = [np.asarray(p, dtype=np.int32).reshape(-1, 2) for p in polys]
+    counts = np.array([p.shape[0] for p in polys], dtype=np.int64)
+    off = np.zeros(len(polys) + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    xy = np.concatenate(polys) if polys else np.zeros((0, 2), dtype=np.int32)
+    cen = np.array([p.mean(axis=0) if p.shape[0] else (0, 0) for p in polys], dtype=np.int64).reshape(-1, 2)
+    return PolySet(np.ascontiguousarray(xy, dtype=np.int32), off, cen,
+                   np.zeros(len(polys), dtype=np.float64))
