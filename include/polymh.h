@@ -1,0 +1,211 @@
+/*
+ * polymh.h -- C ABI of libpolymh, a gfx950 (MI355X) implementation of the
+ * PolyMinHash signing and search path (Subedi, Pokharel, Puri,
+ * "PolyMinHash: Efficient Area-Based MinHashing of Polygons for Approximate
+ * Nearest Neighbor Search", SIGSPATIAL'25, arXiv 2511.16576).
+ *
+ * Conventions for every call below:
+ *  - Array arguments are DEVICE pointers (memory of the current HIP device)
+ *    unless the comment says "host".  The caller owns every buffer; the
+ *    library keeps no pointer after a call returns and never allocates or
+ *    frees device memory inside these calls (scratch comes from caller
+ *    workspaces sized by the *_workspace_size functions).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *    stream-ordered: they enqueue work and return; buffers must stay alive
+ *    until the stream has passed the call.  Calls that synchronise say so.
+ *  - Scalar arguments are validated before anything is enqueued; a failed
+ *    validation returns a negative status and enqueues nothing.  A failed
+ *    kernel launch returns POLYMH_EDEVICE.  polymh_last_error() gives the
+ *    calling thread's text for the last failure.
+ *  - Polygons are CSR: polygon p has vertices xy[2*offsets[p] ..
+ *    2*offsets[p+1]) as interleaved int32 (x, y) pairs, the ring implicitly
+ *    closed (no repeated closing vertex), either orientation.  The method
+ *    treats a polygon as the set of lattice points its crossing-number test
+ *    accepts (see polymh_sign).
+ */
+#ifndef POLYMH_H
+#define POLYMH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t polymh_status;
+#define POLYMH_OK 0
+#define POLYMH_EINVAL (-1)    /* null pointer, bad size or count          */
+#define POLYMH_ERANGE (-2)    /* empty or inverted sampling box           */
+#define POLYMH_EDEVICE (-3)   /* HIP launch or runtime error              */
+#define POLYMH_ECAPACITY (-4) /* a caller buffer or workspace is too small */
+#define POLYMH_ENOTSUP (-5)   /* current device is not gfx950             */
+
+/* Text of the calling thread's last failure ("" if none).  Host string owned
+ * by the library, valid until the thread's next failing call. */
+const char *polymh_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int32_t polymh_version(void);
+
+/* Checks that the current HIP device is a gfx950; POLYMH_ENOTSUP if not.
+ * Synchronous (queries device properties). */
+polymh_status polymh_check_device(void);
+
+/* Inclusive lattice box [xmin, xmax] x [ymin, ymax]: the global MBR B of
+ * Sec. 3.1 that every hash samples (Sec. 3.2).  Requires xmin <= xmax and
+ * ymin <= ymax. */
+typedef struct {
+    int32_t xmin, ymin, xmax, ymax;
+} polymh_box;
+
+/* n CSR polygons (device pointers): offsets has n + 1 entries, offsets[0] = 0,
+ * non-decreasing; xy has 2 * offsets[n] entries. */
+typedef struct {
+    const int32_t *xy;
+    const int64_t *offsets;
+    int64_t n;
+} polymh_polys;
+
+/* ---------------------------------------------------------------------------
+ * polymh_prepare -- per-polygon staging (Sec. 3.1 "global MBR" preprocessing
+ * and Alg. 1's "compute local MBR of P").
+ *   mbr   [n][4] int32 out: (xmin, ymin, xmax, ymax) of polygon p's vertices
+ *                 (all zero for a polygon with no vertex).
+ *   area2 [n]    int64 out (nullable): twice the signed shoelace area, exact.
+ *   flags [n]    uint32 out (nullable): bit 0 = fewer than 3 vertices, bit 1 =
+ *                 all vertices collinear (empty interior), bit 2 = MBR wider
+ *                 or taller than 2^26 (signing then uses 128-bit integer
+ *                 orientation instead of exact FP64).
+ * Stream-ordered. */
+polymh_status polymh_prepare(const polymh_polys *polys, int32_t *mbr, int64_t *area2,
+                             uint32_t *flags, void *stream);
+
+/* polymh_box_of -- the global MBR of all vertices of `polys` (Sec. 3.1),
+ * written to *out_host.  `ws` must hold polymh_box_of_workspace_size() bytes.
+ * SYNCHRONISES the stream.  POLYMH_EINVAL if the set has no vertex. */
+size_t polymh_box_of_workspace_size(void);
+polymh_status polymh_box_of(const polymh_polys *polys, void *ws, size_t ws_bytes,
+                            polymh_box *out_host, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * polymh_sign -- Alg. 1 / Def. 2: the MinHash signature of every polygon.
+ *
+ *   sig[p*k + i] (uint32, [n][k]) = the 1-based index of the first sample of
+ *   stream i that lands inside polygon p, or 0 if none of the first `cap`
+ *   samples does (Alg. 1's initial value; the paper's loop has no cap).
+ *
+ *   Stream i (Sec. 3.2's fixed-seed generators; SplitMix64 of Steele, Lea and
+ *   Flood): key_i = mix64(seed + (i+1)*G) and sample j >= 0 is the lattice
+ *   point of r = mix64(key_i + (j+1)*G), G = 0x9E3779B97F4A7C15,
+ *     x = B.xmin + ((r >> 32) * Wx >> 32),  y = B.ymin + ((r & 0xffffffff) * Wy >> 32),
+ *   Wx = B.xmax - B.xmin + 1, Wy likewise (products in 64-bit unsigned).
+ *   Every polygon walks the same streams (required by Thm. 1).
+ *
+ *   A sample outside the polygon's MBR is rejected (Alg. 1's MBR check), else
+ *   it is inside iff the crossing-number test accepts it: edge (x0,y0)->(x1,y1)
+ *   counts iff (y0 > y) != (y1 > y) and o = (x1-x0)(y-y0) - (x-x0)(y1-y0) has
+ *   the sign of y1 - y0 (exact); an odd count is inside.  A boundary point is
+ *   thus inside iff it is inside after an infinitesimal move up and right.
+ *   Polygons with < 3 vertices or collinear vertices have no interior and get
+ *   all-zero rows.
+ *
+ *   k >= 1, cap >= 1, n >= 0 (n = 0 is a no-op).  `ws` must hold
+ *   polymh_sign_workspace_size(n, cfg) bytes; its contents are scratch.
+ *   `cfg` (host, nullable = defaults) selects the launch shape; every shape
+ *   gives the same bits.  Stream-ordered.
+ */
+typedef struct {
+    int32_t persistent;       /* 1: one persistent launch popping (polygon, hash
+                                 block) items longest-expected-first from a
+                                 device queue; 0: one workgroup per item.   */
+    int32_t block_threads;    /* 64..1024, multiple of 64                     */
+    int32_t hash_block;       /* hashes per work item (1..k; 0 = all k)       */
+    int32_t lds_edges;        /* polygons with more edges stream them from
+                                 global memory instead of LDS (64..8192)     */
+    int32_t samples_per_lane; /* 1 or 2 draws per lane per tile step          */
+    int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CU count   */
+} polymh_sign_config;
+
+void polymh_sign_default_config(polymh_sign_config *cfg_host);
+size_t polymh_sign_workspace_size(int64_t n, const polymh_sign_config *cfg_host);
+polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                          uint32_t cap, uint32_t *sig, const polymh_sign_config *cfg_host,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * polymh_band -- LSH band keys over the signatures (Sec. 3.2 puts polygons in
+ * a hashmap keyed by their MinHash code; the banded form follows the MMDS
+ * banding technique the paper cites).
+ *   keys[p*b + t] (uint64, [n][b]): F_0 = mix64(band_seed + (t+1)*G),
+ *   F_{u+1} = mix64(F_u XOR sig[p*k + t*r + u]) for u < r, key = F_r.
+ *   Requires b >= 1, r >= 1, b*r <= k.  Stream-ordered.
+ */
+polymh_status polymh_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,
+                          uint64_t band_seed, uint64_t *keys, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * polymh_index_build -- the bucket table of Sec. 3.2's hashmap: all n*b
+ * (band key, entry) pairs, entry = p*b + t for band t of polygon p, sorted by
+ * key (ties by ascending entry, i.e. stable), so that one key's bucket is a
+ * contiguous range; polymh_query keeps only entries of the query's band.
+ *   sorted_keys [n*b] uint64 out, sorted_ids [n*b] int32 out (entry index).
+ *   Requires n*b < 2^31.  ws: polymh_index_workspace_size(n, b) bytes of
+ *   scratch.  Stream-ordered.
+ */
+size_t polymh_index_workspace_size(int64_t n, int32_t b);
+polymh_status polymh_index_build(const uint64_t *keys, int64_t n, int32_t b, void *ws,
+                                 size_t ws_bytes, uint64_t *sorted_keys, int32_t *sorted_ids,
+                                 void *stream);
+
+/* ---------------------------------------------------------------------------
+ * polymh_query -- candidate generation: for query q, every dataset polygon p
+ * that shares at least one band key with it (key_t(p) == qkeys[q*b + t] for
+ * some band t), deduplicated, ascending id.  Two phases:
+ *   cand_ids == NULL: count phase; writes cand_off[0..nq] (exclusive prefix
+ *     of the per-query counts, int64) and nothing else.
+ *   cand_ids != NULL: fill phase with the cand_off of the count phase (the
+ *     same inputs); writes cand_ids[cand_off[q] .. cand_off[q+1]).
+ *     cand_cap is the capacity of cand_ids; if cand_off[nq] > cand_cap the
+ *     call returns POLYMH_ECAPACITY after a SYNCHRONOUS read of cand_off[nq];
+ *     pass cand_cap < 0 to skip that read (the caller guarantees capacity).
+ *   n_data is the number of indexed polygons (ids are < n_data).
+ *   ws: polymh_query_workspace_size(n_data, nq) bytes.  Stream-ordered
+ *   except the capacity check above.
+ */
+size_t polymh_query_workspace_size(int64_t n_data, int64_t nq);
+polymh_status polymh_query(const uint64_t *sorted_keys, const int32_t *sorted_ids,
+                           int64_t n_entries, int64_t n_data, const uint64_t *qkeys, int64_t nq,
+                           int32_t b, void *ws, size_t ws_bytes, int64_t *cand_off,
+                           int32_t *cand_ids, int64_t cand_cap, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * polymh_refine -- exact Jaccard of each candidate pair (Sec. 1: area of the
+ * intersection over area of the union; Table 2's refinement phase).
+ *   cand_j[c] (double) = J(data[cand_ids[c]], queries[q]) for
+ *   cand_off[q] <= c < cand_off[q+1].  Intersection area by Green's theorem
+ *   over the two boundaries split at their crossings, with exact orientation
+ *   predicates under a consistent symbolic perturbation; FP64 accumulation
+ *   relative to a local origin.  Disjoint MBRs give 0 without clipping.
+ *   Relative error of the area is about 1e-13 or better for the workloads'
+ *   sizes.  Stream-ordered.
+ */
+polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *queries,
+                            const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                            int64_t n_cand, double *cand_j, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * polymh_topk -- Def. 1 / K-ANN: per query the `topk` candidates with the
+ * largest J, ties by ascending id; rows padded with id -1 and J 0.
+ *   top_ids [nq][topk] int32 out, top_j [nq][topk] double out.
+ *   1 <= topk <= 64.  Stream-ordered.
+ */
+polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, const double *cand_j,
+                          int64_t nq, int32_t topk, int32_t *top_ids, double *top_j,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYMH_H */

@@ -1,0 +1,322 @@
+// Host side of the libpolymh C ABI: argument validation, workspace carving,
+// launch-shape defaults and error reporting.  Every computation is a kernel
+// launch on the caller's stream; nothing here touches polygon data.
+#include "internal.hpp"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+namespace polymh {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+polymh_status set_error(polymh_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+polymh_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(POLYMH_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return POLYMH_OK;
+}
+
+int cu_count()
+{
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cache[dev] = c;
+    }
+    return cache[dev];
+}
+
+}  // namespace polymh
+
+using namespace polymh;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+polymh_status check_polys(const polymh_polys *p, const char *what)
+{
+    if (!p) return set_error(POLYMH_EINVAL, "%s: polygon set is NULL", what);
+    if (p->n < 0) return set_error(POLYMH_EINVAL, "%s: negative polygon count", what);
+    if (p->n > 0 && (!p->xy || !p->offsets))
+        return set_error(POLYMH_EINVAL, "%s: NULL vertex or offset array", what);
+    if (p->n > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "%s: more than 2^31-1 polygons", what);
+    return POLYMH_OK;
+}
+
+polymh_status check_box(const polymh_box &b, const char *what)
+{
+    if (b.xmin > b.xmax || b.ymin > b.ymax)
+        return set_error(POLYMH_ERANGE, "%s: empty sampling box [%d,%d]x[%d,%d]", what, b.xmin,
+                         b.xmax, b.ymin, b.ymax);
+    return POLYMH_OK;
+}
+
+polymh_status check_sign_config(const polymh_sign_config &c)
+{
+    if (c.block_threads < 64 || c.block_threads > 512 || c.block_threads % 64)
+        return set_error(POLYMH_EINVAL, "sign: block_threads must be 64..512, a multiple of 64");
+    if (c.hash_block < 0) return set_error(POLYMH_EINVAL, "sign: negative hash_block");
+    if (c.lds_edges < 64 || c.lds_edges > 8192)
+        return set_error(POLYMH_EINVAL, "sign: lds_edges must be 64..8192");
+    if (c.samples_per_lane != 1 && c.samples_per_lane != 2)
+        return set_error(POLYMH_EINVAL, "sign: samples_per_lane must be 1 or 2");
+    if (c.persistent && (c.blocks_per_cu < 1 || c.blocks_per_cu > 64))
+        return set_error(POLYMH_EINVAL, "sign: blocks_per_cu must be 1..64");
+    return POLYMH_OK;
+}
+
+struct SignWs {
+    unsigned long long *queue;
+    int32_t *mbr;
+    int64_t *area2;
+    uint32_t *flags;
+    int32_t *counts;
+    int32_t *order;
+};
+
+SignWs carve_sign(Carve &c, int64_t n, bool persistent)
+{
+    SignWs w{};
+    w.queue = c.take<unsigned long long>(1);
+    w.mbr = c.take<int32_t>((size_t)n * 4);
+    w.area2 = c.take<int64_t>((size_t)n);
+    w.flags = c.take<uint32_t>((size_t)n);
+    if (persistent) {
+        w.counts = c.take<int32_t>(128);
+        w.order = c.take<int32_t>((size_t)n);
+    }
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *polymh_last_error(void) { return g_err; }
+
+int32_t polymh_version(void) { return 100; }
+
+polymh_status polymh_check_device(void)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "check_device: %s", hipGetErrorString(e));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "check_device: %s", hipGetErrorString(e));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(POLYMH_ENOTSUP, "check_device: device %d is %s, not gfx950", dev, prop.gcnArchName);
+    return POLYMH_OK;
+}
+
+polymh_status polymh_prepare(const polymh_polys *polys, int32_t *mbr, int64_t *area2,
+                             uint32_t *flags, void *stream)
+{
+    polymh_status st = check_polys(polys, "prepare");
+    if (st) return st;
+    if (polys->n > 0 && !mbr) return set_error(POLYMH_EINVAL, "prepare: mbr is NULL");
+    return launch_prepare(polys->xy, polys->offsets, polys->n, mbr, area2, flags, as_stream(stream));
+}
+
+size_t polymh_box_of_workspace_size(void) { return 256; }
+
+polymh_status polymh_box_of(const polymh_polys *polys, void *ws, size_t ws_bytes,
+                            polymh_box *out_host, void *stream)
+{
+    polymh_status st = check_polys(polys, "box_of");
+    if (st) return st;
+    if (!out_host) return set_error(POLYMH_EINVAL, "box_of: out_host is NULL");
+    if (!ws || ws_bytes < polymh_box_of_workspace_size())
+        return set_error(POLYMH_ECAPACITY, "box_of: workspace too small");
+    if (polys->n == 0) return set_error(POLYMH_EINVAL, "box_of: empty polygon set");
+    int64_t nv = 0;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(&nv, polys->offsets + polys->n, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "box_of: %s", hipGetErrorString(e));
+    if (nv <= 0) return set_error(POLYMH_EINVAL, "box_of: polygon set has no vertex");
+    int32_t *acc = static_cast<int32_t *>(ws);
+    st = launch_box_of(polys->xy, nv, acc, s);
+    if (st) return st;
+    int32_t h[4];
+    e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "box_of: %s", hipGetErrorString(e));
+    out_host->xmin = h[0];
+    out_host->ymin = h[1];
+    out_host->xmax = h[2];
+    out_host->ymax = h[3];
+    return POLYMH_OK;
+}
+
+void polymh_sign_default_config(polymh_sign_config *cfg)
+{
+    if (!cfg) return;
+    cfg->persistent = 1;
+    cfg->block_threads = 256;
+    cfg->hash_block = 0;
+    cfg->lds_edges = 1024;
+    cfg->samples_per_lane = 1;
+    cfg->blocks_per_cu = 8;
+}
+
+size_t polymh_sign_workspace_size(int64_t n, const polymh_sign_config *cfg)
+{
+    polymh_sign_config c;
+    if (cfg) c = *cfg;
+    else polymh_sign_default_config(&c);
+    if (n < 0) n = 0;
+    Carve cv{nullptr, 0};
+    carve_sign(cv, n, c.persistent != 0);
+    return align_up(cv.used, 256);
+}
+
+polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                          uint32_t cap, uint32_t *sig, const polymh_sign_config *cfg, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    polymh_status st = check_polys(polys, "sign");
+    if (st) return st;
+    if ((st = check_box(box, "sign"))) return st;
+    if (k < 1) return set_error(POLYMH_EINVAL, "sign: k must be >= 1");
+    if (cap < 1) return set_error(POLYMH_EINVAL, "sign: cap must be >= 1");
+    polymh_sign_config c;
+    if (cfg) c = *cfg;
+    else polymh_sign_default_config(&c);
+    if ((st = check_sign_config(c))) return st;
+    if (polys->n == 0) return POLYMH_OK;
+    if (!sig) return set_error(POLYMH_EINVAL, "sign: sig is NULL");
+    if ((int64_t)polys->n * k > (int64_t)1 << 40)
+        return set_error(POLYMH_EINVAL, "sign: n * k too large");
+    Carve cv{static_cast<char *>(ws), ws_bytes};
+    SignWs w = carve_sign(cv, polys->n, c.persistent != 0);
+    if (!cv.ok)
+        return set_error(POLYMH_ECAPACITY, "sign: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
+    hipStream_t s = as_stream(stream);
+    if ((st = launch_prepare(polys->xy, polys->offsets, polys->n, w.mbr, w.area2, w.flags, s))) return st;
+    if (c.persistent) {
+        if ((st = launch_sign_order(polys->offsets, w.mbr, w.area2, w.flags, polys->n, box, k, cap,
+                                    w.counts, w.order, s)))
+            return st;
+    }
+    SignLaunch L{};
+    L.xy = polys->xy;
+    L.off = polys->offsets;
+    L.mbr = w.mbr;
+    L.flags = w.flags;
+    L.order = c.persistent ? w.order : nullptr;
+    L.queue = c.persistent ? w.queue : nullptr;
+    L.sig = sig;
+    L.n = polys->n;
+    L.box = box;
+    L.seed = seed;
+    L.k = k;
+    L.cap = cap;
+    L.cfg = c;
+    return launch_sign(L, s);
+}
+
+polymh_status polymh_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,
+                          uint64_t band_seed, uint64_t *keys, void *stream)
+{
+    if (n < 0 || k < 1 || b < 1 || r < 1) return set_error(POLYMH_EINVAL, "band: bad sizes");
+    if ((int64_t)b * r > k) return set_error(POLYMH_EINVAL, "band: b*r = %d exceeds k = %d", b * r, k);
+    if (n == 0) return POLYMH_OK;
+    if (!sig || !keys) return set_error(POLYMH_EINVAL, "band: NULL array");
+    return launch_band(sig, n, k, b, r, band_seed, keys, as_stream(stream));
+}
+
+size_t polymh_index_workspace_size(int64_t n, int32_t b)
+{
+    if (n < 0 || b < 1) return 0;
+    return index_workspace_bytes(n * b);
+}
+
+polymh_status polymh_index_build(const uint64_t *keys, int64_t n, int32_t b, void *ws,
+                                 size_t ws_bytes, uint64_t *sorted_keys, int32_t *sorted_ids,
+                                 void *stream)
+{
+    if (n < 0 || b < 1) return set_error(POLYMH_EINVAL, "index_build: bad sizes");
+    if (n == 0) return POLYMH_OK;
+    if (!keys || !sorted_keys || !sorted_ids) return set_error(POLYMH_EINVAL, "index_build: NULL array");
+    return launch_index_build(keys, n, b, ws, ws_bytes, sorted_keys, sorted_ids, as_stream(stream));
+}
+
+size_t polymh_query_workspace_size(int64_t n_data, int64_t nq)
+{
+    if (n_data < 0 || nq < 0) return 0;
+    return query_workspace_bytes(n_data, nq);
+}
+
+polymh_status polymh_query(const uint64_t *sorted_keys, const int32_t *sorted_ids,
+                           int64_t n_entries, int64_t n_data, const uint64_t *qkeys, int64_t nq,
+                           int32_t b, void *ws, size_t ws_bytes, int64_t *cand_off,
+                           int32_t *cand_ids, int64_t cand_cap, void *stream)
+{
+    if (n_entries < 0 || n_data < 0 || nq < 0 || b < 1)
+        return set_error(POLYMH_EINVAL, "query: bad sizes");
+    if (!cand_off) return set_error(POLYMH_EINVAL, "query: cand_off is NULL");
+    if (nq > 0 && !qkeys) return set_error(POLYMH_EINVAL, "query: qkeys is NULL");
+    if (n_entries > 0 && (!sorted_keys || !sorted_ids))
+        return set_error(POLYMH_EINVAL, "query: NULL bucket table");
+    hipStream_t s = as_stream(stream);
+    if (cand_ids && cand_cap >= 0) {
+        int64_t total = 0;
+        hipError_t e = hipMemcpyAsync(&total, cand_off + nq, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "query: %s", hipGetErrorString(e));
+        if (total > cand_cap)
+            return set_error(POLYMH_ECAPACITY, "query: %lld candidates exceed capacity %lld",
+                             (long long)total, (long long)cand_cap);
+    }
+    return launch_query(sorted_keys, sorted_ids, n_entries, n_data, qkeys, nq, b, ws, ws_bytes,
+                        cand_off, cand_ids, s);
+}
+
+polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *queries,
+                            const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                            int64_t n_cand, double *cand_j, void *stream)
+{
+    polymh_status st = check_polys(data, "refine");
+    if (st) return st;
+    if ((st = check_polys(queries, "refine"))) return st;
+    if (nq != queries->n) return set_error(POLYMH_EINVAL, "refine: nq differs from the query count");
+    if (n_cand < 0) return set_error(POLYMH_EINVAL, "refine: negative candidate count");
+    if (n_cand == 0 || nq == 0) return POLYMH_OK;
+    if (!cand_off || !cand_ids || !cand_j) return set_error(POLYMH_EINVAL, "refine: NULL array");
+    return launch_refine(data, queries, cand_off, cand_ids, nq, n_cand, cand_j, as_stream(stream));
+}
+
+polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, const double *cand_j,
+                          int64_t nq, int32_t topk, int32_t *top_ids, double *top_j, void *stream)
+{
+    if (nq < 0 || topk < 1 || topk > 64) return set_error(POLYMH_EINVAL, "topk: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !top_ids || !top_j) return set_error(POLYMH_EINVAL, "topk: NULL array");
+    return launch_topk(cand_off, cand_ids, cand_j, nq, topk, top_ids, top_j, as_stream(stream));
+}
+
+}  // extern "C"

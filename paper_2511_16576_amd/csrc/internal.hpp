@@ -1,0 +1,119 @@
+// Internal declarations shared by the libpolymh translation units (device
+// helpers, kernel launchers, error reporting).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/polymh.h"
+
+namespace polymh {
+
+// SplitMix64 increment (the golden-ratio constant of Steele, Lea, Flood).
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 output function: the per-hash key and every draw of Alg. 1's
+// fixed-seed point streams go through it.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+// Per-polygon flag bits written by the staging kernel.
+constexpr uint32_t kFlagFew = 1u;        // fewer than 3 vertices
+constexpr uint32_t kFlagCollinear = 2u;  // all vertices on one line
+constexpr uint32_t kFlagWide = 4u;       // MBR side >= 2^26: 128-bit orientation
+
+polymh_status set_error(polymh_status st, const char *fmt, ...);
+polymh_status check_launch(const char *what);
+int cu_count();
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace.
+struct Carve {
+    char *base;
+    size_t cap;
+    size_t used = 0;
+    bool ok = true;
+    template <class T>
+    T *take(size_t count)
+    {
+        size_t off = align_up(used, 256);
+        size_t need = off + count * sizeof(T);
+        if (need > cap || base == nullptr) {
+            ok = false;
+            used = need;
+            return nullptr;
+        }
+        used = need;
+        return reinterpret_cast<T *>(base + off);
+    }
+};
+
+// ---- launchers (each defined next to its kernels) -------------------------
+
+// prepare.hip
+polymh_status launch_prepare(const int32_t *xy, const int64_t *off, int64_t n, int32_t *mbr,
+                             int64_t *area2, uint32_t *flags, hipStream_t s);
+polymh_status launch_box_of(const int32_t *xy, int64_t n_vertices, int32_t *acc4, hipStream_t s);
+polymh_status launch_sign_order(const int64_t *off, const int32_t *mbr, const int64_t *area2,
+                                const uint32_t *flags, int64_t n, polymh_box box, int32_t k,
+                                uint32_t cap, int32_t *bucket_counts, int32_t *order,
+                                hipStream_t s);
+
+// sign.hip
+struct SignLaunch {
+    const int32_t *xy;
+    const int64_t *off;
+    const int32_t *mbr;
+    const uint32_t *flags;
+    const int32_t *order;     // nullable: identity
+    unsigned long long *queue;  // nullable: plain grid
+    uint32_t *sig;
+    int64_t n;
+    polymh_box box;
+    uint64_t seed;
+    int32_t k;
+    uint32_t cap;
+    polymh_sign_config cfg;
+};
+polymh_status launch_sign(const SignLaunch &L, hipStream_t s);
+
+// band.hip
+polymh_status launch_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,
+                          uint64_t band_seed, uint64_t *keys, hipStream_t s);
+
+// index.hip
+size_t index_workspace_bytes(int64_t m);
+polymh_status launch_index_build(const uint64_t *keys, int64_t n, int32_t b, void *ws,
+                                 size_t ws_bytes, uint64_t *sorted_keys, int32_t *sorted_ids,
+                                 hipStream_t s);
+
+// query.hip
+size_t query_workspace_bytes(int64_t n_data, int64_t nq);
+polymh_status launch_query(const uint64_t *skeys, const int32_t *sids, int64_t n_entries,
+                           int64_t n_data, const uint64_t *qkeys, int64_t nq, int32_t b, void *ws,
+                           size_t ws_bytes, int64_t *cand_off, int32_t *cand_ids, hipStream_t s);
+
+// refine.hip
+polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
+                            const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                            int64_t n_cand, double *cand_j, hipStream_t s);
+
+// topk.hip
+polymh_status launch_topk(const int64_t *off, const int32_t *ids, const double *js, int64_t nq,
+                          int32_t k, int32_t *top_ids, double *top_j, hipStream_t s);
+
+// util
+polymh_status launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v,
+                              hipStream_t s);
+
+}  // namespace polymh

@@ -1,0 +1,172 @@
+// Candidate generation (Sec. 3.2: a query's candidates are the polygons in
+// its buckets).  Each (query, band) key is looked up by binary search in the
+// sorted bucket table and every entry of the bucket that belongs to the same
+// band sets its polygon's bit in the query's bitmap; a query's candidate list is then its set bits in ascending
+// id order, which deduplicates across bands without any sort.
+#include "internal.hpp"
+
+namespace polymh {
+
+namespace {
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t *p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// One wavefront per (query, band): find the bucket, lanes mark its entries.
+__global__ __launch_bounds__(256) void k_mark(const uint64_t *__restrict__ skeys,
+                                              const int32_t *__restrict__ sids, int64_t n_entries,
+                                              const uint64_t *__restrict__ qkeys, int64_t nq,
+                                              int32_t b, uint32_t *__restrict__ bitmap, int64_t words)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nq * b; w += nw) {
+        // every lane runs the (uniform) binary searches: no lane-0 branch
+        // feeding a cross-lane read
+        const uint64_t key = qkeys[w];
+        const int32_t t = (int32_t)(w % b);
+        const int64_t lo = lower_bound_u64(skeys, n_entries, key);
+        int64_t hi = lo;
+        if (lo < n_entries && skeys[lo] == key)
+            hi = (key == ~0ull) ? n_entries : lower_bound_u64(skeys, n_entries, key + 1);
+        uint32_t *row = bitmap + (w / b) * words;
+        for (int64_t e = lo + lane; e < hi; e += 64) {
+            const int32_t ent = sids[e];          // entry p*b + t'
+            const int32_t id = ent / b;
+            if (ent - id * b == t) atomicOr(&row[id >> 5], 1u << (id & 31));
+        }
+    }
+}
+
+// One block per query: popcount of its bitmap row.
+__global__ __launch_bounds__(256) void k_count(const uint32_t *__restrict__ bitmap, int64_t words,
+                                               int64_t *__restrict__ counts)
+{
+    __shared__ int64_t s[256];
+    const uint32_t *row = bitmap + (int64_t)blockIdx.x * words;
+    int64_t c = 0;
+    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) c += __popc(row[i]);
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = s[0];
+}
+
+// Exclusive prefix of counts[0..nq) into off[0..nq], single block.
+__global__ __launch_bounds__(1024) void k_offsets(int64_t *__restrict__ off, int64_t nq)
+{
+    __shared__ int64_t s[1024];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nq; c0 += 1024) {
+        const int64_t c = c0 + threadIdx.x;
+        const int64_t v = c < nq ? off[c] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (c < nq) off[c] = carry + s[threadIdx.x] - v;
+        carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[nq] = carry;
+}
+
+// One block per query: write its set bits in ascending order.
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ bitmap, int64_t words,
+                                              const int64_t *__restrict__ off,
+                                              int32_t *__restrict__ ids)
+{
+    __shared__ uint32_t s[256];
+    const int64_t q = blockIdx.x;
+    const uint32_t *row = bitmap + q * words;
+    int64_t base = off[q];
+    for (int64_t w0 = 0; w0 < words; w0 += 256) {
+        const int64_t w = w0 + threadIdx.x;
+        uint32_t bits = w < words ? row[w] : 0u;
+        const uint32_t c = __popc(bits);
+        s[threadIdx.x] = c;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const uint32_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        int64_t pos = base + s[threadIdx.x] - c;
+        while (bits) {
+            const int bit = __builtin_ctz(bits);
+            ids[pos++] = (int32_t)(w * 32 + bit);
+            bits &= bits - 1;
+        }
+        base += s[255];
+        __syncthreads();
+    }
+}
+
+int blocks_for(int64_t items, int per_block)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+}  // namespace
+
+size_t query_workspace_bytes(int64_t n_data, int64_t nq)
+{
+    const int64_t words = (n_data + 31) / 32;
+    return align_up((size_t)(nq * words) * sizeof(uint32_t), 256) + 256;
+}
+
+polymh_status launch_query(const uint64_t *skeys, const int32_t *sids, int64_t n_entries,
+                           int64_t n_data, const uint64_t *qkeys, int64_t nq, int32_t b, void *ws,
+                           size_t ws_bytes, int64_t *cand_off, int32_t *cand_ids, hipStream_t s)
+{
+    const int64_t words = (n_data + 31) / 32;
+    Carve cv{static_cast<char *>(ws), ws_bytes};
+    uint32_t *bitmap = cv.take<uint32_t>((size_t)(nq * words));
+    if (!cv.ok)
+        return set_error(POLYMH_ECAPACITY, "query: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
+    if (nq == 0) {
+        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, cand_off, (int64_t)0);
+        return check_launch("query");
+    }
+    if (nq * words > 0)
+        hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nq * words, 256)), dim3(256), 0, s, bitmap, nq * words);
+    if (n_entries > 0 && words > 0)
+        hipLaunchKernelGGL(k_mark, dim3(blocks_for(nq * b, 4)), dim3(256), 0, s, skeys, sids, n_entries,
+                           qkeys, nq, b, bitmap, words);
+    if (!cand_ids) {
+        if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "query: too many queries");
+        hipLaunchKernelGGL(k_count, dim3((unsigned)nq), dim3(256), 0, s, bitmap, words, cand_off);
+        hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, cand_off, nq);
+    } else {
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)nq), dim3(256), 0, s, bitmap, words, cand_off, cand_ids);
+    }
+    return check_launch("query");
+}
+
+}  // namespace polymh

@@ -89,15 +89,22 @@ def _segments(counts: np.ndarray):
     return off, pid
 
 
-def _star_angles(rng, counts):
-    """Sorted angles per polygon, redrawn until every gap is below pi."""
+def _star_angles(rng, counts, stratified=False):
+    """Sorted angles per polygon, redrawn until every gap is below pi.  With
+    ``stratified`` angle i is (i + U(0.25, 0.75)) * 2 pi / n, which keeps every
+    gap at least pi / n (used for polygons whose uniform draws keep failing
+    the lattice validity check)."""
     off, pid = _segments(counts)
     ang = np.empty(off[-1])
     todo = np.arange(counts.shape[0])
     while todo.size:
         sub_cnt = counts[todo]
         sub_off, sub_pid = _segments(sub_cnt)
-        a = rng.random(sub_off[-1]) * TWO_PI
+        if stratified:
+            idx = np.arange(sub_off[-1]) - np.repeat(sub_off[:-1], sub_cnt)
+            a = (idx + rng.uniform(0.25, 0.75, sub_off[-1])) * (TWO_PI / np.repeat(sub_cnt, sub_cnt))
+        else:
+            a = rng.random(sub_off[-1]) * TWO_PI
         a = a[np.lexsort((a, sub_pid))]
         nxt = np.empty_like(a)
         nxt[:-1] = a[1:]
@@ -130,19 +137,22 @@ def _star_valid(xy: np.ndarray, counts: np.ndarray, centre: np.ndarray) -> np.nd
     return ok
 
 
-def star_polygons(rng, counts, centres, radii) -> PolySet:
-    """Star-shaped simple polygons: sorted angles (max gap < pi), radii
-    U[0.5R, R], vertices rounded to the grid; invalid ones are redrawn."""
+def star_polygons(rng, counts, centres, radii, max_rounds: int = 200) -> PolySet:
+    """Star-shaped simple polygons: sorted uniform angles (max gap < pi), radii
+    U[0.5R, R], vertices rounded to the grid; invalid ones are redrawn, from
+    the fourth draw on with stratified angles so that the loop ends."""
     counts = np.asarray(counts, dtype=np.int64)
     centres = np.asarray(centres, dtype=np.int64)
     radii = np.asarray(radii, dtype=np.float64)
     off, pid = _segments(counts)
     xy = np.empty((off[-1], 2), dtype=np.int64)
     todo = np.arange(counts.shape[0])
-    while todo.size:
+    for rnd in range(max_rounds):
+        if todo.size == 0:
+            break
         sub_cnt = counts[todo]
         sub_off, sub_pid = _segments(sub_cnt)
-        ang = _star_angles(rng, sub_cnt)
+        ang = _star_angles(rng, sub_cnt, stratified=rnd >= 3)
         rad = rng.uniform(0.5, 1.0, sub_off[-1]) * radii[todo][sub_pid]
         c = centres[todo][sub_pid]
         sx = np.rint(c[:, 0] + rad * np.cos(ang)).astype(np.int64)
@@ -152,6 +162,9 @@ def star_polygons(rng, counts, centres, radii) -> PolySet:
         dst = np.repeat(off[todo], sub_cnt) + (np.arange(sub_off[-1]) - np.repeat(sub_off[:-1], sub_cnt))
         xy[dst] = sub_xy
         todo = todo[~ok]
+    if todo.size:
+        raise ValueError(f"{todo.size} star polygons stayed invalid after {max_rounds} draws: "
+                         "too many vertices for their radius on the integer grid")
     return PolySet(xy.astype(np.int32), off, centres.copy(), radii.copy())
 
 

@@ -1,0 +1,289 @@
+"""Thin Python binding of libpolymh (the C ABI in include/polymh.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch tensors carry device memory and the current HIP stream.  Names
+mirror the C entry points without their ``polymh_`` prefix.  Unsigned C
+arrays are exposed as signed torch tensors holding the same bits
+(uint32 signatures -> int32, uint64 keys -> int64).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolymh.so")
+
+OK, EINVAL, ERANGE, EDEVICE, ECAPACITY, ENOTSUP = 0, -1, -2, -3, -4, -5
+_NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", EDEVICE: "EDEVICE", ECAPACITY: "ECAPACITY",
+          ENOTSUP: "ENOTSUP"}
+
+
+class PolymhError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"polymh {_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("xmin", ctypes.c_int32), ("ymin", ctypes.c_int32),
+                ("xmax", ctypes.c_int32), ("ymax", ctypes.c_int32)]
+
+
+class Polys(ctypes.Structure):
+    _fields_ = [("xy", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class SignConfig(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("hash_block", ctypes.c_int32), ("lds_edges", ctypes.c_int32),
+                ("samples_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I32, I64, U32, U64, SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+_SIGNATURES = {
+    "polymh_last_error": (ctypes.c_char_p, []),
+    "polymh_version": (I32, []),
+    "polymh_check_device": (I32, []),
+    "polymh_prepare": (I32, [P, P, P, P, P]),
+    "polymh_box_of_workspace_size": (SZ, []),
+    "polymh_box_of": (I32, [P, P, SZ, P, P]),
+    "polymh_sign_default_config": (None, [P]),
+    "polymh_sign_workspace_size": (SZ, [I64, P]),
+    "polymh_sign": (I32, [P, Box, U64, I32, U32, P, P, P, SZ, P]),
+    "polymh_band": (I32, [P, I64, I32, I32, I32, U64, P, P]),
+    "polymh_index_workspace_size": (SZ, [I64, I32]),
+    "polymh_index_build": (I32, [P, I64, I32, P, SZ, P, P, P]),
+    "polymh_query_workspace_size": (SZ, [I64, I64]),
+    "polymh_query": (I32, [P, P, I64, I64, P, I64, I32, P, SZ, P, P, I64, P]),
+    "polymh_refine": (I32, [P, P, P, P, I64, I64, P, P]),
+    "polymh_topk": (I32, [P, P, P, I64, I32, P, P, P]),
+}
+
+
+def lib():
+    """Load libpolymh.so; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2511_16576_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != OK:
+        raise PolymhError(st, lib().polymh_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libpolymh needs a HIP device (torch.cuda.is_available() is False)")
+
+
+_checked_devices = set()
+
+
+def check_device():
+    _require_gpu()
+    d = torch.cuda.current_device()
+    if d not in _checked_devices:
+        _check(lib().polymh_check_device())
+        _checked_devices.add(d)
+
+
+@dataclasses.dataclass
+class DevicePolys:
+    """CSR polygons resident on the device."""
+    xy: torch.Tensor        # int32 [V, 2]
+    offsets: torch.Tensor   # int64 [N + 1]
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    def cstruct(self) -> Polys:
+        return Polys(self.xy.data_ptr(), self.offsets.data_ptr(), self.n)
+
+
+def to_device(polys, device="cuda") -> DevicePolys:
+    """Copy a PolySet-like object (``.xy``, ``.offsets``) to the device."""
+    xy = torch.from_numpy(np.ascontiguousarray(polys.xy, dtype=np.int32).reshape(-1, 2))
+    off = torch.from_numpy(np.ascontiguousarray(polys.offsets, dtype=np.int64))
+    if xy.shape[0] == 0:
+        xy = torch.zeros((1, 2), dtype=torch.int32)    # keep a valid pointer
+    return DevicePolys(xy.to(device), off.to(device))
+
+
+def _box(box) -> Box:
+    if isinstance(box, Box):
+        return box
+    x0, y0, x1, y1 = (int(v) for v in box)
+    return Box(x0, y0, x1, y1)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def default_sign_config() -> SignConfig:
+    c = SignConfig()
+    lib().polymh_sign_default_config(ctypes.byref(c))
+    return c
+
+
+def sign_config(**kw) -> SignConfig:
+    c = default_sign_config()
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, int(v))
+    return c
+
+
+def prepare(polys: DevicePolys, stream=None):
+    """(mbr int32 [N,4], area2 int64 [N], flags int32 [N])."""
+    check_device()
+    dev = polys.offsets.device
+    n = polys.n
+    mbr = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+    area2 = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    flags = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    ps = polys.cstruct()
+    _check(lib().polymh_prepare(ctypes.byref(ps), _ptr(mbr), _ptr(area2), _ptr(flags), _stream(stream)))
+    return mbr[:n], area2[:n], flags[:n]
+
+
+def box_of(polys: DevicePolys, stream=None):
+    check_device()
+    ws = _workspace(lib().polymh_box_of_workspace_size(), polys.offsets.device)
+    out = Box()
+    ps = polys.cstruct()
+    _check(lib().polymh_box_of(ctypes.byref(ps), _ptr(ws), ws.numel(), ctypes.byref(out),
+                               _stream(stream)))
+    return (out.xmin, out.ymin, out.xmax, out.ymax)
+
+
+def sign_workspace_size(n: int, config: SignConfig | None = None) -> int:
+    return int(lib().polymh_sign_workspace_size(n, ctypes.byref(config) if config else None))
+
+
+def sign(polys: DevicePolys, box, seed: int, k: int, cap: int, config: SignConfig | None = None,
+         out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Alg. 1 signatures: int32 [N, k] holding uint32 values (0 = no hit)."""
+    check_device()
+    dev = polys.offsets.device
+    n = polys.n
+    if out is None:
+        out = torch.empty((max(n, 1), k), dtype=torch.int32, device=dev)
+    need = sign_workspace_size(n, config)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    ps = polys.cstruct()
+    _check(lib().polymh_sign(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, _ptr(out),
+                             ctypes.byref(config) if config else None, _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return out[:n]
+
+
+def band(sig: torch.Tensor, b: int, r: int, band_seed: int = 0, out: torch.Tensor | None = None,
+         stream=None) -> torch.Tensor:
+    """Band keys: int64 [N, b] holding uint64 values."""
+    check_device()
+    n, k = sig.shape
+    if out is None:
+        out = torch.empty((max(n, 1), b), dtype=torch.int64, device=sig.device)
+    _check(lib().polymh_band(_ptr(sig), n, k, b, r, band_seed & ((1 << 64) - 1), _ptr(out),
+                             _stream(stream)))
+    return out[:n]
+
+
+def index_build(keys: torch.Tensor, stream=None, ws: torch.Tensor | None = None):
+    """Bucket table: (sorted_keys int64 [N*b], sorted entries int32 [N*b],
+    entry = p*b + t)."""
+    check_device()
+    n, b = keys.shape
+    dev = keys.device
+    m = max(n * b, 1)
+    sk = torch.empty(m, dtype=torch.int64, device=dev)
+    si = torch.empty(m, dtype=torch.int32, device=dev)
+    need = int(lib().polymh_index_workspace_size(n, b))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    _check(lib().polymh_index_build(_ptr(keys), n, b, _ptr(ws), ws.numel(), _ptr(sk), _ptr(si),
+                                    _stream(stream)))
+    return sk[:n * b], si[:n * b]
+
+
+def query(sorted_keys: torch.Tensor, sorted_ids: torch.Tensor, n_data: int, qkeys: torch.Tensor,
+          stream=None, ws: torch.Tensor | None = None):
+    """Candidates: (cand_off int64 [nq+1], cand_ids int32 [C]); synchronises
+    once to size cand_ids."""
+    check_device()
+    nq, b = qkeys.shape
+    dev = qkeys.device
+    need = int(lib().polymh_query_workspace_size(n_data, nq))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    off = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    s = _stream(stream)
+    L = lib()
+    _check(L.polymh_query(_ptr(sorted_keys), _ptr(sorted_ids), sorted_keys.numel(), n_data,
+                          _ptr(qkeys), nq, b, _ptr(ws), ws.numel(), _ptr(off), None, 0, s))
+    total = int(off[-1].item())
+    ids = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+    _check(L.polymh_query(_ptr(sorted_keys), _ptr(sorted_ids), sorted_keys.numel(), n_data,
+                          _ptr(qkeys), nq, b, _ptr(ws), ws.numel(), _ptr(off), _ptr(ids), -1, s))
+    return off, ids[:total]
+
+
+def refine(data: DevicePolys, queries: DevicePolys, cand_off: torch.Tensor, cand_ids: torch.Tensor,
+           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Exact Jaccard per candidate: float64 [C]."""
+    check_device()
+    nq = queries.n
+    c = cand_ids.numel()
+    if out is None:
+        out = torch.empty(max(c, 1), dtype=torch.float64, device=cand_ids.device)
+    dp, qp = data.cstruct(), queries.cstruct()
+    _check(lib().polymh_refine(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                               nq, c, _ptr(out), _stream(stream)))
+    return out[:c]
+
+
+def topk(cand_off: torch.Tensor, cand_ids: torch.Tensor, cand_j: torch.Tensor, k: int, stream=None):
+    """(top_ids int32 [nq, k] (-1 pad), top_j float64 [nq, k])."""
+    check_device()
+    nq = cand_off.numel() - 1
+    dev = cand_off.device
+    ids = torch.empty((max(nq, 1), k), dtype=torch.int32, device=dev)
+    js = torch.empty((max(nq, 1), k), dtype=torch.float64, device=dev)
+    _check(lib().polymh_topk(_ptr(cand_off), _ptr(cand_ids), _ptr(cand_j), nq, k, _ptr(ids), _ptr(js),
+                             _stream(stream)))
+    return ids[:nq], js[:nq]
