@@ -256,60 +256,276 @@ __device__ __forceinline__ void poly_mbr(const int32_t *v, int32_t n, int lane, 
     out[0] = wmin(mnx); out[1] = wmin(mny); out[2] = wmax(mxx); out[3] = wmax(mxy);
 }
 
+// ---------------------------------------------------------------------------
+// Tiled form.  The two boundaries are cut into chunks of 8 edges; only chunk
+// pairs whose boxes overlap are tested, 64 edge pairs per wavefront step
+// (8 x 8 lanes).  Each crossing is found once and credited to both polygons.
+// The membership of each edge's start is not tested directly: it is the
+// membership of the ring's first vertex plus the running sum of the crossing
+// signs met along the ring, so with S_e the net sign of edge e's crossings,
+//   sum_e cr_e * I(e) = sum_e cr_e * (w_0 + s * sum_{e' < e} S_e')
+//                       + s * sum_{crossings} cr_e * sign * (1 - t).
+// Q (the query) is staged once per workgroup; each wavefront stages its data
+// polygon.  Pairs with a polygon beyond kTileCap edges, or coordinate spans of
+// 2^26 and more, take the general per-edge form above.
+
+constexpr int kTileCap = 512;
+constexpr int kWavesPerBlock = 4;
+
+struct RingLds {
+    int2 *v;       // vertices relative to the origin
+    int4 *box;     // per 8-edge chunk: xmin, ymin, xmax, ymax
+    int *S;        // net crossing sign per edge (per pair)
+};
+
+__device__ __forceinline__ double orient_d(int2 a, int2 b, int2 c)
+{
+    const double t = (double)(b.y - a.y) * (double)(c.x - a.x);
+    return __fma_rn((double)(b.x - a.x), (double)(c.y - a.y), -t);
+}
+
+__device__ __forceinline__ int sgn_tb(double o, int tb) { return o > 0 ? 1 : (o < 0 ? -1 : tb); }
+
+// Stage a ring (relative to the origin) and its chunk boxes; lanes of one
+// wavefront (lane0/nl describe the participating threads).
+__device__ void stage_ring(const int32_t *src, int n, int64_t ox, int64_t oy, RingLds R, int t0,
+                           int nt)
+{
+    for (int i = t0; i < n; i += nt)
+        R.v[i] = make_int2((int)((int64_t)src[2 * i] - ox), (int)((int64_t)src[2 * i + 1] - oy));
+}
+
+__device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
+{
+    const int nc = (n + 7) >> 3;
+    for (int c = t0; c < nc; c += nt) {
+        int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+        const int e1 = min(n, 8 * c + 8);
+        for (int v = 8 * c; v <= e1; v++) {
+            const int2 p = R.v[v == n ? 0 : v];
+            x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
+        }
+        R.box[c] = make_int4(x0, y0, x1, y1);
+    }
+}
+
+// Membership of point a + sh*delta in ring R (half-open crossing rule with the
+// perturbation): sh = -1 tests a - delta (a vertex of P against Q + delta),
+// sh = +1 tests a + delta (a vertex of Q + delta against P).
+__device__ int member_wave(RingLds R, int n, int2 a, int sh, int lane)
+{
+    bool odd = false;
+    for (int e = lane; e < n; e += 64) {
+        const int2 c = R.v[e], d = R.v[e + 1 == n ? 0 : e + 1];
+        if (c.x == d.x && c.y == d.y) continue;
+        // straddle of the horizontal through a + sh*(eps, eps^2)
+        const bool st = (sh < 0) ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
+        if (!st) continue;
+        // orient(c, d, a + sh*delta): tie broken by the perturbation
+        const int dx = d.x - c.x, dy = d.y - c.y;
+        const int tb = (sh < 0) ? (dy != 0 ? (dy > 0 ? 1 : -1) : (dx > 0 ? -1 : 1))
+                                : (dy != 0 ? (dy > 0 ? -1 : 1) : (dx > 0 ? 1 : -1));
+        const int so = sgn_tb(orient_d(c, d, a), tb);
+        odd ^= (so == (dy > 0 ? 1 : -1));
+    }
+    return __popcll(__ballot(odd)) & 1;
+}
+
+// sum_e cr_e * w_e with w_e = w0 + s * (exclusive prefix of S along the ring).
+__device__ double membership_term(RingLds R, int n, int w0, int s, int lane)
+{
+    double acc = 0.0;
+    int carry = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int base = 0; base < n; base += 64) {
+        const int e = base + lane;
+        int Se = 0;
+        double cr = 0.0;
+        if (e < n) {
+            Se = R.S[e];
+            const int2 a = R.v[e], b = R.v[e + 1 == n ? 0 : e + 1];
+            cr = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
+        }
+        // inclusive scan of Se over the wavefront (Se is -1, 0 or +1 per crossing sum)
+        int incl = Se;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        const int excl = incl - Se;
+        if (e < n) acc += cr * (double)(w0 + s * (carry + excl));
+        carry += __shfl(incl, 63, 64);
+        (void)lt;
+    }
+    return acc;
+}
+
+__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int lane)
+{
+    // ring-start memberships under Q + delta
+    const int w0p = member_wave(Q, m, P.v[0], -1, lane);
+    const int w0q = member_wave(P, n, Q.v[0], +1, lane);
+    double accP = 0.0, accQ = 0.0;
+    const int ncp = (n + 7) >> 3, ncq = (m + 7) >> 3;
+    const int total = ncp * ncq;
+    const int ti = lane >> 3, tj = lane & 7;
+    for (int base = 0; base < total; base += 64) {
+        const int idx = base + lane;
+        bool ov = false;
+        if (idx < total) {
+            const int4 bp = P.box[idx / ncq], bq = Q.box[idx % ncq];
+            ov = !(bp.z < bq.x || bq.z < bp.x || bp.w < bq.y || bq.w < bp.y);
+        }
+        uint64_t mk = __ballot(ov);
+        while (mk) {
+            const int k = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const int cp = (base + k) / ncq, cq = (base + k) % ncq;
+            const int e = 8 * cp + ti, f = 8 * cq + tj;
+            if (e < n && f < m) {
+                const int2 a = P.v[e], b = P.v[e + 1 == n ? 0 : e + 1];
+                const int2 c = Q.v[f], d = Q.v[f + 1 == m ? 0 : f + 1];
+                const int edx = b.x - a.x, edy = b.y - a.y, fdx = d.x - c.x, fdy = d.y - c.y;
+                if ((edx | edy) && (fdx | fdy)) {
+                    const int tbe = edy != 0 ? (edy > 0 ? -1 : 1) : (edx > 0 ? 1 : -1);
+                    const int tbf = fdy != 0 ? (fdy > 0 ? 1 : -1) : (fdx > 0 ? -1 : 1);
+                    const double oc = orient_d(a, b, c), od = orient_d(a, b, d);
+                    const double oa = orient_d(c, d, a), ob = orient_d(c, d, b);
+                    const int s1 = sgn_tb(oc, tbe), s2 = sgn_tb(od, tbe);
+                    const int s3 = sgn_tb(oa, tbf), s4 = sgn_tb(ob, tbf);
+                    if ((s1 != s2) & (s3 != s4)) {
+                        const double cre = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
+                        const double crf = __fma_rn((double)c.x, (double)d.y, -(double)d.x * (double)c.y);
+                        accP += cre * (double)s4 * (-ob) * rcp_refined(oa - ob);
+                        accQ += crf * (double)s2 * (-od) * rcp_refined(oc - od);
+                        atomicAdd(&P.S[e], s4);
+                        atomicAdd(&Q.S[f], s2);
+                    }
+                }
+            }
+        }
+    }
+    // make the crossing sums visible to the whole wavefront
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    const double mp = membership_term(P, n, w0p, sq, lane);
+    const double mq = membership_term(Q, m, w0q, sp, lane);
+    const double tot = sp * (mp + sq * accP) + sq * (mq + sp * accQ);
+    return wave_sum(tot);
+}
+
+__device__ int64_t ring_area2(RingLds R, int n, int lane)
+{
+    int64_t a = 0;
+    for (int e = lane; e < n; e += 64) {
+        const int2 p = R.v[e], q = R.v[e + 1 == n ? 0 : e + 1];
+        a += (int64_t)p.x * q.y - (int64_t)q.x * p.y;
+    }
+    return wave_sum_i64(a);
+}
+
+// One workgroup per query: Q staged once, wavefronts take its candidates.
 __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                                                 const int64_t *__restrict__ doff,
                                                 const int32_t *__restrict__ qxy,
                                                 const int64_t *__restrict__ qoff,
-                                                const int64_t *__restrict__ cand_off, int64_t nq,
-                                                const int32_t *__restrict__ cand_ids, int64_t n_cand,
+                                                const int64_t *__restrict__ cand_off,
+                                                const int32_t *__restrict__ cand_ids,
                                                 double *__restrict__ cand_j)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; c < n_cand; c += nw) {
-        // query of candidate c: the last q with cand_off[q] <= c
-        int64_t lo = 0, hi = nq;
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (cand_off[mid] <= c) lo = mid;
-            else hi = mid;
+    __shared__ int2 sQv[kTileCap];
+    __shared__ int4 sQbox[kTileCap / 8];
+    __shared__ int2 sPv[kWavesPerBlock][kTileCap];
+    __shared__ int4 sPbox[kWavesPerBlock][kTileCap / 8];
+    __shared__ int sPS[kWavesPerBlock][kTileCap];
+    __shared__ int sQS[kWavesPerBlock][kTileCap];
+    __shared__ int32_t sQmbr[4];
+    __shared__ long long sQa2;
+
+    const int64_t q = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t qa = qoff[q];
+    const int m = (int)(qoff[q + 1] - qa);
+    const int32_t *Qg = qxy + 2 * qa;
+    const int64_t c0 = cand_off[q], c1 = cand_off[q + 1];
+    if (c0 == c1) return;
+    if (m < 3) {
+        for (int64_t c = c0 + tid; c < c1; c += blockDim.x) cand_j[c] = 0.0;
+        return;
+    }
+    const int64_t ox = Qg[0], oy = Qg[1];
+    const bool q_tiled = m <= kTileCap;
+    if (wave == 0) {
+        int32_t qm[4];
+        poly_mbr(Qg, m, lane, qm);
+        const int64_t a2 = poly_area2(Qg, m, ox, oy, lane);
+        if (lane == 0) {
+            sQmbr[0] = qm[0]; sQmbr[1] = qm[1]; sQmbr[2] = qm[2]; sQmbr[3] = qm[3];
+            sQa2 = a2;
         }
-        const int64_t q = lo;
+    }
+    if (q_tiled) {
+        RingLds Qs{sQv, sQbox, nullptr};
+        stage_ring(Qg, m, ox, oy, Qs, tid, blockDim.x);
+        __syncthreads();
+        chunk_boxes(Qs, m, tid, blockDim.x);
+    }
+    __syncthreads();
+    const int32_t qmbr[4] = {sQmbr[0], sQmbr[1], sQmbr[2], sQmbr[3]};
+    const int64_t a2q = sQa2;
+    const int nwaves = blockDim.x >> 6;
+    for (int64_t c = c0 + wave; c < c1; c += nwaves) {
         const int32_t p = cand_ids[c];
-        PairIn in;
-        const int64_t pa = doff[p], qa = qoff[q];
-        in.P = dxy + 2 * pa;
-        in.n = (int32_t)(doff[p + 1] - pa);
-        in.Q = qxy + 2 * qa;
-        in.m = (int32_t)(qoff[q + 1] - qa);
+        const int64_t pa = doff[p];
+        const int n = (int)(doff[p + 1] - pa);
+        const int32_t *Pg = dxy + 2 * pa;
         double J = 0.0;
-        if (in.n >= 3 && in.m >= 3) {
+        if (n >= 3 && a2q != 0) {
             int32_t pm[4];
-            poly_mbr(in.P, in.n, lane, pm);
-            poly_mbr(in.Q, in.m, lane, in.qmbr);
-            const bool disjoint = pm[2] <= in.qmbr[0] || in.qmbr[2] <= pm[0] || pm[3] <= in.qmbr[1] ||
-                                  in.qmbr[3] <= pm[1];
+            poly_mbr(Pg, n, lane, pm);
+            const bool disjoint = pm[2] <= qmbr[0] || qmbr[2] <= pm[0] || pm[3] <= qmbr[1] || qmbr[3] <= pm[1];
             if (!disjoint) {
-                in.ox = in.Q[0];
-                in.oy = in.Q[1];
-                const int64_t span = max(max((int64_t)pm[2], (int64_t)in.qmbr[2]) - min((int64_t)pm[0], (int64_t)in.qmbr[0]),
-                                         max((int64_t)pm[3], (int64_t)in.qmbr[3]) - min((int64_t)pm[1], (int64_t)in.qmbr[1]));
-                double sa, sb;
-                int64_t a2p, a2q;
-                a2q = poly_area2(in.Q, in.m, in.ox, in.oy, lane);
-                in.sq = a2q > 0 ? 1 : -1;
+                const int64_t span = max(max((int64_t)pm[2], (int64_t)qmbr[2]) - min((int64_t)pm[0], (int64_t)qmbr[0]),
+                                         max((int64_t)pm[3], (int64_t)qmbr[3]) - min((int64_t)pm[1], (int64_t)qmbr[1]));
                 const bool wide = span >= (1ll << 26);
-                if (!wide) edges_in_other_P<false>(in, lane, sa, a2p);
-                else edges_in_other_P<true>(in, lane, sa, a2p);
-                a2p = wave_sum_i64(a2p);
-                in.sp = a2p > 0 ? 1 : -1;
-                if (a2p != 0 && a2q != 0) {
-                    int64_t unused;
-                    if (!wide) edges_in_other_Q<false>(in, pm, lane, sb, unused);
-                    else edges_in_other_Q<true>(in, pm, lane, sb, unused);
-                    sa = wave_sum(sa);
-                    sb = wave_sum(sb);
-                    const double inter = 0.5 * (in.sp * sa + in.sq * sb);
+                double inter2 = 0.0;
+                int64_t a2p = 0;
+                bool done = false;
+                if (!wide && q_tiled && n <= kTileCap) {
+                    RingLds Ps{sPv[wave], sPbox[wave], sPS[wave]};
+                    RingLds Qs{sQv, sQbox, sQS[wave]};
+                    stage_ring(Pg, n, ox, oy, Ps, lane, 64);
+                    for (int i = lane; i < n; i += 64) Ps.S[i] = 0;
+                    for (int i = lane; i < m; i += 64) Qs.S[i] = 0;
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
+                    chunk_boxes(Ps, n, lane, 64);
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_wave_barrier();
+                    a2p = ring_area2(Ps, n, lane);
+                    if (a2p != 0) inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, lane);
+                    done = true;
+                }
+                if (!done) {
+                    PairIn in;
+                    in.P = Pg; in.n = n; in.Q = Qg; in.m = m; in.ox = ox; in.oy = oy;
+                    in.qmbr[0] = qmbr[0]; in.qmbr[1] = qmbr[1]; in.qmbr[2] = qmbr[2]; in.qmbr[3] = qmbr[3];
+                    in.sq = a2q > 0 ? 1 : -1;
+                    double sa, sb;
+                    if (!wide) edges_in_other_P<false>(in, lane, sa, a2p);
+                    else edges_in_other_P<true>(in, lane, sa, a2p);
+                    a2p = wave_sum_i64(a2p);
+                    in.sp = a2p > 0 ? 1 : -1;
+                    if (a2p != 0) {
+                        int64_t unused;
+                        if (!wide) edges_in_other_Q<false>(in, pm, lane, sb, unused);
+                        else edges_in_other_Q<true>(in, pm, lane, sb, unused);
+                        inter2 = wave_sum(in.sp * sa) + wave_sum(in.sq * sb);
+                    }
+                }
+                if (a2p != 0) {
+                    const double inter = 0.5 * inter2;
                     const double ap = 0.5 * fabs((double)a2p), aq = 0.5 * fabs((double)a2q);
                     const double u = ap + aq - inter;
                     J = u > 0 ? inter / u : 0.0;
@@ -327,10 +543,9 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
                             int64_t n_cand, double *cand_j, hipStream_t s)
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
-    int64_t g = (n_cand + 3) / 4;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)g), dim3(256), 0, s, data->xy, data->offsets,
-                       queries->xy, queries->offsets, cand_off, nq, cand_ids, n_cand, cand_j);
+    if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "refine: too many queries");
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)nq), dim3(64 * kWavesPerBlock), 0, s, data->xy,
+                       data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j);
     return check_launch("refine");
 }
 

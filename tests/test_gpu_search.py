@@ -190,3 +190,31 @@ def test_pipeline_workload1_recall(pm, orc):
     assert 0.0 < rec <= 1.0
     # the jittered source is found for every query
     assert all(int(w.query_source[q]) in set(oids[ooff[q]:ooff[q + 1]].tolist()) for q in range(Q.n))
+
+
+def test_refine_lattice_degeneracies(pm, orc):
+    # small stars on a 7 x 7 grid share many vertices, T-junctions and
+    # collinear edge overlaps: every area must equal the exact rational one
+    rng = np.random.default_rng(6)
+    data, queries = [], []
+    for _ in range(150):
+        data.append(dg.star_polygons(rng, [int(rng.integers(3, 7))], [[3, 3]], [3.0]).xy)
+        q = dg.star_polygons(rng, [int(rng.integers(3, 7))], [[3, 3]], [3.0]).xy
+        queries.append(q if rng.random() < 0.5 else q[::-1])
+    D, Q = dg.from_list(data), dg.from_list(queries)
+    got = _refine(pm, D, Q, np.arange(151, dtype=np.int64), np.arange(150, dtype=np.int32))
+    for i in range(150):
+        want = float(orc.jaccard_exact(data[i], queries[i]))
+        assert abs(got[i] - want) <= 1e-12, (i, got[i], want)
+
+
+def test_refine_large_polygons_general_path(pm, orc):
+    # polygons beyond the tiled form's 512-edge staging cap
+    rng = np.random.default_rng(7)
+    data = dg.star_polygons(rng, [600, 1500, 40, 2000], [[50000, 50000]] * 4, [40000.0] * 4)
+    queries = dg.star_polygons(rng, [1200, 30, 900], [[52000, 49000]] * 3, [38000.0] * 3)
+    off = np.array([0, 4, 8, 12], dtype=np.int64)
+    ids = np.tile(np.arange(4, dtype=np.int32), 3)
+    got = _refine(pm, data, queries, off, ids)
+    want = orc.jaccard_candidates(data, queries, off, ids)
+    assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
