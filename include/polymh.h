@@ -204,6 +204,98 @@ polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, cons
                           int64_t nq, int32_t topk, int32_t *top_ids, double *top_j,
                           void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned candidate scorer (an AI-systems form beside the method; not in the
+ * paper).  A small MLP predicts a pair's Jaccard from its 256 signature
+ * collisions (each a Bernoulli(J) draw by Thm. 1) and shape features, so that
+ * refinement can visit candidates best-first and stop early; full refinement
+ * stays the fallback.  Network: 288 inputs -> 256 -> 256 -> 1, GELU (tanh
+ * form) after both hidden layers, sigmoid output, MSE loss; BF16 weights and
+ * activations on the MFMA units with FP32 accumulation; Adam on FP32 master
+ * weights.
+ *
+ * Parameter block (FP32, polymh_mlp_param_count() floats):
+ *   W1 [256][288] row-major (out, in) | b1 [256] | W2 [256][256] | b2 [256] |
+ *   w3 [256] | b3 [1].
+ * BF16 copy (polymh_mlp_bf16_count() uint16 bit patterns): W1 then W2,
+ * refreshed by polymh_mlp_sync_bf16 and by every polymh_mlp_adam.
+ * Inputs X: [B][288] BF16 rows (polymh_pair_features); B a multiple of 32.
+ * ------------------------------------------------------------------------- */
+int64_t polymh_mlp_param_count(void);
+int64_t polymh_mlp_bf16_count(void);
+/* Bytes of the activation buffer (z1, z2 FP32; h1, h2 BF16; y) for batch B. */
+size_t polymh_mlp_acts_size(int64_t B);
+/* Bytes of the backward scratch for batch B. */
+size_t polymh_mlp_scratch_size(int64_t B);
+/* wbf16 <- BF16(W1), BF16(W2).  Stream-ordered. */
+polymh_status polymh_mlp_sync_bf16(const float *params, uint16_t *wbf16, void *stream);
+/* y [B] (nullable: kept in acts) = sigmoid(w3 . gelu(W2 gelu(W1 x + b1) + b2) + b3);
+ * acts receives the activations the backward pass needs.  Stream-ordered. */
+polymh_status polymh_mlp_forward(const uint16_t *X, int64_t B, const float *params,
+                                 const uint16_t *wbf16, float *y, void *acts, size_t acts_bytes,
+                                 void *stream);
+/* After polymh_mlp_forward on the same X and acts: grad [param_count] <- the
+ * gradient of the batch loss mean_r (y_r - label_r)^2, *loss (device float)
+ * <- that loss.  Stream-ordered. */
+polymh_status polymh_mlp_backward(const uint16_t *X, int64_t B, const float *params,
+                                  const uint16_t *wbf16, void *acts, size_t acts_bytes,
+                                  const float *label, float *grad, float *loss, void *scratch,
+                                  size_t scratch_bytes, void *stream);
+/* One Adam step (step counts from 1, bias-corrected moments m, v) on the FP32
+ * parameters, then the BF16 copy is refreshed.  Stream-ordered. */
+polymh_status polymh_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step,
+                              float lr, float beta1, float beta2, float eps, uint16_t *wbf16,
+                              void *stream);
+/* C [M][N] (FP32, row-major) = A B with BF16 operands read as
+ * A(i, k) = A[i*a_row_stride + k*a_k_stride], B(k, j) = B[j*b_col_stride +
+ * k*b_k_stride]; M, N multiples of 32, K of 16.  The product the scorer's
+ * layers use, exported for direct checks.  Stream-ordered. */
+polymh_status polymh_gemm_bf16(const uint16_t *A, int64_t a_row_stride, int64_t a_k_stride,
+                               const uint16_t *B, int64_t b_col_stride, int64_t b_k_stride,
+                               int64_t M, int64_t N, int64_t K, float *C, void *stream);
+
+/* Per-polygon shape features, feats [n][12] FP32: ln(A)/ln(N_B),
+ * ln(P^2/(4 pi A))/4, ln(MBR w/h)/2, ln(n)/9, (area centroid - MBR centre)/sqrt(A)
+ * in x and y, A, 0, MBR (x0, y0, x1 + 1, y1 + 1).  N_B = area of the box.
+ * Stream-ordered. */
+polymh_status polymh_poly_features(const polymh_polys *polys, polymh_box box, float *feats,
+                                   void *stream);
+/* Scorer input rows X [R_pad][288] BF16 for pairs (li[r], ri[r]) of a left
+ * table (signatures lsig [.][256], features lfeat [.][12]) and a right table:
+ * 256 collision bits [lsig == rsig], the 6 left and 6 right shape features,
+ * ln(A_l/A_r)/4, min/max area ratio, MBR intersection-over-union, collision
+ * fraction, then zeros; rows R..R_pad-1 are zero.  k must be 256.
+ * Stream-ordered. */
+polymh_status polymh_pair_features(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
+                                   const float *rfeat, int32_t k, const int32_t *li,
+                                   const int32_t *ri, int64_t R, int64_t R_pad, uint16_t *X,
+                                   void *stream);
+/* rows[c] = q for cand_off[q] <= c < cand_off[q+1] (the query of each
+ * candidate).  Stream-ordered. */
+polymh_status polymh_csr_rows(const int64_t *cand_off, int64_t nq, int32_t *rows, void *stream);
+/* out[r] = fraction of the k hashes on which lsig[li[r]] and rsig[ri[r]]
+ * agree: the unbiased estimate of J of Thm. 1.  Stream-ordered. */
+polymh_status polymh_jhat(const uint32_t *lsig, const uint32_t *rsig, int32_t k, const int32_t *li,
+                          const int32_t *ri, int64_t R, float *out, void *stream);
+
+/* Ordered refinement with early stop.  Each query's candidates are visited in
+ * decreasing score (predicted J; ties by position) and refined (as
+ * polymh_refine) in rounds of F per query; a query stops once it holds topk
+ * results and its topk-th exact J >= next score + margin, or when its
+ * candidates are exhausted (margin = +inf refines everything: the fallback,
+ * equal to polymh_refine + polymh_topk).  Queries with more than 8192
+ * candidates are refined fully in their given order.  top_ids/top_j as in
+ * polymh_topk.  *n_refined_host and *rounds_host (nullable, host) receive the
+ * number of refined pairs and rounds.  SYNCHRONISES the stream once per
+ * round.  ws: polymh_rank_workspace_size(nq, n_cand, F) bytes. */
+size_t polymh_rank_workspace_size(int64_t nq, int64_t n_cand, int32_t F);
+polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *queries,
+                                 const int64_t *cand_off, const int32_t *cand_ids,
+                                 const float *score, int64_t nq, int64_t n_cand, int32_t topk,
+                                 int32_t F, float margin, int32_t max_rounds, void *ws,
+                                 size_t ws_bytes, int32_t *top_ids, double *top_j,
+                                 int64_t *n_refined_host, int32_t *rounds_host, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

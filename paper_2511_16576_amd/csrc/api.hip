@@ -319,4 +319,189 @@ polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, cons
     return launch_topk(cand_off, cand_ids, cand_j, nq, topk, top_ids, top_j, as_stream(stream));
 }
 
+/* ------------------------------------------------------------------ scorer */
+
+int64_t polymh_mlp_param_count(void) { return mlp_param_count(); }
+int64_t polymh_mlp_bf16_count(void) { return mlp_bf16_count(); }
+size_t polymh_mlp_acts_size(int64_t B) { return B < 0 ? 0 : mlp_acts_bytes_aligned(B); }
+size_t polymh_mlp_scratch_size(int64_t B) { return B < 0 ? 0 : mlp_backward_scratch_bytes(B); }
+
+polymh_status polymh_mlp_sync_bf16(const float *params, uint16_t *wbf16, void *stream)
+{
+    if (!params || !wbf16) return set_error(POLYMH_EINVAL, "mlp_sync_bf16: NULL array");
+    return launch_mlp_sync_bf16(params, wbf16, as_stream(stream));
+}
+
+static polymh_status check_batch(int64_t B, const char *what)
+{
+    if (B < 0 || B % 32) return set_error(POLYMH_EINVAL, "%s: batch must be a non-negative multiple of 32", what);
+    return POLYMH_OK;
+}
+
+polymh_status polymh_mlp_forward(const uint16_t *X, int64_t B, const float *params,
+                                 const uint16_t *wbf16, float *y, void *acts, size_t acts_bytes,
+                                 void *stream)
+{
+    polymh_status st = check_batch(B, "mlp_forward");
+    if (st) return st;
+    if (B == 0) return POLYMH_OK;
+    if (!X || !params || !wbf16 || !acts) return set_error(POLYMH_EINVAL, "mlp_forward: NULL array");
+    if (acts_bytes < mlp_acts_bytes_aligned(B))
+        return set_error(POLYMH_ECAPACITY, "mlp_forward: activation buffer too small");
+    return launch_mlp_forward(X, B, params, wbf16, y, acts, as_stream(stream));
+}
+
+polymh_status polymh_mlp_backward(const uint16_t *X, int64_t B, const float *params,
+                                  const uint16_t *wbf16, void *acts, size_t acts_bytes,
+                                  const float *label, float *grad, float *loss, void *scratch,
+                                  size_t scratch_bytes, void *stream)
+{
+    polymh_status st = check_batch(B, "mlp_backward");
+    if (st) return st;
+    if (B == 0) return POLYMH_OK;
+    if (!X || !params || !wbf16 || !acts || !label || !grad || !loss || !scratch)
+        return set_error(POLYMH_EINVAL, "mlp_backward: NULL array");
+    if (acts_bytes < mlp_acts_bytes_aligned(B) || scratch_bytes < mlp_backward_scratch_bytes(B))
+        return set_error(POLYMH_ECAPACITY, "mlp_backward: buffer too small");
+    return launch_mlp_backward(X, B, params, wbf16, acts, label, grad, loss, scratch, as_stream(stream));
+}
+
+polymh_status polymh_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step,
+                              float lr, float beta1, float beta2, float eps, uint16_t *wbf16,
+                              void *stream)
+{
+    if (!params || !grad || !m || !v || !wbf16) return set_error(POLYMH_EINVAL, "mlp_adam: NULL array");
+    if (step < 1) return set_error(POLYMH_EINVAL, "mlp_adam: step counts from 1");
+    return launch_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, wbf16, as_stream(stream));
+}
+
+polymh_status polymh_gemm_bf16(const uint16_t *A, int64_t a_row_stride, int64_t a_k_stride,
+                               const uint16_t *B, int64_t b_col_stride, int64_t b_k_stride, int64_t M,
+                               int64_t N, int64_t K, float *C, void *stream)
+{
+    if (M < 0 || N < 0 || K < 0 || M % 32 || N % 32 || K % 16)
+        return set_error(POLYMH_EINVAL, "gemm_bf16: M, N multiples of 32 and K of 16 required");
+    if (M == 0 || N == 0) return POLYMH_OK;
+    if (!A || !B || !C) return set_error(POLYMH_EINVAL, "gemm_bf16: NULL array");
+    return launch_gemm_bf16(A, a_row_stride, a_k_stride, B, b_col_stride, b_k_stride, M, N, K, C,
+                            as_stream(stream));
+}
+
+polymh_status polymh_poly_features(const polymh_polys *polys, polymh_box box, float *feats, void *stream)
+{
+    polymh_status st = check_polys(polys, "poly_features");
+    if (st) return st;
+    if ((st = check_box(box, "poly_features"))) return st;
+    if (polys->n > 0 && !feats) return set_error(POLYMH_EINVAL, "poly_features: feats is NULL");
+    return launch_poly_features(polys, box, feats, as_stream(stream));
+}
+
+polymh_status polymh_pair_features(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
+                                   const float *rfeat, int32_t k, const int32_t *li,
+                                   const int32_t *ri, int64_t R, int64_t R_pad, uint16_t *X,
+                                   void *stream)
+{
+    if (k != 256) return set_error(POLYMH_EINVAL, "pair_features: the scorer takes k = 256 signatures");
+    if (R < 0 || R_pad < R) return set_error(POLYMH_EINVAL, "pair_features: bad row counts");
+    if (R_pad == 0) return POLYMH_OK;
+    if (!X || (R > 0 && (!lsig || !lfeat || !rsig || !rfeat || !li || !ri)))
+        return set_error(POLYMH_EINVAL, "pair_features: NULL array");
+    return launch_pair_features(lsig, lfeat, rsig, rfeat, li, ri, R, R_pad, X, as_stream(stream));
+}
+
+polymh_status polymh_csr_rows(const int64_t *cand_off, int64_t nq, int32_t *rows, void *stream)
+{
+    if (nq < 0) return set_error(POLYMH_EINVAL, "csr_rows: negative count");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !rows) return set_error(POLYMH_EINVAL, "csr_rows: NULL array");
+    return launch_csr_rows(cand_off, nq, rows, as_stream(stream));
+}
+
+polymh_status polymh_jhat(const uint32_t *lsig, const uint32_t *rsig, int32_t k, const int32_t *li,
+                          const int32_t *ri, int64_t R, float *out, void *stream)
+{
+    if (k < 1 || R < 0) return set_error(POLYMH_EINVAL, "jhat: bad sizes");
+    if (R == 0) return POLYMH_OK;
+    if (!lsig || !rsig || !li || !ri || !out) return set_error(POLYMH_EINVAL, "jhat: NULL array");
+    return launch_jhat(lsig, rsig, li, ri, R, k, out, as_stream(stream));
+}
+
+struct RankWs {
+    int32_t *order;
+    uint8_t *sorted_ok, *active;
+    int64_t *cursor, *roff;
+    int32_t *rids, *rpos, *n_active;
+    double *rj;
+};
+
+static RankWs carve_rank(Carve &c, int64_t nq, int64_t n_cand, int32_t F)
+{
+    RankWs w{};
+    w.order = c.take<int32_t>((size_t)(n_cand > 0 ? n_cand : 1));
+    w.sorted_ok = c.take<uint8_t>((size_t)nq + 1);
+    w.active = c.take<uint8_t>((size_t)nq + 1);
+    w.cursor = c.take<int64_t>((size_t)nq + 1);
+    w.roff = c.take<int64_t>((size_t)nq + 1);
+    const size_t per_round = (size_t)nq * (size_t)F + 1;
+    w.rids = c.take<int32_t>(per_round);
+    w.rpos = c.take<int32_t>(per_round);
+    w.rj = c.take<double>(per_round);
+    w.n_active = c.take<int32_t>(1);
+    return w;
+}
+
+size_t polymh_rank_workspace_size(int64_t nq, int64_t n_cand, int32_t F)
+{
+    if (nq < 0 || n_cand < 0 || F < 1) return 0;
+    Carve cv{nullptr, 0};
+    carve_rank(cv, nq, n_cand, F);
+    return align_up(cv.used, 256);
+}
+
+polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *queries,
+                                 const int64_t *cand_off, const int32_t *cand_ids, const float *score,
+                                 int64_t nq, int64_t n_cand, int32_t topk, int32_t F, float margin,
+                                 int32_t max_rounds, void *ws, size_t ws_bytes, int32_t *top_ids,
+                                 double *top_j, int64_t *n_refined_host, int32_t *rounds_host,
+                                 void *stream)
+{
+    polymh_status st = check_polys(data, "rank_refine");
+    if (st) return st;
+    if ((st = check_polys(queries, "rank_refine"))) return st;
+    if (nq != queries->n) return set_error(POLYMH_EINVAL, "rank_refine: nq differs from the query count");
+    if (topk < 1 || topk > 64 || F < 1 || max_rounds < 1 || n_cand < 0)
+        return set_error(POLYMH_EINVAL, "rank_refine: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !top_ids || !top_j || (n_cand > 0 && (!cand_ids || !score)))
+        return set_error(POLYMH_EINVAL, "rank_refine: NULL array");
+    Carve cv{static_cast<char *>(ws), ws_bytes};
+    RankWs w = carve_rank(cv, nq, n_cand, F);
+    if (!cv.ok)
+        return set_error(POLYMH_ECAPACITY, "rank_refine: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
+    hipStream_t s = as_stream(stream);
+    if ((st = launch_rank_sort(cand_off, nq, score, w.order, w.sorted_ok, s))) return st;
+    if ((st = launch_rank_init(nq, topk, w.cursor, w.active, top_ids, top_j, s))) return st;
+    int64_t refined = 0;
+    int32_t r = 0;
+    for (; r < max_rounds; r++) {
+        if ((st = launch_round_count(cand_off, nq, w.cursor, w.active, F, w.roff, s))) return st;
+        if ((st = launch_offsets(w.roff, nq, s))) return st;
+        if ((st = launch_round_fill(cand_off, cand_ids, w.order, w.cursor, w.roff, nq, w.rids, w.rpos, s)))
+            return st;
+        int64_t total = 0;
+        hipError_t e = hipMemcpyAsync(&total, w.roff + nq, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "rank_refine: %s", hipGetErrorString(e));
+        if (total == 0) break;
+        refined += total;
+        if ((st = launch_refine(data, queries, w.roff, w.rids, nq, total, w.rj, s))) return st;
+        if ((st = launch_round_merge(cand_off, score, w.order, w.sorted_ok, w.roff, w.rids, w.rj, nq,
+                                     topk, margin, w.cursor, w.active, top_ids, top_j, w.n_active, s)))
+            return st;
+    }
+    if (n_refined_host) *n_refined_host = refined;
+    if (rounds_host) *rounds_host = r;
+    return POLYMH_OK;
+}
+
 }  // extern "C"

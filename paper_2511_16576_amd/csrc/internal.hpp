@@ -112,6 +112,50 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
 polymh_status launch_topk(const int64_t *off, const int32_t *ids, const double *js, int64_t nq,
                           int32_t k, int32_t *top_ids, double *top_j, hipStream_t s);
 
+// mlp.hip
+int64_t mlp_param_count();
+int64_t mlp_bf16_count();
+size_t mlp_acts_bytes_aligned(int64_t B);
+size_t mlp_backward_scratch_bytes(int64_t B);
+polymh_status launch_mlp_sync_bf16(const float *params, uint16_t *wbf16, hipStream_t s);
+polymh_status launch_mlp_forward(const uint16_t *X, int64_t B, const float *params,
+                                 const uint16_t *wbf16, float *y, void *acts, hipStream_t s);
+polymh_status launch_mlp_backward(const uint16_t *X, int64_t B, const float *params,
+                                  const uint16_t *wbf16, void *acts, const float *label,
+                                  float *grad, float *loss, void *scratch, hipStream_t s);
+polymh_status launch_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step,
+                              float lr, float b1, float b2, float eps, uint16_t *wbf16, hipStream_t s);
+polymh_status launch_gemm_bf16(const uint16_t *A, int64_t sai, int64_t sak, const uint16_t *B,
+                               int64_t sbj, int64_t sbk, int64_t M, int64_t N, int64_t K, float *C,
+                               hipStream_t s);
+
+// features.hip
+polymh_status launch_poly_features(const polymh_polys *p, polymh_box box, float *feats, hipStream_t s);
+polymh_status launch_pair_features(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
+                                   const float *rfeat, const int32_t *li, const int32_t *ri,
+                                   int64_t R, int64_t R_pad, uint16_t *X, hipStream_t s);
+polymh_status launch_csr_rows(const int64_t *off, int64_t nq, int32_t *rows, hipStream_t s);
+
+// rank.hip
+int32_t rank_sort_cap();
+polymh_status launch_rank_sort(const int64_t *off, int64_t nq, const float *score, int32_t *order,
+                               uint8_t *sorted_ok, hipStream_t s);
+polymh_status launch_rank_init(int64_t nq, int32_t topk, int64_t *cursor, uint8_t *active,
+                               int32_t *top_ids, double *top_j, hipStream_t s);
+polymh_status launch_round_count(const int64_t *off, int64_t nq, const int64_t *cursor,
+                                 const uint8_t *active, int32_t F, int64_t *counts, hipStream_t s);
+polymh_status launch_round_fill(const int64_t *off, const int32_t *cand_ids, const int32_t *order,
+                                const int64_t *cursor, const int64_t *roff, int64_t nq,
+                                int32_t *rids, int32_t *rpos, hipStream_t s);
+polymh_status launch_round_merge(const int64_t *off, const float *score, const int32_t *order,
+                                 const uint8_t *sorted_ok, const int64_t *roff, const int32_t *rids,
+                                 const double *rj, int64_t nq, int32_t topk, float margin,
+                                 int64_t *cursor, uint8_t *active, int32_t *top_ids, double *top_j,
+                                 int32_t *n_active, hipStream_t s);
+polymh_status launch_jhat(const uint32_t *lsig, const uint32_t *rsig, const int32_t *li,
+                          const int32_t *ri, int64_t R, int32_t k, float *out, hipStream_t s);
+polymh_status launch_offsets(int64_t *off, int64_t nq, hipStream_t s);
+
 // util
 polymh_status launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v,
                               hipStream_t s);

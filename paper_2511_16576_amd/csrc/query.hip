@@ -135,6 +135,12 @@ int blocks_for(int64_t items, int per_block)
 
 }  // namespace
 
+polymh_status launch_offsets(int64_t *off, int64_t nq, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, off, nq);
+    return check_launch("offsets");
+}
+
 size_t query_workspace_bytes(int64_t n_data, int64_t nq)
 {
     const int64_t words = (n_data + 31) / 32;

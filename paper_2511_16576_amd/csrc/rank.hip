@@ -1,0 +1,244 @@
+// Ordered refinement with early stop (learned candidate scorer).
+//
+// Each query's candidates are sorted by a predicted Jaccard (the MLP's output
+// or the collision fraction of the signatures) and refined in rounds of F
+// candidates in that order.  After each round the query keeps its exact top-k
+// and stops once it holds k results and its k-th exact J is at least the next
+// candidate's predicted J plus a margin, or when its candidates run out.
+// Queries with more than kSortCap candidates are refined in their original
+// order with the stop test disabled, i.e. fully (the fallback).
+#include "internal.hpp"
+
+#include <cfloat>
+
+namespace polymh {
+
+namespace {
+
+constexpr int kSortCap = 8192;
+constexpr int kTopMax = 64;
+
+__device__ __forceinline__ bool key_before(float sa, int ia, float sb, int ib)
+{
+    return sa > sb || (sa == sb && ia < ib);
+}
+
+// One block per query: bitonic sort of (score desc, position asc) in LDS.
+__global__ __launch_bounds__(1024) void k_rank_sort(const int64_t *__restrict__ off,
+                                                    const float *__restrict__ score,
+                                                    int32_t *__restrict__ order,
+                                                    uint8_t *__restrict__ sorted_ok)
+{
+    __shared__ float ss[kSortCap];
+    __shared__ int si[kSortCap];
+    const int64_t q = blockIdx.x;
+    const int64_t a = off[q];
+    const int n = (int)(off[q + 1] - a);
+    if (n > kSortCap) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = i;
+        if (threadIdx.x == 0) sorted_ok[q] = 0;
+        return;
+    }
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        ss[i] = i < n ? score[a + i] : -FLT_MAX;
+        si[i] = i < n ? i : 0x7fffffff;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const bool before = key_before(ss[l], si[l], ss[i], si[i]);
+                    if (before == up) {
+                        const float t = ss[i]; ss[i] = ss[l]; ss[l] = t;
+                        const int u = si[i]; si[i] = si[l]; si[l] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = si[i];
+    if (threadIdx.x == 0) sorted_ok[q] = 1;
+}
+
+__global__ void k_rank_init(int64_t nq, int32_t topk, int64_t *__restrict__ cursor,
+                            uint8_t *__restrict__ active, int32_t *__restrict__ top_ids,
+                            double *__restrict__ top_j)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        cursor[q] = 0;
+        active[q] = 1;
+        for (int t = 0; t < topk; t++) {
+            top_ids[q * topk + t] = -1;
+            top_j[q * topk + t] = 0.0;
+        }
+    }
+}
+
+__global__ void k_round_count(const int64_t *__restrict__ off, int64_t nq,
+                              const int64_t *__restrict__ cursor, const uint8_t *__restrict__ active,
+                              int32_t F, int64_t *__restrict__ counts)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t left = (off[q + 1] - off[q]) - cursor[q];
+        counts[q] = active[q] ? (left < F ? left : F) : 0;
+    }
+}
+
+__global__ void k_round_fill(const int64_t *__restrict__ off, const int32_t *__restrict__ cand_ids,
+                             const int32_t *__restrict__ order, const int64_t *__restrict__ cursor,
+                             const int64_t *__restrict__ roff, int64_t nq,
+                             int32_t *__restrict__ rids, int32_t *__restrict__ rpos)
+{
+    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int64_t b = roff[q], cnt = roff[q + 1] - b;
+        for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int32_t pos = order[off[q] + cursor[q] + t];
+            rpos[b + t] = pos;
+            rids[b + t] = cand_ids[off[q] + pos];
+        }
+    }
+}
+
+// One thread per query: merge the round's exact results into the top-k and
+// apply the stop test.
+__global__ void k_round_merge(const int64_t *__restrict__ off, const float *__restrict__ score,
+                              const int32_t *__restrict__ order, const uint8_t *__restrict__ sorted_ok,
+                              const int64_t *__restrict__ roff, const int32_t *__restrict__ rids,
+                              const double *__restrict__ rj, int64_t nq, int32_t topk, float margin,
+                              int64_t *__restrict__ cursor, uint8_t *__restrict__ active,
+                              int32_t *__restrict__ top_ids, double *__restrict__ top_j,
+                              int32_t *__restrict__ n_active)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        if (!active[q]) continue;
+        int32_t *ti = top_ids + q * topk;
+        double *tj = top_j + q * topk;
+        for (int64_t c = roff[q]; c < roff[q + 1]; c++) {
+            const int32_t id = rids[c];
+            const double j = rj[c];
+            // insertion into the (J desc, id asc) list
+            int at = topk;
+            for (int t = 0; t < topk; t++) {
+                if (ti[t] < 0 || j > tj[t] || (j == tj[t] && id < ti[t])) {
+                    at = t;
+                    break;
+                }
+            }
+            if (at < topk) {
+                for (int t = topk - 1; t > at; t--) {
+                    ti[t] = ti[t - 1];
+                    tj[t] = tj[t - 1];
+                }
+                ti[at] = id;
+                tj[at] = j;
+            }
+        }
+        const int64_t cur = cursor[q] + (roff[q + 1] - roff[q]);
+        cursor[q] = cur;
+        const int64_t nq_c = off[q + 1] - off[q];
+        bool stop = cur >= nq_c;
+        if (!stop && sorted_ok[q] && ti[topk - 1] >= 0) {
+            const float next = score[off[q] + order[off[q] + cur]];
+            stop = tj[topk - 1] >= (double)next + (double)margin;
+        }
+        if (stop) active[q] = 0;
+        else atomicAdd(n_active, 1);
+    }
+}
+
+__global__ void k_zero_i32(int32_t *p) { if (threadIdx.x == 0) p[0] = 0; }
+
+__global__ __launch_bounds__(256) void k_jhat(const uint32_t *__restrict__ lsig,
+                                              const uint32_t *__restrict__ rsig,
+                                              const int32_t *__restrict__ li,
+                                              const int32_t *__restrict__ ri, int64_t R, int32_t k,
+                                              float *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < R; r += nw) {
+        const uint32_t *a = lsig + (int64_t)li[r] * k, *b = rsig + (int64_t)ri[r] * k;
+        int cnt = 0;
+        for (int i = lane; i < k; i += 64) cnt += a[i] == b[i];
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) out[r] = (float)cnt / (float)k;
+    }
+}
+
+int g_of(int64_t items, int per)
+{
+    int64_t g = (items + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+}  // namespace
+
+int32_t rank_sort_cap() { return kSortCap; }
+
+polymh_status launch_rank_sort(const int64_t *off, int64_t nq, const float *score, int32_t *order,
+                               uint8_t *sorted_ok, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_rank_sort, dim3((unsigned)nq), dim3(1024), 0, s, off, score, order, sorted_ok);
+    return check_launch("rank_sort");
+}
+
+polymh_status launch_rank_init(int64_t nq, int32_t topk, int64_t *cursor, uint8_t *active,
+                               int32_t *top_ids, double *top_j, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_rank_init, dim3(g_of(nq, 256)), dim3(256), 0, s, nq, topk, cursor, active,
+                       top_ids, top_j);
+    return check_launch("rank_init");
+}
+
+polymh_status launch_round_count(const int64_t *off, int64_t nq, const int64_t *cursor,
+                                 const uint8_t *active, int32_t F, int64_t *counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_count, dim3(g_of(nq, 256)), dim3(256), 0, s, off, nq, cursor, active,
+                       F, counts);
+    return check_launch("round_count");
+}
+
+polymh_status launch_round_fill(const int64_t *off, const int32_t *cand_ids, const int32_t *order,
+                                const int64_t *cursor, const int64_t *roff, int64_t nq,
+                                int32_t *rids, int32_t *rpos, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_fill, dim3(g_of(nq, 1)), dim3(64), 0, s, off, cand_ids, order, cursor,
+                       roff, nq, rids, rpos);
+    return check_launch("round_fill");
+}
+
+polymh_status launch_round_merge(const int64_t *off, const float *score, const int32_t *order,
+                                 const uint8_t *sorted_ok, const int64_t *roff, const int32_t *rids,
+                                 const double *rj, int64_t nq, int32_t topk, float margin,
+                                 int64_t *cursor, uint8_t *active, int32_t *top_ids, double *top_j,
+                                 int32_t *n_active, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_active);
+    hipLaunchKernelGGL(k_round_merge, dim3(g_of(nq, 256)), dim3(256), 0, s, off, score, order,
+                       sorted_ok, roff, rids, rj, nq, topk, margin, cursor, active, top_ids, top_j,
+                       n_active);
+    return check_launch("round_merge");
+}
+
+polymh_status launch_jhat(const uint32_t *lsig, const uint32_t *rsig, const int32_t *li,
+                          const int32_t *ri, int64_t R, int32_t k, float *out, hipStream_t s)
+{
+    if (R == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_jhat, dim3(g_of(R, 4)), dim3(256), 0, s, lsig, rsig, li, ri, R, k, out);
+    return check_launch("jhat");
+}
+
+}  // namespace polymh

@@ -68,6 +68,23 @@ _SIGNATURES = {
     "polymh_query": (I32, [P, P, I64, I64, P, I64, I32, P, SZ, P, P, I64, P]),
     "polymh_refine": (I32, [P, P, P, P, I64, I64, P, P]),
     "polymh_topk": (I32, [P, P, P, I64, I32, P, P, P]),
+    "polymh_mlp_param_count": (I64, []),
+    "polymh_mlp_bf16_count": (I64, []),
+    "polymh_mlp_acts_size": (SZ, [I64]),
+    "polymh_mlp_scratch_size": (SZ, [I64]),
+    "polymh_mlp_sync_bf16": (I32, [P, P, P]),
+    "polymh_mlp_forward": (I32, [P, I64, P, P, P, P, SZ, P]),
+    "polymh_mlp_backward": (I32, [P, I64, P, P, P, SZ, P, P, P, P, SZ, P]),
+    "polymh_mlp_adam": (I32, [P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, P, P]),
+    "polymh_gemm_bf16": (I32, [P, I64, I64, P, I64, I64, I64, I64, I64, P, P]),
+    "polymh_poly_features": (I32, [P, Box, P, P]),
+    "polymh_pair_features": (I32, [P, P, P, P, I32, P, P, I64, I64, P, P]),
+    "polymh_csr_rows": (I32, [P, I64, P, P]),
+    "polymh_jhat": (I32, [P, P, I32, P, P, I64, P, P]),
+    "polymh_rank_workspace_size": (SZ, [I64, I64, I32]),
+    "polymh_rank_refine": (I32, [P, P, P, P, P, I64, I64, I32, I32, ctypes.c_float, I32, P, SZ,
+                                 P, P, P, P, P]),
 }
 
 
@@ -287,3 +304,106 @@ def topk(cand_off: torch.Tensor, cand_ids: torch.Tensor, cand_j: torch.Tensor, k
     _check(lib().polymh_topk(_ptr(cand_off), _ptr(cand_ids), _ptr(cand_j), nq, k, _ptr(ids), _ptr(js),
                              _stream(stream)))
     return ids[:nq], js[:nq]
+
+
+# ------------------------------------------------------------- scorer calls
+
+def mlp_param_count() -> int:
+    return int(lib().polymh_mlp_param_count())
+
+
+def mlp_bf16_count() -> int:
+    return int(lib().polymh_mlp_bf16_count())
+
+
+def mlp_sync_bf16(params: torch.Tensor, wbf16: torch.Tensor, stream=None):
+    _check(lib().polymh_mlp_sync_bf16(_ptr(params), _ptr(wbf16), _stream(stream)))
+
+
+def mlp_buffers(B: int, device="cuda"):
+    """(acts, scratch) byte buffers for batch B."""
+    L = lib()
+    return (_workspace(L.polymh_mlp_acts_size(B), device),
+            _workspace(L.polymh_mlp_scratch_size(B), device))
+
+
+def mlp_forward(X: torch.Tensor, params, wbf16, acts, y=None, stream=None):
+    """X: int16 [B, 288] (BF16 bits), B a multiple of 32 -> y float32 [B]."""
+    B = X.shape[0]
+    if y is None:
+        y = torch.empty(max(B, 1), dtype=torch.float32, device=X.device)
+    _check(lib().polymh_mlp_forward(_ptr(X), B, _ptr(params), _ptr(wbf16), _ptr(y), _ptr(acts),
+                                    acts.numel(), _stream(stream)))
+    return y[:B]
+
+
+def mlp_backward(X, params, wbf16, acts, label, grad, loss, scratch, stream=None):
+    _check(lib().polymh_mlp_backward(_ptr(X), X.shape[0], _ptr(params), _ptr(wbf16), _ptr(acts),
+                                     acts.numel(), _ptr(label), _ptr(grad), _ptr(loss),
+                                     _ptr(scratch), scratch.numel(), _stream(stream)))
+
+
+def mlp_adam(params, grad, m, v, step, wbf16, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().polymh_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2,
+                                 eps, _ptr(wbf16), _stream(stream)))
+
+
+def gemm_bf16(A, a_row_stride, a_k_stride, B, b_col_stride, b_k_stride, M, N, K, stream=None):
+    C = torch.empty((max(M, 1), max(N, 1)), dtype=torch.float32, device=A.device)
+    _check(lib().polymh_gemm_bf16(_ptr(A), a_row_stride, a_k_stride, _ptr(B), b_col_stride,
+                                  b_k_stride, M, N, K, _ptr(C), _stream(stream)))
+    return C[:M, :N]
+
+
+def poly_features(polys: DevicePolys, box, stream=None) -> torch.Tensor:
+    f = torch.empty((max(polys.n, 1), 12), dtype=torch.float32, device=polys.offsets.device)
+    ps = polys.cstruct()
+    _check(lib().polymh_poly_features(ctypes.byref(ps), _box(box), _ptr(f), _stream(stream)))
+    return f[:polys.n]
+
+
+def pair_features(lsig, lfeat, rsig, rfeat, li, ri, R_pad=None, out=None, stream=None):
+    R = li.numel()
+    R_pad = R if R_pad is None else R_pad
+    if out is None:
+        out = torch.empty((max(R_pad, 1), 288), dtype=torch.int16, device=lsig.device)
+    _check(lib().polymh_pair_features(_ptr(lsig), _ptr(lfeat), _ptr(rsig), _ptr(rfeat),
+                                      lsig.shape[1], _ptr(li), _ptr(ri), R, R_pad, _ptr(out),
+                                      _stream(stream)))
+    return out[:R_pad]
+
+
+def csr_rows(cand_off, n_cand, stream=None):
+    rows = torch.empty(max(n_cand, 1), dtype=torch.int32, device=cand_off.device)
+    _check(lib().polymh_csr_rows(_ptr(cand_off), cand_off.numel() - 1, _ptr(rows), _stream(stream)))
+    return rows[:n_cand]
+
+
+def jhat(lsig, rsig, li, ri, out=None, stream=None):
+    R = li.numel()
+    if out is None:
+        out = torch.empty(max(R, 1), dtype=torch.float32, device=lsig.device)
+    _check(lib().polymh_jhat(_ptr(lsig), _ptr(rsig), lsig.shape[1], _ptr(li), _ptr(ri), R, _ptr(out),
+                             _stream(stream)))
+    return out[:R]
+
+
+def rank_refine(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, score, topk=10, F=16,
+                margin=0.0, max_rounds=1 << 20, ws=None, stream=None):
+    """Best-first refinement with early stop -> (top_ids, top_j, n_refined, rounds)."""
+    nq = queries.n
+    C = cand_ids.numel()
+    dev = cand_off.device
+    need = int(lib().polymh_rank_workspace_size(nq, C, F))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    ids = torch.empty((max(nq, 1), topk), dtype=torch.int32, device=dev)
+    js = torch.empty((max(nq, 1), topk), dtype=torch.float64, device=dev)
+    nref = ctypes.c_int64(0)
+    rounds = ctypes.c_int32(0)
+    dp, qp = data.cstruct(), queries.cstruct()
+    _check(lib().polymh_rank_refine(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                    _ptr(score), nq, C, topk, F, float(margin), max_rounds, _ptr(ws),
+                                    ws.numel(), _ptr(ids), _ptr(js), ctypes.byref(nref),
+                                    ctypes.byref(rounds), _stream(stream)))
+    return ids[:nq], js[:nq], int(nref.value), int(rounds.value)

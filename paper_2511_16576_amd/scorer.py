@@ -1,0 +1,165 @@
+"""Learned candidate scorer: training and the ranked query path.
+
+Every numeric step runs in libpolymh's kernels (features, MFMA forward and
+backward, Adam, ordered refinement); this module sequences the calls, mines
+training pairs (input preparation) and initialises the weights.
+
+Training data (the learned-scorer workload): pairs of workload-2 polygons
+signed at k = 256, half sharing at least one 32 x 8 LSH bucket and half drawn
+uniformly, labelled with their exact Jaccard by the refinement kernel.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import polymh as pm
+
+K_SCORER = 256
+BATCH = 8192
+
+
+@dataclasses.dataclass
+class Scorer:
+    params: torch.Tensor   # float32 [P] master weights
+    wbf16: torch.Tensor    # int16 [W1 + W2] BF16 copy
+    m: torch.Tensor
+    v: torch.Tensor
+    step: int = 0
+
+
+def init_scorer(seed: int = 0, device="cuda") -> Scorer:
+    """Uniform fan-in scaled weights (He-like for GELU), zero biases."""
+    rng = np.random.default_rng(seed)
+    P = pm.mlp_param_count()
+    p = np.zeros(P, dtype=np.float32)
+    n_in, n_hid = 288, 256
+    o_w1, o_b1 = 0, n_hid * n_in
+    o_w2 = o_b1 + n_hid
+    o_b2 = o_w2 + n_hid * n_hid
+    o_w3 = o_b2 + n_hid
+    p[o_w1:o_b1] = rng.uniform(-1, 1, n_hid * n_in) * math.sqrt(6.0 / n_in)
+    p[o_w2:o_b2] = rng.uniform(-1, 1, n_hid * n_hid) * math.sqrt(6.0 / n_hid)
+    p[o_w3:o_w3 + n_hid] = rng.uniform(-1, 1, n_hid) * math.sqrt(1.0 / n_hid)
+    params = torch.from_numpy(p).to(device)
+    wbf16 = torch.empty(pm.mlp_bf16_count(), dtype=torch.int16, device=device)
+    pm.mlp_sync_bf16(params, wbf16)
+    z = torch.zeros_like(params)
+    return Scorer(params, wbf16, z.clone(), z.clone())
+
+
+def mine_pairs(sorted_keys: torch.Tensor, sorted_ent: torch.Tensor, n: int, bands: int,
+               n_pairs: int, seed: int = 0):
+    """(left, right) polygon ids: half from shared buckets, half uniform."""
+    rng = np.random.default_rng(seed)
+    sk = sorted_keys.cpu().numpy()
+    se = sorted_ent.cpu().numpy() // bands
+    half = n_pairs // 2
+    same_next = sk[1:] == sk[:-1]
+    cand = np.flatnonzero(same_next & (se[1:] != se[:-1]))   # entry i pairs with i + 1
+    pick = rng.choice(cand, half, replace=cand.shape[0] < half)
+    left_b, right_b = se[pick], se[pick + 1]
+    left_r = rng.integers(0, n, n_pairs - half)
+    right_r = rng.integers(0, n, n_pairs - half)
+    keep = left_r != right_r
+    left = np.concatenate([left_b, left_r[keep]]).astype(np.int32)
+    right = np.concatenate([right_b, right_r[keep]]).astype(np.int32)
+    perm = rng.permutation(left.shape[0])
+    return left[perm], right[perm]
+
+
+def exact_pair_j(D: pm.DevicePolys, left: np.ndarray, right: np.ndarray) -> torch.Tensor:
+    """Exact J of (left[i], right[i]) by the refinement kernel: pairs grouped
+    by left polygon as the 'query', so no polygon is copied."""
+    order = np.argsort(left, kind="stable")
+    lo = left[order]
+    counts = np.bincount(lo, minlength=D.n)
+    off = np.zeros(D.n + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    dev = D.offsets.device
+    J = pm.refine(D, D, torch.from_numpy(off).to(dev), torch.from_numpy(right[order]).to(dev))
+    out = torch.empty_like(J)
+    out[torch.from_numpy(order).to(dev)] = J
+    return out
+
+
+class Trainer:
+    def __init__(self, scorer: Scorer, batch: int = BATCH, lr: float = 1e-3):
+        self.s = scorer
+        self.batch = batch
+        self.lr = lr
+        dev = scorer.params.device
+        self.X = torch.empty((batch, 288), dtype=torch.int16, device=dev)
+        self.acts, self.scratch = pm.mlp_buffers(batch, dev)
+        self.grad = torch.empty_like(scorer.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    def step(self, sig, feats, li, ri, label):
+        """One Adam step on pairs (li, ri) of the table (sig, feats)."""
+        pm.pair_features(sig, feats, sig, feats, li, ri, R_pad=self.batch, out=self.X)
+        pm.mlp_forward(self.X, self.s.params, self.s.wbf16, self.acts)
+        lab = torch.zeros(self.batch, dtype=torch.float32, device=label.device)
+        lab[:label.numel()] = label
+        pm.mlp_backward(self.X, self.s.params, self.s.wbf16, self.acts, lab, self.grad, self.loss,
+                        self.scratch)
+        self.s.step += 1
+        pm.mlp_adam(self.s.params, self.grad, self.s.m, self.s.v, self.s.step, self.s.wbf16, lr=self.lr)
+        return self.loss
+
+
+def train(scorer: Scorer, sig, feats, left, right, label, epochs: int = 3, batch: int = BATCH,
+          lr: float = 1e-3, seed: int = 0, log=None):
+    """Mini-batch Adam over the pair set; batches are whole (the remainder of
+    an epoch is dropped)."""
+    tr = Trainer(scorer, batch, lr)
+    n = left.shape[0]
+    rng = np.random.default_rng(seed)
+    dev = sig.device
+    L = torch.from_numpy(left).to(dev)
+    R = torch.from_numpy(right).to(dev)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).to(dev)
+        tot, cnt = 0.0, 0
+        t0 = time.perf_counter()
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            loss = tr.step(sig, feats, L[idx].contiguous(), R[idx].contiguous(), label[idx].contiguous())
+            if (b0 // batch) % 16 == 0:
+                tot += float(loss.item())
+                cnt += 1
+        torch.cuda.synchronize()
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.5f} ({time.perf_counter() - t0:.2f} s)")
+    return hist
+
+
+def predict_pairs(scorer: Scorer, lsig, lfeat, rsig, rfeat, li, ri, chunk: int = 1 << 18):
+    """Predicted J of every (li, ri) pair, in chunks of `chunk` rows."""
+    R = li.numel()
+    dev = lsig.device
+    out = torch.empty(max(R, 1), dtype=torch.float32, device=dev)
+    rows = min(chunk, ((R + 31) // 32) * 32) if R else 32
+    X = torch.empty((rows, 288), dtype=torch.int16, device=dev)
+    acts, _ = pm.mlp_buffers(rows, dev)
+    yb = torch.empty(rows, dtype=torch.float32, device=dev)
+    for c0 in range(0, R, rows):
+        c1 = min(R, c0 + rows)
+        pad = ((c1 - c0 + 31) // 32) * 32
+        pm.pair_features(lsig, lfeat, rsig, rfeat, li[c0:c1], ri[c0:c1], R_pad=pad, out=X)
+        pm.mlp_forward(X[:pad], scorer.params, scorer.wbf16, acts, y=yb)
+        out[c0:c1] = yb[:c1 - c0]
+    return out[:R]
+
+
+def candidate_scores(kind: str, scorer, qsig, qfeat, dsig, dfeat, cand_off, cand_ids):
+    """Per-candidate predicted J: 'mlp' (the scorer) or 'jhat' (collision fraction)."""
+    rows = pm.csr_rows(cand_off, cand_ids.numel())
+    if kind == "jhat":
+        return pm.jhat(qsig, dsig, rows, cand_ids)
+    return predict_pairs(scorer, qsig, qfeat, dsig, dfeat, rows, cand_ids)

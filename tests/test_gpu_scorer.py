@@ -1,0 +1,183 @@
+"""GPU parity of the learned scorer: MFMA products, forward, backward and
+Adam against the FP64 oracle on identical BF16-rounded weights and inputs;
+features; ranked refinement; a short training run."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as om
+from paper_2511_16576_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_16576_amd import polymh
+    polymh.check_device()
+    return polymh
+
+
+def _bf16_bits(x):
+    r = om.bf16_round(np.asarray(x, dtype=np.float32))
+    return (r.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("M,N,K", [(32, 32, 16), (64, 96, 48), (128, 288, 256)])
+def test_gemm_bf16_layouts(pm, M, N, K):
+    rng = np.random.default_rng(M + N + K)
+    A = om.bf16_round(rng.normal(size=(M, K)).astype(np.float32)).astype(np.float64)
+    B = om.bf16_round(rng.normal(size=(K, N)).astype(np.float32)).astype(np.float64)
+    want = A @ B
+    Ab, Bb = _bf16_bits(A), _bf16_bits(B)
+    # A row-major (k contiguous) and B stored as [N][K] (k contiguous)
+    C1 = pm.gemm_bf16(_cuda(Ab), K, 1, _cuda(np.ascontiguousarray(Bb.T)), K, 1, M, N, K).cpu().numpy()
+    # A stored transposed [K][M] and B row-major [K][N] (strided k)
+    C2 = pm.gemm_bf16(_cuda(np.ascontiguousarray(Ab.T)), 1, M, _cuda(Bb), 1, N, M, N, K).cpu().numpy()
+    tol = 1e-5 * np.abs(A) @ np.abs(B) + 1e-6
+    assert np.all(np.abs(C1 - want) <= tol)
+    assert np.all(np.abs(C2 - want) <= tol)
+
+
+def _setup(pm, B, seed=0):
+    import torch
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, 0.05, om.N_PARAMS).astype(np.float32)
+    p[om.OFF_W1:om.OFF_B1] = om.bf16_round(p[om.OFF_W1:om.OFF_B1])
+    p[om.OFF_W2:om.OFF_B2] = om.bf16_round(p[om.OFF_W2:om.OFF_B2])
+    X = om.bf16_round(rng.normal(0, 1, (B, om.N_IN)).astype(np.float32))
+    lab = rng.random(B).astype(np.float32)
+    params = _cuda(p)
+    wbf16 = torch.empty(pm.mlp_bf16_count(), dtype=torch.int16, device="cuda")
+    pm.mlp_sync_bf16(params, wbf16)
+    return p.astype(np.float64), X.astype(np.float64), lab.astype(np.float64), params, wbf16, _cuda(_bf16_bits(X)), _cuda(lab)
+
+
+def test_forward_matches_oracle(pm):
+    B = 96
+    p, X, lab, params, wbf16, Xg, _ = _setup(pm, B)
+    acts, _ = pm.mlp_buffers(B)
+    y = pm.mlp_forward(Xg, params, wbf16, acts).cpu().numpy()
+    want = om.forward(X, p)["y"]
+    # hidden activations are rounded to BF16 between layers on the GPU
+    assert np.abs(y - want).max() < 2 ** -7 * math.sqrt(om.N_IN) * 0.05
+
+
+def test_backward_matches_oracle(pm):
+    import torch
+    B = 128
+    p, X, lab, params, wbf16, Xg, labg = _setup(pm, B, seed=1)
+    acts, scratch = pm.mlp_buffers(B)
+    pm.mlp_forward(Xg, params, wbf16, acts)
+    grad = torch.empty_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    pm.mlp_backward(Xg, params, wbf16, acts, labg, grad, loss, scratch)
+    g = grad.cpu().numpy().astype(np.float64)
+    want = om.backward(X, p, lab)
+    assert abs(float(loss.item()) - om.loss(X, p, lab)) < 1e-3
+    for a, b in [(om.OFF_W1, om.OFF_B1), (om.OFF_B1, om.OFF_W2), (om.OFF_W2, om.OFF_B2),
+                 (om.OFF_B2, om.OFF_W3), (om.OFF_W3, om.OFF_B3), (om.OFF_B3, om.N_PARAMS)]:
+        num = np.linalg.norm(g[a:b] - want[a:b])
+        den = np.linalg.norm(want[a:b]) + 1e-12
+        assert num / den < 0.03, (a, b, num / den)
+
+
+def test_adam_matches_oracle(pm):
+    import torch
+    rng = np.random.default_rng(2)
+    P = om.N_PARAMS
+    p = rng.normal(0, 0.1, P).astype(np.float32)
+    params = _cuda(p.copy())
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    wbf16 = torch.empty(pm.mlp_bf16_count(), dtype=torch.int16, device="cuda")
+    po, mo, vo = p.astype(np.float64), np.zeros(P), np.zeros(P)
+    for step in (1, 2, 3):
+        g = rng.normal(0, 1, P).astype(np.float32)
+        pm.mlp_adam(params, _cuda(g), m, v, step, wbf16, lr=1e-3)
+        po, mo, vo = om.adam_step(po, g.astype(np.float64), mo, vo, step, lr=1e-3)
+    assert np.abs(params.cpu().numpy() - po).max() < 1e-6
+    w1 = wbf16[: om.N_HID * om.N_IN].cpu().numpy()
+    assert np.array_equal(w1, _bf16_bits(params.cpu().numpy()[om.OFF_W1:om.OFF_B1]))
+
+
+def test_features_match_oracle(pm):
+    import torch
+    w = dg.workload(2, n=300, n_queries=20)
+    D, Q = pm.to_device(w.data), pm.to_device(w.queries)
+    fd = pm.poly_features(D, w.box).cpu().numpy()
+    fq = pm.poly_features(Q, w.box).cpu().numpy()
+    for p in range(0, 300, 7):
+        want = om.poly_features(w.data.poly(p), w.box)
+        assert np.allclose(fd[p], want, rtol=1e-5, atol=1e-5), p
+    sd = pm.sign(D, w.box, 0, 256, w.cap)
+    sq = pm.sign(Q, w.box, 0, 256, w.cap)
+    li = np.repeat(np.arange(20, dtype=np.int32), 5)
+    ri = np.random.default_rng(0).integers(0, 300, 100).astype(np.int32)
+    ri[::5] = w.query_source[:20]
+    X = pm.pair_features(sq, _cuda(fq), sd, _cuda(fd), _cuda(li), _cuda(ri), R_pad=128).cpu().numpy()
+    sdn, sqn = sd.cpu().numpy(), sq.cpu().numpy()
+    jh = pm.jhat(sq, sd, _cuda(li), _cuda(ri)).cpu().numpy()
+    for r in range(100):
+        row = om.pair_features(sqn[li[r]], fq[li[r]].astype(np.float64), sdn[ri[r]], fd[ri[r]].astype(np.float64))
+        got = om.bf16_bits_to_f64(X[r])
+        want = om.bf16_round(row.astype(np.float32)).astype(np.float64)
+        assert np.array_equal(got[:256], want[:256]), r
+        assert np.allclose(got[256:], want[256:], rtol=2 ** -7, atol=1e-6), r
+        assert jh[r] == row[271]
+    assert (X[100:] == 0).all()
+
+
+def test_rank_refine_fallback_and_perfect_scores(pm, orc):
+    import torch
+    w = dg.workload(1, n=400, n_queries=12)
+    D, Q = pm.to_device(w.data), pm.to_device(w.queries)
+    off = torch.arange(13, device="cuda", dtype=torch.int64) * 400
+    ids = torch.arange(400, device="cuda", dtype=torch.int32).repeat(12)
+    J = pm.refine(D, Q, off, ids)
+    ti, tj = pm.topk(off, ids, J, 10)
+    rng = torch.from_numpy(np.random.default_rng(0).random(4800).astype(np.float32)).cuda()
+    # margin = +inf: everything is refined, result equals refine + top-k
+    a_ids, a_j, nref, _ = pm.rank_refine(D, Q, off, ids, rng, topk=10, F=32, margin=float("inf"))
+    assert nref == 4800
+    assert torch.equal(a_ids, ti) and torch.equal(a_j, tj)
+    # exact scores and margin 0: the exact top-10 with fewer refinements
+    b_ids, b_j, nref2, rounds = pm.rank_refine(D, Q, off, ids, J.float(), topk=10, F=8, margin=0.0)
+    assert nref2 < 4800
+    assert np.allclose(b_j.cpu().numpy(), tj.cpu().numpy(), rtol=0, atol=1e-6)
+
+
+def test_short_training_reduces_loss(pm, orc):
+    import torch
+    from paper_2511_16576_amd import scorer as sc
+    w = dg.workload(2, n=4000, n_queries=0)
+    D = pm.to_device(w.data)
+    sig = pm.sign(D, w.box, 0, 256, w.cap)
+    keys = pm.band(sig, 32, 8, 0)
+    sk, se = pm.index_build(keys)
+    left, right = sc.mine_pairs(sk, se, D.n, 32, 40000, seed=0)
+    J = sc.exact_pair_j(D, left, right).float()
+    # labels agree with the oracle on a sample
+    for i in range(0, 400, 40):
+        ex = orc.jaccard(w.data.poly(left[i]), w.data.poly(right[i]))
+        assert abs(float(J[i]) - ex) <= 1e-6
+    feats = pm.poly_features(D, w.box)
+    s = sc.init_scorer(0)
+    hist = sc.train(s, sig, feats, left, right, J, epochs=4, batch=2048, lr=1e-3)
+    assert hist[-1] < 0.6 * hist[0]
+    Lg, Rg = torch.from_numpy(left).cuda(), torch.from_numpy(right).cuda()
+    pred = sc.predict_pairs(s, sig, feats, sig, feats, Lg, Rg)
+    jh = pm.jhat(sig, sig, Lg, Rg)
+    mse_mlp = float(((pred - J) ** 2).mean())
+    mse_jhat = float(((jh - J) ** 2).mean())
+    print(f"train MSE: scorer {mse_mlp:.5f}, collision fraction {mse_jhat:.5f}")
+    assert mse_mlp < 0.05
