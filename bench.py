@@ -31,6 +31,11 @@ PEAK_VALU = 256 * 4 * 16 * 2.4e9      # lane-cycles/s: 256 CUs x 4 SIMD16 x 2.4 
 # point-in-polygon loop.
 C_DRAW = 26 + 6 * 4
 C_EDGE = 14
+# VALU instructions per lane of one 8 x 8 edge-pair tile of the tiled
+# refinement (counted in the built code: 60 FP64, 22 int->FP64 conversions,
+# compares and selects) and per edge pair of its general per-edge form.
+C_TILE = 114
+C_GENERAL = 40
 
 
 def log(msg):
@@ -47,6 +52,14 @@ def parse():
     ap.add_argument("--rows", type=int, default=4)
     ap.add_argument("--recall-sample", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-queries", type=int, default=1000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 256 MiB device-to-device once (reference for HBM counters)")
+    ap.add_argument("--train-pairs", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=3)
     return ap.parse_args()
 
 
@@ -70,13 +83,20 @@ def main():
     D, Q = pm.to_device(w.data), pm.to_device(w.queries)
     k, cap, b, r = w.k, w.cap, args.bands, args.rows
     cfg = pm.default_sign_config()
+    tune = None
+    if not args.no_tune:
+        from paper_2511_16576_amd import autotune
+        t0 = time.time()
+        cfg, tune = autotune.tune_sign(w.data, w.box, w.seed, k, cap, sample=20000, reps=2)
+        log(f"autotuned signing shape {cfg.as_dict()} in {time.time() - t0:.1f}s "
+            f"({tune['ms']:.3f} ms on the sample vs default {tune.get('default_ms')})")
     dev = D.offsets.device
     ws_d = torch.empty(pm.sign_workspace_size(D.n, cfg), dtype=torch.uint8, device=dev)
     ws_q = torch.empty(pm.sign_workspace_size(Q.n, cfg), dtype=torch.uint8, device=dev)
     sig = torch.empty((D.n, k), dtype=torch.int32, device=dev)
     qsig = torch.empty((Q.n, k), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    names = ["sign", "band+index", "qsign+qband", "query", "refine", "topk"]
+    names = ["sign", "band+index", "qsign", "qband", "query", "refine", "topk"]
 
     def step(times=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] if times is not None else None
@@ -87,20 +107,28 @@ def main():
         sk, si = pm.index_build(keys)
         if ev: ev[2].record(stream)
         pm.sign(Q, w.box, w.seed, k, cap, config=cfg, out=qsig, ws=ws_q)
-        qkeys = pm.band(qsig, b, r, w.seed)
         if ev: ev[3].record(stream)
-        off, ids = pm.query(sk, si, D.n, qkeys)
+        qkeys = pm.band(qsig, b, r, w.seed)
         if ev: ev[4].record(stream)
-        J = pm.refine(D, Q, off, ids)
+        off, ids = pm.query(sk, si, D.n, qkeys)
         if ev: ev[5].record(stream)
-        ti, tj = pm.topk(off, ids, J, 10)
+        J = pm.refine(D, Q, off, ids)
         if ev: ev[6].record(stream)
+        ti, tj = pm.topk(off, ids, J, 10)
+        if ev: ev[7].record(stream)
         if times is not None:
             torch.cuda.synchronize()
             for i, nmk in enumerate(names):
                 times.setdefault(nmk, []).append(ev[i].elapsed_time(ev[i + 1]))
         return off, ids, ti, tj
 
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 256 MiB device-to-device (counter reference)")
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -122,34 +150,91 @@ def main():
     off, ids, ti, tj = out
     n_cand = int(ids.numel())
 
-    # realised draws (sum of signature values = Alg. 1's attempts) and the
-    # expected point-in-polygon edge tests, for the signing roofline
-    s_np = sig.cpu().numpy().view(np.uint32).astype(np.float64)
-    draws = float(s_np.sum()) + float((s_np == 0).sum()) * cap
-    mbr, area2, flags = pm.prepare(D)
-    mbr = mbr.cpu().numpy().astype(np.float64)
-    a_mbr = (mbr[:, 2] - mbr[:, 0] + 1) * (mbr[:, 3] - mbr[:, 1] + 1)
-    a_p = np.maximum(np.abs(area2.cpu().numpy().astype(np.float64)) / 2, 0.5)
-    nverts = np.diff(w.data.offsets).astype(np.float64)
-    edges = float((k * nverts * np.minimum(a_mbr / a_p, s_np.mean(axis=1))).sum())
-    sign_ops = draws * C_DRAW + edges * C_EDGE
-    t_sign = stage_ms["sign"] / 1e3
-    achieved = sign_ops / t_sign
+    # -- signing roofline (k_sign; VALU-issue bound).  Algorithmic work of a
+    # launch: the realised Alg. 1 draws (the sum of the produced signature
+    # values, a 0 counting as cap draws) times C_DRAW plus the expected
+    # point-in-polygon edge tests times C_EDGE.  Averaged over the two launches
+    # of a step (dataset and queries), as rocprof averages the kernel.
+    def sign_work(s_t, polys):
+        s_np = s_t.cpu().numpy().view(np.uint32).astype(np.float64)
+        draws = float(s_np.sum()) + float((s_np == 0).sum()) * cap
+        mbr, area2, _ = pm.prepare(polys)
+        mbr = mbr.cpu().numpy().astype(np.float64)
+        a_mbr = (mbr[:, 2] - mbr[:, 0] + 1) * (mbr[:, 3] - mbr[:, 1] + 1)
+        a_p = np.maximum(np.abs(area2.cpu().numpy().astype(np.float64)) / 2, 0.5)
+        nverts = (polys.offsets[1:] - polys.offsets[:-1]).cpu().numpy().astype(np.float64)
+        edges = float((k * nverts * np.minimum(a_mbr / a_p, s_np.mean(axis=1))).sum())
+        return draws, edges
+    dw_d, ed_d = sign_work(sig, D)
+    dw_q, ed_q = sign_work(qsig, Q)
+    t_sign_avg = 0.5 * (stage_ms["sign"] + stage_ms["qsign"]) / 1e3
+    work_sign = 0.5 * ((dw_d + dw_q) * C_DRAW + (ed_d + ed_q) * C_EDGE)
+    roof_sign = {"bound": "alu", "achieved": work_sign / t_sign_avg / 1e12, "peak": PEAK_VALU / 1e12,
+                 "unit": "T lane-cycles/s", "frac": work_sign / t_sign_avg / PEAK_VALU, "traffic": None,
+                 "kernel": "k_sign", "launch_ms": 1e3 * t_sign_avg,
+                 "draws_per_launch": 0.5 * (dw_d + dw_q), "edge_tests_per_launch": 0.5 * (ed_d + ed_q)}
+    # -- refinement roofline (k_refine; FP64 VALU bound).  Algorithmic work:
+    # the edge pairs the tiled form tests (8 x 8 tiles of chunk pairs whose
+    # boxes overlap) times C_TILE per lane, plus the general form's edge pairs.
+    _, rstats = pm.refine_stats(D, Q, off, ids)
+    tested = 64.0 * rstats[1] + rstats[2]
+    t_ref = stage_ms["refine"] / 1e3
+    work_ref = 64.0 * rstats[1] * C_TILE + rstats[2] * C_GENERAL
+    roof_ref = {"bound": "alu", "achieved": work_ref / t_ref / 1e12, "peak": PEAK_VALU / 1e12,
+                "unit": "T lane-cycles/s", "frac": work_ref / t_ref / PEAK_VALU, "traffic": None,
+                "kernel": "k_refine", "launch_ms": 1e3 * t_ref, "pairs": n_cand,
+                "tiled_pairs": rstats[0], "tiles": rstats[1], "general_edge_pairs": rstats[2],
+                "disjoint_pairs": rstats[3], "edge_pairs_tested": tested}
+    dominant = roof_ref if t_ref > t_sign_avg * 2 else roof_sign
 
-    # recall@10 on a query sample against GPU brute force (all pairs refined)
+    # recall@10 on a query sample against GPU brute force (all pairs refined
+    # by the parity-tested refinement kernel)
     rs = min(args.recall_sample, Q.n)
     rec = None
     if rs > 0:
-        import oracle  # noqa: F401  (recall helper only; the brute force runs on the GPU)
-        qs = np.arange(rs)
-        Qs = pm.to_device(w.queries.subset(qs))
-        bf_off = torch.arange(rs + 1, device=dev, dtype=torch.int64) * D.n
-        bf_ids = torch.arange(D.n, device=dev, dtype=torch.int32).repeat(rs)
-        bfJ = pm.refine(D, Qs, bf_off, bf_ids)
-        bi, bj = pm.topk(bf_off, bf_ids, bfJ, 10)
-        rec = oracle.recall_at_k(ti[:rs].cpu().numpy(), tj[:rs].cpu().numpy(), bi.cpu().numpy(),
-                                 bj.cpu().numpy(), 10)
+        from paper_2511_16576_amd.metrics import recall_at_k
+        from paper_2511_16576_amd.scorer import brute_force_top10
+        Qs = pm.to_device(w.queries.subset(np.arange(rs)))
+        bi, bj = brute_force_top10(D, Qs)
+        rec = recall_at_k(ti[:rs].cpu().numpy(), tj[:rs].cpu().numpy(), bi.cpu().numpy(),
+                          bj.cpu().numpy(), 10)
         log(f"recall@10 over {rs} queries: {rec:.3f}")
+
+    batched = None
+    if not args.no_batched:
+        from paper_2511_16576_amd.pipeline import QueryBatch
+        nb = args.batch_queries
+        sig_d = torch.empty((D.n, k), dtype=torch.int32, device=dev)
+        pm.sign(D, w.box, w.seed, k, cap, config=cfg, out=sig_d, ws=ws_d)
+        sk_b, se_b = pm.index_build(pm.band(sig_d, b, r, w.seed))
+        bl = [w.queries.subset(np.arange(i, i + nb)) for i in range(0, Q.n - nb + 1, nb)]
+        maxv = max(x.xy.shape[0] for x in bl)
+        cand_cap = int(4 * n_cand / Q.n * nb) + 1024
+        qb = QueryBatch(D, sk_b, se_b, w.box, w.seed, k, cap, b, r, nb, maxv, cand_cap, sign_config=cfg)
+        qb.load(bl[0])
+        qb.capture()
+        res = {}
+        for mode in ("eager", "graph"):
+            t_tot = 0.0
+            for rep in range(2):
+                for x in bl:
+                    qb.load(x)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    (qb.run_graph if mode == "graph" else qb.run_eager)()
+                    qb.stream.synchronize()
+                    if rep:
+                        t_tot += time.perf_counter() - t0
+            res[mode] = {"queries_per_s": len(bl) * nb / t_tot, "ms_per_batch": 1e3 * t_tot / len(bl)}
+        qb.result()
+        batched = {"batch_queries": nb, **res}
+        log(f"batched queries: eager {res['eager']['queries_per_s']:.0f} q/s, graph "
+            f"{res['graph']['queries_per_s']:.0f} q/s ({nb} per batch)")
+
+    learned = None
+    if not args.no_learned:
+        from paper_2511_16576_amd import scorer as sc
+        learned = sc.learned_comparison(w, D, Q, log, n_pairs=args.train_pairs, epochs=args.epochs)
 
     cpu = None
     if not args.no_cpu:
@@ -182,15 +267,17 @@ def main():
                                "R 2-15% of a 2^24 grid; k=128, cap 2^22; 10,000 queries (2% jitter)",
                    "n_data": D.n, "n_queries": Q.n, "k": k, "bands": b, "rows": r,
                    "sign_config": cfg.as_dict()},
-        "sign_sig_per_s": D.n * k / t_sign,
+        "sign_sig_per_s": D.n * k / (stage_ms["sign"] / 1e3),
         "queries_per_s": Q.n / (sum(stage_ms[s] for s in names[2:]) / 1e3),
         "candidates_per_query": n_cand / Q.n,
         "recall_at_10": rec,
         "stage_ms": stage_ms,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12,
-                     "unit": "T lane-cycles/s", "frac": achieved / PEAK_VALU, "traffic": None,
-                     "kernel": "k_sign", "draws_per_launch": draws, "edge_tests_per_launch": edges},
+        "roofline": dominant,
+        "roofline_kernels": {"k_sign": roof_sign, "k_refine": roof_ref},
         "cpu_baseline": cpu,
+        "autotune": tune,
+        "batched": batched,
+        "learned": learned,
     }
     print(json.dumps(line), flush=True)
 

@@ -179,6 +179,17 @@ polymh_status polymh_query(const uint64_t *sorted_keys, const int32_t *sorted_id
                            int32_t b, void *ws, size_t ws_bytes, int64_t *cand_off,
                            int32_t *cand_ids, int64_t cand_cap, void *stream);
 
+/* polymh_query_capped -- both phases of polymh_query in one stream-ordered
+ * call with no host synchronisation (so it can be captured in a graph):
+ * cand_off and cand_ids as above; if the total exceeds cand_cap, *overflow
+ * (device int32) is set to 1, every cand_off entry is set to 0 (later stages
+ * then see no candidates) and cand_ids is untouched; otherwise *overflow = 0.
+ * The caller re-runs with a larger capacity after reading the flag. */
+polymh_status polymh_query_capped(const uint64_t *sorted_keys, const int32_t *sorted_ids,
+                                  int64_t n_entries, int64_t n_data, const uint64_t *qkeys, int64_t nq,
+                                  int32_t b, void *ws, size_t ws_bytes, int64_t *cand_off,
+                                  int32_t *cand_ids, int64_t cand_cap, int32_t *overflow, void *stream);
+
 /* ---------------------------------------------------------------------------
  * polymh_refine -- exact Jaccard of each candidate pair (Sec. 1: area of the
  * intersection over area of the union; Table 2's refinement phase).
@@ -194,6 +205,14 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, void *stream);
 
+/* polymh_refine_stats -- polymh_refine that also adds its work counts to
+ * stats [4] (device uint64, caller-zeroed): pairs refined by the tiled form,
+ * 8 x 8 edge-pair tiles tested there, edge pairs tested by the general form,
+ * and pairs skipped because their MBRs are disjoint.  Stream-ordered. */
+polymh_status polymh_refine_stats(const polymh_polys *data, const polymh_polys *queries,
+                                  const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                                  int64_t n_cand, double *cand_j, uint64_t *stats, void *stream);
+
 /* ---------------------------------------------------------------------------
  * polymh_topk -- Def. 1 / K-ANN: per query the `topk` candidates with the
  * largest J, ties by ascending id; rows padded with id -1 and J 0.
@@ -203,6 +222,20 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
 polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, const double *cand_j,
                           int64_t nq, int32_t topk, int32_t *top_ids, double *top_j,
                           void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Graph capture (batching form): record the stream-ordered libpolymh calls a
+ * caller issues on `stream` between polymh_graph_begin and polymh_graph_end
+ * into a HIP graph, then replay it with polymh_graph_launch (same buffers,
+ * new contents).  Calls that synchronise (polymh_box_of, polymh_query with a
+ * capacity check, polymh_rank_refine) must not be captured; use
+ * polymh_query_capped.  The handle is owned by the caller and released by
+ * polymh_graph_destroy. */
+typedef struct polymh_graph_t *polymh_graph;
+polymh_status polymh_graph_begin(void *stream);
+polymh_status polymh_graph_end(void *stream, polymh_graph *out_host);
+polymh_status polymh_graph_launch(polymh_graph graph, void *stream);
+void polymh_graph_destroy(polymh_graph graph);
 
 /* ---------------------------------------------------------------------------
  * Learned candidate scorer (an AI-systems form beside the method; not in the
@@ -277,6 +310,22 @@ polymh_status polymh_csr_rows(const int64_t *cand_off, int64_t nq, int32_t *rows
  * agree: the unbiased estimate of J of Thm. 1.  Stream-ordered. */
 polymh_status polymh_jhat(const uint32_t *lsig, const uint32_t *rsig, int32_t k, const int32_t *li,
                           const int32_t *ri, int64_t R, float *out, void *stream);
+
+/* The head of each query's candidate order: order [n_cand] (int32) receives
+ * each query's candidate positions sorted by decreasing score (ties by
+ * position; sorted_ok [nq] = 0 marks queries beyond 8192 candidates, left in
+ * their given order); head_off [nq+1] (int64, CSR) with head_query (int32
+ * query), head_cand (int64 global candidate index) and head_id (int32 data
+ * polygon) list the first min(M, C_q) candidates of each query.  A cascade
+ * uses it to re-score only the most promising candidates with the scorer.
+ * The head arrays hold at most nq * M entries.  Stream-ordered. */
+polymh_status polymh_rank_head(const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                               const float *score, int32_t M, int32_t *order, uint8_t *sorted_ok,
+                               int64_t *head_off, int32_t *head_query, int64_t *head_cand,
+                               int32_t *head_id, void *stream);
+/* score[idx[i]] = val[i] for i < n.  Stream-ordered. */
+polymh_status polymh_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,
+                                    void *stream);
 
 /* Ordered refinement with early stop.  Each query's candidates are visited in
  * decreasing score (predicted J; ties by position) and refined (as

@@ -296,6 +296,22 @@ polymh_status polymh_query(const uint64_t *sorted_keys, const int32_t *sorted_id
                         cand_off, cand_ids, s);
 }
 
+polymh_status polymh_query_capped(const uint64_t *sorted_keys, const int32_t *sorted_ids,
+                                  int64_t n_entries, int64_t n_data, const uint64_t *qkeys, int64_t nq,
+                                  int32_t b, void *ws, size_t ws_bytes, int64_t *cand_off,
+                                  int32_t *cand_ids, int64_t cand_cap, int32_t *overflow, void *stream)
+{
+    if (n_entries < 0 || n_data < 0 || nq < 0 || b < 1 || cand_cap < 0)
+        return set_error(POLYMH_EINVAL, "query_capped: bad sizes");
+    if (!cand_off || !overflow || (cand_cap > 0 && !cand_ids))
+        return set_error(POLYMH_EINVAL, "query_capped: NULL output");
+    if (nq > 0 && !qkeys) return set_error(POLYMH_EINVAL, "query_capped: qkeys is NULL");
+    if (n_entries > 0 && (!sorted_keys || !sorted_ids))
+        return set_error(POLYMH_EINVAL, "query_capped: NULL bucket table");
+    return launch_query_capped(sorted_keys, sorted_ids, n_entries, n_data, qkeys, nq, b, ws, ws_bytes,
+                               cand_off, cand_ids, cand_cap, overflow, as_stream(stream));
+}
+
 polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, void *stream)
@@ -308,6 +324,21 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
     if (!cand_off || !cand_ids || !cand_j) return set_error(POLYMH_EINVAL, "refine: NULL array");
     return launch_refine(data, queries, cand_off, cand_ids, nq, n_cand, cand_j, as_stream(stream));
+}
+
+polymh_status polymh_refine_stats(const polymh_polys *data, const polymh_polys *queries,
+                                  const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                                  int64_t n_cand, double *cand_j, uint64_t *stats, void *stream)
+{
+    polymh_status st = check_polys(data, "refine_stats");
+    if (st) return st;
+    if ((st = check_polys(queries, "refine_stats"))) return st;
+    if (nq != queries->n) return set_error(POLYMH_EINVAL, "refine_stats: nq differs from the query count");
+    if (n_cand < 0 || !stats) return set_error(POLYMH_EINVAL, "refine_stats: bad arguments");
+    if (n_cand == 0 || nq == 0) return POLYMH_OK;
+    if (!cand_off || !cand_ids || !cand_j) return set_error(POLYMH_EINVAL, "refine_stats: NULL array");
+    return launch_refine(data, queries, cand_off, cand_ids, nq, n_cand, cand_j, as_stream(stream),
+                         reinterpret_cast<unsigned long long *>(stats));
 }
 
 polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, const double *cand_j,
@@ -424,6 +455,32 @@ polymh_status polymh_jhat(const uint32_t *lsig, const uint32_t *rsig, int32_t k,
     if (R == 0) return POLYMH_OK;
     if (!lsig || !rsig || !li || !ri || !out) return set_error(POLYMH_EINVAL, "jhat: NULL array");
     return launch_jhat(lsig, rsig, li, ri, R, k, out, as_stream(stream));
+}
+
+polymh_status polymh_rank_head(const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                               const float *score, int32_t M, int32_t *order, uint8_t *sorted_ok,
+                               int64_t *head_off, int32_t *head_query, int64_t *head_cand,
+                               int32_t *head_id, void *stream)
+{
+    if (nq < 0 || M < 1) return set_error(POLYMH_EINVAL, "rank_head: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !cand_ids || !score || !order || !sorted_ok || !head_off || !head_query ||
+        !head_cand || !head_id)
+        return set_error(POLYMH_EINVAL, "rank_head: NULL array");
+    hipStream_t s = as_stream(stream);
+    polymh_status st = launch_rank_sort(cand_off, nq, score, order, sorted_ok, s);
+    if (st) return st;
+    return launch_head_select(cand_off, cand_ids, nq, order, M, head_off, head_query, head_cand,
+                              head_id, s);
+}
+
+polymh_status polymh_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,
+                                    void *stream)
+{
+    if (n < 0) return set_error(POLYMH_EINVAL, "scatter_scores: negative count");
+    if (n == 0) return POLYMH_OK;
+    if (!idx || !val || !score) return set_error(POLYMH_EINVAL, "scatter_scores: NULL array");
+    return launch_scatter_scores(idx, val, n, score, as_stream(stream));
 }
 
 struct RankWs {

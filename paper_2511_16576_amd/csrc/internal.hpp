@@ -106,7 +106,8 @@ polymh_status launch_query(const uint64_t *skeys, const int32_t *sids, int64_t n
 // refine.hip
 polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
-                            int64_t n_cand, double *cand_j, hipStream_t s);
+                            int64_t n_cand, double *cand_j, hipStream_t s,
+                            unsigned long long *stats = nullptr);
 
 // topk.hip
 polymh_status launch_topk(const int64_t *off, const int32_t *ids, const double *js, int64_t nq,
@@ -138,6 +139,11 @@ polymh_status launch_csr_rows(const int64_t *off, int64_t nq, int32_t *rows, hip
 
 // rank.hip
 int32_t rank_sort_cap();
+polymh_status launch_head_select(const int64_t *off, const int32_t *cand_ids, int64_t nq,
+                                 const int32_t *order, int32_t M, int64_t *hoff, int32_t *hq,
+                                 int64_t *hc, int32_t *hid, hipStream_t s);
+polymh_status launch_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,
+                                    hipStream_t s);
 polymh_status launch_rank_sort(const int64_t *off, int64_t nq, const float *score, int32_t *order,
                                uint8_t *sorted_ok, hipStream_t s);
 polymh_status launch_rank_init(int64_t nq, int32_t topk, int64_t *cursor, uint8_t *active,
@@ -155,6 +161,10 @@ polymh_status launch_round_merge(const int64_t *off, const float *score, const i
 polymh_status launch_jhat(const uint32_t *lsig, const uint32_t *rsig, const int32_t *li,
                           const int32_t *ri, int64_t R, int32_t k, float *out, hipStream_t s);
 polymh_status launch_offsets(int64_t *off, int64_t nq, hipStream_t s);
+polymh_status launch_query_capped(const uint64_t *skeys, const int32_t *sids, int64_t n_entries,
+                                  int64_t n_data, const uint64_t *qkeys, int64_t nq, int32_t b,
+                                  void *ws, size_t ws_bytes, int64_t *cand_off, int32_t *cand_ids,
+                                  int64_t cand_cap, int32_t *overflow, hipStream_t s);
 
 // util
 polymh_status launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long v,

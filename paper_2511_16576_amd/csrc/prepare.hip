@@ -163,15 +163,31 @@ __global__ void k_order_scan(int32_t *counts)
     }
 }
 
+// Each block reserves, per bucket, one contiguous range of the order with a
+// single global atomic, then places its polygons inside it through LDS
+// atomics (one block-stride slice of polygons per pass).
 __global__ __launch_bounds__(256) void k_order_scatter(const int64_t *off, const int32_t *mbr,
                                                        const int64_t *area2, const uint32_t *flags,
                                                        int64_t n, double nb, int32_t k, double cap,
                                                        int32_t *counts, int32_t *order)
 {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int b = cost_bucket(off, mbr, area2, flags, p, nb, k, cap);
-        order[atomicAdd(&counts[kBuckets + b], 1)] = (int32_t)p;
+    __shared__ int32_t h[kBuckets];
+    __shared__ int32_t base[kBuckets];
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < n; p0 += (int64_t)gridDim.x * blockDim.x) {
+        if (threadIdx.x < kBuckets) h[threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t p = p0 + threadIdx.x;
+        int b = -1, rank = 0;
+        if (p < n) {
+            b = cost_bucket(off, mbr, area2, flags, p, nb, k, cap);
+            rank = atomicAdd(&h[b], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x < kBuckets && h[threadIdx.x])
+            base[threadIdx.x] = atomicAdd(&counts[kBuckets + threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+        if (b >= 0) order[base[b] + rank] = (int32_t)p;
+        __syncthreads();
     }
 }
 

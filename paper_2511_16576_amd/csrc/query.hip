@@ -125,6 +125,22 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ bitma
     }
 }
 
+// Capacity guard for graph-captured lookups: if the candidates do not fit,
+// raise the flag and empty every query's range so later stages see none.
+__global__ __launch_bounds__(256) void k_cap_guard(int64_t *__restrict__ off, int64_t nq, int64_t cap,
+                                                   int32_t *__restrict__ overflow)
+{
+    const int64_t total = off[nq];
+    if (total <= cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) overflow[0] = 0;
+        return;
+    }
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= nq;
+         q += (int64_t)gridDim.x * blockDim.x)
+        off[q] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) overflow[0] = 1;
+}
+
 int blocks_for(int64_t items, int per_block)
 {
     int64_t g = (items + per_block - 1) / per_block;
@@ -134,6 +150,29 @@ int blocks_for(int64_t items, int per_block)
 }
 
 }  // namespace
+
+polymh_status launch_query_capped(const uint64_t *skeys, const int32_t *sids, int64_t n_entries,
+                                  int64_t n_data, const uint64_t *qkeys, int64_t nq, int32_t b,
+                                  void *ws, size_t ws_bytes, int64_t *cand_off, int32_t *cand_ids,
+                                  int64_t cand_cap, int32_t *overflow, hipStream_t s)
+{
+    const int64_t words = (n_data + 31) / 32;
+    Carve cv{static_cast<char *>(ws), ws_bytes};
+    uint32_t *bitmap = cv.take<uint32_t>((size_t)(nq * words));
+    if (!cv.ok)
+        return set_error(POLYMH_ECAPACITY, "query_capped: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
+    if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "query_capped: too many queries");
+    if (nq * words > 0)
+        hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nq * words, 256)), dim3(256), 0, s, bitmap, nq * words);
+    if (n_entries > 0 && words > 0 && nq > 0)
+        hipLaunchKernelGGL(k_mark, dim3(blocks_for(nq * b, 4)), dim3(256), 0, s, skeys, sids, n_entries,
+                           qkeys, nq, b, bitmap, words);
+    if (nq > 0) hipLaunchKernelGGL(k_count, dim3((unsigned)nq), dim3(256), 0, s, bitmap, words, cand_off);
+    hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, cand_off, nq);
+    hipLaunchKernelGGL(k_cap_guard, dim3(blocks_for(nq + 1, 256)), dim3(256), 0, s, cand_off, nq, cand_cap, overflow);
+    if (nq > 0) hipLaunchKernelGGL(k_emit, dim3((unsigned)nq), dim3(256), 0, s, bitmap, words, cand_off, cand_ids);
+    return check_launch("query_capped");
+}
 
 polymh_status launch_offsets(int64_t *off, int64_t nq, hipStream_t s)
 {

@@ -157,6 +157,42 @@ __global__ void k_round_merge(const int64_t *__restrict__ off, const float *__re
 
 __global__ void k_zero_i32(int32_t *p) { if (threadIdx.x == 0) p[0] = 0; }
 
+// Head of each query's order: the first min(M, C_q) candidates, as (row of
+// the query, candidate index) pairs in a CSR of per-query counts.
+__global__ void k_head_count(const int64_t *__restrict__ off, int64_t nq, int32_t M,
+                             int64_t *__restrict__ counts)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = off[q + 1] - off[q];
+        counts[q] = c < M ? c : M;
+    }
+}
+
+__global__ void k_head_fill(const int64_t *__restrict__ off, const int32_t *__restrict__ cand_ids,
+                            const int32_t *__restrict__ order, const int64_t *__restrict__ hoff,
+                            int64_t nq, int32_t *__restrict__ hq, int64_t *__restrict__ hc,
+                            int32_t *__restrict__ hid)
+{
+    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int64_t b = hoff[q], cnt = hoff[q + 1] - b;
+        for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int64_t c = off[q] + order[off[q] + t];
+            hq[b + t] = (int32_t)q;
+            hc[b + t] = c;
+            hid[b + t] = cand_ids[c];
+        }
+    }
+}
+
+__global__ void k_scatter_scores(const int64_t *__restrict__ idx, const float *__restrict__ val,
+                                 int64_t n, float *__restrict__ score)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        score[idx[i]] = val[i];
+}
+
 __global__ __launch_bounds__(256) void k_jhat(const uint32_t *__restrict__ lsig,
                                               const uint32_t *__restrict__ rsig,
                                               const int32_t *__restrict__ li,
@@ -185,6 +221,27 @@ int g_of(int64_t items, int per)
 }  // namespace
 
 int32_t rank_sort_cap() { return kSortCap; }
+
+polymh_status launch_head_select(const int64_t *off, const int32_t *cand_ids, int64_t nq,
+                                 const int32_t *order, int32_t M, int64_t *hoff, int32_t *hq,
+                                 int64_t *hc, int32_t *hid, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_head_count, dim3(g_of(nq, 256)), dim3(256), 0, s, off, nq, M, hoff);
+    polymh_status st = launch_offsets(hoff, nq, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_head_fill, dim3(g_of(nq, 1)), dim3(64), 0, s, off, cand_ids, order, hoff, nq,
+                       hq, hc, hid);
+    return check_launch("head_select");
+}
+
+polymh_status launch_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,
+                                    hipStream_t s)
+{
+    if (n == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_scatter_scores, dim3(g_of(n, 256)), dim3(256), 0, s, idx, val, n, score);
+    return check_launch("scatter_scores");
+}
 
 polymh_status launch_rank_sort(const int64_t *off, int64_t nq, const float *score, int32_t *order,
                                uint8_t *sorted_ok, hipStream_t s)

@@ -360,7 +360,8 @@ __device__ double membership_term(RingLds R, int n, int w0, int s, int lane)
     return acc;
 }
 
-__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int lane)
+__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int lane,
+                             unsigned long long *tiles)
 {
     // ring-start memberships under Q + delta
     const int w0p = member_wave(Q, m, P.v[0], -1, lane);
@@ -377,6 +378,7 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
             ov = !(bp.z < bq.x || bq.z < bp.x || bp.w < bq.y || bq.w < bp.y);
         }
         uint64_t mk = __ballot(ov);
+        *tiles += (unsigned long long)__popcll(mk);
         while (mk) {
             const int k = __builtin_ctzll(mk);
             mk &= mk - 1;
@@ -431,7 +433,8 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                                                 const int64_t *__restrict__ qoff,
                                                 const int64_t *__restrict__ cand_off,
                                                 const int32_t *__restrict__ cand_ids,
-                                                double *__restrict__ cand_j)
+                                                double *__restrict__ cand_j,
+                                                unsigned long long *__restrict__ stats)
 {
     __shared__ int2 sQv[kTileCap];
     __shared__ int4 sQbox[kTileCap / 8];
@@ -475,6 +478,7 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     const int32_t qmbr[4] = {sQmbr[0], sQmbr[1], sQmbr[2], sQmbr[3]};
     const int64_t a2q = sQa2;
     const int nwaves = blockDim.x >> 6;
+    unsigned long long st_tiled = 0, st_tiles = 0, st_general = 0, st_disjoint = 0;
     for (int64_t c = c0 + wave; c < c1; c += nwaves) {
         const int32_t p = cand_ids[c];
         const int64_t pa = doff[p];
@@ -485,6 +489,7 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
             int32_t pm[4];
             poly_mbr(Pg, n, lane, pm);
             const bool disjoint = pm[2] <= qmbr[0] || qmbr[2] <= pm[0] || pm[3] <= qmbr[1] || qmbr[3] <= pm[1];
+            st_disjoint += disjoint;
             if (!disjoint) {
                 const int64_t span = max(max((int64_t)pm[2], (int64_t)qmbr[2]) - min((int64_t)pm[0], (int64_t)qmbr[0]),
                                          max((int64_t)pm[3], (int64_t)qmbr[3]) - min((int64_t)pm[1], (int64_t)qmbr[1]));
@@ -504,10 +509,12 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                     __builtin_amdgcn_s_waitcnt(0xc07f);
                     __builtin_amdgcn_wave_barrier();
                     a2p = ring_area2(Ps, n, lane);
-                    if (a2p != 0) inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, lane);
+                    if (a2p != 0) inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, lane, &st_tiles);
+                    st_tiled++;
                     done = true;
                 }
                 if (!done) {
+                    st_general += 2ull * (unsigned long long)n * (unsigned long long)m;
                     PairIn in;
                     in.P = Pg; in.n = n; in.Q = Qg; in.m = m; in.ox = ox; in.oy = oy;
                     in.qmbr[0] = qmbr[0]; in.qmbr[1] = qmbr[1]; in.qmbr[2] = qmbr[2]; in.qmbr[3] = qmbr[3];
@@ -534,18 +541,25 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
         }
         if (lane == 0) cand_j[c] = J;
     }
+    if (stats && lane == 0) {
+        atomicAdd(stats + 0, (unsigned long long)(st_tiled));
+        atomicAdd(stats + 1, st_tiles);
+        atomicAdd(stats + 2, st_general);
+        atomicAdd(stats + 3, st_disjoint);
+    }
 }
 
 }  // namespace
 
 polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
-                            int64_t n_cand, double *cand_j, hipStream_t s)
+                            int64_t n_cand, double *cand_j, hipStream_t s,
+                            unsigned long long *stats)
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
     if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "refine: too many queries");
     hipLaunchKernelGGL(k_refine, dim3((unsigned)nq), dim3(64 * kWavesPerBlock), 0, s, data->xy,
-                       data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j);
+                       data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j, stats);
     return check_launch("refine");
 }
 

@@ -67,6 +67,12 @@ _SIGNATURES = {
     "polymh_query_workspace_size": (SZ, [I64, I64]),
     "polymh_query": (I32, [P, P, I64, I64, P, I64, I32, P, SZ, P, P, I64, P]),
     "polymh_refine": (I32, [P, P, P, P, I64, I64, P, P]),
+    "polymh_refine_stats": (I32, [P, P, P, P, I64, I64, P, P, P]),
+    "polymh_query_capped": (I32, [P, P, I64, I64, P, I64, I32, P, SZ, P, P, I64, P, P]),
+    "polymh_graph_begin": (I32, [P]),
+    "polymh_graph_end": (I32, [P, P]),
+    "polymh_graph_launch": (I32, [P, P]),
+    "polymh_graph_destroy": (None, [P]),
     "polymh_topk": (I32, [P, P, P, I64, I32, P, P, P]),
     "polymh_mlp_param_count": (I64, []),
     "polymh_mlp_bf16_count": (I64, []),
@@ -83,6 +89,8 @@ _SIGNATURES = {
     "polymh_csr_rows": (I32, [P, I64, P, P]),
     "polymh_jhat": (I32, [P, P, I32, P, P, I64, P, P]),
     "polymh_rank_workspace_size": (SZ, [I64, I64, I32]),
+    "polymh_rank_head": (I32, [P, P, I64, P, I32, P, P, P, P, P, P, P]),
+    "polymh_scatter_scores": (I32, [P, P, I64, P, P]),
     "polymh_rank_refine": (I32, [P, P, P, P, P, I64, I64, I32, I32, ctypes.c_float, I32, P, SZ,
                                  P, P, P, P, P]),
 }
@@ -281,11 +289,12 @@ def query(sorted_keys: torch.Tensor, sorted_ids: torch.Tensor, n_data: int, qkey
 
 
 def refine(data: DevicePolys, queries: DevicePolys, cand_off: torch.Tensor, cand_ids: torch.Tensor,
-           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Exact Jaccard per candidate: float64 [C]."""
+           out: torch.Tensor | None = None, stream=None, n_cand: int | None = None) -> torch.Tensor:
+    """Exact Jaccard per candidate: float64 [C] (C = n_cand, default the
+    length of cand_ids; ranges come from cand_off on the device)."""
     check_device()
     nq = queries.n
-    c = cand_ids.numel()
+    c = cand_ids.numel() if n_cand is None else n_cand
     if out is None:
         out = torch.empty(max(c, 1), dtype=torch.float64, device=cand_ids.device)
     dp, qp = data.cstruct(), queries.cstruct()
@@ -294,13 +303,28 @@ def refine(data: DevicePolys, queries: DevicePolys, cand_off: torch.Tensor, cand
     return out[:c]
 
 
-def topk(cand_off: torch.Tensor, cand_ids: torch.Tensor, cand_j: torch.Tensor, k: int, stream=None):
+def refine_stats(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, stream=None):
+    """(J float64 [C], work counts: tiled pairs, tiles, general edge pairs, disjoint pairs)."""
+    c = cand_ids.numel()
+    out = torch.empty(max(c, 1), dtype=torch.float64, device=cand_ids.device)
+    stats = torch.zeros(4, dtype=torch.int64, device=cand_ids.device)
+    dp, qp = data.cstruct(), queries.cstruct()
+    _check(lib().polymh_refine_stats(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                     queries.n, c, _ptr(out), _ptr(stats), _stream(stream)))
+    return out[:c], [int(v) for v in stats.cpu().tolist()]
+
+
+def topk(cand_off: torch.Tensor, cand_ids: torch.Tensor, cand_j: torch.Tensor, k: int, stream=None,
+         out=None):
     """(top_ids int32 [nq, k] (-1 pad), top_j float64 [nq, k])."""
     check_device()
     nq = cand_off.numel() - 1
     dev = cand_off.device
-    ids = torch.empty((max(nq, 1), k), dtype=torch.int32, device=dev)
-    js = torch.empty((max(nq, 1), k), dtype=torch.float64, device=dev)
+    if out is not None:
+        ids, js = out
+    else:
+        ids = torch.empty((max(nq, 1), k), dtype=torch.int32, device=dev)
+        js = torch.empty((max(nq, 1), k), dtype=torch.float64, device=dev)
     _check(lib().polymh_topk(_ptr(cand_off), _ptr(cand_ids), _ptr(cand_j), nq, k, _ptr(ids), _ptr(js),
                              _stream(stream)))
     return ids[:nq], js[:nq]
@@ -388,6 +412,27 @@ def jhat(lsig, rsig, li, ri, out=None, stream=None):
     return out[:R]
 
 
+def rank_head(cand_off, cand_ids, score, M, stream=None):
+    """Per query, the first min(M, C_q) candidates by decreasing score:
+    (head_off int64 [nq+1], head_query int32, head_cand int64, head_id int32)."""
+    nq = cand_off.numel() - 1
+    dev = cand_off.device
+    C = score.numel()
+    order = torch.empty(max(C, 1), dtype=torch.int32, device=dev)
+    ok = torch.empty(max(nq, 1), dtype=torch.uint8, device=dev)
+    hoff = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+    hq = torch.empty(max(nq * M, 1), dtype=torch.int32, device=dev)
+    hc = torch.empty(max(nq * M, 1), dtype=torch.int64, device=dev)
+    hid = torch.empty(max(nq * M, 1), dtype=torch.int32, device=dev)
+    _check(lib().polymh_rank_head(_ptr(cand_off), _ptr(cand_ids), nq, _ptr(score), M, _ptr(order),
+                                  _ptr(ok), _ptr(hoff), _ptr(hq), _ptr(hc), _ptr(hid), _stream(stream)))
+    return hoff, hq, hc, hid
+
+
+def scatter_scores(idx, val, score, stream=None):
+    _check(lib().polymh_scatter_scores(_ptr(idx), _ptr(val), idx.numel(), _ptr(score), _stream(stream)))
+
+
 def rank_refine(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, score, topk=10, F=16,
                 margin=0.0, max_rounds=1 << 20, ws=None, stream=None):
     """Best-first refinement with early stop -> (top_ids, top_j, n_refined, rounds)."""
@@ -407,3 +452,43 @@ def rank_refine(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, sco
                                     ws.numel(), _ptr(ids), _ptr(js), ctypes.byref(nref),
                                     ctypes.byref(rounds), _stream(stream)))
     return ids[:nq], js[:nq], int(nref.value), int(rounds.value)
+
+
+# ------------------------------------------------------- graphs (batching)
+
+def query_capped(sorted_keys, sorted_ids, n_data, qkeys, cand_off, cand_ids, overflow, ws, stream=None):
+    """Both lookup phases with a fixed capacity and a device overflow flag."""
+    nq, b = qkeys.shape
+    _check(lib().polymh_query_capped(_ptr(sorted_keys), _ptr(sorted_ids), sorted_keys.numel(), n_data,
+                                     _ptr(qkeys), nq, b, _ptr(ws), ws.numel(), _ptr(cand_off),
+                                     _ptr(cand_ids), cand_ids.numel(), _ptr(overflow), _stream(stream)))
+
+
+class Graph:
+    """A captured sequence of libpolymh calls; replay with launch()."""
+
+    def __init__(self, handle, stream):
+        self.handle = handle
+        self.stream = stream
+
+    def launch(self, stream=None):
+        _check(lib().polymh_graph_launch(self.handle, _stream(stream or self.stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.polymh_graph_destroy(self.handle)
+            self.handle = None
+
+
+def capture(fn, stream):
+    """Run fn() with every libpolymh call recorded on `stream` (a
+    torch.cuda.Stream that fn must use) and return the instantiated graph."""
+    _check(lib().polymh_graph_begin(_stream(stream)))
+    try:
+        with torch.cuda.stream(stream):
+            fn()
+    finally:
+        h = ctypes.c_void_p()
+        st = lib().polymh_graph_end(_stream(stream), ctypes.byref(h))
+    _check(st)
+    return Graph(h, stream)

@@ -143,23 +143,139 @@ def predict_pairs(scorer: Scorer, lsig, lfeat, rsig, rfeat, li, ri, chunk: int =
     """Predicted J of every (li, ri) pair, in chunks of `chunk` rows."""
     R = li.numel()
     dev = lsig.device
-    out = torch.empty(max(R, 1), dtype=torch.float32, device=dev)
-    rows = min(chunk, ((R + 31) // 32) * 32) if R else 32
+    R32 = max(((R + 31) // 32) * 32, 32)
+    out = torch.empty(R32, dtype=torch.float32, device=dev)   # padded: chunks write whole tiles
+    rows = min(chunk, R32)
     X = torch.empty((rows, 288), dtype=torch.int16, device=dev)
     acts, _ = pm.mlp_buffers(rows, dev)
-    yb = torch.empty(rows, dtype=torch.float32, device=dev)
     for c0 in range(0, R, rows):
         c1 = min(R, c0 + rows)
         pad = ((c1 - c0 + 31) // 32) * 32
         pm.pair_features(lsig, lfeat, rsig, rfeat, li[c0:c1], ri[c0:c1], R_pad=pad, out=X)
-        pm.mlp_forward(X[:pad], scorer.params, scorer.wbf16, acts, y=yb)
-        out[c0:c1] = yb[:c1 - c0]
+        pm.mlp_forward(X[:pad], scorer.params, scorer.wbf16, acts, y=out[c0:c0 + pad])
     return out[:R]
 
 
-def candidate_scores(kind: str, scorer, qsig, qfeat, dsig, dfeat, cand_off, cand_ids):
-    """Per-candidate predicted J: 'mlp' (the scorer) or 'jhat' (collision fraction)."""
+HEAD = 64
+
+
+def candidate_scores(kind: str, scorer, qsig, qfeat, dsig, dfeat, cand_off, cand_ids, head: int = HEAD):
+    """Per-candidate predicted J.  'jhat': the collision fraction of the
+    signatures (Thm. 1's estimate).  'mlp': a cascade -- the collision
+    fraction orders every candidate, then the scorer re-predicts the first
+    `head` candidates of each query (the only ones early stop can reach)."""
     rows = pm.csr_rows(cand_off, cand_ids.numel())
+    jh = pm.jhat(qsig, dsig, rows, cand_ids)
     if kind == "jhat":
-        return pm.jhat(qsig, dsig, rows, cand_ids)
-    return predict_pairs(scorer, qsig, qfeat, dsig, dfeat, rows, cand_ids)
+        return jh
+    hoff, hq, hc, hid = pm.rank_head(cand_off, cand_ids, jh, head)
+    H = int(hoff[-1].item())
+    pred = predict_pairs(scorer, qsig, qfeat, dsig, dfeat, hq[:H], hid[:H])
+    pm.scatter_scores(hc[:H], pred, jh)
+    return jh
+
+
+# ------------------------------------------------------------ measurement --
+
+def brute_force_top10(D: pm.DevicePolys, Q: pm.DevicePolys):
+    """Exact top-10 of every query against the whole dataset (all pairs
+    refined by the refinement kernel)."""
+    dev = D.offsets.device
+    off = torch.arange(Q.n + 1, device=dev, dtype=torch.int64) * D.n
+    ids = torch.arange(D.n, device=dev, dtype=torch.int32).repeat(Q.n)
+    J = pm.refine(D, Q, off, ids)
+    return pm.topk(off, ids, J, 10)
+
+
+def _prefix(off, ids, n):
+    """CSR of the first n queries."""
+    o = off[:n + 1]
+    return o, ids[:int(o[-1].item())]
+
+
+def learned_comparison(w, D, Q, log, n_pairs=2_000_000, epochs=3, bands=64, rows=4, n_calib=1000,
+                       n_eval=1000, reps=3, F=16, target=0.95):
+    """Plain full refinement vs best-first refinement with early stop ordered
+    by the collision fraction or by the trained scorer, on the learned-scorer
+    workload (workload-2 polygons signed at k = 256)."""
+    from .metrics import recall_at_k
+    k, cap = K_SCORER, w.cap
+    dev = D.offsets.device
+    out = {"k": k, "bands": bands, "rows": rows, "train_pairs": n_pairs, "epochs": epochs}
+    t0 = time.perf_counter()
+    sig = pm.sign(D, w.box, w.seed, k, cap)
+    feats = pm.poly_features(D, w.box)
+    keys8 = pm.band(sig, 32, 8, w.seed)
+    sk8, se8 = pm.index_build(keys8)
+    left, right = mine_pairs(sk8, se8, D.n, 32, n_pairs, seed=1)
+    J = exact_pair_j(D, left, right).float()
+    torch.cuda.synchronize()
+    out["label_s"] = time.perf_counter() - t0
+    n_val = max(len(left) // 50, 1024)
+    s = init_scorer(0)
+    t0 = time.perf_counter()
+    hist = train(s, sig, feats, left[n_val:], right[n_val:], J[n_val:], epochs=epochs, log=log)
+    out["train_s"] = time.perf_counter() - t0
+    out["train_loss"] = hist
+    Lv, Rv = torch.from_numpy(left[:n_val]).to(dev), torch.from_numpy(right[:n_val]).to(dev)
+    pv = predict_pairs(s, sig, feats, sig, feats, Lv, Rv)
+    jv = pm.jhat(sig, sig, Lv, Rv)
+    out["val_mse_scorer"] = float(((pv - J[:n_val]) ** 2).mean())
+    out["val_mse_collision_fraction"] = float(((jv - J[:n_val]) ** 2).mean())
+    log(f"held-out MSE: scorer {out['val_mse_scorer']:.5f}, collision fraction {out['val_mse_collision_fraction']:.5f}")
+
+    keys = pm.band(sig, bands, rows, w.seed)
+    sk, se = pm.index_build(keys)
+    qfeats = pm.poly_features(Q, w.box)
+
+    def candidates(Qp):
+        qs = pm.sign(Qp, w.box, w.seed, k, cap)
+        qk = pm.band(qs, bands, rows, w.seed)
+        off, ids = pm.query(sk, se, D.n, qk)
+        return qs, off, ids
+
+    def run(method, Qp, qf, margin, timed=False):
+        qs, off, ids = candidates(Qp)
+        if method == "plain":
+            Jc = pm.refine(D, Qp, off, ids)
+            ti, tj = pm.topk(off, ids, Jc, 10)
+            return ti, tj, ids.numel()
+        score = candidate_scores("mlp" if method == "scorer" else "jhat", s, qs, qf, sig, feats, off, ids)
+        ti, tj, nref, _ = pm.rank_refine(D, Qp, off, ids, score, topk=10, F=F, margin=margin)
+        return ti, tj, nref
+
+    # calibration and evaluation query samples, with brute-force answers
+    import numpy as np_
+    cal = pm.to_device(w.queries.subset(np_.arange(n_calib)))
+    ev = pm.to_device(w.queries.subset(np_.arange(n_calib, n_calib + n_eval)))
+    cal_f, ev_f = qfeats[:n_calib].contiguous(), qfeats[n_calib:n_calib + n_eval].contiguous()
+    bci, bcj = brute_force_top10(D, cal)
+    bei, bej = brute_force_top10(D, ev)
+    bci, bcj, bei, bej = (x.cpu().numpy() for x in (bci, bcj, bei, bej))
+    grid = [0.0, 0.005, 0.01, 0.015, 0.02, 0.025, 0.03, 0.04, 0.05, 0.06, 0.08, 0.1, 0.15, 0.2, 0.3, 0.5]
+    res = {}
+    for method in ("plain", "collision_fraction", "scorer"):
+        margin = float("inf")
+        if method != "plain":
+            for m in grid:
+                ti, tj, _ = run(method, cal, cal_f, m)
+                # calibrate with a small safety margin over the target
+                if recall_at_k(ti.cpu().numpy(), tj.cpu().numpy(), bci, bcj, 10) >= target + 0.005:
+                    margin = m
+                    break
+        ti, tj, nref = run(method, ev, ev_f, margin)
+        rec = recall_at_k(ti.cpu().numpy(), tj.cpu().numpy(), bei, bej, 10)
+        # throughput over all queries
+        run(method, Q, qfeats, margin)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            _, _, nref_all = run(method, Q, qfeats, margin)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        res[method] = {"margin": margin, "recall_at_10": rec, "queries_per_s": Q.n / dt,
+                       "ms_per_batch": 1e3 * dt, "refined_pairs_per_query": nref_all / Q.n}
+        log(f"{method}: margin {margin}, recall@10 {rec:.3f}, {Q.n / dt:.0f} q/s, "
+            f"{nref_all / Q.n:.1f} refined pairs/query")
+    out["methods"] = res
+    return out
