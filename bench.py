@@ -31,11 +31,13 @@ PEAK_VALU = 256 * 4 * 16 * 2.4e9      # lane-cycles/s: 256 CUs x 4 SIMD16 x 2.4 
 # point-in-polygon loop.
 C_DRAW = 26 + 6 * 4
 C_EDGE = 14
-# VALU instructions per lane of one 8 x 8 edge-pair tile of the tiled
-# refinement (counted in the built code: 60 FP64, 22 int->FP64 conversions,
-# compares and selects) and per edge pair of its general per-edge form.
-C_TILE = 114
-C_GENERAL = 40
+# Algorithmic VALU operations of one exact edge-pair test in the refinement:
+# the four orientations from one shared difference r = c - a and X = cross(e, f)
+# (2 subtractions, 3 products with their fused subtractions = 6, 2 additions)
+# plus the 4 sign decisions; the general per-edge form adds the half-open
+# membership update (2 compares, and, xor).
+C_PAIR = 14
+C_GENERAL = 18
 
 
 def log(msg):
@@ -175,11 +177,12 @@ def main():
                  "draws_per_launch": 0.5 * (dw_d + dw_q), "edge_tests_per_launch": 0.5 * (ed_d + ed_q)}
     # -- refinement roofline (k_refine; FP64 VALU bound).  Algorithmic work:
     # the edge pairs the tiled form tests (8 x 8 tiles of chunk pairs whose
-    # boxes overlap) times C_TILE per lane, plus the general form's edge pairs.
+    # boxes overlap) times C_PAIR, plus the general form's edge pairs times
+    # C_GENERAL.
     _, rstats = pm.refine_stats(D, Q, off, ids)
     tested = 64.0 * rstats[1] + rstats[2]
     t_ref = stage_ms["refine"] / 1e3
-    work_ref = 64.0 * rstats[1] * C_TILE + rstats[2] * C_GENERAL
+    work_ref = 64.0 * rstats[1] * C_PAIR + rstats[2] * C_GENERAL
     roof_ref = {"bound": "alu", "achieved": work_ref / t_ref / 1e12, "peak": PEAK_VALU / 1e12,
                 "unit": "T lane-cycles/s", "frac": work_ref / t_ref / PEAK_VALU, "traffic": None,
                 "kernel": "k_refine", "launch_ms": 1e3 * t_ref, "pairs": n_cand,

@@ -26,6 +26,102 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z;
 }
 
+// ---- wavefront reductions and scans over DPP ------------------------------
+// Data-parallel-primitive moves read a neighbour lane's register inside the
+// VALU, without the LDS crossbar that a shuffle goes through.  GFX9 controls:
+// quad permutes, row (16-lane) rotates and shifts, and the two broadcasts of
+// lane 15 of each row into the next row and of lane 31 into rows 2 and 3.
+// Every lane of the wavefront must be active.
+namespace dpp {
+constexpr int kQuad1032 = 0xB1;
+constexpr int kQuad2301 = 0x4E;
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr3 = 0x113, kRowShr4 = 0x114,
+              kRowShr8 = 0x118;
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWS = 0xf, int BANKS = 0xf>
+__device__ __forceinline__ int mov(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, ROWS, BANKS, false);
+}
+template <int CTRL, int ROWS = 0xf, int BANKS = 0xf>
+__device__ __forceinline__ uint64_t mov64(uint64_t old, uint64_t src)
+{
+    const uint32_t lo = (uint32_t)mov<CTRL, ROWS, BANKS>((int)(uint32_t)old, (int)(uint32_t)src);
+    const uint32_t hi = (uint32_t)mov<CTRL, ROWS, BANKS>((int)(uint32_t)(old >> 32), (int)(uint32_t)(src >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+}  // namespace dpp
+
+// Reduction of a 32-bit value over the wavefront; the result is uniform.
+// Quads, then rows (rotate by 4 and 8: every lane holds its row's total),
+// then rows 1/3 take rows 0/2 and rows 2-3 take lane 31: lane 63 ends with
+// the total.
+template <class Op>
+__device__ __forceinline__ int wave_reduce32(int x, int id, Op op)
+{
+    x = op(x, dpp::mov<dpp::kQuad1032>(id, x));
+    x = op(x, dpp::mov<dpp::kQuad2301>(id, x));
+    x = op(x, dpp::mov<dpp::kRowRor4>(id, x));
+    x = op(x, dpp::mov<dpp::kRowRor8>(id, x));
+    x = op(x, dpp::mov<dpp::kRowBcast15, 0xa>(id, x));
+    x = op(x, dpp::mov<dpp::kRowBcast31, 0xc>(id, x));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+__device__ __forceinline__ int wave_min32(int x)
+{
+    return wave_reduce32(x, INT32_MAX, [](int a, int b) { return a < b ? a : b; });
+}
+__device__ __forceinline__ int wave_max32(int x)
+{
+    return wave_reduce32(x, INT32_MIN, [](int a, int b) { return a > b ? a : b; });
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+    uint64_t x = (uint64_t)v;
+    x += dpp::mov64<dpp::kQuad1032>(0, x);
+    x += dpp::mov64<dpp::kQuad2301>(0, x);
+    x += dpp::mov64<dpp::kRowRor4>(0, x);
+    x += dpp::mov64<dpp::kRowRor8>(0, x);
+    x += dpp::mov64<dpp::kRowBcast15, 0xa>(0, x);
+    x += dpp::mov64<dpp::kRowBcast31, 0xc>(0, x);
+    return (int64_t)dpp::readlane64(x, 63);
+}
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    auto step = [](double x, uint64_t moved) { return x + __longlong_as_double((long long)moved); };
+    const uint64_t z = (uint64_t)__double_as_longlong(0.0);
+    v = step(v, dpp::mov64<dpp::kQuad1032>(z, (uint64_t)__double_as_longlong(v)));
+    v = step(v, dpp::mov64<dpp::kQuad2301>(z, (uint64_t)__double_as_longlong(v)));
+    v = step(v, dpp::mov64<dpp::kRowRor4>(z, (uint64_t)__double_as_longlong(v)));
+    v = step(v, dpp::mov64<dpp::kRowRor8>(z, (uint64_t)__double_as_longlong(v)));
+    v = step(v, dpp::mov64<dpp::kRowBcast15, 0xa>(z, (uint64_t)__double_as_longlong(v)));
+    v = step(v, dpp::mov64<dpp::kRowBcast31, 0xc>(z, (uint64_t)__double_as_longlong(v)));
+    return __longlong_as_double((long long)dpp::readlane64((uint64_t)__double_as_longlong(v), 63));
+}
+// Inclusive prefix sum of a 32-bit value over the wavefront (lane 63 holds
+// the total): within each row by shifts of 1, 2, 3, then 4 (lanes 4-15) and
+// 8 (lanes 8-15), then across rows by the two broadcasts.
+__device__ __forceinline__ int wave_incl_scan32(int x)
+{
+    int s = x;
+    s += dpp::mov<dpp::kRowShr1>(0, x);
+    s += dpp::mov<dpp::kRowShr2>(0, x);
+    s += dpp::mov<dpp::kRowShr3>(0, x);
+    s += dpp::mov<dpp::kRowShr4, 0xf, 0xe>(0, s);
+    s += dpp::mov<dpp::kRowShr8, 0xf, 0xc>(0, s);
+    s += dpp::mov<dpp::kRowBcast15, 0xa>(0, s);
+    s += dpp::mov<dpp::kRowBcast31, 0xc>(0, s);
+    return s;
+}
+
 // Per-polygon flag bits written by the staging kernel.
 constexpr uint32_t kFlagFew = 1u;        // fewer than 3 vertices
 constexpr uint32_t kFlagCollinear = 2u;  // all vertices on one line

@@ -93,26 +93,9 @@ __device__ __forceinline__ double rcp_refined(double d)
     return r;
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ int32_t wmin(int32_t v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int32_t wmax(int32_t v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
+__device__ __forceinline__ int32_t wmin(int32_t v) { return wave_min32(v); }
+__device__ __forceinline__ int32_t wmax(int32_t v) { return wave_max32(v); }
 
 struct PairIn {
     const int32_t *P;   // data polygon vertices
@@ -258,25 +241,67 @@ __device__ __forceinline__ void poly_mbr(const int32_t *v, int32_t n, int lane, 
 
 // ---------------------------------------------------------------------------
 // Tiled form.  The two boundaries are cut into chunks of 8 edges; only chunk
-// pairs whose boxes overlap are tested, 64 edge pairs per wavefront step
-// (8 x 8 lanes).  Each crossing is found once and credited to both polygons.
-// The membership of each edge's start is not tested directly: it is the
-// membership of the ring's first vertex plus the running sum of the crossing
-// signs met along the ring, so with S_e the net sign of edge e's crossings,
+// pairs whose boxes overlap (tiles of 8 x 8 edge pairs) are tested.  Each
+// crossing is found once and credited to both polygons.  The membership of
+// each edge's start is not tested directly: it is the membership of the
+// ring's first vertex plus the running sum of the crossing signs met along
+// the ring, so with S_e the net sign of edge e's crossings,
 //   sum_e cr_e * I(e) = sum_e cr_e * (w_0 + s * sum_{e' < e} S_e')
 //                       + s * sum_{crossings} cr_e * sign * (1 - t).
 // Q (the query) is staged once per workgroup; each wavefront stages its data
 // polygon.  Pairs with a polygon beyond kTileCap edges, or coordinate spans of
 // 2^26 and more, take the general per-edge form above.
+//
+// Work layout: overlapping tiles are compacted into a per-wavefront list and
+// taken 8 at a time; lane (slot, j) keeps edge j of its tile's Q chunk in
+// registers and sweeps the 8 edges of the tile's P chunk.  With e = b - a,
+// f = d - c, r = c - a and X = cross(e, f) the four orientations are
+//   orient(a,b,c) = cross(e, r),  orient(a,b,d) = orient(a,b,c) + X,
+//   orient(c,d,a) = cross(r, f),  orient(c,d,b) = orient(c,d,a) - X,
+// all exact integers in FP64 (differences < 2^26).  The symbolic tie-break is
+// folded into one compare: against a threshold of -1/2 or +1/2 for P's
+// edges, and for Q's edges a floating-point class test whose "positive" set
+// is {+denormal, +normal, +inf}, plus both zeros when the tie resolves to +1.
+// Rings are padded with copies of vertex 0, so edges past the end are
+// zero-length and can never cross: no per-lane bounds checks in the sweep.
 
 constexpr int kTileCap = 512;
+constexpr int kRingLds = kTileCap + 16;   // ring vertices incl. padding
 constexpr int kWavesPerBlock = 4;
+constexpr int kListCap = 128;             // per-wavefront ring of tile entries
+constexpr int kCrossCap = 128;            // per-wavefront crossing buffer
+constexpr int kClassPos = (1 << 7) | (1 << 8) | (1 << 9);
+constexpr int kClassPosZ = kClassPos | (1 << 5) | (1 << 6);
 
 struct RingLds {
-    int2 *v;       // vertices relative to the origin
-    int4 *box;     // per 8-edge chunk: xmin, ymin, xmax, ymax
-    int *S;        // net crossing sign per edge (per pair)
+    int2 *v;            // vertices relative to the origin; v[n..] repeat v[0]
+    int4 *box;          // per 8-edge chunk: xmin, ymin, xmax, ymax
+    uint32_t *S;        // net crossing sign per edge, two biased 16-bit halves a word
+    uint16_t *cls;      // Q only: per edge, the class set counted as positive
 };
+
+// Crossing-sign sums are kept as 16-bit halves biased by 2^15 inside 32-bit
+// words (|S| <= kTileCap, so a half never wraps and never borrows from its
+// neighbour); one LDS atomic adds +-1 to either half.
+constexpr uint32_t kSBias = 0x80008000u;
+__device__ __forceinline__ void s_add(uint32_t *S, int e, int v)
+{
+    atomicAdd(&S[e >> 1], (uint32_t)v << (16 * (e & 1)));
+}
+__device__ __forceinline__ int s_get(const uint32_t *S, int e)
+{
+    return (int)((S[e >> 1] >> (16 * (e & 1))) & 0xffffu) - 0x8000;
+}
+
+// Tie-break threshold of a P edge (e = b - a) for orientations of points of
+// Q + delta: a zero counts as positive when the edge points down, or is
+// horizontal and points right.  Orientations are integers, so o > -1/2 is
+// o >= 0 and o > +1/2 is o > 0.  fma(ey, 2^32, -ex) carries the sign of ey,
+// or of -ex when ey = 0 (|ex| < 2^26), and the threshold takes that sign.
+__device__ __forceinline__ double p_edge_threshold(double ex, double ey)
+{
+    return copysign(0.5, __fma_rn(ey, 4294967296.0, -ex));
+}
 
 __device__ __forceinline__ double orient_d(int2 a, int2 b, int2 c)
 {
@@ -286,13 +311,37 @@ __device__ __forceinline__ double orient_d(int2 a, int2 b, int2 c)
 
 __device__ __forceinline__ int sgn_tb(double o, int tb) { return o > 0 ? 1 : (o < 0 ? -1 : tb); }
 
-// Stage a ring (relative to the origin) and its chunk boxes; lanes of one
-// wavefront (lane0/nl describe the participating threads).
-__device__ void stage_ring(const int32_t *src, int n, int64_t ox, int64_t oy, RingLds R, int t0,
-                           int nt)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    for (int i = t0; i < n; i += nt)
-        R.v[i] = make_int2((int)((int64_t)src[2 * i] - ox), (int)((int64_t)src[2 * i + 1] - oy));
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Stage a ring relative to the origin into entries [0, pad_to), entries from
+// n on repeating vertex 0.
+__device__ void stage_ring(const int32_t *src, int n, int pad_to, int64_t ox, int64_t oy, RingLds R,
+                           int t0, int nt)
+{
+    for (int i = t0; i < pad_to; i += nt) {
+        const int k = i < n ? i : 0;
+        R.v[i] = make_int2((int)((int64_t)src[2 * k] - ox), (int)((int64_t)src[2 * k + 1] - oy));
+    }
+}
+
+// Wavefront staging of a data polygon (as stage_ring) that also returns the
+// MBR of its absolute coordinates (uniform).
+__device__ void stage_ring_mbr(const int32_t *src, int n, int pad_to, int64_t ox, int64_t oy,
+                               RingLds R, int lane, int32_t *mbr)
+{
+    int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+    const int2 *v = reinterpret_cast<const int2 *>(src);
+    for (int i = lane; i < pad_to; i += 64) {
+        const int2 p = v[i < n ? i : 0];
+        x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
+        R.v[i] = make_int2((int)((int64_t)p.x - ox), (int)((int64_t)p.y - oy));
+    }
+    mbr[0] = wave_min32(x0); mbr[1] = wave_min32(y0);
+    mbr[2] = wave_max32(x1); mbr[3] = wave_max32(y1);
 }
 
 __device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
@@ -302,10 +351,27 @@ __device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
         int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
         const int e1 = min(n, 8 * c + 8);
         for (int v = 8 * c; v <= e1; v++) {
-            const int2 p = R.v[v == n ? 0 : v];
+            const int2 p = R.v[v];
             x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
         }
         R.box[c] = make_int4(x0, y0, x1, y1);
+    }
+}
+
+// Tie-break class sets of Q's edges [0, total): for a shifted Q edge
+// (c + delta, d + delta) tested against a point of P, a zero orientation
+// counts as positive when dy > 0, or dy = 0 and dx < 0.  Zero-length and
+// padding edges get the strict set (they never cross either way).
+__device__ void edge_classes_q(RingLds R, int n, int total, int t0, int nt)
+{
+    for (int e = t0; e < total; e += nt) {
+        bool pz = false;
+        if (e < n) {
+            const int2 a = R.v[e], b = R.v[e + 1];
+            const int dx = b.x - a.x, dy = b.y - a.y;
+            pz = dy > 0 || (dy == 0 && dx < 0);
+        }
+        R.cls[e] = (uint16_t)(pz ? kClassPosZ : kClassPos);
     }
 }
 
@@ -316,7 +382,7 @@ __device__ int member_wave(RingLds R, int n, int2 a, int sh, int lane)
 {
     bool odd = false;
     for (int e = lane; e < n; e += 64) {
-        const int2 c = R.v[e], d = R.v[e + 1 == n ? 0 : e + 1];
+        const int2 c = R.v[e], d = R.v[e + 1];
         if (c.x == d.x && c.y == d.y) continue;
         // straddle of the horizontal through a + sh*(eps, eps^2)
         const bool st = (sh < 0) ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
@@ -336,32 +402,103 @@ __device__ double membership_term(RingLds R, int n, int w0, int s, int lane)
 {
     double acc = 0.0;
     int carry = 0;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int base = 0; base < n; base += 64) {
+        // branch-free so that the scan below runs with every lane active
         const int e = base + lane;
-        int Se = 0;
-        double cr = 0.0;
-        if (e < n) {
-            Se = R.S[e];
-            const int2 a = R.v[e], b = R.v[e + 1 == n ? 0 : e + 1];
-            cr = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
-        }
-        // inclusive scan of Se over the wavefront (Se is -1, 0 or +1 per crossing sum)
-        int incl = Se;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += t;
-        }
+        const bool live = e < n;
+        const int ee = live ? e : 0;
+        const int Se = live ? s_get(R.S, ee) : 0;
+        const int2 a = R.v[ee], b = R.v[ee + 1];
+        const double cr = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
+        // inclusive scan of Se over the wavefront
+        const int incl = wave_incl_scan32(Se);
         const int excl = incl - Se;
-        if (e < n) acc += cr * (double)(w0 + s * (carry + excl));
-        carry += __shfl(incl, 63, 64);
-        (void)lt;
+        acc += live ? cr * (double)(w0 + s * (carry + excl)) : 0.0;
+        carry += __builtin_amdgcn_readlane(incl, 63);
     }
     return acc;
 }
 
+// Crossing contributions of buffered (e, f) pairs, 64 at a time with every
+// lane busy: the orientations are recomputed exactly as in the sweep, so the
+// signs and parameters are the ones that detected the crossing.
+__device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int count, int lane,
+                                double &accP, double &accQ)
+{
+    for (int k = lane; k < count; k += 64) {
+        const uint32_t ef = buf[k];
+        const int e = (int)(ef >> 16), f = (int)(ef & 0xffffu);
+        const int2 a = P.v[e], b = P.v[e + 1], c = Q.v[f], d = Q.v[f + 1];
+        const double ax = (double)a.x, ay = (double)a.y, bx = (double)b.x, by = (double)b.y;
+        const double cx = (double)c.x, cy = (double)c.y;
+        const double ex = bx - ax, ey = by - ay;
+        const double fx = (double)(d.x - c.x), fy = (double)(d.y - c.y);
+        const double rx = cx - ax, ry = cy - ay;
+        const double oc = __fma_rn(ex, ry, -(ey * rx));
+        const double oa = __fma_rn(fy, rx, -(fx * ry));
+        const double X = __fma_rn(ex, fy, -(ey * fx));
+        const double od = oc + X, ob = oa - X;
+        const bool p2 = od > p_edge_threshold(ex, ey);
+        const bool p4 = __builtin_amdgcn_class(ob, (int)Q.cls[f]);
+        const double cre = __fma_rn(ax, by, -(bx * ay));
+        const double crf = __fma_rn(cx, fy, -(fx * cy));
+        accP += cre * (p4 ? 1.0 : -1.0) * (-ob) * rcp_refined(oa - ob);
+        accQ += crf * (p2 ? 1.0 : -1.0) * (-od) * rcp_refined(oc - od);
+        s_add(P.S, e, p4 ? 1 : -1);
+        s_add(Q.S, f, p2 ? 1 : -1);
+    }
+}
+
+// Up to 8 tiles: lane (lane >> 3, j) takes Q edge j of its tile's Q chunk and
+// sweeps the tile's 8 P edges.  entry = (P chunk << 16) | Q chunk.  Crossing
+// lanes only append (e << 16 | f) to the wavefront's crossing buffer, which
+// is flushed before it can overflow.
+__device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int lane, uint32_t *xbuf,
+                                           int &xcount, double &accP, double &accQ)
+{
+    const int cp = entry >> 16, cq = entry & 0xffff;
+    const int f = 8 * cq + (lane & 7);
+    const int2 c = Q.v[f], d = Q.v[f + 1];
+    const double cx = (double)c.x, cy = (double)c.y;
+    const double fx = (double)(d.x - c.x), fy = (double)(d.y - c.y);
+    const int mf = Q.cls[f];
+    const int e0 = 8 * cp;
+    const int2 a0 = P.v[e0];
+    double ax = (double)a0.x, ay = (double)a0.y;
+    double rx = cx - ax, ry = cy - ay;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int2 b = P.v[e0 + i + 1];
+        const double bx = (double)b.x, by = (double)b.y;
+        const double ex = bx - ax, ey = by - ay;
+        const double thr = p_edge_threshold(ex, ey);
+        const double oc = __fma_rn(ex, ry, -(ey * rx));
+        const double oa = __fma_rn(fy, rx, -(fx * ry));
+        const double X = __fma_rn(ex, fy, -(ey * fx));
+        const double od = oc + X, ob = oa - X;
+        const bool p1 = oc > thr, p2 = od > thr;
+        const bool p3 = __builtin_amdgcn_class(oa, mf), p4 = __builtin_amdgcn_class(ob, mf);
+        const bool cross = (p1 != p2) & (p3 != p4);
+        const uint64_t cm = __ballot(cross);
+        if (cross) {
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+            xbuf[xcount + rank] = ((uint32_t)(e0 + i) << 16) | (uint32_t)f;
+        }
+        xcount += __popcll(cm);
+        if (xcount > kCrossCap - 64) {
+            wave_lds_sync();
+            flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ);
+            wave_lds_sync();
+            xcount = 0;
+        }
+        ax = bx; ay = by;
+        rx = cx - bx; ry = cy - by;
+    }
+}
+
 __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int lane,
-                             unsigned long long *tiles)
+                             uint32_t *list, uint32_t *xbuf, unsigned long long *tiles)
 {
     // ring-start memberships under Q + delta
     const int w0p = member_wave(Q, m, P.v[0], -1, lane);
@@ -369,47 +506,47 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
     double accP = 0.0, accQ = 0.0;
     const int ncp = (n + 7) >> 3, ncq = (m + 7) >> 3;
     const int total = ncp * ncq;
-    const int ti = lane >> 3, tj = lane & 7;
+    // idx -> (idx / ncq, idx % ncq) without an integer division: the float
+    // quotient of idx + 1/2 is at least 1/(2 ncq) >= 1/128 away from an
+    // integer while its rounding error is below 2^-10 (idx < 2^12).
+    const float rq = 1.0f / (float)ncq;
+    const int slot = lane >> 3;
+    int head = 0, tail = 0, xcount = 0;
     for (int base = 0; base < total; base += 64) {
         const int idx = base + lane;
         bool ov = false;
+        int entry = 0;
         if (idx < total) {
-            const int4 bp = P.box[idx / ncq], bq = Q.box[idx % ncq];
+            const int cp = (int)(((float)idx + 0.5f) * rq);
+            const int cq = idx - cp * ncq;
+            const int4 bp = P.box[cp], bq = Q.box[cq];
             ov = !(bp.z < bq.x || bq.z < bp.x || bp.w < bq.y || bq.w < bp.y);
+            entry = (cp << 16) | cq;
         }
-        uint64_t mk = __ballot(ov);
-        *tiles += (unsigned long long)__popcll(mk);
-        while (mk) {
-            const int k = __builtin_ctzll(mk);
-            mk &= mk - 1;
-            const int cp = (base + k) / ncq, cq = (base + k) % ncq;
-            const int e = 8 * cp + ti, f = 8 * cq + tj;
-            if (e < n && f < m) {
-                const int2 a = P.v[e], b = P.v[e + 1 == n ? 0 : e + 1];
-                const int2 c = Q.v[f], d = Q.v[f + 1 == m ? 0 : f + 1];
-                const int edx = b.x - a.x, edy = b.y - a.y, fdx = d.x - c.x, fdy = d.y - c.y;
-                if ((edx | edy) && (fdx | fdy)) {
-                    const int tbe = edy != 0 ? (edy > 0 ? -1 : 1) : (edx > 0 ? 1 : -1);
-                    const int tbf = fdy != 0 ? (fdy > 0 ? 1 : -1) : (fdx > 0 ? -1 : 1);
-                    const double oc = orient_d(a, b, c), od = orient_d(a, b, d);
-                    const double oa = orient_d(c, d, a), ob = orient_d(c, d, b);
-                    const int s1 = sgn_tb(oc, tbe), s2 = sgn_tb(od, tbe);
-                    const int s3 = sgn_tb(oa, tbf), s4 = sgn_tb(ob, tbf);
-                    if ((s1 != s2) & (s3 != s4)) {
-                        const double cre = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
-                        const double crf = __fma_rn((double)c.x, (double)d.y, -(double)d.x * (double)c.y);
-                        accP += cre * (double)s4 * (-ob) * rcp_refined(oa - ob);
-                        accQ += crf * (double)s2 * (-od) * rcp_refined(oc - od);
-                        atomicAdd(&P.S[e], s4);
-                        atomicAdd(&Q.S[f], s2);
-                    }
-                }
-            }
+        const uint64_t mk = __ballot(ov);
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+        if (ov) list[(tail + rank) & (kListCap - 1)] = (uint32_t)entry;
+        tail += __popcll(mk);
+        wave_lds_sync();
+        while (tail - head >= 8) {
+            tile_group(P, Q, (int)list[(head + slot) & (kListCap - 1)], lane, xbuf, xcount, accP, accQ);
+            head += 8;
         }
     }
+    if (tail > head) {
+        // partial group: empty slots take the all-padding Q chunk ncq
+        const int k = tail - head;
+        const int entry = slot < k ? (int)list[(head + slot) & (kListCap - 1)] : ncq;
+        tile_group(P, Q, entry, lane, xbuf, xcount, accP, accQ);
+    }
+    if (xcount > 0) {
+        wave_lds_sync();
+        flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ);
+    }
+    *tiles += (unsigned long long)tail;
     // make the crossing sums visible to the whole wavefront
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     const double mp = membership_term(P, n, w0p, sq, lane);
     const double mq = membership_term(Q, m, w0q, sp, lane);
     const double tot = sp * (mp + sq * accP) + sq * (mq + sp * accQ);
@@ -420,7 +557,7 @@ __device__ int64_t ring_area2(RingLds R, int n, int lane)
 {
     int64_t a = 0;
     for (int e = lane; e < n; e += 64) {
-        const int2 p = R.v[e], q = R.v[e + 1 == n ? 0 : e + 1];
+        const int2 p = R.v[e], q = R.v[e + 1];
         a += (int64_t)p.x * q.y - (int64_t)q.x * p.y;
     }
     return wave_sum_i64(a);
@@ -436,12 +573,15 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                                                 double *__restrict__ cand_j,
                                                 unsigned long long *__restrict__ stats)
 {
-    __shared__ int2 sQv[kTileCap];
+    __shared__ int2 sQv[kRingLds];
     __shared__ int4 sQbox[kTileCap / 8];
-    __shared__ int2 sPv[kWavesPerBlock][kTileCap];
+    __shared__ uint16_t sQcls[kRingLds];
+    __shared__ int2 sPv[kWavesPerBlock][kRingLds];
     __shared__ int4 sPbox[kWavesPerBlock][kTileCap / 8];
-    __shared__ int sPS[kWavesPerBlock][kTileCap];
-    __shared__ int sQS[kWavesPerBlock][kTileCap];
+    __shared__ uint32_t sPS[kWavesPerBlock][kTileCap / 2];
+    __shared__ uint32_t sQS[kWavesPerBlock][kTileCap / 2];
+    __shared__ uint32_t sList[kWavesPerBlock][kListCap];
+    __shared__ uint32_t sCross[kWavesPerBlock][kCrossCap];
     __shared__ int32_t sQmbr[4];
     __shared__ long long sQa2;
 
@@ -469,25 +609,44 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
         }
     }
     if (q_tiled) {
-        RingLds Qs{sQv, sQbox, nullptr};
-        stage_ring(Qg, m, ox, oy, Qs, tid, blockDim.x);
+        // Q padded by one extra chunk: the all-padding chunk ncq fills empty
+        // slots of a partial tile group
+        const int qpad = 8 * ((m + 7) >> 3) + 8;
+        RingLds Qs{sQv, sQbox, nullptr, sQcls};
+        stage_ring(Qg, m, qpad + 1, ox, oy, Qs, tid, blockDim.x);
         __syncthreads();
         chunk_boxes(Qs, m, tid, blockDim.x);
+        edge_classes_q(Qs, m, qpad, tid, blockDim.x);
     }
     __syncthreads();
     const int32_t qmbr[4] = {sQmbr[0], sQmbr[1], sQmbr[2], sQmbr[3]};
     const int64_t a2q = sQa2;
     const int nwaves = blockDim.x >> 6;
     unsigned long long st_tiled = 0, st_tiles = 0, st_general = 0, st_disjoint = 0;
-    for (int64_t c = c0 + wave; c < c1; c += nwaves) {
-        const int32_t p = cand_ids[c];
-        const int64_t pa = doff[p];
-        const int n = (int)(doff[p + 1] - pa);
+    // Candidate metadata is fetched ahead: the id two candidates on and the
+    // vertex range of the next one, so their latency hides behind this pair.
+    int64_t c = c0 + wave;
+    int32_t p_ahead = c < c1 ? cand_ids[c] : 0;
+    int64_t pa_next = 0, pe_next = 0;
+    if (c < c1) { pa_next = doff[p_ahead]; pe_next = doff[p_ahead + 1]; }
+    p_ahead = (c + nwaves < c1) ? cand_ids[c + nwaves] : 0;
+    for (; c < c1; c += nwaves) {
+        const int64_t pa = pa_next;
+        const int n = (int)(pe_next - pa_next);
+        if (c + nwaves < c1) { pa_next = doff[p_ahead]; pe_next = doff[p_ahead + 1]; }
+        p_ahead = (c + 2 * nwaves < c1) ? cand_ids[c + 2 * nwaves] : 0;
         const int32_t *Pg = dxy + 2 * pa;
         double J = 0.0;
         if (n >= 3 && a2q != 0) {
+            const bool tiled_size = q_tiled && n <= kTileCap;
+            RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr};
+            RingLds Qs{sQv, sQbox, sQS[wave], sQcls};
+            const int ppad = 8 * ((n + 7) >> 3);
             int32_t pm[4];
-            poly_mbr(Pg, n, lane, pm);
+            // staging records the MBR of the absolute coordinates, so a wide
+            // pair (whose relative coordinates do not fit) is still detected
+            if (tiled_size) stage_ring_mbr(Pg, n, ppad + 1, ox, oy, Ps, lane, pm);
+            else poly_mbr(Pg, n, lane, pm);
             const bool disjoint = pm[2] <= qmbr[0] || qmbr[2] <= pm[0] || pm[3] <= qmbr[1] || qmbr[3] <= pm[1];
             st_disjoint += disjoint;
             if (!disjoint) {
@@ -496,24 +655,18 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                 const bool wide = span >= (1ll << 26);
                 double inter2 = 0.0;
                 int64_t a2p = 0;
-                bool done = false;
-                if (!wide && q_tiled && n <= kTileCap) {
-                    RingLds Ps{sPv[wave], sPbox[wave], sPS[wave]};
-                    RingLds Qs{sQv, sQbox, sQS[wave]};
-                    stage_ring(Pg, n, ox, oy, Ps, lane, 64);
-                    for (int i = lane; i < n; i += 64) Ps.S[i] = 0;
-                    for (int i = lane; i < m; i += 64) Qs.S[i] = 0;
-                    __builtin_amdgcn_s_waitcnt(0xc07f);
-                    __builtin_amdgcn_wave_barrier();
+                if (!wide && tiled_size) {
+                    for (int i = lane; i < (n + 1) >> 1; i += 64) Ps.S[i] = kSBias;
+                    for (int i = lane; i < (m + 1) >> 1; i += 64) Qs.S[i] = kSBias;
+                    wave_lds_sync();
                     chunk_boxes(Ps, n, lane, 64);
-                    __builtin_amdgcn_s_waitcnt(0xc07f);
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_sync();
                     a2p = ring_area2(Ps, n, lane);
-                    if (a2p != 0) inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, lane, &st_tiles);
+                    if (a2p != 0)
+                        inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, lane,
+                                            sList[wave], sCross[wave], &st_tiles);
                     st_tiled++;
-                    done = true;
-                }
-                if (!done) {
+                } else {
                     st_general += 2ull * (unsigned long long)n * (unsigned long long)m;
                     PairIn in;
                     in.P = Pg; in.n = n; in.Q = Qg; in.m = m; in.ox = ox; in.oy = oy;
