@@ -188,6 +188,17 @@ def main():
                 "kernel": "k_refine", "launch_ms": 1e3 * t_ref, "pairs": n_cand,
                 "tiled_pairs": rstats[0], "tiles": rstats[1], "general_edge_pairs": rstats[2],
                 "disjoint_pairs": rstats[3], "edge_pairs_tested": tested}
+    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE runs,
+    # only while the kernel's sources are the ones the counters were taken on
+    from paper_2511_16576_amd import profiling
+    tpath = os.path.join(ROOT, "profiles", "hbm_traffic_workload2.json")
+    if os.path.exists(tpath):
+        tr = json.load(open(tpath)).get("kernels", {})
+        for kname, roof in (("k_refine", roof_ref), ("k_sign", roof_sign)):
+            rec = tr.get(kname)
+            if rec and rec.get("source_hash") == profiling.source_hash(kname):
+                roof["traffic"] = rec["bytes"]
+                roof["traffic_unit"] = "bytes per launch"
     dominant = roof_ref if t_ref > t_sign_avg * 2 else roof_sign
 
     # recall@10 on a query sample against GPU brute force (all pairs refined

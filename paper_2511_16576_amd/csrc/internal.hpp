@@ -122,6 +122,21 @@ __device__ __forceinline__ int wave_incl_scan32(int x)
     return s;
 }
 
+// The same inclusive prefix sum for 64-bit integers.
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x)
+{
+    uint64_t s = (uint64_t)x;
+    const uint64_t u = (uint64_t)x;
+    s += dpp::mov64<dpp::kRowShr1>(0, u);
+    s += dpp::mov64<dpp::kRowShr2>(0, u);
+    s += dpp::mov64<dpp::kRowShr3>(0, u);
+    s += dpp::mov64<dpp::kRowShr4, 0xf, 0xe>(0, s);
+    s += dpp::mov64<dpp::kRowShr8, 0xf, 0xc>(0, s);
+    s += dpp::mov64<dpp::kRowBcast15, 0xa>(0, s);
+    s += dpp::mov64<dpp::kRowBcast31, 0xc>(0, s);
+    return (int64_t)s;
+}
+
 // Per-polygon flag bits written by the staging kernel.
 constexpr uint32_t kFlagFew = 1u;        // fewer than 3 vertices
 constexpr uint32_t kFlagCollinear = 2u;  // all vertices on one line

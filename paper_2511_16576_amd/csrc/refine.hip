@@ -268,7 +268,7 @@ __device__ __forceinline__ void poly_mbr(const int32_t *v, int32_t n, int lane, 
 constexpr int kTileCap = 512;
 constexpr int kRingLds = kTileCap + 16;   // ring vertices incl. padding
 constexpr int kWavesPerBlock = 4;
-constexpr int kListCap = 128;             // per-wavefront ring of tile entries
+constexpr int kListCap = 256;             // per-wavefront ring of tile entries (< 8 pending + 128 new)
 constexpr int kCrossCap = 128;            // per-wavefront crossing buffer
 constexpr int kClassPos = (1 << 7) | (1 << 8) | (1 << 9);
 constexpr int kClassPosZ = kClassPos | (1 << 5) | (1 << 6);
@@ -276,8 +276,9 @@ constexpr int kClassPosZ = kClassPos | (1 << 5) | (1 << 6);
 struct RingLds {
     int2 *v;            // vertices relative to the origin; v[n..] repeat v[0]
     int4 *box;          // per 8-edge chunk: xmin, ymin, xmax, ymax
-    uint32_t *S;        // net crossing sign per edge, two biased 16-bit halves a word
+    uint32_t *S;        // P only: net crossing sign per edge, two biased 16-bit halves a word
     uint16_t *cls;      // Q only: per edge, the class set counted as positive
+    double *suf;        // Q only: suffix sums of the edges' cross products (see below)
 };
 
 // Crossing-sign sums are kept as 16-bit halves biased by 2^15 inside 32-bit
@@ -358,6 +359,28 @@ __device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
     }
 }
 
+// Wavefront form for P (lane = chunk, ncp <= 64): the chunk boxes, and the
+// ring's doubled area accumulated over the same vertex walk (uniform).
+__device__ int64_t chunk_boxes_area(RingLds R, int n, int lane)
+{
+    const int nc = (n + 7) >> 3;
+    int64_t a2 = 0;
+    if (lane < nc) {
+        int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+        const int e1 = min(n, 8 * lane + 8);
+        int2 p = R.v[8 * lane];
+        for (int v = 8 * lane; v < e1; v++) {
+            const int2 q = R.v[v + 1];
+            x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
+            a2 += (int64_t)p.x * q.y - (int64_t)q.x * p.y;
+            p = q;
+        }
+        x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
+        R.box[lane] = make_int4(x0, y0, x1, y1);
+    }
+    return wave_sum_i64(a2);
+}
+
 // Tie-break class sets of Q's edges [0, total): for a shifted Q edge
 // (c + delta, d + delta) tested against a point of P, a zero orientation
 // counts as positive when dy > 0, or dy = 0 and dx < 0.  Zero-length and
@@ -375,55 +398,85 @@ __device__ void edge_classes_q(RingLds R, int n, int total, int t0, int nt)
     }
 }
 
-// Membership of point a + sh*delta in ring R (half-open crossing rule with the
-// perturbation): sh = -1 tests a - delta (a vertex of P against Q + delta),
-// sh = +1 tests a + delta (a vertex of Q + delta against P).
-__device__ int member_wave(RingLds R, int n, int2 a, int sh, int lane)
+// One edge's parity term in the membership of point a + sh*delta in a ring
+// (half-open crossing rule with the perturbation): sh = -1 tests a - delta
+// (a vertex of P against Q + delta), sh = +1 tests a + delta (a vertex of
+// Q + delta against P).  A straddling edge is never horizontal.
+__device__ __forceinline__ bool member_edge(const int2 *v, int e, int2 a, int sh)
 {
-    bool odd = false;
-    for (int e = lane; e < n; e += 64) {
-        const int2 c = R.v[e], d = R.v[e + 1];
-        if (c.x == d.x && c.y == d.y) continue;
-        // straddle of the horizontal through a + sh*(eps, eps^2)
-        const bool st = (sh < 0) ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
-        if (!st) continue;
-        // orient(c, d, a + sh*delta): tie broken by the perturbation
-        const int dx = d.x - c.x, dy = d.y - c.y;
-        const int tb = (sh < 0) ? (dy != 0 ? (dy > 0 ? 1 : -1) : (dx > 0 ? -1 : 1))
-                                : (dy != 0 ? (dy > 0 ? -1 : 1) : (dx > 0 ? 1 : -1));
-        const int so = sgn_tb(orient_d(c, d, a), tb);
-        odd ^= (so == (dy > 0 ? 1 : -1));
-    }
-    return __popcll(__ballot(odd)) & 1;
+    const int2 c = v[e], d = v[e + 1];
+    const bool st = sh < 0 ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
+    const int up = d.y > c.y ? 1 : -1;
+    const int tb = sh < 0 ? up : -up;   // sign of orient(c, d, a + sh*delta) when orient(c, d, a) = 0
+    const double o = orient_d(c, d, a);
+    const int so = o > 0 ? 1 : (o < 0 ? -1 : tb);
+    return st & (so == up);
 }
 
-// sum_e cr_e * w_e with w_e = w0 + s * (exclusive prefix of S along the ring).
-__device__ double membership_term(RingLds R, int n, int w0, int s, int lane)
+// Ring-start memberships of both rings in one pass: w0p for P's vertex 0
+// against Q + delta, w0q for Q's vertex 0 + delta against P.
+__device__ void member_starts(RingLds P, int n, RingLds Q, int m, int lane, int &w0p, int &w0q)
+{
+    const int2 p0 = P.v[0], q0 = Q.v[0];
+    bool oddp = false, oddq = false;
+    const int top = max(n, m);
+    for (int e = lane; e < top; e += 64) {
+        const bool lq = e < m, lp = e < n;
+        oddp ^= lq & member_edge(Q.v, lq ? e : 0, p0, -1);
+        oddq ^= lp & member_edge(P.v, lp ? e : 0, q0, +1);
+    }
+    w0p = __popcll(__ballot(oddp)) & 1;
+    w0q = __popcll(__ballot(oddq)) & 1;
+}
+
+// P's membership sum: sum_e cr_e * w_e with w_e = w0 + s * (exclusive prefix
+// of S along the ring), s = Q's orientation; a per-lane partial.  Branch-free,
+// so the scan runs with every lane active.
+//
+// Q's sum needs no pass per pair: exchanging the order of summation,
+//   sum_f cr_f * (w0 + s' * sum_{f' < f} S_f') = w0 * A2Q + s' * sum_{f'} S_f' * Suf(f'),
+// with Suf(f') = sum_{f > f'} cr_f fixed by Q alone (staged once per query),
+// so every crossing on Q's edge f' adds its sign times Suf(f').
+__device__ double membership_term_p(RingLds P, int n, int w0, int s, int lane)
 {
     double acc = 0.0;
     int carry = 0;
     for (int base = 0; base < n; base += 64) {
-        // branch-free so that the scan below runs with every lane active
         const int e = base + lane;
         const bool live = e < n;
         const int ee = live ? e : 0;
-        const int Se = live ? s_get(R.S, ee) : 0;
-        const int2 a = R.v[ee], b = R.v[ee + 1];
+        const int Se = live ? s_get(P.S, ee) : 0;
+        const int2 a = P.v[ee], b = P.v[ee + 1];
         const double cr = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
-        // inclusive scan of Se over the wavefront
         const int incl = wave_incl_scan32(Se);
-        const int excl = incl - Se;
-        acc += live ? cr * (double)(w0 + s * (carry + excl)) : 0.0;
+        acc += live ? cr * (double)(w0 + s * (carry + incl - Se)) : 0.0;
         carry += __builtin_amdgcn_readlane(incl, 63);
     }
     return acc;
+}
+
+// Q's suffix sums Suf(f) = A2Q - sum_{f' <= f} cr_f' (exact in 64-bit
+// integers), by one wavefront.
+__device__ void q_suffix_sums(RingLds Q, int m, int64_t a2q, int lane)
+{
+    int64_t carry = 0;
+    for (int base = 0; base < m; base += 64) {
+        const int e = base + lane;
+        const bool live = e < m;
+        const int ee = live ? e : 0;
+        const int2 a = Q.v[ee], b = Q.v[ee + 1];
+        const int64_t cr = live ? (int64_t)a.x * b.y - (int64_t)b.x * a.y : 0;
+        const int64_t incl = carry + wave_incl_scan64(cr);
+        if (live) Q.suf[e] = (double)(a2q - incl);
+        carry = (int64_t)dpp::readlane64((uint64_t)incl, 63);
+    }
 }
 
 // Crossing contributions of buffered (e, f) pairs, 64 at a time with every
 // lane busy: the orientations are recomputed exactly as in the sweep, so the
 // signs and parameters are the ones that detected the crossing.
 __device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int count, int lane,
-                                double &accP, double &accQ)
+                                double &accP, double &accQ, double &accM)
 {
     for (int k = lane; k < count; k += 64) {
         const uint32_t ef = buf[k];
@@ -445,30 +498,34 @@ __device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int c
         accP += cre * (p4 ? 1.0 : -1.0) * (-ob) * rcp_refined(oa - ob);
         accQ += crf * (p2 ? 1.0 : -1.0) * (-od) * rcp_refined(oc - od);
         s_add(P.S, e, p4 ? 1 : -1);
-        s_add(Q.S, f, p2 ? 1 : -1);
+        accM += (p2 ? 1.0 : -1.0) * Q.suf[f];
     }
 }
 
 // Up to 8 tiles: lane (lane >> 3, j) takes Q edge j of its tile's Q chunk and
-// sweeps the tile's 8 P edges.  entry = (P chunk << 16) | Q chunk.  Crossing
+// sweeps the tile's 8 P edges.  entry = (P chunk << 8) | Q chunk.  Crossing
 // lanes only append (e << 16 | f) to the wavefront's crossing buffer, which
 // is flushed before it can overflow.
 __device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int lane, uint32_t *xbuf,
-                                           int &xcount, double &accP, double &accQ)
+                                           int &xcount, double &accP, double &accQ, double &accM)
 {
-    const int cp = entry >> 16, cq = entry & 0xffff;
+    const int cp = entry >> 8, cq = entry & 0xff;
     const int f = 8 * cq + (lane & 7);
     const int2 c = Q.v[f], d = Q.v[f + 1];
     const double cx = (double)c.x, cy = (double)c.y;
     const double fx = (double)(d.x - c.x), fy = (double)(d.y - c.y);
     const int mf = Q.cls[f];
     const int e0 = 8 * cp;
-    const int2 a0 = P.v[e0];
-    double ax = (double)a0.x, ay = (double)a0.y;
+    // the chunk's 9 vertices up front: the crossing-buffer stores in the
+    // sweep would otherwise keep these loads from being issued early
+    int2 pv[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) pv[i] = P.v[e0 + i];
+    double ax = (double)pv[0].x, ay = (double)pv[0].y;
     double rx = cx - ax, ry = cy - ay;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-        const int2 b = P.v[e0 + i + 1];
+        const int2 b = pv[i + 1];
         const double bx = (double)b.x, by = (double)b.y;
         const double ex = bx - ax, ey = by - ay;
         const double thr = p_edge_threshold(ex, ey);
@@ -488,7 +545,7 @@ __device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int 
         xcount += __popcll(cm);
         if (xcount > kCrossCap - 64) {
             wave_lds_sync();
-            flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ);
+            flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ, accM);
             wave_lds_sync();
             xcount = 0;
         }
@@ -497,13 +554,13 @@ __device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int 
     }
 }
 
-__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int lane,
-                             uint32_t *list, uint32_t *xbuf, unsigned long long *tiles)
+__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int64_t a2q, int lane,
+                             uint16_t *list, uint32_t *xbuf, unsigned long long *tiles)
 {
     // ring-start memberships under Q + delta
-    const int w0p = member_wave(Q, m, P.v[0], -1, lane);
-    const int w0q = member_wave(P, n, Q.v[0], +1, lane);
-    double accP = 0.0, accQ = 0.0;
+    int w0p, w0q;
+    member_starts(P, n, Q, m, lane, w0p, w0q);
+    double accP = 0.0, accQ = 0.0, accM = 0.0;
     const int ncp = (n + 7) >> 3, ncq = (m + 7) >> 3;
     const int total = ncp * ncq;
     // idx -> (idx / ncq, idx % ncq) without an integer division: the float
@@ -512,55 +569,52 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
     const float rq = 1.0f / (float)ncq;
     const int slot = lane >> 3;
     int head = 0, tail = 0, xcount = 0;
-    for (int base = 0; base < total; base += 64) {
-        const int idx = base + lane;
-        bool ov = false;
-        int entry = 0;
-        if (idx < total) {
-            const int cp = (int)(((float)idx + 0.5f) * rq);
-            const int cq = idx - cp * ncq;
-            const int4 bp = P.box[cp], bq = Q.box[cq];
-            ov = !(bp.z < bq.x || bq.z < bp.x || bp.w < bq.y || bq.w < bp.y);
-            entry = (cp << 16) | cq;
+    // two batches of 64 chunk pairs per round trip through the list
+    for (int base = 0; base < total; base += 128) {
+        int en[2];
+        bool ov[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int idx = base + 64 * h + lane;
+            ov[h] = false;
+            en[h] = 0;
+            if (idx < total) {
+                const int cp = (int)(((float)idx + 0.5f) * rq);
+                const int cq = idx - cp * ncq;
+                const int4 bp = P.box[cp], bq = Q.box[cq];
+                ov[h] = !(bp.z < bq.x || bq.z < bp.x || bp.w < bq.y || bq.w < bp.y);
+                en[h] = (cp << 8) | cq;
+            }
         }
-        const uint64_t mk = __ballot(ov);
-        const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-        if (ov) list[(tail + rank) & (kListCap - 1)] = (uint32_t)entry;
-        tail += __popcll(mk);
+        const uint64_t mk0 = __ballot(ov[0]), mk1 = __ballot(ov[1]);
+        const int r0 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk0, 0u));
+        const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk1, 0u));
+        const int c0 = __popcll(mk0);
+        if (ov[0]) list[(tail + r0) & (kListCap - 1)] = (uint16_t)en[0];
+        if (ov[1]) list[(tail + c0 + r1) & (kListCap - 1)] = (uint16_t)en[1];
+        tail += c0 + __popcll(mk1);
         wave_lds_sync();
         while (tail - head >= 8) {
-            tile_group(P, Q, (int)list[(head + slot) & (kListCap - 1)], lane, xbuf, xcount, accP, accQ);
+            tile_group(P, Q, (int)list[(head + slot) & (kListCap - 1)], lane, xbuf, xcount, accP, accQ, accM);
             head += 8;
         }
     }
     if (tail > head) {
         // partial group: empty slots take the all-padding Q chunk ncq
         const int k = tail - head;
-        const int entry = slot < k ? (int)list[(head + slot) & (kListCap - 1)] : ncq;
-        tile_group(P, Q, entry, lane, xbuf, xcount, accP, accQ);
+        const int entry = slot < k ? (int)list[(head + slot) & (kListCap - 1)] : ncq;  // P chunk 0
+        tile_group(P, Q, entry, lane, xbuf, xcount, accP, accQ, accM);
     }
     if (xcount > 0) {
         wave_lds_sync();
-        flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ);
+        flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ, accM);
     }
     *tiles += (unsigned long long)tail;
     // make the crossing sums visible to the whole wavefront
     wave_lds_sync();
-    const double mp = membership_term(P, n, w0p, sq, lane);
-    const double mq = membership_term(Q, m, w0q, sp, lane);
-    const double tot = sp * (mp + sq * accP) + sq * (mq + sp * accQ);
-    return wave_sum(tot);
-}
-
-__device__ int64_t ring_area2(RingLds R, int n, int lane)
-{
-    int64_t a = 0;
-    for (int e = lane; e < n; e += 64) {
-        const int2 p = R.v[e], q = R.v[e + 1];
-        a += (int64_t)p.x * q.y - (int64_t)q.x * p.y;
-    }
-    return wave_sum_i64(a);
+    // sp * (mp + sq * accP) + sq * (mq + sp * accQ), mq = w0q * A2Q + sp * accM
+    const double tot = sp * membership_term_p(P, n, w0p, sq, lane) + (double)(sp * sq) * (accP + accQ + accM);
+    return wave_sum(tot) + (double)(sq * w0q) * (double)a2q;
 }
 
 // One workgroup per query: Q staged once, wavefronts take its candidates.
@@ -579,8 +633,8 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     __shared__ int2 sPv[kWavesPerBlock][kRingLds];
     __shared__ int4 sPbox[kWavesPerBlock][kTileCap / 8];
     __shared__ uint32_t sPS[kWavesPerBlock][kTileCap / 2];
-    __shared__ uint32_t sQS[kWavesPerBlock][kTileCap / 2];
-    __shared__ uint32_t sList[kWavesPerBlock][kListCap];
+    __shared__ double sQsuf[kTileCap];
+    __shared__ uint16_t sList[kWavesPerBlock][kListCap];
     __shared__ uint32_t sCross[kWavesPerBlock][kCrossCap];
     __shared__ int32_t sQmbr[4];
     __shared__ long long sQa2;
@@ -612,11 +666,13 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
         // Q padded by one extra chunk: the all-padding chunk ncq fills empty
         // slots of a partial tile group
         const int qpad = 8 * ((m + 7) >> 3) + 8;
-        RingLds Qs{sQv, sQbox, nullptr, sQcls};
+        RingLds Qs{sQv, sQbox, nullptr, sQcls, sQsuf};
         stage_ring(Qg, m, qpad + 1, ox, oy, Qs, tid, blockDim.x);
         __syncthreads();
         chunk_boxes(Qs, m, tid, blockDim.x);
         edge_classes_q(Qs, m, qpad, tid, blockDim.x);
+        __syncthreads();
+        if (wave == 0) q_suffix_sums(Qs, m, sQa2, lane);
     }
     __syncthreads();
     const int32_t qmbr[4] = {sQmbr[0], sQmbr[1], sQmbr[2], sQmbr[3]};
@@ -639,8 +695,8 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
         double J = 0.0;
         if (n >= 3 && a2q != 0) {
             const bool tiled_size = q_tiled && n <= kTileCap;
-            RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr};
-            RingLds Qs{sQv, sQbox, sQS[wave], sQcls};
+            RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr, nullptr};
+            RingLds Qs{sQv, sQbox, nullptr, sQcls, sQsuf};
             const int ppad = 8 * ((n + 7) >> 3);
             int32_t pm[4];
             // staging records the MBR of the absolute coordinates, so a wide
@@ -657,13 +713,11 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                 int64_t a2p = 0;
                 if (!wide && tiled_size) {
                     for (int i = lane; i < (n + 1) >> 1; i += 64) Ps.S[i] = kSBias;
-                    for (int i = lane; i < (m + 1) >> 1; i += 64) Qs.S[i] = kSBias;
                     wave_lds_sync();
-                    chunk_boxes(Ps, n, lane, 64);
+                    a2p = chunk_boxes_area(Ps, n, lane);
                     wave_lds_sync();
-                    a2p = ring_area2(Ps, n, lane);
                     if (a2p != 0)
-                        inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, lane,
+                        inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2q, lane,
                                             sList[wave], sCross[wave], &st_tiles);
                     st_tiled++;
                 } else {

@@ -1,0 +1,155 @@
+"""Summaries of rocprofv3 output for the records kept under ``profiles/``.
+
+Two commands (run from the repository root):
+
+``python -m paper_2511_16576_amd.profiling stats --csv <kernel_stats.csv> --out <file.md> --title T --command C``
+    Markdown table of a ``--kernel-trace --stats`` run (per-kernel calls,
+    average / min / max duration, share of GPU time).
+
+``python -m paper_2511_16576_amd.profiling traffic --fetch <counter_collection.csv> --write <counter_collection.csv> --out <file.json> --md <file.md> --command-fetch C1 --command-write C2``
+    HBM traffic per dispatch of the hot kernels from one ``--pmc FETCH_SIZE``
+    and one ``--pmc WRITE_SIZE`` run.  Both runs include one device-to-device
+    copy of a known size (``bench.py --copy-calibration``: 256 MiB); each
+    counter is scaled by (copy bytes) / (what that counter reads for the copy
+    dispatch), so the result is in bytes moved.  The JSON also records a hash
+    of each kernel's sources: a reader (``bench.py``) uses the figure only
+    while the kernel is unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+COPY_BYTES = 256 << 20
+
+# kernel -> the sources it is built from
+KERNEL_SOURCES = {
+    "k_refine": ["refine.hip", "internal.hpp"],
+    "k_sign": ["sign.hip", "internal.hpp"],
+}
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    if "(anonymous namespace)::" in name:
+        name = name.split("(anonymous namespace)::")[1]
+    name = name.split("(")[0].replace("void ", "")
+    if name.startswith("k_sign"):
+        return "k_sign"
+    return name
+
+
+def stats_markdown(csv_path: str, title: str, command: str, notes: str = "", top: int = 18) -> str:
+    rows = list(csv.DictReader(open(csv_path)))
+    out = [f"# {title}", "", "Command (from `/tmp` with `TMPDIR=/tmp`; `<repo>` is the repository root):", "",
+           "```", command, "```", ""]
+    if notes:
+        out += [notes, ""]
+    out += ["| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        nm = r["Name"]
+        if "(anonymous namespace)::" in nm:
+            nm = nm.split("(anonymous namespace)::")[1]
+        nm = nm.split("(")[0].replace("void ", "")
+        out.append(f"| {nm} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(csv_path: str, counter: str):
+    """kernel short name -> list of per-dispatch counter values (KiB)."""
+    per = collections.defaultdict(list)
+    copies = []
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        nm = r["Kernel_Name"]
+        if "copyBuffer" in nm:
+            copies.append(v)
+        per[short_name(nm)].append(v)
+    return per, copies
+
+
+def traffic(fetch_csv: str, write_csv: str, kernels=("k_refine", "k_sign")) -> dict:
+    fetch, fcopies = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopies = _per_kernel(write_csv, "WRITE_SIZE")
+    if not fcopies or not wcopies:
+        raise RuntimeError("no copy dispatch in the counter runs (run bench.py with --copy-calibration)")
+    # the calibration copy is the largest copy dispatch of each run
+    f_copy, w_copy = max(fcopies), max(wcopies)
+    f_scale = COPY_BYTES / (f_copy * 1024.0)
+    w_scale = COPY_BYTES / (w_copy * 1024.0)
+    out = {"copy_bytes": COPY_BYTES, "fetch_kib_for_copy": f_copy, "write_kib_for_copy": w_copy,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for k in kernels:
+        fv, wv = fetch.get(k, []), write.get(k, [])
+        if not fv or not wv:
+            continue
+        f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
+        out["kernels"][k] = {
+            "dispatches": len(fv), "fetch_kib": f_kib, "write_kib": w_kib,
+            "fetch_bytes": f_kib * 1024.0 * f_scale, "write_bytes": w_kib * 1024.0 * w_scale,
+            "bytes": f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale,
+            "source_hash": source_hash(k),
+        }
+    return out
+
+
+def traffic_markdown(t: dict, cmd_fetch: str, cmd_write: str) -> str:
+    out = ["# HBM traffic per dispatch of the hot kernels (workload 2 bench step)", "",
+           "Commands (from `/tmp` with `TMPDIR=/tmp`; `<repo>` is the repository root):", "", "```",
+           cmd_fetch, cmd_write, "```", "",
+           f"Calibration: a {t['copy_bytes'] >> 20} MiB device-to-device copy reads as "
+           f"FETCH_SIZE = {t['fetch_kib_for_copy']:.1f} KiB and WRITE_SIZE = {t['write_kib_for_copy']:.1f} KiB, "
+           f"so FETCH_SIZE is scaled by {t['fetch_scale']:.4f} and WRITE_SIZE by {t['write_scale']:.4f} "
+           "to give bytes.", "",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes read | bytes written | total | source hash |",
+           "|---|---|---|---|---|---|---|---|"]
+    for k, v in t["kernels"].items():
+        out.append(f"| {k} | {v['dispatches']} | {v['fetch_kib']:.1f} | {v['write_kib']:.1f} | "
+                   f"{v['fetch_bytes'] / 1e6:.1f} MB | {v['write_bytes'] / 1e6:.1f} MB | {v['bytes'] / 1e6:.1f} MB | "
+                   f"`{v['source_hash']}` |")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--csv", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--notes", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--md", required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        open(a.out, "w").write(stats_markdown(a.csv, a.title, a.command, a.notes))
+    else:
+        res = traffic(a.fetch, a.write)
+        json.dump(res, open(a.out, "w"), indent=1)
+        open(a.md, "w").write(traffic_markdown(res, a.command_fetch, a.command_write))
+
+
+if __name__ == "__main__":
+    main()
