@@ -176,18 +176,24 @@ def main():
                  "kernel": "k_sign", "launch_ms": 1e3 * t_sign_avg,
                  "draws_per_launch": 0.5 * (dw_d + dw_q), "edge_tests_per_launch": 0.5 * (ed_d + ed_q)}
     # -- refinement roofline (k_refine; FP64 VALU bound).  Algorithmic work:
-    # the edge pairs the tiled form tests (8 x 8 tiles of chunk pairs whose
-    # boxes overlap) times C_PAIR, plus the general form's edge pairs times
-    # C_GENERAL.
+    # the edge pairs the tiled form tests (counted by the kernel: 8 per kept
+    # (P chunk, Q edge) unit) times C_PAIR, plus the general form's edge pairs
+    # times C_GENERAL.
     _, rstats = pm.refine_stats(D, Q, off, ids)
-    tested = 64.0 * rstats[1] + rstats[2]
+    tested = float(rstats[1] + rstats[2])
     t_ref = stage_ms["refine"] / 1e3
-    work_ref = 64.0 * rstats[1] * C_PAIR + rstats[2] * C_GENERAL
+    work_ref = rstats[1] * C_PAIR + rstats[2] * C_GENERAL
     roof_ref = {"bound": "alu", "achieved": work_ref / t_ref / 1e12, "peak": PEAK_VALU / 1e12,
                 "unit": "T lane-cycles/s", "frac": work_ref / t_ref / PEAK_VALU, "traffic": None,
                 "kernel": "k_refine", "launch_ms": 1e3 * t_ref, "pairs": n_cand,
-                "tiled_pairs": rstats[0], "tiles": rstats[1], "general_edge_pairs": rstats[2],
+                "tiled_pairs": rstats[0], "edge_pairs_swept": rstats[1], "general_edge_pairs": rstats[2],
                 "disjoint_pairs": rstats[3], "edge_pairs_tested": tested}
+    # context: all n x m edge pairs of the candidate pairs (what a test of
+    # every pair would cost); the chunk and edge boxes cull the rest
+    nd = (D.offsets[1:] - D.offsets[:-1]).double()
+    nqv = (Q.offsets[1:] - Q.offsets[:-1]).double()
+    qrow = torch.repeat_interleave(torch.arange(Q.n, device=dev), off[1:] - off[:-1])
+    roof_ref["edge_pairs_all"] = float((nd[ids.long()] * nqv[qrow]).sum())
     # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE runs,
     # only while the kernel's sources are the ones the counters were taken on
     from paper_2511_16576_amd import profiling

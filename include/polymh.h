@@ -207,8 +207,9 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
 
 /* polymh_refine_stats -- polymh_refine that also adds its work counts to
  * stats [4] (device uint64, caller-zeroed): pairs refined by the tiled form,
- * 8 x 8 edge-pair tiles tested there, edge pairs tested by the general form,
- * and pairs skipped because their MBRs are disjoint.  Stream-ordered. */
+ * edge pairs that form tested (8 per kept (P chunk, Q edge) unit), edge
+ * pairs tested by the general form, and pairs skipped because their MBRs are
+ * disjoint.  Stream-ordered. */
 polymh_status polymh_refine_stats(const polymh_polys *data, const polymh_polys *queries,
                                   const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                                   int64_t n_cand, double *cand_j, uint64_t *stats, void *stream);

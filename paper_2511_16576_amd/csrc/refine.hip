@@ -268,8 +268,9 @@ __device__ __forceinline__ void poly_mbr(const int32_t *v, int32_t n, int lane, 
 constexpr int kTileCap = 512;
 constexpr int kRingLds = kTileCap + 16;   // ring vertices incl. padding
 constexpr int kWavesPerBlock = 4;
-constexpr int kListCap = 256;             // per-wavefront ring of tile entries (< 8 pending + 128 new)
+constexpr int kListCap = 256;             // per-wavefront ring of tile entries (< 16 pending + 128 new)
 constexpr int kCrossCap = 128;            // per-wavefront crossing buffer
+constexpr int kUnitCap = 256;             // per-wavefront ring of sweep units (< 64 pending + 128 new)
 constexpr int kClassPos = (1 << 7) | (1 << 8) | (1 << 9);
 constexpr int kClassPosZ = kClassPos | (1 << 5) | (1 << 6);
 
@@ -277,7 +278,6 @@ struct RingLds {
     int2 *v;            // vertices relative to the origin; v[n..] repeat v[0]
     int4 *box;          // per 8-edge chunk: xmin, ymin, xmax, ymax
     uint32_t *S;        // P only: net crossing sign per edge, two biased 16-bit halves a word
-    uint16_t *cls;      // Q only: per edge, the class set counted as positive
     double *suf;        // Q only: suffix sums of the edges' cross products (see below)
 };
 
@@ -292,6 +292,14 @@ __device__ __forceinline__ void s_add(uint32_t *S, int e, int v)
 __device__ __forceinline__ int s_get(const uint32_t *S, int e)
 {
     return (int)((S[e >> 1] >> (16 * (e & 1))) & 0xffffu) - 0x8000;
+}
+
+// Tie-break class set of a shifted Q edge (c + delta, d + delta), f = d - c,
+// for orientations of points of P: a zero counts as positive when fy > 0, or
+// fy = 0 and fx < 0 (zero-length edges never cross either way).
+__device__ __forceinline__ int q_edge_class(int fx, int fy)
+{
+    return (fy > 0 || (fy == 0 && fx < 0)) ? kClassPosZ : kClassPos;
 }
 
 // Tie-break threshold of a P edge (e = b - a) for orientations of points of
@@ -330,19 +338,28 @@ __device__ void stage_ring(const int32_t *src, int n, int pad_to, int64_t ox, in
 }
 
 // Wavefront staging of a data polygon (as stage_ring) that also returns the
-// MBR of its absolute coordinates (uniform).
+// MBR of its absolute coordinates (uniform) and the first vertex strictly
+// outside the box qb (-1 if none): that vertex is outside Q, and so is the
+// vertex minus delta.
 __device__ void stage_ring_mbr(const int32_t *src, int n, int pad_to, int64_t ox, int64_t oy,
-                               RingLds R, int lane, int32_t *mbr)
+                               RingLds R, int lane, const int32_t *qb, int32_t *mbr, int &anchor)
 {
     int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
     const int2 *v = reinterpret_cast<const int2 *>(src);
-    for (int i = lane; i < pad_to; i += 64) {
+    int k = -1;
+    for (int base = 0; base < pad_to; base += 64) {
+        const int i = base + lane;
+        const bool live = i < pad_to;
         const int2 p = v[i < n ? i : 0];
+        if (live) R.v[i] = make_int2((int)((int64_t)p.x - ox), (int)((int64_t)p.y - oy));
         x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
-        R.v[i] = make_int2((int)((int64_t)p.x - ox), (int)((int64_t)p.y - oy));
+        const bool out = (i < n) & ((p.x < qb[0]) | (p.x > qb[2]) | (p.y < qb[1]) | (p.y > qb[3]));
+        const uint64_t mk = __ballot(out);
+        if (k < 0 && mk != 0) k = base + __builtin_ctzll(mk);
     }
     mbr[0] = wave_min32(x0); mbr[1] = wave_min32(y0);
     mbr[2] = wave_max32(x1); mbr[3] = wave_max32(y1);
+    anchor = k;
 }
 
 __device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
@@ -381,23 +398,6 @@ __device__ int64_t chunk_boxes_area(RingLds R, int n, int lane)
     return wave_sum_i64(a2);
 }
 
-// Tie-break class sets of Q's edges [0, total): for a shifted Q edge
-// (c + delta, d + delta) tested against a point of P, a zero orientation
-// counts as positive when dy > 0, or dy = 0 and dx < 0.  Zero-length and
-// padding edges get the strict set (they never cross either way).
-__device__ void edge_classes_q(RingLds R, int n, int total, int t0, int nt)
-{
-    for (int e = t0; e < total; e += nt) {
-        bool pz = false;
-        if (e < n) {
-            const int2 a = R.v[e], b = R.v[e + 1];
-            const int dx = b.x - a.x, dy = b.y - a.y;
-            pz = dy > 0 || (dy == 0 && dx < 0);
-        }
-        R.cls[e] = (uint16_t)(pz ? kClassPosZ : kClassPos);
-    }
-}
-
 // One edge's parity term in the membership of point a + sh*delta in a ring
 // (half-open crossing rule with the perturbation): sh = -1 tests a - delta
 // (a vertex of P against Q + delta), sh = +1 tests a + delta (a vertex of
@@ -415,13 +415,14 @@ __device__ __forceinline__ bool member_edge(const int2 *v, int e, int2 a, int sh
 
 // Ring-start memberships of both rings in one pass: w0p for P's vertex 0
 // against Q + delta, w0q for Q's vertex 0 + delta against P.
-__device__ void member_starts(RingLds P, int n, RingLds Q, int m, int lane, int &w0p, int &w0q)
+__device__ void member_starts(RingLds P, int n, RingLds Q, int m, int lane, bool need_p, bool need_q,
+                              int &w0p, int &w0q)
 {
     const int2 p0 = P.v[0], q0 = Q.v[0];
     bool oddp = false, oddq = false;
-    const int top = max(n, m);
+    const int top = max(need_p ? m : 0, need_q ? n : 0);
     for (int e = lane; e < top; e += 64) {
-        const bool lq = e < m, lp = e < n;
+        const bool lq = need_p & (e < m), lp = need_q & (e < n);
         oddp ^= lq & member_edge(Q.v, lq ? e : 0, p0, -1);
         oddq ^= lp & member_edge(P.v, lp ? e : 0, q0, +1);
     }
@@ -437,10 +438,16 @@ __device__ void member_starts(RingLds P, int n, RingLds Q, int m, int lane, int 
 //   sum_f cr_f * (w0 + s' * sum_{f' < f} S_f') = w0 * A2Q + s' * sum_{f'} S_f' * Suf(f'),
 // with Suf(f') = sum_{f > f'} cr_f fixed by Q alone (staged once per query),
 // so every crossing on Q's edge f' adds its sign times Suf(f').
-__device__ double membership_term_p(RingLds P, int n, int w0, int s, int lane)
+//
+// Here the sum is split as w0 * A2P + s * T, T = sum_e cr_e * pre(e) with
+// pre(e) the exclusive prefix of S; the function returns T (a per-lane
+// partial) and K = pre(anchor) (uniform), so that a known membership at any
+// anchor vertex fixes w0 = w(anchor) - s * K.
+__device__ double membership_term_p(RingLds P, int n, int anchor, int lane, int &K)
 {
     double acc = 0.0;
     int carry = 0;
+    K = 0;
     for (int base = 0; base < n; base += 64) {
         const int e = base + lane;
         const bool live = e < n;
@@ -449,10 +456,33 @@ __device__ double membership_term_p(RingLds P, int n, int w0, int s, int lane)
         const int2 a = P.v[ee], b = P.v[ee + 1];
         const double cr = __fma_rn((double)a.x, (double)b.y, -(double)b.x * (double)a.y);
         const int incl = wave_incl_scan32(Se);
-        acc += live ? cr * (double)(w0 + s * (carry + incl - Se)) : 0.0;
+        const int excl = carry + incl - Se;
+        acc += live ? cr * (double)excl : 0.0;
+        if (anchor >= base && anchor < base + 64) K = __builtin_amdgcn_readlane(excl, anchor - base);
         carry += __builtin_amdgcn_readlane(incl, 63);
     }
     return acc;
+}
+
+// Indices of a leftmost, a rightmost, a lowest and a highest vertex of Q
+// (rb: Q's MBR relative to the origin), by one wavefront.  A pair whose P
+// MBR leaves one of those sides of Q's MBR open anchors Q's memberships at
+// that vertex (it lies outside P).
+__device__ void q_extremes(RingLds Q, int m, int4 rb, int lane, int *ext)
+{
+    int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
+    for (int base = 0; base < m; base += 64) {
+        const int i = base + lane;
+        const bool live = i < m;
+        const int2 p = Q.v[live ? i : 0];
+        const uint64_t b0 = __ballot(live & (p.x == rb.x)), b1 = __ballot(live & (p.x == rb.z));
+        const uint64_t b2 = __ballot(live & (p.y == rb.y)), b3 = __ballot(live & (p.y == rb.w));
+        if (k0 < 0 && b0 != 0) k0 = base + __builtin_ctzll(b0);
+        if (k1 < 0 && b1 != 0) k1 = base + __builtin_ctzll(b1);
+        if (k2 < 0 && b2 != 0) k2 = base + __builtin_ctzll(b2);
+        if (k3 < 0 && b3 != 0) k3 = base + __builtin_ctzll(b3);
+    }
+    if (lane == 0) { ext[0] = k0; ext[1] = k1; ext[2] = k2; ext[3] = k3; }
 }
 
 // Q's suffix sums Suf(f) = A2Q - sum_{f' <= f} cr_f' (exact in 64-bit
@@ -475,8 +505,8 @@ __device__ void q_suffix_sums(RingLds Q, int m, int64_t a2q, int lane)
 // Crossing contributions of buffered (e, f) pairs, 64 at a time with every
 // lane busy: the orientations are recomputed exactly as in the sweep, so the
 // signs and parameters are the ones that detected the crossing.
-__device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int count, int lane,
-                                double &accP, double &accQ, double &accM)
+__device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int count, int lane, int kq,
+                                double &accP, double &accQ, double &accM, double &accK)
 {
     for (int k = lane; k < count; k += 64) {
         const uint32_t ef = buf[k];
@@ -492,29 +522,30 @@ __device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int c
         const double X = __fma_rn(ex, fy, -(ey * fx));
         const double od = oc + X, ob = oa - X;
         const bool p2 = od > p_edge_threshold(ex, ey);
-        const bool p4 = __builtin_amdgcn_class(ob, (int)Q.cls[f]);
+        const bool p4 = __builtin_amdgcn_class(ob, q_edge_class(d.x - c.x, d.y - c.y));
         const double cre = __fma_rn(ax, by, -(bx * ay));
         const double crf = __fma_rn(cx, fy, -(fx * cy));
         accP += cre * (p4 ? 1.0 : -1.0) * (-ob) * rcp_refined(oa - ob);
         accQ += crf * (p2 ? 1.0 : -1.0) * (-od) * rcp_refined(oc - od);
         s_add(P.S, e, p4 ? 1 : -1);
         accM += (p2 ? 1.0 : -1.0) * Q.suf[f];
+        accK += f < kq ? (p2 ? 1.0 : -1.0) : 0.0;
     }
 }
 
-// Up to 8 tiles: lane (lane >> 3, j) takes Q edge j of its tile's Q chunk and
-// sweeps the tile's 8 P edges.  entry = (P chunk << 8) | Q chunk.  Crossing
-// lanes only append (e << 16 | f) to the wavefront's crossing buffer, which
-// is flushed before it can overflow.
-__device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int lane, uint32_t *xbuf,
-                                           int &xcount, double &accP, double &accQ, double &accM)
+// One sweep unit per lane: Q edge f held in registers against the 8 edges of
+// P chunk cp (entry = cp << 10 | f).  Crossing lanes only append
+// (e << 16 | f) to the wavefront's crossing buffer, which is flushed before
+// it can overflow.
+__device__ __forceinline__ void sweep_units(RingLds P, RingLds Q, int entry, int lane, uint32_t *xbuf,
+                                            int &xcount, int kq, double &accP, double &accQ, double &accM,
+                                            double &accK)
 {
-    const int cp = entry >> 8, cq = entry & 0xff;
-    const int f = 8 * cq + (lane & 7);
+    const int cp = entry >> 10, f = entry & 1023;
     const int2 c = Q.v[f], d = Q.v[f + 1];
     const double cx = (double)c.x, cy = (double)c.y;
     const double fx = (double)(d.x - c.x), fy = (double)(d.y - c.y);
-    const int mf = Q.cls[f];
+    const int mf = q_edge_class(d.x - c.x, d.y - c.y);
     const int e0 = 8 * cp;
     // the chunk's 9 vertices up front: the crossing-buffer stores in the
     // sweep would otherwise keep these loads from being issued early
@@ -545,7 +576,7 @@ __device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int 
         xcount += __popcll(cm);
         if (xcount > kCrossCap - 64) {
             wave_lds_sync();
-            flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ, accM);
+            flush_crossings(P, Q, xbuf, xcount, lane, kq, accP, accQ, accM, accK);
             wave_lds_sync();
             xcount = 0;
         }
@@ -554,22 +585,65 @@ __device__ __forceinline__ void tile_group(RingLds P, RingLds Q, int entry, int 
     }
 }
 
-__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int64_t a2q, int lane,
-                             uint16_t *list, uint32_t *xbuf, unsigned long long *tiles)
+// Expand up to 16 listed tiles (lane = tile slot x Q edge j, two slots per
+// lane) into sweep units, keeping the (P chunk, Q edge) pairs whose boxes
+// touch: a crossing needs the Q edge's box to meet the box of the P edge it
+// crosses, inside the chunk's.
+__device__ __forceinline__ void expand_tiles(RingLds P, RingLds Q, int m, const uint16_t *tiles, int head,
+                                             int count, int lane, uint16_t *units, int &utail)
 {
-    // ring-start memberships under Q + delta
-    int w0p, w0q;
-    member_starts(P, n, Q, m, lane, w0p, w0q);
-    double accP = 0.0, accQ = 0.0, accM = 0.0;
+    bool keep[2];
+    int entry[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int slot = (lane >> 3) + 8 * h;
+        keep[h] = false;
+        entry[h] = 0;
+        if (slot < count) {
+            const int t = (int)tiles[(head + slot) & (kListCap - 1)];
+            const int cp = t >> 8, cq = t & 0xff;
+            const int f = 8 * cq + (lane & 7);
+            if (f < m) {
+                const int2 c = Q.v[f], d = Q.v[f + 1];
+                const int4 bp = P.box[cp];
+                keep[h] = !(max(c.x, d.x) < bp.x || bp.z < min(c.x, d.x) || max(c.y, d.y) < bp.y ||
+                            bp.w < min(c.y, d.y));
+                entry[h] = (cp << 10) | f;
+            }
+        }
+    }
+    const uint64_t mk0 = __ballot(keep[0]), mk1 = __ballot(keep[1]);
+    const int r0 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk0, 0u));
+    const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk1, 0u));
+    const int c0 = __popcll(mk0);
+    if (keep[0]) units[(utail + r0) & (kUnitCap - 1)] = (uint16_t)entry[0];
+    if (keep[1]) units[(utail + c0 + r1) & (kUnitCap - 1)] = (uint16_t)entry[1];
+    utail += c0 + __popcll(mk1);
+}
+
+// kp / kq: a vertex of P outside Q (and of Q outside P), or -1; the ring's
+// memberships are anchored there (membership 0), else at vertex 0 by a
+// crossing-number pass.
+__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int64_t a2p, int64_t a2q,
+                             int kp, int kq, int lane, uint16_t *list, uint16_t *units, uint32_t *xbuf,
+                             unsigned long long *swept)
+{
+    int wkp = 0, wkq = 0;
+    if (kp < 0 || kq < 0) {
+        int w0p, w0q;
+        member_starts(P, n, Q, m, lane, kp < 0, kq < 0, w0p, w0q);
+        if (kp < 0) { kp = 0; wkp = w0p; }
+        if (kq < 0) { kq = 0; wkq = w0q; }
+    }
+    double accP = 0.0, accQ = 0.0, accM = 0.0, accK = 0.0;
     const int ncp = (n + 7) >> 3, ncq = (m + 7) >> 3;
     const int total = ncp * ncq;
     // idx -> (idx / ncq, idx % ncq) without an integer division: the float
     // quotient of idx + 1/2 is at least 1/(2 ncq) >= 1/128 away from an
     // integer while its rounding error is below 2^-10 (idx < 2^12).
     const float rq = 1.0f / (float)ncq;
-    const int slot = lane >> 3;
-    int head = 0, tail = 0, xcount = 0;
-    // two batches of 64 chunk pairs per round trip through the list
+    int head = 0, tail = 0, uhead = 0, utail = 0, xcount = 0;
+    // two batches of 64 chunk pairs per round trip through the tile list
     for (int base = 0; base < total; base += 128) {
         int en[2];
         bool ov[2];
@@ -593,28 +667,49 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
         if (ov[0]) list[(tail + r0) & (kListCap - 1)] = (uint16_t)en[0];
         if (ov[1]) list[(tail + c0 + r1) & (kListCap - 1)] = (uint16_t)en[1];
         tail += c0 + __popcll(mk1);
-        wave_lds_sync();
-        while (tail - head >= 8) {
-            tile_group(P, Q, (int)list[(head + slot) & (kListCap - 1)], lane, xbuf, xcount, accP, accQ, accM);
-            head += 8;
+        const bool last = base + 128 >= total;
+        while (tail - head >= 16 || (last && tail > head)) {
+            wave_lds_sync();
+            const int cnt = min(16, tail - head);
+            expand_tiles(P, Q, m, list, head, cnt, lane, units, utail);
+            head += cnt;
+            wave_lds_sync();
+            while (utail - uhead >= 64) {
+                sweep_units(P, Q, (int)units[(uhead + lane) & (kUnitCap - 1)], lane, xbuf, xcount, kq, accP, accQ, accM, accK);
+                uhead += 64;
+            }
         }
     }
-    if (tail > head) {
-        // partial group: empty slots take the all-padding Q chunk ncq
-        const int k = tail - head;
-        const int entry = slot < k ? (int)list[(head + slot) & (kListCap - 1)] : ncq;  // P chunk 0
-        tile_group(P, Q, entry, lane, xbuf, xcount, accP, accQ, accM);
+    if (utail > uhead) {
+        // partial sweep: idle lanes take a padding edge of Q (zero length)
+        const int k = utail - uhead;
+        const int entry = lane < k ? (int)units[(uhead + lane) & (kUnitCap - 1)] : 8 * ncq;
+        sweep_units(P, Q, entry, lane, xbuf, xcount, kq, accP, accQ, accM, accK);
     }
     if (xcount > 0) {
         wave_lds_sync();
-        flush_crossings(P, Q, xbuf, xcount, lane, accP, accQ, accM);
+        flush_crossings(P, Q, xbuf, xcount, lane, kq, accP, accQ, accM, accK);
     }
-    *tiles += (unsigned long long)tail;
+    *swept += 8ull * (unsigned long long)utail;   // edge pairs tested (idle lanes excluded)
     // make the crossing sums visible to the whole wavefront
     wave_lds_sync();
-    // sp * (mp + sq * accP) + sq * (mq + sp * accQ), mq = w0q * A2Q + sp * accM
-    const double tot = sp * membership_term_p(P, n, w0p, sq, lane) + (double)(sp * sq) * (accP + accQ + accM);
-    return wave_sum(tot) + (double)(sq * w0q) * (double)a2q;
+    // 2 A = sp * (mp + sq * accP) + sq * (mq + sp * accQ) with
+    //   mp = w0p * A2P + sq * T,  w0p = w(kp) - sq * pre_P(kp),
+    //   mq = w0q * A2Q + sp * accM,  w0q = w(kq) - sp * pre_Q(kq), pre_Q(kq) = sum of accK
+    int K;
+    const double T = membership_term_p(P, n, kp, lane, K);
+    const double tot = (double)(sp * sq) * (T + accP + accQ + accM - (double)a2q * accK);
+    return wave_sum(tot) + (double)(sp * (wkp - sq * K)) * (double)a2p + (double)(sq * wkq) * (double)a2q;
+}
+
+// A vertex of Q strictly outside P's MBR among Q's extreme vertices, or -1.
+__device__ __forceinline__ int anchor_q(const int32_t *qb, const int32_t *pb, const int *ext)
+{
+    if (qb[0] < pb[0]) return ext[0];
+    if (qb[2] > pb[2]) return ext[1];
+    if (qb[1] < pb[1]) return ext[2];
+    if (qb[3] > pb[3]) return ext[3];
+    return -1;
 }
 
 // One workgroup per query: Q staged once, wavefronts take its candidates.
@@ -629,15 +724,16 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
 {
     __shared__ int2 sQv[kRingLds];
     __shared__ int4 sQbox[kTileCap / 8];
-    __shared__ uint16_t sQcls[kRingLds];
     __shared__ int2 sPv[kWavesPerBlock][kRingLds];
     __shared__ int4 sPbox[kWavesPerBlock][kTileCap / 8];
     __shared__ uint32_t sPS[kWavesPerBlock][kTileCap / 2];
     __shared__ double sQsuf[kTileCap];
     __shared__ uint16_t sList[kWavesPerBlock][kListCap];
+    __shared__ uint16_t sUnits[kWavesPerBlock][kUnitCap];
     __shared__ uint32_t sCross[kWavesPerBlock][kCrossCap];
     __shared__ int32_t sQmbr[4];
     __shared__ long long sQa2;
+    __shared__ int sQext[4];
 
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -666,19 +762,24 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
         // Q padded by one extra chunk: the all-padding chunk ncq fills empty
         // slots of a partial tile group
         const int qpad = 8 * ((m + 7) >> 3) + 8;
-        RingLds Qs{sQv, sQbox, nullptr, sQcls, sQsuf};
+        RingLds Qs{sQv, sQbox, nullptr, sQsuf};
         stage_ring(Qg, m, qpad + 1, ox, oy, Qs, tid, blockDim.x);
         __syncthreads();
         chunk_boxes(Qs, m, tid, blockDim.x);
-        edge_classes_q(Qs, m, qpad, tid, blockDim.x);
         __syncthreads();
-        if (wave == 0) q_suffix_sums(Qs, m, sQa2, lane);
+        if (wave == 0) {
+            q_suffix_sums(Qs, m, sQa2, lane);
+            const int4 rb = make_int4((int)((int64_t)sQmbr[0] - ox), (int)((int64_t)sQmbr[1] - oy),
+                                      (int)((int64_t)sQmbr[2] - ox), (int)((int64_t)sQmbr[3] - oy));
+            q_extremes(Qs, m, rb, lane, sQext);
+        }
     }
     __syncthreads();
     const int32_t qmbr[4] = {sQmbr[0], sQmbr[1], sQmbr[2], sQmbr[3]};
+    const int qext[4] = {sQext[0], sQext[1], sQext[2], sQext[3]};
     const int64_t a2q = sQa2;
     const int nwaves = blockDim.x >> 6;
-    unsigned long long st_tiled = 0, st_tiles = 0, st_general = 0, st_disjoint = 0;
+    unsigned long long st_tiled = 0, st_swept = 0, st_general = 0, st_disjoint = 0;
     // Candidate metadata is fetched ahead: the id two candidates on and the
     // vertex range of the next one, so their latency hides behind this pair.
     int64_t c = c0 + wave;
@@ -695,13 +796,14 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
         double J = 0.0;
         if (n >= 3 && a2q != 0) {
             const bool tiled_size = q_tiled && n <= kTileCap;
-            RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr, nullptr};
-            RingLds Qs{sQv, sQbox, nullptr, sQcls, sQsuf};
+            RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr};
+            RingLds Qs{sQv, sQbox, nullptr, sQsuf};
             const int ppad = 8 * ((n + 7) >> 3);
             int32_t pm[4];
             // staging records the MBR of the absolute coordinates, so a wide
             // pair (whose relative coordinates do not fit) is still detected
-            if (tiled_size) stage_ring_mbr(Pg, n, ppad + 1, ox, oy, Ps, lane, pm);
+            int kp = -1;
+            if (tiled_size) stage_ring_mbr(Pg, n, ppad + 1, ox, oy, Ps, lane, qmbr, pm, kp);
             else poly_mbr(Pg, n, lane, pm);
             const bool disjoint = pm[2] <= qmbr[0] || qmbr[2] <= pm[0] || pm[3] <= qmbr[1] || qmbr[3] <= pm[1];
             st_disjoint += disjoint;
@@ -717,8 +819,9 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                     a2p = chunk_boxes_area(Ps, n, lane);
                     wave_lds_sync();
                     if (a2p != 0)
-                        inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2q, lane,
-                                            sList[wave], sCross[wave], &st_tiles);
+                        inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2p, a2q, kp,
+                                            anchor_q(qmbr, pm, qext), lane,
+                                            sList[wave], sUnits[wave], sCross[wave], &st_swept);
                     st_tiled++;
                 } else {
                     st_general += 2ull * (unsigned long long)n * (unsigned long long)m;
@@ -750,7 +853,7 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     }
     if (stats && lane == 0) {
         atomicAdd(stats + 0, (unsigned long long)(st_tiled));
-        atomicAdd(stats + 1, st_tiles);
+        atomicAdd(stats + 1, st_swept);
         atomicAdd(stats + 2, st_general);
         atomicAdd(stats + 3, st_disjoint);
     }

@@ -304,7 +304,8 @@ def refine(data: DevicePolys, queries: DevicePolys, cand_off: torch.Tensor, cand
 
 
 def refine_stats(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, stream=None):
-    """(J float64 [C], work counts: tiled pairs, tiles, general edge pairs, disjoint pairs)."""
+    """(J float64 [C], work counts: tiled pairs, edge pairs swept by the tiled form,
+    general edge pairs, disjoint pairs)."""
     c = cand_ids.numel()
     out = torch.empty(max(c, 1), dtype=torch.float64, device=cand_ids.device)
     stats = torch.zeros(4, dtype=torch.int64, device=cand_ids.device)

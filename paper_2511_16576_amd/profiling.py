@@ -6,6 +6,11 @@ Two commands (run from the repository root):
     Markdown table of a ``--kernel-trace --stats`` run (per-kernel calls,
     average / min / max duration, share of GPU time).
 
+``python -m paper_2511_16576_amd.profiling valu --pmc <counter_collection.csv> --stats <kernel_stats.csv> --out <file.md> --command C``
+    Issued VALU work per dispatch (``SQ_INSTS_VALU`` x 64 lanes) over the
+    kernel's average duration from the trace run, against the VALU peak of
+    256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+
 ``python -m paper_2511_16576_amd.profiling traffic --fetch <counter_collection.csv> --write <counter_collection.csv> --out <file.json> --md <file.md> --command-fetch C1 --command-write C2``
     HBM traffic per dispatch of the hot kernels from one ``--pmc FETCH_SIZE``
     and one ``--pmc WRITE_SIZE`` run.  Both runs include one device-to-device
@@ -126,6 +131,37 @@ def traffic_markdown(t: dict, cmd_fetch: str, cmd_write: str) -> str:
     return "\n".join(out) + "\n"
 
 
+PEAK_LANE_CYCLES = 256 * 4 * 16 * 2.4e9
+
+
+def valu_markdown(pmc_csv: str, stats_csv: str, command: str, kernels=("k_refine", "k_sign")) -> str:
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(pmc_csv)):
+        per[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = {}
+    for r in csv.DictReader(open(stats_csv)):
+        dur.setdefault(short_name(r["Name"]), float(r["AverageNs"]) * 1e-9)
+    out = ["# Issued VALU work of the hot kernels (workload 2 bench step)", "",
+           "Command (from `/tmp` with `TMPDIR=/tmp`; `<repo>` is the repository root):", "", "```", command,
+           "```", "",
+           "Hardware VALU fraction = SQ_INSTS_VALU x 64 lane-cycles / average duration (kernel-trace run) / "
+           "39.3 T lane-cycles/s.  It counts every issued VALU instruction, useful or not; the bench's "
+           "`roofline.frac` counts only the algorithmic operations.", "",
+           "| kernel | dispatches | VALU instr / dispatch | SALU instr / dispatch | waves / dispatch | avg duration ms | "
+           "issued T lane-cycles/s | hardware VALU fraction |", "|---|---|---|---|---|---|---|---|"]
+    for k in kernels:
+        d = per.get(k)
+        if not d or k not in dur:
+            continue
+        mean = {c: sum(v) / len(v) for c, v in d.items()}
+        valu = mean.get("SQ_INSTS_VALU", 0.0)
+        rate = valu * 64 / dur[k]
+        out.append(f"| {k} | {len(d['SQ_INSTS_VALU'])} | {valu:.4g} | {mean.get('SQ_INSTS_SALU', 0):.4g} | "
+                   f"{mean.get('SQ_WAVES', 0):.4g} | {dur[k] * 1e3:.3f} | {rate / 1e12:.2f} | "
+                   f"{rate / PEAK_LANE_CYCLES:.3f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -135,6 +171,11 @@ def main():
     s.add_argument("--title", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--notes", default="")
+    v = sub.add_parser("valu")
+    v.add_argument("--pmc", required=True)
+    v.add_argument("--stats", required=True)
+    v.add_argument("--out", required=True)
+    v.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -145,6 +186,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "stats":
         open(a.out, "w").write(stats_markdown(a.csv, a.title, a.command, a.notes))
+    elif a.cmd == "valu":
+        open(a.out, "w").write(valu_markdown(a.pmc, a.stats, a.command))
     else:
         res = traffic(a.fetch, a.write)
         json.dump(res, open(a.out, "w"), indent=1)
