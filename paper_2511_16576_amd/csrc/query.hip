@@ -9,17 +9,6 @@ namespace polymh {
 
 namespace {
 
-__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v)
-{
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (a[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(256) void k_zero_u32(uint32_t *p, int64_t count)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -27,7 +16,33 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t *p, int64_t count)
         p[i] = 0u;
 }
 
+// First index in a[lo, hi) whose value is >= v, by a 64-way search: each
+// round the lanes sample 64 evenly spaced positions and the count of samples
+// below v (a ballot) narrows the range by a factor of 64.  All lanes of the
+// wavefront take part; the result is uniform.
+__device__ __forceinline__ int64_t lower_bound_wave(const uint64_t *a, int64_t lo, int64_t hi, uint64_t v,
+                                                    int lane)
+{
+    while (hi - lo > 64) {
+        const int64_t step = (hi - lo + 63) >> 6;
+        const int64_t p = lo + (int64_t)lane * step;
+        const bool valid = p < hi;
+        const bool less = valid && a[valid ? p : lo] < v;
+        const int c = __popcll(__ballot(less));
+        const int nvalid = __popcll(__ballot(valid));
+        const int64_t nlo = c > 0 ? lo + (int64_t)(c - 1) * step + 1 : lo;
+        const int64_t nhi = c < nvalid ? lo + (int64_t)c * step : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const int64_t p = lo + lane;
+    const bool less = p < hi && a[p < hi ? p : lo] < v;
+    return lo + __popcll(__ballot(less));
+}
+
 // One wavefront per (query, band): find the bucket, lanes mark its entries.
+// The bucket's end is found by scanning forward 64 entries at a time (a
+// bucket holds the polygons sharing one 64-bit key: a handful).
 __global__ __launch_bounds__(256) void k_mark(const uint64_t *__restrict__ skeys,
                                               const int32_t *__restrict__ sids, int64_t n_entries,
                                               const uint64_t *__restrict__ qkeys, int64_t nq,
@@ -36,19 +51,21 @@ __global__ __launch_bounds__(256) void k_mark(const uint64_t *__restrict__ skeys
     const int lane = threadIdx.x & 63;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nq * b; w += nw) {
-        // every lane runs the (uniform) binary searches: no lane-0 branch
-        // feeding a cross-lane read
         const uint64_t key = qkeys[w];
         const int32_t t = (int32_t)(w % b);
-        const int64_t lo = lower_bound_u64(skeys, n_entries, key);
-        int64_t hi = lo;
-        if (lo < n_entries && skeys[lo] == key)
-            hi = (key == ~0ull) ? n_entries : lower_bound_u64(skeys, n_entries, key + 1);
         uint32_t *row = bitmap + (w / b) * words;
-        for (int64_t e = lo + lane; e < hi; e += 64) {
-            const int32_t ent = sids[e];          // entry p*b + t'
-            const int32_t id = ent / b;
-            if (ent - id * b == t) atomicOr(&row[id >> 5], 1u << (id & 31));
+        int64_t e0 = lower_bound_wave(skeys, 0, n_entries, key, lane);
+        while (e0 < n_entries) {
+            const int64_t e = e0 + lane;
+            const bool in = e < n_entries && skeys[e < n_entries ? e : 0] == key;
+            const uint64_t mk = __ballot(in);
+            if (in) {
+                const int32_t ent = sids[e];          // entry p*b + t'
+                const int32_t id = ent / b;
+                if (ent - id * b == t) atomicOr(&row[id >> 5], 1u << (id & 31));
+            }
+            if (mk != ~0ull) break;                   // the bucket ended inside this window
+            e0 += 64;
         }
     }
 }
