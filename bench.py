@@ -163,6 +163,24 @@ def main():
     ms = 1e3 * elapsed / args.steps
     log(f"timed {args.steps} steps: {ms:.2f} ms/step")
 
+    # the same dataset signing as a plain launch (one workgroup per (polygon,
+    # hash block), no persistent longest-first queue): the batched-versus-plain
+    # comparison of the signing launch
+    cfg_plain = pm.sign_config(**{**cfg.as_dict(), "persistent": 0})
+    ws_p = torch.empty(pm.sign_workspace_size(D.n, cfg_plain), dtype=torch.uint8, device=dev)
+    sig_p = torch.empty_like(sig)
+    pm.sign(D, w.box, w.seed, k, cap, config=cfg_plain, out=sig_p, ws=ws_p)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        pm.sign(D, w.box, w.seed, k, cap, config=cfg_plain, out=sig_p, ws=ws_p)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / 3 / 1e3
+    if not torch.equal(sig_p, sig):
+        raise RuntimeError("plain and persistent signing launches disagree")
+    log(f"dataset signing as a plain launch: {1e3 * t_plain:.3f} ms")
+
     # per-stage breakdown from a separate instrumented pass
     times = {}
     for _ in range(2):
@@ -244,34 +262,41 @@ def main():
 
     batched = None
     if not args.no_batched:
+        # query batches through the preallocated pipeline (sign, band, capped
+        # lookup, refine, top-10), each batch issued eagerly (one library call
+        # per stage) or replayed as one captured HIP graph; per-batch latency
+        # with the batch's queries loaded beforehand, at three batch sizes
         from paper_2511_16576_amd.pipeline import QueryBatch
-        nb = args.batch_queries
         sig_d = torch.empty((D.n, k), dtype=torch.int32, device=dev)
         pm.sign(D, w.box, w.seed, k, cap, config=cfg, out=sig_d, ws=ws_d)
         sk_b, se_b = pm.index_build(pm.band(sig_d, b, r, w.seed))
-        bl = [w.queries.subset(np.arange(i, i + nb)) for i in range(0, Q.n - nb + 1, nb)]
-        maxv = max(x.xy.shape[0] for x in bl)
-        cand_cap = int(4 * n_cand / Q.n * nb) + 1024
-        qb = QueryBatch(D, sk_b, se_b, w.box, w.seed, k, cap, b, r, nb, maxv, cand_cap, sign_config=cfg)
-        qb.load(bl[0])
-        qb.capture()
-        res = {}
-        for mode in ("eager", "graph"):
-            t_tot = 0.0
-            for rep in range(2):
-                for x in bl:
-                    qb.load(x)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    (qb.run_graph if mode == "graph" else qb.run_eager)()
-                    qb.stream.synchronize()
-                    if rep:
-                        t_tot += time.perf_counter() - t0
-            res[mode] = {"queries_per_s": len(bl) * nb / t_tot, "ms_per_batch": 1e3 * t_tot / len(bl)}
-        qb.result()
-        batched = {"batch_queries": nb, **res}
-        log(f"batched queries: eager {res['eager']['queries_per_s']:.0f} q/s, graph "
-            f"{res['graph']['queries_per_s']:.0f} q/s ({nb} per batch)")
+        batched = {}
+        for nb in sorted({10, 100, args.batch_queries}):
+            nbat = min(Q.n // nb, max(20, 2000 // nb))
+            bl = [w.queries.subset(np.arange(i * nb, (i + 1) * nb)) for i in range(nbat)]
+            maxv = max(x.xy.shape[0] for x in bl)
+            cand_cap = int(4 * n_cand / Q.n * nb) + 4096
+            qb = QueryBatch(D, sk_b, se_b, w.box, w.seed, k, cap, b, r, nb, maxv, cand_cap, sign_config=cfg)
+            qb.load(bl[0])
+            qb.capture()
+            res = {}
+            for mode in ("eager", "graph"):
+                t_tot = 0.0
+                for rep in range(2):
+                    for x in bl:
+                        qb.load(x)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        (qb.run_graph if mode == "graph" else qb.run_eager)()
+                        qb.stream.synchronize()
+                        if rep:
+                            t_tot += time.perf_counter() - t0
+                        qb.result()          # raises if the candidate capacity overflowed
+                res[mode] = {"queries_per_s": nbat * nb / t_tot, "ms_per_batch": 1e3 * t_tot / nbat}
+            batched[str(nb)] = res
+            log(f"batched queries, {nb} per batch: eager {res['eager']['ms_per_batch']:.3f} ms/batch "
+                f"({res['eager']['queries_per_s']:.0f} q/s), graph {res['graph']['ms_per_batch']:.3f} ms/batch "
+                f"({res['graph']['queries_per_s']:.0f} q/s)")
 
     learned = None
     if not args.no_learned:
@@ -310,6 +335,7 @@ def main():
                    "n_data": D.n, "n_queries": Q.n, "k": k, "bands": b, "rows": r,
                    "sign_config": cfg.as_dict()},
         "sign_sig_per_s": D.n * k / (stage_ms["sign"] / 1e3),
+        "sign_plain_launch_sig_per_s": D.n * k / t_plain,
         "queries_per_s": Q.n / (sum(stage_ms[s] for s in names[2:]) / 1e3),
         "candidates_per_query": n_cand / Q.n,
         "recall_at_10": rec,

@@ -20,6 +20,8 @@
 //
 // One wavefront per candidate pair; lanes take the edges of one polygon while
 // the other polygon's vertices are read at a uniform index (scalar loads).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace polymh {
@@ -720,7 +722,8 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                                                 const int64_t *__restrict__ cand_off,
                                                 const int32_t *__restrict__ cand_ids,
                                                 double *__restrict__ cand_j,
-                                                unsigned long long *__restrict__ stats)
+                                                unsigned long long *__restrict__ stats,
+                                                int slices)
 {
     __shared__ int2 sQv[kRingLds];
     __shared__ int4 sQbox[kTileCap / 8];
@@ -735,7 +738,10 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     __shared__ long long sQa2;
     __shared__ int sQext[4];
 
-    const int64_t q = blockIdx.x;
+    // `slices` workgroups share a query (small batches): slice s's wavefronts
+    // take candidates s * waves + wave, stepping by slices * waves
+    const int64_t q = blockIdx.x / slices;
+    const int slice = (int)(blockIdx.x % slices);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t qa = qoff[q];
@@ -744,7 +750,8 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     const int64_t c0 = cand_off[q], c1 = cand_off[q + 1];
     if (c0 == c1) return;
     if (m < 3) {
-        for (int64_t c = c0 + tid; c < c1; c += blockDim.x) cand_j[c] = 0.0;
+        for (int64_t c = c0 + (int64_t)slice * blockDim.x + tid; c < c1; c += (int64_t)slices * blockDim.x)
+            cand_j[c] = 0.0;
         return;
     }
     const int64_t ox = Qg[0], oy = Qg[1];
@@ -778,11 +785,11 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     const int32_t qmbr[4] = {sQmbr[0], sQmbr[1], sQmbr[2], sQmbr[3]};
     const int qext[4] = {sQext[0], sQext[1], sQext[2], sQext[3]};
     const int64_t a2q = sQa2;
-    const int nwaves = blockDim.x >> 6;
+    const int nwaves = (int)(blockDim.x >> 6) * slices;   // wavefronts on this query
     unsigned long long st_tiled = 0, st_swept = 0, st_general = 0, st_disjoint = 0;
     // Candidate metadata is fetched ahead: the id two candidates on and the
     // vertex range of the next one, so their latency hides behind this pair.
-    int64_t c = c0 + wave;
+    int64_t c = c0 + (int64_t)slice * (blockDim.x >> 6) + wave;
     int32_t p_ahead = c < c1 ? cand_ids[c] : 0;
     int64_t pa_next = 0, pe_next = 0;
     if (c < c1) { pa_next = doff[p_ahead]; pe_next = doff[p_ahead + 1]; }
@@ -868,8 +875,12 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
     if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "refine: too many queries");
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)nq), dim3(64 * kWavesPerBlock), 0, s, data->xy,
-                       data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j, stats);
+    // small batches spread each query over several workgroups (every
+    // workgroup stages the query once); from 2048 queries on, one each
+    const int slices = nq >= 2048 ? 1 : (int)std::min<int64_t>(16, (2048 + nq - 1) / nq);
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)(nq * slices)), dim3(64 * kWavesPerBlock), 0, s, data->xy,
+                       data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j, stats,
+                       slices);
     return check_launch("refine");
 }
 
