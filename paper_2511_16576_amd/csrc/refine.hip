@@ -87,12 +87,13 @@ __device__ __forceinline__ int tb_shift_edge(int64_t dx, int64_t dy)
     return dy != 0 ? (dy > 0 ? 1 : -1) : (dx > 0 ? -1 : 1);
 }
 
+// 1/d: the hardware reciprocal (relative error about 2^-24 on gfx950) and
+// one Newton step (error about 2^-48, measured), ample for crossing
+// parameters summed into areas checked to 1e-9.
 __device__ __forceinline__ double rcp_refined(double d)
 {
-    double r = __builtin_amdgcn_rcp(d);
-    r = __fma_rn(r, __fma_rn(-d, r, 1.0), r);
-    r = __fma_rn(r, __fma_rn(-d, r, 1.0), r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(d);
+    return __fma_rn(r, __fma_rn(-d, r, 1.0), r);
 }
 
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
@@ -340,27 +341,51 @@ __device__ void stage_ring(const int32_t *src, int n, int pad_to, int64_t ox, in
 }
 
 // Wavefront staging of a data polygon (as stage_ring) that also returns the
-// MBR of its absolute coordinates (uniform) and the first vertex strictly
-// outside the box qb (-1 if none): that vertex is outside Q, and so is the
-// vertex minus delta.
+// MBR of its absolute coordinates (uniform), the ring's doubled area about
+// the origin (exact, 64-bit; meaningful when the pair is not wide) and the
+// first vertex strictly outside the box qb (-1 if none): that vertex is
+// outside Q, and so is the vertex minus delta.
+// Vertices i and i + 1 of the first two 64-vertex windows, fetched one
+// candidate ahead (indices as the staging loop clamps them).
+struct RingPrefetch {
+    int2 p[2], q[2];
+};
+
+__device__ __forceinline__ void prefetch_ring(const int32_t *src, int n, int lane, RingPrefetch &pf)
+{
+    const int2 *v = reinterpret_cast<const int2 *>(src);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int i = 64 * h + lane;
+        pf.p[h] = v[i < n ? i : 0];
+        pf.q[h] = v[i + 1 < n ? i + 1 : 0];
+    }
+}
+
 __device__ void stage_ring_mbr(const int32_t *src, int n, int pad_to, int64_t ox, int64_t oy,
-                               RingLds R, int lane, const int32_t *qb, int32_t *mbr, int &anchor)
+                               RingLds R, int lane, const int32_t *qb, const RingPrefetch &pf, int32_t *mbr,
+                               int64_t &area2, int &anchor)
 {
     int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
     const int2 *v = reinterpret_cast<const int2 *>(src);
     int k = -1;
+    int64_t a2 = 0;
     for (int base = 0; base < pad_to; base += 64) {
         const int i = base + lane;
-        const bool live = i < pad_to;
-        const int2 p = v[i < n ? i : 0];
-        if (live) R.v[i] = make_int2((int)((int64_t)p.x - ox), (int)((int64_t)p.y - oy));
+        const bool live = i < pad_to, edge = i < n;
+        const int2 p = base == 0 ? pf.p[0] : base == 64 ? pf.p[1] : v[edge ? i : 0];
+        const int2 q = base == 0 ? pf.q[0] : base == 64 ? pf.q[1] : v[i + 1 < n ? i + 1 : 0];
+        const int64_t px = (int64_t)p.x - ox, py = (int64_t)p.y - oy;
+        if (live) R.v[i] = make_int2((int)px, (int)py);
+        a2 += edge ? px * ((int64_t)q.y - oy) - ((int64_t)q.x - ox) * py : 0;
         x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
-        const bool out = (i < n) & ((p.x < qb[0]) | (p.x > qb[2]) | (p.y < qb[1]) | (p.y > qb[3]));
+        const bool out = edge & ((p.x < qb[0]) | (p.x > qb[2]) | (p.y < qb[1]) | (p.y > qb[3]));
         const uint64_t mk = __ballot(out);
         if (k < 0 && mk != 0) k = base + __builtin_ctzll(mk);
     }
     mbr[0] = wave_min32(x0); mbr[1] = wave_min32(y0);
     mbr[2] = wave_max32(x1); mbr[3] = wave_max32(y1);
+    area2 = wave_sum_i64(a2);
     anchor = k;
 }
 
@@ -378,26 +403,24 @@ __device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
     }
 }
 
-// Wavefront form for P (lane = chunk, ncp <= 64): the chunk boxes, and the
-// ring's doubled area accumulated over the same vertex walk (uniform).
-__device__ int64_t chunk_boxes_area(RingLds R, int n, int lane)
+// Wavefront form for P (lane = chunk, ncp <= 64): the chunk boxes.
+// The 9 vertices of a chunk are read at once (indices clamped to the ring's
+// end, which only repeats a vertex) so their LDS latencies overlap.
+__device__ void chunk_boxes_p(RingLds R, int n, int lane)
 {
     const int nc = (n + 7) >> 3;
-    int64_t a2 = 0;
     if (lane < nc) {
-        int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
         const int e1 = min(n, 8 * lane + 8);
-        int2 p = R.v[8 * lane];
-        for (int v = 8 * lane; v < e1; v++) {
-            const int2 q = R.v[v + 1];
-            x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
-            a2 += (int64_t)p.x * q.y - (int64_t)q.x * p.y;
-            p = q;
+        int2 p[9];
+#pragma unroll
+        for (int j = 0; j < 9; j++) p[j] = R.v[min(8 * lane + j, e1)];
+        int x0 = p[0].x, y0 = p[0].y, x1 = p[0].x, y1 = p[0].y;
+#pragma unroll
+        for (int j = 1; j < 9; j++) {
+            x0 = min(x0, p[j].x); y0 = min(y0, p[j].y); x1 = max(x1, p[j].x); y1 = max(y1, p[j].y);
         }
-        x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
         R.box[lane] = make_int4(x0, y0, x1, y1);
     }
-    return wave_sum_i64(a2);
 }
 
 // One edge's parity term in the membership of point a + sh*delta in a ring
@@ -598,21 +621,18 @@ __device__ __forceinline__ void expand_tiles(RingLds P, RingLds Q, int m, const 
     int entry[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
+        // branch-free (see the batch loop); slots past `count` read entry 0
         const int slot = (lane >> 3) + 8 * h;
-        keep[h] = false;
-        entry[h] = 0;
-        if (slot < count) {
-            const int t = (int)tiles[(head + slot) & (kListCap - 1)];
-            const int cp = t >> 8, cq = t & 0xff;
-            const int f = 8 * cq + (lane & 7);
-            if (f < m) {
-                const int2 c = Q.v[f], d = Q.v[f + 1];
-                const int4 bp = P.box[cp];
-                keep[h] = !(max(c.x, d.x) < bp.x || bp.z < min(c.x, d.x) || max(c.y, d.y) < bp.y ||
-                            bp.w < min(c.y, d.y));
-                entry[h] = (cp << 10) | f;
-            }
-        }
+        const bool live = slot < count;
+        const int t = (int)tiles[(head + (live ? slot : 0)) & (kListCap - 1)];
+        const int cp = t >> 8, cq = t & 0xff;
+        const int f = 8 * cq + (lane & 7);
+        const int2 c = Q.v[f], d = Q.v[f + 1];
+        const int4 bp = P.box[cp];
+        const bool apart = (max(c.x, d.x) < bp.x) | (bp.z < min(c.x, d.x)) | (max(c.y, d.y) < bp.y) |
+                           (bp.w < min(c.y, d.y));
+        keep[h] = live & (f < m) & !apart;
+        entry[h] = (cp << 10) | f;
     }
     const uint64_t mk0 = __ballot(keep[0]), mk1 = __ballot(keep[1]);
     const int r0 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk0, 0u));
@@ -649,18 +669,19 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
     for (int base = 0; base < total; base += 128) {
         int en[2];
         bool ov[2];
+        // branch-free: whole boxes loaded at once, bitwise tests (no
+        // short-circuit chains of dependent LDS reads)
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            const int idx = base + 64 * h + lane;
-            ov[h] = false;
-            en[h] = 0;
-            if (idx < total) {
-                const int cp = (int)(((float)idx + 0.5f) * rq);
-                const int cq = idx - cp * ncq;
-                const int4 bp = P.box[cp], bq = Q.box[cq];
-                ov[h] = !(bp.z < bq.x || bq.z < bp.x || bp.w < bq.y || bq.w < bp.y);
-                en[h] = (cp << 8) | cq;
-            }
+            const int i0 = base + 64 * h + lane;
+            const bool live = i0 < total;
+            const int idx = live ? i0 : 0;
+            const int cp = (int)(((float)idx + 0.5f) * rq);
+            const int cq = idx - cp * ncq;
+            const int4 bp = P.box[cp], bq = Q.box[cq];
+            const bool apart = (bp.z < bq.x) | (bq.z < bp.x) | (bp.w < bq.y) | (bq.w < bp.y);
+            ov[h] = live & !apart;
+            en[h] = (cp << 8) | cq;
         }
         const uint64_t mk0 = __ballot(ov[0]), mk1 = __ballot(ov[1]);
         const int r0 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk0, 0u));
@@ -715,7 +736,7 @@ __device__ __forceinline__ int anchor_q(const int32_t *qb, const int32_t *pb, co
 }
 
 // One workgroup per query: Q staged once, wavefronts take its candidates.
-__global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
+__global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ dxy,
                                                 const int64_t *__restrict__ doff,
                                                 const int32_t *__restrict__ qxy,
                                                 const int64_t *__restrict__ qoff,
@@ -794,24 +815,33 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
     int64_t pa_next = 0, pe_next = 0;
     if (c < c1) { pa_next = doff[p_ahead]; pe_next = doff[p_ahead + 1]; }
     p_ahead = (c + nwaves < c1) ? cand_ids[c + nwaves] : 0;
+    // the data polygon's first 128 vertices are fetched one candidate ahead
+    RingPrefetch pf_next;
+    if (c < c1 && pe_next - pa_next >= 3) prefetch_ring(dxy + 2 * pa_next, (int)(pe_next - pa_next), lane, pf_next);
     for (; c < c1; c += nwaves) {
         const int64_t pa = pa_next;
         const int n = (int)(pe_next - pa_next);
+        const RingPrefetch pf = pf_next;
         if (c + nwaves < c1) { pa_next = doff[p_ahead]; pe_next = doff[p_ahead + 1]; }
         p_ahead = (c + 2 * nwaves < c1) ? cand_ids[c + 2 * nwaves] : 0;
         const int32_t *Pg = dxy + 2 * pa;
         double J = 0.0;
-        if (n >= 3 && a2q != 0) {
-            const bool tiled_size = q_tiled && n <= kTileCap;
-            RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr};
-            RingLds Qs{sQv, sQbox, nullptr, sQsuf};
-            const int ppad = 8 * ((n + 7) >> 3);
-            int32_t pm[4];
-            // staging records the MBR of the absolute coordinates, so a wide
-            // pair (whose relative coordinates do not fit) is still detected
-            int kp = -1;
-            if (tiled_size) stage_ring_mbr(Pg, n, ppad + 1, ox, oy, Ps, lane, qmbr, pm, kp);
-            else poly_mbr(Pg, n, lane, pm);
+        const bool valid = n >= 3 && a2q != 0;
+        const bool tiled_size = valid && q_tiled && n <= kTileCap;
+        RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr};
+        RingLds Qs{sQv, sQbox, nullptr, sQsuf};
+        const int ppad = 8 * ((n + 7) >> 3);
+        int32_t pm[4] = {0, 0, 0, 0};
+        // staging records the MBR of the absolute coordinates, so a wide
+        // pair (whose relative coordinates do not fit) is still detected
+        int kp = -1;
+        int64_t a2p_staged = 0;
+        if (tiled_size) stage_ring_mbr(Pg, n, ppad + 1, ox, oy, Ps, lane, qmbr, pf, pm, a2p_staged, kp);
+        else if (valid) poly_mbr(Pg, n, lane, pm);
+        // the next candidate's vertices, whatever this pair turns out to need
+        if (c + nwaves < c1 && pe_next - pa_next >= 3)
+            prefetch_ring(dxy + 2 * pa_next, (int)(pe_next - pa_next), lane, pf_next);
+        if (valid) {
             const bool disjoint = pm[2] <= qmbr[0] || qmbr[2] <= pm[0] || pm[3] <= qmbr[1] || qmbr[3] <= pm[1];
             st_disjoint += disjoint;
             if (!disjoint) {
@@ -823,7 +853,8 @@ __global__ __launch_bounds__(256) void k_refine(const int32_t *__restrict__ dxy,
                 if (!wide && tiled_size) {
                     for (int i = lane; i < (n + 1) >> 1; i += 64) Ps.S[i] = kSBias;
                     wave_lds_sync();
-                    a2p = chunk_boxes_area(Ps, n, lane);
+                    chunk_boxes_p(Ps, n, lane);
+                    a2p = a2p_staged;
                     wave_lds_sync();
                     if (a2p != 0)
                         inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2p, a2q, kp,
