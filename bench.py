@@ -313,7 +313,7 @@ def main():
         tc = time.perf_counter() - t2
         cpu = {"value": ids_s.size * k / tc, "unit": "signatures/s", "cores": th, "kind": "oracle",
                "sample": f"oracle Alg. 1 signing of {ids_s.size} workload-2 polygons x {k} hashes "
-                         f"({tc:.1f} s, OpenMP over polygons)"}
+                         f"({tc:.1f} s wall on {th} threads, ~{tc * th:.0f} core-seconds; OpenMP over polygons)"}
         log(f"cpu oracle: {cpu['value']:.3g} sig/s on {th} threads")
 
     total_sigs = (D.n + Q.n) * k
