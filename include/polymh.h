@@ -81,6 +81,23 @@ typedef struct {
 polymh_status polymh_prepare(const polymh_polys *polys, int32_t *mbr, int64_t *area2,
                              uint32_t *flags, void *stream);
 
+/* polymh_centre -- Sec. 3.1 centring: every polygon translated so that its
+ * area centroid, rounded to the lattice, is the origin (the paper centres
+ * polygons before hashing, for a translation-invariant shape search).
+ *   The centroid is the area-weighted mean of the signed fan triangles,
+ *   computed exactly in 128-bit integers; each coordinate is rounded by
+ *   floor(c + 1/2), which commutes with integer translations, so a polygon
+ *   and any integer translate of it centre to identical vertices.  Polygons
+ *   with fewer than 3 vertices or zero area are not moved.
+ *   xy_out     [V][2] int32 out: the translated vertices (same offsets as
+ *               `polys`; may not alias polys->xy).
+ *   shift      [n][2] int32 out (nullable): the rounded centroid removed.
+ *   range_flag int32 (nullable, caller-zeroed): set to 1 if a translated
+ *               coordinate leaves int32 (a polygon spanning 2^31 or more).
+ * Recompute B of the centred set with polymh_box_of.  Stream-ordered. */
+polymh_status polymh_centre(const polymh_polys *polys, int32_t *xy_out, int32_t *shift,
+                            int32_t *range_flag, void *stream);
+
 /* polymh_box_of -- the global MBR of all vertices of `polys` (Sec. 3.1),
  * written to *out_host.  `ws` must hold polymh_box_of_workspace_size() bytes.
  * SYNCHRONISES the stream.  POLYMH_EINVAL if the set has no vertex. */

@@ -140,6 +140,16 @@ polymh_status polymh_prepare(const polymh_polys *polys, int32_t *mbr, int64_t *a
     return launch_prepare(polys->xy, polys->offsets, polys->n, mbr, area2, flags, as_stream(stream));
 }
 
+polymh_status polymh_centre(const polymh_polys *polys, int32_t *xy_out, int32_t *shift,
+                            int32_t *range_flag, void *stream)
+{
+    polymh_status st = check_polys(polys, "centre");
+    if (st) return st;
+    if (polys->n > 0 && !xy_out) return set_error(POLYMH_EINVAL, "centre: xy_out is NULL");
+    if (polys->n > 0 && xy_out == polys->xy) return set_error(POLYMH_EINVAL, "centre: xy_out aliases the input");
+    return launch_centre(polys->xy, polys->offsets, polys->n, xy_out, shift, range_flag, as_stream(stream));
+}
+
 size_t polymh_box_of_workspace_size(void) { return 256; }
 
 polymh_status polymh_box_of(const polymh_polys *polys, void *ws, size_t ws_bytes,

@@ -179,6 +179,9 @@ polymh_status launch_sign_order(const int64_t *off, const int32_t *mbr, const in
                                 const uint32_t *flags, int64_t n, polymh_box box, int32_t k,
                                 uint32_t cap, int32_t *bucket_counts, int32_t *order,
                                 hipStream_t s);
+// centre.hip
+polymh_status launch_centre(const int32_t *xy, const int64_t *off, int64_t n, int32_t *out,
+                            int32_t *shift, int32_t *range_flag, hipStream_t s);
 
 // sign.hip
 struct SignLaunch {

@@ -56,6 +56,7 @@ _SIGNATURES = {
     "polymh_version": (I32, []),
     "polymh_check_device": (I32, []),
     "polymh_prepare": (I32, [P, P, P, P, P]),
+    "polymh_centre": (I32, [P, P, P, P, P]),
     "polymh_box_of_workspace_size": (SZ, []),
     "polymh_box_of": (I32, [P, P, SZ, P, P]),
     "polymh_sign_default_config": (None, [P]),
@@ -203,6 +204,21 @@ def prepare(polys: DevicePolys, stream=None):
     ps = polys.cstruct()
     _check(lib().polymh_prepare(ctypes.byref(ps), _ptr(mbr), _ptr(area2), _ptr(flags), _stream(stream)))
     return mbr[:n], area2[:n], flags[:n]
+
+
+def centre(polys: DevicePolys, stream=None):
+    """Sec. 3.1 centring: (centred DevicePolys with the same offsets, shift
+    int32 [N, 2]).  Synchronises once to check the int32 range flag."""
+    check_device()
+    dev = polys.offsets.device
+    xy = torch.empty_like(polys.xy)
+    shift = torch.empty((max(polys.n, 1), 2), dtype=torch.int32, device=dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    ps = polys.cstruct()
+    _check(lib().polymh_centre(ctypes.byref(ps), _ptr(xy), _ptr(shift), _ptr(flag), _stream(stream)))
+    if int(flag.item()):
+        raise ValueError("centre: a polygon spans 2^31 or more; its centred coordinates leave int32")
+    return DevicePolys(xy, polys.offsets), shift[:polys.n]
 
 
 def box_of(polys: DevicePolys, stream=None):
