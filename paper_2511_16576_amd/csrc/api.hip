@@ -249,6 +249,63 @@ polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t se
     return launch_sign(L, s);
 }
 
+size_t polymh_sign_binned_workspace_size(int64_t n, int32_t k, uint32_t cap, uint32_t horizon, int32_t bin_bits,
+                                         const polymh_sign_config *cfg)
+{
+    (void)cfg;
+    if (n < 0) n = 0;
+    if (k < 1 || bin_bits < 0 || bin_bits > 4 || horizon < 1) return 0;
+    if (horizon > cap) horizon = cap;
+    Carve cv{nullptr, 0};
+    carve_sign(cv, n, true);
+    return align_up(cv.used, 256) + binned_workspace_bytes(k, horizon, bin_bits, n) + 256;
+}
+
+polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, uint32_t *sig,
+                                 const polymh_sign_config *cfg, void *ws, size_t ws_bytes, void *stream)
+{
+    polymh_status st = check_polys(polys, "sign_binned");
+    if (st) return st;
+    if ((st = check_box(box, "sign_binned"))) return st;
+    if (k < 1 || k > 65535) return set_error(POLYMH_EINVAL, "sign_binned: k must be 1..65535");
+    if (cap < 1) return set_error(POLYMH_EINVAL, "sign_binned: cap must be >= 1");
+    if (horizon < 1) return set_error(POLYMH_EINVAL, "sign_binned: horizon must be >= 1");
+    if (bin_bits < 0 || bin_bits > 4) return set_error(POLYMH_EINVAL, "sign_binned: bin_bits must be 0..4");
+    if (horizon > cap) horizon = cap;
+    polymh_sign_config c;
+    if (cfg) c = *cfg;
+    else polymh_sign_default_config(&c);
+    c.persistent = 1;
+    if ((st = check_sign_config(c))) return st;
+    if (polys->n == 0) return POLYMH_OK;
+    if (!sig) return set_error(POLYMH_EINVAL, "sign_binned: sig is NULL");
+    if ((int64_t)polys->n * k > (int64_t)1 << 40)
+        return set_error(POLYMH_EINVAL, "sign_binned: n * k too large");
+    Carve cv{static_cast<char *>(ws), ws_bytes};
+    SignWs w = carve_sign(cv, polys->n, true);
+    if (!cv.ok)
+        return set_error(POLYMH_ECAPACITY, "sign_binned: workspace of %zu bytes too small", ws_bytes);
+    const size_t used = align_up(cv.used, 256);
+    hipStream_t s = as_stream(stream);
+    if ((st = launch_prepare(polys->xy, polys->offsets, polys->n, w.mbr, w.area2, w.flags, s))) return st;
+    SignLaunch L{};
+    L.xy = polys->xy;
+    L.off = polys->offsets;
+    L.mbr = w.mbr;
+    L.flags = w.flags;
+    L.queue = w.queue;
+    L.sig = sig;
+    L.n = polys->n;
+    L.box = box;
+    L.seed = seed;
+    L.k = k;
+    L.cap = cap;
+    L.cfg = c;
+    if (used > ws_bytes) return set_error(POLYMH_ECAPACITY, "sign_binned: workspace too small");
+    return launch_sign_binned(L, horizon, bin_bits, static_cast<char *>(ws) + used, ws_bytes - used, s);
+}
+
 polymh_status polymh_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,
                           uint64_t band_seed, uint64_t *keys, void *stream)
 {

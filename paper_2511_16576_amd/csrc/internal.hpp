@@ -192,6 +192,7 @@ struct SignLaunch {
     const int32_t *order;     // nullable: identity
     unsigned long long *queue;  // nullable: plain grid
     uint32_t *sig;
+    const int32_t *n_dev;     // nullable: the first *n_dev entries of `order` (n bounds it)
     int64_t n;
     polymh_box box;
     uint64_t seed;
@@ -200,6 +201,11 @@ struct SignLaunch {
     polymh_sign_config cfg;
 };
 polymh_status launch_sign(const SignLaunch &L, hipStream_t s);
+
+// binned.hip
+size_t binned_workspace_bytes(int32_t k, uint32_t horizon, int32_t bits, int64_t n);
+polymh_status launch_sign_binned(const SignLaunch &L, uint32_t horizon, int32_t bits, void *ws, size_t ws_bytes,
+                                 hipStream_t s);
 
 // band.hip
 polymh_status launch_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,

@@ -14,6 +14,7 @@
 // bounded by the MBR's width * height; for sides below 2^26 the FP64 product
 // and fused multiply-add are exact.  Wider polygons use 128-bit integers.
 #include "internal.hpp"
+#include "sign_common.hpp"
 
 namespace polymh {
 
@@ -27,6 +28,7 @@ struct SignArgs {
     const int32_t *order;
     unsigned long long *queue;
     uint32_t *sig;
+    const int32_t *n_dev;   // nullable: polygon count read on the device (persistent form only)
     uint64_t seed;
     int64_t n_items;
     int32_t k;
@@ -38,45 +40,6 @@ struct SignArgs {
     uint32_t wx, wy;    // box widths for the multiply-shift map (0 encodes 2^32)
     int32_t shx, shy;   // power-of-two widths: shift 32 - log2(W)
 };
-
-// Lattice offset of a 32-bit half-draw: floor(h * W / 2^32).
-template <bool POW2>
-__device__ __forceinline__ uint32_t lattice(uint32_t h, uint32_t w, int32_t sh)
-{
-    if constexpr (POW2)
-        return h >> sh;
-    else
-        return w ? __umulhi(h, w) : h;
-}
-
-// Edge record staged in LDS, oriented upward: (x_lo, y_lo, y_hi, x_hi - x_lo).
-__device__ __forceinline__ int4 make_edge(int32_t x0, int32_t y0, int32_t x1, int32_t y1)
-{
-    return (y0 <= y1) ? make_int4(x0, y0, y1, x1 - x0) : make_int4(x1, y1, y0, x0 - x1);
-}
-
-// Crossing of the ray from (px, py) to +x with an upward edge, exact in FP64
-// (edge endpoints and the sample lie in an MBR with sides < 2^26).
-__device__ __forceinline__ bool crosses_fp64(int4 e, int32_t px, int32_t py)
-{
-    const bool straddle = (e.y <= py) & (py < e.z);
-    const double t = (double)(px - e.x) * (double)(e.z - e.y);
-    const double o = __fma_rn((double)e.w, (double)(py - e.y), -t);
-    return straddle & (o > 0.0);
-}
-
-__device__ __forceinline__ bool crosses_i128(const int32_t *v0, const int32_t *v1, int32_t px,
-                                             int32_t py)
-{
-    int64_t xl = v0[0], yl = v0[1], xh = v1[0], yh = v1[1];
-    if (yl > yh) {
-        int64_t t = xl; xl = xh; xh = t;
-        t = yl; yl = yh; yh = t;
-    }
-    if (!(yl <= py && py < yh)) return false;
-    const __int128 o = (__int128)(xh - xl) * ((int64_t)py - yl) - (__int128)((int64_t)px - xl) * (yh - yl);
-    return o > 0;
-}
 
 enum EdgeMode { kLds = 0, kStream = 1, kWide = 2 };
 
@@ -173,6 +136,7 @@ __global__ __launch_bounds__(512) void k_sign(SignArgs A)
     // flow is uniform)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = blockDim.x >> 6;
     int64_t it = blockIdx.x;
+    const int64_t n_items = A.n_dev ? (int64_t)A.n_dev[0] * A.items_per_poly : A.n_items;
     for (;;) {
         if (A.queue) {
             __syncthreads();
@@ -180,7 +144,7 @@ __global__ __launch_bounds__(512) void k_sign(SignArgs A)
             __syncthreads();
             it = s_item;
         }
-        if (it >= A.n_items) break;
+        if (it >= n_items) break;
 
         const int64_t slot = it / A.items_per_poly;
         const int32_t blk = (int32_t)(it - slot * A.items_per_poly);
@@ -249,6 +213,7 @@ polymh_status launch_sign(const SignLaunch &L, hipStream_t s)
     A.order = L.order;
     A.queue = L.queue;
     A.sig = L.sig;
+    A.n_dev = L.n_dev;
     A.seed = L.seed;
     A.k = L.k;
     A.cap = L.cap;
@@ -267,6 +232,7 @@ polymh_status launch_sign(const SignLaunch &L, hipStream_t s)
     A.wx = (uint32_t)wx;  // 2^32 wraps to 0, which the multiply-shift form maps as identity
     A.wy = (uint32_t)wy;
     if (A.n_items == 0) return POLYMH_OK;
+    if (A.n_dev && !A.queue) return set_error(POLYMH_EINVAL, "sign: a device-side count needs the persistent form");
     const int bt = L.cfg.block_threads;
     const size_t lds = (size_t)L.cfg.lds_edges * sizeof(int4);
     int64_t grid = A.n_items;

@@ -62,6 +62,8 @@ _SIGNATURES = {
     "polymh_sign_default_config": (None, [P]),
     "polymh_sign_workspace_size": (SZ, [I64, P]),
     "polymh_sign": (I32, [P, Box, U64, I32, U32, P, P, P, SZ, P]),
+    "polymh_sign_binned_workspace_size": (SZ, [I64, I32, U32, U32, I32, P]),
+    "polymh_sign_binned": (I32, [P, Box, U64, I32, U32, U32, I32, P, P, P, SZ, P]),
     "polymh_band": (I32, [P, I64, I32, I32, I32, U64, P, P]),
     "polymh_index_workspace_size": (SZ, [I64, I32]),
     "polymh_index_build": (I32, [P, I64, I32, P, SZ, P, P, P]),
@@ -250,6 +252,60 @@ def sign(polys: DevicePolys, box, seed: int, k: int, cap: int, config: SignConfi
     _check(lib().polymh_sign(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, _ptr(out),
                              ctypes.byref(config) if config else None, _ptr(ws), ws.numel(),
                              _stream(stream)))
+    return out[:n]
+
+
+def binned_params(polys: DevicePolys, box, k: int, cap: int, max_bytes: int = 1 << 31):
+    """(horizon, bin_bits) for sign_binned from the set's shape: the horizon
+    covers about 16 expected first-hit indices N_B / N_P (Thm. 2) of the
+    polygon at the 0.1% smallest area, within ``max_bytes`` of binned
+    samples; the grid side puts about one median MBR side in a cell.  A
+    host-side choice: the signatures do not depend on it."""
+    mbr, area2, _ = prepare(polys)
+    wx = float(box[2]) - float(box[0]) + 1.0
+    wy = float(box[3]) - float(box[1]) + 1.0
+    a = area2.double().cpu().numpy() / 2.0
+    a = a[a > 0]
+    if a.size == 0:
+        return min(cap, 256), 0
+    p_small = max(float(np.quantile(a, 0.001)) / (wx * wy), 1e-12)
+    horizon = int(min(cap, 16.0 / p_small, max_bytes // (10 * k)))
+    horizon = max(256, (horizon + 255) // 256 * 256) if horizon < cap else cap
+    m = mbr.double().cpu().numpy()
+    side = float(np.median(np.maximum(m[:, 2] - m[:, 0], m[:, 3] - m[:, 1]) + 1.0))
+    bits = int(np.clip(np.round(np.log2(max(wx, wy) / max(side, 1.0))), 0, 4))
+    return horizon, bits
+
+
+def sign_binned_workspace_size(n: int, k: int, cap: int, horizon: int, bin_bits: int,
+                               config: SignConfig | None = None) -> int:
+    return int(lib().polymh_sign_binned_workspace_size(n, k, cap, horizon, bin_bits,
+                                                       ctypes.byref(config) if config else None))
+
+
+def sign_binned(polys: DevicePolys, box, seed: int, k: int, cap: int, horizon: int | None = None,
+                bin_bits: int | None = None, config: SignConfig | None = None,
+                out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """Alg. 1 signatures from shared binned samples (equal to ``sign``'s, bit
+    for bit).  ``horizon`` / ``bin_bits`` default to ``binned_params``."""
+    check_device()
+    dev = polys.offsets.device
+    n = polys.n
+    if horizon is None or bin_bits is None:
+        h, b = binned_params(polys, box, k, cap)
+        horizon = h if horizon is None else horizon
+        bin_bits = b if bin_bits is None else bin_bits
+    if out is None:
+        out = torch.empty((max(n, 1), k), dtype=torch.int32, device=dev)
+    # zero for invalid arguments, which the call itself then reports
+    need = max(sign_binned_workspace_size(n, k, cap, horizon, bin_bits, config), 256)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    ps = polys.cstruct()
+    _check(lib().polymh_sign_binned(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, horizon,
+                                    bin_bits, _ptr(out), ctypes.byref(config) if config else None,
+                                    _ptr(ws), ws.numel(), _stream(stream)))
     return out[:n]
 
 

@@ -1,0 +1,140 @@
+"""GPU parity of shared-sample binned signing (Alg. 1 / Def. 2 computed from
+one binned point stream per hash) against the CPU oracle: bit-exact.  Small
+horizons force the per-unit walk for the units the bins leave unresolved, so
+both halves of the path are compared; horizon = cap checks that a unit with
+no hit below the cap is 0 without any walk."""
+import numpy as np
+import pytest
+
+from paper_2511_16576_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_16576_amd import polymh
+    polymh.check_device()
+    return polymh
+
+
+def _binned(pm, polys, box, seed, k, cap, horizon=None, bits=None, **cfg):
+    import torch
+    D = pm.to_device(polys)
+    config = pm.sign_config(**cfg) if cfg else None
+    s = pm.sign_binned(D, box, seed, k, cap, horizon=horizon, bin_bits=bits, config=config)
+    torch.cuda.synchronize()
+    return s.cpu().numpy().view(np.uint32)
+
+
+def _first_diff(a, b):
+    d = np.argwhere(a != b)
+    return None if d.size == 0 else (tuple(d[0]), a[tuple(d[0])], b[tuple(d[0])])
+
+
+def test_binned_workload1_default_params(pm, orc):
+    w = dg.workload(1)
+    print("params", pm.binned_params(pm.to_device(w.data), w.box, w.k, w.cap), flush=True)
+    want = orc.sign(w.data, w.box, w.seed, w.k, w.cap)
+    got = _binned(pm, w.data, w.box, w.seed, w.k, w.cap)
+    assert _first_diff(got, want) is None, _first_diff(got, want)
+
+
+@pytest.mark.parametrize("horizon,bits", [(256, 0), (300, 2), (1000, 4), (5000, 3), (1 << 16, 1)])
+def test_binned_workload1_horizons(pm, orc, horizon, bits):
+    w = dg.workload(1, n=300, n_queries=0)
+    want = orc.sign(w.data, w.box, w.seed, w.k, w.cap)
+    got = _binned(pm, w.data, w.box, w.seed, w.k, w.cap, horizon, bits)
+    assert _first_diff(got, want) is None, (horizon, bits, _first_diff(got, want))
+
+
+def test_binned_workload2_subset(pm, orc):
+    w = dg.workload(2, n=1500, n_queries=0)
+    want = orc.sign(w.data, w.box, w.seed, w.k, w.cap)
+    got = _binned(pm, w.data, w.box, w.seed, w.k, w.cap)
+    assert _first_diff(got, want) is None, _first_diff(got, want)
+
+
+def test_binned_equals_walk_workload2_full_size(pm, orc):
+    # the full 100,000-polygon set: binned and walked signatures equal
+    # everywhere, 200 sampled polygons recomputed by the oracle
+    import torch
+    w = dg.workload(2)
+    D = pm.to_device(w.data)
+    h, b = pm.binned_params(D, w.box, w.k, w.cap)
+    print("params", h, b, flush=True)
+    got = pm.sign_binned(D, w.box, w.seed, w.k, w.cap, horizon=h, bin_bits=b)
+    walk = pm.sign(D, w.box, w.seed, w.k, w.cap)
+    assert torch.equal(got, walk)
+    ids = np.sort(np.random.default_rng(5).choice(w.data.n, 200, replace=False))
+    want = orc.sign(w.data.subset(ids), w.box, w.seed, w.k, w.cap)
+    g = got.cpu().numpy().view(np.uint32)[ids]
+    assert _first_diff(g, want) is None, _first_diff(g, want)
+
+
+@pytest.mark.parametrize("horizon,bits,lds", [(None, None, 1024), (2048, 4, 1024), (512, 2, 64)])
+def test_binned_heavy_tail(pm, orc, horizon, bits, lds):
+    # workload 5's Pareto vertex counts (up to 8192: LDS and streamed edge
+    # tests) and small polygons; a horizon below N_B / N_P of most units
+    w = dg.workload(5, n=300, n_queries=0)
+    k, cap = 16, 1 << 16
+    want = orc.sign(w.data, w.box, w.seed, k, cap)
+    got = _binned(pm, w.data, w.box, w.seed, k, cap, horizon, bits, lds_edges=lds)
+    assert _first_diff(got, want) is None, (horizon, bits, lds, _first_diff(got, want))
+
+
+@pytest.mark.parametrize("k", [1, 9, 64, 70, 300])
+def test_binned_hash_counts(pm, orc, k):
+    # k not a multiple of the 64 lanes or the 256 hashes of a workgroup
+    w = dg.workload(2, n=120, n_queries=0)
+    want = orc.sign(w.data, w.box, w.seed, k, w.cap)
+    got = _binned(pm, w.data, w.box, w.seed, k, w.cap, 777, 3)
+    assert _first_diff(got, want) is None, (k, _first_diff(got, want))
+
+
+def test_binned_edge_cases(pm, orc):
+    rng = np.random.default_rng(1)
+    star = dg.star_polygons(rng, [40], [[500, 500]], [300.0]).xy
+    big = dg.star_polygons(rng, [3000], [[600, 400]], [6000.0]).xy     # > lds_edges
+    wide = dg.star_polygons(rng, [12], [[0, 0]], [float(1 << 26)]).xy  # 128-bit path
+    polys = [
+        np.zeros((0, 2)), [[1, 1]], [[1, 1], [5, 5]],
+        [[0, 0], [40, 20], [80, 40], [20, 10]],          # collinear
+        dg.rectangle(0, 0, 1, 1), dg.rectangle(3, 4, 900, 30),
+        star, star[::-1], np.roll(star, 7, axis=0),
+        dg.rectangle(-500, -500, 20, 20),                  # crosses B's corner
+        dg.rectangle(2000, 2000, 2100, 2100),              # outside B
+        big, wide,
+    ]
+    ps = dg.from_list(polys)
+    for box in [(0, 0, 1023, 1023), (-7, 3, 993, 1099), (5, 5, 5, 5), (0, 0, 1, 2000),
+                (-6000, -6000, 8191, 8191)]:
+        for k, cap in [(1, 1), (9, 17), (33, 1 << 20)]:
+            want = orc.sign(ps, box, 3, k, cap)
+            for horizon, bits in [(cap, 4), (min(cap, 300), 0), (min(cap, 4096), 2)]:
+                got = _binned(pm, ps, box, 3, k, cap, horizon, bits)
+                assert _first_diff(got, want) is None, (box, k, cap, horizon, bits, _first_diff(got, want))
+
+
+def test_binned_extreme_box(pm, orc):
+    ps = dg.from_list([dg.rectangle(-(1 << 30), -(1 << 30), 1 << 30, 1 << 30),
+                       dg.rectangle(0, 0, 1 << 29, 1 << 28)])
+    for box in [(-(1 << 31), -(1 << 31), (1 << 31) - 1, (1 << 31) - 1),
+                (-(1 << 31), -5, (1 << 31) - 1, 3 * (1 << 29))]:
+        want = orc.sign(ps, box, 11, 24, 1 << 12)
+        for bits in (0, 4):
+            got = _binned(pm, ps, box, 11, 24, 1 << 12, 1 << 12, bits)
+            assert _first_diff(got, want) is None, (box, bits, _first_diff(got, want))
+
+
+def test_binned_empty_set_and_invalid(pm):
+    ps = dg.from_list([])
+    assert _binned(pm, ps, (0, 0, 15, 15), 0, 8, 100, 100, 2).shape == (0, 8)
+    D = pm.to_device(dg.from_list([dg.rectangle(0, 0, 2, 2)]))
+    for horizon, bits, k in [(100, 5, 8), (100, -1, 8), (0, 2, 8), (100, 2, 0), (100, 2, 70000)]:
+        with pytest.raises(pm.PolymhError) as e:
+            pm.sign_binned(D, (0, 0, 15, 15), 0, k, 100, horizon=horizon, bin_bits=bits)
+        assert e.value.status == pm.EINVAL
