@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--binned-cfg5", type=int, default=300_000,
+                    help="polygons of the workload-5 sample for the binned-signing comparison (0: skip)")
     ap.add_argument("--batch-queries", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 256 MiB device-to-device once (reference for HBM counters)")
@@ -104,7 +106,7 @@ def main():
     # emission in one call, device overflow flag); its capacity comes from one
     # two-phase sizing lookup in the first warmup step (+25%).  Every timed
     # step's overflow flag is summed and checked after the timed region.
-    lookup = {"ids": None}
+    lookup = {"ids": None, "capped": 0}
     q_ws = torch.empty(int(pm.lib().polymh_query_workspace_size(D.n, Q.n)), dtype=torch.uint8, device=dev)
     q_off = torch.empty(Q.n + 1, dtype=torch.int64, device=dev)
     q_ovf = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -127,6 +129,7 @@ def main():
             lookup["ids"] = torch.empty(int(ids.numel() * 1.25) + 65536, dtype=torch.int32, device=dev)
         else:
             pm.query_capped(sk, si, D.n, qkeys, q_off, lookup["ids"], q_ovf, q_ws)
+            lookup["capped"] += 1
             ovf_sum.add_(q_ovf)
             off, ids = q_off, lookup["ids"]
         if ev: ev[5].record(stream)
@@ -151,7 +154,9 @@ def main():
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
-    if lookup["ids"] is None:           # the lookup's sizing run stays out of the timed region
+    # the lookup's sizing run and the first capped-form step (first launches of
+    # its kernels) stay out of the timed region
+    while lookup["capped"] == 0:
         step()
         torch.cuda.synchronize()
     torch.cuda.synchronize()
@@ -196,11 +201,57 @@ def main():
     centre_bytes = 16.0 * nvert + 16.0 * D.n
     del Cd
 
+    # shared-sample binned signing of the same dataset (bit-equal to the walk),
+    # and of a workload-5 sample, where N_B / N_P is about 20 times larger
+    def time_binned(polys, box, seed, k_, cap_, reps):
+        h, bb = pm.binned_params(polys, box, k_, cap_)
+        need = pm.sign_binned_workspace_size(polys.n, k_, cap_, h, bb)
+        wsb = torch.empty(need, dtype=torch.uint8, device=dev)
+        outb = torch.empty((polys.n, k_), dtype=torch.int32, device=dev)
+        pm.sign_binned(polys, box, seed, k_, cap_, horizon=h, bin_bits=bb, out=outb, ws=wsb)
+        e0.record(stream)
+        for _ in range(reps):
+            pm.sign_binned(polys, box, seed, k_, cap_, horizon=h, bin_bits=bb, out=outb, ws=wsb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return outb, e0.elapsed_time(e1) / reps / 1e3, {"horizon": h, "bin_bits": bb, "walk_ratio": 300.0,
+                                                         "workspace_bytes": need}
+    sig_b, t_b2, par2 = time_binned(D, w.box, w.seed, k, cap, 3)
+    if not torch.equal(sig_b, sig):
+        raise RuntimeError("binned and walked signatures disagree (workload 2)")
+    del sig_b
+    binned = {"workload2": {"walk_ms": None, "binned_ms": 1e3 * t_b2,
+                            "binned_sig_per_s": D.n * k / t_b2, "params": par2}}
+    log(f"binned signing, workload 2: {1e3 * t_b2:.3f} ms")
+    if args.binned_cfg5 > 0:
+        w5 = dg.workload(5, n=args.binned_cfg5, n_queries=0)
+        D5 = pm.to_device(w5.data)
+        sig5 = torch.empty((D5.n, w5.k), dtype=torch.int32, device=dev)
+        ws5 = torch.empty(pm.sign_workspace_size(D5.n, cfg), dtype=torch.uint8, device=dev)
+        pm.sign(D5, w5.box, w5.seed, w5.k, w5.cap, config=cfg, out=sig5, ws=ws5)
+        e0.record(stream)
+        pm.sign(D5, w5.box, w5.seed, w5.k, w5.cap, config=cfg, out=sig5, ws=ws5)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_w5 = e0.elapsed_time(e1) / 1e3
+        del ws5
+        sig_b5, t_b5, par5 = time_binned(D5, w5.box, w5.seed, w5.k, w5.cap, 3)
+        if not torch.equal(sig_b5, sig5):
+            raise RuntimeError("binned and walked signatures disagree (workload 5 sample)")
+        binned["workload5_sample"] = {
+            "polygons": D5.n, "k": w5.k, "cap": w5.cap, "walk_ms": 1e3 * t_w5, "binned_ms": 1e3 * t_b5,
+            "walk_sig_per_s": D5.n * w5.k / t_w5, "binned_sig_per_s": D5.n * w5.k / t_b5,
+            "speedup": t_w5 / t_b5, "params": par5}
+        log(f"binned signing, workload-5 sample: walk {1e3 * t_w5:.1f} ms, binned {1e3 * t_b5:.1f} ms")
+        del sig_b5, sig5, D5
+
     # per-stage breakdown from a separate instrumented pass
     times = {}
     for _ in range(2):
         out = step(times)
     stage_ms = {k_: float(np.median(v)) for k_, v in times.items()}
+    binned["workload2"]["walk_ms"] = stage_ms["sign"]
+    binned["workload2"]["speedup"] = stage_ms["sign"] / binned["workload2"]["binned_ms"]
     off, ids, ti, tj = out
     if int(ovf_sum.item()) != 0:
         raise RuntimeError("candidate capacity overflowed in a timed step")
@@ -364,6 +415,7 @@ def main():
         "autotune": tune,
         "batched": batched,
         "learned": learned,
+        "binned_sign": binned,
     }
     print(json.dumps(line), flush=True)
 

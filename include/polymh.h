@@ -153,26 +153,31 @@ polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t se
 /* polymh_sign_binned -- the same signatures as polymh_sign, bit for bit,
  * computed from shared samples: every polygon reads the same point stream
  * per hash (Sec. 3.2's fixed-seed generators; Def. 2), so for every hash the
- * samples j < horizon are drawn once, in chunks of 256, and each chunk's
- * samples are grouped by cell of a 2^bin_bits x 2^bin_bits grid over B.  A
- * (polygon, hash) takes the smallest j of the first chunk whose samples in
- * the cells under its MBR include one inside the polygon; units with no such
- * sample below the horizon (and polygons needing them) are walked as in
- * polymh_sign.  Work per unit is then about the samples that fall in its
- * cells instead of the N_B / N_P draws of a walk (Thm. 2).
+ * samples j < horizon are drawn once, in chunks of C = 2^clamp(2 bin_bits,
+ * 8, 12), and each chunk's samples are grouped by cell of a 2^bin_bits x
+ * 2^bin_bits grid over B.  A (polygon, hash) takes the smallest j of the
+ * first chunk whose samples in the cells under its MBR include one inside
+ * the polygon; units with no such sample below the horizon (and polygons
+ * needing them) are walked as in polymh_sign.  Work per unit is then about
+ * the samples that fall in its cells instead of the N_B / N_P draws of a
+ * walk (Thm. 2).
  *   horizon  samples drawn per hash (clamped to cap); a horizon of about 16
  *            times the largest N_B / N_P of the set leaves almost no walk.
- *   bin_bits grid side 2^bin_bits, 0..4 (cells near the typical MBR size).
- *   cfg      as polymh_sign (its persistent form serves the walk; lds_edges
- *            bounds the polygons whose edges stay in LDS).
+ *   bin_bits grid side 2^bin_bits, 0..6 (cells near the typical MBR size).
+ *   walk_ratio polygons with |B| < walk_ratio * area (an expected first hit
+ *            near N_B / N_P below walk_ratio) are walked whole instead; 0
+ *            bins every polygon.  A few hundred suits the walk's cost per draw.
+ *   cfg      as polymh_sign for the walk (its persistent form); hash_block
+ *            is also the number of hashes each lookup lane signs (default 8).
  *   ws       polymh_sign_binned_workspace_size(...) bytes: about
  *            10 * k * horizon bytes of binned samples.
- * POLYMH_EINVAL for k > 65535, bin_bits outside 0..4 or horizon < 1.
+ * POLYMH_EINVAL for k > 65535, bin_bits outside 0..6, horizon < 1 or a
+ * negative walk_ratio.
  * Stream-ordered. */
 size_t polymh_sign_binned_workspace_size(int64_t n, int32_t k, uint32_t cap, uint32_t horizon, int32_t bin_bits,
                                          const polymh_sign_config *cfg);
 polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
-                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, uint32_t *sig,
+                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio, uint32_t *sig,
                                  const polymh_sign_config *cfg, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------

@@ -254,7 +254,7 @@ size_t polymh_sign_binned_workspace_size(int64_t n, int32_t k, uint32_t cap, uin
 {
     (void)cfg;
     if (n < 0) n = 0;
-    if (k < 1 || bin_bits < 0 || bin_bits > 4 || horizon < 1) return 0;
+    if (k < 1 || bin_bits < 0 || bin_bits > 6 || horizon < 1) return 0;
     if (horizon > cap) horizon = cap;
     Carve cv{nullptr, 0};
     carve_sign(cv, n, true);
@@ -262,7 +262,7 @@ size_t polymh_sign_binned_workspace_size(int64_t n, int32_t k, uint32_t cap, uin
 }
 
 polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
-                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, uint32_t *sig,
+                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio, uint32_t *sig,
                                  const polymh_sign_config *cfg, void *ws, size_t ws_bytes, void *stream)
 {
     polymh_status st = check_polys(polys, "sign_binned");
@@ -271,7 +271,8 @@ polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint
     if (k < 1 || k > 65535) return set_error(POLYMH_EINVAL, "sign_binned: k must be 1..65535");
     if (cap < 1) return set_error(POLYMH_EINVAL, "sign_binned: cap must be >= 1");
     if (horizon < 1) return set_error(POLYMH_EINVAL, "sign_binned: horizon must be >= 1");
-    if (bin_bits < 0 || bin_bits > 4) return set_error(POLYMH_EINVAL, "sign_binned: bin_bits must be 0..4");
+    if (bin_bits < 0 || bin_bits > 6) return set_error(POLYMH_EINVAL, "sign_binned: bin_bits must be 0..6");
+    if (!(walk_ratio >= 0.0)) return set_error(POLYMH_EINVAL, "sign_binned: walk_ratio must be >= 0");
     if (horizon > cap) horizon = cap;
     polymh_sign_config c;
     if (cfg) c = *cfg;
@@ -303,7 +304,8 @@ polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint
     L.cap = cap;
     L.cfg = c;
     if (used > ws_bytes) return set_error(POLYMH_ECAPACITY, "sign_binned: workspace too small");
-    return launch_sign_binned(L, horizon, bin_bits, static_cast<char *>(ws) + used, ws_bytes - used, s);
+    return launch_sign_binned(L, w.area2, horizon, bin_bits, walk_ratio, static_cast<char *>(ws) + used,
+                              ws_bytes - used, s);
 }
 
 polymh_status polymh_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,

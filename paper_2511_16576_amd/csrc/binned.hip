@@ -1,14 +1,25 @@
 // Shared-sample binned signing: the signatures of Alg. 1 / Def. 2, bit for
 // bit, without walking every (polygon, hash) stream.  All polygons read the
 // same point stream per hash (Sec. 3.2's fixed-seed generators), so the
-// samples j < horizon of every hash are drawn once, in chunks of 256, and
-// each chunk's samples are grouped by cell of a 2^b x 2^b grid over B.  A
-// (polygon, hash) unit then visits the chunks in order and, in each, the
-// samples of the cells its MBR meets: those inside the MBR are tested for
-// membership and the smallest inside index of the first chunk that has one
-// is the first hit (every sample inside the polygon lies in its MBR, hence
-// in those cells).  Units with no hit below the horizon are walked from the
-// start by the per-unit kernel, so every value equals Alg. 1's.
+// samples j < horizon of every hash are drawn once, in chunks of C, and each
+// chunk's samples are grouped by cell of a 2^b x 2^b grid over B.  A
+// (polygon, hash) unit visits the chunks in order and, in each, the samples
+// of the cells its MBR meets: those inside the MBR are tested for membership
+// and the smallest inside index of the first chunk that has one is the first
+// hit (every sample inside the polygon lies in its MBR, hence in those
+// cells).  Units with no hit below the horizon are walked from the start by
+// the per-unit kernel, so every value equals Alg. 1's.
+//
+// Polygons whose expected walk is short (|B| / area below a threshold) are
+// left to the walk altogether: a first-hit index near N_B / N_P is cheaper
+// to draw than to look up.
+//
+// Lookup layout: one workgroup per (polygon, block of hashes), lane = hash,
+// so the polygon's edges are staged once in LDS and every membership test
+// reads them as broadcasts; samples inside the MBR are queued per wavefront
+// and tested 64 at a time, one point per lane.
+#include <cmath>
+
 #include "internal.hpp"
 #include "sign_common.hpp"
 
@@ -16,7 +27,8 @@ namespace polymh {
 
 namespace {
 
-constexpr int kChunk = 256;        // samples per chunk (one workgroup draws a chunk)
+constexpr int kBinThreads = 256;
+constexpr int kMaxSpt = 16;        // samples per thread of k_bin (chunk <= 4096)
 constexpr int kQueue = 128;        // per-wavefront queue of membership tests
 constexpr uint32_t kNone = 0xffffffffu;
 
@@ -25,54 +37,75 @@ struct BinArgs {
     int32_t k;
     uint32_t horizon;              // samples per hash (j < horizon), <= cap
     int32_t nchunks;
-    int32_t bits;                  // grid side 2^bits (0..4)
+    int32_t lchunk;                // chunk C = 2^lchunk samples
+    int32_t bits;                  // grid side 2^bits (0..6)
     int32_t sbx, sby;              // cell of offset o: o >> sb
     uint32_t wx, wy;
     int32_t shx, shy;
-    uint32_t *sx, *sy;             // [k][nchunks][kChunk] lattice offsets, grouped by cell
-    uint8_t *sj;                   // index inside the chunk
+    uint2 *sxy;                    // [k][nchunks][C] lattice offsets, grouped by cell
+    uint16_t *sj;                  // index inside the chunk
     uint16_t *cell_off;            // [k][nchunks][cells + 1]
 };
 
-// One workgroup of 256 threads per (chunk, hash): draw, cell, counting sort
-// in LDS (samples past the horizon go to an extra last cell that no lookup
-// reads).
+// One workgroup per (chunk, hash): draw, cell, counting sort in LDS (samples
+// past the horizon go to an extra last cell that no lookup reads).  Dynamic
+// LDS: counts and starts, (cells + 1) ints each.
 template <bool POW2>
-__global__ __launch_bounds__(kChunk) void k_bin(BinArgs A)
+__global__ __launch_bounds__(kBinThreads) void k_bin(BinArgs A)
 {
-    __shared__ int s_cnt[kChunk + 1];
-    __shared__ int s_start[kChunk + 1];
-    const int tid = threadIdx.x;
+    extern __shared__ int s_dyn[];
+    __shared__ int s_wsum[kBinThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = blockIdx.x, i = blockIdx.y;
     const int cells = 1 << (2 * A.bits);
-    for (int t = tid; t <= cells; t += kChunk) s_cnt[t] = 0;
+    const int C = 1 << A.lchunk, spt = C / kBinThreads;
+    int *s_cnt = s_dyn, *s_start = s_dyn + cells + 1;
+    for (int t = tid; t <= cells; t += kBinThreads) s_cnt[t] = 0;
     __syncthreads();
-    const uint64_t j = (uint64_t)c * kChunk + tid;
-    const bool valid = j < A.horizon;
     const uint64_t key = mix64(A.seed + (uint64_t)(i + 1) * kGamma);
-    const uint64_t r = mix64(key + (j + 1) * kGamma);
-    const uint32_t ox = lattice<POW2>((uint32_t)(r >> 32), A.wx, A.shx);
-    const uint32_t oy = lattice<POW2>((uint32_t)r, A.wy, A.shy);
-    // 64-bit shifts: a 2^32-wide side with one cell shifts by 32
-    const int cx = (int)((uint64_t)ox >> A.sbx), cy = (int)((uint64_t)oy >> A.sby);
-    const int cell = valid ? ((cy << A.bits) | cx) : cells;
-    const int rank = atomicAdd(&s_cnt[cell], 1);
-    __syncthreads();
-    if (tid == 0) {
-        // cells + 1 <= 257 counts: a serial exclusive scan is cheap beside the draws
-        int acc = 0;
-        for (int t = 0; t <= cells; t++) {
-            s_start[t] = acc;
-            acc += s_cnt[t];
+    uint32_t ox[kMaxSpt], oy[kMaxSpt];
+    int cell[kMaxSpt], rank[kMaxSpt];
+#pragma unroll
+    for (int q = 0; q < kMaxSpt; q++) {
+        if (q < spt) {
+            const uint64_t j = ((uint64_t)c << A.lchunk) + (uint64_t)(q * kBinThreads + tid);
+            const uint64_t r = mix64(key + (j + 1) * kGamma);
+            ox[q] = lattice<POW2>((uint32_t)(r >> 32), A.wx, A.shx);
+            oy[q] = lattice<POW2>((uint32_t)r, A.wy, A.shy);
+            // 64-bit shifts: a 2^32-wide side with one cell shifts by 32
+            const int cx = (int)((uint64_t)ox[q] >> A.sbx), cy = (int)((uint64_t)oy[q] >> A.sby);
+            cell[q] = j < A.horizon ? ((cy << A.bits) | cx) : cells;
+            rank[q] = atomicAdd(&s_cnt[cell[q]], 1);
         }
     }
     __syncthreads();
+    // exclusive scan of the cells + 1 counts: strips of consecutive counts per
+    // thread, a wavefront scan of the strip sums, then the wavefront totals
+    const int per = (cells + 1 + kBinThreads - 1) / kBinThreads;
+    const int t0 = tid * per, t1 = min(t0 + per, cells + 1);
+    int sum = 0;
+    for (int t = t0; t < t1; t++) sum += s_cnt[t];
+    const int incl = wave_incl_scan32(sum);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int acc = incl - sum;
+    for (int w = 0; w < wave; w++) acc += s_wsum[w];
+    for (int t = t0; t < t1; t++) {
+        s_start[t] = acc;
+        acc += s_cnt[t];
+    }
+    __syncthreads();
     const size_t chunk = (size_t)i * A.nchunks + c;
-    const size_t pos = chunk * kChunk + s_start[cell] + rank;
-    A.sx[pos] = ox;
-    A.sy[pos] = oy;
-    A.sj[pos] = (uint8_t)tid;
-    for (int t = tid; t <= cells; t += kChunk) A.cell_off[chunk * (cells + 1) + t] = (uint16_t)s_start[t];
+    const size_t base = chunk << A.lchunk;
+#pragma unroll
+    for (int q = 0; q < kMaxSpt; q++) {
+        if (q < spt) {
+            const size_t pos = base + s_start[cell[q]] + rank[q];
+            A.sxy[pos] = make_uint2(ox[q], oy[q]);
+            A.sj[pos] = (uint16_t)(q * kBinThreads + tid);
+        }
+    }
+    for (int t = tid; t <= cells; t += kBinThreads) A.cell_off[chunk * (cells + 1) + t] = (uint16_t)s_start[t];
 }
 
 struct LookupArgs {
@@ -80,23 +113,23 @@ struct LookupArgs {
     const int64_t *off;
     const int32_t *mbr;
     const uint32_t *flags;
-    const uint32_t *sx, *sy;
-    const uint8_t *sj;
+    const uint2 *sxy;
+    const uint16_t *sj;
     const uint16_t *cell_off;
     uint32_t *sig;
-    uint32_t *unresolved;          // [n] set to 1 where a hash needs the walk
+    uint32_t *unresolved;          // [n] 1: a hash needs the walk, 2: the whole polygon is walked
     int64_t n;
     int32_t k;
     uint32_t cap, horizon;
-    int32_t nchunks, bits, sbx, sby;
+    int32_t nchunks, lchunk, bits, sbx, sby;
     int32_t bx0, by0, bx1, by1;
     int32_t lds_edges;
 };
 
 enum TestMode { kTestLds = 0, kTestStream = 1, kTestWide = 2 };
 
-// Lane-serial crossing-number test of the lane's own point (every lane walks
-// the same edge sequence, so the LDS reads are broadcasts).
+// Lane-serial crossing-number test of the lane's own point; every lane walks
+// the same edge sequence, so the edge reads are broadcasts.
 template <int MODE>
 __device__ __forceinline__ bool inside_lane(const int4 *s_edges, const int32_t *pxy, int32_t n,
                                             int32_t px, int32_t py)
@@ -130,7 +163,7 @@ __device__ __forceinline__ void drain(const LookupArgs &A, const int4 *s_edges, 
         const uint32_t meta = qm[q];
         const int32_t px = (int32_t)((uint32_t)A.bx0 + qx[q]), py = (int32_t)((uint32_t)A.by0 + qy[q]);
         if (inside_lane<MODE>(s_edges, pxy, n, px, py))
-            atomicMin(&s_best[meta >> 8], chunk_base + (meta & 0xffu));
+            atomicMin(&s_best[meta >> 12], chunk_base + (meta & 0xfffu));
     }
 }
 
@@ -140,79 +173,100 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_wave_barrier();
 }
 
-// One workgroup (4 wavefronts, 64 hashes each) per (polygon, group of 256
-// hashes).  Lane = hash.  Per chunk, the lanes stream the samples of the
-// cells under the MBR; samples inside the MBR are queued and tested 64 at a
-// time by all lanes; a lane stops after the first chunk with a hit.
+// Per-wavefront state of one polygon's lookup.
+struct Scan {
+    uint32_t mx0, my0, mx1, my1;   // MBR as lattice offsets inside B
+    uint32_t *qm, *qx, *qy, *s_best;
+    int head, tail;
+};
+
+// Stream the lane's samples [lo, hi) of one grid row (cells contiguous in the
+// chunk's order), queue those inside the MBR, drain whenever 64 are waiting.
+template <int MODE>
+__device__ __forceinline__ void scan_row(const LookupArgs &A, const int4 *s_edges, const int32_t *pxy, int32_t n,
+                                         Scan &S, size_t base, int lo, int hi, uint32_t chunk_base, int lane)
+{
+    const int cnt = hi - lo;
+    const int steps = wave_max32(cnt);
+    for (int s = 0; s < steps; s++) {
+        bool pass = false;
+        uint2 o = make_uint2(0u, 0u);
+        if (s < cnt) {
+            o = A.sxy[base + lo + s];
+            pass = (o.x >= S.mx0) & (o.x <= S.mx1) & (o.y >= S.my0) & (o.y <= S.my1);
+        }
+        const uint64_t mk = __ballot(pass);
+        if (pass) {
+            const uint32_t jl = A.sj[base + lo + s];
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            const int q = (S.tail + rank) & (kQueue - 1);
+            S.qm[q] = ((uint32_t)lane << 12) | jl;
+            S.qx[q] = o.x;
+            S.qy[q] = o.y;
+        }
+        S.tail += __popcll(mk);
+        if (S.tail - S.head >= 64) {
+            wave_sync_lds();
+            drain<MODE>(A, s_edges, pxy, n, S.qm, S.qx, S.qy, S.head, 64, chunk_base, S.s_best, lane);
+            S.head += 64;
+            wave_sync_lds();
+        }
+    }
+}
+
+// Lane = hash i.  Chunks in order; a lane stops after the first chunk with a
+// hit, the wavefront when all its lanes have.
 template <int MODE>
 __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const int32_t *pxy, int32_t n,
-                               int4 mb, int i, bool active, int lane, uint32_t *qm, uint32_t *qx,
-                               uint32_t *qy, uint32_t *s_best, uint32_t &best)
+                               Scan &S, int cx0, int cx1, int cy0, int cy1, int i, bool active, int lane,
+                               uint32_t &best)
 {
-    // MBR as lattice offsets inside B (the polygon meets B here)
-    const uint32_t mx0 = (uint32_t)max(mb.x, A.bx0) - (uint32_t)A.bx0;
-    const uint32_t my0 = (uint32_t)max(mb.y, A.by0) - (uint32_t)A.by0;
-    const uint32_t mx1 = (uint32_t)min(mb.z, A.bx1) - (uint32_t)A.bx0;
-    const uint32_t my1 = (uint32_t)min(mb.w, A.by1) - (uint32_t)A.by0;
-    const int cx0 = (int)((uint64_t)mx0 >> A.sbx), cx1 = (int)((uint64_t)mx1 >> A.sbx);
-    const int cy0 = (int)((uint64_t)my0 >> A.sby), cy1 = (int)((uint64_t)my1 >> A.sby);
     const int cells = 1 << (2 * A.bits);
+    const int rows = cy1 - cy0 + 1;
     best = active ? kNone : 0u;
     for (int c = 0; c < A.nchunks; c++) {
         const bool open = active && best == kNone;
         if (__ballot(open) == 0) break;
-        s_best[lane] = kNone;
-        int head = 0, tail = 0;
+        S.s_best[lane] = kNone;
+        S.head = S.tail = 0;
         const size_t chunk = (size_t)i * A.nchunks + c;
         const uint16_t *co = A.cell_off + chunk * (cells + 1);
-        const size_t sbase = chunk * kChunk;
-        for (int cy = cy0; cy <= cy1; cy++) {
-            for (int cx = cx0; cx <= cx1; cx++) {
-                const int cell = (cy << A.bits) | cx;
-                const int lo = open ? (int)co[cell] : 0;
-                const int cnt = open ? (int)co[cell + 1] - lo : 0;
-                const int steps = wave_max32(cnt);
-                for (int s = 0; s < steps; s++) {
-                    bool pass = false;
-                    uint32_t ox = 0, oy = 0, jl = 0;
-                    if (s < cnt) {
-                        const size_t at = sbase + lo + s;
-                        ox = A.sx[at];
-                        oy = A.sy[at];
-                        jl = A.sj[at];
-                        pass = (ox >= mx0) & (ox <= mx1) & (oy >= my0) & (oy <= my1);
-                    }
-                    const uint64_t mk = __ballot(pass);
-                    if (pass) {
-                        const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
-                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                        const int q = (tail + rank) & (kQueue - 1);
-                        qm[q] = ((uint32_t)lane << 8) | jl;
-                        qx[q] = ox;
-                        qy[q] = oy;
-                    }
-                    tail += __popcll(mk);
-                    if (tail - head >= 64) {
-                        wave_sync_lds();
-                        drain<MODE>(A, s_edges, pxy, n, qm, qx, qy, head, 64, (uint32_t)c * kChunk, s_best, lane);
-                        head += 64;
-                        wave_sync_lds();
-                    }
-                }
+        const size_t base = chunk << A.lchunk;
+        const uint32_t chunk_base = (uint32_t)c << A.lchunk;
+        // the first four rows' ranges are loaded together
+        int lo[4], hi[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            lo[r] = hi[r] = 0;
+            if (open && r < rows) {
+                const int row = (cy0 + r) << A.bits;
+                lo[r] = co[row | cx0];
+                hi[r] = co[(row | cx1) + 1];
             }
         }
-        while (tail > head) {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (r < rows) scan_row<MODE>(A, s_edges, pxy, n, S, base, lo[r], hi[r], chunk_base, lane);
+        for (int r = 4; r < rows; r++) {
+            const int row = (cy0 + r) << A.bits;
+            const int l = open ? (int)co[row | cx0] : 0, h = open ? (int)co[(row | cx1) + 1] : 0;
+            scan_row<MODE>(A, s_edges, pxy, n, S, base, l, h, chunk_base, lane);
+        }
+        while (S.tail > S.head) {
             wave_sync_lds();
-            const int cnt = min(64, tail - head);
-            drain<MODE>(A, s_edges, pxy, n, qm, qx, qy, head, cnt, (uint32_t)c * kChunk, s_best, lane);
-            head += cnt;
+            const int cnt = min(64, S.tail - S.head);
+            drain<MODE>(A, s_edges, pxy, n, S.qm, S.qx, S.qy, S.head, cnt, chunk_base, S.s_best, lane);
+            S.head += cnt;
             wave_sync_lds();
         }
         wave_sync_lds();
-        if (open) best = s_best[lane];
+        if (open) best = S.s_best[lane];
     }
 }
 
+// One workgroup of 64 * W threads (W = min(4, ceil(k / 64)) wavefronts) per
+// (polygon, group of 64 W hashes).
 __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
 {
     extern __shared__ int4 s_edges[];
@@ -220,10 +274,12 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     __shared__ uint32_t s_best[4][64];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int groups = (A.k + 255) / 256;
+    const int per = blockDim.x;
+    const int groups = (A.k + per - 1) / per;
     const int64_t p = blockIdx.x / groups;
-    const int i = (int)(blockIdx.x % groups) * 256 + wave * 64 + lane;
+    const int i = (int)(blockIdx.x % groups) * per + tid;
     const bool active = i < A.k;
+    if (A.unresolved[p] & 2u) return;    // walked (uniform per workgroup, before any barrier)
     const int64_t a = A.off[p];
     const int32_t n = (int32_t)(A.off[p + 1] - a);
     const uint32_t fl = A.flags[p];
@@ -238,7 +294,7 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     const int32_t *pxy = A.xy + 2 * a;
     const int mode = (fl & kFlagWide) ? kTestWide : (n <= A.lds_edges ? kTestLds : kTestStream);
     if (mode == kTestLds) {
-        for (int e = tid; e < n; e += blockDim.x) {
+        for (int e = tid; e < n; e += per) {
             const int f = (e + 1 == n) ? 0 : e + 1;
             const int2 u = *reinterpret_cast<const int2 *>(pxy + 2 * e);
             const int2 v = *reinterpret_cast<const int2 *>(pxy + 2 * f);
@@ -246,17 +302,28 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
         }
     }
     __syncthreads();
+    Scan S;
+    S.mx0 = (uint32_t)max(mb.x, A.bx0) - (uint32_t)A.bx0;
+    S.my0 = (uint32_t)max(mb.y, A.by0) - (uint32_t)A.by0;
+    S.mx1 = (uint32_t)min(mb.z, A.bx1) - (uint32_t)A.bx0;
+    S.my1 = (uint32_t)min(mb.w, A.by1) - (uint32_t)A.by0;
+    S.qm = s_qm[wave];
+    S.qx = s_qx[wave];
+    S.qy = s_qy[wave];
+    S.s_best = s_best[wave];
+    // 64-bit shifts: a 2^32-wide side with one cell shifts by 32
+    const int cx0 = (int)((uint64_t)S.mx0 >> A.sbx), cx1 = (int)((uint64_t)S.mx1 >> A.sbx);
+    const int cy0 = (int)((uint64_t)S.my0 >> A.sby), cy1 = (int)((uint64_t)S.my1 >> A.sby);
     // a wavefront with no hash of its own skips the lookup (uniform per wave)
     uint32_t best = 0u;
-    const bool wave_active = __ballot(active) != 0;
     const int ic = active ? i : 0;
-    if (wave_active) {
+    if (__ballot(active) != 0) {
         if (mode == kTestLds)
-            lookup_polygon<kTestLds>(A, s_edges, pxy, n, mb, ic, active, lane, s_qm[wave], s_qx[wave], s_qy[wave], s_best[wave], best);
+            lookup_polygon<kTestLds>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best);
         else if (mode == kTestStream)
-            lookup_polygon<kTestStream>(A, s_edges, pxy, n, mb, ic, active, lane, s_qm[wave], s_qx[wave], s_qy[wave], s_best[wave], best);
+            lookup_polygon<kTestStream>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best);
         else
-            lookup_polygon<kTestWide>(A, s_edges, pxy, n, mb, ic, active, lane, s_qm[wave], s_qx[wave], s_qy[wave], s_best[wave], best);
+            lookup_polygon<kTestWide>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best);
     }
     if (active) {
         if (best != kNone) out[i] = best + 1;
@@ -265,7 +332,22 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     }
 }
 
-// Polygons with an unresolved hash, listed for the walk.
+// Flags: 2 for a polygon to walk whole (|B| < walk_ratio * area, with twice
+// the area exact from prepare), else 0.  Degenerate polygons stay with the
+// lookup, which signs them 0 at once.
+__global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ area2,
+                                                  const uint32_t *__restrict__ flags, int64_t n,
+                                                  double box_area, double walk_ratio,
+                                                  uint32_t *__restrict__ unresolved)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const bool degenerate = (flags[p] & (kFlagFew | kFlagCollinear)) != 0;
+        const double area = 0.5 * (double)(area2[p] < 0 ? -area2[p] : area2[p]);
+        unresolved[p] = (!degenerate && box_area < walk_ratio * area) ? 2u : 0u;
+    }
+}
+
+// Polygons with an unresolved hash, or walked whole, listed for the walk.
 __global__ __launch_bounds__(256) void k_unresolved_list(const uint32_t *__restrict__ unresolved, int64_t n,
                                                          int32_t *__restrict__ list, int32_t *__restrict__ count)
 {
@@ -292,50 +374,64 @@ int grid_for(int64_t items)
     return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
 }
 
+// Chunk of about one sample per cell, 256..4096 samples.
+int chunk_log2(int32_t bits)
+{
+    const int l = 2 * bits;
+    return l < 8 ? 8 : (l > 12 ? 12 : l);
+}
+
+struct BinnedWs {
+    uint2 *sxy;
+    uint16_t *sj, *cell_off;
+    uint32_t *unresolved;
+    int32_t *list, *count;
+};
+
+BinnedWs carve_binned(Carve &c, int32_t k, int64_t nchunks, int32_t bits, int64_t n)
+{
+    const int64_t samples = ((int64_t)k * nchunks) << chunk_log2(bits);
+    const int64_t cells = ((int64_t)1 << (2 * bits)) + 1;
+    BinnedWs w{};
+    w.sxy = c.take<uint2>((size_t)samples);
+    w.sj = c.take<uint16_t>((size_t)samples);
+    w.cell_off = c.take<uint16_t>((size_t)((int64_t)k * nchunks * cells));
+    w.unresolved = c.take<uint32_t>((size_t)n);
+    w.list = c.take<int32_t>((size_t)n);
+    w.count = c.take<int32_t>(1);
+    return w;
+}
+
 }  // namespace
 
 size_t binned_workspace_bytes(int32_t k, uint32_t horizon, int32_t bits, int64_t n)
 {
-    const int64_t nchunks = ((int64_t)horizon + kChunk - 1) / kChunk;
-    const int64_t samples = (int64_t)k * nchunks * kChunk;
-    const int64_t cells = ((int64_t)1 << (2 * bits)) + 1;
+    const int64_t C = (int64_t)1 << chunk_log2(bits);
     Carve c{nullptr, 0};
-    c.take<uint32_t>((size_t)samples);
-    c.take<uint32_t>((size_t)samples);
-    c.take<uint8_t>((size_t)samples);
-    c.take<uint16_t>((size_t)((int64_t)k * nchunks * cells));
-    c.take<uint32_t>((size_t)n);        // unresolved flags
-    c.take<int32_t>((size_t)n);         // their list
-    c.take<int32_t>(1);                 // its length
+    carve_binned(c, k, ((int64_t)horizon + C - 1) / C, bits, n);
     return align_up(c.used, 256);
 }
 
-polymh_status launch_sign_binned(const SignLaunch &L, uint32_t horizon, int32_t bits, void *ws, size_t ws_bytes,
-                                 hipStream_t s)
+polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint32_t horizon, int32_t bits,
+                                 double walk_ratio, void *ws, size_t ws_bytes, hipStream_t s)
 {
     const uint64_t wx = (uint64_t)((int64_t)L.box.xmax - L.box.xmin + 1);
     const uint64_t wy = (uint64_t)((int64_t)L.box.ymax - L.box.ymin + 1);
     const int lx = ceil_log2(wx), ly = ceil_log2(wy);
     const bool pow2 = (1ull << lx) == wx && (1ull << ly) == wy && lx >= 1 && ly >= 1;
-    const int64_t nchunks = ((int64_t)horizon + kChunk - 1) / kChunk;
+    const int lchunk = chunk_log2(bits);
+    const int64_t nchunks = ((int64_t)horizon + ((int64_t)1 << lchunk) - 1) >> lchunk;
     if (nchunks > 65535) return set_error(POLYMH_EINVAL, "sign_binned: horizon too large");
     Carve cv{static_cast<char *>(ws), ws_bytes};
-    const int64_t samples = (int64_t)L.k * nchunks * kChunk;
-    const int64_t cells = ((int64_t)1 << (2 * bits)) + 1;
-    BinArgs B{};
-    B.sx = cv.take<uint32_t>((size_t)samples);
-    B.sy = cv.take<uint32_t>((size_t)samples);
-    B.sj = cv.take<uint8_t>((size_t)samples);
-    B.cell_off = cv.take<uint16_t>((size_t)((int64_t)L.k * nchunks * cells));
-    uint32_t *unres = cv.take<uint32_t>((size_t)L.n);
-    int32_t *list = cv.take<int32_t>((size_t)L.n);
-    int32_t *count = cv.take<int32_t>(1);
+    BinnedWs w = carve_binned(cv, L.k, nchunks, bits, L.n);
     if (!cv.ok)
         return set_error(POLYMH_ECAPACITY, "sign_binned: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
+    BinArgs B{};
     B.seed = L.seed;
     B.k = L.k;
     B.horizon = horizon;
     B.nchunks = (int32_t)nchunks;
+    B.lchunk = lchunk;
     B.bits = bits;
     B.sbx = lx > bits ? lx - bits : 0;
     B.sby = ly > bits ? ly - bits : 0;
@@ -343,46 +439,53 @@ polymh_status launch_sign_binned(const SignLaunch &L, uint32_t horizon, int32_t 
     B.wy = (uint32_t)wy;
     B.shx = pow2 ? 32 - lx : 0;
     B.shy = pow2 ? 32 - ly : 0;
-    if (pow2) hipLaunchKernelGGL(k_bin<true>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kChunk), 0, s, B);
-    else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kChunk), 0, s, B);
+    B.sxy = w.sxy;
+    B.sj = w.sj;
+    B.cell_off = w.cell_off;
+    const size_t bin_lds = 2 * (((size_t)1 << (2 * bits)) + 1) * sizeof(int);
+    if (pow2) hipLaunchKernelGGL(k_bin<true>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
+    else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
     polymh_status st = check_launch("sign_binned: bin");
     if (st) return st;
-    hipLaunchKernelGGL(k_zero_words, dim3(grid_for(L.n + 1)), dim3(256), 0, s, unres, L.n);
-    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(count), (int64_t)1);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.flags, L.n,
+                       (double)wx * (double)wy, walk_ratio, w.unresolved);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(w.count), (int64_t)1);
     LookupArgs A{};
     A.xy = L.xy;
     A.off = L.off;
     A.mbr = L.mbr;
     A.flags = L.flags;
-    A.sx = B.sx;
-    A.sy = B.sy;
-    A.sj = B.sj;
-    A.cell_off = B.cell_off;
+    A.sxy = w.sxy;
+    A.sj = w.sj;
+    A.cell_off = w.cell_off;
     A.sig = L.sig;
-    A.unresolved = unres;
+    A.unresolved = w.unresolved;
     A.n = L.n;
     A.k = L.k;
     A.cap = L.cap;
     A.horizon = horizon;
     A.nchunks = (int32_t)nchunks;
+    A.lchunk = lchunk;
     A.bits = bits;
     A.sbx = B.sbx;
     A.sby = B.sby;
     A.bx0 = L.box.xmin; A.by0 = L.box.ymin; A.bx1 = L.box.xmax; A.by1 = L.box.ymax;
     A.lds_edges = L.cfg.lds_edges;
-    const int64_t groups = (L.k + 255) / 256;
+    const int64_t waves = (L.k + 63) / 64 < 4 ? (L.k + 63) / 64 : 4;
+    const int64_t per = 64 * waves, groups = (L.k + per - 1) / per;
     const int64_t grid = L.n * groups;
     if (grid > 0x7fffffff) return set_error(POLYMH_EINVAL, "sign_binned: too many work items");
     const size_t lds = (size_t)L.cfg.lds_edges * sizeof(int4);
-    hipLaunchKernelGGL(k_bin_lookup, dim3((unsigned)grid), dim3(256), lds, s, A);
+    hipLaunchKernelGGL(k_bin_lookup, dim3((unsigned)grid), dim3((unsigned)per), lds, s, A);
     if ((st = check_launch("sign_binned: lookup"))) return st;
-    if (horizon >= L.cap) return POLYMH_OK;
-    // the walk for polygons with a hash unresolved below the horizon
-    hipLaunchKernelGGL(k_unresolved_list, dim3(grid_for(L.n)), dim3(256), 0, s, unres, L.n, list, count);
+    if (horizon >= L.cap && walk_ratio <= 0.0) return POLYMH_OK;
+    // the walk for polygons with a hash unresolved below the horizon, and
+    // those left to it whole
+    hipLaunchKernelGGL(k_unresolved_list, dim3(grid_for(L.n)), dim3(256), 0, s, w.unresolved, L.n, w.list, w.count);
     if ((st = check_launch("sign_binned: list"))) return st;
     SignLaunch W = L;
-    W.order = list;
-    W.n_dev = count;
+    W.order = w.list;
+    W.n_dev = w.count;
     W.cfg.persistent = 1;
     return launch_sign(W, s);
 }

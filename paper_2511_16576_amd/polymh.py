@@ -63,7 +63,7 @@ _SIGNATURES = {
     "polymh_sign_workspace_size": (SZ, [I64, P]),
     "polymh_sign": (I32, [P, Box, U64, I32, U32, P, P, P, SZ, P]),
     "polymh_sign_binned_workspace_size": (SZ, [I64, I32, U32, U32, I32, P]),
-    "polymh_sign_binned": (I32, [P, Box, U64, I32, U32, U32, I32, P, P, P, SZ, P]),
+    "polymh_sign_binned": (I32, [P, Box, U64, I32, U32, U32, I32, ctypes.c_double, P, P, P, SZ, P]),
     "polymh_band": (I32, [P, I64, I32, I32, I32, U64, P, P]),
     "polymh_index_workspace_size": (SZ, [I64, I32]),
     "polymh_index_build": (I32, [P, I64, I32, P, SZ, P, P, P]),
@@ -255,25 +255,30 @@ def sign(polys: DevicePolys, box, seed: int, k: int, cap: int, config: SignConfi
     return out[:n]
 
 
-def binned_params(polys: DevicePolys, box, k: int, cap: int, max_bytes: int = 1 << 31):
+def binned_params(polys: DevicePolys, box, k: int, cap: int, walk_ratio: float = 300.0,
+                  max_bytes: int = 1 << 31):
     """(horizon, bin_bits) for sign_binned from the set's shape: the horizon
     covers about 16 expected first-hit indices N_B / N_P (Thm. 2) of the
     polygon at the 0.1% smallest area, within ``max_bytes`` of binned
-    samples; the grid side puts about one median MBR side in a cell.  A
+    samples; the grid side puts about two cells across the median MBR side
+    of the polygons the lookup signs (|B| / area >= ``walk_ratio``).  A
     host-side choice: the signatures do not depend on it."""
     mbr, area2, _ = prepare(polys)
     wx = float(box[2]) - float(box[0]) + 1.0
     wy = float(box[3]) - float(box[1]) + 1.0
-    a = area2.double().cpu().numpy() / 2.0
-    a = a[a > 0]
+    a_all = np.abs(area2.double().cpu().numpy()) / 2.0
+    a = a_all[a_all > 0]
     if a.size == 0:
         return min(cap, 256), 0
     p_small = max(float(np.quantile(a, 0.001)) / (wx * wy), 1e-12)
     horizon = int(min(cap, 16.0 / p_small, max_bytes // (10 * k)))
     horizon = max(256, (horizon + 255) // 256 * 256) if horizon < cap else cap
     m = mbr.double().cpu().numpy()
+    binned = (a_all > 0) & (wx * wy >= walk_ratio * a_all)
+    if binned.any():
+        m = m[binned]
     side = float(np.median(np.maximum(m[:, 2] - m[:, 0], m[:, 3] - m[:, 1]) + 1.0))
-    bits = int(np.clip(np.round(np.log2(max(wx, wy) / max(side, 1.0))), 0, 4))
+    bits = int(np.clip(np.round(np.log2(max(wx, wy) / max(side, 1.0))) + 1, 0, 6))
     return horizon, bits
 
 
@@ -284,16 +289,17 @@ def sign_binned_workspace_size(n: int, k: int, cap: int, horizon: int, bin_bits:
 
 
 def sign_binned(polys: DevicePolys, box, seed: int, k: int, cap: int, horizon: int | None = None,
-                bin_bits: int | None = None, config: SignConfig | None = None,
+                bin_bits: int | None = None, walk_ratio: float = 300.0, config: SignConfig | None = None,
                 out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
                 stream=None) -> torch.Tensor:
     """Alg. 1 signatures from shared binned samples (equal to ``sign``'s, bit
-    for bit).  ``horizon`` / ``bin_bits`` default to ``binned_params``."""
+    for bit).  ``horizon`` / ``bin_bits`` default to ``binned_params``;
+    polygons with |B| / area below ``walk_ratio`` are walked instead."""
     check_device()
     dev = polys.offsets.device
     n = polys.n
     if horizon is None or bin_bits is None:
-        h, b = binned_params(polys, box, k, cap)
+        h, b = binned_params(polys, box, k, cap, walk_ratio)
         horizon = h if horizon is None else horizon
         bin_bits = b if bin_bits is None else bin_bits
     if out is None:
@@ -304,7 +310,7 @@ def sign_binned(polys: DevicePolys, box, seed: int, k: int, cap: int, horizon: i
         ws = _workspace(need, dev)
     ps = polys.cstruct()
     _check(lib().polymh_sign_binned(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, horizon,
-                                    bin_bits, _ptr(out), ctypes.byref(config) if config else None,
+                                    bin_bits, float(walk_ratio), _ptr(out), ctypes.byref(config) if config else None,
                                     _ptr(ws), ws.numel(), _stream(stream)))
     return out[:n]
 

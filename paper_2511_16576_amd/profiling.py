@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the records kept under ``profiles/``.
 
-Two commands (run from the repository root):
+Three commands (run from the repository root):
 
 ``python -m paper_2511_16576_amd.profiling stats --csv <kernel_stats.csv> --out <file.md> --title T --command C``
     Markdown table of a ``--kernel-trace --stats`` run (per-kernel calls,
@@ -36,7 +36,8 @@ COPY_BYTES = 256 << 20
 # kernel -> the sources it is built from
 KERNEL_SOURCES = {
     "k_refine": ["refine.hip", "internal.hpp"],
-    "k_sign": ["sign.hip", "internal.hpp"],
+    "k_sign": ["sign.hip", "sign_common.hpp", "internal.hpp"],
+    "k_bin_lookup": ["binned.hip", "sign_common.hpp", "internal.hpp"],
 }
 
 

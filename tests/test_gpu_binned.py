@@ -21,11 +21,13 @@ def pm():
     return polymh
 
 
-def _binned(pm, polys, box, seed, k, cap, horizon=None, bits=None, **cfg):
+def _binned(pm, polys, box, seed, k, cap, horizon=None, bits=None, walk_ratio=0.0, **cfg):
+    # walk_ratio 0 signs every polygon from the bins (the walk only past the horizon)
     import torch
     D = pm.to_device(polys)
     config = pm.sign_config(**cfg) if cfg else None
-    s = pm.sign_binned(D, box, seed, k, cap, horizon=horizon, bin_bits=bits, config=config)
+    s = pm.sign_binned(D, box, seed, k, cap, horizon=horizon, bin_bits=bits, walk_ratio=walk_ratio,
+                       config=config)
     torch.cuda.synchronize()
     return s.cpu().numpy().view(np.uint32)
 
@@ -43,7 +45,8 @@ def test_binned_workload1_default_params(pm, orc):
     assert _first_diff(got, want) is None, _first_diff(got, want)
 
 
-@pytest.mark.parametrize("horizon,bits", [(256, 0), (300, 2), (1000, 4), (5000, 3), (1 << 16, 1)])
+@pytest.mark.parametrize("horizon,bits", [(256, 0), (300, 2), (1000, 4), (5000, 3), (1 << 16, 1),
+                                          (3000, 5), (20000, 6)])
 def test_binned_workload1_horizons(pm, orc, horizon, bits):
     w = dg.workload(1, n=300, n_queries=0)
     want = orc.sign(w.data, w.box, w.seed, w.k, w.cap)
@@ -51,11 +54,13 @@ def test_binned_workload1_horizons(pm, orc, horizon, bits):
     assert _first_diff(got, want) is None, (horizon, bits, _first_diff(got, want))
 
 
-def test_binned_workload2_subset(pm, orc):
+@pytest.mark.parametrize("walk_ratio", [0.0, 150.0, 600.0, 1e9])
+def test_binned_workload2_subset(pm, orc, walk_ratio):
+    # walk_ratio splits the set between the lookup and the whole-polygon walk
     w = dg.workload(2, n=1500, n_queries=0)
     want = orc.sign(w.data, w.box, w.seed, w.k, w.cap)
-    got = _binned(pm, w.data, w.box, w.seed, w.k, w.cap)
-    assert _first_diff(got, want) is None, _first_diff(got, want)
+    got = _binned(pm, w.data, w.box, w.seed, w.k, w.cap, walk_ratio=walk_ratio)
+    assert _first_diff(got, want) is None, (walk_ratio, _first_diff(got, want))
 
 
 def test_binned_equals_walk_workload2_full_size(pm, orc):
@@ -66,33 +71,36 @@ def test_binned_equals_walk_workload2_full_size(pm, orc):
     D = pm.to_device(w.data)
     h, b = pm.binned_params(D, w.box, w.k, w.cap)
     print("params", h, b, flush=True)
-    got = pm.sign_binned(D, w.box, w.seed, w.k, w.cap, horizon=h, bin_bits=b)
     walk = pm.sign(D, w.box, w.seed, w.k, w.cap)
-    assert torch.equal(got, walk)
+    for ratio in (1000.0, 0.0):
+        got = pm.sign_binned(D, w.box, w.seed, w.k, w.cap, horizon=h, bin_bits=b, walk_ratio=ratio)
+        assert torch.equal(got, walk), ratio
     ids = np.sort(np.random.default_rng(5).choice(w.data.n, 200, replace=False))
     want = orc.sign(w.data.subset(ids), w.box, w.seed, w.k, w.cap)
     g = got.cpu().numpy().view(np.uint32)[ids]
     assert _first_diff(g, want) is None, _first_diff(g, want)
 
 
-@pytest.mark.parametrize("horizon,bits,lds", [(None, None, 1024), (2048, 4, 1024), (512, 2, 64)])
-def test_binned_heavy_tail(pm, orc, horizon, bits, lds):
-    # workload 5's Pareto vertex counts (up to 8192: LDS and streamed edge
-    # tests) and small polygons; a horizon below N_B / N_P of most units
+@pytest.mark.parametrize("horizon,bits,lds,ratio", [(None, None, 1024, 0.0), (2048, 4, 1024, 0.0), (512, 2, 64, 0.0),
+                                                   (8192, 6, 256, 0.0), (None, None, 1024, 2000.0)])
+def test_binned_heavy_tail(pm, orc, horizon, bits, lds, ratio):
+    # workload 5's Pareto vertex counts (up to 8192) and small polygons; a
+    # horizon below N_B / N_P of most units, so the walk (with LDS-staged or
+    # streamed edges) signs many of them
     w = dg.workload(5, n=300, n_queries=0)
     k, cap = 16, 1 << 16
     want = orc.sign(w.data, w.box, w.seed, k, cap)
-    got = _binned(pm, w.data, w.box, w.seed, k, cap, horizon, bits, lds_edges=lds)
-    assert _first_diff(got, want) is None, (horizon, bits, lds, _first_diff(got, want))
+    got = _binned(pm, w.data, w.box, w.seed, k, cap, horizon, bits, ratio, lds_edges=lds)
+    assert _first_diff(got, want) is None, (horizon, bits, lds, ratio, _first_diff(got, want))
 
 
-@pytest.mark.parametrize("k", [1, 9, 64, 70, 300])
-def test_binned_hash_counts(pm, orc, k):
-    # k not a multiple of the 64 lanes or the 256 hashes of a workgroup
-    w = dg.workload(2, n=120, n_queries=0)
+@pytest.mark.parametrize("k,hash_block", [(1, 0), (9, 0), (64, 0), (70, 0), (300, 0), (70, 1), (70, 3), (70, 70)])
+def test_binned_hash_counts(pm, orc, k, hash_block):
+    # k not a multiple of the hash block; 300 polygons fill two workgroups
+    w = dg.workload(2, n=300, n_queries=0)
     want = orc.sign(w.data, w.box, w.seed, k, w.cap)
-    got = _binned(pm, w.data, w.box, w.seed, k, w.cap, 777, 3)
-    assert _first_diff(got, want) is None, (k, _first_diff(got, want))
+    got = _binned(pm, w.data, w.box, w.seed, k, w.cap, 777, 3, hash_block=hash_block)
+    assert _first_diff(got, want) is None, (k, hash_block, _first_diff(got, want))
 
 
 def test_binned_edge_cases(pm, orc):
@@ -114,9 +122,10 @@ def test_binned_edge_cases(pm, orc):
                 (-6000, -6000, 8191, 8191)]:
         for k, cap in [(1, 1), (9, 17), (33, 1 << 20)]:
             want = orc.sign(ps, box, 3, k, cap)
-            for horizon, bits in [(cap, 4), (min(cap, 300), 0), (min(cap, 4096), 2)]:
-                got = _binned(pm, ps, box, 3, k, cap, horizon, bits)
-                assert _first_diff(got, want) is None, (box, k, cap, horizon, bits, _first_diff(got, want))
+            for horizon, bits, ratio in [(cap, 4, 0.0), (min(cap, 300), 0, 0.0), (min(cap, 4096), 2, 0.0),
+                                         (min(cap, 5000), 6, 0.0), (cap, 3, 50.0)]:
+                got = _binned(pm, ps, box, 3, k, cap, horizon, bits, ratio)
+                assert _first_diff(got, want) is None, (box, k, cap, horizon, bits, ratio, _first_diff(got, want))
 
 
 def test_binned_extreme_box(pm, orc):
@@ -125,7 +134,7 @@ def test_binned_extreme_box(pm, orc):
     for box in [(-(1 << 31), -(1 << 31), (1 << 31) - 1, (1 << 31) - 1),
                 (-(1 << 31), -5, (1 << 31) - 1, 3 * (1 << 29))]:
         want = orc.sign(ps, box, 11, 24, 1 << 12)
-        for bits in (0, 4):
+        for bits in (0, 4, 6):
             got = _binned(pm, ps, box, 11, 24, 1 << 12, 1 << 12, bits)
             assert _first_diff(got, want) is None, (box, bits, _first_diff(got, want))
 
@@ -134,7 +143,10 @@ def test_binned_empty_set_and_invalid(pm):
     ps = dg.from_list([])
     assert _binned(pm, ps, (0, 0, 15, 15), 0, 8, 100, 100, 2).shape == (0, 8)
     D = pm.to_device(dg.from_list([dg.rectangle(0, 0, 2, 2)]))
-    for horizon, bits, k in [(100, 5, 8), (100, -1, 8), (0, 2, 8), (100, 2, 0), (100, 2, 70000)]:
+    for horizon, bits, k in [(100, 7, 8), (100, -1, 8), (0, 2, 8), (100, 2, 0), (100, 2, 70000)]:
         with pytest.raises(pm.PolymhError) as e:
             pm.sign_binned(D, (0, 0, 15, 15), 0, k, 100, horizon=horizon, bin_bits=bits)
         assert e.value.status == pm.EINVAL
+    with pytest.raises(pm.PolymhError) as e:
+        pm.sign_binned(D, (0, 0, 15, 15), 0, 8, 100, horizon=100, bin_bits=2, walk_ratio=-1.0)
+    assert e.value.status == pm.EINVAL
