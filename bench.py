@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-binned", action="store_true", help="skip the binned-signing comparison")
     ap.add_argument("--binned-cfg5", type=int, default=300_000,
                     help="polygons of the workload-5 sample for the binned-signing comparison (0: skip)")
     ap.add_argument("--batch-queries", type=int, default=1000)
@@ -216,14 +217,16 @@ def main():
         torch.cuda.synchronize()
         return outb, e0.elapsed_time(e1) / reps / 1e3, {"horizon": h, "bin_bits": bb, "walk_ratio": 300.0,
                                                          "workspace_bytes": need}
-    sig_b, t_b2, par2 = time_binned(D, w.box, w.seed, k, cap, 3)
-    if not torch.equal(sig_b, sig):
-        raise RuntimeError("binned and walked signatures disagree (workload 2)")
-    del sig_b
-    binned = {"workload2": {"walk_ms": None, "binned_ms": 1e3 * t_b2,
-                            "binned_sig_per_s": D.n * k / t_b2, "params": par2}}
-    log(f"binned signing, workload 2: {1e3 * t_b2:.3f} ms")
-    if args.binned_cfg5 > 0:
+    binned = None
+    if not args.no_binned:
+        sig_b, t_b2, par2 = time_binned(D, w.box, w.seed, k, cap, 3)
+        if not torch.equal(sig_b, sig):
+            raise RuntimeError("binned and walked signatures disagree (workload 2)")
+        del sig_b
+        binned = {"workload2": {"walk_ms": None, "binned_ms": 1e3 * t_b2,
+                                "binned_sig_per_s": D.n * k / t_b2, "params": par2}}
+        log(f"binned signing, workload 2: {1e3 * t_b2:.3f} ms")
+    if binned is not None and args.binned_cfg5 > 0:
         w5 = dg.workload(5, n=args.binned_cfg5, n_queries=0)
         D5 = pm.to_device(w5.data)
         sig5 = torch.empty((D5.n, w5.k), dtype=torch.int32, device=dev)
@@ -250,8 +253,9 @@ def main():
     for _ in range(2):
         out = step(times)
     stage_ms = {k_: float(np.median(v)) for k_, v in times.items()}
-    binned["workload2"]["walk_ms"] = stage_ms["sign"]
-    binned["workload2"]["speedup"] = stage_ms["sign"] / binned["workload2"]["binned_ms"]
+    if binned is not None:
+        binned["workload2"]["walk_ms"] = stage_ms["sign"]
+        binned["workload2"]["speedup"] = stage_ms["sign"] / binned["workload2"]["binned_ms"]
     off, ids, ti, tj = out
     if int(ovf_sum.item()) != 0:
         raise RuntimeError("candidate capacity overflowed in a timed step")

@@ -265,7 +265,8 @@ polymh_status polymh_refine_stats(const polymh_polys *data, const polymh_polys *
  * polymh_topk -- Def. 1 / K-ANN: per query the `topk` candidates with the
  * largest J, ties by ascending id; rows padded with id -1 and J 0.
  *   top_ids [nq][topk] int32 out, top_j [nq][topk] double out.
- *   1 <= topk <= 64.  Stream-ordered.
+ *   1 <= topk <= 1024 (topk passes over each query's candidates: meant for
+ *   the K of a recall@K, not for sorting whole lists).  Stream-ordered.
  */
 polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, const double *cand_j,
                           int64_t nq, int32_t topk, int32_t *top_ids, double *top_j,

@@ -413,7 +413,7 @@ polymh_status polymh_refine_stats(const polymh_polys *data, const polymh_polys *
 polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, const double *cand_j,
                           int64_t nq, int32_t topk, int32_t *top_ids, double *top_j, void *stream)
 {
-    if (nq < 0 || topk < 1 || topk > 64) return set_error(POLYMH_EINVAL, "topk: bad sizes");
+    if (nq < 0 || topk < 1 || topk > 1024) return set_error(POLYMH_EINVAL, "topk: bad sizes");
     if (nq == 0) return POLYMH_OK;
     if (!cand_off || !top_ids || !top_j) return set_error(POLYMH_EINVAL, "topk: NULL array");
     return launch_topk(cand_off, cand_ids, cand_j, nq, topk, top_ids, top_j, as_stream(stream));

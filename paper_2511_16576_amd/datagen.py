@@ -24,6 +24,12 @@ Workloads (all on a W x W integer grid, sampling box [0, W-1]^2, hash seed 0):
 4. pairs mined from workload 2's polygons (signed at k=256).
 5. W=2^24, N=4,000,000, n = clip(round(8 (1 + Lomax(1.5))), 8, 8192),
    R ~ U(0.005, 0.03) W, k=256, cap 2^26, 32 x 8, 10,000 queries.
+
+Stand-ins of Table 1's datasets (``table1_standin``): each dataset's
+geometry count, query count and mean vertex count; star polygons on a 2^24
+grid with R = 2^16 exp(N(0, 0.5^2)) clipped to [2^13, 2^19], vertex counts
+max(4, round(LogNormal(ln(mean) - 0.18, 0.6))) (the 0.18 = 0.6^2 / 2 keeps
+the mean near the table's), queries 2%-jittered copies of dataset members.
 """
 from __future__ import annotations
 
@@ -242,6 +248,37 @@ def concat(sets) -> PolySet:
     np.cumsum(counts, out=off[1:])
     return PolySet(np.concatenate(xs), off, np.concatenate([s.centre for s in sets]),
                    np.concatenate([s.radius for s in sets]))
+
+
+# Table 1: geometries, queries, average vertex count
+TABLE1 = {
+    "urban": (11_800, 3_000, 95.40),
+    "cemetery": (149_000, 3_000, 9.26),
+    "parks": (300_000, 3_000, 319.0),
+    "sports": (1_000_000, 20_000, 12.0),
+}
+
+
+def table1_standin(name: str, n: int | None = None, n_queries: int | None = None) -> Workload:
+    """Synthetic stand-in of Table 1's dataset ``name`` (urban, cemetery,
+    parks, sports); ``n`` / ``n_queries`` shrink it.  The signature length,
+    tables and cap are the experiment's to choose (k, bands, rows here are
+    placeholders for one 3-row table)."""
+    N0, Q0, mean = TABLE1[name]
+    rng = _rng(100 + list(TABLE1).index(name))
+    N = N0 if n is None else n
+    Q = Q0 if n_queries is None else n_queries
+    gb = 24
+
+    def counts(r, m):
+        mu = math.log(mean) - 0.18
+        return np.clip(np.rint(np.exp(r.normal(mu, 0.6, m))), 4, 8192).astype(np.int64)
+    radii = np.clip(65536.0 * np.exp(rng.normal(0.0, 0.5, N)), 8192.0, 524288.0)
+    cnt = counts(rng, N)
+    data = star_polygons(rng, cnt, _centres(rng, radii, gb), radii)
+    src = rng.integers(0, N, Q)
+    q = jittered(rng, data, src, 0.02, gb)
+    return Workload(f"table1-{name}", gb, data, q, src, k=3, cap=1 << 22, bands=1, rows=3)
 
 
 def _rng(cfg: int, stream: int = 0):
