@@ -906,9 +906,17 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
     if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "refine: too many queries");
-    // small batches spread each query over several workgroups (every
-    // workgroup stages the query once); from 2048 queries on, one each
-    const int slices = nq >= 2048 ? 1 : (int)std::min<int64_t>(16, (2048 + nq - 1) / nq);
+    // a query's candidates are spread over several workgroups (each stages
+    // the query once) when the batch is small or its lists are long: at
+    // least 2048 workgroups, at most about 64 candidates per workgroup on
+    // average (16 per wavefront: the query's staging is cheap beside them
+    // and the long lists no longer set the launch's tail), at most 64
+    // workgroups per query
+    const int64_t by_batch = (2048 + nq - 1) / nq;
+    const int64_t by_length = (n_cand + nq * 64 - 1) / (nq * 64);
+    int64_t sl = std::max<int64_t>(1, std::min<int64_t>(64, std::max(by_batch, by_length)));
+    if (nq * sl > 0x7fffffffLL) sl = 1;
+    const int slices = (int)sl;
     hipLaunchKernelGGL(k_refine, dim3((unsigned)(nq * slices)), dim3(64 * kWavesPerBlock), 0, s, data->xy,
                        data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j, stats,
                        slices);
