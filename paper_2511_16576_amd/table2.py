@@ -20,8 +20,11 @@ measured on that sample.  When ``--queries`` is below the table's query
 count, PolyMinHash times are scaled the same way.
 
 Run: ``python -m paper_2511_16576_amd.table2 --dataset cemetery [--m 1 2 3]
-[--tables 1 2] [--bf-queries 200] [--queries Q] [--n N] [--json out.json]``
-(``--dataset all`` runs the four)."""
+[--tables 1 2] [--bf-queries B] [--queries Q] [--n N] [--json out.json]``
+(``--dataset all`` runs the four).  Defaults per dataset: Table 2's m
+values, and for Parks (319 vertices on average, about 0.9 us per exact J
+once centred) and Sports (20,000 queries) a timed query subset of 300 and
+2,000 queries with brute force on 50 and 100 of them."""
 from __future__ import annotations
 
 import argparse
@@ -37,6 +40,12 @@ from . import metrics
 from . import polymh as pm
 
 KS = (10, 50, 100)
+# Table 2's MinHash lengths per dataset; query subset and brute-force sample
+PAPER_M = {"urban": (1, 2, 3), "cemetery": (1, 3, 5), "parks": (1, 2, 3), "sports": (1, 3)}
+QUERIES = {"urban": None, "cemetery": None, "parks": 300, "sports": 2000}
+BF_QUERIES = {"urban": 200, "cemetery": 200, "parks": 50, "sports": 100}
+# queries per lookup batch (bounded by candidate memory and by progress lines)
+BATCH = {"urban": 1000, "cemetery": 1000, "parks": 100, "sports": 250}
 
 
 def log(msg):
@@ -65,7 +74,7 @@ class _Timer:
         return self.e0.elapsed_time(self.e1)
 
 
-def brute_force(D: pm.DevicePolys, Q: pm.DevicePolys, kmax: int, chunk_pairs: int = 1 << 25):
+def brute_force(D: pm.DevicePolys, Q: pm.DevicePolys, kmax: int, chunk_pairs: int = 1 << 25, log=None):
     """Exact top-kmax of every query of Q against all of D: (ids, J, ms)."""
     n, nq = D.n, Q.n
     per = max(1, chunk_pairs // max(n, 1))
@@ -84,20 +93,27 @@ def brute_force(D: pm.DevicePolys, Q: pm.DevicePolys, kmax: int, chunk_pairs: in
         top_i.append(ti.cpu().numpy())
         top_j.append(tj.cpu().numpy())
         del J, ids
+        if log is not None and nq > per:
+            log(f"  brute force: queries {a}-{b} of {nq}, {ms:.0f} ms")
     return np.concatenate(top_i), np.concatenate(top_j), ms
 
 
-def run_config(D, Q, box, seed, m, tables, cap, sample, bf_i, bf_j, batch):
-    """One (m, tables) configuration over all of Q's queries."""
+def run_config(D, Q, box, seed, m, tables, cap, sample, bf_i, bf_j, batch=100):
+    """One (m, tables) configuration over all of Q's queries.  Times in ms,
+    dataset-side (once) and query-side (proportional to the query count)."""
     k = m * tables
     t = _Timer()
     t.start()
     sd = pm.sign(D, box, seed, k, cap)
+    ms_sign_d = t.stop()
+    t.start()
     sq = pm.sign(Q, box, seed, k, cap)
-    ms_sign = t.stop()
+    ms_sign_q = t.stop()
     t.start()
     kd = pm.band(sd, tables, m, seed)
     sk, si = pm.index_build(kd)
+    ms_index = t.stop()
+    t.start()
     kq = pm.band(sq, tables, m, seed)
     ms_lookup = t.stop()
     cand_total = 0
@@ -114,18 +130,25 @@ def run_config(D, Q, box, seed, m, tables, cap, sample, bf_i, bf_j, batch):
         ti, tj = pm.topk(off, ids, J, max(KS))
         ms_lookup += t.stop()
         cand_total += int(off[-1].item())
+        if Q.n > batch:
+            log(f"  m={m} tables={tables}: queries {a}-{b}, {int(off[-1].item())} candidates, {ms_lookup:.0f} ms")
         sel = np.flatnonzero(in_sample[a:b])
         if sel.size:
             ann_i[a + sel] = ti.cpu().numpy()[sel]
             ann_j[a + sel] = tj.cpu().numpy()[sel]
         del off, ids, J
     rec = {f"recall@{kk}": metrics.recall_at_k(ann_i[sample], ann_j[sample], bf_i, bf_j, kk) for kk in KS}
-    return {"m": m, "tables": tables, "k": k, **rec, "minhash_ms": ms_sign, "lookup_refine_ms": ms_lookup,
+    return {"m": m, "tables": tables, "k": k, **rec, "sign_data_ms": ms_sign_d, "sign_queries_ms": ms_sign_q,
+            "index_ms": ms_index, "lookup_refine_queries_ms": ms_lookup,
             "candidates_per_query": cand_total / Q.n, "pruning_pct": 100.0 * (1.0 - cand_total / (Q.n * D.n))}
 
 
-def run_dataset(name, ms=(1, 2, 3, 4, 5), tables=(1, 2), bf_queries=200, n=None, n_queries=None,
-                cap=1 << 22, batch=500, seed=0):
+def run_dataset(name, ms=None, tables=(1, 2), bf_queries=None, n=None, n_queries=None,
+                cap=1 << 22, batch=None, seed=0):
+    ms = PAPER_M[name] if ms is None else ms
+    batch = BATCH[name] if batch is None else batch
+    bf_queries = BF_QUERIES[name] if bf_queries is None else bf_queries
+    n_queries = QUERIES[name] if n_queries is None else n_queries
     t0 = time.time()
     w = dg.table1_standin(name, n=n, n_queries=n_queries)
     q_full = dg.TABLE1[name][1]
@@ -140,7 +163,7 @@ def run_dataset(name, ms=(1, 2, 3, 4, 5), tables=(1, 2), bf_queries=200, n=None,
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(Q.n, min(bf_queries, Q.n), replace=False))
     Qb = pm.DevicePolys(*_gather(Q, sample))
-    bf_i, bf_j, bf_ms = brute_force(D, Qb, max(KS))
+    bf_i, bf_j, bf_ms = brute_force(D, Qb, max(KS), log=log)
     scale_q = q_full / Q.n
     bf_total_s = bf_ms / 1e3 * q_full / sample.size
     log(f"{name}: brute force {bf_ms:.0f} ms for {sample.size} queries -> {bf_total_s:.1f} s for {q_full}")
@@ -148,9 +171,10 @@ def run_dataset(name, ms=(1, 2, 3, 4, 5), tables=(1, 2), bf_queries=200, n=None,
     for tb in tables:
         for m in ms:
             r = run_config(D, Q, box, seed, m, tb, cap, sample, bf_i, bf_j, batch)
-            total_s = (r["minhash_ms"] + r["lookup_refine_ms"]) / 1e3 * scale_q
-            r.update({"dataset": name, "minhash_s": r["minhash_ms"] / 1e3 * scale_q,
-                      "lookup_refine_s": r["lookup_refine_ms"] / 1e3 * scale_q, "total_s": total_s,
+            minhash_s = (r["sign_data_ms"] + r["sign_queries_ms"] * scale_q) / 1e3
+            lookup_s = (r["index_ms"] + r["lookup_refine_queries_ms"] * scale_q) / 1e3
+            total_s = minhash_s + lookup_s
+            r.update({"dataset": name, "minhash_s": minhash_s, "lookup_refine_s": lookup_s, "total_s": total_s,
                       "bf_s": bf_total_s, "speedup": bf_total_s / total_s})
             rows.append(r)
             log(f"{name} tables={tb} m={m}: recall@10/50/100 {r['recall@10']:.2f}/{r['recall@50']:.2f}/"
@@ -188,12 +212,12 @@ def table_markdown(results) -> str:
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--dataset", default="cemetery", choices=list(dg.TABLE1) + ["all"])
-    ap.add_argument("--m", type=int, nargs="+", default=[1, 2, 3, 4, 5])
+    ap.add_argument("--m", type=int, nargs="+", default=None)
     ap.add_argument("--tables", type=int, nargs="+", default=[1, 2])
-    ap.add_argument("--bf-queries", type=int, default=200)
+    ap.add_argument("--bf-queries", type=int, default=None)
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--n", type=int, default=None)
-    ap.add_argument("--batch", type=int, default=500)
+    ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     pm.check_device()
