@@ -25,6 +25,13 @@ Workloads (all on a W x W integer grid, sampling box [0, W-1]^2, hash seed 0):
 5. W=2^24, N=4,000,000, n = clip(round(8 (1 + Lomax(1.5))), 8, 8192),
    R ~ U(0.005, 0.03) W, k=256, cap 2^26, 32 x 8, 10,000 queries.
 
+Polygons with holes and multipolygons (``ring_polygons``): a polygon is a
+list of rings, filled rings counter-clockwise and holes clockwise (the OGC
+convention); ``RingSet`` stores them as vertices, ring offsets and each
+polygon's ring range.  Holes are stars inside the largest disc about the
+outer ring's centre that the outer ring contains; a second component sits
+3R away.
+
 Stand-ins of Table 1's datasets (``table1_standin``): each dataset's
 geometry count, query count and mean vertex count; star polygons on a 2^24
 grid with R = 2^16 exp(N(0, 0.5^2)) clipped to [2^13, 2^19], vertex counts
@@ -248,6 +255,81 @@ def concat(sets) -> PolySet:
     np.cumsum(counts, out=off[1:])
     return PolySet(np.concatenate(xs), off, np.concatenate([s.centre for s in sets]),
                    np.concatenate([s.radius for s in sets]))
+
+
+@dataclasses.dataclass
+class RingSet:
+    xy: np.ndarray           # int32 [V, 2]
+    ring_offsets: np.ndarray  # int64 [R + 1]: ring r is xy[ring_offsets[r]:ring_offsets[r+1]]
+    poly_rings: np.ndarray    # int64 [N + 1]: polygon p owns rings poly_rings[p]:poly_rings[p+1]
+
+    @property
+    def n(self) -> int:
+        return int(self.poly_rings.shape[0] - 1)
+
+    def rings(self, p: int):
+        return [self.xy[self.ring_offsets[r]:self.ring_offsets[r + 1]]
+                for r in range(int(self.poly_rings[p]), int(self.poly_rings[p + 1]))]
+
+
+def from_rings(polys) -> RingSet:
+    """RingSet from a list of polygons, each a list of (k, 2) rings."""
+    rings = [np.asarray(r, dtype=np.int64).reshape(-1, 2) for p in polys for r in p]
+    counts = np.array([r.shape[0] for r in rings], dtype=np.int64)
+    roff = np.zeros(counts.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=roff[1:])
+    proff = np.zeros(len(polys) + 1, dtype=np.int64)
+    np.cumsum([len(p) for p in polys], out=proff[1:])
+    xy = np.concatenate(rings).astype(np.int32) if rings else np.zeros((0, 2), dtype=np.int32)
+    return RingSet(xy, roff, proff)
+
+
+def _inner_radius(ring: np.ndarray, c) -> float:
+    """Distance from c to the nearest point of the closed ring (float)."""
+    a = ring.astype(np.float64) - np.asarray(c, dtype=np.float64)
+    b = np.roll(a, -1, axis=0)
+    d = b - a
+    t = np.clip(-(a * d).sum(axis=1) / np.maximum((d * d).sum(axis=1), 1e-30), 0.0, 1.0)
+    p = a + t[:, None] * d
+    return float(np.sqrt((p * p).sum(axis=1)).min())
+
+
+def ring_polygons(rng, n: int, grid_bits: int, count_fn, rfrac_lo: float, rfrac_hi: float,
+                  hole_probs=(0.4, 0.35, 0.25), multi_prob: float = 0.25) -> RingSet:
+    """``n`` polygons: one or (with probability ``multi_prob``) two star
+    components of radius R, each with 0, 1 or 2 star holes (``hole_probs``).
+    One hole is centred with radius 0.8 d, two sit at +-0.5 d with radius
+    0.4 d, where d is the distance from the component's centre to its outer
+    ring; holes are reversed to clockwise.  Components are 3R apart."""
+    w = 1 << grid_bits
+    polys = []
+    for _ in range(n):
+        multi = rng.random() < multi_prob
+        R = float(rng.uniform(rfrac_lo, rfrac_hi) * w)
+        m = int(math.ceil(R))
+        span = 4 * m if multi else m
+        cx = int(rng.integers(m, w - 1 - span + 1))
+        cy = int(rng.integers(m, w - 1 - m + 1))
+        centres = [(cx, cy)] + ([(cx + 3 * m, cy)] if multi else [])
+        rings = []
+        for c in centres:
+            cnt = count_fn(rng, 1)
+            outer = star_polygons(rng, cnt, [c], [R]).xy
+            rings.append(outer)
+            d = _inner_radius(outer, c)
+            nh = int(rng.choice(3, p=hole_probs))
+            if nh == 1:
+                hc, hr = [c], [0.8 * d]
+            elif nh == 2:
+                off = int(0.5 * d)
+                hc, hr = [(c[0] - off, c[1]), (c[0] + off, c[1])], [0.4 * d, 0.4 * d]
+            else:
+                hc, hr = [], []
+            for h, r in zip(hc, hr):
+                hole = star_polygons(rng, rng.integers(3, 13, 1), [h], [r]).xy
+                rings.append(hole[::-1])
+        polys.append(rings)
+    return from_rings(polys)
 
 
 # Table 1: geometries, queries, average vertex count
