@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned-signing comparison")
+    ap.add_argument("--no-rings", action="store_true", help="skip the holes / multipolygon measurement")
     ap.add_argument("--binned-cfg5", type=int, default=300_000,
                     help="polygons of the workload-5 sample for the binned-signing comparison (0: skip)")
     ap.add_argument("--batch-queries", type=int, default=1000)
@@ -248,6 +249,58 @@ def main():
         log(f"binned signing, workload-5 sample: walk {1e3 * t_w5:.1f} ms, binned {1e3 * t_b5:.1f} ms")
         del sig_b5, sig5, D5
 
+    # polygons with holes and multipolygons: 100,000 shapes of workload 2's
+    # sizes (0-2 holes per component, a quarter with two components) joined
+    # into single rings on the device (HBM-bound copy: 8 B read and 8 B
+    # written per vertex, plus the offsets), then signed like workload 2
+    rings = None
+    if not args.no_rings:
+        t0 = time.time()
+        rs = dg.ring_polygons(np.random.default_rng(np.random.SeedSequence([6, 0])), 100_000, 24,
+                              lambda r_, m_: dg._lognormal_counts(r_, m_, 512), 0.02, 0.15)
+        log(f"ring shapes generated in {time.time() - t0:.1f}s: {rs.n} shapes, "
+            f"{rs.ring_offsets.shape[0] - 1} rings, {rs.xy.shape[0]} vertices")
+        Rd = pm.rings_to_device(rs)
+        Jd = pm.join_rings(Rd)            # checks the input flag once
+        nv_out = int(Jd.xy.shape[0])
+        # the launch alone, into the same buffers (no flag read in the timed region)
+        nv_in, nr_in = int(Rd.xy.shape[0]), int(Rd.ring_offsets.shape[0] - 1)
+        bad = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def join_launch():
+            st_ = pm.lib().polymh_join_rings(Rd.xy.data_ptr(), nv_in, Rd.ring_offsets.data_ptr(), nr_in,
+                                             Rd.poly_rings.data_ptr(), rs.n, Jd.xy.data_ptr(), nv_out,
+                                             Jd.offsets.data_ptr(), bad.data_ptr(), stream.cuda_stream)
+            if st_ != 0:
+                raise RuntimeError(pm.lib().polymh_last_error().decode())
+        join_launch()
+        e0.record(stream)
+        for _ in range(5):
+            join_launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if int(bad.item()):
+            raise RuntimeError("join_rings flagged the generated shapes")
+        t_join = e0.elapsed_time(e1) / 5 / 1e3
+        join_bytes = 8.0 * rs.xy.shape[0] + 8.0 * nv_out + 8.0 * rs.ring_offsets.shape[0] + 16.0 * (rs.n + 1)
+        sig_r = torch.empty((rs.n, k), dtype=torch.int32, device=dev)
+        ws_r = torch.empty(pm.sign_workspace_size(rs.n, cfg), dtype=torch.uint8, device=dev)
+        pm.sign(Jd, w.box, w.seed, k, cap, config=cfg, out=sig_r, ws=ws_r)
+        e0.record(stream)
+        for _ in range(3):
+            pm.sign(Jd, w.box, w.seed, k, cap, config=cfg, out=sig_r, ws=ws_r)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_sr = e0.elapsed_time(e1) / 3 / 1e3
+        rings = {"shapes": rs.n, "rings": int(rs.ring_offsets.shape[0] - 1), "vertices": int(rs.xy.shape[0]),
+                 "joined_vertices": nv_out, "join_ms": 1e3 * t_join,
+                 "join_roofline": {"bound": "hbm", "achieved": join_bytes / t_join / 1e9, "peak": 8000.0,
+                                   "unit": "GB/s", "frac": join_bytes / t_join / 8e12, "traffic": None,
+                                   "kernel": "k_join", "bytes_per_launch": join_bytes},
+                 "sign_ms": 1e3 * t_sr, "sign_sig_per_s": rs.n * k / t_sr}
+        log(f"ring shapes: join {1e3 * t_join:.3f} ms, signing {1e3 * t_sr:.3f} ms")
+        del Rd, Jd, sig_r, ws_r
+
     # per-stage breakdown from a separate instrumented pass
     times = {}
     for _ in range(2):
@@ -420,6 +473,7 @@ def main():
         "batched": batched,
         "learned": learned,
         "binned_sign": binned,
+        "rings": rings,
     }
     print(json.dumps(line), flush=True)
 

@@ -150,6 +150,34 @@ polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t se
                           uint32_t cap, uint32_t *sig, const polymh_sign_config *cfg_host,
                           void *ws, size_t ws_bytes, void *stream);
 
+/* polymh_join_rings -- polygons with holes and multipolygons (the shapes of
+ * the paper's real datasets, Sec. 5.1) as single rings that every call of
+ * this library takes as they are.  Input: shape p owns rings
+ * poly_rings[p] .. poly_rings[p+1]-1, ring r is vertices
+ * ring_offsets[r] .. ring_offsets[r+1]-1 of xy (int32 pairs); filled rings
+ * counter-clockwise and holes clockwise (or every ring reversed), rings
+ * non-overlapping.  Output: each shape's rings joined through bridges to
+ * the first ring's first vertex v0 (R0, v0, R1, R1[0], v0, ..., Rk, Rk[0],
+ * closing to v0); a bridge's two edges coincide with opposite directions,
+ * so membership (crossing parity over all rings, Alg. 1's test), areas,
+ * centroids and the refinement's boundary sums are those of the even-odd
+ * region.  A one-ring shape is copied unchanged.
+ *   xy [n_vertices][2], ring_offsets [n_rings+1], poly_rings [n_polys+1]:
+ *   device, caller-owned.
+ *   out_xy [out_capacity][2] int32 (polymh_join_rings_size(V, R, N) vertices
+ *   suffice), out_offsets [N+1] int64, device, caller-owned; shape p's
+ *   joined ring starts at ring_offsets[poly_rings[p]] + 2 (poly_rings[p] - p).
+ *   bad_flag  nullable device int32, set to 1 (never cleared) if a shape has
+ *   no ring, indices out of range or more output than out_capacity (such a
+ *   shape is skipped and its offsets are meaningless), or a ring has fewer
+ *   than 3 vertices.
+ * POLYMH_EINVAL for NULL arrays, negative sizes or out_xy == xy.
+ * Stream-ordered. */
+int64_t polymh_join_rings_size(int64_t n_vertices, int64_t n_rings, int64_t n_polys);
+polymh_status polymh_join_rings(const int32_t *xy, int64_t n_vertices, const int64_t *ring_offsets,
+                                int64_t n_rings, const int64_t *poly_rings, int64_t n_polys, int32_t *out_xy,
+                                int64_t out_capacity, int64_t *out_offsets, int32_t *bad_flag, void *stream);
+
 /* polymh_sign_binned -- the same signatures as polymh_sign, bit for bit,
  * computed from shared samples: every polygon reads the same point stream
  * per hash (Sec. 3.2's fixed-seed generators; Def. 2), so for every hash the

@@ -249,6 +249,26 @@ polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t se
     return launch_sign(L, s);
 }
 
+int64_t polymh_join_rings_size(int64_t n_vertices, int64_t n_rings, int64_t n_polys)
+{
+    if (n_vertices < 0 || n_rings < 0 || n_polys < 0) return -1;
+    return n_vertices + 2 * (n_rings - n_polys);
+}
+
+polymh_status polymh_join_rings(const int32_t *xy, int64_t n_vertices, const int64_t *ring_offsets,
+                                int64_t n_rings, const int64_t *poly_rings, int64_t n_polys, int32_t *out_xy,
+                                int64_t out_capacity, int64_t *out_offsets, int32_t *bad_flag, void *stream)
+{
+    if (n_polys < 0 || n_rings < 0 || n_vertices < 0 || out_capacity < 0)
+        return set_error(POLYMH_EINVAL, "join_rings: negative size");
+    if (n_polys == 0) return POLYMH_OK;
+    if (!xy || !ring_offsets || !poly_rings || !out_xy || !out_offsets)
+        return set_error(POLYMH_EINVAL, "join_rings: NULL array");
+    if (out_xy == xy) return set_error(POLYMH_EINVAL, "join_rings: out_xy aliases xy");
+    return launch_join_rings(xy, n_vertices, ring_offsets, n_rings, poly_rings, n_polys, out_xy, out_capacity,
+                             out_offsets, bad_flag, as_stream(stream));
+}
+
 size_t polymh_sign_binned_workspace_size(int64_t n, int32_t k, uint32_t cap, uint32_t horizon, int32_t bin_bits,
                                          const polymh_sign_config *cfg)
 {

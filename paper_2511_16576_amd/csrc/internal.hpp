@@ -202,6 +202,11 @@ struct SignLaunch {
 };
 polymh_status launch_sign(const SignLaunch &L, hipStream_t s);
 
+// rings.hip
+polymh_status launch_join_rings(const int32_t *xy, int64_t nv, const int64_t *ring_off, int64_t nr,
+                                const int64_t *poly_rings, int64_t n, int32_t *out_xy, int64_t out_cap,
+                                int64_t *out_off, int32_t *bad, hipStream_t s);
+
 // binned.hip
 size_t binned_workspace_bytes(int32_t k, uint32_t horizon, int32_t bits, int64_t n);
 polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint32_t horizon, int32_t bits,

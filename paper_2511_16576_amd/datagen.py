@@ -284,52 +284,71 @@ def from_rings(polys) -> RingSet:
     return RingSet(xy, roff, proff)
 
 
-def _inner_radius(ring: np.ndarray, c) -> float:
-    """Distance from c to the nearest point of the closed ring (float)."""
-    a = ring.astype(np.float64) - np.asarray(c, dtype=np.float64)
-    b = np.roll(a, -1, axis=0)
-    d = b - a
+def _inner_radii(ps: PolySet) -> np.ndarray:
+    """Per polygon, the distance from its centre to the nearest point of its
+    ring (float)."""
+    off, pid = _segments(ps.counts())
+    a = ps.xy.astype(np.float64) - ps.centre[pid].astype(np.float64)
+    nxt = np.arange(off[-1]) + 1
+    nxt[off[1:] - 1] = off[:-1]
+    d = a[nxt] - a
     t = np.clip(-(a * d).sum(axis=1) / np.maximum((d * d).sum(axis=1), 1e-30), 0.0, 1.0)
-    p = a + t[:, None] * d
-    return float(np.sqrt((p * p).sum(axis=1)).min())
+    q = a + t[:, None] * d
+    return np.minimum.reduceat(np.sqrt((q * q).sum(axis=1)), off[:-1])
 
 
 def ring_polygons(rng, n: int, grid_bits: int, count_fn, rfrac_lo: float, rfrac_hi: float,
                   hole_probs=(0.4, 0.35, 0.25), multi_prob: float = 0.25) -> RingSet:
-    """``n`` polygons: one or (with probability ``multi_prob``) two star
+    """``n`` shapes: one or (with probability ``multi_prob``) two star
     components of radius R, each with 0, 1 or 2 star holes (``hole_probs``).
     One hole is centred with radius 0.8 d, two sit at +-0.5 d with radius
     0.4 d, where d is the distance from the component's centre to its outer
-    ring; holes are reversed to clockwise.  Components are 3R apart."""
+    ring (holes under 64 units of radius are left out); holes have 3-12
+    vertices and are reversed to clockwise.  Components are 3R apart."""
     w = 1 << grid_bits
-    polys = []
-    for _ in range(n):
-        multi = rng.random() < multi_prob
-        R = float(rng.uniform(rfrac_lo, rfrac_hi) * w)
-        m = int(math.ceil(R))
-        span = 4 * m if multi else m
-        cx = int(rng.integers(m, w - 1 - span + 1))
-        cy = int(rng.integers(m, w - 1 - m + 1))
-        centres = [(cx, cy)] + ([(cx + 3 * m, cy)] if multi else [])
-        rings = []
-        for c in centres:
-            cnt = count_fn(rng, 1)
-            outer = star_polygons(rng, cnt, [c], [R]).xy
-            rings.append(outer)
-            d = _inner_radius(outer, c)
-            nh = int(rng.choice(3, p=hole_probs))
-            if nh == 1:
-                hc, hr = [c], [0.8 * d]
-            elif nh == 2:
-                off = int(0.5 * d)
-                hc, hr = [(c[0] - off, c[1]), (c[0] + off, c[1])], [0.4 * d, 0.4 * d]
-            else:
-                hc, hr = [], []
-            for h, r in zip(hc, hr):
-                hole = star_polygons(rng, rng.integers(3, 13, 1), [h], [r]).xy
-                rings.append(hole[::-1])
-        polys.append(rings)
-    return from_rings(polys)
+    multi = rng.random(n) < multi_prob
+    R = rng.uniform(rfrac_lo, rfrac_hi, n) * w
+    m = np.ceil(R).astype(np.int64)
+    span = np.where(multi, 4 * m, m)
+    cx = m + np.floor(rng.random(n) * (w - 1 - span - m + 1)).astype(np.int64)
+    cy = m + np.floor(rng.random(n) * (w - 1 - 2 * m + 1)).astype(np.int64)
+    # components: shape s has component 0, and component 1 when multi
+    comp_shape = np.concatenate([np.arange(n), np.flatnonzero(multi)])
+    comp_second = np.concatenate([np.zeros(n, bool), np.ones(int(multi.sum()), bool)])
+    order = np.lexsort((comp_second, comp_shape))
+    comp_shape, comp_second = comp_shape[order], comp_second[order]
+    cc = np.stack([cx[comp_shape] + np.where(comp_second, 3 * m[comp_shape], 0), cy[comp_shape]], axis=1)
+    outer = star_polygons(rng, count_fn(rng, comp_shape.shape[0]), cc, R[comp_shape])
+    d = _inner_radii(outer)
+    nh = rng.choice(3, size=comp_shape.shape[0], p=hole_probs)
+    h_comp, h_c, h_r = [], [], []
+    for k_, places in ((1, [(0.0, 0.8)]), (2, [(-0.5, 0.4), (0.5, 0.4)])):
+        sel = np.flatnonzero(nh == k_)
+        for fx, fr in places:
+            h_comp.append(sel)
+            h_c.append(np.stack([cc[sel, 0] + (fx * d[sel]).astype(np.int64), cc[sel, 1]], axis=1))
+            h_r.append(fr * d[sel])
+    h_comp, h_c, h_r = np.concatenate(h_comp), np.concatenate(h_c), np.concatenate(h_r)
+    keep = h_r >= 64.0
+    h_comp, h_c, h_r = h_comp[keep], h_c[keep], h_r[keep]
+    h_order = np.lexsort((h_c[:, 0], h_comp))
+    h_comp, h_c, h_r = h_comp[h_order], h_c[h_order], h_r[h_order]
+    holes = star_polygons(rng, rng.integers(3, 13, h_comp.shape[0]), h_c, h_r)
+    # assemble: per component its outer ring, then its holes (clockwise)
+    hole_first = np.searchsorted(h_comp, np.arange(comp_shape.shape[0]), side="left")
+    hole_last = np.searchsorted(h_comp, np.arange(comp_shape.shape[0]), side="right")
+    rings, per_shape = [], np.zeros(n, dtype=np.int64)
+    for c in range(comp_shape.shape[0]):
+        rings.append(outer.poly(c))
+        for h in range(hole_first[c], hole_last[c]):
+            rings.append(holes.poly(h)[::-1])
+        per_shape[comp_shape[c]] += 1 + hole_last[c] - hole_first[c]
+    counts = np.array([r.shape[0] for r in rings], dtype=np.int64)
+    roff = np.zeros(counts.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=roff[1:])
+    proff = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(per_shape, out=proff[1:])
+    return RingSet(np.concatenate(rings).astype(np.int32), roff, proff)
 
 
 # Table 1: geometries, queries, average vertex count

@@ -62,6 +62,8 @@ _SIGNATURES = {
     "polymh_sign_default_config": (None, [P]),
     "polymh_sign_workspace_size": (SZ, [I64, P]),
     "polymh_sign": (I32, [P, Box, U64, I32, U32, P, P, P, SZ, P]),
+    "polymh_join_rings_size": (I64, [I64, I64, I64]),
+    "polymh_join_rings": (I32, [P, I64, P, I64, P, I64, P, I64, P, P, P]),
     "polymh_sign_binned_workspace_size": (SZ, [I64, I32, U32, U32, I32, P]),
     "polymh_sign_binned": (I32, [P, Box, U64, I32, U32, U32, I32, ctypes.c_double, P, P, P, SZ, P]),
     "polymh_band": (I32, [P, I64, I32, I32, I32, U64, P, P]),
@@ -221,6 +223,50 @@ def centre(polys: DevicePolys, stream=None):
     if int(flag.item()):
         raise ValueError("centre: a polygon spans 2^31 or more; its centred coordinates leave int32")
     return DevicePolys(xy, polys.offsets), shift[:polys.n]
+
+
+@dataclasses.dataclass
+class DeviceRings:
+    """Polygons with holes / multipolygons resident on the device: ring r is
+    xy[ring_offsets[r]:ring_offsets[r+1]], shape p owns rings
+    poly_rings[p]:poly_rings[p+1]."""
+    xy: torch.Tensor            # int32 [V, 2]
+    ring_offsets: torch.Tensor  # int64 [R + 1]
+    poly_rings: torch.Tensor    # int64 [N + 1]
+
+    @property
+    def n(self) -> int:
+        return int(self.poly_rings.shape[0] - 1)
+
+
+def rings_to_device(rs, device="cuda") -> DeviceRings:
+    """Copy a RingSet-like object (``.xy``, ``.ring_offsets``, ``.poly_rings``)."""
+    xy = torch.from_numpy(np.ascontiguousarray(rs.xy, dtype=np.int32).reshape(-1, 2))
+    if xy.shape[0] == 0:
+        xy = torch.zeros((1, 2), dtype=torch.int32)
+    ro = torch.from_numpy(np.ascontiguousarray(rs.ring_offsets, dtype=np.int64))
+    pr = torch.from_numpy(np.ascontiguousarray(rs.poly_rings, dtype=np.int64))
+    return DeviceRings(xy.to(device), ro.to(device), pr.to(device))
+
+
+def join_rings(R: DeviceRings, stream=None) -> DevicePolys:
+    """Each shape's rings joined into one ring (``polymh_join_rings``), so
+    that every other call takes shapes with holes and several components.
+    Synchronises once to check the input flag."""
+    check_device()
+    n = R.n
+    nv = int(R.xy.shape[0])
+    nr = int(R.ring_offsets.shape[0] - 1)
+    size = max(int(lib().polymh_join_rings_size(nv, nr, n)), 0)
+    dev = R.poly_rings.device
+    out = torch.empty((max(size, 1), 2), dtype=torch.int32, device=dev)
+    off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    bad = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(lib().polymh_join_rings(_ptr(R.xy), nv, _ptr(R.ring_offsets), nr, _ptr(R.poly_rings), n, _ptr(out),
+                                   size, _ptr(off), _ptr(bad), _stream(stream)))
+    if int(bad.item()):
+        raise ValueError("join_rings: a shape without rings, or a ring with fewer than 3 vertices")
+    return DevicePolys(out, off)
 
 
 def box_of(polys: DevicePolys, stream=None):
