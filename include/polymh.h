@@ -280,6 +280,21 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, void *stream);
 
+/* polymh_refine_ws -- polymh_refine (stats nullable, as polymh_refine_stats)
+ * with a workspace of polymh_refine_workspace_size() bytes (device,
+ * caller-owned, contents overwritten).  With it, pairs on the general form
+ * with n m >= 2^17 edge pairs (polygons beyond 512 edges) are not computed by
+ * one wavefront but split over 32 wavefronts by two further launches, so a
+ * few very large pairs no longer set the call's duration; the values are
+ * those of polymh_refine up to the order of floating-point additions.  Up to
+ * 8192 such pairs per call are split (the rest run in place).  ws NULL is
+ * polymh_refine.  Stream-ordered and graph-capturable; two calls sharing a
+ * workspace must not overlap. */
+size_t polymh_refine_workspace_size(void);
+polymh_status polymh_refine_ws(const polymh_polys *data, const polymh_polys *queries, const int64_t *cand_off,
+                               const int32_t *cand_ids, int64_t nq, int64_t n_cand, double *cand_j,
+                               uint64_t *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* polymh_refine_stats -- polymh_refine that also adds its work counts to
  * stats [4] (device uint64, caller-zeroed): pairs refined by the tiled form,
  * edge pairs that form tested (8 per kept (P chunk, Q edge) unit), edge

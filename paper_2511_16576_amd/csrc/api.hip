@@ -415,6 +415,23 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
     return launch_refine(data, queries, cand_off, cand_ids, nq, n_cand, cand_j, as_stream(stream));
 }
 
+size_t polymh_refine_workspace_size(void) { return refine_workspace_bytes(); }
+
+polymh_status polymh_refine_ws(const polymh_polys *data, const polymh_polys *queries, const int64_t *cand_off,
+                               const int32_t *cand_ids, int64_t nq, int64_t n_cand, double *cand_j,
+                               uint64_t *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    polymh_status st = check_polys(data, "refine_ws");
+    if (st) return st;
+    if ((st = check_polys(queries, "refine_ws"))) return st;
+    if (nq != queries->n) return set_error(POLYMH_EINVAL, "refine_ws: nq differs from the query count");
+    if (n_cand < 0) return set_error(POLYMH_EINVAL, "refine_ws: negative candidate count");
+    if (n_cand == 0 || nq == 0) return POLYMH_OK;
+    if (!cand_off || !cand_ids || !cand_j) return set_error(POLYMH_EINVAL, "refine_ws: NULL array");
+    return launch_refine(data, queries, cand_off, cand_ids, nq, n_cand, cand_j, as_stream(stream),
+                         reinterpret_cast<unsigned long long *>(stats), ws, ws ? ws_bytes : 0);
+}
+
 polymh_status polymh_refine_stats(const polymh_polys *data, const polymh_polys *queries,
                                   const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                                   int64_t n_cand, double *cand_j, uint64_t *stats, void *stream)

@@ -111,24 +111,43 @@ struct PairIn {
     int sp;             // orientation of P
 };
 
+// The other ring's vertices are read 64 at a time, one per lane, by a
+// wavefront whose lanes are all active, and handed to the edge loop by
+// readlane: one coalesced load per 64 iterations instead of a dependent load
+// in each.  Vertex (jb + lane + 1) mod m of an m-vertex ring.
+__device__ __forceinline__ int2 next_vertex_block(const int32_t *V, int m, int jb, int lane)
+{
+    const int j = jb + lane + 1;
+    const int jn = j < m ? j : (j == m ? 0 : 0);
+    return *reinterpret_cast<const int2 *>(V + 2 * jn);
+}
+
 // Sum over P's edges of cross(a, b) * (fraction of the edge inside Q + delta),
 // plus the exact doubled area of P (shoelace about the origin).
+// Only the 64-edge blocks b0, b0 + bstride, ... of P (a split pair); (0, 1)
+// takes them all.
 template <bool WIDE>
-__device__ void edges_in_other_P(const PairIn &in, int lane, double &sum, int64_t &area2)
+__device__ void edges_in_other_P(const PairIn &in, int lane, double &sum, int64_t &area2, int b0 = 0,
+                                 int bstride = 1)
 {
     using G = Geo<WIDE>;
     sum = 0.0;
     area2 = 0;
-    for (int e = lane; e < in.n; e += 64) {
-        const int f = (e + 1 == in.n) ? 0 : e + 1;
-        const int64_t ax = (int64_t)in.P[2 * e] - in.ox, ay = (int64_t)in.P[2 * e + 1] - in.oy;
+    for (int eb = 64 * b0; eb < in.n; eb += 64 * bstride) {
+        // every lane stays in the loop (the vertex blocks need all of them)
+        const int e = eb + lane;
+        const bool live = e < in.n;
+        const int ei = live ? e : 0;
+        const int f = (ei + 1 == in.n) ? 0 : ei + 1;
+        const int64_t ax = (int64_t)in.P[2 * ei] - in.ox, ay = (int64_t)in.P[2 * ei + 1] - in.oy;
         const int64_t bx = (int64_t)in.P[2 * f] - in.ox, by = (int64_t)in.P[2 * f + 1] - in.oy;
         const __int128 cr = (__int128)ax * by - (__int128)bx * ay;
-        area2 += (int64_t)cr;
-        if (ax == bx && ay == by) continue;
+        if (live) area2 += (int64_t)cr;
         const int64_t ex0 = min(ax, bx) + in.ox, ex1 = max(ax, bx) + in.ox;
         const int64_t ey0 = min(ay, by) + in.oy, ey1 = max(ay, by) + in.oy;
-        if (ex1 < in.qmbr[0] || ex0 > in.qmbr[2] || ey1 < in.qmbr[1] || ey0 > in.qmbr[3]) continue;
+        const bool act = live && !(ax == bx && ay == by) &&
+                         !(ex1 < in.qmbr[0] || ex0 > in.qmbr[2] || ey1 < in.qmbr[1] || ey0 > in.qmbr[3]);
+        if (__ballot(act) == 0) continue;
         const int tbe = tb_shift_point(bx - ax, by - ay);
         const auto Ax = G::conv(ax), Ay = G::conv(ay), Bx = G::conv(bx), By = G::conv(by);
         int64_t cx = (int64_t)in.Q[0] - in.ox, cy = (int64_t)in.Q[1] - in.oy;
@@ -137,9 +156,16 @@ __device__ void edges_in_other_P(const PairIn &in, int lane, double &sum, int64_
         sc = sc ? sc : tbe;
         int w = 0;
         double acc = 0.0;
-        for (int j = 0; j < in.m; j++) {
-            const int jn = (j + 1 == in.m) ? 0 : j + 1;
-            const int64_t dx = (int64_t)in.Q[2 * jn] - in.ox, dy = (int64_t)in.Q[2 * jn + 1] - in.oy;
+        for (int jb = 0; jb < in.m; jb += 64) {
+          const int2 blk = next_vertex_block(in.Q, in.m, jb, lane);
+          const int cnt = min(64, in.m - jb);
+          for (int t = 0; t < cnt; t++) {
+            const int64_t dx = (int64_t)__builtin_amdgcn_readlane(blk.x, t) - in.ox;
+            const int64_t dy = (int64_t)__builtin_amdgcn_readlane(blk.y, t) - in.oy;
+            if (!act) {
+                cx = dx; cy = dy;
+                continue;
+            }
             const auto Dx = G::conv(dx), Dy = G::conv(dy), Cx = G::conv(cx), Cy = G::conv(cy);
             auto od = G::orient(Ax, Ay, Bx, By, Dx, Dy);
             int sd = G::sgn(od);
@@ -159,9 +185,10 @@ __device__ void edges_in_other_P(const PairIn &in, int lane, double &sum, int64_
                 }
             }
             cx = dx; cy = dy; sc = sd;
+          }
         }
         // crossings change Q's winding number by sb; membership = sq * winding
-        sum += i128_to_double(cr) * ((double)w + (double)in.sq * acc);
+        if (act) sum += i128_to_double(cr) * ((double)w + (double)in.sq * acc);
     }
 }
 
@@ -169,21 +196,26 @@ __device__ void edges_in_other_P(const PairIn &in, int lane, double &sum, int64_
 // plus the exact doubled area of Q.
 template <bool WIDE>
 __device__ void edges_in_other_Q(const PairIn &in, const int32_t *pmbr, int lane, double &sum,
-                                 int64_t &area2)
+                                 int64_t &area2, int b0 = 0, int bstride = 1)
 {
     using G = Geo<WIDE>;
     sum = 0.0;
     area2 = 0;
-    for (int f = lane; f < in.m; f += 64) {
-        const int g = (f + 1 == in.m) ? 0 : f + 1;
-        const int64_t cx = (int64_t)in.Q[2 * f] - in.ox, cy = (int64_t)in.Q[2 * f + 1] - in.oy;
+    for (int fb = 64 * b0; fb < in.m; fb += 64 * bstride) {
+        // every lane stays in the loop (the vertex blocks need all of them)
+        const int f = fb + lane;
+        const bool live = f < in.m;
+        const int fi = live ? f : 0;
+        const int g = (fi + 1 == in.m) ? 0 : fi + 1;
+        const int64_t cx = (int64_t)in.Q[2 * fi] - in.ox, cy = (int64_t)in.Q[2 * fi + 1] - in.oy;
         const int64_t dx = (int64_t)in.Q[2 * g] - in.ox, dy = (int64_t)in.Q[2 * g + 1] - in.oy;
         const __int128 cr = (__int128)cx * dy - (__int128)dx * cy;
-        area2 += (int64_t)cr;
-        if (cx == dx && cy == dy) continue;
+        if (live) area2 += (int64_t)cr;
         const int64_t fx0 = min(cx, dx) + in.ox, fx1 = max(cx, dx) + in.ox;
         const int64_t fy0 = min(cy, dy) + in.oy, fy1 = max(cy, dy) + in.oy;
-        if (fx1 < pmbr[0] || fx0 > pmbr[2] || fy1 < pmbr[1] || fy0 > pmbr[3]) continue;
+        const bool act = live && !(cx == dx && cy == dy) &&
+                         !(fx1 < pmbr[0] || fx0 > pmbr[2] || fy1 < pmbr[1] || fy0 > pmbr[3]);
+        if (__ballot(act) == 0) continue;
         const int tbf = tb_shift_edge(dx - cx, dy - cy);
         const auto Cx = G::conv(cx), Cy = G::conv(cy), Dx = G::conv(dx), Dy = G::conv(dy);
         int64_t ax = (int64_t)in.P[0] - in.ox, ay = (int64_t)in.P[1] - in.oy;
@@ -192,9 +224,16 @@ __device__ void edges_in_other_Q(const PairIn &in, const int32_t *pmbr, int lane
         sa = sa ? sa : tbf;
         int w = 0;
         double acc = 0.0;
-        for (int i = 0; i < in.n; i++) {
-            const int in_ = (i + 1 == in.n) ? 0 : i + 1;
-            const int64_t bx = (int64_t)in.P[2 * in_] - in.ox, by = (int64_t)in.P[2 * in_ + 1] - in.oy;
+        for (int ib = 0; ib < in.n; ib += 64) {
+          const int2 blk = next_vertex_block(in.P, in.n, ib, lane);
+          const int cnt = min(64, in.n - ib);
+          for (int t = 0; t < cnt; t++) {
+            const int64_t bx = (int64_t)__builtin_amdgcn_readlane(blk.x, t) - in.ox;
+            const int64_t by = (int64_t)__builtin_amdgcn_readlane(blk.y, t) - in.oy;
+            if (!act) {
+                ax = bx; ay = by;
+                continue;
+            }
             const auto Ax = G::conv(ax), Ay = G::conv(ay), Bx = G::conv(bx), By = G::conv(by);
             auto ob = G::orient(Cx, Cy, Dx, Dy, Bx, By);
             int sb = G::sgn(ob);
@@ -214,8 +253,9 @@ __device__ void edges_in_other_Q(const PairIn &in, const int32_t *pmbr, int lane
                 }
             }
             ax = bx; ay = by; sa = sb;
+          }
         }
-        sum += i128_to_double(cr) * ((double)w + (double)in.sp * acc);
+        if (act) sum += i128_to_double(cr) * ((double)w + (double)in.sp * acc);
     }
 }
 
@@ -736,6 +776,41 @@ __device__ __forceinline__ int anchor_q(const int32_t *qb, const int32_t *pb, co
 }
 
 // One workgroup per query: Q staged once, wavefronts take its candidates.
+// Heavy pairs: a pair on the general form with n m >= kHeavyMin edge pairs
+// would keep one wavefront busy for a long serial run (milliseconds for a few
+// thousand edges a side), so it is deferred: the wavefront records it, and a
+// second launch splits each side's edges into kHeavySlices strided slices,
+// one wavefront each, whose partial sums a third launch adds in a fixed
+// order.  Up to kHeavyCap pairs per call are deferred; the rest run in place.
+constexpr int kHeavySlices = 16;
+constexpr int kHeavyCap = 8192;
+constexpr int64_t kHeavyMin = 1 << 17;
+
+struct HeavyPair {
+    int64_t c;            // candidate slot of the result
+    int64_t pa, qa;       // first vertex of P (data) and of Q (query)
+    int64_t ox, oy;       // local origin of the pair
+    int64_t a2p, a2q;     // exact doubled areas
+    int32_t n, m;
+    int32_t qmbr[4], pm[4];
+    int32_t wide;
+    int32_t pad;
+};
+
+struct HeavyWs {
+    int32_t *count;       // pairs recorded (may exceed kHeavyCap: the excess ran in place)
+    HeavyPair *pairs;     // [kHeavyCap]
+    double *partial;      // [kHeavyCap][2][kHeavySlices]
+};
+
+__device__ __forceinline__ double jaccard_of(double inter2, int64_t a2p, int64_t a2q)
+{
+    const double inter = 0.5 * inter2;
+    const double ap = 0.5 * fabs((double)a2p), aq = 0.5 * fabs((double)a2q);
+    const double u = ap + aq - inter;
+    return u > 0 ? inter / u : 0.0;
+}
+
 __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ dxy,
                                                 const int64_t *__restrict__ doff,
                                                 const int32_t *__restrict__ qxy,
@@ -744,7 +819,7 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                                                 const int32_t *__restrict__ cand_ids,
                                                 double *__restrict__ cand_j,
                                                 unsigned long long *__restrict__ stats,
-                                                int slices)
+                                                int slices, HeavyWs hw)
 {
     __shared__ int2 sQv[kRingLds];
     __shared__ int4 sQbox[kTileCap / 8];
@@ -826,6 +901,8 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
         p_ahead = (c + 2 * nwaves < c1) ? cand_ids[c + 2 * nwaves] : 0;
         const int32_t *Pg = dxy + 2 * pa;
         double J = 0.0;
+        bool deferred = false;
+        int slot = 0;
         const bool valid = n >= 3 && a2q != 0;
         const bool tiled_size = valid && q_tiled && n <= kTileCap;
         RingLds Ps{sPv[wave], sPbox[wave], sPS[wave], nullptr};
@@ -861,6 +938,19 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                                             anchor_q(qmbr, pm, qext), lane,
                                             sList[wave], sUnits[wave], sCross[wave], &st_swept);
                     st_tiled++;
+                } else if (hw.count && (int64_t)n * m >= kHeavyMin &&
+                           (a2p = poly_area2(Pg, n, ox, oy, lane)) != 0 &&
+                           (slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count, 1) : 0)) <
+                               kHeavyCap) {
+                    // split over many wavefronts by the next launches
+                    st_general += 2ull * (unsigned long long)n * (unsigned long long)m;
+                    if (lane == 0) {
+                        HeavyPair &h = hw.pairs[slot];
+                        h.c = c; h.pa = pa; h.qa = qa; h.ox = ox; h.oy = oy; h.a2p = a2p; h.a2q = a2q;
+                        h.n = n; h.m = m; h.wide = wide; h.pad = 0;
+                        for (int i = 0; i < 4; i++) { h.qmbr[i] = qmbr[i]; h.pm[i] = pm[i]; }
+                    }
+                    deferred = true;
                 } else {
                     st_general += 2ull * (unsigned long long)n * (unsigned long long)m;
                     PairIn in;
@@ -879,15 +969,10 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                         inter2 = wave_sum(in.sp * sa) + wave_sum(in.sq * sb);
                     }
                 }
-                if (a2p != 0) {
-                    const double inter = 0.5 * inter2;
-                    const double ap = 0.5 * fabs((double)a2p), aq = 0.5 * fabs((double)a2q);
-                    const double u = ap + aq - inter;
-                    J = u > 0 ? inter / u : 0.0;
-                }
+                if (a2p != 0) J = jaccard_of(inter2, a2p, a2q);
             }
         }
-        if (lane == 0) cand_j[c] = J;
+        if (lane == 0 && !deferred) cand_j[c] = J;
     }
     if (stats && lane == 0) {
         atomicAdd(stats + 0, (unsigned long long)(st_tiled));
@@ -897,14 +982,94 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
     }
 }
 
+// One wavefront per (heavy pair, side, slice): the slice's share of that
+// side's edge sums; slices past the side's last block add nothing.
+__global__ __launch_bounds__(256) void k_heavy(const int32_t *__restrict__ dxy, const int32_t *__restrict__ qxy,
+                                               HeavyWs hw)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t count = min(hw.count[0], kHeavyCap);
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < count * 2 * kHeavySlices;
+         t += nw) {
+        const int64_t h = t / (2 * kHeavySlices);
+        const int side = (int)((t / kHeavySlices) & 1), slice = (int)(t % kHeavySlices);
+        const HeavyPair &e = hw.pairs[h];
+        PairIn in;
+        in.P = dxy + 2 * e.pa; in.n = e.n; in.Q = qxy + 2 * e.qa; in.m = e.m; in.ox = e.ox; in.oy = e.oy;
+        for (int i = 0; i < 4; i++) in.qmbr[i] = e.qmbr[i];
+        in.sq = e.a2q > 0 ? 1 : -1;
+        in.sp = e.a2p > 0 ? 1 : -1;
+        int32_t pm[4] = {e.pm[0], e.pm[1], e.pm[2], e.pm[3]};
+        double s = 0.0;
+        int64_t unused;
+        if (side == 0) {
+            if (e.wide) edges_in_other_P<true>(in, lane, s, unused, slice, kHeavySlices);
+            else edges_in_other_P<false>(in, lane, s, unused, slice, kHeavySlices);
+        } else {
+            if (e.wide) edges_in_other_Q<true>(in, pm, lane, s, unused, slice, kHeavySlices);
+            else edges_in_other_Q<false>(in, pm, lane, s, unused, slice, kHeavySlices);
+        }
+        s = wave_sum(s);
+        if (lane == 0) hw.partial[(h * 2 + side) * kHeavySlices + slice] = s;
+    }
+}
+
+// One wavefront per heavy pair: the slices' sums in a fixed order, then J.
+__global__ __launch_bounds__(256) void k_heavy_finish(HeavyWs hw, double *__restrict__ cand_j)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t count = min(hw.count[0], kHeavyCap);
+    for (int64_t h = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; h < count; h += nw) {
+        const HeavyPair &e = hw.pairs[h];
+        const double sp = e.a2p > 0 ? 1.0 : -1.0, sq = e.a2q > 0 ? 1.0 : -1.0;
+        double vp = 0.0, vq = 0.0;
+        if (lane < kHeavySlices) {
+            vp = hw.partial[(h * 2 + 0) * kHeavySlices + lane];
+            vq = hw.partial[(h * 2 + 1) * kHeavySlices + lane];
+        }
+        const double inter2 = wave_sum(sp * vp) + wave_sum(sq * vq);
+        if (lane == 0) cand_j[e.c] = jaccard_of(inter2, e.a2p, e.a2q);
+    }
+}
+
+HeavyWs carve_heavy(Carve &cv)
+{
+    HeavyWs hw{};
+    hw.count = cv.take<int32_t>(64);
+    hw.pairs = cv.take<HeavyPair>(kHeavyCap);
+    hw.partial = cv.take<double>((size_t)kHeavyCap * 2 * kHeavySlices);
+    return hw;
+}
+
+__global__ void k_zero_count(int32_t *p)
+{
+    if (threadIdx.x == 0) p[0] = 0;
+}
+
 }  // namespace
+
+size_t refine_workspace_bytes()
+{
+    Carve cv{nullptr, 0};
+    carve_heavy(cv);
+    return align_up(cv.used, 256);
+}
 
 polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, hipStream_t s,
-                            unsigned long long *stats)
+                            unsigned long long *stats, void *ws, size_t ws_bytes)
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
+    HeavyWs hw{};
+    if (ws) {
+        Carve cv{static_cast<char *>(ws), ws_bytes};
+        hw = carve_heavy(cv);
+        if (!cv.ok) return set_error(POLYMH_ECAPACITY, "refine: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, hw.count);
+    }
     if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "refine: too many queries");
     // a query's candidates are spread over several workgroups (each stages
     // the query once) when the batch is small or its lists are long: at
@@ -919,8 +1084,15 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
     const int slices = (int)sl;
     hipLaunchKernelGGL(k_refine, dim3((unsigned)(nq * slices)), dim3(64 * kWavesPerBlock), 0, s, data->xy,
                        data->offsets, queries->xy, queries->offsets, cand_off, cand_ids, cand_j, stats,
-                       slices);
-    return check_launch("refine");
+                       slices, hw);
+    polymh_status st = check_launch("refine");
+    if (st || !ws) return st;
+    // deferred heavy pairs: a grid that covers every (pair, side, slice) of a
+    // full list in a few rounds, then the per-pair sums
+    hipLaunchKernelGGL(k_heavy, dim3(2048), dim3(256), 0, s, data->xy, queries->xy, hw);
+    if ((st = check_launch("refine: heavy pairs"))) return st;
+    hipLaunchKernelGGL(k_heavy_finish, dim3(256), dim3(256), 0, s, hw, cand_j);
+    return check_launch("refine: heavy pairs");
 }
 
 }  // namespace polymh

@@ -14,7 +14,10 @@ from . import polymh as pm
 class QueryBatch:
     def __init__(self, D: pm.DevicePolys, sorted_keys, sorted_ent, box, seed: int, k: int, cap: int,
                  bands: int, rows: int, n_queries: int, max_vertices: int, cand_cap: int,
-                 sign_config=None, topk: int = 10):
+                 sign_config=None, topk: int = 10, binned=None):
+        """``binned``: None signs the queries by the walk; a dict with
+        horizon, bin_bits and walk_ratio signs them from binned samples
+        (``polymh_sign_binned``, the same bits)."""
         dev = D.offsets.device
         self.D, self.sk, self.se = D, sorted_keys, sorted_ent
         self.box, self.seed, self.k, self.cap = box, seed, k, cap
@@ -25,7 +28,12 @@ class QueryBatch:
         self.off = torch.zeros(n_queries + 1, dtype=torch.int64, device=dev)
         self.Q = pm.DevicePolys(self.xy, self.off)
         self.sig = torch.empty((n_queries, k), dtype=torch.int32, device=dev)
-        self.ws_sign = torch.empty(pm.sign_workspace_size(n_queries, self.cfg), dtype=torch.uint8, device=dev)
+        self.binned = binned
+        if binned is None:
+            ws = pm.sign_workspace_size(n_queries, self.cfg)
+        else:
+            ws = pm.sign_binned_workspace_size(n_queries, k, cap, binned["horizon"], binned["bin_bits"], self.cfg)
+        self.ws_sign = torch.empty(ws, dtype=torch.uint8, device=dev)
         self.keys = torch.empty((n_queries, bands), dtype=torch.int64, device=dev)
         self.cand_off = torch.empty(n_queries + 1, dtype=torch.int64, device=dev)
         self.cand_ids = torch.empty(cand_cap, dtype=torch.int32, device=dev)
@@ -33,6 +41,7 @@ class QueryBatch:
         self.overflow = torch.zeros(1, dtype=torch.int32, device=dev)
         self.ws_query = torch.empty(int(pm.lib().polymh_query_workspace_size(D.n, n_queries)),
                                     dtype=torch.uint8, device=dev)
+        self.ws_refine = pm.refine_workspace(dev)
         self.top_ids = torch.empty((n_queries, topk), dtype=torch.int32, device=dev)
         self.top_j = torch.empty((n_queries, topk), dtype=torch.float64, device=dev)
         self.stream = torch.cuda.Stream()
@@ -48,13 +57,19 @@ class QueryBatch:
 
     def _issue(self):
         s = torch.cuda.current_stream()
-        pm.sign(self.Q, self.box, self.seed, self.k, self.cap, config=self.cfg, out=self.sig,
-                ws=self.ws_sign, stream=s)
+        if self.binned is None:
+            pm.sign(self.Q, self.box, self.seed, self.k, self.cap, config=self.cfg, out=self.sig,
+                    ws=self.ws_sign, stream=s)
+        else:
+            b = self.binned
+            pm.sign_binned(self.Q, self.box, self.seed, self.k, self.cap, horizon=b["horizon"],
+                           bin_bits=b["bin_bits"], walk_ratio=b.get("walk_ratio", 300.0), config=self.cfg,
+                           out=self.sig, ws=self.ws_sign, stream=s)
         pm.band(self.sig, self.bands, self.rows, self.seed, out=self.keys, stream=s)
         pm.query_capped(self.sk, self.se, self.D.n, self.keys, self.cand_off, self.cand_ids,
                         self.overflow, self.ws_query, stream=s)
         pm.refine(self.D, self.Q, self.cand_off, self.cand_ids, out=self.cand_j, stream=s,
-                  n_cand=self.cand_ids.numel())
+                  n_cand=self.cand_ids.numel(), ws=self.ws_refine)
         pm.topk(self.cand_off, self.cand_ids, self.cand_j, self.topk, stream=s,
                 out=(self.top_ids, self.top_j))
 

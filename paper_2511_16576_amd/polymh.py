@@ -73,6 +73,8 @@ _SIGNATURES = {
     "polymh_query": (I32, [P, P, I64, I64, P, I64, I32, P, SZ, P, P, I64, P]),
     "polymh_refine": (I32, [P, P, P, P, I64, I64, P, P]),
     "polymh_refine_stats": (I32, [P, P, P, P, I64, I64, P, P, P]),
+    "polymh_refine_workspace_size": (SZ, []),
+    "polymh_refine_ws": (I32, [P, P, P, P, I64, I64, P, P, P, SZ, P]),
     "polymh_query_capped": (I32, [P, P, I64, I64, P, I64, I32, P, SZ, P, P, I64, P, P]),
     "polymh_graph_begin": (I32, [P]),
     "polymh_graph_end": (I32, [P, P]),
@@ -412,30 +414,51 @@ def query(sorted_keys: torch.Tensor, sorted_ids: torch.Tensor, n_data: int, qkey
     return off, ids[:total]
 
 
+def refine_workspace(device="cuda") -> torch.Tensor:
+    """A workspace for ``refine`` (heavy pairs split over many wavefronts)."""
+    return _workspace(int(lib().polymh_refine_workspace_size()), device)
+
+
 def refine(data: DevicePolys, queries: DevicePolys, cand_off: torch.Tensor, cand_ids: torch.Tensor,
-           out: torch.Tensor | None = None, stream=None, n_cand: int | None = None) -> torch.Tensor:
+           out: torch.Tensor | None = None, stream=None, n_cand: int | None = None,
+           ws: torch.Tensor | None = None, split_heavy: bool = True) -> torch.Tensor:
     """Exact Jaccard per candidate: float64 [C] (C = n_cand, default the
-    length of cand_ids; ranges come from cand_off on the device)."""
+    length of cand_ids; ranges come from cand_off on the device).  With
+    ``split_heavy`` (``polymh_refine_ws``) very large pairs are spread over
+    many wavefronts; ``ws`` defaults to a fresh workspace."""
     check_device()
     nq = queries.n
     c = cand_ids.numel() if n_cand is None else n_cand
     if out is None:
         out = torch.empty(max(c, 1), dtype=torch.float64, device=cand_ids.device)
     dp, qp = data.cstruct(), queries.cstruct()
-    _check(lib().polymh_refine(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
-                               nq, c, _ptr(out), _stream(stream)))
+    if not split_heavy:
+        _check(lib().polymh_refine(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                   nq, c, _ptr(out), _stream(stream)))
+        return out[:c]
+    if ws is None:
+        ws = refine_workspace(cand_ids.device)
+    _check(lib().polymh_refine_ws(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                  nq, c, _ptr(out), None, _ptr(ws), ws.numel(), _stream(stream)))
     return out[:c]
 
 
-def refine_stats(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, stream=None):
+def refine_stats(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, stream=None,
+                 split_heavy: bool = True):
     """(J float64 [C], work counts: tiled pairs, edge pairs swept by the tiled form,
     general edge pairs, disjoint pairs)."""
     c = cand_ids.numel()
     out = torch.empty(max(c, 1), dtype=torch.float64, device=cand_ids.device)
     stats = torch.zeros(4, dtype=torch.int64, device=cand_ids.device)
     dp, qp = data.cstruct(), queries.cstruct()
-    _check(lib().polymh_refine_stats(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
-                                     queries.n, c, _ptr(out), _ptr(stats), _stream(stream)))
+    if split_heavy:
+        ws = refine_workspace(cand_ids.device)
+        _check(lib().polymh_refine_ws(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                      queries.n, c, _ptr(out), _ptr(stats), _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+    else:
+        _check(lib().polymh_refine_stats(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                         queries.n, c, _ptr(out), _ptr(stats), _stream(stream)))
     return out[:c], [int(v) for v in stats.cpu().tolist()]
 
 

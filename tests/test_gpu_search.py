@@ -218,3 +218,39 @@ def test_refine_large_polygons_general_path(pm, orc):
     got = _refine(pm, data, queries, off, ids)
     want = orc.jaccard_candidates(data, queries, off, ids)
     assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
+
+
+def test_refine_heavy_pairs_split(pm, orc):
+    # pairs with n m >= 2^17 edge pairs are split over many wavefronts: the
+    # values equal the oracle's and the in-place form's, and the work counts
+    # are the same
+    import torch
+    rng = np.random.default_rng(8)
+    data = dg.star_polygons(rng, [600, 1500, 40, 2000, 3000], [[50000, 50000]] * 5, [40000.0] * 5)
+    queries = dg.star_polygons(rng, [1200, 30, 900, 2500], [[52000, 49000]] * 4, [38000.0] * 4)
+    D, Q = pm.to_device(data), pm.to_device(queries)
+    off = torch.tensor([0, 5, 10, 15, 20], dtype=torch.int64, device="cuda")
+    ids = torch.arange(5, dtype=torch.int32, device="cuda").repeat(4)
+    split, st_split = pm.refine_stats(D, Q, off, ids)
+    inplace, st_inplace = pm.refine_stats(D, Q, off, ids, split_heavy=False)
+    want = orc.jaccard_candidates(data, queries, off.cpu().numpy(), ids.cpu().numpy())
+    got = split.cpu().numpy()
+    assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
+    assert np.all(np.abs(got - inplace.cpu().numpy()) <= 1e-12 + 1e-12 * np.abs(want))
+    assert st_split == st_inplace
+
+
+def test_refine_more_heavy_pairs_than_the_split_list(pm):
+    # 8,400 heavy pairs (400 x 400 edges): the first 8,192 are split, the
+    # rest run in place; every value equals the in-place form's
+    import torch
+    rng = np.random.default_rng(9)
+    data = dg.star_polygons(rng, [400] * 120, [[50000 + 50 * i, 50000] for i in range(120)], [30000.0] * 120)
+    queries = dg.star_polygons(rng, [400] * 70, [[51000, 49000 + 30 * i] for i in range(70)], [30000.0] * 70)
+    D, Q = pm.to_device(data), pm.to_device(queries)
+    off = torch.arange(71, dtype=torch.int64, device="cuda") * 120
+    ids = torch.arange(120, dtype=torch.int32, device="cuda").repeat(70)
+    split = pm.refine(D, Q, off, ids).cpu().numpy()
+    inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy()
+    assert (inplace > 0.2).all()
+    assert np.all(np.abs(split - inplace) <= 1e-12 + 1e-12 * np.abs(inplace))
