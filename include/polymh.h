@@ -284,7 +284,7 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
  * with a workspace of polymh_refine_workspace_size() bytes (device,
  * caller-owned, contents overwritten).  With it, pairs on the general form
  * with n m >= 2^17 edge pairs (polygons beyond 512 edges) are not computed by
- * one wavefront but split over 32 wavefronts by two further launches, so a
+ * one wavefront but split over 128 wavefronts by two further launches, so a
  * few very large pairs no longer set the call's duration; the values are
  * those of polymh_refine up to the order of floating-point additions.  Up to
  * 8192 such pairs per call are split (the rest run in place).  ws NULL is

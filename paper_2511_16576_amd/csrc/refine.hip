@@ -782,7 +782,7 @@ __device__ __forceinline__ int anchor_q(const int32_t *qb, const int32_t *pb, co
 // second launch splits each side's edges into kHeavySlices strided slices,
 // one wavefront each, whose partial sums a third launch adds in a fixed
 // order.  Up to kHeavyCap pairs per call are deferred; the rest run in place.
-constexpr int kHeavySlices = 16;
+constexpr int kHeavySlices = 64;
 constexpr int kHeavyCap = 8192;
 constexpr int64_t kHeavyMin = 1 << 17;
 
