@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-binned", action="store_true", help="skip the binned-signing comparison")
     ap.add_argument("--no-rings", action="store_true", help="skip the holes / multipolygon measurement")
+    ap.add_argument("--cfg5-queries", type=int, default=10_000,
+                    help="workload-5 queries per captured-graph batch (0: skip the workload-5 query pipeline)")
     ap.add_argument("--binned-cfg5", type=int, default=4_000_000,
                     help="polygons of workload 5 for the binned-signing comparison (4,000,000: all; 0: skip)")
     ap.add_argument("--batch-queries", type=int, default=1000)
@@ -67,6 +69,70 @@ def parse():
     ap.add_argument("--train-pairs", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=3)
     return ap.parse_args()
+
+
+def cfg5_pipeline(w5, D5, sig5, par5, cfg, dev):
+    """Workload 5's query side: 32 x 8 bucket table over the 4,000,000
+    signatures, then all queries as one batch through the preallocated
+    pipeline (queries signed from binned samples, band, capped lookup,
+    refine, top-10), issued eagerly or replayed as a captured HIP graph;
+    the same batch with walked query signatures; recall@10 of 200 sampled
+    queries against brute force (MBR-prefiltered exact J)."""
+    import torch
+    from paper_2511_16576_amd import metrics
+    from paper_2511_16576_amd import polymh as pm
+    from paper_2511_16576_amd.pipeline import QueryBatch
+    b5, r5 = 32, 8
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st = torch.cuda.current_stream()
+    e0.record(st)
+    keys = pm.band(sig5, b5, r5, w5.seed)
+    sk, se = pm.index_build(keys)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_index = e0.elapsed_time(e1)
+    del keys
+    Qh = w5.queries
+    nq = Qh.n
+    Qd = pm.to_device(Qh)
+    qs = pm.sign_binned(Qd, w5.box, w5.seed, w5.k, w5.cap, horizon=par5["horizon"], bin_bits=par5["bin_bits"])
+    off, _ = pm.query(sk, se, D5.n, pm.band(qs, b5, r5, w5.seed))
+    n_cand = int(off[-1].item())
+    out = {"queries": nq, "bands": b5, "rows": r5, "index_ms": t_index, "candidates_per_query": n_cand / nq}
+    for name, bparams in (("binned", par5), ("walk", None)):
+        qb = QueryBatch(D5, sk, se, w5.box, w5.seed, w5.k, w5.cap, b5, r5, nq, Qh.xy.shape[0],
+                        int(1.25 * n_cand) + 65536, sign_config=cfg, binned=bparams)
+        qb.load(Qh)
+        qb.capture()
+        res = {}
+        for mode in ("eager", "graph"):
+            (qb.run_graph if mode == "graph" else qb.run_eager)()
+            qb.result()
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                (qb.run_graph if mode == "graph" else qb.run_eager)()
+                qb.stream.synchronize()
+                ts.append(time.perf_counter() - t0)
+                qb.result()          # raises if the candidate capacity overflowed
+            t = float(np.median(ts))
+            res[mode] = {"ms_per_batch": 1e3 * t, "queries_per_s": nq / t}
+        out[name] = res
+        if name == "binned":
+            ti, tj = (x.cpu().numpy() for x in qb.result())
+        log(f"workload-5 queries ({name} query signing): eager {res['eager']['ms_per_batch']:.1f} ms, "
+            f"graph {res['graph']['ms_per_batch']:.1f} ms per {nq}-query batch")
+        del qb
+    sample = np.sort(np.random.default_rng(5).choice(nq, min(200, nq), replace=False))
+    bi, bj = metrics.brute_force_topk_mbr(D5, pm.to_device(Qh.subset(sample)), 10)
+    out["recall_at_10"] = metrics.recall_at_k(ti[sample], tj[sample], bi, bj, 10)
+    out["recall_sample"] = int(sample.size)
+    # share of all queries whose top-10 holds the polygon they were jittered from
+    out["source_in_top10"] = float((ti == w5.query_source[:, None]).any(axis=1).mean())
+    log(f"workload-5 recall@10 over {sample.size} queries: {out['recall_at_10']:.3f}; "
+        f"source polygon in the top-10 for {out['source_in_top10']:.3f} of the queries")
+    return out
 
 
 def main():
@@ -229,7 +295,7 @@ def main():
                                 "binned_sig_per_s": D.n * k / t_b2, "params": par2}}
         log(f"binned signing, workload 2: {1e3 * t_b2:.3f} ms")
     if binned is not None and args.binned_cfg5 > 0:
-        w5 = dg.workload(5, n=args.binned_cfg5, n_queries=0)
+        w5 = dg.workload(5, n=args.binned_cfg5, n_queries=args.cfg5_queries)
         D5 = pm.to_device(w5.data)
         sig5 = torch.empty((D5.n, w5.k), dtype=torch.int32, device=dev)
         ws5 = torch.empty(pm.sign_workspace_size(D5.n, cfg), dtype=torch.uint8, device=dev)
@@ -248,7 +314,10 @@ def main():
             "walk_sig_per_s": D5.n * w5.k / t_w5, "binned_sig_per_s": D5.n * w5.k / t_b5,
             "speedup": t_w5 / t_b5, "params": par5}
         log(f"binned signing, workload 5 ({D5.n} polygons): walk {1e3 * t_w5:.1f} ms, binned {1e3 * t_b5:.1f} ms")
-        del sig_b5, sig5, D5
+        del sig5
+        if args.cfg5_queries > 0:
+            binned["workload5"]["pipeline"] = cfg5_pipeline(w5, D5, sig_b5, par5, cfg, dev)
+        del sig_b5, D5
 
     # polygons with holes and multipolygons: 100,000 shapes of workload 2's
     # sizes (0-2 holes per component, a quarter with two components) joined
