@@ -797,10 +797,13 @@ struct HeavyPair {
     int32_t pad;
 };
 
+constexpr int kStatSlots = 64;   // work counters spread over slots, folded at the end
+
 struct HeavyWs {
     int32_t *count;       // pairs recorded (may exceed kHeavyCap: the excess ran in place)
     HeavyPair *pairs;     // [kHeavyCap]
     double *partial;      // [kHeavyCap][2][kHeavySlices]
+    unsigned long long *stat_slots;   // [kStatSlots][4]
 };
 
 __device__ __forceinline__ double jaccard_of(double inter2, int64_t a2p, int64_t a2q)
@@ -974,11 +977,24 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
         }
         if (lane == 0 && !deferred) cand_j[c] = J;
     }
-    if (stats && lane == 0) {
-        atomicAdd(stats + 0, (unsigned long long)(st_tiled));
-        atomicAdd(stats + 1, st_swept);
-        atomicAdd(stats + 2, st_general);
-        atomicAdd(stats + 3, st_disjoint);
+    if (stats) {
+        // one sum per workgroup, added to one of kStatSlots slots when the
+        // workspace has them (atomics of every wavefront on four words
+        // serialise at the cache), nonzero counts only
+        __shared__ unsigned long long sStat[kWavesPerBlock][4];
+        if (lane == 0) {
+            sStat[wave][0] = st_tiled; sStat[wave][1] = st_swept;
+            sStat[wave][2] = st_general; sStat[wave][3] = st_disjoint;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            unsigned long long v = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); w++) v += sStat[w][tid];
+            if (v) {
+                if (hw.stat_slots) atomicAdd(hw.stat_slots + (blockIdx.x % kStatSlots) * 4 + tid, v);
+                else atomicAdd(stats + tid, v);
+            }
+        }
     }
 }
 
@@ -1040,12 +1056,26 @@ HeavyWs carve_heavy(Carve &cv)
     hw.count = cv.take<int32_t>(64);
     hw.pairs = cv.take<HeavyPair>(kHeavyCap);
     hw.partial = cv.take<double>((size_t)kHeavyCap * 2 * kHeavySlices);
+    hw.stat_slots = cv.take<unsigned long long>(kStatSlots * 4);
     return hw;
 }
 
-__global__ void k_zero_count(int32_t *p)
+// Clears the pair count and the counter slots (256 threads).
+__global__ void k_zero_count(int32_t *p, unsigned long long *slots)
 {
     if (threadIdx.x == 0) p[0] = 0;
+    if (threadIdx.x < kStatSlots * 4) slots[threadIdx.x] = 0;
+}
+
+// Adds the counter slots to the caller's four counters (one wavefront).
+__global__ void k_fold_stats(const unsigned long long *slots, unsigned long long *stats)
+{
+    const int i = threadIdx.x;
+    if (i < 4) {
+        unsigned long long v = 0;
+        for (int s = 0; s < kStatSlots; s++) v += slots[s * 4 + i];
+        if (v) atomicAdd(stats + i, v);
+    }
 }
 
 }  // namespace
@@ -1068,7 +1098,7 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
         Carve cv{static_cast<char *>(ws), ws_bytes};
         hw = carve_heavy(cv);
         if (!cv.ok) return set_error(POLYMH_ECAPACITY, "refine: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
-        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, hw.count);
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(kStatSlots * 4), 0, s, hw.count, hw.stat_slots);
     }
     if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "refine: too many queries");
     // a query's candidates are spread over several workgroups (each stages
@@ -1092,7 +1122,10 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
     hipLaunchKernelGGL(k_heavy, dim3(2048), dim3(256), 0, s, data->xy, queries->xy, hw);
     if ((st = check_launch("refine: heavy pairs"))) return st;
     hipLaunchKernelGGL(k_heavy_finish, dim3(256), dim3(256), 0, s, hw, cand_j);
-    return check_launch("refine: heavy pairs");
+    if ((st = check_launch("refine: heavy pairs"))) return st;
+    if (!stats) return POLYMH_OK;
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(64), 0, s, hw.stat_slots, stats);
+    return check_launch("refine: counters");
 }
 
 }  // namespace polymh
