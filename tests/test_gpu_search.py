@@ -254,3 +254,23 @@ def test_refine_more_heavy_pairs_than_the_split_list(pm):
     inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy()
     assert (inplace > 0.2).all()
     assert np.all(np.abs(split - inplace) <= 1e-12 + 1e-12 * np.abs(inplace))
+
+
+def test_refine_heavy_pairs_wide_coordinates(pm, orc):
+    # large pairs whose coordinate span needs the 128-bit orientation form,
+    # split over wavefronts like the others
+    import torch
+    rng = np.random.default_rng(10)
+    big = float(1 << 27)
+    data = dg.star_polygons(rng, [700, 900], [[0, 0], [1 << 20, 0]], [big, big])
+    queries = dg.star_polygons(rng, [800, 650], [[1 << 19, 1 << 19], [0, 1 << 21]], [big, big])
+    D, Q = pm.to_device(data), pm.to_device(queries)
+    off = torch.tensor([0, 2, 4], dtype=torch.int64, device="cuda")
+    ids = torch.tensor([0, 1, 0, 1], dtype=torch.int32, device="cuda")
+    got, st = pm.refine_stats(D, Q, off, ids)
+    want = orc.jaccard_candidates(data, queries, off.cpu().numpy(), ids.cpu().numpy())
+    got = got.cpu().numpy()
+    assert st[2] > 0 and (want > 0.3).all()
+    assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
+    inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy()
+    assert np.all(np.abs(got - inplace) <= 1e-12 + 1e-12 * np.abs(want))
