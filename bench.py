@@ -138,8 +138,8 @@ def cfg5_pipeline(w5, D5, sig5, par5, cfg, dev):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the signing path has no multi-GPU form in this "
-              "build (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the signing path has no multi-GPU form; a shard "
+              "of a larger index is measured as one GPU's share", file=sys.stderr)
         sys.exit(2)
     import torch
 

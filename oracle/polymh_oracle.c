@@ -3,7 +3,7 @@
  *
  * A plain, slow, obviously-correct C implementation of what the signing path
  * computes, used by the test suite, the smoke check and the CPU baseline of
- * the benchmark to judge the GPU library.  It shares no code, header, table
+ * the benchmark to check the GPU library.  It shares no code, header, table
  * or helper with the GPU library and must never be linked into it.
  *
  * Paper: "PolyMinHash: Efficient Area-Based MinHashing of Polygons for
