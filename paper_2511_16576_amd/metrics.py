@@ -62,8 +62,8 @@ def brute_force_topk_mbr(D, Q, k: int, chunk: int = 16):
             free = np.flatnonzero(row < 0)
             if free.size:
                 taken = set(int(x) for x in row if x >= 0)
-                fill = [i for i in range(k + len(taken)) if i not in taken][:free.size]
-                row[free] = fill
+                fill = [i for i in range(min(D.n, k + len(taken))) if i not in taken][:free.size]
+                row[free[:len(fill)]] = fill          # fewer than k polygons: -1 pads the rest
                 j_out[q_, free] = 0.0
     return ids_out, j_out
 
