@@ -85,3 +85,24 @@ def test_collision_rate_is_lattice_jaccard(orc):
     s = orr.sign_rings(rs, (0, 0, 15, 15), 1, 2000, 1 << 12)
     rate = float((s[0] == s[1]).mean())
     assert abs(rate - 0.84) < 4 * np.sqrt(0.84 * 0.16 / 2000)
+
+
+def test_ring_generator_shapes(orc):
+    # the generator's shapes meet the ring format's conditions: filled rings
+    # counter-clockwise, holes clockwise and strictly inside exactly one
+    # filled ring of their shape, components apart
+    rng = np.random.default_rng(12)
+    rs = dg.ring_polygons(rng, 60, 18, lambda r, m: r.integers(6, 30, m), 0.03, 0.1)
+    assert rs.n == 60 and rs.poly_rings[-1] == rs.ring_offsets.shape[0] - 1
+    for p in range(rs.n):
+        rings = rs.rings(p)
+        filled = [r for r in rings if orc.area2(r) > 0]
+        holes = [r for r in rings if orc.area2(r) < 0]
+        assert 1 <= len(filled) <= 2 and len(filled) + len(holes) == len(rings)
+        for h in holes:
+            inside = [bool(orc.inside_points(f, h).all()) for f in filled]
+            assert sum(inside) == 1
+        if len(filled) == 2:
+            a, b = filled
+            assert a[:, 0].max() < b[:, 0].min() or b[:, 0].max() < a[:, 0].min()
+        assert orr.area2_rings(rings) > 0
