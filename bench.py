@@ -274,17 +274,18 @@ def main():
     # is about 20 times larger
     def time_binned(polys, box, seed, k_, cap_, reps):
         h, bb = pm.binned_params(polys, box, k_, cap_)
-        need = pm.sign_binned_workspace_size(polys.n, k_, cap_, h, bb)
+        cfgb = pm.binned_config(polys)
+        need = pm.sign_binned_workspace_size(polys.n, k_, cap_, h, bb, cfgb)
         wsb = torch.empty(need, dtype=torch.uint8, device=dev)
         outb = torch.empty((polys.n, k_), dtype=torch.int32, device=dev)
-        pm.sign_binned(polys, box, seed, k_, cap_, horizon=h, bin_bits=bb, out=outb, ws=wsb)
+        pm.sign_binned(polys, box, seed, k_, cap_, horizon=h, bin_bits=bb, config=cfgb, out=outb, ws=wsb)
         e0.record(stream)
         for _ in range(reps):
-            pm.sign_binned(polys, box, seed, k_, cap_, horizon=h, bin_bits=bb, out=outb, ws=wsb)
+            pm.sign_binned(polys, box, seed, k_, cap_, horizon=h, bin_bits=bb, config=cfgb, out=outb, ws=wsb)
         e1.record(stream)
         torch.cuda.synchronize()
         return outb, e0.elapsed_time(e1) / reps / 1e3, {"horizon": h, "bin_bits": bb, "walk_ratio": 300.0,
-                                                         "workspace_bytes": need}
+                                                         "lds_edges": cfgb.lds_edges, "workspace_bytes": need}
     binned = None
     if not args.no_binned:
         sig_b, t_b2, par2 = time_binned(D, w.box, w.seed, k, cap, 3)

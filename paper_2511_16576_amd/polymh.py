@@ -330,6 +330,19 @@ def binned_params(polys: DevicePolys, box, k: int, cap: int, walk_ratio: float =
     return horizon, bits
 
 
+def binned_config(polys: DevicePolys) -> SignConfig:
+    """Launch shape for sign_binned: the default with an LDS edge cache just
+    large enough for the set's largest polygon (64..1024 edges; larger
+    polygons stream their edges), so more lookup workgroups share a CU.
+    Synchronises once."""
+    cnt = polys.offsets[1:] - polys.offsets[:-1]
+    vmax = int(cnt.max().item()) if cnt.numel() else 0
+    lds = 64
+    while lds < min(vmax, 1024):
+        lds *= 2
+    return sign_config(lds_edges=lds)
+
+
 def sign_binned_workspace_size(n: int, k: int, cap: int, horizon: int, bin_bits: int,
                                config: SignConfig | None = None) -> int:
     return int(lib().polymh_sign_binned_workspace_size(n, k, cap, horizon, bin_bits,
