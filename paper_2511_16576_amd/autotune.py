@@ -21,7 +21,7 @@ DEFAULT_SPACE = {
     "persistent": [1, 0],
     "block_threads": [64, 128, 256],
     "hash_block": [0, 32],
-    "lds_edges": [256, 1024],
+    "lds_edges": [256, 512, 1024],
     "samples_per_lane": [1, 2],
     "blocks_per_cu": [8, 16],
 }
