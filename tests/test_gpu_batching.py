@@ -84,3 +84,59 @@ def test_autotuner_choice_is_bit_identical(pm, tmp_path, monkeypatch):
     assert torch.equal(a, b)
     cfg2, rep2 = autotune.tune_sign(w.data, w.box, w.seed, 64, w.cap, sample=3000, reps=1, space=space)
     assert rep2 == rep and cfg2.as_dict() == cfg.as_dict()   # served from the cache
+
+
+def test_graph_replays_binned_signing_and_split_pairs(pm, orc):
+    # the batch pipeline with binned query signing, over polygons large
+    # enough that refinement splits pairs over wavefronts: graph replays and
+    # eager runs equal the plain calls (walked signatures, refinement), and
+    # the batch's top-10 equals the oracle's for one batch
+    import torch
+    from paper_2511_16576_amd.pipeline import QueryBatch
+    rng = np.random.default_rng(17)
+    w = dg.workload(5, n=2500, n_queries=0)
+    big = np.argsort(-w.data.counts())[:20]
+    src = np.concatenate([big, rng.choice(w.data.n, 20, replace=False)])
+    queries = dg.jittered(rng, w.data, src, 0.02, w.grid_bits)
+    k, cap, bands, rows = 32, 1 << 22, 8, 4
+    D = pm.to_device(w.data)
+    sig = pm.sign(D, w.box, w.seed, k, cap)
+    sk, se = pm.index_build(pm.band(sig, bands, rows, w.seed))
+    h, b = pm.binned_params(D, w.box, k, cap)
+    nb = 20
+    batches = [queries.subset(np.arange(i, i + nb)) for i in range(0, 40, nb)]
+    maxv = max(x.xy.shape[0] for x in batches)
+    qb = QueryBatch(D, sk, se, w.box, w.seed, k, cap, bands, rows, nb, maxv, cand_cap=nb * 2500,
+                    binned={"horizon": h, "bin_bits": b, "walk_ratio": 300.0})
+    qb.load(batches[0])
+    qb.capture()
+    split_seen = 0
+    for rep in range(2):
+        for x in batches:
+            Q = pm.to_device(x)
+            qk = pm.band(pm.sign(Q, w.box, w.seed, k, cap), bands, rows, w.seed)
+            off, ids = pm.query(sk, se, D.n, qk)
+            J, st = pm.refine_stats(D, Q, off, ids)
+            split_seen += st[2]
+            ti, tj = pm.topk(off, ids, J, 10)
+            qb.load(x)
+            torch.cuda.synchronize()
+            qb.run_graph()
+            gi, gj = qb.result()
+            assert torch.equal(gi, ti) and torch.equal(gj, tj)
+            qb.run_eager()
+            ei, ej = qb.result()
+            assert torch.equal(ei, ti) and torch.equal(ej, tj)
+    assert split_seen > 0
+    # the oracle's top-10 of the first batch over the same candidates
+    x = batches[0]
+    oq = orc.band(orc.sign(x, w.box, w.seed, k, cap), bands, rows, w.seed)
+    od = orc.band(orc.sign(w.data, w.box, w.seed, k, cap), bands, rows, w.seed)
+    ooff, oids = orc.candidates(od, oq)
+    wj = orc.jaccard_candidates(w.data, x, ooff, oids)
+    wi, wjt = orc.topk(ooff, oids, wj, 10)
+    qb.load(x)
+    torch.cuda.synchronize()
+    qb.run_graph()
+    gi, gj = (t.cpu().numpy() for t in qb.result())
+    assert np.allclose(gj, wjt, rtol=1e-9, atol=1e-12)
