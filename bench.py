@@ -428,6 +428,10 @@ def main():
     nqv = (Q.offsets[1:] - Q.offsets[:-1]).double()
     qrow = torch.repeat_interleave(torch.arange(Q.n, device=dev), off[1:] - off[:-1])
     roof_ref["edge_pairs_all"] = float((nd[ids.long()] * nqv[qrow]).sum())
+    # the same launch counted as a test of every n x m edge pair (the unit of
+    # a plain pairwise refinement): above 1 where culling, not issue rate,
+    # carries the speed
+    roof_ref["frac_if_every_pair_tested"] = roof_ref["edge_pairs_all"] * C_PAIR / t_ref / PEAK_VALU
     # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE runs,
     # only while the kernel's sources are the ones the counters were taken on
     from paper_2511_16576_amd import profiling
