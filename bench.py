@@ -516,6 +516,23 @@ def main():
                "sample": f"oracle Alg. 1 signing of {ids_s.size} workload-2 polygons x {k} hashes "
                          f"({tc:.1f} s wall on {th} threads, ~{tc * th:.0f} core-seconds; OpenMP over polygons)"}
         log(f"cpu oracle: {cpu['value']:.3g} sig/s on {th} threads")
+        # context: one thread on a slice of the same set, and seeded subsets
+        # of workloads 3 and 5 on all threads (their rates per (polygon, hash)
+        # stand for the full sets: extrapolated)
+        ids_1 = np.arange(min(D.n, 6_250))
+        t2 = time.perf_counter()
+        oracle.sign(w.data.subset(ids_1), w.box, w.seed, k, cap, threads=1)
+        cpu["single_thread_sig_per_s"] = ids_1.size * k / (time.perf_counter() - t2)
+        for cfg_id, n_sub in ((3, 10_000), (5, 2_000)):
+            ws_ = dg.workload(cfg_id, n=n_sub, n_queries=0)
+            t2 = time.perf_counter()
+            oracle.sign(ws_.data, ws_.box, ws_.seed, ws_.k, ws_.cap, threads=th)
+            cpu[f"workload{cfg_id}_subset_sig_per_s"] = n_sub * ws_.k / (time.perf_counter() - t2)
+        cpu["context"] = ("single thread: 6,250 workload-2 polygons; workloads 3 and 5: seeded subsets of "
+                          "10,000 and 2,000 polygons at their k and cap, all threads, rates extrapolated "
+                          "per (polygon, hash)")
+        log(f"cpu oracle: one thread {cpu['single_thread_sig_per_s']:.3g} sig/s; workload 3 subset "
+            f"{cpu['workload3_subset_sig_per_s']:.3g}, workload 5 subset {cpu['workload5_subset_sig_per_s']:.3g} sig/s")
 
     total_sigs = (D.n + Q.n) * k
     line = {
