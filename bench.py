@@ -257,17 +257,31 @@ def main():
     # centring (Sec. 3.1) of the dataset: not part of the workload's step (its
     # polygons are placed in a fixed domain), timed on its own; HBM-bound:
     # algorithmic bytes = 8 read + 8 written per vertex, offsets and shift
-    # (8 + 8) per polygon
-    pm.centre(D)
+    # (8 + 8) per polygon.  The launch alone into preallocated buffers (the
+    # binding's range-flag read stays out of the timed region).
+    import ctypes
+    Cd, _ = pm.centre(D)               # checks the range flag once
+    c_shift = torch.empty((D.n, 2), dtype=torch.int32, device=dev)
+    c_flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    dps = D.cstruct()
+
+    def centre_launch():
+        st_ = pm.lib().polymh_centre(ctypes.byref(dps), Cd.xy.data_ptr(), c_shift.data_ptr(), c_flag.data_ptr(),
+                                     stream.cuda_stream)
+        if st_ != 0:
+            raise RuntimeError(pm.lib().polymh_last_error().decode())
+    centre_launch()
     e0.record(stream)
-    for _ in range(3):
-        Cd, _ = pm.centre(D)
+    for _ in range(5):
+        centre_launch()
     e1.record(stream)
     torch.cuda.synchronize()
-    t_centre = e0.elapsed_time(e1) / 3 / 1e3
+    t_centre = e0.elapsed_time(e1) / 5 / 1e3
+    if int(c_flag.item()):
+        raise RuntimeError("centring flagged workload 2's polygons")
     nvert = int(D.xy.shape[0])
     centre_bytes = 16.0 * nvert + 16.0 * D.n
-    del Cd
+    del Cd, c_shift, c_flag
 
     # shared-sample binned signing of the same dataset (bit-equal to the walk),
     # and of workload 5 (all 4,000,000 polygons by default), where N_B / N_P

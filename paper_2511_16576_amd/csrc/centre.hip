@@ -14,9 +14,8 @@ namespace {
 
 using i128 = __int128;
 
-// Wavefront sum of a 128-bit integer over DPP row operations (the
-// reduction order of wave_sum_i64: quads, rows, row broadcasts), carried as
-// two 64-bit halves; lane 63's total is returned to every lane.
+// One DPP step of a 128-bit sum carried as two 64-bit halves: add the value
+// the DPP control brings from another lane, with the carry between halves.
 template <int CTRL, int ROWS = 0xf>
 __device__ __forceinline__ void dpp_add128(uint64_t &lo, uint64_t &hi)
 {
@@ -26,17 +25,15 @@ __device__ __forceinline__ void dpp_add128(uint64_t &lo, uint64_t &hi)
     lo = nl;
 }
 
-__device__ __forceinline__ i128 wave_sum_i128(i128 v)
+// Sum over one 16-lane DPP row (quads, then rotations by 4 and 8 within the
+// row): every lane of the row receives the row's total.
+__device__ __forceinline__ i128 row_sum_i128(i128 v)
 {
     uint64_t lo = (uint64_t)v, hi = (uint64_t)((unsigned __int128)v >> 64);
     dpp_add128<dpp::kQuad1032>(lo, hi);
     dpp_add128<dpp::kQuad2301>(lo, hi);
     dpp_add128<dpp::kRowRor4>(lo, hi);
     dpp_add128<dpp::kRowRor8>(lo, hi);
-    dpp_add128<dpp::kRowBcast15, 0xa>(lo, hi);
-    dpp_add128<dpp::kRowBcast31, 0xc>(lo, hi);
-    lo = dpp::readlane64(lo, 63);
-    hi = dpp::readlane64(hi, 63);
     return (i128)(((unsigned __int128)hi << 64) | lo);
 }
 
@@ -63,23 +60,26 @@ __device__ __forceinline__ int64_t floor_div_small(i128 num, i128 den)
     return q;
 }
 
-// One wavefront per polygon (every lane takes part in the reductions).
+// One 16-lane DPP row per polygon, four polygons per wavefront: the fan
+// sums are row reductions of four DPP steps, and each row divides for its own
+// polygon (a whole row is active or not, so the row operations only ever read
+// lanes of the same polygon).
 __global__ __launch_bounds__(256) void k_centre(const int32_t *__restrict__ xy,
                                                 const int64_t *__restrict__ off, int64_t n,
                                                 int32_t *__restrict__ out, int32_t *__restrict__ shift,
                                                 int32_t *__restrict__ range_flag)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; p < n; p += nwaves) {
+    const int rl = threadIdx.x & 15;
+    const int64_t nrows = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; p < n; p += nrows) {
         const int64_t a = off[p], b = off[p + 1], m = b - a;
         int64_t sx = 0, sy = 0;
         if (m >= 3) {
             const int64_t x0 = xy[2 * a], y0 = xy[2 * a + 1];
             i128 a2 = 0, nx = 0, ny = 0;
             const int2 *v = reinterpret_cast<const int2 *>(xy + 2 * a);
-            for (int64_t base = 0; base < m; base += 64) {
-                const int64_t i = base + lane;
+            for (int64_t base = 0; base < m; base += 16) {
+                const int64_t i = base + rl;
                 const bool live = i < m;
                 const int2 pi = v[live ? i : 0], pj = v[i + 1 < m ? i + 1 : 0];
                 const int64_t dx = pi.x - x0, dy = pi.y - y0;
@@ -89,20 +89,20 @@ __global__ __launch_bounds__(256) void k_centre(const int32_t *__restrict__ xy,
                 nx += (i128)(dx + ex) * c;
                 ny += (i128)(dy + ey) * c;
             }
-            a2 = wave_sum_i128(a2);
-            nx = wave_sum_i128(nx);
-            ny = wave_sum_i128(ny);
+            a2 = row_sum_i128(a2);
+            nx = row_sum_i128(nx);
+            ny = row_sum_i128(ny);
             if (a2 != 0) {
                 sx = x0 + floor_div_small(2 * nx + 3 * a2, 6 * a2);
                 sy = y0 + floor_div_small(2 * ny + 3 * a2, 6 * a2);
             }
         }
-        if (shift && lane == 0) {
+        if (shift && rl == 0) {
             shift[2 * p] = (int32_t)sx;
             shift[2 * p + 1] = (int32_t)sy;
         }
         bool bad = false;
-        for (int64_t i = lane; i < m; i += 64) {
+        for (int64_t i = rl; i < m; i += 16) {
             const int64_t x = xy[2 * (a + i)] - sx, y = xy[2 * (a + i) + 1] - sy;
             bad |= x < INT32_MIN || x > INT32_MAX || y < INT32_MIN || y > INT32_MAX;
             out[2 * (a + i)] = (int32_t)x;
@@ -118,7 +118,7 @@ polymh_status launch_centre(const int32_t *xy, const int64_t *off, int64_t n, in
                             int32_t *shift, int32_t *range_flag, hipStream_t s)
 {
     if (n == 0) return POLYMH_OK;
-    int64_t blocks = (n + 3) / 4;
+    int64_t blocks = (n + 15) / 16;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_centre, dim3((unsigned)blocks), dim3(256), 0, s, xy, off, n, out, shift, range_flag);
     return check_launch("centre");
