@@ -102,6 +102,27 @@ def _segments(counts: np.ndarray):
     return off, pid
 
 
+def _sort_segments(a: np.ndarray, counts: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """Values of ``a`` sorted within each CSR segment.  Segments are grouped
+    by the power of two above their length and sorted as rows of a padded
+    matrix (padding +inf sorts last), which is much faster than one global
+    two-key sort of the whole array."""
+    out = np.empty_like(a)
+    level = np.ceil(np.log2(np.maximum(counts, 1))).astype(np.int64)
+    for lv in np.unique(level):
+        sel = np.flatnonzero(level == lv)
+        c = counts[sel]
+        width = int(c.max())
+        s_off, s_row = _segments(c)
+        col = np.arange(s_off[-1]) - np.repeat(s_off[:-1], c)
+        src = np.repeat(off[sel], c) + col
+        M = np.full((sel.size, width), np.inf)
+        M[s_row, col] = a[src]
+        M.sort(axis=1)
+        out[src] = M[s_row, col]
+    return out
+
+
 def _star_angles(rng, counts, stratified=False):
     """Sorted angles per polygon, redrawn until every gap is below pi.  With
     ``stratified`` angle i is (i + U(0.25, 0.75)) * 2 pi / n, which keeps every
@@ -118,7 +139,7 @@ def _star_angles(rng, counts, stratified=False):
             a = (idx + rng.uniform(0.25, 0.75, sub_off[-1])) * (TWO_PI / np.repeat(sub_cnt, sub_cnt))
         else:
             a = rng.random(sub_off[-1]) * TWO_PI
-        a = a[np.lexsort((a, sub_pid))]
+        a = _sort_segments(a, sub_cnt, sub_off)
         nxt = np.empty_like(a)
         nxt[:-1] = a[1:]
         last = sub_off[1:] - 1
@@ -194,6 +215,13 @@ def _edge_ok(xy: np.ndarray, counts: np.ndarray, centre: np.ndarray) -> np.ndarr
     return (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]) > 0, nxt_idx
 
 
+def _edges_ok(xy: np.ndarray, edges: np.ndarray, nxt: np.ndarray, centre: np.ndarray) -> np.ndarray:
+    """``_edge_ok`` for the listed edges only (``centre`` given per edge)."""
+    a = xy[edges] - centre
+    b = xy[nxt[edges]] - centre
+    return (a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0]) > 0
+
+
 def jittered(rng, base: PolySet, ids, noise, grid_bits: int, max_rounds: int = 64) -> PolySet:
     """Copies of base polygons ``ids`` with every coordinate moved by
     round(U[-d, d]), d = noise * R, clipped to the grid.  The two vertices of
@@ -210,13 +238,23 @@ def jittered(rng, base: PolySet, ids, noise, grid_bits: int, max_rounds: int = 6
     d = (noise * src.radius)[pid]
     out = orig.copy()
     redo = np.arange(off[-1])
-    for _ in range(max_rounds):
+    nxt = np.arange(off[-1]) + 1
+    nxt[off[1:] - 1] = off[:-1]
+    prv = np.arange(off[-1]) - 1
+    prv[off[:-1]] = off[1:] - 1
+    for rnd in range(max_rounds):
         if redo.size == 0:
             break
         j = np.rint(rng.uniform(-1.0, 1.0, (redo.size, 2)) * d[redo][:, None]).astype(np.int64)
         out[redo] = np.clip(orig[redo] + j, 0, hi)
-        ok, nxt = _edge_ok(out, counts, src.centre)
-        bad = np.flatnonzero(~ok)
+        if rnd == 0:
+            ok, _ = _edge_ok(out, counts, src.centre)
+            bad = np.flatnonzero(~ok)
+        else:
+            # an edge with neither end redrawn kept its vertices, and it was
+            # good in the last round (a bad edge has both ends redrawn)
+            edges = np.unique(np.concatenate([redo, prv[redo]]))
+            bad = edges[~_edges_ok(out, edges, nxt, src.centre[pid[edges]])]
         redo = np.unique(np.concatenate([bad, nxt[bad]]))
     stuck = ~_star_valid(out, counts, src.centre)
     if stuck.any():   # rare: such copies keep their source vertices
@@ -408,10 +446,11 @@ def workload(cfg: int, n: int | None = None, n_queries: int | None = None) -> Wo
         N = 1_000_000 if n is None else n
         Q = 1000 if n_queries is None else n_queries
         n_clu_target = int(round(0.2 * N))
-        sizes = []
-        while sum(sizes) < n_clu_target:
+        sizes, total = [], 0
+        while total < n_clu_target:
             sizes.append(int(rng.integers(2, 11)))
-        sizes[-1] -= sum(sizes) - n_clu_target
+            total += sizes[-1]
+        sizes[-1] -= total - n_clu_target
         if sizes and sizes[-1] < 1:
             sizes.pop()
         sizes = np.asarray(sizes, dtype=np.int64)
