@@ -443,23 +443,28 @@ __device__ void chunk_boxes(RingLds R, int n, int t0, int nt)
     }
 }
 
-// Wavefront form for P (lane = chunk, ncp <= 64): the chunk boxes.
+// Wavefront form for P (lane = chunk, up to MAXC chunks): the chunk boxes.
 // The 9 vertices of a chunk are read at once (indices clamped to the ring's
 // end, which only repeats a vertex) so their LDS latencies overlap.
+template <int MAXC>
 __device__ void chunk_boxes_p(RingLds R, int n, int lane)
 {
     const int nc = (n + 7) >> 3;
-    if (lane < nc) {
-        const int e1 = min(n, 8 * lane + 8);
-        int2 p[9];
 #pragma unroll
-        for (int j = 0; j < 9; j++) p[j] = R.v[min(8 * lane + j, e1)];
-        int x0 = p[0].x, y0 = p[0].y, x1 = p[0].x, y1 = p[0].y;
+    for (int c0 = 0; c0 < MAXC; c0 += 64) {
+        const int c = c0 + lane;
+        if (c < nc) {
+            const int e1 = min(n, 8 * c + 8);
+            int2 p[9];
 #pragma unroll
-        for (int j = 1; j < 9; j++) {
-            x0 = min(x0, p[j].x); y0 = min(y0, p[j].y); x1 = max(x1, p[j].x); y1 = max(y1, p[j].y);
+            for (int j = 0; j < 9; j++) p[j] = R.v[min(8 * c + j, e1)];
+            int x0 = p[0].x, y0 = p[0].y, x1 = p[0].x, y1 = p[0].y;
+#pragma unroll
+            for (int j = 1; j < 9; j++) {
+                x0 = min(x0, p[j].x); y0 = min(y0, p[j].y); x1 = max(x1, p[j].x); y1 = max(y1, p[j].y);
+            }
+            R.box[c] = make_int4(x0, y0, x1, y1);
         }
-        R.box[lane] = make_int4(x0, y0, x1, y1);
     }
 }
 
@@ -599,14 +604,15 @@ __device__ void flush_crossings(RingLds P, RingLds Q, const uint32_t *buf, int c
 }
 
 // One sweep unit per lane: Q edge f held in registers against the 8 edges of
-// P chunk cp (entry = cp << 10 | f).  Crossing lanes only append
+// P chunk cp (entry = cp << USHIFT | f).  Crossing lanes only append
 // (e << 16 | f) to the wavefront's crossing buffer, which is flushed before
 // it can overflow.
+template <int USHIFT>
 __device__ __forceinline__ void sweep_units(RingLds P, RingLds Q, int entry, int lane, uint32_t *xbuf,
                                             int &xcount, int kq, double &accP, double &accQ, double &accM,
                                             double &accK)
 {
-    const int cp = entry >> 10, f = entry & 1023;
+    const int cp = entry >> USHIFT, f = entry & ((1 << USHIFT) - 1);
     const int2 c = Q.v[f], d = Q.v[f + 1];
     const double cx = (double)c.x, cy = (double)c.y;
     const double fx = (double)(d.x - c.x), fy = (double)(d.y - c.y);
@@ -654,8 +660,9 @@ __device__ __forceinline__ void sweep_units(RingLds P, RingLds Q, int entry, int
 // lane) into sweep units, keeping the (P chunk, Q edge) pairs whose boxes
 // touch: a crossing needs the Q edge's box to meet the box of the P edge it
 // crosses, inside the chunk's.
+template <typename UnitT, int USHIFT>
 __device__ __forceinline__ void expand_tiles(RingLds P, RingLds Q, int m, const uint16_t *tiles, int head,
-                                             int count, int lane, uint16_t *units, int &utail)
+                                             int count, int lane, UnitT *units, int &utail)
 {
     bool keep[2];
     int entry[2];
@@ -672,22 +679,24 @@ __device__ __forceinline__ void expand_tiles(RingLds P, RingLds Q, int m, const 
         const bool apart = (max(c.x, d.x) < bp.x) | (bp.z < min(c.x, d.x)) | (max(c.y, d.y) < bp.y) |
                            (bp.w < min(c.y, d.y));
         keep[h] = live & (f < m) & !apart;
-        entry[h] = (cp << 10) | f;
+        entry[h] = (cp << USHIFT) | f;
     }
     const uint64_t mk0 = __ballot(keep[0]), mk1 = __ballot(keep[1]);
     const int r0 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk0, 0u));
     const int r1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk1, 0u));
     const int c0 = __popcll(mk0);
-    if (keep[0]) units[(utail + r0) & (kUnitCap - 1)] = (uint16_t)entry[0];
-    if (keep[1]) units[(utail + c0 + r1) & (kUnitCap - 1)] = (uint16_t)entry[1];
+    if (keep[0]) units[(utail + r0) & (kUnitCap - 1)] = (UnitT)entry[0];
+    if (keep[1]) units[(utail + c0 + r1) & (kUnitCap - 1)] = (UnitT)entry[1];
     utail += c0 + __popcll(mk1);
 }
 
 // kp / kq: a vertex of P outside Q (and of Q outside P), or -1; the ring's
 // memberships are anchored there (membership 0), else at vertex 0 by a
-// crossing-number pass.
+// crossing-number pass.  Sweep units are (P chunk, Q edge) entries packed as
+// cp << USHIFT | f in UnitT (16 bits up to 512 edges a side, 32 beyond).
+template <typename UnitT, int USHIFT>
 __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int64_t a2p, int64_t a2q,
-                             int kp, int kq, int lane, uint16_t *list, uint16_t *units, uint32_t *xbuf,
+                             int kp, int kq, int lane, uint16_t *list, UnitT *units, uint32_t *xbuf,
                              unsigned long long *swept)
 {
     int wkp = 0, wkq = 0;
@@ -701,8 +710,9 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
     const int ncp = (n + 7) >> 3, ncq = (m + 7) >> 3;
     const int total = ncp * ncq;
     // idx -> (idx / ncq, idx % ncq) without an integer division: the float
-    // quotient of idx + 1/2 is at least 1/(2 ncq) >= 1/128 away from an
-    // integer while its rounding error is below 2^-10 (idx < 2^12).
+    // quotient of idx + 1/2 is at least 1/(2 ncq) >= 1/256 away from an
+    // integer (ncq <= 128) while its rounding error is below 2^-15 (the
+    // quotient is below ncp <= 128 and carries two roundings of 2^-24).
     const float rq = 1.0f / (float)ncq;
     int head = 0, tail = 0, uhead = 0, utail = 0, xcount = 0;
     // two batches of 64 chunk pairs per round trip through the tile list
@@ -734,11 +744,12 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
         while (tail - head >= 16 || (last && tail > head)) {
             wave_lds_sync();
             const int cnt = min(16, tail - head);
-            expand_tiles(P, Q, m, list, head, cnt, lane, units, utail);
+            expand_tiles<UnitT, USHIFT>(P, Q, m, list, head, cnt, lane, units, utail);
             head += cnt;
             wave_lds_sync();
             while (utail - uhead >= 64) {
-                sweep_units(P, Q, (int)units[(uhead + lane) & (kUnitCap - 1)], lane, xbuf, xcount, kq, accP, accQ, accM, accK);
+                sweep_units<USHIFT>(P, Q, (int)units[(uhead + lane) & (kUnitCap - 1)], lane, xbuf, xcount, kq, accP,
+                                    accQ, accM, accK);
                 uhead += 64;
             }
         }
@@ -747,7 +758,7 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
         // partial sweep: idle lanes take a padding edge of Q (zero length)
         const int k = utail - uhead;
         const int entry = lane < k ? (int)units[(uhead + lane) & (kUnitCap - 1)] : 8 * ncq;
-        sweep_units(P, Q, entry, lane, xbuf, xcount, kq, accP, accQ, accM, accK);
+        sweep_units<USHIFT>(P, Q, entry, lane, xbuf, xcount, kq, accP, accQ, accM, accK);
     }
     if (xcount > 0) {
         wave_lds_sync();
@@ -799,11 +810,29 @@ struct HeavyPair {
 
 constexpr int kStatSlots = 64;   // work counters spread over slots, folded at the end
 
+// Wide tiled pairs: a pair with a polygon beyond kTileCap edges but none
+// beyond kWideCap (and coordinate spans below 2^26) would take the general
+// form, which tests all n m edge pairs; it is deferred instead, and a second
+// launch runs the tiled form on it with one wavefront staging both rings.
+// Up to kWideListCap pairs per call are deferred; the rest run in place.
+constexpr int kWideCap = 1024;
+constexpr int kWideRing = kWideCap + 16;   // ring vertices incl. padding
+constexpr int kWideListCap = 1 << 20;
+
+struct WidePair {
+    int64_t c;            // candidate slot of the result
+    int64_t pa;           // first vertex of P (data)
+    int32_t n;            // P's vertex count
+    int32_t q;            // query index
+};
+
 struct HeavyWs {
-    int32_t *count;       // pairs recorded (may exceed kHeavyCap: the excess ran in place)
+    int32_t *count;       // [0] heavy pairs, [1] wide tiled pairs recorded (either may exceed its cap:
+                          // the excess ran in place)
     HeavyPair *pairs;     // [kHeavyCap]
     double *partial;      // [kHeavyCap][2][kHeavySlices]
     unsigned long long *stat_slots;   // [kStatSlots][4]
+    WidePair *wide;       // [kWideListCap]
 };
 
 __device__ __forceinline__ double jaccard_of(double inter2, int64_t a2p, int64_t a2q)
@@ -933,14 +962,23 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                 if (!wide && tiled_size) {
                     for (int i = lane; i < (n + 1) >> 1; i += 64) Ps.S[i] = kSBias;
                     wave_lds_sync();
-                    chunk_boxes_p(Ps, n, lane);
+                    chunk_boxes_p<kTileCap / 8>(Ps, n, lane);
                     a2p = a2p_staged;
                     wave_lds_sync();
                     if (a2p != 0)
-                        inter2 = tiled_pair(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2p, a2q, kp,
-                                            anchor_q(qmbr, pm, qext), lane,
-                                            sList[wave], sUnits[wave], sCross[wave], &st_swept);
+                        inter2 = tiled_pair<uint16_t, 10>(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2p,
+                                                          a2q, kp, anchor_q(qmbr, pm, qext), lane,
+                                                          sList[wave], sUnits[wave], sCross[wave], &st_swept);
                     st_tiled++;
+                } else if (hw.count && !wide && n <= kWideCap && m <= kWideCap &&
+                           (slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, 1) : 0)) <
+                               kWideListCap) {
+                    // tiled form with both rings staged by one wavefront of the next launch
+                    if (lane == 0) {
+                        WidePair &w = hw.wide[slot];
+                        w.c = c; w.pa = pa; w.n = n; w.q = (int32_t)q;
+                    }
+                    deferred = true;
                 } else if (hw.count && (int64_t)n * m >= kHeavyMin &&
                            (a2p = poly_area2(Pg, n, ox, oy, lane)) != 0 &&
                            (slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count, 1) : 0)) <
@@ -995,6 +1033,78 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                 else atomicAdd(stats + tid, v);
             }
         }
+    }
+}
+
+// One wavefront per deferred wide pair (workgroups of one wavefront, so four
+// fit a CU's LDS): Q and P staged like k_refine's rings at up to kWideCap
+// edges, then the tiled form.  Work counts go to the counter slots.
+__global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ dxy,
+                                                    const int32_t *__restrict__ qxy,
+                                                    const int64_t *__restrict__ qoff,
+                                                    double *__restrict__ cand_j, HeavyWs hw, int want_stats)
+{
+    __shared__ int2 sQv[kWideRing];
+    __shared__ int4 sQbox[kWideCap / 8];
+    __shared__ double sQsuf[kWideCap];
+    __shared__ int2 sPv[kWideRing];
+    __shared__ int4 sPbox[kWideCap / 8];
+    __shared__ uint32_t sPS[kWideCap / 2];
+    __shared__ uint16_t sList[kListCap];
+    __shared__ uint32_t sUnits[kUnitCap];
+    __shared__ uint32_t sCross[kCrossCap];
+    __shared__ int sQext[4];
+
+    const int lane = threadIdx.x;
+    const int64_t count = min((int64_t)hw.count[1], (int64_t)kWideListCap);
+    unsigned long long st_pairs = 0, st_swept = 0;
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const WidePair w = hw.wide[i];
+        const int64_t qa = qoff[w.q];
+        const int m = (int)(qoff[w.q + 1] - qa), n = w.n;
+        const int32_t *Qg = qxy + 2 * qa, *Pg = dxy + 2 * w.pa;
+        const int64_t ox = Qg[0], oy = Qg[1];
+        int32_t qm[4];
+        poly_mbr(Qg, m, lane, qm);
+        const int64_t a2q = poly_area2(Qg, m, ox, oy, lane);
+        RingLds Qs{sQv, sQbox, nullptr, sQsuf};
+        RingLds Ps{sPv, sPbox, sPS, nullptr};
+        // Q padded by one extra chunk, as in k_refine
+        const int qpad = 8 * ((m + 7) >> 3) + 8;
+        stage_ring(Qg, m, qpad + 1, ox, oy, Qs, lane, 64);
+        wave_lds_sync();
+        chunk_boxes(Qs, m, lane, 64);
+        q_suffix_sums(Qs, m, a2q, lane);
+        const int4 rb = make_int4((int)((int64_t)qm[0] - ox), (int)((int64_t)qm[1] - oy),
+                                  (int)((int64_t)qm[2] - ox), (int)((int64_t)qm[3] - oy));
+        q_extremes(Qs, m, rb, lane, sQext);
+        RingPrefetch pf;
+        prefetch_ring(Pg, n, lane, pf);
+        int32_t pm[4];
+        int64_t a2p = 0;
+        int kp = -1;
+        stage_ring_mbr(Pg, n, 8 * ((n + 7) >> 3) + 1, ox, oy, Ps, lane, qm, pf, pm, a2p, kp);
+        for (int j = lane; j < (n + 1) >> 1; j += 64) Ps.S[j] = kSBias;
+        wave_lds_sync();
+        chunk_boxes_p<kWideCap / 8>(Ps, n, lane);
+        wave_lds_sync();
+        const int qext[4] = {sQext[0], sQext[1], sQext[2], sQext[3]};
+        double J = 0.0;
+        if (a2p != 0) {
+            const double inter2 = tiled_pair<uint32_t, 16>(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2p,
+                                                           a2q, kp, anchor_q(qm, pm, qext), lane, sList, sUnits,
+                                                           sCross, &st_swept);
+            J = jaccard_of(inter2, a2p, a2q);
+        }
+        st_pairs++;
+        if (lane == 0) cand_j[w.c] = J;
+        // every lane is done with both rings before the next pair restages them
+        wave_lds_sync();
+    }
+    if (want_stats && lane == 0) {
+        unsigned long long *slot = hw.stat_slots + (blockIdx.x % kStatSlots) * 4;
+        if (st_pairs) atomicAdd(slot + 0, st_pairs);
+        if (st_swept) atomicAdd(slot + 1, st_swept);
     }
 }
 
@@ -1057,13 +1167,14 @@ HeavyWs carve_heavy(Carve &cv)
     hw.pairs = cv.take<HeavyPair>(kHeavyCap);
     hw.partial = cv.take<double>((size_t)kHeavyCap * 2 * kHeavySlices);
     hw.stat_slots = cv.take<unsigned long long>(kStatSlots * 4);
+    hw.wide = cv.take<WidePair>(kWideListCap);
     return hw;
 }
 
-// Clears the pair count and the counter slots (256 threads).
+// Clears the two pair counts and the counter slots (256 threads).
 __global__ void k_zero_count(int32_t *p, unsigned long long *slots)
 {
-    if (threadIdx.x == 0) p[0] = 0;
+    if (threadIdx.x < 2) p[threadIdx.x] = 0;
     if (threadIdx.x < kStatSlots * 4) slots[threadIdx.x] = 0;
 }
 
@@ -1117,6 +1228,10 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
                        slices, hw);
     polymh_status st = check_launch("refine");
     if (st || !ws) return st;
+    // deferred wide tiled pairs: four one-wavefront workgroups per CU
+    hipLaunchKernelGGL(k_refine_wide, dim3(1024), dim3(64), 0, s, data->xy, queries->xy, queries->offsets, cand_j,
+                       hw, stats ? 1 : 0);
+    if ((st = check_launch("refine: wide pairs"))) return st;
     // deferred heavy pairs: a grid that covers every (pair, side, slice) of a
     // full list in a few rounds, then the per-pair sums
     hipLaunchKernelGGL(k_heavy, dim3(2048), dim3(256), 0, s, data->xy, queries->xy, hw);

@@ -221,9 +221,10 @@ def test_refine_large_polygons_general_path(pm, orc):
 
 
 def test_refine_heavy_pairs_split(pm, orc):
-    # pairs with n m >= 2^17 edge pairs are split over many wavefronts: the
-    # values equal the oracle's and the in-place form's, and the work counts
-    # are the same
+    # with the workspace, general-form pairs with n m >= 2^17 edge pairs are
+    # split over many wavefronts and pairs of at most 1024 edges a side move
+    # to the tiled form: the values equal the oracle's and the in-place
+    # form's, and the work counts move by exactly those pairs
     import torch
     rng = np.random.default_rng(8)
     data = dg.star_polygons(rng, [600, 1500, 40, 2000, 3000], [[50000, 50000]] * 5, [40000.0] * 5)
@@ -236,17 +237,25 @@ def test_refine_heavy_pairs_split(pm, orc):
     want = orc.jaccard_candidates(data, queries, off.cpu().numpy(), ids.cpu().numpy())
     got = split.cpu().numpy()
     assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
-    assert np.all(np.abs(got - inplace.cpu().numpy()) <= 1e-12 + 1e-12 * np.abs(want))
-    assert st_split == st_inplace
+    assert np.all(np.abs(got - inplace.cpu().numpy()) <= REL * np.abs(want) + ABS)
+    n = data.counts()[ids.cpu().numpy()]
+    m = np.repeat(queries.counts(), 5)
+    big = np.maximum(n, m)
+    moved = (big > 512) & (big <= 1024)
+    assert moved.sum() == 3 and (big > 1024).sum() > 0
+    assert st_split[0] == st_inplace[0] + moved.sum()
+    assert st_inplace[2] - st_split[2] == int((2 * n * m)[moved].sum())
+    assert st_split[3] == st_inplace[3]
 
 
 def test_refine_more_heavy_pairs_than_the_split_list(pm):
-    # 8,400 heavy pairs (400 x 400 edges): the first 8,192 are split, the
-    # rest run in place; every value equals the in-place form's
+    # 8,400 heavy pairs (1,100 x 130 edges: beyond the tiled forms, n m >=
+    # 2^17): the first 8,192 are split, the rest run in place; every value
+    # equals the in-place form's
     import torch
     rng = np.random.default_rng(9)
-    data = dg.star_polygons(rng, [400] * 120, [[50000 + 50 * i, 50000] for i in range(120)], [30000.0] * 120)
-    queries = dg.star_polygons(rng, [400] * 70, [[51000, 49000 + 30 * i] for i in range(70)], [30000.0] * 70)
+    data = dg.star_polygons(rng, [1100] * 120, [[50000 + 50 * i, 50000] for i in range(120)], [30000.0] * 120)
+    queries = dg.star_polygons(rng, [130] * 70, [[51000, 49000 + 30 * i] for i in range(70)], [30000.0] * 70)
     D, Q = pm.to_device(data), pm.to_device(queries)
     off = torch.arange(71, dtype=torch.int64, device="cuda") * 120
     ids = torch.arange(120, dtype=torch.int32, device="cuda").repeat(70)
@@ -274,3 +283,74 @@ def test_refine_heavy_pairs_wide_coordinates(pm, orc):
     assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
     inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy()
     assert np.all(np.abs(got - inplace) <= 1e-12 + 1e-12 * np.abs(want))
+
+
+def test_refine_wide_tiled_pairs(pm, orc):
+    # pairs with a polygon of 513 to 1024 edges (none beyond) take the tiled
+    # form in a second launch, one wavefront staging both rings: the values
+    # equal the oracle's and the general form's, and every pair is counted as
+    # tiled
+    import torch
+    rng = np.random.default_rng(11)
+    data = dg.star_polygons(rng, [513, 1024, 700, 40, 900, 8], [[50000, 50000]] * 6, [40000.0] * 6)
+    queries = dg.star_polygons(rng, [1000, 30, 513, 800, 1024], [[52000, 49000]] * 5, [38000.0] * 5)
+    D, Q = pm.to_device(data), pm.to_device(queries)
+    off = torch.arange(6, dtype=torch.int64, device="cuda") * 6
+    ids = torch.arange(6, dtype=torch.int32, device="cuda").repeat(5)
+    got, st = pm.refine_stats(D, Q, off, ids)
+    inplace, st0 = pm.refine_stats(D, Q, off, ids, split_heavy=False)
+    want = orc.jaccard_candidates(data, queries, off.cpu().numpy(), ids.cpu().numpy())
+    got, inplace = got.cpu().numpy(), inplace.cpu().numpy()
+    assert (want > 0.2).sum() >= 25
+    assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
+    assert np.all(np.abs(inplace - want) <= REL * np.abs(want) + ABS)
+    assert st[0] == 30 and st[2] == 0 and st[1] > 0
+    assert st0[2] > 0
+
+
+def _subdivided_rect(x0, y0, x1, y1, k):
+    """Counter-clockwise rectangle with k vertices per side (all on its edges)."""
+    i = np.arange(k)
+    w, h = x1 - x0, y1 - y0
+    return np.concatenate([np.stack([x0 + w * i // k, np.full(k, y0)], 1),
+                           np.stack([np.full(k, x1), y0 + h * i // k], 1),
+                           np.stack([x1 - w * i // k, np.full(k, y1)], 1),
+                           np.stack([np.full(k, x0), y1 - h * i // k], 1)]).astype(np.int64)
+
+
+def test_refine_wide_tiled_degenerate_contacts(pm, orc):
+    # the degenerate contacts of the small cases at 513 to 1024 edges: every
+    # side of a 400 x 400 square carries 200 (or 150) vertices, so edges
+    # overlap collinearly, vertices lie on edges and shapes share corners
+    L = 400
+    sq = _subdivided_rect(0, 0, L, L, 200)                     # 800 vertices
+    sq6 = _subdivided_rect(0, 0, L, L, 150)                    # 600 vertices, every third shared
+    k = 200
+    i = np.arange(k)
+    tri = np.concatenate([np.stack([L * i // k, np.zeros(k, np.int64)], 1),
+                          np.stack([L - L * i // k, L * i // k], 1),
+                          np.stack([np.zeros(k, np.int64), L - L * i // k], 1)])   # 600 vertices
+    cases = [
+        (sq, sq, Fraction(1)),                                   # identical
+        (sq, sq[::-1], Fraction(1)),                             # opposite orientation
+        (sq, np.roll(sq, 337, axis=0), Fraction(1)),             # rotated start
+        (sq, sq6, Fraction(1)),                                  # same square, other subdivision
+        (sq, dg.rectangle(0, 0, L, L), Fraction(1)),
+        (sq, _subdivided_rect(L, 0, 2 * L, L, 200), Fraction(0)),               # shared edge
+        (sq, _subdivided_rect(L, L, 2 * L, 2 * L, 200), Fraction(0)),           # shared corner
+        (sq, _subdivided_rect(L // 2, 0, L // 2 + L, L, 200), Fraction(1, 3)),  # collinear overlaps
+        (sq, dg.rectangle(0, 0, L // 2, L // 2), Fraction(1, 4)),               # nested, shared corner
+        (sq, dg.rectangle(80, 0, 320, L), Fraction(60, 100)),                   # T-junctions
+        (sq, tri, Fraction(1, 2)),                               # shared diagonal endpoints
+        (tri, sq6, Fraction(1, 2)),
+        (sq, np.array([[L // 2, 0], [L, L // 2], [L // 2, L], [0, L // 2]]), Fraction(1, 2)),  # vertices on edges
+    ]
+    D = dg.from_list([c[0] for c in cases])
+    Q = dg.from_list([c[1] for c in cases])
+    off = np.arange(len(cases) + 1, dtype=np.int64)
+    ids = np.arange(len(cases), dtype=np.int32)
+    got = _refine(pm, D, Q, off, ids)
+    for j, (_, _, want) in enumerate(cases):
+        assert abs(got[j] - float(want)) <= 1e-12, (j, got[j], want)
+    want = orc.jaccard_candidates(D, Q, off, ids)
+    assert np.all(np.abs(want - np.array([float(c[2]) for c in cases])) <= 1e-9)
