@@ -282,21 +282,23 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
 
 /* polymh_refine_ws -- polymh_refine (stats nullable, as polymh_refine_stats)
  * with a workspace of polymh_refine_workspace_size() bytes (device,
- * caller-owned, contents overwritten).  With it, two kinds of pair that
+ * caller-owned, contents overwritten).  With it, every pair that
  * polymh_refine computes by the general form (every edge of one polygon
- * against every edge of the other, one wavefront per pair) are deferred to
- * further launches:
- *   - a pair with a polygon of 513 to 1024 edges and none larger (coordinate
- *     spans below 2^26) takes the tiled form of the smaller pairs, which
- *     tests only edges whose boxes meet, on one wavefront that stages both
- *     rings (up to 2^20 such pairs per call);
- *   - a larger pair with n m >= 2^17 edge pairs is split over 128
- *     wavefronts (up to 8192 per call),
+ * against every edge of the other, one wavefront per pair: a polygon beyond
+ * 512 edges) is deferred to further launches:
+ *   - with coordinate spans below 2^26, it takes the tiled form of the
+ *     smaller pairs (only edges whose boxes meet are tested), both polygons
+ *     passing through on-chip memory in windows of 1024 edges; a pair whose
+ *     smaller polygon has more than 1024 edges is split over its windows,
+ *     one wavefront each, and the partial sums are added in window order
+ *     (up to 2^20 list entries and 8192 split pairs per call);
+ *   - with wider spans (128-bit signs), a pair with n m >= 2^17 edge pairs
+ *     is split over 128 wavefronts of the general form (up to 8192 pairs),
  * so the few large pairs of a batch no longer set the call's duration.  The
  * values are those of polymh_refine within the refinement's rounding (the
- * same intersection area summed in another order); pairs beyond either cap
- * run in place.  ws NULL is polymh_refine.  Stream-ordered and
- * graph-capturable; two calls sharing a workspace must not overlap. */
+ * same intersection area summed in another order; deterministic); pairs
+ * beyond the caps run in place.  ws NULL is polymh_refine.  Stream-ordered
+ * and graph-capturable; two calls sharing a workspace must not overlap. */
 size_t polymh_refine_workspace_size(void);
 polymh_status polymh_refine_ws(const polymh_polys *data, const polymh_polys *queries, const int64_t *cand_off,
                                const int32_t *cand_ids, int64_t nq, int64_t n_cand, double *cand_j,

@@ -513,11 +513,13 @@ __device__ void member_starts(RingLds P, int n, RingLds Q, int m, int lane, bool
 // pre(e) the exclusive prefix of S; the function returns T (a per-lane
 // partial) and K = pre(anchor) (uniform), so that a known membership at any
 // anchor vertex fixes w0 = w(anchor) - s * K.
-__device__ double membership_term_p(RingLds P, int n, int anchor, int lane, int &K)
+// Over a window of a longer ring: carry holds the crossing signs of the
+// edges before the window (in and out), K is set only when the anchor's
+// index (relative to the window) falls inside it, and crs gathers the
+// window's cross products (per-lane partial).
+__device__ double membership_term_window(RingLds P, int n, int anchor, int lane, int &carry, int &K, double &crs)
 {
     double acc = 0.0;
-    int carry = 0;
-    K = 0;
     for (int base = 0; base < n; base += 64) {
         const int e = base + lane;
         const bool live = e < n;
@@ -528,10 +530,19 @@ __device__ double membership_term_p(RingLds P, int n, int anchor, int lane, int 
         const int incl = wave_incl_scan32(Se);
         const int excl = carry + incl - Se;
         acc += live ? cr * (double)excl : 0.0;
+        crs += live ? cr : 0.0;
         if (anchor >= base && anchor < base + 64) K = __builtin_amdgcn_readlane(excl, anchor - base);
         carry += __builtin_amdgcn_readlane(incl, 63);
     }
     return acc;
+}
+
+__device__ double membership_term_p(RingLds P, int n, int anchor, int lane, int &K)
+{
+    int carry = 0;
+    double crs = 0.0;
+    K = 0;
+    return membership_term_window(P, n, anchor, lane, carry, K, crs);
 }
 
 // Indices of a leftmost, a rightmost, a lowest and a highest vertex of Q
@@ -557,9 +568,8 @@ __device__ void q_extremes(RingLds Q, int m, int4 rb, int lane, int *ext)
 
 // Q's suffix sums Suf(f) = A2Q - sum_{f' <= f} cr_f' (exact in 64-bit
 // integers), by one wavefront.
-__device__ void q_suffix_sums(RingLds Q, int m, int64_t a2q, int lane)
+__device__ int64_t q_suffix_sums(RingLds Q, int m, int64_t a2q, int lane, int64_t carry = 0)
 {
-    int64_t carry = 0;
     for (int base = 0; base < m; base += 64) {
         const int e = base + lane;
         const bool live = e < m;
@@ -570,6 +580,7 @@ __device__ void q_suffix_sums(RingLds Q, int m, int64_t a2q, int lane)
         if (live) Q.suf[e] = (double)(a2q - incl);
         carry = (int64_t)dpp::readlane64((uint64_t)incl, 63);
     }
+    return carry;
 }
 
 // Crossing contributions of buffered (e, f) pairs, 64 at a time with every
@@ -690,23 +701,16 @@ __device__ __forceinline__ void expand_tiles(RingLds P, RingLds Q, int m, const 
     utail += c0 + __popcll(mk1);
 }
 
-// kp / kq: a vertex of P outside Q (and of Q outside P), or -1; the ring's
-// memberships are anchored there (membership 0), else at vertex 0 by a
-// crossing-number pass.  Sweep units are (P chunk, Q edge) entries packed as
-// cp << USHIFT | f in UnitT (16 bits up to 512 edges a side, 32 beyond).
+// The crossings of P's edges with the m edges of Q staged in LDS (a whole
+// ring, or a window of a longer one) added to the four sums; kq is the
+// anchor's index relative to the staged edges.  Sweep units are (P chunk,
+// Q edge) entries packed as cp << USHIFT | f in UnitT (16 bits up to 512
+// edges a side, 32 beyond).
 template <typename UnitT, int USHIFT>
-__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int64_t a2p, int64_t a2q,
-                             int kp, int kq, int lane, uint16_t *list, UnitT *units, uint32_t *xbuf,
-                             unsigned long long *swept)
+__device__ void tiled_accumulate(RingLds P, int n, RingLds Q, int m, int kq, int lane, uint16_t *list,
+                                 UnitT *units, uint32_t *xbuf, unsigned long long *swept, double &accP,
+                                 double &accQ, double &accM, double &accK)
 {
-    int wkp = 0, wkq = 0;
-    if (kp < 0 || kq < 0) {
-        int w0p, w0q;
-        member_starts(P, n, Q, m, lane, kp < 0, kq < 0, w0p, w0q);
-        if (kp < 0) { kp = 0; wkp = w0p; }
-        if (kq < 0) { kq = 0; wkq = w0q; }
-    }
-    double accP = 0.0, accQ = 0.0, accM = 0.0, accK = 0.0;
     const int ncp = (n + 7) >> 3, ncq = (m + 7) >> 3;
     const int total = ncp * ncq;
     // idx -> (idx / ncq, idx % ncq) without an integer division: the float
@@ -765,6 +769,13 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
         flush_crossings(P, Q, xbuf, xcount, lane, kq, accP, accQ, accM, accK);
     }
     *swept += 8ull * (unsigned long long)utail;   // edge pairs tested (idle lanes excluded)
+}
+
+// 2 A(P n Q) from the crossing sums and the anchors' memberships (wkp at
+// P's vertex kp, wkq at Q's vertex kq).
+__device__ double tiled_finish(RingLds P, int n, int sp, int sq, int64_t a2p, int64_t a2q, int kp, int wkp,
+                               int wkq, int lane, double accP, double accQ, double accM, double accK)
+{
     // make the crossing sums visible to the whole wavefront
     wave_lds_sync();
     // 2 A = sp * (mp + sq * accP) + sq * (mq + sp * accQ) with
@@ -774,6 +785,26 @@ __device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq,
     const double T = membership_term_p(P, n, kp, lane, K);
     const double tot = (double)(sp * sq) * (T + accP + accQ + accM - (double)a2q * accK);
     return wave_sum(tot) + (double)(sp * (wkp - sq * K)) * (double)a2p + (double)(sq * wkq) * (double)a2q;
+}
+
+// kp / kq: a vertex of P outside Q (and of Q outside P), or -1; the ring's
+// memberships are anchored there (membership 0), else at vertex 0 by a
+// crossing-number pass.
+template <typename UnitT, int USHIFT>
+__device__ double tiled_pair(RingLds P, int n, RingLds Q, int m, int sp, int sq, int64_t a2p, int64_t a2q,
+                             int kp, int kq, int lane, uint16_t *list, UnitT *units, uint32_t *xbuf,
+                             unsigned long long *swept)
+{
+    int wkp = 0, wkq = 0;
+    if (kp < 0 || kq < 0) {
+        int w0p, w0q;
+        member_starts(P, n, Q, m, lane, kp < 0, kq < 0, w0p, w0q);
+        if (kp < 0) { kp = 0; wkp = w0p; }
+        if (kq < 0) { kq = 0; wkq = w0q; }
+    }
+    double accP = 0.0, accQ = 0.0, accM = 0.0, accK = 0.0;
+    tiled_accumulate<UnitT, USHIFT>(P, n, Q, m, kq, lane, list, units, xbuf, swept, accP, accQ, accM, accK);
+    return tiled_finish(P, n, sp, sq, a2p, a2q, kp, wkp, wkq, lane, accP, accQ, accM, accK);
 }
 
 // A vertex of Q strictly outside P's MBR among Q's extreme vertices, or -1.
@@ -819,21 +850,75 @@ constexpr int kWideCap = 1024;
 constexpr int kWideRing = kWideCap + 16;   // ring vertices incl. padding
 constexpr int kWideListCap = 1 << 20;
 
+// A pair whose staged polygon (P's role in k_refine_wide) has more than
+// kWideCap edges is split over its P windows, one wavefront each (up to
+// kMultiUnits); each writes its partial sums and k_refine_multi_finish adds
+// them in window order.  Up to kMultiCap such pairs per call (the rest take
+// all their windows on one wavefront).
+constexpr int kMultiCap = 8192;
+constexpr int kMultiUnits = 64;
+
 struct WidePair {
-    int64_t c;            // candidate slot of the result
-    int64_t pa;           // first vertex of P (data)
-    int32_t n;            // P's vertex count
+    int64_t c;            // candidate slot of the result (-1: an unused entry)
+    int64_t pa;           // first vertex of the data polygon
+    int32_t n;            // its vertex count
     int32_t q;            // query index
+    int32_t pw;           // P window of a split pair, or -1 for all windows
+    int32_t slot;         // the split pair's slot, or -1
+};
+
+struct MultiPair {
+    int64_t c;            // candidate slot (-1: the pair was not deferred)
+    int64_t pa;
+    int32_t n, q, units, pad;
+};
+
+struct MultiUnit {
+    double part;          // sp sq x (P window's membership term + crossing sums), summed over the wavefront
+    double cr;            // sum of the window's cross products
+    int32_t stot;         // sum of the window's crossing signs
+    int32_t kloc;         // exclusive prefix of crossing signs at the anchor, if in this window
 };
 
 struct HeavyWs {
-    int32_t *count;       // [0] heavy pairs, [1] wide tiled pairs recorded (either may exceed its cap:
-                          // the excess ran in place)
+    int32_t *count;       // [0] heavy pairs, [1] wide list entries, [2] split pairs recorded (each
+                          // may exceed its cap: the excess ran in place)
     HeavyPair *pairs;     // [kHeavyCap]
     double *partial;      // [kHeavyCap][2][kHeavySlices]
     unsigned long long *stat_slots;   // [kStatSlots][4]
     WidePair *wide;       // [kWideListCap]
+    MultiPair *multi;     // [kMultiCap]
+    MultiUnit *units;     // [kMultiCap][kMultiUnits]
 };
+
+// Records a pair for k_refine_wide: one list entry, or, when its staged
+// polygon has more than kWideCap edges, one entry per P window and a split
+// slot.  False when the list is full (entries that did not fit are marked
+// unused).
+__device__ bool defer_wide(const HeavyWs &hw, int64_t c, int64_t pa, int n, int m, int32_t q, int lane)
+{
+    const int np = (n > kWideCap && n > m) ? m : n;
+    int units = (np + kWideCap - 1) / kWideCap;
+    int ms = -1;
+    if (units > 1) {
+        if (units <= kMultiUnits)
+            ms = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 2, 1) : 0);
+        if (ms >= kMultiCap) ms = -1;
+        if (ms < 0) units = 1;
+    }
+    const int slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, units) : 0);
+    const bool ok = slot <= kWideListCap - units;
+    if (lane < units && slot + lane < kWideListCap) {
+        WidePair &w = hw.wide[slot + lane];
+        w.c = ok ? c : -1; w.pa = pa; w.n = n; w.q = q;
+        w.pw = ms < 0 ? -1 : lane; w.slot = ms;
+    }
+    if (ms >= 0 && lane == 0) {
+        MultiPair &mp = hw.multi[ms];
+        mp.c = ok ? c : -1; mp.pa = pa; mp.n = n; mp.q = q; mp.units = units; mp.pad = 0;
+    }
+    return ok;
+}
 
 __device__ __forceinline__ double jaccard_of(double inter2, int64_t a2p, int64_t a2q)
 {
@@ -970,14 +1055,8 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                                                           a2q, kp, anchor_q(qmbr, pm, qext), lane,
                                                           sList[wave], sUnits[wave], sCross[wave], &st_swept);
                     st_tiled++;
-                } else if (hw.count && !wide && n <= kWideCap && m <= kWideCap &&
-                           (slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, 1) : 0)) <
-                               kWideListCap) {
-                    // tiled form with both rings staged by one wavefront of the next launch
-                    if (lane == 0) {
-                        WidePair &w = hw.wide[slot];
-                        w.c = c; w.pa = pa; w.n = n; w.q = (int32_t)q;
-                    }
+                } else if (hw.count && !wide && defer_wide(hw, c, pa, n, m, (int32_t)q, lane)) {
+                    // tiled form on wavefronts of the next launch
                     deferred = true;
                 } else if (hw.count && (int64_t)n * m >= kHeavyMin &&
                            (a2p = poly_area2(Pg, n, ox, oy, lane)) != 0 &&
@@ -1036,9 +1115,82 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
     }
 }
 
-// One wavefront per deferred wide pair (workgroups of one wavefront, so four
-// fit a CU's LDS): Q and P staged like k_refine's rings at up to kWideCap
-// edges, then the tiled form.  Work counts go to the counter slots.
+// Vertex i of an m-vertex ring in global memory, relative to the origin.
+__device__ __forceinline__ int2 ring_vertex(const int32_t *V, int m, int i, int64_t ox, int64_t oy)
+{
+    const int k = i < m ? i : i - m;
+    return make_int2((int)((int64_t)V[2 * k] - ox), (int)((int64_t)V[2 * k + 1] - oy));
+}
+
+// Membership of point a + sh*delta (relative coordinates) in a ring read from
+// global memory: the half-open crossing rule of member_edge over every edge.
+__device__ int member_point_global(const int32_t *V, int m, int64_t ox, int64_t oy, int2 a, int sh, int lane)
+{
+    bool odd = false;
+    for (int e = lane; e < m; e += 64) {
+        const int2 c = ring_vertex(V, m, e, ox, oy), d = ring_vertex(V, m, e + 1, ox, oy);
+        const bool st = sh < 0 ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
+        const int up = d.y > c.y ? 1 : -1;
+        const int tb = sh < 0 ? up : -up;
+        const double o = orient_d(c, d, a);
+        const int so = o > 0 ? 1 : (o < 0 ? -1 : tb);
+        odd ^= st & (so == up);
+    }
+    return __popcll(__ballot(odd)) & 1;
+}
+
+// Indices of a leftmost, a rightmost, a lowest and a highest vertex of a ring
+// in global memory (mbr: its absolute MBR), as q_extremes.
+__device__ void extremes_global(const int32_t *V, int m, const int32_t *mbr, int lane, int *ext)
+{
+    int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
+    for (int base = 0; base < m; base += 64) {
+        const int i = base + lane;
+        const bool live = i < m;
+        const int x = V[2 * (live ? i : 0)], y = V[2 * (live ? i : 0) + 1];
+        const uint64_t b0 = __ballot(live & (x == mbr[0])), b1 = __ballot(live & (x == mbr[2]));
+        const uint64_t b2 = __ballot(live & (y == mbr[1])), b3 = __ballot(live & (y == mbr[3]));
+        if (k0 < 0 && b0 != 0) k0 = base + __builtin_ctzll(b0);
+        if (k1 < 0 && b1 != 0) k1 = base + __builtin_ctzll(b1);
+        if (k2 < 0 && b2 != 0) k2 = base + __builtin_ctzll(b2);
+        if (k3 < 0 && b3 != 0) k3 = base + __builtin_ctzll(b3);
+    }
+    ext[0] = k0; ext[1] = k1; ext[2] = k2; ext[3] = k3;
+}
+
+// Edges [w0, w0 + len) of an m-vertex ring staged as a chain: entry i holds
+// vertex w0 + i for i <= len (vertex m is vertex 0), entries beyond len repeat
+// vertex w0 + len, so edges from len on have zero length and never cross.
+__device__ void stage_window(const int32_t *V, int m, int w0, int len, int pad_to, int64_t ox, int64_t oy,
+                             RingLds R, int lane)
+{
+    for (int i = lane; i < pad_to; i += 64) R.v[i] = ring_vertex(V, m, w0 + min(i, len), ox, oy);
+}
+
+// First vertex of a ring in global memory strictly outside the box b, or -1.
+__device__ int first_outside_global(const int32_t *V, int n, const int32_t *b, int lane)
+{
+    for (int base = 0; base < n; base += 64) {
+        const int i = base + lane;
+        const bool live = i < n;
+        const int x = V[2 * (live ? i : 0)], y = V[2 * (live ? i : 0) + 1];
+        const uint64_t mk = __ballot(live & ((x < b[0]) | (x > b[2]) | (y < b[1]) | (y > b[3])));
+        if (mk != 0) return base + __builtin_ctzll(mk);
+    }
+    return -1;
+}
+
+// One wavefront per deferred pair (workgroups of one wavefront, so four fit a
+// CU's LDS), any sizes: both rings pass through LDS in windows of up to
+// kWideCap edges, P's windows in the outer loop and Q's in the inner one.
+// Every sum of the tiled form adds over Q's edges, and P's membership term
+// adds over P's edges once the crossing signs of the earlier windows are
+// carried in, so each (P window, Q window) adds its crossings, with Q's
+// suffix sums carried from window to window.  P is the data polygon, or the
+// query when the data polygon has more than kWideCap edges and more than the
+// query (so a polygon of at most kWideCap edges is staged once); exchanging
+// the roles translates the data polygon by delta instead of the query:
+// another consistent perturbation with the same limit area.
 __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ dxy,
                                                     const int32_t *__restrict__ qxy,
                                                     const int64_t *__restrict__ qoff,
@@ -1053,51 +1205,96 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
     __shared__ uint16_t sList[kListCap];
     __shared__ uint32_t sUnits[kUnitCap];
     __shared__ uint32_t sCross[kCrossCap];
-    __shared__ int sQext[4];
 
     const int lane = threadIdx.x;
     const int64_t count = min((int64_t)hw.count[1], (int64_t)kWideListCap);
     unsigned long long st_pairs = 0, st_swept = 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         const WidePair w = hw.wide[i];
+        if (w.c < 0) continue;
         const int64_t qa = qoff[w.q];
-        const int m = (int)(qoff[w.q + 1] - qa), n = w.n;
-        const int32_t *Qg = qxy + 2 * qa, *Pg = dxy + 2 * w.pa;
+        const int mq = (int)(qoff[w.q + 1] - qa);
+        const bool swap = w.n > kWideCap && w.n > mq;
+        const int32_t *Pg = swap ? qxy + 2 * qa : dxy + 2 * w.pa;
+        const int32_t *Qg = swap ? dxy + 2 * w.pa : qxy + 2 * qa;
+        const int n = swap ? mq : w.n, m = swap ? w.n : mq;
         const int64_t ox = Qg[0], oy = Qg[1];
-        int32_t qm[4];
+        int32_t qm[4], pm[4];
         poly_mbr(Qg, m, lane, qm);
+        poly_mbr(Pg, n, lane, pm);
         const int64_t a2q = poly_area2(Qg, m, ox, oy, lane);
-        RingLds Qs{sQv, sQbox, nullptr, sQsuf};
-        RingLds Ps{sPv, sPbox, sPS, nullptr};
-        // Q padded by one extra chunk, as in k_refine
-        const int qpad = 8 * ((m + 7) >> 3) + 8;
-        stage_ring(Qg, m, qpad + 1, ox, oy, Qs, lane, 64);
-        wave_lds_sync();
-        chunk_boxes(Qs, m, lane, 64);
-        q_suffix_sums(Qs, m, a2q, lane);
-        const int4 rb = make_int4((int)((int64_t)qm[0] - ox), (int)((int64_t)qm[1] - oy),
-                                  (int)((int64_t)qm[2] - ox), (int)((int64_t)qm[3] - oy));
-        q_extremes(Qs, m, rb, lane, sQext);
-        RingPrefetch pf;
-        prefetch_ring(Pg, n, lane, pf);
-        int32_t pm[4];
-        int64_t a2p = 0;
-        int kp = -1;
-        stage_ring_mbr(Pg, n, 8 * ((n + 7) >> 3) + 1, ox, oy, Ps, lane, qm, pf, pm, a2p, kp);
-        for (int j = lane; j < (n + 1) >> 1; j += 64) Ps.S[j] = kSBias;
-        wave_lds_sync();
-        chunk_boxes_p<kWideCap / 8>(Ps, n, lane);
-        wave_lds_sync();
-        const int qext[4] = {sQext[0], sQext[1], sQext[2], sQext[3]};
+        const int64_t a2p = poly_area2(Pg, n, ox, oy, lane);
+        // P windows of this entry: all, or one of a split pair
+        const int pfirst = w.pw < 0 ? 0 : w.pw * kWideCap;
+        const int pend = w.pw < 0 ? n : min(n, pfirst + kWideCap);
         double J = 0.0;
-        if (a2p != 0) {
-            const double inter2 = tiled_pair<uint32_t, 16>(Ps, n, Qs, m, a2p > 0 ? 1 : -1, a2q > 0 ? 1 : -1, a2p,
-                                                           a2q, kp, anchor_q(qm, pm, qext), lane, sList, sUnits,
-                                                           sCross, &st_swept);
-            J = jaccard_of(inter2, a2p, a2q);
+        MultiUnit unit{0.0, 0.0, 0, 0};
+        if (a2p != 0 && a2q != 0) {
+            // anchors: a vertex outside the other polygon's MBR has
+            // membership 0; without one, a crossing-number pass (by the
+            // finish for a split pair)
+            int qext[4];
+            extremes_global(Qg, m, qm, lane, qext);
+            int kq = anchor_q(qm, pm, qext);
+            int kp = first_outside_global(Pg, n, qm, lane);
+            int wkp = 0, wkq = 0;
+            if (kp < 0 && w.pw < 0) {
+                const int2 p0 = make_int2((int)((int64_t)Pg[0] - ox), (int)((int64_t)Pg[1] - oy));
+                wkp = member_point_global(Qg, m, ox, oy, p0, -1, lane);
+                kp = 0;
+            }
+            if (kq < 0 && w.pw < 0) {
+                // Q's vertex 0 is the origin
+                wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
+            }
+            kp = max(kp, 0);
+            kq = max(kq, 0);
+            RingLds Qs{sQv, sQbox, nullptr, sQsuf};
+            RingLds Ps{sPv, sPbox, sPS, nullptr};
+            double accP = 0.0, accQ = 0.0, accM = 0.0, accK = 0.0, T = 0.0, crs = 0.0;
+            int pcarry = 0, K = 0;
+            for (int p0 = pfirst; p0 < pend; p0 += kWideCap) {
+                const int plen = min(kWideCap, n - p0);
+                stage_window(Pg, n, p0, plen, 8 * ((plen + 7) >> 3) + 1, ox, oy, Ps, lane);
+                for (int j = lane; j < (plen + 1) >> 1; j += 64) Ps.S[j] = kSBias;
+                wave_lds_sync();
+                chunk_boxes_p<kWideCap / 8>(Ps, plen, lane);
+                int64_t qcarry = 0;
+                for (int w0 = 0; w0 < m; w0 += kWideCap) {
+                    const int len = min(kWideCap, m - w0);
+                    // one all-padding chunk past the window, as for whole rings
+                    stage_window(Qg, m, w0, len, 8 * ((len + 7) >> 3) + 9, ox, oy, Qs, lane);
+                    wave_lds_sync();
+                    chunk_boxes(Qs, len, lane, 64);
+                    qcarry = q_suffix_sums(Qs, len, a2q, lane, qcarry);
+                    wave_lds_sync();
+                    tiled_accumulate<uint32_t, 16>(Ps, plen, Qs, len, kq - w0, lane, sList, sUnits, sCross,
+                                                   &st_swept, accP, accQ, accM, accK);
+                    // every lane is done with the window before the next one
+                    wave_lds_sync();
+                }
+                T += membership_term_window(Ps, plen, kp - p0, lane, pcarry, K, crs);
+                wave_lds_sync();
+            }
+            // as tiled_finish, with T summed over P's windows
+            const int sp = a2p > 0 ? 1 : -1, sq = a2q > 0 ? 1 : -1;
+            const double tot = wave_sum((double)(sp * sq) * (T + accP + accQ + accM - (double)a2q * accK));
+            if (w.pw < 0) {
+                const double inter2 = tot + (double)(sp * (wkp - sq * K)) * (double)a2p +
+                                      (double)(sq * wkq) * (double)a2q;
+                J = jaccard_of(inter2, a2p, a2q);
+            } else {
+                unit.part = tot;
+                unit.cr = wave_sum(crs);
+                unit.stot = pcarry;
+                unit.kloc = K;
+            }
         }
-        st_pairs++;
-        if (lane == 0) cand_j[w.c] = J;
+        st_pairs += w.pw <= 0;
+        if (lane == 0) {
+            if (w.pw < 0) cand_j[w.c] = J;
+            else hw.units[(int64_t)w.slot * kMultiUnits + w.pw] = unit;
+        }
         // every lane is done with both rings before the next pair restages them
         wave_lds_sync();
     }
@@ -1105,6 +1302,63 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
         unsigned long long *slot = hw.stat_slots + (blockIdx.x % kStatSlots) * 4;
         if (st_pairs) atomicAdd(slot + 0, st_pairs);
         if (st_swept) atomicAdd(slot + 1, st_swept);
+    }
+}
+
+// One wavefront per split pair: the anchors' memberships, then the P
+// windows' sums in window order with the crossing signs of the earlier
+// windows carried into each (deterministic), then J.
+__global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__restrict__ dxy,
+                                                            const int32_t *__restrict__ qxy,
+                                                            const int64_t *__restrict__ qoff,
+                                                            double *__restrict__ cand_j, HeavyWs hw)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t count = min((int64_t)hw.count[2], (int64_t)kMultiCap);
+    for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; s < count; s += nw) {
+        const MultiPair mp = hw.multi[s];
+        if (mp.c < 0) continue;
+        // the roles of k_refine_wide
+        const int64_t qa = qoff[mp.q];
+        const int mq = (int)(qoff[mp.q + 1] - qa);
+        const bool swap = mp.n > kWideCap && mp.n > mq;
+        const int32_t *Pg = swap ? qxy + 2 * qa : dxy + 2 * mp.pa;
+        const int32_t *Qg = swap ? dxy + 2 * mp.pa : qxy + 2 * qa;
+        const int n = swap ? mq : mp.n, m = swap ? mp.n : mq;
+        const int64_t ox = Qg[0], oy = Qg[1];
+        int32_t qm[4], pm[4];
+        poly_mbr(Qg, m, lane, qm);
+        poly_mbr(Pg, n, lane, pm);
+        const int64_t a2q = poly_area2(Qg, m, ox, oy, lane);
+        const int64_t a2p = poly_area2(Pg, n, ox, oy, lane);
+        double J = 0.0;
+        if (a2p != 0 && a2q != 0) {
+            int qext[4];
+            extremes_global(Qg, m, qm, lane, qext);
+            const int kq = anchor_q(qm, pm, qext);
+            int kp = first_outside_global(Pg, n, qm, lane);
+            int wkp = 0, wkq = 0;
+            if (kp < 0) {
+                const int2 p0 = make_int2((int)((int64_t)Pg[0] - ox), (int)((int64_t)Pg[1] - oy));
+                wkp = member_point_global(Qg, m, ox, oy, p0, -1, lane);
+                kp = 0;
+            }
+            if (kq < 0) wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
+            const int sp = a2p > 0 ? 1 : -1, sq = a2q > 0 ? 1 : -1;
+            const int pk = kp / kWideCap;
+            double total = 0.0;
+            int carry = 0, K = 0;
+            for (int u = 0; u < mp.units; u++) {
+                const MultiUnit U = hw.units[s * kMultiUnits + u];
+                total += U.part + (double)(sp * sq) * U.cr * (double)carry;
+                if (u == pk) K = carry + U.kloc;
+                carry += U.stot;
+            }
+            const double inter2 = total + (double)(sp * (wkp - sq * K)) * (double)a2p + (double)(sq * wkq) * (double)a2q;
+            J = jaccard_of(inter2, a2p, a2q);
+        }
+        if (lane == 0) cand_j[mp.c] = J;
     }
 }
 
@@ -1168,13 +1422,15 @@ HeavyWs carve_heavy(Carve &cv)
     hw.partial = cv.take<double>((size_t)kHeavyCap * 2 * kHeavySlices);
     hw.stat_slots = cv.take<unsigned long long>(kStatSlots * 4);
     hw.wide = cv.take<WidePair>(kWideListCap);
+    hw.multi = cv.take<MultiPair>(kMultiCap);
+    hw.units = cv.take<MultiUnit>((size_t)kMultiCap * kMultiUnits);
     return hw;
 }
 
-// Clears the two pair counts and the counter slots (256 threads).
+// Clears the three pair counts and the counter slots (256 threads).
 __global__ void k_zero_count(int32_t *p, unsigned long long *slots)
 {
-    if (threadIdx.x < 2) p[threadIdx.x] = 0;
+    if (threadIdx.x < 3) p[threadIdx.x] = 0;
     if (threadIdx.x < kStatSlots * 4) slots[threadIdx.x] = 0;
 }
 
@@ -1232,6 +1488,9 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
     hipLaunchKernelGGL(k_refine_wide, dim3(1024), dim3(64), 0, s, data->xy, queries->xy, queries->offsets, cand_j,
                        hw, stats ? 1 : 0);
     if ((st = check_launch("refine: wide pairs"))) return st;
+    hipLaunchKernelGGL(k_refine_multi_finish, dim3(64), dim3(256), 0, s, data->xy, queries->xy, queries->offsets,
+                       cand_j, hw);
+    if ((st = check_launch("refine: split wide pairs"))) return st;
     // deferred heavy pairs: a grid that covers every (pair, side, slice) of a
     // full list in a few rounds, then the per-pair sums
     hipLaunchKernelGGL(k_heavy, dim3(2048), dim3(256), 0, s, data->xy, queries->xy, hw);

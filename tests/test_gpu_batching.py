@@ -88,9 +88,10 @@ def test_autotuner_choice_is_bit_identical(pm, tmp_path, monkeypatch):
 
 def test_graph_replays_binned_signing_and_split_pairs(pm, orc):
     # the batch pipeline with binned query signing, over polygons large
-    # enough that refinement splits pairs over wavefronts: graph replays and
-    # eager runs equal the plain calls (walked signatures, refinement), and
-    # the batch's top-10 equals the oracle's for one batch
+    # enough that refinement defers pairs to its windowed launches (a pair
+    # of two 1,510-vertex polygons split over two windows): graph replays
+    # and eager runs equal the plain calls (walked signatures, refinement),
+    # and the batch's top-10 equals the oracle's for one batch
     import torch
     from paper_2511_16576_amd.pipeline import QueryBatch
     rng = np.random.default_rng(17)
@@ -110,14 +111,19 @@ def test_graph_replays_binned_signing_and_split_pairs(pm, orc):
                     binned={"horizon": h, "bin_bits": b, "walk_ratio": 300.0})
     qb.load(batches[0])
     qb.capture()
-    split_seen = 0
+    deferred_seen = split_seen = 0
+    dcount = w.data.counts()
     for rep in range(2):
         for x in batches:
             Q = pm.to_device(x)
             qk = pm.band(pm.sign(Q, w.box, w.seed, k, cap), bands, rows, w.seed)
             off, ids = pm.query(sk, se, D.n, qk)
             J, st = pm.refine_stats(D, Q, off, ids)
-            split_seen += st[2]
+            n = dcount[ids.cpu().numpy()]
+            m = np.repeat(x.counts(), np.diff(off.cpu().numpy()))
+            deferred_seen += int((np.maximum(n, m) > 512).sum())
+            split_seen += int(((n > 1024) & (m > 1024)).sum())
+            assert st[0] == ids.numel() and st[2] == 0     # all on the tiled forms
             ti, tj = pm.topk(off, ids, J, 10)
             qb.load(x)
             torch.cuda.synchronize()
@@ -127,7 +133,7 @@ def test_graph_replays_binned_signing_and_split_pairs(pm, orc):
             qb.run_eager()
             ei, ej = qb.result()
             assert torch.equal(ei, ti) and torch.equal(ej, tj)
-    assert split_seen > 0
+    assert deferred_seen > 0 and split_seen > 0
     # the oracle's top-10 of the first batch over the same candidates
     x = batches[0]
     oq = orc.band(orc.sign(x, w.box, w.seed, k, cap), bands, rows, w.seed)

@@ -221,10 +221,11 @@ def test_refine_large_polygons_general_path(pm, orc):
 
 
 def test_refine_heavy_pairs_split(pm, orc):
-    # with the workspace, general-form pairs with n m >= 2^17 edge pairs are
-    # split over many wavefronts and pairs of at most 1024 edges a side move
-    # to the tiled form: the values equal the oracle's and the in-place
-    # form's, and the work counts move by exactly those pairs
+    # with the workspace, every pair with coordinate spans below 2^26 takes
+    # the tiled form (in windows beyond 1024 edges) where the in-place call
+    # takes the general form beyond 512 edges: the values equal the oracle's
+    # and the in-place form's, and the work counts move by exactly those
+    # pairs
     import torch
     rng = np.random.default_rng(8)
     data = dg.star_polygons(rng, [600, 1500, 40, 2000, 3000], [[50000, 50000]] * 5, [40000.0] * 5)
@@ -240,22 +241,24 @@ def test_refine_heavy_pairs_split(pm, orc):
     assert np.all(np.abs(got - inplace.cpu().numpy()) <= REL * np.abs(want) + ABS)
     n = data.counts()[ids.cpu().numpy()]
     m = np.repeat(queries.counts(), 5)
-    big = np.maximum(n, m)
-    moved = (big > 512) & (big <= 1024)
-    assert moved.sum() == 3 and (big > 1024).sum() > 0
+    moved = np.maximum(n, m) > 512
+    assert moved.sum() == 19 and ((n > 1024) & (m > 1024)).sum() == 6
+    assert st_split[0] == 20 and st_split[2] == 0
     assert st_split[0] == st_inplace[0] + moved.sum()
-    assert st_inplace[2] - st_split[2] == int((2 * n * m)[moved].sum())
+    assert st_inplace[2] == int((2 * n * m)[moved].sum())
     assert st_split[3] == st_inplace[3]
 
 
 def test_refine_more_heavy_pairs_than_the_split_list(pm):
-    # 8,400 heavy pairs (1,100 x 130 edges: beyond the tiled forms, n m >=
-    # 2^17): the first 8,192 are split, the rest run in place; every value
-    # equals the in-place form's
+    # 8,400 heavy pairs (400 x 400 edges, n m >= 2^17, coordinate spans
+    # beyond 2^26, so the general form with 128-bit signs): the first 8,192
+    # are split, the rest run in place; every value equals the in-place
+    # form's
     import torch
     rng = np.random.default_rng(9)
-    data = dg.star_polygons(rng, [1100] * 120, [[50000 + 50 * i, 50000] for i in range(120)], [30000.0] * 120)
-    queries = dg.star_polygons(rng, [130] * 70, [[51000, 49000 + 30 * i] for i in range(70)], [30000.0] * 70)
+    big = float(1 << 26)
+    data = dg.star_polygons(rng, [400] * 120, [[50000 * i, 0] for i in range(120)], [big] * 120)
+    queries = dg.star_polygons(rng, [400] * 70, [[0, 40000 * i] for i in range(70)], [big] * 70)
     D, Q = pm.to_device(data), pm.to_device(queries)
     off = torch.arange(71, dtype=torch.int64, device="cuda") * 120
     ids = torch.arange(120, dtype=torch.int32, device="cuda").repeat(70)
@@ -264,6 +267,25 @@ def test_refine_more_heavy_pairs_than_the_split_list(pm):
     assert (inplace > 0.2).all()
     assert np.all(np.abs(split - inplace) <= 1e-12 + 1e-12 * np.abs(inplace))
 
+
+def test_refine_more_split_pairs_than_the_split_list(pm):
+    # 8,400 pairs of two 1,100-edge polygons: each is split over its two
+    # P windows (one wavefront each, added up by the finish) while split
+    # slots last (8,192), the rest take both windows on one wavefront;
+    # every value equals the general form's (the call without workspace)
+    import torch
+    rng = np.random.default_rng(14)
+    data = dg.star_polygons(rng, [1100] * 120, [[50000 + 50 * i, 50000] for i in range(120)], [30000.0] * 120)
+    queries = dg.star_polygons(rng, [1100] * 70, [[51000, 49000 + 30 * i] for i in range(70)], [30000.0] * 70)
+    D, Q = pm.to_device(data), pm.to_device(queries)
+    off = torch.arange(71, dtype=torch.int64, device="cuda") * 120
+    ids = torch.arange(120, dtype=torch.int32, device="cuda").repeat(70)
+    split, st = pm.refine_stats(D, Q, off, ids)
+    split = split.cpu().numpy()
+    inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy()
+    assert (inplace > 0.2).all()
+    assert np.all(np.abs(split - inplace) <= REL * np.abs(inplace) + ABS), np.abs(split - inplace).max()
+    assert st[0] == 8400 and st[2] == 0
 
 def test_refine_heavy_pairs_wide_coordinates(pm, orc):
     # large pairs whose coordinate span needs the 128-bit orientation form,
@@ -345,6 +367,69 @@ def test_refine_wide_tiled_degenerate_contacts(pm, orc):
         (tri, sq6, Fraction(1, 2)),
         (sq, np.array([[L // 2, 0], [L, L // 2], [L // 2, L], [0, L // 2]]), Fraction(1, 2)),  # vertices on edges
     ]
+    D = dg.from_list([c[0] for c in cases])
+    Q = dg.from_list([c[1] for c in cases])
+    off = np.arange(len(cases) + 1, dtype=np.int64)
+    ids = np.arange(len(cases), dtype=np.int32)
+    got = _refine(pm, D, Q, off, ids)
+    for j, (_, _, want) in enumerate(cases):
+        assert abs(got[j] - float(want)) <= 1e-12, (j, got[j], want)
+    want = orc.jaccard_candidates(D, Q, off, ids)
+    assert np.all(np.abs(want - np.array([float(c[2]) for c in cases])) <= 1e-9)
+
+
+def test_refine_windowed_pairs(pm, orc):
+    # a polygon of at most 1024 edges against one of any length: the small
+    # one is staged whole (the query when the data polygon is the larger),
+    # the other passes in windows of 1024 edges (2,048: two full windows;
+    # 1,025: a last window of one edge); pairs with both beyond 1024 edges
+    # stay on the general form
+    import torch
+    rng = np.random.default_rng(13)
+    data = dg.star_polygons(rng, [3000, 20, 1025, 2048, 700, 8], [[50000, 50000]] * 6, [40000.0] * 6)
+    queries = dg.star_polygons(rng, [40, 5000, 1100, 300, 1025], [[52000, 49000]] * 5, [38000.0] * 5)
+    D, Q = pm.to_device(data), pm.to_device(queries)
+    off = torch.arange(6, dtype=torch.int64, device="cuda") * 6
+    ids = torch.arange(6, dtype=torch.int32, device="cuda").repeat(5)
+    got, st = pm.refine_stats(D, Q, off, ids)
+    inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy()
+    want = orc.jaccard_candidates(data, queries, off.cpu().numpy(), ids.cpu().numpy())
+    got = got.cpu().numpy()
+    assert (want > 0.2).sum() >= 25
+    assert np.all(np.abs(got - want) <= REL * np.abs(want) + ABS), np.abs(got - want).max()
+    assert np.all(np.abs(inplace - want) <= REL * np.abs(want) + ABS)
+    n = data.counts()[ids.cpu().numpy()]
+    m = np.repeat(queries.counts(), 6)
+    assert ((n > 1024) & (m > 1024)).sum() == 9     # windows on both sides
+    assert st[0] == 30 and st[2] == 0
+
+
+def test_refine_windowed_degenerate_contacts(pm, orc):
+    # exact J with a 3,200-vertex square (800 collinear vertices a side, four
+    # windows) on either side of the pair: shared and collinear edges,
+    # corners, T-junctions, vertices on edges, a small square inside it (no
+    # vertex of the small polygon outside the other's MBR) and a square
+    # around it (no vertex of the large one outside the other's MBR)
+    L = 1600
+    big = _subdivided_rect(0, 0, L, L, 800)
+    others = [
+        (dg.rectangle(0, 0, L, L), Fraction(1)),
+        (_subdivided_rect(0, 0, L, L, 200), Fraction(1)),
+        (_subdivided_rect(L, 0, 2 * L, L, 200), Fraction(0)),                   # shared edge
+        (dg.rectangle(L, L, 2 * L, 2 * L), Fraction(0)),                        # shared corner
+        (_subdivided_rect(L // 2, 0, L // 2 + L, L, 200), Fraction(1, 3)),      # collinear overlaps
+        (dg.rectangle(0, 0, L // 2, L // 2), Fraction(1, 4)),                   # nested, shared corner
+        (dg.rectangle(320, 0, 1280, L), Fraction(60, 100)),                     # T-junctions
+        (np.array([[L // 2, 0], [L, L // 2], [L // 2, L], [0, L // 2]]), Fraction(1, 2)),  # vertices on edges
+        (dg.rectangle(400, 400, 800, 800), Fraction(1, 16)),                    # inside, away from the edges
+        (dg.rectangle(-10, -10, L + 10, L + 10), Fraction(L * L, (L + 20) ** 2)),  # around it
+    ]
+    # the large square as the query, then as the data polygon; then both
+    # large (windows on both sides)
+    cases = [(o, big, j) for o, j in others] + [(big, o, j) for o, j in others] + [
+        (big, big, Fraction(1)), (big, big[::-1], Fraction(1)), (big, np.roll(big, 1234, axis=0), Fraction(1)),
+        (big, _subdivided_rect(L // 2, 0, L // 2 + L, L, 800), Fraction(1, 3)),
+        (big, _subdivided_rect(L, 0, 2 * L, L, 800), Fraction(0))]
     D = dg.from_list([c[0] for c in cases])
     Q = dg.from_list([c[1] for c in cases])
     off = np.arange(len(cases) + 1, dtype=np.int64)
