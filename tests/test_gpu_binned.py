@@ -150,3 +150,26 @@ def test_binned_empty_set_and_invalid(pm):
     with pytest.raises(pm.PolymhError) as e:
         pm.sign_binned(D, (0, 0, 15, 15), 0, 8, 100, horizon=100, bin_bits=2, walk_ratio=-1.0)
     assert e.value.status == pm.EINVAL
+
+
+def test_binned_split_and_unsplit_launches_agree(pm, orc):
+    # the same workload-5 polygons signed in one launch of 40,000 (one
+    # workgroup per polygon) and in launches of 2,000 and 300 (small
+    # polygons' chunks split over several workgroups, joined by an atomic
+    # minimum): identical, and equal to the walk and, on a sample, the oracle
+    import torch
+    w = dg.workload(5, n=40000, n_queries=0)
+    k, cap = 64, 1 << 26
+    D = pm.to_device(w.data)
+    h, b = pm.binned_params(D, w.box, k, cap)
+    whole = pm.sign_binned(D, w.box, w.seed, k, cap, horizon=h, bin_bits=b, walk_ratio=0.0)
+    walk = pm.sign(D, w.box, w.seed, k, cap)
+    assert torch.equal(whole, walk)
+    for size in (2000, 300):
+        for a in range(0, 6000, size):
+            sub = w.data.subset(np.arange(a, a + size))
+            part = pm.sign_binned(pm.to_device(sub), w.box, w.seed, k, cap, horizon=h, bin_bits=b, walk_ratio=0.0)
+            assert torch.equal(part, whole[a:a + size]), (size, a)
+    rows = np.random.default_rng(4).choice(w.data.n, 24, replace=False)
+    want = orc.sign(w.data.subset(rows), w.box, w.seed, k, cap)
+    assert np.array_equal(whole.cpu().numpy().view(np.uint32)[rows], want)
