@@ -193,8 +193,11 @@ polymh_status polymh_join_rings(const int32_t *xy, int64_t n_vertices, const int
  *            times the largest N_B / N_P of the set leaves almost no walk.
  *   bin_bits grid side 2^bin_bits, 0..6 (cells near the typical MBR size).
  *   walk_ratio polygons with |B| < walk_ratio * area (an expected first hit
- *            near N_B / N_P below walk_ratio) are walked whole instead; 0
- *            bins every polygon.  A few hundred suits the walk's cost per draw.
+ *            near N_B / N_P below walk_ratio) are walked whole instead, and
+ *            so are those whose walk is expected to cost fewer edge tests
+ *            than their lookup (many edges and an MBR holding many of a
+ *            chunk's samples); 0 bins every polygon.  A few hundred suits
+ *            the walk's cost per draw.  The signatures do not depend on it.
  *   cfg      as polymh_sign for the walk (its persistent form); hash_block
  *            is also the number of hashes each lookup lane signs (default 8).
  *   ws       polymh_sign_binned_workspace_size(...) bytes: about

@@ -380,18 +380,37 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     }
 }
 
-// Flags: 2 for a polygon to walk whole (|B| < walk_ratio * area, with twice
-// the area exact from prepare), else 0.  Degenerate polygons stay with the
-// lookup, which signs them 0 at once.
+// Flags: 2 for a polygon to walk whole, else 0 (twice the area exact from
+// prepare).  With walk_ratio > 0 a polygon is walked when |B| < walk_ratio x
+// area, or when its walk is expected to cost less than its lookup, in edge
+// tests per hash: the walk draws about |B| / area points (kDrawTests edge
+// tests each) and tests the about A_mbr / area of them inside the MBR against
+// its n edges; the lookup tests every sample of the hit's chunk that lies in
+// the MBR, about max(1, C A_mbr / |B|), against its n edges.  Either way the
+// signature is the same.  Degenerate polygons stay with the lookup, which
+// signs them 0 at once.
+constexpr double kDrawTests = 5.0;
+
 __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ area2,
-                                                  const uint32_t *__restrict__ flags, int64_t n,
-                                                  double box_area, double walk_ratio,
+                                                  const uint32_t *__restrict__ flags,
+                                                  const int64_t *__restrict__ off,
+                                                  const int32_t *__restrict__ mbr, int64_t n,
+                                                  double box_area, double walk_ratio, double chunk,
                                                   uint32_t *__restrict__ unresolved)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const bool degenerate = (flags[p] & (kFlagFew | kFlagCollinear)) != 0;
         const double area = 0.5 * (double)(area2[p] < 0 ? -area2[p] : area2[p]);
-        unresolved[p] = (!degenerate && box_area < walk_ratio * area) ? 2u : 0u;
+        bool walk = false;
+        if (!degenerate && walk_ratio > 0.0 && area > 0.0) {
+            const int4 m = *reinterpret_cast<const int4 *>(mbr + 4 * p);
+            const double a_mbr = ((double)m.z - (double)m.x + 1.0) * ((double)m.w - (double)m.y + 1.0);
+            const double edges = (double)(off[p + 1] - off[p]);
+            const double walk_cost = kDrawTests * box_area / area + edges * a_mbr / area;
+            const double bin_cost = edges * fmax(1.0, chunk * a_mbr / box_area);
+            walk = box_area < walk_ratio * area || walk_cost < bin_cost;
+        }
+        unresolved[p] = walk ? 2u : 0u;
     }
 }
 
@@ -503,8 +522,8 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
     polymh_status st = check_launch("sign_binned: bin");
     if (st) return st;
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.flags, L.n,
-                       (double)wx * (double)wy, walk_ratio, w.unresolved);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.flags, L.off, L.mbr, L.n,
+                       (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), w.unresolved);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(w.count), (int64_t)1);
     LookupArgs A{};
     A.xy = L.xy;
