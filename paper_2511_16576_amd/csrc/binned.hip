@@ -160,12 +160,45 @@ __device__ __forceinline__ bool inside_lane(const int4 *s_edges, const int32_t *
     return odd;
 }
 
+// Crossing-number test of each lane's point against edges read from memory
+// 64 at a time, one edge per lane in one coalesced load, and handed to every
+// lane by readlane (a load per edge made each step wait on memory).  Every
+// lane of the wavefront takes part.
+__device__ __forceinline__ bool inside_stream_block(const int32_t *pxy, int32_t n, int32_t px, int32_t py,
+                                                    int lane)
+{
+    bool odd = false;
+    for (int e0 = 0; e0 < n; e0 += 64) {
+        const int e = e0 + lane < n ? e0 + lane : 0;
+        const int f = (e + 1 == n) ? 0 : e + 1;
+        const int2 a = *reinterpret_cast<const int2 *>(pxy + 2 * e);
+        const int2 b = *reinterpret_cast<const int2 *>(pxy + 2 * f);
+        const int4 ed = make_edge(a.x, a.y, b.x, b.y);
+        const int cnt = min(64, n - e0);
+        for (int t = 0; t < cnt; t++) {
+            const int4 et = make_int4(__builtin_amdgcn_readlane(ed.x, t), __builtin_amdgcn_readlane(ed.y, t),
+                                      __builtin_amdgcn_readlane(ed.z, t), __builtin_amdgcn_readlane(ed.w, t));
+            odd ^= crosses_fp64(et, px, py);
+        }
+    }
+    return odd;
+}
+
 // Test up to 64 queued points (lane = entry) and lower the owners' best index.
 template <int MODE>
 __device__ __forceinline__ void drain(const LookupArgs &A, const int4 *s_edges, const int32_t *pxy,
                                       int32_t n, const uint32_t *qm, const uint32_t *qx, const uint32_t *qy,
                                       int head, int count, uint32_t chunk_base, uint32_t *s_best, int lane)
 {
+    if constexpr (MODE == kTestStream) {
+        // all lanes load the edge blocks; lanes past count test entry head
+        const int q = (head + (lane < count ? lane : 0)) & (kQueue - 1);
+        const uint32_t meta = qm[q];
+        const int32_t px = (int32_t)((uint32_t)A.bx0 + qx[q]), py = (int32_t)((uint32_t)A.by0 + qy[q]);
+        const bool in = inside_stream_block(pxy, n, px, py, lane);
+        if (lane < count && in) atomicMin(&s_best[meta >> 12], chunk_base + (meta & 0xfffu));
+        return;
+    }
     if (lane < count) {
         const int q = (head + lane) & (kQueue - 1);
         const uint32_t meta = qm[q];
