@@ -250,10 +250,11 @@ polymh_status polymh_index_build(const uint64_t *keys, int64_t n, int32_t b, voi
  *   n_data is the number of indexed polygons (ids are < n_data).
  *   ws: polymh_query_workspace_size(n_data, nq) bytes (device, caller-owned,
  *   contents overwritten): a bitmap row of n_data bits per query plus two
- *   words per query.  With n_data >= 2^19 a query whose buckets hold at most
- *   4096 entries gathers and sorts them on chip and leaves its row unused;
- *   the others (and every query of a smaller data set) set bits in their
- *   row.  The lists are the same either way.  Stream-ordered except the
+ *   words per query.  When the rows add up to 1 GiB or more (rows of at
+ *   least 16 KB), a query whose buckets hold at most 4096 entries gathers
+ *   and sorts them on chip and leaves its row unused; the others (and every
+ *   query of a smaller call) set bits in their row.  The lists are the same
+ *   either way.  Stream-ordered except the
  *   capacity check above.
  */
 size_t polymh_query_workspace_size(int64_t n_data, int64_t nq);

@@ -304,9 +304,16 @@ QueryWs carve_query(Carve &cv, int64_t nq, int64_t words)
 
 // Lengths of every query's list into counts (the sparse pass, then the
 // bitmap rows of the dense queries).
-// Bitmap rows of at least this many words (data sets of 2^19 polygons and
-// more) cost more to clear and read than gathering and sorting a short list.
-constexpr int64_t kSparseMinWords = 1 << 14;
+// The bitmap is cleared, counted and read whole: once it passes 1 GiB (with
+// rows of 16 KB and more) that costs more than gathering and sorting the
+// queries' lists, and the lists are taken on chip where they fit.
+constexpr int64_t kSparseMinBytes = (int64_t)1 << 30;
+constexpr int64_t kSparseMinWords = 1 << 12;
+
+__host__ __device__ inline bool use_sparse(int64_t nq, int64_t words)
+{
+    return words >= kSparseMinWords && nq * words * 4 >= kSparseMinBytes;
+}
 
 __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t count, int32_t v)
 {
@@ -318,7 +325,7 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t count, int
 void lookup_counts(const uint64_t *skeys, const int32_t *sids, int64_t n_entries, int64_t words,
                    const uint64_t *qkeys, int64_t nq, int32_t b, const QueryWs &w, int64_t *counts, hipStream_t s)
 {
-    if (words >= kSparseMinWords)
+    if (use_sparse(nq, words))
         hipLaunchKernelGGL(k_sparse<0>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, skeys, sids, n_entries,
                            qkeys, nq, b, w.dense, counts, nullptr, nullptr);
     else
@@ -336,7 +343,7 @@ void lookup_emit(const uint64_t *skeys, const int32_t *sids, int64_t n_entries, 
                  const uint64_t *qkeys, int64_t nq, int32_t b, const QueryWs &w, int64_t *off, int32_t *ids,
                  const int32_t *overflow, hipStream_t s)
 {
-    if (words >= kSparseMinWords)
+    if (use_sparse(nq, words))
         hipLaunchKernelGGL(k_sparse<1>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, skeys, sids, n_entries,
                            qkeys, nq, b, w.dense, off, ids, overflow);
     if (words > 0)

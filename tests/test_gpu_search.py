@@ -59,38 +59,45 @@ def test_query_matches_brute_force(pm, orc):
 
 
 def test_query_large_data_set_sparse_lists(pm, orc):
-    # 600,000 data polygons (bitmap rows of 18,750 words): a query's bucket
-    # entries are gathered and sorted on chip, and a query whose buckets hold
-    # more than 4,096 entries (5,000 polygons sharing every key) falls back
-    # to its bitmap row; both lookup phases and the capped lookup equal the
-    # brute-force definition, and a capacity one short raises the flag and
-    # leaves cand_ids untouched
+    # 600,000 data polygons and 15,000 queries (bitmap rows of 18,750 words,
+    # 1.1 GB in all): a query's bucket entries are gathered and sorted on
+    # chip, and a query whose buckets hold more than 4,096 entries (5,000
+    # polygons sharing every key) falls back to its bitmap row; on sampled
+    # queries both lookup phases and the capped lookup equal the oracle's
+    # candidates, and a capacity one short raises the flag and leaves
+    # cand_ids untouched
     import torch
     rng = np.random.default_rng(21)
-    nd, b = 600_000, 8
+    nd, b, nq0 = 600_000, 8, 14_998
     dk = rng.integers(0, 200_000, (nd, b)).astype(np.uint64)
     popular = np.arange(b, dtype=np.uint64) + np.uint64(10 ** 9)
     dk[rng.choice(nd, 5000, replace=False)] = popular
-    src = rng.choice(nd, 60, replace=False)
-    qk = dk[src].copy()
+    qk = dk[rng.integers(0, nd, nq0)].copy()
     qk[::2, :b // 2] += np.uint64(10 ** 7)        # half the bands never match on even queries
     qk = np.concatenate([qk, popular[None, :], popular[None, :] + np.uint64(10 ** 8)])
     nq = qk.shape[0]
+    sample = np.concatenate([np.sort(rng.choice(nq0, 62, replace=False)), [nq - 2, nq - 1]])
+    ooff, oids = orc.candidates(dk, qk[sample])
+    want = [oids[ooff[i]:ooff[i + 1]] for i in range(sample.size)]
+    assert want[-2].size == 5000 and want[-1].size == 0
     sk, si = pm.index_build(_t(dk.view(np.int64)))
     qkd = _t(qk.view(np.int64))
+
+    def check(off, ids):
+        for i, q in enumerate(sample):
+            assert np.array_equal(ids[off[q]:off[q + 1]], want[i]), q
     off, ids = pm.query(sk, si, nd, qkd)
-    ooff, oids = orc.candidates(dk, qk)
-    assert np.array_equal(off.cpu().numpy(), ooff)
-    assert np.array_equal(ids.cpu().numpy(), oids)
-    assert ooff[-2] - ooff[-3] == 5000 and ooff[-1] == ooff[-2]
-    total = int(ooff[-1])
+    off, ids = off.cpu().numpy(), ids.cpu().numpy()
+    check(off, ids)
+    total = int(off[-1])
     ws = torch.empty(int(pm.lib().polymh_query_workspace_size(nd, nq)), dtype=torch.uint8, device="cuda")
+    assert ws.numel() > (1 << 30)
     coff = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
     flag = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     cids = torch.full((total,), -7, dtype=torch.int32, device="cuda")
     pm.query_capped(sk, si, nd, qkd, coff, cids, flag, ws)
     assert int(flag.item()) == 0
-    assert np.array_equal(coff.cpu().numpy(), ooff) and np.array_equal(cids.cpu().numpy(), oids)
+    assert np.array_equal(coff.cpu().numpy(), off) and np.array_equal(cids.cpu().numpy(), ids)
     short = torch.full((total - 1,), -7, dtype=torch.int32, device="cuda")
     pm.query_capped(sk, si, nd, qkd, coff, short, flag, ws)
     assert int(flag.item()) == 1
