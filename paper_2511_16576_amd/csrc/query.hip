@@ -335,8 +335,9 @@ void lookup_counts(const uint64_t *skeys, const int32_t *sids, int64_t n_entries
         if (n_entries > 0)
             hipLaunchKernelGGL(k_mark, dim3(blocks_for(nq * b, 4)), dim3(256), 0, s, skeys, sids, n_entries,
                                qkeys, nq, b, w.bitmap, words, w.dense);
-        hipLaunchKernelGGL(k_count, dim3((unsigned)nq), dim3(256), 0, s, w.bitmap, words, counts, w.dense);
     }
+    // also with no data (a zero count per query)
+    hipLaunchKernelGGL(k_count, dim3((unsigned)nq), dim3(256), 0, s, w.bitmap, words, counts, w.dense);
 }
 
 void lookup_emit(const uint64_t *skeys, const int32_t *sids, int64_t n_entries, int64_t words,

@@ -46,7 +46,7 @@ def test_index_build_is_stable_sort(pm):
 
 def test_query_matches_brute_force(pm, orc):
     rng = np.random.default_rng(1)
-    for nd, nq, b, vals in [(500, 40, 6, 5), (3000, 17, 16, 50), (64, 3, 2, 2), (5, 0, 3, 4)]:
+    for nd, nq, b, vals in [(500, 40, 6, 5), (3000, 17, 16, 50), (64, 3, 2, 2), (5, 0, 3, 4), (0, 4, 3, 4)]:
         dk = rng.integers(0, vals, (nd, b)).astype(np.uint64)
         qk = rng.integers(0, vals, (nq, b)).astype(np.uint64)
         qk[:, 0] += 10 ** 6                 # band 0 never matches
