@@ -121,3 +121,29 @@ def test_invalid_shapes_raise(pm):
     rs.xy = rs.xy[:4]
     with pytest.raises(ValueError):
         pm.join_rings(pm.rings_to_device(rs))
+
+
+def test_refine_large_rings_windowed(pm, orc):
+    # joined shapes of about 500 to 3,000 vertices (components of 500-1,400
+    # with holes and bridges): pairs beyond 512 edges take the tiled form in
+    # windows (split over windows beyond 1,024 a side) and equal the ring
+    # oracle and the general form (the call without workspace)
+    import torch
+    rng = np.random.default_rng(15)
+    data = dg.ring_polygons(rng, 12, 16, lambda r, m: r.integers(500, 1400, m), 0.04, 0.12)
+    queries = _moved(data, rng)
+    D = pm.join_rings(pm.rings_to_device(data))
+    Q = pm.join_rings(pm.rings_to_device(queries))
+    nd = np.diff(D.offsets.cpu().numpy())
+    assert nd.min() < 1024 < nd.max()
+    off = torch.arange(Q.n + 1, dtype=torch.int64, device="cuda") * D.n
+    ids = torch.arange(D.n, dtype=torch.int32, device="cuda").repeat(Q.n)
+    got, st = pm.refine_stats(D, Q, off, ids)
+    got = got.cpu().numpy().reshape(Q.n, D.n)
+    inplace = pm.refine(D, Q, off, ids, split_heavy=False).cpu().numpy().reshape(Q.n, D.n)
+    want = np.array([[orr.jaccard_rings(data.rings(p), queries.rings(q)) for p in range(D.n)]
+                     for q in range(Q.n)])
+    err = np.abs(got - want)
+    assert np.all(err <= REL * np.abs(want) + ABS), (err.max(), np.unravel_index(np.argmax(err), err.shape))
+    assert np.all(np.abs(inplace - want) <= REL * np.abs(want) + ABS)
+    assert (np.diag(want) > 0.2).sum() >= 8 and st[2] == 0
