@@ -258,12 +258,13 @@ __device__ __forceinline__ void scan_row(const LookupArgs &A, const int4 *s_edge
 
 // Lane = hash i.  Chunks in order; a lane stops after the first chunk with a
 // hit, the wavefront when all its lanes have.
-// Chunks [c0, c1) only; with `seen` (a split polygon) a lane also stops once
-// another segment has recorded an earlier hit there.
+// Chunks [c0, c1) only; with `seen` (a split polygon) a lane records its hit
+// there as soon as it finds it, and stops once another segment has recorded
+// an earlier one.
 template <int MODE>
 __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const int32_t *pxy, int32_t n,
                                Scan &S, int cx0, int cx1, int cy0, int cy1, int i, bool active, int lane,
-                               uint32_t &best, int c0, int c1, const uint32_t *seen)
+                               uint32_t &best, int c0, int c1, uint32_t *seen)
 {
     const int cells = 1 << (2 * A.bits);
     const int rows = cy1 - cy0 + 1;
@@ -306,7 +307,10 @@ __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const i
             wave_sync_lds();
         }
         wave_sync_lds();
-        if (open) best = S.s_best[lane];
+        if (open) {
+            best = S.s_best[lane];
+            if (seen != nullptr && best != kNone) atomicMin(&seen[i], best);
+        }
     }
 }
 
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     // a wavefront with no hash of its own skips the lookup (uniform per wave)
     uint32_t best = 0u;
     const int ic = active ? i : 0;
-    const uint32_t *seen = segs > 1 ? out : nullptr;
+    uint32_t *seen = segs > 1 ? out : nullptr;
     if (__ballot(active) != 0 && c0 < c1) {
         if (mode == kTestLds)
             lookup_polygon<kTestLds>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best, c0, c1, seen);
