@@ -424,8 +424,13 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
 // tests each) and tests the about A_mbr / area of them inside the MBR against
 // its n edges; the lookup tests every sample of the hit's chunk that lies in
 // the MBR, about max(1, C A_mbr / |B|), against its n edges.  Either way the
-// signature is the same.  Degenerate polygons stay with the lookup, which
-// signs them 0 at once.
+// signature is the same.  In a large launch (one with no split polygons) a
+// polygon beyond the lookup's LDS edge cache (walk_edges) is walked too: the
+// lookup tests up to 64 points a wavefront at a time against its edges one
+// after another, a long serial loop, where the walk splits each test over
+// the lanes; in a small launch the walk of a few such polygons would set its
+// duration.  Degenerate polygons stay with the lookup, which signs them 0 at
+// once.
 constexpr double kDrawTests = 5.0;
 
 __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ area2,
@@ -433,7 +438,7 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ ar
                                                   const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ mbr, int64_t n,
                                                   double box_area, double walk_ratio, double chunk,
-                                                  uint32_t *__restrict__ unresolved)
+                                                  double walk_edges, uint32_t *__restrict__ unresolved)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const bool degenerate = (flags[p] & (kFlagFew | kFlagCollinear)) != 0;
@@ -445,7 +450,7 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ ar
             const double edges = (double)(off[p + 1] - off[p]);
             const double walk_cost = kDrawTests * box_area / area + edges * a_mbr / area;
             const double bin_cost = edges * fmax(1.0, chunk * a_mbr / box_area);
-            walk = box_area < walk_ratio * area || walk_cost < bin_cost;
+            walk = box_area < walk_ratio * area || walk_cost < bin_cost || edges > walk_edges;
         }
         unresolved[p] = walk ? 2u : 0u;
     }
@@ -559,8 +564,18 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
     polymh_status st = check_launch("sign_binned: bin");
     if (st) return st;
+    // a launch of few workgroups lasts as long as its slowest polygon (the
+    // smallest, whose hits lie deepest): there, such polygons are split over
+    // up to 32 workgroups; large launches keep one per polygon and group
+    const int64_t waves = (L.k + 63) / 64 < 4 ? (L.k + 63) / 64 : 4;
+    const int64_t per = 64 * waves, groups = (L.k + per - 1) / per;
+    const int64_t units = L.n * groups;
+    int32_t split = 1;
+    if (units < 32768) split = (int32_t)std::min<int64_t>(32, std::max<int64_t>(2, (1 << 18) / std::max<int64_t>(units, 1)));
+    const double walk_edges = split > 1 ? 1e300 : (double)L.cfg.lds_edges;
     hipLaunchKernelGGL(k_classify, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.flags, L.off, L.mbr, L.n,
-                       (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), w.unresolved);
+                       (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), walk_edges,
+                       w.unresolved);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(w.count), (int64_t)1);
     LookupArgs A{};
     A.xy = L.xy;
@@ -583,14 +598,6 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     A.sby = B.sby;
     A.bx0 = L.box.xmin; A.by0 = L.box.ymin; A.bx1 = L.box.xmax; A.by1 = L.box.ymax;
     A.lds_edges = L.cfg.lds_edges;
-    const int64_t waves = (L.k + 63) / 64 < 4 ? (L.k + 63) / 64 : 4;
-    const int64_t per = 64 * waves, groups = (L.k + per - 1) / per;
-    // a launch of few workgroups lasts as long as its slowest polygon (the
-    // smallest, whose hits lie deepest): there, such polygons are split over
-    // up to 32 workgroups; large launches keep one per polygon and group
-    const int64_t units = L.n * groups;
-    int32_t split = 1;
-    if (units < 32768) split = (int32_t)std::min<int64_t>(32, std::max<int64_t>(2, (1 << 18) / std::max<int64_t>(units, 1)));
     A.split = split;
     A.area2 = area2;
     A.box_area = (double)wx * (double)wy;
