@@ -446,7 +446,9 @@ polymh_status polymh_scatter_scores(const int64_t *idx, const float *val, int64_
  * candidates are refined fully in their given order.  top_ids/top_j as in
  * polymh_topk.  *n_refined_host and *rounds_host (nullable, host) receive the
  * number of refined pairs and rounds.  SYNCHRONISES the stream once per
- * round.  ws: polymh_rank_workspace_size(nq, n_cand, F) bytes. */
+ * round.  Each round refines as polymh_refine_ws (pairs beyond 512 edges on
+ * the windowed tiled form).  ws: polymh_rank_workspace_size(nq, n_cand, F)
+ * bytes (it includes the refinement's workspace). */
 size_t polymh_rank_workspace_size(int64_t nq, int64_t n_cand, int32_t F);
 polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *queries,
                                  const int64_t *cand_off, const int32_t *cand_ids,

@@ -595,6 +595,7 @@ struct RankWs {
     int64_t *cursor, *roff;
     int32_t *rids, *rpos, *n_active;
     double *rj;
+    char *refine_ws;      // the refinement's own workspace (pairs beyond 512 edges deferred)
 };
 
 static RankWs carve_rank(Carve &c, int64_t nq, int64_t n_cand, int32_t F)
@@ -610,6 +611,7 @@ static RankWs carve_rank(Carve &c, int64_t nq, int64_t n_cand, int32_t F)
     w.rpos = c.take<int32_t>(per_round);
     w.rj = c.take<double>(per_round);
     w.n_active = c.take<int32_t>(1);
+    w.refine_ws = c.take<char>(refine_workspace_bytes());
     return w;
 }
 
@@ -657,7 +659,9 @@ polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *q
         if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "rank_refine: %s", hipGetErrorString(e));
         if (total == 0) break;
         refined += total;
-        if ((st = launch_refine(data, queries, w.roff, w.rids, nq, total, w.rj, s))) return st;
+        if ((st = launch_refine(data, queries, w.roff, w.rids, nq, total, w.rj, s, nullptr, w.refine_ws,
+                                refine_workspace_bytes())))
+            return st;
         if ((st = launch_round_merge(cand_off, score, w.order, w.sorted_ok, w.roff, w.rids, w.rj, nq,
                                      topk, margin, w.cursor, w.active, top_ids, top_j, w.n_active, s)))
             return st;
