@@ -194,16 +194,25 @@ def _prefix(off, ids, n):
 
 
 def learned_comparison(w, D, Q, log, n_pairs=2_000_000, epochs=3, bands=64, rows=4, n_calib=1000,
-                       n_eval=1000, reps=3, F=16, target=0.95):
+                       n_eval=1000, reps=3, F=16, target=0.95, sig=None, brute=None):
     """Plain full refinement vs best-first refinement with early stop ordered
-    by the collision fraction or by the trained scorer, on the learned-scorer
-    workload (workload-2 polygons signed at k = 256)."""
+    by the collision fraction or by the trained scorer: the learned-scorer
+    workload (workload-2 polygons signed at k = 256), or another one given
+    its dataset signatures at k = 256 (``sig``) and a brute-force top-10
+    (``brute(D, Q) -> (ids, J)``; default: every pair refined).  The early
+    stop is calibrated to recall@10 >= ``target`` on the calibration queries,
+    or, with ``target`` None, to the plain pipeline's own recall there less
+    0.01 (for a workload whose plain recall stays below any fixed target)."""
     from .metrics import recall_at_k
     k, cap = K_SCORER, w.cap
     dev = D.offsets.device
+    brute = brute_force_top10 if brute is None else brute
     out = {"k": k, "bands": bands, "rows": rows, "train_pairs": n_pairs, "epochs": epochs}
     t0 = time.perf_counter()
-    sig = pm.sign(D, w.box, w.seed, k, cap)
+    if sig is None:
+        sig = pm.sign(D, w.box, w.seed, k, cap)
+    elif sig.shape[1] != k:
+        raise ValueError(f"learned_comparison: signatures of {k} hashes expected")
     feats = pm.poly_features(D, w.box)
     keys8 = pm.band(sig, 32, 8, w.seed)
     sk8, se8 = pm.index_build(keys8)
@@ -249,13 +258,17 @@ def learned_comparison(w, D, Q, log, n_pairs=2_000_000, epochs=3, bands=64, rows
     cal = pm.to_device(w.queries.subset(np_.arange(n_calib)))
     ev = pm.to_device(w.queries.subset(np_.arange(n_calib, n_calib + n_eval)))
     cal_f, ev_f = qfeats[:n_calib].contiguous(), qfeats[n_calib:n_calib + n_eval].contiguous()
-    bci, bcj = brute_force_top10(D, cal)
-    bei, bej = brute_force_top10(D, ev)
-    bci, bcj, bei, bej = (x.cpu().numpy() for x in (bci, bcj, bei, bej))
+    bci, bcj = brute(D, cal)
+    bei, bej = brute(D, ev)
+    bci, bcj, bei, bej = (x.cpu().numpy() if torch.is_tensor(x) else x for x in (bci, bcj, bei, bej))
     grid = [0.0, 0.005, 0.01, 0.015, 0.02, 0.025, 0.03, 0.04, 0.05, 0.06, 0.08, 0.1, 0.15, 0.2, 0.3, 0.5]
     res = {}
     for method in ("plain", "collision_fraction", "scorer"):
         margin = float("inf")
+        if method == "plain" and target is None:
+            ti, tj, _ = run(method, cal, cal_f, margin)
+            target = recall_at_k(ti.cpu().numpy(), tj.cpu().numpy(), bci, bcj, 10) - 0.01
+            out["target_recall_at_10"] = target
         if method != "plain":
             for m in grid:
                 ti, tj, _ = run(method, cal, cal_f, m)
