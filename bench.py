@@ -425,12 +425,12 @@ def main():
             binned["workload5"]["pipeline"] = cfg5_pipeline(w5, D5, sig_b5, par5, cfg, dev)
             if not args.no_learned:
                 # the learned scorer against the plain pipeline on workload 5
-                # (64 x 4 bands; early stop calibrated to the plain recall)
+                # (64 x 4 bands; early stop calibrated to recall@10 >= 0.95)
                 from paper_2511_16576_amd import metrics
                 from paper_2511_16576_amd import scorer as sc
                 binned["workload5"]["learned"] = sc.learned_comparison(
                     w5, D5, pm.to_device(w5.queries), log, n_pairs=args.train_pairs, epochs=args.epochs,
-                    n_calib=200, n_eval=200, target=None, sig=sig_b5,
+                    n_calib=200, n_eval=200, sig=sig_b5,
                     brute=lambda D_, Q_: metrics.brute_force_topk_mbr(D_, Q_, 10))
         del sig_b5, D5
 

@@ -200,9 +200,8 @@ def learned_comparison(w, D, Q, log, n_pairs=2_000_000, epochs=3, bands=64, rows
     workload (workload-2 polygons signed at k = 256), or another one given
     its dataset signatures at k = 256 (``sig``) and a brute-force top-10
     (``brute(D, Q) -> (ids, J)``; default: every pair refined).  The early
-    stop is calibrated to recall@10 >= ``target`` on the calibration queries,
-    or, with ``target`` None, to the plain pipeline's own recall there less
-    0.01 (for a workload whose plain recall stays below any fixed target)."""
+    stop is calibrated to recall@10 >= ``target`` on the calibration
+    queries."""
     from .metrics import recall_at_k
     k, cap = K_SCORER, w.cap
     dev = D.offsets.device
@@ -265,10 +264,6 @@ def learned_comparison(w, D, Q, log, n_pairs=2_000_000, epochs=3, bands=64, rows
     res = {}
     for method in ("plain", "collision_fraction", "scorer"):
         margin = float("inf")
-        if method == "plain" and target is None:
-            ti, tj, _ = run(method, cal, cal_f, margin)
-            target = recall_at_k(ti.cpu().numpy(), tj.cpu().numpy(), bci, bcj, 10) - 0.01
-            out["target_recall_at_10"] = target
         if method != "plain":
             for m in grid:
                 ti, tj, _ = run(method, cal, cal_f, m)
