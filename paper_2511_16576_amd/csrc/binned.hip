@@ -124,15 +124,7 @@ struct LookupArgs {
     int32_t nchunks, lchunk, bits, sbx, sby;
     int32_t bx0, by0, bx1, by1;
     int32_t lds_edges;
-    // small launches: a polygon's chunks split over up to `split` workgroups
-    int32_t split;
-    const int64_t *area2;          // twice the polygons' areas (exact)
-    double box_area;               // |B| in lattice points
-    int32_t *seg_done;             // [n * groups] segments finished (split > 1)
 };
-
-// Chunks a segment of a split polygon aims to cover.
-constexpr int kSegChunks = 4;
 
 enum TestMode { kTestLds = 0, kTestStream = 1, kTestWide = 2 };
 
@@ -258,21 +250,16 @@ __device__ __forceinline__ void scan_row(const LookupArgs &A, const int4 *s_edge
 
 // Lane = hash i.  Chunks in order; a lane stops after the first chunk with a
 // hit, the wavefront when all its lanes have.
-// Chunks [c0, c1) only; with `seen` (a split polygon) a lane records its hit
-// there as soon as it finds it, and stops once another segment has recorded
-// an earlier one.
 template <int MODE>
 __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const int32_t *pxy, int32_t n,
                                Scan &S, int cx0, int cx1, int cy0, int cy1, int i, bool active, int lane,
-                               uint32_t &best, int c0, int c1, uint32_t *seen)
+                               uint32_t &best)
 {
     const int cells = 1 << (2 * A.bits);
     const int rows = cy1 - cy0 + 1;
     best = active ? kNone : 0u;
-    for (int c = c0; c < c1; c++) {
-        bool open = active && best == kNone;
-        // a stale (larger) value only delays the stop
-        if (seen != nullptr && open) open = seen[i] > ((uint32_t)c << A.lchunk);
+    for (int c = 0; c < A.nchunks; c++) {
+        const bool open = active && best == kNone;
         if (__ballot(open) == 0) break;
         S.s_best[lane] = kNone;
         S.head = S.tail = 0;
@@ -307,10 +294,7 @@ __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const i
             wave_sync_lds();
         }
         wave_sync_lds();
-        if (open) {
-            best = S.s_best[lane];
-            if (seen != nullptr && best != kNone) atomicMin(&seen[i], best);
-        }
+        if (open) best = S.s_best[lane];
     }
 }
 
@@ -325,10 +309,8 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int per = blockDim.x;
     const int groups = (A.k + per - 1) / per;
-    const int64_t unit = blockIdx.x / A.split;
-    const int seg = (int)(blockIdx.x % A.split);
-    const int64_t p = unit / groups;
-    const int i = (int)(unit % groups) * per + tid;
+    const int64_t p = blockIdx.x / groups;
+    const int i = (int)(blockIdx.x % groups) * per + tid;
     const bool active = i < A.k;
     if (A.unresolved[p] & 2u) return;    // walked (uniform per workgroup, before any barrier)
     const int64_t a = A.off[p];
@@ -339,24 +321,9 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     const bool empty = (fl & (kFlagFew | kFlagCollinear)) || mb.z < A.bx0 || mb.x > A.bx1 ||
                        mb.w < A.by0 || mb.y > A.by1;
     if (empty) {
-        if (active && seg == 0) out[i] = 0u;
+        if (active) out[i] = 0u;
         return;
     }
-    // segments: a polygon expected to need many chunks (its first hit for one
-    // hash lies about |B| / area samples in; the last of k hashes a few times
-    // further) is split into contiguous chunk ranges, the last one open-ended
-    int segs = 1, c0 = 0, c1 = A.nchunks;
-    if (A.split > 1) {
-        const double area = 0.5 * fabs((double)A.area2[p]);
-        const double e = area > 0.0 ? A.box_area / area / (double)(1 << A.lchunk) : (double)A.nchunks;
-        const double need = fmin((double)A.nchunks, 6.0 * e + 1.0);
-        segs = (int)fmin((double)A.split, ceil(need / (double)kSegChunks));
-        segs = segs < 1 ? 1 : segs;
-        const int len = (int)ceil(need / (double)segs);
-        c0 = min(A.nchunks, seg * len);
-        c1 = seg == segs - 1 ? A.nchunks : min(A.nchunks, (seg + 1) * len);
-    }
-    if (seg >= segs) return;                // uniform per workgroup
     const int32_t *pxy = A.xy + 2 * a;
     const int mode = (fl & kFlagWide) ? kTestWide : (n <= A.lds_edges ? kTestLds : kTestStream);
     if (mode == kTestLds) {
@@ -383,37 +350,18 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     // a wavefront with no hash of its own skips the lookup (uniform per wave)
     uint32_t best = 0u;
     const int ic = active ? i : 0;
-    uint32_t *seen = segs > 1 ? out : nullptr;
-    if (__ballot(active) != 0 && c0 < c1) {
+    if (__ballot(active) != 0) {
         if (mode == kTestLds)
-            lookup_polygon<kTestLds>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best, c0, c1, seen);
+            lookup_polygon<kTestLds>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best);
         else if (mode == kTestStream)
-            lookup_polygon<kTestStream>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best, c0, c1,
-                                        seen);
+            lookup_polygon<kTestStream>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best);
         else
-            lookup_polygon<kTestWide>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best, c0, c1,
-                                      seen);
-    }
-    if (segs > 1) {
-        // the segments' earliest hit gathers in out (preset to kNone); the
-        // last segment to finish turns it into the signature value
-        __shared__ int s_last;
-        if (active && best != kNone) atomicMin(&out[i], best);
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) s_last = atomicAdd(&A.seg_done[unit], 1) == segs - 1;
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-        best = active ? atomicOr(&out[i], 0u) : 0u;
+            lookup_polygon<kTestWide>(A, s_edges, pxy, n, S, cx0, cx1, cy0, cy1, ic, active, lane, best);
     }
     if (active) {
         if (best != kNone) out[i] = best + 1;
         else if (A.horizon >= A.cap) out[i] = 0u;
-        else {
-            if (segs > 1) out[i] = 0u;
-            atomicOr(&A.unresolved[p], 1u);
-        }
+        else atomicOr(&A.unresolved[p], 1u);
     }
 }
 
@@ -424,12 +372,10 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
 // tests each) and tests the about A_mbr / area of them inside the MBR against
 // its n edges; the lookup tests every sample of the hit's chunk that lies in
 // the MBR, about max(1, C A_mbr / |B|), against its n edges.  Either way the
-// signature is the same.  In a large launch (one with no split polygons) a
-// polygon beyond the lookup's LDS edge cache (walk_edges) is walked too: the
-// lookup tests up to 64 points a wavefront at a time against its edges one
-// after another, a long serial loop, where the walk splits each test over
-// the lanes; in a small launch the walk of a few such polygons would set its
-// duration.  Degenerate polygons stay with the lookup, which signs them 0 at
+// signature is the same.  A polygon beyond the lookup's LDS edge cache
+// (walk_edges) is walked too: the lookup tests up to 64 points a wavefront at
+// a time against its edges one after another, a long serial loop, where the
+// walk splits each test over the lanes.  Degenerate polygons stay with the lookup, which signs them 0 at
 // once.
 constexpr double kDrawTests = 5.0;
 
@@ -470,11 +416,6 @@ __global__ __launch_bounds__(256) void k_zero_words(uint32_t *p, int64_t count)
         p[t] = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_fill_words(uint32_t *p, int64_t count, uint32_t v)
-{
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
-        p[t] = v;
-}
 
 int ceil_log2(uint64_t w)
 {
@@ -501,7 +442,6 @@ struct BinnedWs {
     uint16_t *sj, *cell_off;
     uint32_t *unresolved;
     int32_t *list, *count;
-    int32_t *seg_done;
 };
 
 BinnedWs carve_binned(Carve &c, int32_t k, int64_t nchunks, int32_t bits, int64_t n)
@@ -515,7 +455,6 @@ BinnedWs carve_binned(Carve &c, int32_t k, int64_t nchunks, int32_t bits, int64_
     w.unresolved = c.take<uint32_t>((size_t)n);
     w.list = c.take<int32_t>((size_t)n);
     w.count = c.take<int32_t>(1);
-    w.seg_done = c.take<int32_t>((size_t)n * (size_t)((k + 255) / 256 + 1));
     return w;
 }
 
@@ -564,15 +503,11 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
     polymh_status st = check_launch("sign_binned: bin");
     if (st) return st;
-    // a launch of few workgroups lasts as long as its slowest polygon (the
-    // smallest, whose hits lie deepest): there, such polygons are split over
-    // up to 32 workgroups; large launches keep one per polygon and group
+    // one workgroup per (polygon, group of up to 256 hashes)
     const int64_t waves = (L.k + 63) / 64 < 4 ? (L.k + 63) / 64 : 4;
     const int64_t per = 64 * waves, groups = (L.k + per - 1) / per;
     const int64_t units = L.n * groups;
-    int32_t split = 1;
-    if (units < 32768) split = (int32_t)std::min<int64_t>(32, std::max<int64_t>(2, (1 << 18) / std::max<int64_t>(units, 1)));
-    const double walk_edges = split > 1 ? 1e300 : (double)L.cfg.lds_edges;
+    const double walk_edges = (double)L.cfg.lds_edges;
     hipLaunchKernelGGL(k_classify, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.flags, L.off, L.mbr, L.n,
                        (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), walk_edges,
                        w.unresolved);
@@ -598,17 +533,8 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     A.sby = B.sby;
     A.bx0 = L.box.xmin; A.by0 = L.box.ymin; A.bx1 = L.box.xmax; A.by1 = L.box.ymax;
     A.lds_edges = L.cfg.lds_edges;
-    A.split = split;
-    A.area2 = area2;
-    A.box_area = (double)wx * (double)wy;
-    A.seg_done = w.seg_done;
-    const int64_t grid = units * split;
+    const int64_t grid = units;
     if (grid > 0x7fffffff) return set_error(POLYMH_EINVAL, "sign_binned: too many work items");
-    if (split > 1) {
-        hipLaunchKernelGGL(k_fill_words, dim3(grid_for(L.n * L.k)), dim3(256), 0, s, L.sig, L.n * (int64_t)L.k, kNone);
-        hipLaunchKernelGGL(k_zero_words, dim3(grid_for(units)), dim3(256), 0, s,
-                           reinterpret_cast<uint32_t *>(w.seg_done), units);
-    }
     const size_t lds = (size_t)L.cfg.lds_edges * sizeof(int4);
     hipLaunchKernelGGL(k_bin_lookup, dim3((unsigned)grid), dim3((unsigned)per), lds, s, A);
     if ((st = check_launch("sign_binned: lookup"))) return st;

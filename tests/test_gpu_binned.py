@@ -152,11 +152,11 @@ def test_binned_empty_set_and_invalid(pm):
     assert e.value.status == pm.EINVAL
 
 
-def test_binned_split_and_unsplit_launches_agree(pm, orc):
-    # the same workload-5 polygons signed in one launch of 40,000 (one
-    # workgroup per polygon) and in launches of 2,000 and 300 (small
-    # polygons' chunks split over several workgroups, joined by an atomic
-    # minimum): identical, and equal to the walk and, on a sample, the oracle
+def test_binned_large_and_small_launches_agree(pm, orc):
+    # the same workload-5 polygons signed in one launch of 40,000 and in
+    # launches of 2,000 and 300 (walk_ratio 0: every polygon from the bins,
+    # those beyond the edge cache with their edges read in blocks of 64):
+    # identical, and equal to the walk and, on a sample, the oracle
     import torch
     w = dg.workload(5, n=40000, n_queries=0)
     k, cap = 64, 1 << 26
