@@ -547,6 +547,10 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     W.order = w.list;
     W.n_dev = w.count;
     W.cfg.persistent = 1;
+    // the few polygons left to the walk are the costly ones (many edges or
+    // deep hits): 16 hashes a work item, so one polygon's hashes spread over
+    // many workgroups instead of four wavefronts
+    if (W.cfg.hash_block <= 0 || W.cfg.hash_block > 16) W.cfg.hash_block = 16;
     return launch_sign(W, s);
 }
 
