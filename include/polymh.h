@@ -198,8 +198,10 @@ polymh_status polymh_join_rings(const int32_t *xy, int64_t n_vertices, const int
  *            than their lookup (many edges and an MBR holding many of a
  *            chunk's samples); 0 bins every polygon.  A few hundred suits
  *            the walk's cost per draw.  The signatures do not depend on it.
- *   cfg      as polymh_sign for the walk (its persistent form); hash_block
- *            is also the number of hashes each lookup lane signs (default 8).
+ *   cfg      as polymh_sign for the walk of the polygons left to it (its
+ *            persistent form, at most 16 hashes a work item); lds_edges is
+ *            also the lookup's edge cache (polygons beyond it are walked
+ *            when walk_ratio > 0).
  *   ws       polymh_sign_binned_workspace_size(...) bytes: about
  *            10 * k * horizon bytes of binned samples.
  * POLYMH_EINVAL for k > 65535, bin_bits outside 0..6, horizon < 1 or a
