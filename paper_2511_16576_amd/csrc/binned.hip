@@ -547,10 +547,12 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     W.order = w.list;
     W.n_dev = w.count;
     W.cfg.persistent = 1;
-    // the few polygons left to the walk are the costly ones (many edges or
-    // deep hits): 16 hashes a work item, so one polygon's hashes spread over
-    // many workgroups instead of four wavefronts
-    if (W.cfg.hash_block <= 0 || W.cfg.hash_block > 16) W.cfg.hash_block = 16;
+    // in a small launch the few polygons left to the walk are the costly
+    // ones (many edges or deep hits) and set its duration: 16 hashes a work
+    // item spread one polygon's hashes over many workgroups instead of four
+    // wavefronts (in a large launch that only multiplies the staging of the
+    // many cheap walks of large polygons)
+    if (units < 32768 && (W.cfg.hash_block <= 0 || W.cfg.hash_block > 16)) W.cfg.hash_block = 16;
     return launch_sign(W, s);
 }
 
