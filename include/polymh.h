@@ -213,6 +213,19 @@ polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint
                                  uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio, uint32_t *sig,
                                  const polymh_sign_config *cfg, void *ws, size_t ws_bytes, void *stream);
 
+/* polymh_sign_binned_prebinned -- polymh_sign_binned without drawing and
+ * binning the samples: ws must hold the bins of an earlier
+ * polymh_sign_binned call on this device with the same workspace, polygon
+ * count, box, seed, k, cap, horizon, bin_bits and cfg (only the polygons'
+ * coordinates may differ), as a batch of queries signed again and again.
+ * The bins depend on none of the polygons, so the signatures equal
+ * polymh_sign's.  Not checked: a workspace without those bins gives wrong
+ * signatures (every read stays inside the workspace).  Stream-ordered. */
+polymh_status polymh_sign_binned_prebinned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                           uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio,
+                                           uint32_t *sig, const polymh_sign_config *cfg, void *ws, size_t ws_bytes,
+                                           void *stream);
+
 /* ---------------------------------------------------------------------------
  * polymh_band -- LSH band keys over the signatures (Sec. 3.2 puts polygons in
  * a hashmap keyed by their MinHash code; the banded form follows the MMDS

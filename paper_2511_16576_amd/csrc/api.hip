@@ -281,9 +281,10 @@ size_t polymh_sign_binned_workspace_size(int64_t n, int32_t k, uint32_t cap, uin
     return align_up(cv.used, 256) + binned_workspace_bytes(k, horizon, bin_bits, n) + 256;
 }
 
-polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
-                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio, uint32_t *sig,
-                                 const polymh_sign_config *cfg, void *ws, size_t ws_bytes, void *stream)
+static polymh_status sign_binned_impl(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                      uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio,
+                                      uint32_t *sig, const polymh_sign_config *cfg, void *ws, size_t ws_bytes,
+                                      void *stream, bool rebin)
 {
     polymh_status st = check_polys(polys, "sign_binned");
     if (st) return st;
@@ -325,7 +326,24 @@ polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint
     L.cfg = c;
     if (used > ws_bytes) return set_error(POLYMH_ECAPACITY, "sign_binned: workspace too small");
     return launch_sign_binned(L, w.area2, horizon, bin_bits, walk_ratio, static_cast<char *>(ws) + used,
-                              ws_bytes - used, s);
+                              ws_bytes - used, s, rebin);
+}
+
+polymh_status polymh_sign_binned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                 uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio, uint32_t *sig,
+                                 const polymh_sign_config *cfg, void *ws, size_t ws_bytes, void *stream)
+{
+    return sign_binned_impl(polys, box, seed, k, cap, horizon, bin_bits, walk_ratio, sig, cfg, ws, ws_bytes, stream,
+                            true);
+}
+
+polymh_status polymh_sign_binned_prebinned(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                           uint32_t cap, uint32_t horizon, int32_t bin_bits, double walk_ratio,
+                                           uint32_t *sig, const polymh_sign_config *cfg, void *ws, size_t ws_bytes,
+                                           void *stream)
+{
+    return sign_binned_impl(polys, box, seed, k, cap, horizon, bin_bits, walk_ratio, sig, cfg, ws, ws_bytes, stream,
+                            false);
 }
 
 polymh_status polymh_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,

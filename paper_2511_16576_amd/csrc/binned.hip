@@ -256,6 +256,7 @@ __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const i
                                uint32_t &best)
 {
     const int cells = 1 << (2 * A.bits);
+    const int C = 1 << A.lchunk;
     const int rows = cy1 - cy0 + 1;
     best = active ? kNone : 0u;
     for (int c = 0; c < A.nchunks; c++) {
@@ -274,8 +275,8 @@ __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const i
             lo[r] = hi[r] = 0;
             if (open && r < rows) {
                 const int row = (cy0 + r) << A.bits;
-                lo[r] = co[row | cx0];
-                hi[r] = co[(row | cx1) + 1];
+                lo[r] = min((int)co[row | cx0], C);
+                hi[r] = min((int)co[(row | cx1) + 1], C);
             }
         }
 #pragma unroll
@@ -283,7 +284,7 @@ __device__ void lookup_polygon(const LookupArgs &A, const int4 *s_edges, const i
             if (r < rows) scan_row<MODE>(A, s_edges, pxy, n, S, base, lo[r], hi[r], chunk_base, lane);
         for (int r = 4; r < rows; r++) {
             const int row = (cy0 + r) << A.bits;
-            const int l = open ? (int)co[row | cx0] : 0, h = open ? (int)co[(row | cx1) + 1] : 0;
+            const int l = open ? min((int)co[row | cx0], C) : 0, h = open ? min((int)co[(row | cx1) + 1], C) : 0;
             scan_row<MODE>(A, s_edges, pxy, n, S, base, l, h, chunk_base, lane);
         }
         while (S.tail > S.head) {
@@ -469,7 +470,7 @@ size_t binned_workspace_bytes(int32_t k, uint32_t horizon, int32_t bits, int64_t
 }
 
 polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint32_t horizon, int32_t bits,
-                                 double walk_ratio, void *ws, size_t ws_bytes, hipStream_t s)
+                                 double walk_ratio, void *ws, size_t ws_bytes, hipStream_t s, bool rebin)
 {
     const uint64_t wx = (uint64_t)((int64_t)L.box.xmax - L.box.xmin + 1);
     const uint64_t wy = (uint64_t)((int64_t)L.box.ymax - L.box.ymin + 1);
@@ -499,8 +500,13 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     B.sj = w.sj;
     B.cell_off = w.cell_off;
     const size_t bin_lds = 2 * (((size_t)1 << (2 * bits)) + 1) * sizeof(int);
-    if (pow2) hipLaunchKernelGGL(k_bin<true>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
-    else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
+    // without rebin the workspace already holds these bins (an earlier call
+    // with the same arguments); the lookup clamps every cell range to its
+    // chunk, so bins that are not there give wrong values, never a stray read
+    if (rebin) {
+        if (pow2) hipLaunchKernelGGL(k_bin<true>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
+        else hipLaunchKernelGGL(k_bin<false>, dim3((unsigned)nchunks, (unsigned)L.k), dim3(kBinThreads), bin_lds, s, B);
+    }
     polymh_status st = check_launch("sign_binned: bin");
     if (st) return st;
     // one workgroup per (polygon, group of up to 256 hashes)

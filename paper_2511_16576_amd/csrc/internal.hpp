@@ -210,7 +210,7 @@ polymh_status launch_join_rings(const int32_t *xy, int64_t nv, const int64_t *ri
 // binned.hip
 size_t binned_workspace_bytes(int32_t k, uint32_t horizon, int32_t bits, int64_t n);
 polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint32_t horizon, int32_t bits,
-                                 double walk_ratio, void *ws, size_t ws_bytes, hipStream_t s);
+                                 double walk_ratio, void *ws, size_t ws_bytes, hipStream_t s, bool rebin = true);
 
 // band.hip
 polymh_status launch_band(const uint32_t *sig, int64_t n, int32_t k, int32_t b, int32_t r,

@@ -29,6 +29,7 @@ class QueryBatch:
         self.Q = pm.DevicePolys(self.xy, self.off)
         self.sig = torch.empty((n_queries, k), dtype=torch.int32, device=dev)
         self.binned = binned
+        self._binned_ready = False
         if binned is None:
             ws = pm.sign_workspace_size(n_queries, self.cfg)
         else:
@@ -61,10 +62,13 @@ class QueryBatch:
             pm.sign(self.Q, self.box, self.seed, self.k, self.cap, config=self.cfg, out=self.sig,
                     ws=self.ws_sign, stream=s)
         else:
+            # the samples are binned by the first run only: they depend on
+            # none of the query polygons
             b = self.binned
             pm.sign_binned(self.Q, self.box, self.seed, self.k, self.cap, horizon=b["horizon"],
                            bin_bits=b["bin_bits"], walk_ratio=b.get("walk_ratio", 300.0), config=self.cfg,
-                           out=self.sig, ws=self.ws_sign, stream=s)
+                           out=self.sig, ws=self.ws_sign, stream=s, rebin=not self._binned_ready)
+            self._binned_ready = True
         pm.band(self.sig, self.bands, self.rows, self.seed, out=self.keys, stream=s)
         pm.query_capped(self.sk, self.se, self.D.n, self.keys, self.cand_off, self.cand_ids,
                         self.overflow, self.ws_query, stream=s)

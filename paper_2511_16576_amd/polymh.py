@@ -66,6 +66,7 @@ _SIGNATURES = {
     "polymh_join_rings": (I32, [P, I64, P, I64, P, I64, P, I64, P, P, P]),
     "polymh_sign_binned_workspace_size": (SZ, [I64, I32, U32, U32, I32, P]),
     "polymh_sign_binned": (I32, [P, Box, U64, I32, U32, U32, I32, ctypes.c_double, P, P, P, SZ, P]),
+    "polymh_sign_binned_prebinned": (I32, [P, Box, U64, I32, U32, U32, I32, ctypes.c_double, P, P, P, SZ, P]),
     "polymh_band": (I32, [P, I64, I32, I32, I32, U64, P, P]),
     "polymh_index_workspace_size": (SZ, [I64, I32]),
     "polymh_index_build": (I32, [P, I64, I32, P, SZ, P, P, P]),
@@ -352,11 +353,15 @@ def sign_binned_workspace_size(n: int, k: int, cap: int, horizon: int, bin_bits:
 def sign_binned(polys: DevicePolys, box, seed: int, k: int, cap: int, horizon: int | None = None,
                 bin_bits: int | None = None, walk_ratio: float = 300.0, config: SignConfig | None = None,
                 out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
-                stream=None) -> torch.Tensor:
+                stream=None, rebin: bool = True) -> torch.Tensor:
     """Alg. 1 signatures from shared binned samples (equal to ``sign``'s, bit
     for bit).  ``horizon`` / ``bin_bits`` default to ``binned_params``;
-    polygons with |B| / area below ``walk_ratio`` are walked instead."""
+    polygons with |B| / area below ``walk_ratio`` are walked instead.
+    ``rebin=False`` reuses the bins already in ``ws`` from an earlier call
+    with the same workspace and arguments (``polymh_sign_binned_prebinned``)."""
     check_device()
+    if not rebin and ws is None:
+        raise ValueError("sign_binned: rebin=False needs the workspace that holds the bins")
     dev = polys.offsets.device
     n = polys.n
     if horizon is None or bin_bits is None:
@@ -370,9 +375,9 @@ def sign_binned(polys: DevicePolys, box, seed: int, k: int, cap: int, horizon: i
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
     ps = polys.cstruct()
-    _check(lib().polymh_sign_binned(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, horizon,
-                                    bin_bits, float(walk_ratio), _ptr(out), ctypes.byref(config) if config else None,
-                                    _ptr(ws), ws.numel(), _stream(stream)))
+    fn = lib().polymh_sign_binned if rebin else lib().polymh_sign_binned_prebinned
+    _check(fn(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, horizon, bin_bits, float(walk_ratio),
+              _ptr(out), ctypes.byref(config) if config else None, _ptr(ws), ws.numel(), _stream(stream)))
     return out[:n]
 
 

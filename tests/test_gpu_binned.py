@@ -173,3 +173,20 @@ def test_binned_large_and_small_launches_agree(pm, orc):
     rows = np.random.default_rng(4).choice(w.data.n, 24, replace=False)
     want = orc.sign(w.data.subset(rows), w.box, w.seed, k, cap)
     assert np.array_equal(whole.cpu().numpy().view(np.uint32)[rows], want)
+
+
+def test_binned_prebinned_reuses_the_bins(pm, orc):
+    # the bins drawn by one call (they depend on box, seed, k and horizon
+    # only) serve later calls on other polygons of the same count in the same
+    # workspace: each call's signatures equal the walk's
+    import torch
+    w = dg.workload(5, n=3000, n_queries=0)
+    k, cap = 64, 1 << 26
+    sets = [pm.to_device(w.data.subset(np.arange(a, a + 1000))) for a in (0, 1000, 2000)]
+    h, b = pm.binned_params(sets[0], w.box, k, cap)
+    ws = torch.empty(pm.sign_binned_workspace_size(1000, k, cap, h, b), dtype=torch.uint8, device="cuda")
+    for i, P in enumerate(sets):
+        got = pm.sign_binned(P, w.box, w.seed, k, cap, horizon=h, bin_bits=b, ws=ws, rebin=(i == 0))
+        assert torch.equal(got, pm.sign(P, w.box, w.seed, k, cap)), i
+    with pytest.raises(ValueError):
+        pm.sign_binned(sets[0], w.box, w.seed, k, cap, horizon=h, bin_bits=b, rebin=False)
