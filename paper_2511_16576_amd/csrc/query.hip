@@ -94,23 +94,21 @@ __device__ __forceinline__ void wave_lds_fence()
 
 // One wavefront per query (four per block): its bucket entries of the same
 // band gathered in LDS, sorted (bitonic, padded to a power of two with
-// INT32_MAX) and read without repeats.  EMIT 0: dense[q] = 1 when they do
-// not fit (the bitmap takes the query), else 0 and counts[q] = the list's
-// length.  EMIT 1: the list written from off[q], for the other queries,
-// unless the capacity flag is raised.
-template <int EMIT>
+// INT32_MAX) and kept without repeats in the query's own bitmap row, which
+// the list leaves unused (rows hold at least kSparseCap words).  dense[q] =
+// 1 when they do not fit (the bitmap takes the query), else 0 and counts[q]
+// = the list's length.
 __global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ skeys,
                                                 const int32_t *__restrict__ sids, int64_t n_entries,
                                                 const uint64_t *__restrict__ qkeys, int64_t nq, int32_t b,
                                                 int32_t *__restrict__ dense, int64_t *__restrict__ counts,
-                                                int32_t *__restrict__ ids, const int32_t *__restrict__ overflow)
+                                                uint32_t *__restrict__ bitmap, int64_t words)
 {
     __shared__ int32_t lists[4][kSparseCap];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     if (q >= nq) return;                       // wavefront-uniform; no block barriers below
-    if (EMIT && (dense[q] || (overflow && overflow[0]))) return;
     int32_t *L = lists[wave];
     int cnt = 0;
     // lane = band: every lane searches its own key, then the lanes walk their
@@ -146,11 +144,9 @@ __global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ ske
             e++;
         }
     }
-    if (!EMIT) {
-        const bool over = cnt > kSparseCap;
-        if (lane == 0) dense[q] = over ? 1 : 0;
-        if (over) return;
-    }
+    const bool over = cnt > kSparseCap;
+    if (lane == 0) dense[q] = over ? 1 : 0;
+    if (over) return;
     int P = 64;
     while (P < cnt) P <<= 1;
     for (int i = cnt + lane; i < P; i += 64) L[i] = INT32_MAX;
@@ -167,7 +163,7 @@ __global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ ske
             wave_lds_fence();
         }
     }
-    const int64_t base = EMIT ? counts[q] : 0;      // EMIT: counts holds the offsets
+    int32_t *row = reinterpret_cast<int32_t *>(bitmap + q * words);
     int u = 0;
     for (int i0 = 0; i0 < cnt; i0 += 64) {
         const int i = i0 + lane;
@@ -175,14 +171,29 @@ __global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ ske
         const int32_t v = live ? L[i] : 0;
         const bool first = live && (i == 0 || L[i - 1] != v);
         const uint64_t fm = __ballot(first);
-        if (EMIT && first) {
+        if (first) {
             const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
-            ids[base + u + r] = v;
+            row[u + r] = v;
         }
         u += __popcll(fm);
     }
-    if (!EMIT && lane == 0) counts[q] = u;
+    if (lane == 0) counts[q] = u;
+}
+
+// One wavefront per query taken by k_sparse: its list copied from its row to
+// off[q] (nothing when the capacity flag is raised).
+__global__ __launch_bounds__(256) void k_sparse_emit(const uint32_t *__restrict__ bitmap, int64_t words,
+                                                     const int32_t *__restrict__ dense, int64_t nq,
+                                                     const int64_t *__restrict__ off, int32_t *__restrict__ ids,
+                                                     const int32_t *__restrict__ overflow)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (q >= nq || dense[q] || (overflow && overflow[0])) return;
+    const int32_t *row = reinterpret_cast<const int32_t *>(bitmap + q * words);
+    const int64_t base = off[q], n = off[q + 1] - base;
+    for (int64_t i = lane; i < n; i += 64) ids[base + i] = row[i];
 }
 
 // One block per dense query: popcount of its bitmap row.
@@ -309,6 +320,7 @@ QueryWs carve_query(Carve &cv, int64_t nq, int64_t words)
 // queries' lists, and the lists are taken on chip where they fit.
 constexpr int64_t kSparseMinBytes = (int64_t)1 << 30;
 constexpr int64_t kSparseMinWords = 1 << 12;
+static_assert(kSparseMinWords >= kSparseCap, "a sparse list is kept in its query's bitmap row");
 
 __host__ __device__ inline bool use_sparse(int64_t nq, int64_t words)
 {
@@ -326,8 +338,8 @@ void lookup_counts(const uint64_t *skeys, const int32_t *sids, int64_t n_entries
                    const uint64_t *qkeys, int64_t nq, int32_t b, const QueryWs &w, int64_t *counts, hipStream_t s)
 {
     if (use_sparse(nq, words))
-        hipLaunchKernelGGL(k_sparse<0>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, skeys, sids, n_entries,
-                           qkeys, nq, b, w.dense, counts, nullptr, nullptr);
+        hipLaunchKernelGGL(k_sparse, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, skeys, sids, n_entries,
+                           qkeys, nq, b, w.dense, counts, w.bitmap, words);
     else
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nq, 256)), dim3(256), 0, s, w.dense, nq, 1);
     if (words > 0) {
@@ -345,8 +357,8 @@ void lookup_emit(const uint64_t *skeys, const int32_t *sids, int64_t n_entries, 
                  const int32_t *overflow, hipStream_t s)
 {
     if (use_sparse(nq, words))
-        hipLaunchKernelGGL(k_sparse<1>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, skeys, sids, n_entries,
-                           qkeys, nq, b, w.dense, off, ids, overflow);
+        hipLaunchKernelGGL(k_sparse_emit, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, w.bitmap, words, w.dense,
+                           nq, off, ids, overflow);
     if (words > 0)
         hipLaunchKernelGGL(k_emit, dim3((unsigned)nq), dim3(256), 0, s, w.bitmap, words, off, ids, w.dense,
                            overflow);
