@@ -882,7 +882,7 @@ struct MultiUnit {
 
 struct HeavyWs {
     int32_t *count;       // [0] heavy pairs, [1] wide list entries, [2] split pairs recorded (each
-                          // may exceed its cap: the excess ran in place)
+                          // may exceed its cap: the excess ran in place), [3] wide entries taken
     HeavyPair *pairs;     // [kHeavyCap]
     double *partial;      // [kHeavyCap][2][kHeavySlices]
     unsigned long long *stat_slots;   // [kStatSlots][4]
@@ -1209,7 +1209,11 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
     const int lane = threadIdx.x;
     const int64_t count = min((int64_t)hw.count[1], (int64_t)kWideListCap);
     unsigned long long st_pairs = 0, st_swept = 0;
-    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    // entries are taken from a counter as wavefronts come free: their costs
+    // range from one window to many
+    for (;;) {
+        const int64_t i = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 3, 1) : 0);
+        if (i >= count) break;
         const WidePair w = hw.wide[i];
         if (w.c < 0) continue;
         const int64_t qa = qoff[w.q];
@@ -1427,10 +1431,10 @@ HeavyWs carve_heavy(Carve &cv)
     return hw;
 }
 
-// Clears the three pair counts and the counter slots (256 threads).
+// Clears the pair counts, the work counter and the counter slots (256 threads).
 __global__ void k_zero_count(int32_t *p, unsigned long long *slots)
 {
-    if (threadIdx.x < 3) p[threadIdx.x] = 0;
+    if (threadIdx.x < 4) p[threadIdx.x] = 0;
     if (threadIdx.x < kStatSlots * 4) slots[threadIdx.x] = 0;
 }
 
