@@ -850,20 +850,46 @@ constexpr int kWideCap = 1024;
 constexpr int kWideRing = kWideCap + 16;   // ring vertices incl. padding
 constexpr int kWideListCap = 1 << 20;
 
-// A pair whose staged polygon (P's role in k_refine_wide) has more than
-// kWideCap edges is split over its P windows, one wavefront each (up to
-// kMultiUnits); each writes its partial sums and k_refine_multi_finish adds
-// them in window order.  Up to kMultiCap such pairs per call (the rest take
-// all their windows on one wavefront).
-constexpr int kMultiCap = 8192;
-constexpr int kMultiUnits = 64;
+// A pair that spans more than two window pairs (of kWideCap edges a side) is
+// split into units of one wavefront each: P windows of plen edges (the
+// shortest of 256, 512 and kWideCap that keeps the units within
+// kMultiUnits), each walking Q's windows, or, when Q has more than two
+// windows, each (P window, Q window) alone.  Every unit writes its partial
+// sums, all linear in the crossing signs, and k_refine_multi_finish adds them
+// in window order.  Up to kMultiCap such pairs per call (the rest take all
+// their windows on one wavefront).
+constexpr int kMultiCap = 4096;
+constexpr int kMultiUnits = 256;
+constexpr int kSplitMinP = 256;
+
+struct SplitShape {
+    int plen;             // P window length of the units
+    int qs;               // units per P window (Q windows, or 1)
+    int units;            // 1: the pair is not split
+};
+
+// The split of a pair whose staged polygon (P's role) has np edges and the
+// other nq; deterministic, so the wide kernel and the finish recompute it.
+__device__ __forceinline__ SplitShape split_shape(int np, int nq)
+{
+    const int npw = (np + kWideCap - 1) / kWideCap, nqw = (nq + kWideCap - 1) / kWideCap;
+    if (npw * nqw <= 2) return {kWideCap, 1, 1};
+    for (int qs = nqw > 2 ? nqw : 1;; qs = 1) {
+        for (int plen = kSplitMinP; plen <= kWideCap; plen *= 2) {
+            const int units = (np + plen - 1) / plen * qs;
+            if (units <= kMultiUnits) return {plen, qs, units};
+        }
+        if (qs == 1) return {kWideCap, 1, 1};
+    }
+}
 
 struct WidePair {
     int64_t c;            // candidate slot of the result (-1: an unused entry)
     int64_t pa;           // first vertex of the data polygon
     int32_t n;            // its vertex count
     int32_t q;            // query index
-    int32_t pw;           // P window of a split pair, or -1 for all windows
+    int16_t pw;           // P window of a split pair, or -1 for all windows
+    int16_t qw;           // Q window of a pair split on both sides, or -1 for all
     int32_t slot;         // the split pair's slot, or -1
 };
 
@@ -875,7 +901,7 @@ struct MultiPair {
 
 struct MultiUnit {
     double part;          // sp sq x (P window's membership term + crossing sums), summed over the wavefront
-    double cr;            // sum of the window's cross products
+    double cr;            // sum of the P window's cross products (first Q window's unit only)
     int32_t stot;         // sum of the window's crossing signs
     int32_t kloc;         // exclusive prefix of crossing signs at the anchor, if in this window
 };
@@ -891,31 +917,33 @@ struct HeavyWs {
     MultiUnit *units;     // [kMultiCap][kMultiUnits]
 };
 
-// Records a pair for k_refine_wide: one list entry, or, when its staged
-// polygon has more than kWideCap edges, one entry per P window and a split
-// slot.  False when the list is full (entries that did not fit are marked
-// unused).
+// Records a pair for k_refine_wide: one list entry, or, when split_shape
+// splits it, one entry per unit and a split slot.  False when the list is
+// full (entries that did not fit are marked unused).
 __device__ bool defer_wide(const HeavyWs &hw, int64_t c, int64_t pa, int n, int m, int32_t q, int lane)
 {
-    const int np = (n > kWideCap && n > m) ? m : n;
-    int units = (np + kWideCap - 1) / kWideCap;
+    const bool swap = n > kWideCap && n > m;
+    SplitShape sh = split_shape(swap ? m : n, swap ? n : m);
     int ms = -1;
-    if (units > 1) {
-        if (units <= kMultiUnits)
-            ms = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 2, 1) : 0);
-        if (ms >= kMultiCap) ms = -1;
-        if (ms < 0) units = 1;
+    if (sh.units > 1) {
+        ms = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 2, 1) : 0);
+        if (ms >= kMultiCap) {
+            ms = -1;
+            sh.units = sh.qs = 1;
+        }
     }
-    const int slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, units) : 0);
-    const bool ok = slot <= kWideListCap - units;
-    if (lane < units && slot + lane < kWideListCap) {
-        WidePair &w = hw.wide[slot + lane];
+    const int slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, sh.units) : 0);
+    const bool ok = slot <= kWideListCap - sh.units;
+    for (int u = lane; u < sh.units && slot + u < kWideListCap; u += 64) {
+        WidePair &w = hw.wide[slot + u];
         w.c = ok ? c : -1; w.pa = pa; w.n = n; w.q = q;
-        w.pw = ms < 0 ? -1 : lane; w.slot = ms;
+        w.pw = (int16_t)(ms < 0 ? -1 : u / sh.qs);
+        w.qw = (int16_t)(ms < 0 || sh.qs == 1 ? -1 : u % sh.qs);
+        w.slot = ms;
     }
     if (ms >= 0 && lane == 0) {
         MultiPair &mp = hw.multi[ms];
-        mp.c = ok ? c : -1; mp.pa = pa; mp.n = n; mp.q = q; mp.units = units; mp.pad = 0;
+        mp.c = ok ? c : -1; mp.pa = pa; mp.n = n; mp.q = q; mp.units = sh.units; mp.pad = 0;
     }
     return ok;
 }
@@ -1122,19 +1150,71 @@ __device__ __forceinline__ int2 ring_vertex(const int32_t *V, int m, int i, int6
     return make_int2((int)((int64_t)V[2 * k] - ox), (int)((int64_t)V[2 * k + 1] - oy));
 }
 
+// The passes below read a ring in global memory with one wavefront and
+// kPassU vertices a lane in flight: a long ring costs a few round trips to
+// memory rather than one per 64 vertices.
+constexpr int kPassU = 8;
+
+// One pass: the ring's MBR (absolute coordinates), twice its signed area
+// about the origin (as poly_area2) and the sum of the cross products of its
+// edges before edge `end`, the suffix-sum carry into a window that starts
+// there (exact in 64-bit integers).
+__device__ void ring_sums_global(const int32_t *V, int m, int64_t ox, int64_t oy, int end, int lane,
+                                 int32_t *mbr, int64_t &a2, int64_t &pre)
+{
+    const int2 *W = reinterpret_cast<const int2 *>(V);
+    int32_t mnx = INT32_MAX, mny = INT32_MAX, mxx = INT32_MIN, mxy = INT32_MIN;
+    int64_t a = 0, p = 0;
+    for (int base = 0; base < m; base += 64 * kPassU) {
+        int2 v[kPassU], w[kPassU];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) {
+            const int i = min(base + 64 * k + lane, m - 1);
+            v[k] = W[i];
+            w[k] = W[i + 1 == m ? 0 : i + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) {
+            const int i = base + 64 * k + lane;
+            if (i < m) {
+                mnx = min(mnx, v[k].x); mxx = max(mxx, v[k].x);
+                mny = min(mny, v[k].y); mxy = max(mxy, v[k].y);
+                const int64_t ax = (int64_t)v[k].x - ox, ay = (int64_t)v[k].y - oy;
+                const int64_t bx = (int64_t)w[k].x - ox, by = (int64_t)w[k].y - oy;
+                const int64_t c = (int64_t)((__int128)ax * by - (__int128)bx * ay);
+                a += c;
+                p += i < end ? c : 0;
+            }
+        }
+    }
+    mbr[0] = wmin(mnx); mbr[1] = wmin(mny); mbr[2] = wmax(mxx); mbr[3] = wmax(mxy);
+    a2 = wave_sum_i64(a);
+    pre = wave_sum_i64(p);
+}
+
 // Membership of point a + sh*delta (relative coordinates) in a ring read from
 // global memory: the half-open crossing rule of member_edge over every edge.
 __device__ int member_point_global(const int32_t *V, int m, int64_t ox, int64_t oy, int2 a, int sh, int lane)
 {
     bool odd = false;
-    for (int e = lane; e < m; e += 64) {
-        const int2 c = ring_vertex(V, m, e, ox, oy), d = ring_vertex(V, m, e + 1, ox, oy);
-        const bool st = sh < 0 ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
-        const int up = d.y > c.y ? 1 : -1;
-        const int tb = sh < 0 ? up : -up;
-        const double o = orient_d(c, d, a);
-        const int so = o > 0 ? 1 : (o < 0 ? -1 : tb);
-        odd ^= st & (so == up);
+    for (int base = 0; base < m; base += 64 * kPassU) {
+        int2 cv[kPassU], dv[kPassU];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) {
+            const int e = min(base + 64 * k + lane, m - 1);
+            cv[k] = ring_vertex(V, m, e, ox, oy);
+            dv[k] = ring_vertex(V, m, e + 1, ox, oy);
+        }
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) {
+            const int2 c = cv[k], d = dv[k];
+            const bool st = sh < 0 ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
+            const int up = d.y > c.y ? 1 : -1;
+            const int tb = sh < 0 ? up : -up;
+            const double o = orient_d(c, d, a);
+            const int so = o > 0 ? 1 : (o < 0 ? -1 : tb);
+            odd ^= (base + 64 * k + lane < m) & st & (so == up);
+        }
     }
     return __popcll(__ballot(odd)) & 1;
 }
@@ -1143,17 +1223,23 @@ __device__ int member_point_global(const int32_t *V, int m, int64_t ox, int64_t 
 // in global memory (mbr: its absolute MBR), as q_extremes.
 __device__ void extremes_global(const int32_t *V, int m, const int32_t *mbr, int lane, int *ext)
 {
+    const int2 *W = reinterpret_cast<const int2 *>(V);
     int k0 = -1, k1 = -1, k2 = -1, k3 = -1;
-    for (int base = 0; base < m; base += 64) {
-        const int i = base + lane;
-        const bool live = i < m;
-        const int x = V[2 * (live ? i : 0)], y = V[2 * (live ? i : 0) + 1];
-        const uint64_t b0 = __ballot(live & (x == mbr[0])), b1 = __ballot(live & (x == mbr[2]));
-        const uint64_t b2 = __ballot(live & (y == mbr[1])), b3 = __ballot(live & (y == mbr[3]));
-        if (k0 < 0 && b0 != 0) k0 = base + __builtin_ctzll(b0);
-        if (k1 < 0 && b1 != 0) k1 = base + __builtin_ctzll(b1);
-        if (k2 < 0 && b2 != 0) k2 = base + __builtin_ctzll(b2);
-        if (k3 < 0 && b3 != 0) k3 = base + __builtin_ctzll(b3);
+    for (int base = 0; base < m; base += 64 * kPassU) {
+        int2 v[kPassU];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) v[k] = W[min(base + 64 * k + lane, m - 1)];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) {
+            const int b = base + 64 * k;
+            const bool live = b + lane < m;
+            const uint64_t b0 = __ballot(live & (v[k].x == mbr[0])), b1 = __ballot(live & (v[k].x == mbr[2]));
+            const uint64_t b2 = __ballot(live & (v[k].y == mbr[1])), b3 = __ballot(live & (v[k].y == mbr[3]));
+            if (k0 < 0 && b0 != 0) k0 = b + __builtin_ctzll(b0);
+            if (k1 < 0 && b1 != 0) k1 = b + __builtin_ctzll(b1);
+            if (k2 < 0 && b2 != 0) k2 = b + __builtin_ctzll(b2);
+            if (k3 < 0 && b3 != 0) k3 = b + __builtin_ctzll(b3);
+        }
     }
     ext[0] = k0; ext[1] = k1; ext[2] = k2; ext[3] = k3;
 }
@@ -1164,18 +1250,31 @@ __device__ void extremes_global(const int32_t *V, int m, const int32_t *mbr, int
 __device__ void stage_window(const int32_t *V, int m, int w0, int len, int pad_to, int64_t ox, int64_t oy,
                              RingLds R, int lane)
 {
-    for (int i = lane; i < pad_to; i += 64) R.v[i] = ring_vertex(V, m, w0 + min(i, len), ox, oy);
+    for (int base = 0; base < pad_to; base += 64 * kPassU) {
+        int2 v[kPassU];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) v[k] = ring_vertex(V, m, w0 + min(base + 64 * k + lane, len), ox, oy);
+#pragma unroll
+        for (int k = 0; k < kPassU; k++)
+            if (base + 64 * k + lane < pad_to) R.v[base + 64 * k + lane] = v[k];
+    }
 }
 
 // First vertex of a ring in global memory strictly outside the box b, or -1.
 __device__ int first_outside_global(const int32_t *V, int n, const int32_t *b, int lane)
 {
-    for (int base = 0; base < n; base += 64) {
-        const int i = base + lane;
-        const bool live = i < n;
-        const int x = V[2 * (live ? i : 0)], y = V[2 * (live ? i : 0) + 1];
-        const uint64_t mk = __ballot(live & ((x < b[0]) | (x > b[2]) | (y < b[1]) | (y > b[3])));
-        if (mk != 0) return base + __builtin_ctzll(mk);
+    const int2 *W = reinterpret_cast<const int2 *>(V);
+    for (int base = 0; base < n; base += 64 * kPassU) {
+        int2 v[kPassU];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) v[k] = W[min(base + 64 * k + lane, n - 1)];
+#pragma unroll
+        for (int k = 0; k < kPassU; k++) {
+            const int x = v[k].x, y = v[k].y;
+            const bool live = base + 64 * k + lane < n;
+            const uint64_t mk = __ballot(live & ((x < b[0]) | (x > b[2]) | (y < b[1]) | (y > b[3])));
+            if (mk != 0) return base + 64 * k + __builtin_ctzll(mk);
+        }
     }
     return -1;
 }
@@ -1223,14 +1322,17 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
         const int32_t *Qg = swap ? dxy + 2 * w.pa : qxy + 2 * qa;
         const int n = swap ? mq : w.n, m = swap ? w.n : mq;
         const int64_t ox = Qg[0], oy = Qg[1];
+        // windows of this entry: all, or one P window (and one Q window) of
+        // a split pair
+        const SplitShape sh = split_shape(n, m);
+        const int pfirst = w.pw < 0 ? 0 : w.pw * sh.plen;
+        const int pend = w.pw < 0 ? n : min(n, pfirst + sh.plen);
+        const int qfirst = w.qw < 0 ? 0 : w.qw * kWideCap;
+        const int qend = w.qw < 0 ? m : min(m, qfirst + kWideCap);
         int32_t qm[4], pm[4];
-        poly_mbr(Qg, m, lane, qm);
-        poly_mbr(Pg, n, lane, pm);
-        const int64_t a2q = poly_area2(Qg, m, ox, oy, lane);
-        const int64_t a2p = poly_area2(Pg, n, ox, oy, lane);
-        // P windows of this entry: all, or one of a split pair
-        const int pfirst = w.pw < 0 ? 0 : w.pw * kWideCap;
-        const int pend = w.pw < 0 ? n : min(n, pfirst + kWideCap);
+        int64_t a2q, a2p, qpre, ppre;
+        ring_sums_global(Qg, m, ox, oy, qfirst, lane, qm, a2q, qpre);
+        ring_sums_global(Pg, n, ox, oy, 0, lane, pm, a2p, ppre);
         double J = 0.0;
         MultiUnit unit{0.0, 0.0, 0, 0};
         if (a2p != 0 && a2q != 0) {
@@ -1257,14 +1359,15 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
             RingLds Ps{sPv, sPbox, sPS, nullptr};
             double accP = 0.0, accQ = 0.0, accM = 0.0, accK = 0.0, T = 0.0, crs = 0.0;
             int pcarry = 0, K = 0;
-            for (int p0 = pfirst; p0 < pend; p0 += kWideCap) {
-                const int plen = min(kWideCap, n - p0);
+            const int pstep = w.pw < 0 ? kWideCap : sh.plen;
+            for (int p0 = pfirst; p0 < pend; p0 += pstep) {
+                const int plen = min(pstep, pend - p0);
                 stage_window(Pg, n, p0, plen, 8 * ((plen + 7) >> 3) + 1, ox, oy, Ps, lane);
                 for (int j = lane; j < (plen + 1) >> 1; j += 64) Ps.S[j] = kSBias;
                 wave_lds_sync();
                 chunk_boxes_p<kWideCap / 8>(Ps, plen, lane);
-                int64_t qcarry = 0;
-                for (int w0 = 0; w0 < m; w0 += kWideCap) {
+                int64_t qcarry = qpre;
+                for (int w0 = qfirst; w0 < qend; w0 += kWideCap) {
                     const int len = min(kWideCap, m - w0);
                     // one all-padding chunk past the window, as for whole rings
                     stage_window(Qg, m, w0, len, 8 * ((len + 7) >> 3) + 9, ox, oy, Qs, lane);
@@ -1289,15 +1392,19 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
                 J = jaccard_of(inter2, a2p, a2q);
             } else {
                 unit.part = tot;
-                unit.cr = wave_sum(crs);
+                // the P window's cross products are the same in each of its
+                // Q windows' units: the finish takes them from the first
+                const double cr = wave_sum(crs);
+                unit.cr = w.qw <= 0 ? cr : 0.0;
                 unit.stot = pcarry;
                 unit.kloc = K;
             }
         }
-        st_pairs += w.pw <= 0;
+        st_pairs += (w.pw <= 0) & (w.qw <= 0);
         if (lane == 0) {
+            const int u = w.qw < 0 ? w.pw : w.pw * sh.qs + w.qw;
             if (w.pw < 0) cand_j[w.c] = J;
-            else hw.units[(int64_t)w.slot * kMultiUnits + w.pw] = unit;
+            else hw.units[(int64_t)w.slot * kMultiUnits + u] = unit;
         }
         // every lane is done with both rings before the next pair restages them
         wave_lds_sync();
@@ -1310,8 +1417,9 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
 }
 
 // One wavefront per split pair: the anchors' memberships, then the P
-// windows' sums in window order with the crossing signs of the earlier
-// windows carried into each (deterministic), then J.
+// windows' sums in window order (each the sum of its Q windows' units) with
+// the crossing signs of the earlier windows carried into each
+// (deterministic), then J.
 __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__restrict__ dxy,
                                                             const int32_t *__restrict__ qxy,
                                                             const int64_t *__restrict__ qoff,
@@ -1332,10 +1440,9 @@ __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__re
         const int n = swap ? mq : mp.n, m = swap ? mp.n : mq;
         const int64_t ox = Qg[0], oy = Qg[1];
         int32_t qm[4], pm[4];
-        poly_mbr(Qg, m, lane, qm);
-        poly_mbr(Pg, n, lane, pm);
-        const int64_t a2q = poly_area2(Qg, m, ox, oy, lane);
-        const int64_t a2p = poly_area2(Pg, n, ox, oy, lane);
+        int64_t a2q, a2p, pre;
+        ring_sums_global(Qg, m, ox, oy, 0, lane, qm, a2q, pre);
+        ring_sums_global(Pg, n, ox, oy, 0, lane, pm, a2p, pre);
         double J = 0.0;
         if (a2p != 0 && a2q != 0) {
             int qext[4];
@@ -1350,14 +1457,23 @@ __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__re
             }
             if (kq < 0) wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
             const int sp = a2p > 0 ? 1 : -1, sq = a2q > 0 ? 1 : -1;
-            const int pk = kp / kWideCap;
+            const SplitShape sh = split_shape(n, m);
+            const int pk = kp / sh.plen;
             double total = 0.0;
             int carry = 0, K = 0;
-            for (int u = 0; u < mp.units; u++) {
-                const MultiUnit U = hw.units[s * kMultiUnits + u];
-                total += U.part + (double)(sp * sq) * U.cr * (double)carry;
-                if (u == pk) K = carry + U.kloc;
-                carry += U.stot;
+            const int qs = sh.qs;
+            for (int u = 0; u < mp.units; u += qs) {
+                const MultiUnit *U = hw.units + s * kMultiUnits + u;
+                double part = 0.0;
+                int stot = 0, kloc = 0;
+                for (int v = 0; v < qs; v++) {
+                    part += U[v].part;
+                    stot += U[v].stot;
+                    kloc += U[v].kloc;
+                }
+                total += part + (double)(sp * sq) * U[0].cr * (double)carry;
+                if (u / qs == pk) K = carry + kloc;
+                carry += stot;
             }
             const double inter2 = total + (double)(sp * (wkp - sq * K)) * (double)a2p + (double)(sq * wkq) * (double)a2q;
             J = jaccard_of(inter2, a2p, a2q);

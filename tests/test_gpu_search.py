@@ -315,9 +315,10 @@ def test_refine_more_heavy_pairs_than_the_split_list(pm):
 
 
 def test_refine_more_split_pairs_than_the_split_list(pm):
-    # 8,400 pairs of two 1,100-edge polygons: each is split over its two
-    # P windows (one wavefront each, added up by the finish) while split
-    # slots last (8,192), the rest take both windows on one wavefront;
+    # 8,400 pairs of two 1,100-edge polygons: each is split into five P
+    # windows of 256 edges (one wavefront each, added up by the finish)
+    # while split slots last (4,096), the rest take both windows on one
+    # wavefront;
     # every value equals the general form's (the call without workspace)
     import torch
     rng = np.random.default_rng(14)
