@@ -870,17 +870,22 @@ struct SplitShape {
 
 // The split of a pair whose staged polygon (P's role) has np edges and the
 // other nq; deterministic, so the wide kernel and the finish recompute it.
+__device__ __forceinline__ int split_plen(int np, int qs)
+{
+    return ((np + 255) >> 8) * qs <= kMultiUnits ? 256
+         : ((np + 511) >> 9) * qs <= kMultiUnits ? 512
+         : ((np + 1023) >> 10) * qs <= kMultiUnits ? 1024 : 0;
+}
+
 __device__ __forceinline__ SplitShape split_shape(int np, int nq)
 {
     const int npw = (np + kWideCap - 1) / kWideCap, nqw = (nq + kWideCap - 1) / kWideCap;
     if (npw * nqw <= 2) return {kWideCap, 1, 1};
-    for (int qs = nqw > 2 ? nqw : 1;; qs = 1) {
-        for (int plen = kSplitMinP; plen <= kWideCap; plen *= 2) {
-            const int units = (np + plen - 1) / plen * qs;
-            if (units <= kMultiUnits) return {plen, qs, units};
-        }
-        if (qs == 1) return {kWideCap, 1, 1};
-    }
+    int qs = nqw > 2 ? nqw : 1;
+    int plen = split_plen(np, qs);
+    if (plen == 0 && qs > 1) plen = split_plen(np, qs = 1);
+    if (plen == 0) return {kWideCap, 1, 1};
+    return {plen, qs, (np + plen - 1) / plen * qs};
 }
 
 struct WidePair {
@@ -907,8 +912,9 @@ struct MultiUnit {
 };
 
 struct HeavyWs {
-    int32_t *count;       // [0] heavy pairs, [1] wide list entries, [2] split pairs recorded (each
-                          // may exceed its cap: the excess ran in place), [3] wide entries taken
+    int32_t *count;       // [0] heavy pairs, [1] wide list entries recorded, [2] split pairs, [4] split
+                          // units appended after the recorded entries (each may exceed its cap: the
+                          // excess runs in place or whole), [3] wide entries taken
     HeavyPair *pairs;     // [kHeavyCap]
     double *partial;      // [kHeavyCap][2][kHeavySlices]
     unsigned long long *stat_slots;   // [kStatSlots][4]
@@ -917,35 +923,17 @@ struct HeavyWs {
     MultiUnit *units;     // [kMultiCap][kMultiUnits]
 };
 
-// Records a pair for k_refine_wide: one list entry, or, when split_shape
-// splits it, one entry per unit and a split slot.  False when the list is
-// full (entries that did not fit are marked unused).
-__device__ bool defer_wide(const HeavyWs &hw, int64_t c, int64_t pa, int n, int m, int32_t q, int lane)
+// Records a pair for k_refine_wide as one list entry (k_expand splits the
+// ones split_shape splits).  False when the list is full.
+__device__ bool defer_wide(const HeavyWs &hw, int64_t c, int64_t pa, int n, int32_t q, int lane)
 {
-    const bool swap = n > kWideCap && n > m;
-    SplitShape sh = split_shape(swap ? m : n, swap ? n : m);
-    int ms = -1;
-    if (sh.units > 1) {
-        ms = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 2, 1) : 0);
-        if (ms >= kMultiCap) {
-            ms = -1;
-            sh.units = sh.qs = 1;
-        }
+    const int slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, 1) : 0);
+    if (slot >= kWideListCap) return false;
+    if (lane == 0) {
+        WidePair &w = hw.wide[slot];
+        w.c = c; w.pa = pa; w.n = n; w.q = q; w.pw = -1; w.qw = -1; w.slot = -1;
     }
-    const int slot = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 1, sh.units) : 0);
-    const bool ok = slot <= kWideListCap - sh.units;
-    for (int u = lane; u < sh.units && slot + u < kWideListCap; u += 64) {
-        WidePair &w = hw.wide[slot + u];
-        w.c = ok ? c : -1; w.pa = pa; w.n = n; w.q = q;
-        w.pw = (int16_t)(ms < 0 ? -1 : u / sh.qs);
-        w.qw = (int16_t)(ms < 0 || sh.qs == 1 ? -1 : u % sh.qs);
-        w.slot = ms;
-    }
-    if (ms >= 0 && lane == 0) {
-        MultiPair &mp = hw.multi[ms];
-        mp.c = ok ? c : -1; mp.pa = pa; mp.n = n; mp.q = q; mp.units = sh.units; mp.pad = 0;
-    }
-    return ok;
+    return true;
 }
 
 __device__ __forceinline__ double jaccard_of(double inter2, int64_t a2p, int64_t a2q)
@@ -1083,7 +1071,7 @@ __global__ __launch_bounds__(256, 4) void k_refine(const int32_t *__restrict__ d
                                                           a2q, kp, anchor_q(qmbr, pm, qext), lane,
                                                           sList[wave], sUnits[wave], sCross[wave], &st_swept);
                     st_tiled++;
-                } else if (hw.count && !wide && defer_wide(hw, c, pa, n, m, (int32_t)q, lane)) {
+                } else if (hw.count && !wide && defer_wide(hw, c, pa, n, (int32_t)q, lane)) {
                     // tiled form on wavefronts of the next launch
                     deferred = true;
                 } else if (hw.count && (int64_t)n * m >= kHeavyMin &&
@@ -1279,6 +1267,42 @@ __device__ int first_outside_global(const int32_t *V, int n, const int32_t *b, i
     return -1;
 }
 
+// Splits the recorded wide entries that split_shape splits, one thread per
+// entry: a split slot, then the units appended after the recorded entries
+// (the recorded entry is then marked unused).  A pair stays whole when the
+// split slots run out; when its units do not fit the list, the positions it
+// claimed are marked unused and its slot is dropped.
+__global__ __launch_bounds__(256) void k_expand(const int64_t *__restrict__ qoff, HeavyWs hw)
+{
+    const int64_t norig = min((int64_t)hw.count[1], (int64_t)kWideListCap);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < norig;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const WidePair w = hw.wide[i];
+        const int mq = (int)(qoff[w.q + 1] - qoff[w.q]);
+        const bool swap = w.n > kWideCap && w.n > mq;
+        const SplitShape sh = split_shape(swap ? mq : w.n, swap ? w.n : mq);
+        if (sh.units <= 1) continue;
+        const int ms = atomicAdd(hw.count + 2, 1);
+        if (ms >= kMultiCap) continue;
+        MultiPair &mp = hw.multi[ms];
+        const int64_t base = norig + atomicAdd(hw.count + 4, sh.units);
+        if (base + sh.units > kWideListCap) {
+            for (int64_t j = base; j < kWideListCap; j++) hw.wide[j].c = -1;
+            mp.c = -1;
+            continue;
+        }
+        mp.c = w.c; mp.pa = w.pa; mp.n = w.n; mp.q = w.q; mp.units = sh.units; mp.pad = 0;
+        for (int u = 0; u < sh.units; u++) {
+            WidePair e = w;
+            e.pw = (int16_t)(u / sh.qs);
+            e.qw = (int16_t)(sh.qs == 1 ? -1 : u % sh.qs);
+            e.slot = ms;
+            hw.wide[base + u] = e;
+        }
+        hw.wide[i].c = -1;
+    }
+}
+
 // One wavefront per deferred pair (workgroups of one wavefront, so four fit a
 // CU's LDS), any sizes: both rings pass through LDS in windows of up to
 // kWideCap edges, P's windows in the outer loop and Q's in the inner one.
@@ -1306,14 +1330,15 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
     __shared__ uint32_t sCross[kCrossCap];
 
     const int lane = threadIdx.x;
-    const int64_t count = min((int64_t)hw.count[1], (int64_t)kWideListCap);
+    const int64_t norig = min((int64_t)hw.count[1], (int64_t)kWideListCap);
+    const int64_t nunits = max((int64_t)0, min((int64_t)hw.count[4], (int64_t)kWideListCap - norig));
     unsigned long long st_pairs = 0, st_swept = 0;
-    // entries are taken from a counter as wavefronts come free: their costs
-    // range from one window to many
+    // entries are taken from a counter as wavefronts come free, the split
+    // pairs' units first: costs range from one window to many
     for (;;) {
-        const int64_t i = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 3, 1) : 0);
-        if (i >= count) break;
-        const WidePair w = hw.wide[i];
+        const int64_t t = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(hw.count + 3, 1) : 0);
+        if (t >= norig + nunits) break;
+        const WidePair w = hw.wide[t < nunits ? norig + t : t - nunits];
         if (w.c < 0) continue;
         const int64_t qa = qoff[w.q];
         const int mq = (int)(qoff[w.q + 1] - qa);
@@ -1550,7 +1575,7 @@ HeavyWs carve_heavy(Carve &cv)
 // Clears the pair counts, the work counter and the counter slots (256 threads).
 __global__ void k_zero_count(int32_t *p, unsigned long long *slots)
 {
-    if (threadIdx.x < 4) p[threadIdx.x] = 0;
+    if (threadIdx.x < 5) p[threadIdx.x] = 0;
     if (threadIdx.x < kStatSlots * 4) slots[threadIdx.x] = 0;
 }
 
@@ -1604,6 +1629,8 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
                        slices, hw);
     polymh_status st = check_launch("refine");
     if (st || !ws) return st;
+    hipLaunchKernelGGL(k_expand, dim3(64), dim3(256), 0, s, queries->offsets, hw);
+    if ((st = check_launch("refine: split wide pairs"))) return st;
     // deferred wide tiled pairs: four one-wavefront workgroups per CU
     hipLaunchKernelGGL(k_refine_wide, dim3(1024), dim3(64), 0, s, data->xy, queries->xy, queries->offsets, cand_j,
                        hw, stats ? 1 : 0);
