@@ -1332,6 +1332,7 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
     const int lane = threadIdx.x;
     const int64_t norig = min((int64_t)hw.count[1], (int64_t)kWideListCap);
     const int64_t nunits = max((int64_t)0, min((int64_t)hw.count[4], (int64_t)kWideListCap - norig));
+    if (norig + nunits == 0) return;   // nothing deferred (the usual case): no atomics on the counter
     unsigned long long st_pairs = 0, st_swept = 0;
     // entries are taken from a counter as wavefronts come free, the split
     // pairs' units first: costs range from one window to many
