@@ -486,3 +486,38 @@ def test_refine_windowed_degenerate_contacts(pm, orc):
         assert abs(got[j] - float(want)) <= 1e-12, (j, got[j], want)
     want = orc.jaccard_candidates(D, Q, off, ids)
     assert np.all(np.abs(want - np.array([float(c[2]) for c in cases])) <= 1e-9)
+
+
+def test_refine_split_units_exact(pm):
+    # exact J for pairs split into units of each shape: 9,000-vertex squares
+    # (P windows of 512 edges, each with one of the 9 Q windows: windows of
+    # 256 would give more than 256 units), 20,000-vertex squares (P windows
+    # of 256 edges walking all 20 Q windows: a unit per Q window would
+    # exceed the cap) and a 4-vertex rectangle against a 20,000-vertex
+    # square, either way round (one P window, each of the 20 Q windows a
+    # unit of its own); collinear overlaps, shared edges and a reversed ring
+    # included
+    import torch
+    L9, L20 = 9000, 20000
+    a9 = _subdivided_rect(0, 0, L9, L9, 2250)
+    a20 = _subdivided_rect(0, 0, L20, L20, 5000)
+    small = dg.rectangle(1000, 1000, 3000, 5000)
+    cases = [
+        (a9, a9, Fraction(1)), (a9, a9[::-1], Fraction(1)),
+        (a9, _subdivided_rect(L9 // 2, 0, L9 // 2 + L9, L9, 2250), Fraction(1, 3)),
+        (a9, _subdivided_rect(L9, 0, 2 * L9, L9, 2250), Fraction(0)),
+        (a20, a20, Fraction(1)),
+        (a20, _subdivided_rect(L20 // 2, 0, L20 // 2 + L20, L20, 5000), Fraction(1, 3)),
+        (small, a20, Fraction(2000 * 4000, L20 * L20)),
+        (a20, small, Fraction(2000 * 4000, L20 * L20)),
+    ]
+    D = pm.to_device(dg.from_list([c[0] for c in cases]))
+    Q = pm.to_device(dg.from_list([c[1] for c in cases]))
+    off = torch.arange(len(cases) + 1, dtype=torch.int64, device="cuda")
+    ids = torch.arange(len(cases), dtype=torch.int32, device="cuda")
+    got, st = pm.refine_stats(D, Q, off, ids)
+    got = got.cpu().numpy()
+    for j, (_, _, want) in enumerate(cases):
+        assert abs(got[j] - float(want)) <= 1e-12, (j, got[j], want)
+    # the pair sharing an edge has MBRs that only touch: counted disjoint
+    assert st[0] == len(cases) - 1 and st[3] == 1 and st[2] == 0
