@@ -1443,9 +1443,9 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
 }
 
 // One wavefront per split pair: the anchors' memberships, then the P
-// windows' sums in window order (each the sum of its Q windows' units) with
-// the crossing signs of the earlier windows carried into each
-// (deterministic), then J.
+// windows' sums (each the sum of its Q windows' units, one window a lane)
+// with the crossing signs of the earlier windows carried into each, added in
+// a fixed order (deterministic), then J.
 __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__restrict__ dxy,
                                                             const int32_t *__restrict__ qxy,
                                                             const int64_t *__restrict__ qoff,
@@ -1485,22 +1485,33 @@ __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__re
             const int sp = a2p > 0 ? 1 : -1, sq = a2q > 0 ? 1 : -1;
             const SplitShape sh = split_shape(n, m);
             const int pk = kp / sh.plen;
-            double total = 0.0;
+            // lanes take the P windows, 64 at a time; the carry of crossing
+            // signs into each is a scan in window order
+            const int qs = sh.qs, npw = mp.units / qs;
+            const MultiUnit *U = hw.units + s * kMultiUnits;
+            double acc = 0.0;
             int carry = 0, K = 0;
-            const int qs = sh.qs;
-            for (int u = 0; u < mp.units; u += qs) {
-                const MultiUnit *U = hw.units + s * kMultiUnits + u;
-                double part = 0.0;
+            for (int base = 0; base < npw; base += 64) {
+                const int wdw = base + lane;
+                const bool live = wdw < npw;
+                double part = 0.0, cr = 0.0;
                 int stot = 0, kloc = 0;
-                for (int v = 0; v < qs; v++) {
-                    part += U[v].part;
-                    stot += U[v].stot;
-                    kloc += U[v].kloc;
+                if (live) {
+                    cr = U[wdw * qs].cr;
+                    for (int v = 0; v < qs; v++) {
+                        const MultiUnit x = U[wdw * qs + v];
+                        part += x.part;
+                        stot += x.stot;
+                        kloc += x.kloc;
+                    }
                 }
-                total += part + (double)(sp * sq) * U[0].cr * (double)carry;
-                if (u / qs == pk) K = carry + kloc;
-                carry += stot;
+                const int incl = wave_incl_scan32(stot);
+                const int excl = carry + incl - stot;
+                acc += live ? part + (double)(sp * sq) * cr * (double)excl : 0.0;
+                if (pk >= base && pk < base + 64) K = __builtin_amdgcn_readlane(excl + kloc, pk - base);
+                carry += __builtin_amdgcn_readlane(incl, 63);
             }
+            const double total = wave_sum(acc);
             const double inter2 = total + (double)(sp * (wkp - sq * K)) * (double)a2p + (double)(sq * wkq) * (double)a2q;
             J = jaccard_of(inter2, a2p, a2q);
         }
