@@ -356,7 +356,7 @@ polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, cons
  * into a HIP graph, then replay it with polymh_graph_launch (same buffers,
  * new contents).  Calls that synchronise (polymh_box_of, polymh_query with a
  * capacity check, polymh_rank_refine) must not be captured; use
- * polymh_query_capped.  The handle is owned by the caller and released by
+ * polymh_query_capped and polymh_rank_refine_ordered.  The handle is owned by the caller and released by
  * polymh_graph_destroy. */
 typedef struct polymh_graph_t *polymh_graph;
 polymh_status polymh_graph_begin(void *stream);
@@ -424,7 +424,8 @@ polymh_status polymh_poly_features(const polymh_polys *polys, polymh_box box, fl
  * table (signatures lsig [.][256], features lfeat [.][12]) and a right table:
  * 256 collision bits [lsig == rsig], the 6 left and 6 right shape features,
  * ln(A_l/A_r)/4, min/max area ratio, MBR intersection-over-union, collision
- * fraction, then zeros; rows R..R_pad-1 are zero.  k must be 256.
+ * fraction, then zeros; rows R..R_pad-1, and rows whose li or ri is negative
+ * (empty head slots), are zero.  k must be 256.
  * Stream-ordered. */
 polymh_status polymh_pair_features(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
                                    const float *rfeat, int32_t k, const int32_t *li,
@@ -450,7 +451,8 @@ polymh_status polymh_rank_head(const int64_t *cand_off, const int32_t *cand_ids,
                                const float *score, int32_t M, int32_t *order, uint8_t *sorted_ok,
                                int64_t *head_off, int32_t *head_query, int64_t *head_cand,
                                int32_t *head_id, void *stream);
-/* score[idx[i]] = val[i] for i < n.  Stream-ordered. */
+/* score[idx[i]] = val[i] for i < n with idx[i] >= 0 (negative indices, the
+ * empty slots of polymh_rank_head_fixed, are skipped).  Stream-ordered. */
 polymh_status polymh_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,
                                     void *stream);
 
@@ -461,11 +463,16 @@ polymh_status polymh_scatter_scores(const int64_t *idx, const float *val, int64_
  * candidates are exhausted (margin = +inf refines everything: the fallback,
  * equal to polymh_refine + polymh_topk).  Queries with more than 8192
  * candidates are refined fully in their given order.  top_ids/top_j as in
- * polymh_topk.  *n_refined_host and *rounds_host (nullable, host) receive the
- * number of refined pairs and rounds.  SYNCHRONISES the stream once per
- * round.  Each round refines as polymh_refine_ws (pairs beyond 512 edges on
- * the windowed tiled form).  ws: polymh_rank_workspace_size(nq, n_cand, F)
- * bytes (it includes the refinement's workspace). */
+ * polymh_topk.  If max_rounds rounds pass with queries still active, one
+ * finishing pass refines all the candidates those queries have left (so the
+ * top-k is always complete; only the work saved by early stop is lost).
+ * *n_refined_host and *rounds_host (nullable, host) receive the number of
+ * refined pairs and of rounds taken before the finishing pass.
+ * SYNCHRONISES the stream once per round (the stop test of the round is read
+ * back); polymh_rank_refine_ordered is the form without host reads.  Each
+ * round refines as polymh_refine_ws (pairs beyond 512 edges on the windowed
+ * tiled form).  ws: polymh_rank_workspace_size(nq, n_cand, F) bytes (it
+ * includes the refinement's workspace). */
 size_t polymh_rank_workspace_size(int64_t nq, int64_t n_cand, int32_t F);
 polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *queries,
                                  const int64_t *cand_off, const int32_t *cand_ids,
@@ -473,6 +480,59 @@ polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *q
                                  int32_t F, float margin, int32_t max_rounds, void *ws,
                                  size_t ws_bytes, int32_t *top_ids, double *top_j,
                                  int64_t *n_refined_host, int32_t *rounds_host, void *stream);
+
+/* polymh_rank_jhat_order -- the collision fraction of every candidate pair
+ * (Thm. 1: each hash collides with probability J, so the share of agreeing
+ * hashes is an unbiased estimate of J) and each query's best-first order in
+ * one pass.
+ *   qsig [nq][k], dsig [n_data][k]: signatures of the queries and of the
+ *   indexed polygons; cand_off/cand_ids: the candidate CSR of polymh_query.
+ *   score [C] float out: agreeing hashes / k for candidate c.
+ *   order [C] int32 out: per query, the positions (0-based, within the query's
+ *   list) sorted by decreasing score, ties by position; sorted_ok [nq] uint8
+ *   out: 0 for a query beyond 8192 candidates (left in its given order).
+ * Stream-ordered, no host reads (graph-capturable). */
+polymh_status polymh_rank_jhat_order(const uint32_t *qsig, const uint32_t *dsig, int32_t k,
+                                     const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                                     float *score, int32_t *order, uint8_t *sorted_ok, void *stream);
+
+/* polymh_rank_order -- order and sorted_ok as polymh_rank_jhat_order, from
+ * scores the caller provides (e.g. the network's predictions written into
+ * the collision fractions by polymh_scatter_scores).  Stream-ordered. */
+polymh_status polymh_rank_order(const int64_t *cand_off, int64_t nq, const float *score,
+                                int32_t *order, uint8_t *sorted_ok, void *stream);
+
+/* polymh_rank_head_fixed -- the first M candidates of each query's order in
+ * fixed slots s = q*M + t (t < M): head_query[s] = q, head_cand[s] = global
+ * candidate index (int64) and head_id[s] = data polygon of the t-th best
+ * candidate, or -1 in both when the query has t or fewer candidates (an empty
+ * slot; polymh_pair_features gives it a zero row and polymh_scatter_scores
+ * skips it).  Arrays of nq*M entries; the size does not depend on the
+ * lookup's counts, so a captured graph can hold the call.  Stream-ordered. */
+polymh_status polymh_rank_head_fixed(const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                                     const int32_t *order, int32_t M, int32_t *head_query,
+                                     int64_t *head_cand, int32_t *head_id, void *stream);
+
+/* polymh_rank_refine_ordered -- polymh_rank_refine without host reads, so
+ * that a whole query batch (signing, lookup, scoring, ordered refinement)
+ * can be captured in one graph.  The order comes from the caller
+ * (polymh_rank_jhat_order or polymh_rank_order on the same scores); exactly
+ * `rounds` rounds of F refinements per active query run (a round with no
+ * active query refines nothing), then the finishing pass of
+ * polymh_rank_refine completes every query still active, so the result is
+ * the same as polymh_rank_refine's with max_rounds = rounds.
+ *   counts [2] int64 device out (nullable): pairs refined, and queries the
+ *   finishing pass completed.
+ * ws: polymh_rank_workspace_size(nq, n_cand, F) bytes; n_cand is the size
+ * of cand_ids (a bound on the lookup's total, e.g. its capacity).
+ * Stream-ordered, no host reads; calls sharing ws must not overlap. */
+polymh_status polymh_rank_refine_ordered(const polymh_polys *data, const polymh_polys *queries,
+                                         const int64_t *cand_off, const int32_t *cand_ids,
+                                         const float *score, const int32_t *order,
+                                         const uint8_t *sorted_ok, int64_t nq, int64_t n_cand,
+                                         int32_t topk, int32_t F, int32_t rounds, float margin,
+                                         void *ws, size_t ws_bytes, int32_t *top_ids, double *top_j,
+                                         int64_t *counts, void *stream);
 
 #ifdef __cplusplus
 }

@@ -3,6 +3,8 @@
 // launch on the caller's stream; nothing here touches polygon data.
 #include "internal.hpp"
 
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -613,9 +615,12 @@ struct RankWs {
     int64_t *cursor, *roff;
     int32_t *rids, *rpos, *n_active;
     double *rj;
+    unsigned long long *counters;
     char *refine_ws;      // the refinement's own workspace (pairs beyond 512 edges deferred)
 };
 
+// A round lists at most nq * F pairs; the finishing pass up to every
+// candidate, so the round lists hold max(nq * F, n_cand) entries.
 static RankWs carve_rank(Carve &c, int64_t nq, int64_t n_cand, int32_t F)
 {
     RankWs w{};
@@ -624,11 +629,12 @@ static RankWs carve_rank(Carve &c, int64_t nq, int64_t n_cand, int32_t F)
     w.active = c.take<uint8_t>((size_t)nq + 1);
     w.cursor = c.take<int64_t>((size_t)nq + 1);
     w.roff = c.take<int64_t>((size_t)nq + 1);
-    const size_t per_round = (size_t)nq * (size_t)F + 1;
+    const size_t per_round = std::max((size_t)nq * (size_t)F, (size_t)n_cand) + 1;
     w.rids = c.take<int32_t>(per_round);
     w.rpos = c.take<int32_t>(per_round);
     w.rj = c.take<double>(per_round);
     w.n_active = c.take<int32_t>(1);
+    w.counters = c.take<unsigned long long>(2);
     w.refine_ws = c.take<char>(refine_workspace_bytes());
     return w;
 }
@@ -641,6 +647,54 @@ size_t polymh_rank_workspace_size(int64_t nq, int64_t n_cand, int32_t F)
     return align_up(cv.used, 256);
 }
 
+namespace {
+
+__global__ void k_zero_counters(unsigned long long *c)
+{
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
+__global__ void k_copy_counters(const unsigned long long *c, int64_t *out)
+{
+    if (threadIdx.x < 2) out[threadIdx.x] = (int64_t)c[threadIdx.x];
+}
+
+// One round: per-query counts (F <= 0: everything left), their offsets, the
+// round's pair list, its exact J and the merge into the running top-k.
+polymh_status rank_round(const polymh_polys *data, const polymh_polys *queries, const int64_t *cand_off,
+                         const int32_t *cand_ids, const float *score, int64_t nq, int32_t topk, int32_t F,
+                         float margin, const RankWs &w, int32_t *top_ids, double *top_j, bool with_n_active,
+                         bool finishing, hipStream_t s)
+{
+    polymh_status st;
+    if ((st = launch_round_count(cand_off, nq, w.cursor, w.active, F, w.roff, s))) return st;
+    if ((st = launch_offsets(w.roff, nq, s))) return st;
+    if ((st = launch_round_fill(cand_off, cand_ids, w.order, w.cursor, w.roff, nq, w.rids, w.rpos, s))) return st;
+    // the pair count lives on the device: the refinement's grid is sized by
+    // the round's bound (F per query; one workgroup per query for the
+    // finishing pass), and workgroups of queries without pairs return at once
+    const int64_t hint = finishing ? nq : nq * (int64_t)F;
+    if ((st = launch_refine(data, queries, w.roff, w.rids, nq, hint, w.rj, s, nullptr, w.refine_ws,
+                            refine_workspace_bytes())))
+        return st;
+    return launch_round_merge(cand_off, score, w.order, w.sorted_ok, w.roff, w.rids, w.rj, nq, topk,
+                              finishing ? INFINITY : margin, w.cursor, w.active, top_ids, top_j,
+                              with_n_active ? w.n_active : nullptr, w.counters, finishing ? 1 : 0, s);
+}
+
+polymh_status check_rank_args(const polymh_polys *data, const polymh_polys *queries, int64_t nq, int64_t n_cand,
+                              int32_t topk, int32_t F, const char *who)
+{
+    polymh_status st = check_polys(data, who);
+    if (st) return st;
+    if ((st = check_polys(queries, who))) return st;
+    if (nq != queries->n) return set_error(POLYMH_EINVAL, "%s: nq differs from the query count", who);
+    if (topk < 1 || topk > 64 || F < 1 || n_cand < 0) return set_error(POLYMH_EINVAL, "%s: bad sizes", who);
+    return POLYMH_OK;
+}
+
+}  // namespace
+
 polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *queries,
                                  const int64_t *cand_off, const int32_t *cand_ids, const float *score,
                                  int64_t nq, int64_t n_cand, int32_t topk, int32_t F, float margin,
@@ -648,12 +702,9 @@ polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *q
                                  double *top_j, int64_t *n_refined_host, int32_t *rounds_host,
                                  void *stream)
 {
-    polymh_status st = check_polys(data, "rank_refine");
+    polymh_status st = check_rank_args(data, queries, nq, n_cand, topk, F, "rank_refine");
     if (st) return st;
-    if ((st = check_polys(queries, "rank_refine"))) return st;
-    if (nq != queries->n) return set_error(POLYMH_EINVAL, "rank_refine: nq differs from the query count");
-    if (topk < 1 || topk > 64 || F < 1 || max_rounds < 1 || n_cand < 0)
-        return set_error(POLYMH_EINVAL, "rank_refine: bad sizes");
+    if (max_rounds < 1) return set_error(POLYMH_EINVAL, "rank_refine: bad sizes");
     if (nq == 0) return POLYMH_OK;
     if (!cand_off || !top_ids || !top_j || (n_cand > 0 && (!cand_ids || !score)))
         return set_error(POLYMH_EINVAL, "rank_refine: NULL array");
@@ -664,29 +715,103 @@ polymh_status polymh_rank_refine(const polymh_polys *data, const polymh_polys *q
     hipStream_t s = as_stream(stream);
     if ((st = launch_rank_sort(cand_off, nq, score, w.order, w.sorted_ok, s))) return st;
     if ((st = launch_rank_init(nq, topk, w.cursor, w.active, top_ids, top_j, s))) return st;
-    int64_t refined = 0;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, w.counters);
     int32_t r = 0;
+    bool done = false;
     for (; r < max_rounds; r++) {
-        if ((st = launch_round_count(cand_off, nq, w.cursor, w.active, F, w.roff, s))) return st;
-        if ((st = launch_offsets(w.roff, nq, s))) return st;
-        if ((st = launch_round_fill(cand_off, cand_ids, w.order, w.cursor, w.roff, nq, w.rids, w.rpos, s)))
+        if ((st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, F, margin, w, top_ids, top_j, true,
+                             false, s)))
             return st;
-        int64_t total = 0;
-        hipError_t e = hipMemcpyAsync(&total, w.roff + nq, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        int32_t still = 0;
+        hipError_t e = hipMemcpyAsync(&still, w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "rank_refine: %s", hipGetErrorString(e));
-        if (total == 0) break;
-        refined += total;
-        if ((st = launch_refine(data, queries, w.roff, w.rids, nq, total, w.rj, s, nullptr, w.refine_ws,
-                                refine_workspace_bytes())))
-            return st;
-        if ((st = launch_round_merge(cand_off, score, w.order, w.sorted_ok, w.roff, w.rids, w.rj, nq,
-                                     topk, margin, w.cursor, w.active, top_ids, top_j, w.n_active, s)))
-            return st;
+        if (still == 0) {
+            done = true;
+            r++;
+            break;
+        }
     }
-    if (n_refined_host) *n_refined_host = refined;
+    // rounds exhausted with queries still active: their remaining candidates
+    // are refined in full, so the top-k is always complete
+    if (!done && (st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, F, margin, w, top_ids,
+                                  top_j, false, true, s)))
+        return st;
+    if (n_refined_host) {
+        unsigned long long c[2] = {0, 0};
+        hipError_t e = hipMemcpyAsync(c, w.counters, sizeof(c), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "rank_refine: %s", hipGetErrorString(e));
+        *n_refined_host = (int64_t)c[0];
+    }
     if (rounds_host) *rounds_host = r;
     return POLYMH_OK;
+}
+
+polymh_status polymh_rank_jhat_order(const uint32_t *qsig, const uint32_t *dsig, int32_t k, const int64_t *cand_off,
+                                     const int32_t *cand_ids, int64_t nq, float *score, int32_t *order,
+                                     uint8_t *sorted_ok, void *stream)
+{
+    if (nq < 0 || k < 1) return set_error(POLYMH_EINVAL, "rank_jhat_order: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!qsig || !dsig || !cand_off || !cand_ids || !score || !order || !sorted_ok)
+        return set_error(POLYMH_EINVAL, "rank_jhat_order: NULL array");
+    return launch_rank_jhat_sort(qsig, dsig, k, cand_off, cand_ids, nq, score, order, sorted_ok, as_stream(stream));
+}
+
+polymh_status polymh_rank_order(const int64_t *cand_off, int64_t nq, const float *score, int32_t *order,
+                                uint8_t *sorted_ok, void *stream)
+{
+    if (nq < 0) return set_error(POLYMH_EINVAL, "rank_order: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !score || !order || !sorted_ok) return set_error(POLYMH_EINVAL, "rank_order: NULL array");
+    return launch_rank_sort(cand_off, nq, score, order, sorted_ok, as_stream(stream));
+}
+
+polymh_status polymh_rank_head_fixed(const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
+                                     const int32_t *order, int32_t M, int32_t *head_query, int64_t *head_cand,
+                                     int32_t *head_id, void *stream)
+{
+    if (nq < 0 || M < 1) return set_error(POLYMH_EINVAL, "rank_head_fixed: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !cand_ids || !order || !head_query || !head_cand || !head_id)
+        return set_error(POLYMH_EINVAL, "rank_head_fixed: NULL array");
+    return launch_head_fixed(cand_off, cand_ids, nq, order, M, head_query, head_cand, head_id, as_stream(stream));
+}
+
+polymh_status polymh_rank_refine_ordered(const polymh_polys *data, const polymh_polys *queries,
+                                         const int64_t *cand_off, const int32_t *cand_ids, const float *score,
+                                         const int32_t *order, const uint8_t *sorted_ok, int64_t nq,
+                                         int64_t n_cand, int32_t topk, int32_t F, int32_t rounds, float margin,
+                                         void *ws, size_t ws_bytes, int32_t *top_ids, double *top_j,
+                                         int64_t *counts, void *stream)
+{
+    polymh_status st = check_rank_args(data, queries, nq, n_cand, topk, F, "rank_refine_ordered");
+    if (st) return st;
+    if (rounds < 0) return set_error(POLYMH_EINVAL, "rank_refine_ordered: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !top_ids || !top_j || !order || !sorted_ok || (n_cand > 0 && (!cand_ids || !score)))
+        return set_error(POLYMH_EINVAL, "rank_refine_ordered: NULL array");
+    Carve cv{static_cast<char *>(ws), ws_bytes};
+    RankWs w = carve_rank(cv, nq, n_cand, F);
+    if (!cv.ok)
+        return set_error(POLYMH_ECAPACITY, "rank_refine_ordered: workspace of %zu bytes, need %zu", ws_bytes,
+                         cv.used);
+    hipStream_t s = as_stream(stream);
+    // the caller's order is used as given: point the workspace at it
+    w.order = const_cast<int32_t *>(order);
+    w.sorted_ok = const_cast<uint8_t *>(sorted_ok);
+    if ((st = launch_rank_init(nq, topk, w.cursor, w.active, top_ids, top_j, s))) return st;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, w.counters);
+    for (int32_t r = 0; r < rounds; r++)
+        if ((st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, F, margin, w, top_ids, top_j,
+                             false, false, s)))
+            return st;
+    if ((st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, F, margin, w, top_ids, top_j, false,
+                         true, s)))
+        return st;
+    if (counts) hipLaunchKernelGGL(k_copy_counters, dim3(1), dim3(64), 0, s, w.counters, counts);
+    return check_launch("rank_refine_ordered");
 }
 
 }  // extern "C"

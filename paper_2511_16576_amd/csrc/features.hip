@@ -96,7 +96,8 @@ __global__ __launch_bounds__(256) void k_pair_feats(const uint32_t *__restrict__
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < R_pad; r += nw) {
         __bf16 *row = X + r * kCols;
-        if (r >= R) {
+        // rows past R and rows of an empty head slot (negative index) are zero
+        if (r >= R || li[r] < 0 || ri[r] < 0) {
             for (int c = lane; c < kCols; c += 64) row[c] = (__bf16)0.f;
             continue;
         }

@@ -283,7 +283,12 @@ polymh_status launch_round_merge(const int64_t *off, const float *score, const i
                                  const uint8_t *sorted_ok, const int64_t *roff, const int32_t *rids,
                                  const double *rj, int64_t nq, int32_t topk, float margin,
                                  int64_t *cursor, uint8_t *active, int32_t *top_ids, double *top_j,
-                                 int32_t *n_active, hipStream_t s);
+                                 int32_t *n_active, unsigned long long *counters, int finishing, hipStream_t s);
+polymh_status launch_head_fixed(const int64_t *off, const int32_t *cand_ids, int64_t nq, const int32_t *order,
+                                int32_t M, int32_t *hq, int64_t *hc, int32_t *hid, hipStream_t s);
+polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, int32_t k, const int64_t *off,
+                                    const int32_t *cand_ids, int64_t nq, float *score, int32_t *order,
+                                    uint8_t *sorted_ok, hipStream_t s);
 polymh_status launch_jhat(const uint32_t *lsig, const uint32_t *rsig, const int32_t *li,
                           const int32_t *ri, int64_t R, int32_t k, float *out, hipStream_t s);
 polymh_status launch_offsets(int64_t *off, int64_t nq, hipStream_t s);

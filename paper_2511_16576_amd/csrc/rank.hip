@@ -6,7 +6,10 @@
 // and stops once it holds k results and its k-th exact J is at least the next
 // candidate's predicted J plus a margin, or when its candidates run out.
 // Queries with more than kSortCap candidates are refined in their original
-// order with the stop test disabled, i.e. fully (the fallback).
+// order with the stop test disabled, i.e. fully (the fallback).  After the
+// last round, a finishing pass refines every candidate a still-active query
+// has left, so the result is always complete; the rounds and that pass keep
+// their counts on the device and never wait on the host.
 #include "internal.hpp"
 
 #include <cfloat>
@@ -66,6 +69,99 @@ __global__ __launch_bounds__(1024) void k_rank_sort(const int64_t *__restrict__ 
     if (threadIdx.x == 0) sorted_ok[q] = 1;
 }
 
+
+// One block per query: the collision fraction of every candidate (the
+// unbiased estimate of J of Thm. 1: the share of the k hashes on which the
+// two signatures agree), written to score[], then the (score desc, position
+// asc) order as k_rank_sort.  One wavefront per candidate; with k a multiple
+// of 4 and at most 1024 and both tables 16-byte aligned (`vec`), a lane keeps
+// its 16-byte slices of the query's signature in registers and reads the
+// candidate's with 16-byte loads.
+__global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restrict__ qsig,
+                                                         const uint32_t *__restrict__ dsig, int32_t k,
+                                                         int vec, const int64_t *__restrict__ off,
+                                                         const int32_t *__restrict__ cand_ids,
+                                                         float *__restrict__ score,
+                                                         int32_t *__restrict__ order,
+                                                         uint8_t *__restrict__ sorted_ok)
+{
+    __shared__ float ss[kSortCap];
+    __shared__ int si[kSortCap];
+    const int64_t q = blockIdx.x;
+    const int64_t a = off[q];
+    const int n = (int)(off[q + 1] - a);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nwave = (int)(blockDim.x >> 6);
+    const uint32_t *sq = qsig + q * (int64_t)k;
+    const float inv_k = 1.0f / (float)k;
+    uint4 qv[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int h = 4 * lane + 256 * t;
+        qv[t] = (vec && h < k) ? *reinterpret_cast<const uint4 *>(sq + h) : make_uint4(0, 0, 0, 0);
+    }
+    for (int i = wave; i < n; i += nwave) {
+        const uint32_t *sp = dsig + (int64_t)cand_ids[a + i] * k;
+        int cnt = 0;
+        if (vec) {
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int h = 4 * lane + 256 * t;
+                if (256 * t < k) {   // wave-uniform
+                    const bool in = h < k;
+                    const uint4 pv = in ? *reinterpret_cast<const uint4 *>(sp + h) : make_uint4(0, 0, 0, 0);
+                    cnt += __popcll(__ballot(in && pv.x == qv[t].x)) + __popcll(__ballot(in && pv.y == qv[t].y)) +
+                           __popcll(__ballot(in && pv.z == qv[t].z)) + __popcll(__ballot(in && pv.w == qv[t].w));
+                }
+            }
+        } else {
+            for (int h0 = 0; h0 < k; h0 += 64) {
+                const int h = h0 + lane;
+                cnt += __popcll(__ballot(h < k && sq[h] == sp[h]));
+            }
+        }
+        const float s = (float)cnt * inv_k;
+        if (lane == 0) {
+            score[a + i] = s;
+            if (i < kSortCap) {
+                ss[i] = s;
+                si[i] = i;
+            }
+        }
+    }
+    if (n > kSortCap) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = i;
+        if (threadIdx.x == 0) sorted_ok[q] = 0;
+        return;
+    }
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = n + threadIdx.x; i < np; i += blockDim.x) {
+        ss[i] = -FLT_MAX;
+        si[i] = 0x7fffffff;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= np; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & kk) == 0;
+                    const bool before = key_before(ss[l], si[l], ss[i], si[i]);
+                    if (before == up) {
+                        const float t = ss[i]; ss[i] = ss[l]; ss[l] = t;
+                        const int u = si[i]; si[i] = si[l]; si[l] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = si[i];
+    if (threadIdx.x == 0) sorted_ok[q] = 1;
+}
+
 __global__ void k_rank_init(int64_t nq, int32_t topk, int64_t *__restrict__ cursor,
                             uint8_t *__restrict__ active, int32_t *__restrict__ top_ids,
                             double *__restrict__ top_j)
@@ -88,7 +184,7 @@ __global__ void k_round_count(const int64_t *__restrict__ off, int64_t nq,
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
          q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t left = (off[q + 1] - off[q]) - cursor[q];
-        counts[q] = active[q] ? (left < F ? left : F) : 0;
+        counts[q] = active[q] ? ((F <= 0 || left < F) ? left : F) : 0;
     }
 }
 
@@ -115,11 +211,16 @@ __global__ void k_round_merge(const int64_t *__restrict__ off, const float *__re
                               const double *__restrict__ rj, int64_t nq, int32_t topk, float margin,
                               int64_t *__restrict__ cursor, uint8_t *__restrict__ active,
                               int32_t *__restrict__ top_ids, double *__restrict__ top_j,
-                              int32_t *__restrict__ n_active)
+                              int32_t *__restrict__ n_active, unsigned long long *__restrict__ counters,
+                              int finishing)
 {
+    // counters[0] += pairs refined in this round; counters[1] += queries the
+    // finishing pass had to complete
+    if (counters && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&counters[0], (unsigned long long)roff[nq]);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
          q += (int64_t)gridDim.x * blockDim.x) {
         if (!active[q]) continue;
+        if (finishing && counters && roff[q + 1] > roff[q]) atomicAdd(&counters[1], 1ull);
         int32_t *ti = top_ids + q * topk;
         double *tj = top_j + q * topk;
         for (int64_t c = roff[q]; c < roff[q + 1]; c++) {
@@ -151,7 +252,7 @@ __global__ void k_round_merge(const int64_t *__restrict__ off, const float *__re
             stop = tj[topk - 1] >= (double)next + (double)margin;
         }
         if (stop) active[q] = 0;
-        else atomicAdd(n_active, 1);
+        else if (n_active) atomicAdd(n_active, 1);
     }
 }
 
@@ -185,12 +286,40 @@ __global__ void k_head_fill(const int64_t *__restrict__ off, const int32_t *__re
     }
 }
 
+
+// Head of each query's order in fixed slots: slot q*M + t holds the t-th
+// best candidate (t < min(M, C_q)) as its global index and data polygon, or
+// -1 in both (an empty slot).  Sizes are known before the lookup's counts,
+// so the call needs no host read.
+__global__ void k_head_fixed(const int64_t *__restrict__ off, const int32_t *__restrict__ cand_ids,
+                             const int32_t *__restrict__ order, int64_t nq, int32_t M,
+                             int32_t *__restrict__ hq, int64_t *__restrict__ hc,
+                             int32_t *__restrict__ hid)
+{
+    const int64_t total = nq * (int64_t)M;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = s / M;
+        const int t = (int)(s - q * M);
+        const int64_t a = off[q], n = off[q + 1] - a;
+        hq[s] = (int32_t)q;
+        if (t < n) {
+            const int64_t c = a + order[a + t];
+            hc[s] = c;
+            hid[s] = cand_ids[c];
+        } else {
+            hc[s] = -1;
+            hid[s] = -1;
+        }
+    }
+}
+
 __global__ void k_scatter_scores(const int64_t *__restrict__ idx, const float *__restrict__ val,
                                  int64_t n, float *__restrict__ score)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        score[idx[i]] = val[i];
+        if (idx[i] >= 0) score[idx[i]] = val[i];
 }
 
 __global__ __launch_bounds__(256) void k_jhat(const uint32_t *__restrict__ lsig,
@@ -233,6 +362,28 @@ polymh_status launch_head_select(const int64_t *off, const int32_t *cand_ids, in
     hipLaunchKernelGGL(k_head_fill, dim3(g_of(nq, 1)), dim3(64), 0, s, off, cand_ids, order, hoff, nq,
                        hq, hc, hid);
     return check_launch("head_select");
+}
+
+polymh_status launch_head_fixed(const int64_t *off, const int32_t *cand_ids, int64_t nq, const int32_t *order,
+                                int32_t M, int32_t *hq, int64_t *hc, int32_t *hid, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_head_fixed, dim3(g_of(nq * (int64_t)M, 256)), dim3(256), 0, s, off, cand_ids, order, nq,
+                       M, hq, hc, hid);
+    return check_launch("head_fixed");
+}
+
+polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, int32_t k, const int64_t *off,
+                                    const int32_t *cand_ids, int64_t nq, float *score, int32_t *order,
+                                    uint8_t *sorted_ok, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "rank_jhat: too many queries");
+    const int vec = (k & 3) == 0 && k <= 1024 && (reinterpret_cast<uintptr_t>(qsig) & 15) == 0 &&
+                    (reinterpret_cast<uintptr_t>(dsig) & 15) == 0;
+    hipLaunchKernelGGL(k_rank_jhat_sort, dim3((unsigned)nq), dim3(1024), 0, s, qsig, dsig, k, vec, off, cand_ids,
+                       score, order, sorted_ok);
+    return check_launch("rank_jhat");
 }
 
 polymh_status launch_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,
@@ -281,12 +432,12 @@ polymh_status launch_round_merge(const int64_t *off, const float *score, const i
                                  const uint8_t *sorted_ok, const int64_t *roff, const int32_t *rids,
                                  const double *rj, int64_t nq, int32_t topk, float margin,
                                  int64_t *cursor, uint8_t *active, int32_t *top_ids, double *top_j,
-                                 int32_t *n_active, hipStream_t s)
+                                 int32_t *n_active, unsigned long long *counters, int finishing, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_active);
+    if (n_active) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_active);
     hipLaunchKernelGGL(k_round_merge, dim3(g_of(nq, 256)), dim3(256), 0, s, off, score, order,
                        sorted_ok, roff, rids, rj, nq, topk, margin, cursor, active, top_ids, top_j,
-                       n_active);
+                       n_active, counters, finishing);
     return check_launch("round_merge");
 }
 

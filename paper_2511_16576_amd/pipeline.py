@@ -2,7 +2,18 @@
 refinement -> top-10 for a fixed-shape batch of queries, run eagerly or
 captured once as a HIP graph and replayed per batch.  Every buffer is
 allocated up front; the lookup has a fixed candidate capacity with a device
-overflow flag, so no stage needs the host."""
+overflow flag, so no stage needs the host.
+
+Three ways to refine the candidates of a batch (``method``):
+  "plain"  every candidate refined, then the top-10;
+  "jhat"   candidates ordered by their collision fraction (Thm. 1's estimate
+           of J) and refined best-first with early stop;
+  "scorer" the same order, then the learned scorer re-predicts the first
+           ``head`` candidates of each query and the order is rebuilt from
+           those predictions before the early-stop refinement.
+The early stop runs a fixed number of rounds of F refinements per active
+query on the device, then a finishing pass completes any query still
+active, so the result never depends on a host read."""
 from __future__ import annotations
 
 import numpy as np
@@ -14,10 +25,14 @@ from . import polymh as pm
 class QueryBatch:
     def __init__(self, D: pm.DevicePolys, sorted_keys, sorted_ent, box, seed: int, k: int, cap: int,
                  bands: int, rows: int, n_queries: int, max_vertices: int, cand_cap: int,
-                 sign_config=None, topk: int = 10, binned=None):
+                 sign_config=None, topk: int = 10, binned=None, method: str = "plain", dsig=None,
+                 scorer=None, dfeat=None, head: int = 32, F: int = 8, rounds: int = 4, margin: float = 0.0):
         """``binned``: None signs the queries by the walk; a dict with
         horizon, bin_bits and walk_ratio signs them from binned samples
-        (``polymh_sign_binned``, the same bits)."""
+        (``polymh_sign_binned``, the same bits).  ``method`` "jhat" and
+        "scorer" need the data signatures ``dsig`` ([N][k]); "scorer" also
+        the trained ``scorer`` (params, BF16 weights) and the data shape
+        features ``dfeat``."""
         dev = D.offsets.device
         self.D, self.sk, self.se = D, sorted_keys, sorted_ent
         self.box, self.seed, self.k, self.cap = box, seed, k, cap
@@ -45,6 +60,32 @@ class QueryBatch:
         self.ws_refine = pm.refine_workspace(dev)
         self.top_ids = torch.empty((n_queries, topk), dtype=torch.int32, device=dev)
         self.top_j = torch.empty((n_queries, topk), dtype=torch.float64, device=dev)
+        if method not in ("plain", "jhat", "scorer"):
+            raise ValueError(f"unknown method {method!r}")
+        self.method = method
+        self.F, self.rounds, self.margin, self.head = F, rounds, margin, head
+        if method != "plain":
+            if dsig is None or dsig.shape[1] != k:
+                raise ValueError("ranked methods need the data signatures at the batch's k")
+            self.dsig = dsig
+            self.score = torch.empty(cand_cap, dtype=torch.float32, device=dev)
+            self.order = torch.empty(cand_cap, dtype=torch.int32, device=dev)
+            self.sorted_ok = torch.empty(n_queries, dtype=torch.uint8, device=dev)
+            self.ws_rank = pm.rank_workspace(n_queries, cand_cap, F, dev)
+            self.counts = torch.zeros(2, dtype=torch.int64, device=dev)
+        if method == "scorer":
+            if scorer is None or dfeat is None:
+                raise ValueError("the scorer method needs a trained scorer and the data features")
+            self.scorer, self.dfeat = scorer, dfeat
+            self.qfeat = torch.empty((n_queries, 12), dtype=torch.float32, device=dev)
+            R = n_queries * head
+            self.R_pad = ((R + 31) // 32) * 32
+            self.hq = torch.empty(max(R, 1), dtype=torch.int32, device=dev)
+            self.hc = torch.empty(max(R, 1), dtype=torch.int64, device=dev)
+            self.hid = torch.empty(max(R, 1), dtype=torch.int32, device=dev)
+            self.X = torch.empty((self.R_pad, 288), dtype=torch.int16, device=dev)
+            self.acts, _ = pm.mlp_buffers(self.R_pad, dev)
+            self.y = torch.empty(self.R_pad, dtype=torch.float32, device=dev)
         self.stream = torch.cuda.Stream()
         self.graph = None
 
@@ -72,10 +113,27 @@ class QueryBatch:
         pm.band(self.sig, self.bands, self.rows, self.seed, out=self.keys, stream=s)
         pm.query_capped(self.sk, self.se, self.D.n, self.keys, self.cand_off, self.cand_ids,
                         self.overflow, self.ws_query, stream=s)
-        pm.refine(self.D, self.Q, self.cand_off, self.cand_ids, out=self.cand_j, stream=s,
-                  n_cand=self.cand_ids.numel(), ws=self.ws_refine)
-        pm.topk(self.cand_off, self.cand_ids, self.cand_j, self.topk, stream=s,
-                out=(self.top_ids, self.top_j))
+        if self.method == "plain":
+            pm.refine(self.D, self.Q, self.cand_off, self.cand_ids, out=self.cand_j, stream=s,
+                      n_cand=self.cand_ids.numel(), ws=self.ws_refine)
+            pm.topk(self.cand_off, self.cand_ids, self.cand_j, self.topk, stream=s,
+                    out=(self.top_ids, self.top_j))
+            return
+        pm.rank_jhat_order(self.sig, self.dsig, self.cand_off, self.cand_ids, score=self.score, order=self.order,
+                           sorted_ok=self.sorted_ok, stream=s)
+        if self.method == "scorer":
+            sc = self.scorer
+            pm.rank_head_fixed(self.cand_off, self.cand_ids, self.order, self.head,
+                               out=(self.hq, self.hc, self.hid), stream=s)
+            pm.poly_features(self.Q, self.box, out=self.qfeat, stream=s)
+            pm.pair_features(self.sig, self.qfeat, self.dsig, self.dfeat, self.hq, self.hid, R_pad=self.R_pad,
+                             out=self.X, stream=s)
+            pm.mlp_forward(self.X, sc.params, sc.wbf16, self.acts, y=self.y, stream=s)
+            pm.scatter_scores(self.hc, self.y[:self.hc.numel()], self.score, stream=s)
+            pm.rank_order(self.cand_off, self.score, self.order, self.sorted_ok, stream=s)
+        pm.rank_refine_ordered(self.D, self.Q, self.cand_off, self.cand_ids, self.score, self.order,
+                               self.sorted_ok, topk=self.topk, F=self.F, rounds=self.rounds, margin=self.margin,
+                               ws=self.ws_rank, out=(self.top_ids, self.top_j), counts=self.counts, stream=s)
 
     def run_eager(self):
         with torch.cuda.stream(self.stream):

@@ -101,6 +101,11 @@ _SIGNATURES = {
     "polymh_scatter_scores": (I32, [P, P, I64, P, P]),
     "polymh_rank_refine": (I32, [P, P, P, P, P, I64, I64, I32, I32, ctypes.c_float, I32, P, SZ,
                                  P, P, P, P, P]),
+    "polymh_rank_jhat_order": (I32, [P, P, I32, P, P, I64, P, P, P, P]),
+    "polymh_rank_order": (I32, [P, I64, P, P, P, P]),
+    "polymh_rank_head_fixed": (I32, [P, P, I64, P, I32, P, P, P, P]),
+    "polymh_rank_refine_ordered": (I32, [P, P, P, P, P, P, P, I64, I64, I32, I32, I32, ctypes.c_float,
+                                         P, SZ, P, P, P, P]),
 }
 
 
@@ -545,8 +550,8 @@ def gemm_bf16(A, a_row_stride, a_k_stride, B, b_col_stride, b_k_stride, M, N, K,
     return C[:M, :N]
 
 
-def poly_features(polys: DevicePolys, box, stream=None) -> torch.Tensor:
-    f = torch.empty((max(polys.n, 1), 12), dtype=torch.float32, device=polys.offsets.device)
+def poly_features(polys: DevicePolys, box, out=None, stream=None) -> torch.Tensor:
+    f = torch.empty((max(polys.n, 1), 12), dtype=torch.float32, device=polys.offsets.device) if out is None else out
     ps = polys.cstruct()
     _check(lib().polymh_poly_features(ctypes.byref(ps), _box(box), _ptr(f), _stream(stream)))
     return f[:polys.n]
@@ -618,6 +623,70 @@ def rank_refine(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, sco
                                     ws.numel(), _ptr(ids), _ptr(js), ctypes.byref(nref),
                                     ctypes.byref(rounds), _stream(stream)))
     return ids[:nq], js[:nq], int(nref.value), int(rounds.value)
+
+
+def rank_jhat_order(qsig, dsig, cand_off, cand_ids, score=None, order=None, sorted_ok=None, stream=None):
+    """Collision fraction of every candidate and each query's best-first
+    order: (score float32 [C], order int32 [C], sorted_ok uint8 [nq])."""
+    nq = cand_off.numel() - 1
+    dev = cand_off.device
+    C = cand_ids.numel()
+    score = torch.empty(max(C, 1), dtype=torch.float32, device=dev) if score is None else score
+    order = torch.empty(max(C, 1), dtype=torch.int32, device=dev) if order is None else order
+    sorted_ok = torch.empty(max(nq, 1), dtype=torch.uint8, device=dev) if sorted_ok is None else sorted_ok
+    _check(lib().polymh_rank_jhat_order(_ptr(qsig), _ptr(dsig), qsig.shape[1], _ptr(cand_off), _ptr(cand_ids),
+                                        nq, _ptr(score), _ptr(order), _ptr(sorted_ok), _stream(stream)))
+    return score, order, sorted_ok
+
+
+def rank_order(cand_off, score, order, sorted_ok, stream=None):
+    """Best-first order of each query's candidates by the given scores."""
+    _check(lib().polymh_rank_order(_ptr(cand_off), cand_off.numel() - 1, _ptr(score), _ptr(order),
+                                   _ptr(sorted_ok), _stream(stream)))
+
+
+def rank_head_fixed(cand_off, cand_ids, order, M, out=None, stream=None):
+    """First M candidates of each query's order in fixed slots q*M + t:
+    (head_query int32, head_cand int64 (-1 empty), head_id int32 (-1 empty))."""
+    nq = cand_off.numel() - 1
+    dev = cand_off.device
+    if out is None:
+        n = max(nq * M, 1)
+        out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int64, device=dev),
+               torch.empty(n, dtype=torch.int32, device=dev))
+    hq, hc, hid = out
+    _check(lib().polymh_rank_head_fixed(_ptr(cand_off), _ptr(cand_ids), nq, _ptr(order), M, _ptr(hq), _ptr(hc),
+                                        _ptr(hid), _stream(stream)))
+    return hq, hc, hid
+
+
+def rank_refine_ordered(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, score, order, sorted_ok,
+                        topk=10, F=16, rounds=4, margin=0.0, ws=None, out=None, counts=None, n_cand=None,
+                        stream=None):
+    """Best-first refinement with early stop and no host reads (graph-
+    capturable): (top_ids, top_j, counts int64 [2] = refined pairs, queries
+    completed by the finishing pass)."""
+    nq = queries.n
+    C = cand_ids.numel() if n_cand is None else n_cand
+    dev = cand_off.device
+    need = int(lib().polymh_rank_workspace_size(nq, C, F))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    if out is None:
+        out = (torch.empty((max(nq, 1), topk), dtype=torch.int32, device=dev),
+               torch.empty((max(nq, 1), topk), dtype=torch.float64, device=dev))
+    ids, js = out
+    counts = torch.zeros(2, dtype=torch.int64, device=dev) if counts is None else counts
+    dp, qp = data.cstruct(), queries.cstruct()
+    _check(lib().polymh_rank_refine_ordered(ctypes.byref(dp), ctypes.byref(qp), _ptr(cand_off), _ptr(cand_ids),
+                                            _ptr(score), _ptr(order), _ptr(sorted_ok), nq, C, topk, F, rounds,
+                                            float(margin), _ptr(ws), ws.numel(), _ptr(ids), _ptr(js),
+                                            _ptr(counts), _stream(stream)))
+    return ids[:nq], js[:nq], counts
+
+
+def rank_workspace(nq, n_cand, F, device="cuda"):
+    return _workspace(int(lib().polymh_rank_workspace_size(nq, n_cand, F)), device)
 
 
 # ------------------------------------------------------- graphs (batching)

@@ -1,0 +1,216 @@
+"""Ranked refinement without host reads (the form a captured query batch
+uses): collision-fraction scores and orders, fixed head slots, the ordered
+early-stop refinement with its finishing pass, and whole query batches of
+each method replayed as graphs against their eager runs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_16576_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_16576_amd import polymh
+    polymh.check_device()
+    return polymh
+
+
+@pytest.fixture(scope="module")
+def setup(pm):
+    """A 3,000-polygon workload-2 subset signed at k = 256 (bit-exact with the
+    oracle, checked here), 64 x 4 bands, 48 queries and their candidates."""
+    import torch
+    w = dg.workload(2, n=3000, n_queries=48)
+    D, Q = pm.to_device(w.data), pm.to_device(w.queries)
+    k = 256
+    sig = pm.sign(D, w.box, 0, k, w.cap)
+    qsig = pm.sign(Q, w.box, 0, k, w.cap)
+    osig = oracle.sign(w.data, w.box, 0, k, w.cap)
+    oqsig = oracle.sign(w.queries, w.box, 0, k, w.cap)
+    assert np.array_equal(sig.cpu().numpy().view(np.uint32), osig)
+    assert np.array_equal(qsig.cpu().numpy().view(np.uint32), oqsig)
+    sk, se = pm.index_build(pm.band(sig, 64, 4, 0))
+    off, ids = pm.query(sk, se, D.n, pm.band(qsig, 64, 4, 0))
+    torch.cuda.synchronize()
+    return dict(w=w, D=D, Q=Q, sig=sig, qsig=qsig, osig=osig, oqsig=oqsig, sk=sk, se=se, off=off, ids=ids)
+
+
+def _check_order(score, off, order):
+    """Within each query, positions sorted by (score desc, position asc)."""
+    for q in range(off.size - 1):
+        a, b = off[q], off[q + 1]
+        pos = order[a:b]
+        assert np.array_equal(np.sort(pos), np.arange(b - a)), q
+        s = score[a + pos]
+        key = np.lexsort((pos, -s))
+        assert np.array_equal(key, np.arange(b - a)), q
+
+
+def test_jhat_order_matches_definition(pm, setup):
+    off, ids = setup["off"], setup["ids"]
+    score, order, ok = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
+    o, i = off.cpu().numpy(), ids.cpu().numpy()
+    sc, od = score.cpu().numpy()[:i.size], order.cpu().numpy()[:i.size]
+    # the share of the 256 oracle hashes on which query and candidate agree
+    rows = np.repeat(np.arange(o.size - 1), np.diff(o))
+    want = (setup["oqsig"][rows] == setup["osig"][i]).mean(axis=1).astype(np.float32)
+    assert np.array_equal(sc, want)
+    assert (ok.cpu().numpy() == 1).all()
+    _check_order(sc, o, od)
+    # rank_order on the same scores gives the same order
+    order2 = order.clone()
+    pm.rank_order(off, score, order2, ok)
+    assert np.array_equal(order2.cpu().numpy()[:i.size], od)
+
+
+@pytest.mark.parametrize("k", [1, 37, 64, 100, 300])
+def test_jhat_order_other_k(pm, k):
+    """Signature lengths off the vector path (not a multiple of 4, or beyond
+    256) and tiny ones."""
+    import torch
+    rng = np.random.default_rng(k)
+    qs = rng.integers(1, 4, (5, k)).astype(np.uint32)
+    ds = rng.integers(1, 4, (40, k)).astype(np.uint32)
+    counts = np.array([0, 7, 40, 1, 13])
+    off = np.zeros(6, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    ids = np.concatenate([rng.choice(40, c, replace=False) for c in counts]).astype(np.int32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    score, order, ok = pm.rank_jhat_order(t(qs.view(np.int32)), t(ds.view(np.int32)), t(off), t(ids))
+    rows = np.repeat(np.arange(5), counts)
+    want = (qs[rows] == ds[ids]).sum(axis=1).astype(np.float32) * np.float32(1.0 / k)
+    assert np.array_equal(score.cpu().numpy()[:ids.size], want)
+    _check_order(want, off, order.cpu().numpy()[:ids.size])
+
+
+def test_head_fixed(pm, setup):
+    off, ids = setup["off"], setup["ids"]
+    score, order, ok = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
+    M = 20
+    hq, hc, hid = (x.cpu().numpy() for x in pm.rank_head_fixed(off, ids, order, M))
+    o, i, od = off.cpu().numpy(), ids.cpu().numpy(), order.cpu().numpy()
+    for q in range(o.size - 1):
+        n = o[q + 1] - o[q]
+        for t in range(M):
+            s = q * M + t
+            assert hq[s] == q
+            if t < n:
+                c = o[q] + od[o[q] + t]
+                assert hc[s] == c and hid[s] == i[c]
+            else:
+                assert hc[s] == -1 and hid[s] == -1
+
+
+def test_ordered_refine_inf_margin_is_full(pm, setup):
+    D, Q, off, ids = setup["D"], setup["Q"], setup["off"], setup["ids"]
+    J = pm.refine(D, Q, off, ids)
+    ti, tj = pm.topk(off, ids, J, 10)
+    score, order, ok = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
+    for rounds in (0, 1, 3):
+        a_ids, a_j, cnt = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=8, rounds=rounds,
+                                                 margin=float("inf"))
+        assert np.array_equal(a_ids.cpu().numpy(), ti.cpu().numpy()), rounds
+        assert np.array_equal(a_j.cpu().numpy(), tj.cpu().numpy()), rounds
+        c = cnt.cpu().numpy()
+        assert c[0] == ids.numel(), rounds
+        # queries with more than rounds * F candidates are completed by the finishing pass
+        want_fin = int((np.diff(off.cpu().numpy()) > rounds * 8).sum())
+        assert c[1] == want_fin, (rounds, c[1], want_fin)
+
+
+def test_ordered_refine_exact_scores(pm, setup):
+    """With the exact J as scores and margin 0 the early stop returns the
+    exact top-10 (every candidate it skips has a J at most the 10th best),
+    refines fewer pairs, and equals the host-driven rank_refine."""
+    D, Q, off, ids = setup["D"], setup["Q"], setup["off"], setup["ids"]
+    J = pm.refine(D, Q, off, ids)
+    ti, tj = pm.topk(off, ids, J, 10)
+    score = J.float()
+    order = torch_empty_like_int(ids)
+    ok = torch_empty_u8(Q.n)
+    pm.rank_order(off, score, order, ok)
+    b_ids, b_j, cnt = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=4, rounds=64, margin=0.0)
+    assert np.allclose(b_j.cpu().numpy(), tj.cpu().numpy(), rtol=0, atol=1e-6)
+    c = cnt.cpu().numpy()
+    assert c[0] < ids.numel() and c[1] == 0
+    h_ids, h_j, nref, rounds = pm.rank_refine(D, Q, off, ids, score, topk=10, F=4, margin=0.0)
+    assert nref == c[0]
+    assert np.array_equal(h_ids.cpu().numpy(), b_ids.cpu().numpy())
+    assert np.array_equal(h_j.cpu().numpy(), b_j.cpu().numpy())
+    # too few rounds: the finishing pass completes the active queries
+    f_ids, f_j, cnt1 = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=1, rounds=2,
+                                              margin=0.0)
+    assert np.allclose(f_j.cpu().numpy(), tj.cpu().numpy(), rtol=0, atol=1e-6)
+    assert cnt1.cpu().numpy()[1] > 0
+    # the host-driven call with max_rounds exhausted now finishes too
+    g_ids, g_j, nref1, r1 = pm.rank_refine(D, Q, off, ids, score, topk=10, F=1, margin=0.0, max_rounds=2)
+    assert r1 == 2
+    assert np.array_equal(g_ids.cpu().numpy(), f_ids.cpu().numpy())
+    assert nref1 == int(cnt1.cpu().numpy()[0])
+
+
+def torch_empty_like_int(t):
+    import torch
+    return torch.empty(max(t.numel(), 1), dtype=torch.int32, device=t.device)
+
+
+def torch_empty_u8(n):
+    import torch
+    return torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("method", ["jhat", "scorer"])
+def test_ranked_batch_graph_equals_eager(pm, setup, method):
+    """A whole batch (sign, band, capped lookup, ranking, early-stop
+    refinement) captured as one graph: every replay equals the eager run,
+    with eager work between replays; margin +inf equals the plain batch."""
+    import torch
+    from paper_2511_16576_amd import scorer as sc
+    from paper_2511_16576_amd.pipeline import QueryBatch
+    w, D = setup["w"], setup["D"]
+    feats = pm.poly_features(D, w.box)
+    s = sc.init_scorer(0)
+    cap = int(setup["ids"].numel()) * 2 + 1024
+    common = dict(box=w.box, seed=0, k=256, cap=w.cap, bands=64, rows=4, n_queries=w.queries.n,
+                  max_vertices=w.queries.xy.shape[0], cand_cap=cap)
+    plain = QueryBatch(D, setup["sk"], setup["se"], **common)
+    plain.load(w.queries)
+    plain.run_eager()
+    p_ids, p_j = (x.clone() for x in plain.result())
+    for margin in (0.02, float("inf")):
+        qb = QueryBatch(D, setup["sk"], setup["se"], **common, method=method, dsig=setup["sig"], scorer=s,
+                        dfeat=feats, head=16, F=4, rounds=3, margin=margin)
+        qb.load(w.queries)
+        qb.run_eager()
+        e_ids, e_j = (x.clone() for x in qb.result())
+        e_cnt = qb.counts.clone()
+        qb.capture()
+        for rep in range(3):
+            qb.top_ids.fill_(-7)
+            torch.cuda.synchronize()
+            qb.run_graph()
+            g_ids, g_j = qb.result()
+            assert torch.equal(g_ids, e_ids) and torch.equal(g_j, e_j), (margin, rep)
+            assert torch.equal(qb.counts, e_cnt)
+            # eager work of the program between replays
+            pm.refine(D, plain.Q, plain.cand_off, plain.cand_ids, n_cand=plain.cand_ids.numel())
+            torch.cuda.synchronize()
+        if margin == float("inf"):
+            assert torch.equal(e_ids, p_ids) and torch.equal(e_j, p_j)
+        else:
+            # every answer is an exact J of its pair, in (J desc, id asc) order
+            J = pm.refine(D, qb.Q, qb.cand_off, qb.cand_ids).cpu().numpy()
+            o, i = qb.cand_off.cpu().numpy(), qb.cand_ids.cpu().numpy()
+            ei, ej = e_ids.cpu().numpy(), e_j.cpu().numpy()
+            for q in range(o.size - 1):
+                lst = dict(zip(i[o[q]:o[q + 1]].tolist(), J[o[q]:o[q + 1]].tolist()))
+                got = [(x, y) for x, y in zip(ei[q], ej[q]) if x >= 0]
+                assert all(lst[x] == y for x, y in got), q
+                assert got == sorted(got, key=lambda t: (-t[1], t[0])), q
+        del qb
