@@ -150,6 +150,25 @@ polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t se
                           uint32_t cap, uint32_t *sig, const polymh_sign_config *cfg_host,
                           void *ws, size_t ws_bytes, void *stream);
 
+/* polymh_sign_static -- polymh_sign without a caller workspace, for callers
+ * that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The staging polymh_sign
+ * keeps in `ws` lives instead in a static device array of the library
+ * (about 8 MiB, room for POLYMH_SIGN_STATIC_MAX_POLYS polygons), one copy per
+ * GPU, held until the process ends; the call allocates and frees nothing.
+ *   n > POLYMH_SIGN_STATIC_MAX_POLYS: POLYMH_EINVAL (use polymh_sign).
+ *   Every call on a GPU shares that GPU's array, and the kernels set every
+ *   word they read from it: calls that overlap on one GPU (other streams,
+ *   other host threads) race and give wrong signatures, so callers must
+ *   serialise them.  The first call on a device looks up the array's device
+ *   address (hipGetSymbolAddress, not a stream operation).
+ * Otherwise exactly polymh_sign (same arguments, bits and errors).
+ * Stream-ordered. */
+#define POLYMH_SIGN_STATIC_MAX_POLYS 262144
+polymh_status polymh_sign_static(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                 uint32_t cap, uint32_t *sig, const polymh_sign_config *cfg_host,
+                                 void *stream);
+
 /* polymh_join_rings -- polygons with holes and multipolygons (the shapes of
  * the paper's real datasets, Sec. 5.1) as single rings that every call of
  * this library takes as they are.  Input: shape p owns rings

@@ -251,6 +251,67 @@ polymh_status polymh_sign(const polymh_polys *polys, polymh_box box, uint64_t se
     return launch_sign(L, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of polymh_sign_static: the staging polymh_sign keeps in its
+// workspace (work-queue counter, MBRs, doubled areas, flags, longest-first
+// order) for up to POLYMH_SIGN_STATIC_MAX_POLYS polygons, laid out as
+// carve_sign lays out a workspace.  One copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device
+// memory: kernels get the address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kStaticSignBytes = (8u << 20) + 4096;
+__device__ __align__(256) unsigned char scratch[kStaticSignBytes];
+
+// The device address of this GPU's `scratch`, looked up once per device with
+// that device current.
+polymh_status static_scratch(char **out)
+{
+    static std::mutex mu;
+    static char *ptrs[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(POLYMH_EDEVICE, "sign_static: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return set_error(POLYMH_EINVAL, "sign_static: device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(POLYMH_EDEVICE, "sign_static: scratch address: %s", hipGetErrorString(e));
+        ptrs[dev] = static_cast<char *>(p);
+    }
+    *out = ptrs[dev];
+    return POLYMH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+polymh_status polymh_sign_static(const polymh_polys *polys, polymh_box box, uint64_t seed, int32_t k,
+                                 uint32_t cap, uint32_t *sig, const polymh_sign_config *cfg, void *stream)
+{
+    polymh_status st = check_polys(polys, "sign_static");
+    if (st) return st;
+    if (polys->n > POLYMH_SIGN_STATIC_MAX_POLYS)
+        return set_error(POLYMH_EINVAL, "sign_static: %lld polygons, at most %d (use polymh_sign with a workspace)",
+                         (long long)polys->n, POLYMH_SIGN_STATIC_MAX_POLYS);
+    polymh_sign_config c;
+    if (cfg) c = *cfg;
+    else polymh_sign_default_config(&c);
+    Carve need{nullptr, 0};
+    carve_sign(need, polys->n, c.persistent != 0);
+    if (need.used > kStaticSignBytes)
+        return set_error(POLYMH_EINVAL, "sign_static: staging needs %zu bytes, the scratch holds %zu", need.used,
+                         kStaticSignBytes);
+    char *ws = nullptr;
+    if ((st = static_scratch(&ws))) return st;
+    return polymh_sign(polys, box, seed, k, cap, sig, &c, ws, kStaticSignBytes, stream);
+}
+
 int64_t polymh_join_rings_size(int64_t n_vertices, int64_t n_rings, int64_t n_polys)
 {
     if (n_vertices < 0 || n_rings < 0 || n_polys < 0) return -1;

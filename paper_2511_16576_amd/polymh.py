@@ -62,6 +62,7 @@ _SIGNATURES = {
     "polymh_sign_default_config": (None, [P]),
     "polymh_sign_workspace_size": (SZ, [I64, P]),
     "polymh_sign": (I32, [P, Box, U64, I32, U32, P, P, P, SZ, P]),
+    "polymh_sign_static": (I32, [P, Box, U64, I32, U32, P, P, P]),
     "polymh_join_rings_size": (I64, [I64, I64, I64]),
     "polymh_join_rings": (I32, [P, I64, P, I64, P, I64, P, I64, P, P, P]),
     "polymh_sign_binned_workspace_size": (SZ, [I64, I32, U32, U32, I32, P]),
@@ -306,6 +307,23 @@ def sign(polys: DevicePolys, box, seed: int, k: int, cap: int, config: SignConfi
     _check(lib().polymh_sign(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, _ptr(out),
                              ctypes.byref(config) if config else None, _ptr(ws), ws.numel(),
                              _stream(stream)))
+    return out[:n]
+
+
+SIGN_STATIC_MAX_POLYS = 262144
+
+
+def sign_static(polys: DevicePolys, box, seed: int, k: int, cap: int, config: SignConfig | None = None,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """``sign`` on the library's static scratch (no workspace): int32 [n, k]."""
+    check_device()
+    n = polys.n
+    if out is None:
+        out = torch.empty((max(n, 1), k), dtype=torch.int32, device=polys.offsets.device)
+    ps = polys.cstruct()
+    cfg = ctypes.byref(config) if config is not None else None
+    _check(lib().polymh_sign_static(ctypes.byref(ps), _box(box), seed & ((1 << 64) - 1), k, cap, _ptr(out), cfg,
+                                    _stream(stream)))
     return out[:n]
 
 
