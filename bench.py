@@ -1,12 +1,19 @@
-"""Benchmark of the PolyMinHash signing and search path on one MI355X.
+"""Benchmark of the PolyMinHash search path on one MI355X.
 
-One step = the whole path over one batch, inputs resident in HBM:
-  sign the 100,000-polygon workload (k=128, cap 2^22, persistent launch),
-  band it, build the bucket table, then answer 10,000 queries (sign, band,
-  candidate lookup, exact-Jaccard refinement, top-10).
-value = signatures produced per second of step time ((N + Q) * k / step).
-The line also carries per-stage times (HIP events), the signing kernel's
-roofline figures and the CPU oracle's rate on the host cores.
+Headline (one step = one replay of a captured HIP graph over a batch of
+10,000 queries against the 4,000,000-polygon heavy-tailed workload, k = 256,
+cap 2^26, inputs resident in HBM): sign the queries from the shared binned
+samples, band them (64 x 4), look their candidates up in the bucket table,
+order the candidates (collision fraction, re-scored by the learned scorer),
+refine best-first with early stop, top-10.  The early-stop margin is
+calibrated on 1,000 queries to recall@10 >= 0.95 against brute force, and
+recall is measured on 1,000 other queries.  value = queries per second of
+the learned form; the plain pipeline (every candidate refined) and the
+collision-fraction order are timed the same way beside it, and the
+dataset's signing rate (binned, 4,000,000 x 256) is reported as its own
+field.  Secondary sections: the workload-2 signing and refinement rooflines,
+binned against walked signing, workload 3's bandings, the learned-scorer
+workload 4, holed shapes, centring, query batches, the autotuner.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -49,7 +56,21 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--queries", type=int, default=10_000)
+    ap.add_argument("--queries", type=int, default=10_000, help="queries per batch (both workloads)")
+    ap.add_argument("--cfg5-polygons", type=int, default=4_000_000)
+    ap.add_argument("--head-bands", type=int, default=64, help="bands of the headline's bucket table")
+    ap.add_argument("--head-rows", type=int, default=4)
+    ap.add_argument("--calib", type=int, default=1000, help="calibration queries (recall of the early stop)")
+    ap.add_argument("--eval", type=int, default=1000, help="held-out queries for the reported recall")
+    ap.add_argument("--rank-F", type=int, default=10, help="refinements per query in the first early-stop rounds")
+    ap.add_argument("--rank-rounds", type=int, default=5,
+                    help="early-stop rounds (F, F, 2F, 4F, ...) before the finishing pass")
+    ap.add_argument("--scorer-head", type=int, default=32, help="candidates per query the network re-scores")
+    ap.add_argument("--only-headline", action="store_true", help="skip every secondary section")
+    ap.add_argument("--trace-window", default=None,
+                    help="comma list of methods (plain, jhat, scorer): after the headline, --trace-replays "
+                         "replays of each method's graph between marker kernels (windowed rocprofv3 summaries)")
+    ap.add_argument("--trace-replays", type=int, default=5)
     ap.add_argument("--bands", type=int, default=32)
     ap.add_argument("--rows", type=int, default=4)
     ap.add_argument("--recall-sample", type=int, default=100)
@@ -60,10 +81,7 @@ def parse():
     ap.add_argument("--no-binned", action="store_true", help="skip the binned-signing comparison")
     ap.add_argument("--no-rings", action="store_true", help="skip the holes / multipolygon measurement")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the workload-3 query pipeline")
-    ap.add_argument("--cfg5-queries", type=int, default=10_000,
-                    help="workload-5 queries per captured-graph batch (0: skip the workload-5 query pipeline)")
-    ap.add_argument("--binned-cfg5", type=int, default=4_000_000,
-                    help="polygons of workload 5 for the binned-signing comparison (4,000,000: all; 0: skip)")
+    ap.add_argument("--no-walk5", action="store_true", help="skip the walk of the 4,000,000 workload-5 polygons")
     ap.add_argument("--batch-queries", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 256 MiB device-to-device once (reference for HBM counters)")
@@ -72,68 +90,187 @@ def parse():
     return ap.parse_args()
 
 
-def cfg5_pipeline(w5, D5, sig5, par5, cfg, dev):
-    """Workload 5's query side: 32 x 8 bucket table over the 4,000,000
-    signatures, then all queries as one batch through the preallocated
-    pipeline (queries signed from binned samples, band, capped lookup,
-    refine, top-10), issued eagerly or replayed as a captured HIP graph;
-    the same batch with walked query signatures; recall@10 of 200 sampled
-    queries against brute force (MBR-prefiltered exact J)."""
+# early-stop margins tried in order (the first reaching the recall target
+# on the calibration queries is kept); a negative margin stops before the
+# next candidate's predicted J falls below the 10th exact J
+MARGINS = [-0.12, -0.1, -0.08, -0.07, -0.06, -0.05, -0.04, -0.03, -0.025, -0.02, -0.015, -0.01, -0.005, 0.0, 0.005, 0.01, 0.015, 0.02, 0.025,
+           0.03, 0.04, 0.05, 0.06, 0.08, 0.1, 0.15, 0.2, 0.3, 0.5]
+
+
+def headline(args):
+    """Workload 5's query side: returns (line fields, reusable state)."""
     import torch
+    from paper_2511_16576_amd import datagen as dg
     from paper_2511_16576_amd import metrics
     from paper_2511_16576_amd import polymh as pm
+    from paper_2511_16576_amd import scorer as sc
     from paper_2511_16576_amd.pipeline import QueryBatch
-    b5, r5 = 32, 8
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dev = torch.device("cuda")
     st = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    t0 = time.time()
+    w5 = dg.workload(5, n=args.cfg5_polygons, n_queries=args.queries)
+    log(f"workload 5 generated in {time.time() - t0:.1f}s: {w5.data.n} polygons, {w5.data.xy.shape[0]} vertices, "
+        f"{w5.queries.n} queries")
+    D5 = pm.to_device(w5.data)
+    k, cap, B, R, nq = w5.k, w5.cap, args.head_bands, args.head_rows, w5.queries.n
+    # -- the dataset's signatures from the shared binned samples (the same
+    # bits as Alg. 1's walk; every launch of them is timed by HIP events)
+    h5, bb5 = pm.binned_params(D5, w5.box, k, cap)
+    cfgb = pm.binned_config(D5)
+    par5 = {"horizon": h5, "bin_bits": bb5, "walk_ratio": 300.0}
+    wsb = torch.empty(pm.sign_binned_workspace_size(D5.n, k, cap, h5, bb5, cfgb), dtype=torch.uint8, device=dev)
+    sig5 = torch.empty((D5.n, k), dtype=torch.int32, device=dev)
+    pm.sign_binned(D5, w5.box, w5.seed, k, cap, horizon=h5, bin_bits=bb5, config=cfgb, out=sig5, ws=wsb)
+    e0, e1 = ev(), ev()
     e0.record(st)
-    keys = pm.band(sig5, b5, r5, w5.seed)
+    for _ in range(2):
+        pm.sign_binned(D5, w5.box, w5.seed, k, cap, horizon=h5, bin_bits=bb5, config=cfgb, out=sig5, ws=wsb)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_sign = e0.elapsed_time(e1) / 2 / 1e3
+    del wsb
+    log(f"workload 5: dataset signed (binned) in {1e3 * t_sign:.1f} ms ({D5.n * k / t_sign:.3g} sig/s)")
+    # -- bucket table of the query batch's banding
+    e0.record(st)
+    keys = pm.band(sig5, B, R, w5.seed)
     sk, se = pm.index_build(keys)
     e1.record(st)
     torch.cuda.synchronize()
-    t_index = e0.elapsed_time(e1)
+    t_index = e0.elapsed_time(e1) / 1e3
     del keys
-    Qh = w5.queries
-    nq = Qh.n
-    Qd = pm.to_device(Qh)
-    qs = pm.sign_binned(Qd, w5.box, w5.seed, w5.k, w5.cap, horizon=par5["horizon"], bin_bits=par5["bin_bits"])
-    off, _ = pm.query(sk, se, D5.n, pm.band(qs, b5, r5, w5.seed))
+    dfeat = pm.poly_features(D5, w5.box)
+    # -- the learned scorer: 2,000,000 pairs mined from the 32 x 8 buckets of
+    # this set (half sharing a bucket, half uniform), exact J labels from the
+    # refinement kernel, trained on the GPU by the project's MFMA kernels
+    t0 = time.perf_counter()
+    sk8, se8 = pm.index_build(pm.band(sig5, 32, 8, w5.seed))
+    left, right = sc.mine_pairs(sk8, se8, D5.n, 32, args.train_pairs, seed=1)
+    del sk8, se8
+    J = sc.exact_pair_j(D5, left, right).float()
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    n_val = max(len(left) // 50, 1024)
+    scorer = sc.init_scorer(0)
+    t0 = time.perf_counter()
+    hist = sc.train(scorer, sig5, dfeat, left[n_val:], right[n_val:], J[n_val:], epochs=args.epochs, log=log)
+    t_train = time.perf_counter() - t0
+    Lv, Rv = torch.from_numpy(left[:n_val]).to(dev), torch.from_numpy(right[:n_val]).to(dev)
+    pv = sc.predict_pairs(scorer, sig5, dfeat, sig5, dfeat, Lv, Rv)
+    jv = pm.jhat(sig5, sig5, Lv, Rv)
+    learned = {"train_pairs": int(len(left)), "epochs": args.epochs, "label_s": t_label, "train_s": t_train,
+               "train_loss": hist, "val_mse_scorer": float(((pv - J[:n_val]) ** 2).mean()),
+               "val_mse_collision_fraction": float(((jv - J[:n_val]) ** 2).mean())}
+    log(f"scorer: held-out MSE {learned['val_mse_scorer']:.5f} (collision fraction "
+        f"{learned['val_mse_collision_fraction']:.5f}); trained in {t_train:.2f} s")
+    del J, pv, jv, Lv, Rv
+    # -- brute force (every dataset polygon whose MBR meets the query's,
+    # exact J by the refinement kernel) for the calibration queries and the
+    # held-out evaluation queries
+    ncal, nev = min(args.calib, nq), min(args.eval, max(nq - args.calib, 0))
+    t0 = time.time()
+    bi, bj = metrics.brute_force_topk_mbr(D5, pm.to_device(w5.queries.subset(np.arange(ncal + nev))), 10, chunk=64)
+    log(f"brute force top-10 of {ncal + nev} queries over {D5.n} polygons in {time.time() - t0:.1f}s")
+    cal, evq = np.arange(ncal), np.arange(ncal, ncal + nev)
+    # -- candidate capacity from one sizing lookup (+25%)
+    Qd = pm.to_device(w5.queries)
+    qs = pm.sign_binned(Qd, w5.box, w5.seed, k, cap, horizon=h5, bin_bits=bb5)
+    off, _ = pm.query(sk, se, D5.n, pm.band(qs, B, R, w5.seed))
     n_cand = int(off[-1].item())
-    out = {"queries": nq, "bands": b5, "rows": r5, "index_ms": t_index, "candidates_per_query": n_cand / nq}
-    for name, bparams in (("binned", par5), ("walk", None)):
-        qb = QueryBatch(D5, sk, se, w5.box, w5.seed, w5.k, w5.cap, b5, r5, nq, Qh.xy.shape[0],
-                        int(1.25 * n_cand) + 65536, sign_config=cfg, binned=bparams)
-        qb.load(Qh)
+    n_long = int(((off[1:] - off[:-1]) > 4096).sum().item())
+    cand_cap = int(1.25 * n_cand) + 65536
+    del qs, off, Qd
+    cfgq = pm.binned_config(pm.to_device(w5.queries))
+    methods = {}
+    batches = {}
+    for method in ("plain", "jhat", "scorer"):
+        qb = QueryBatch(D5, sk, se, w5.box, w5.seed, k, cap, B, R, nq, w5.queries.xy.shape[0], cand_cap,
+                        sign_config=cfgq, binned=par5, method=method, dsig=sig5, scorer=scorer, dfeat=dfeat,
+                        head=args.scorer_head, F=args.rank_F, rounds=args.rank_rounds,
+                        margin=float("inf") if method == "plain" else 0.0)
+        qb.load(w5.queries)
+        margin = float("inf")
+        if method != "plain":
+            # smallest margin of the grid whose recall@10 on the calibration
+            # queries reaches the target plus a safety step (two standard
+            # errors of a 1,000-query recall near 0.95)
+            for m in MARGINS:
+                qb.margin = m
+                qb.run_eager()
+                ti, tj = (x.cpu().numpy() for x in qb.result())
+                if metrics.recall_at_k(ti[cal], tj[cal], bi[cal], bj[cal], 10) >= 0.95 + 0.01:
+                    margin = m
+                    break
+            qb.margin = margin
         qb.capture()
-        res = {}
-        for mode in ("eager", "graph"):
-            (qb.run_graph if mode == "graph" else qb.run_eager)()
-            qb.result()
-            ts = []
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                (qb.run_graph if mode == "graph" else qb.run_eager)()
-                qb.stream.synchronize()
-                ts.append(time.perf_counter() - t0)
-                qb.result()          # raises if the candidate capacity overflowed
-            t = float(np.median(ts))
-            res[mode] = {"ms_per_batch": 1e3 * t, "queries_per_s": nq / t}
-        out[name] = res
-        if name == "binned":
-            ti, tj = (x.cpu().numpy() for x in qb.result())
-        log(f"workload-5 queries ({name} query signing): eager {res['eager']['ms_per_batch']:.1f} ms, "
-            f"graph {res['graph']['ms_per_batch']:.1f} ms per {nq}-query batch")
-        del qb
-    sample = np.sort(np.random.default_rng(5).choice(nq, min(200, nq), replace=False))
-    bi, bj = metrics.brute_force_topk_mbr(D5, pm.to_device(Qh.subset(sample)), 10)
-    out["recall_at_10"] = metrics.recall_at_k(ti[sample], tj[sample], bi, bj, 10)
-    out["recall_sample"] = int(sample.size)
-    # share of all queries whose top-10 holds the polygon they were jittered from
-    out["source_in_top10"] = float((ti == w5.query_source[:, None]).any(axis=1).mean())
-    log(f"workload-5 recall@10 over {sample.size} queries: {out['recall_at_10']:.3f}; "
-        f"source polygon in the top-10 for {out['source_in_top10']:.3f} of the queries")
-    return out
+        for _ in range(args.warmup):
+            qb.run_graph()
+        qb.result()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            qb.run_graph()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        ti, tj = (x.cpu().numpy() for x in qb.result())      # raises if the candidate capacity overflowed
+        rec = metrics.recall_at_k(ti[evq], tj[evq], bi[evq], bj[evq], 10)
+        cnt = qb.counts.cpu().numpy() if method != "plain" else np.array([n_cand, 0])
+        stages = qb.run_instrumented()
+        methods[method] = {"margin": margin, "recall_at_10": rec, "recall_queries": int(evq.size),
+                           "queries_per_s": nq / dt, "ms_per_batch": 1e3 * dt,
+                           "refined_pairs_per_query": float(cnt[0]) / nq, "finished_by_fallback": int(cnt[1]),
+                           "stage_ms": stages}
+        log(f"{method}: margin {margin}, recall@10 {rec:.4f} on {evq.size} held-out queries, "
+            f"{1e3 * dt:.2f} ms per {nq}-query graph replay ({nq / dt:.3g} q/s), "
+            f"{float(cnt[0]) / nq:.1f} refined pairs/query; stages " +
+            ", ".join(f"{a} {b:.3f}" for a, b in stages.items()))
+        batches[method] = qb
+    if args.trace_window:
+        torch.cuda.synchronize()
+        torch.cuda._sleep(1000)              # marker kernel: the first window opens
+        torch.cuda.synchronize()
+        for name in args.trace_window.split(","):
+            qb = batches[name]
+            for _ in range(args.trace_replays):
+                qb.run_graph()
+            qb.stream.synchronize()
+            torch.cuda._sleep(1000)          # marker kernel: this window closes, the next opens
+            torch.cuda.synchronize()
+            log(f"traced {args.trace_replays} replays of the {name} batch between marker kernels")
+    out = {
+        "workload": "workload 5: 4,000,000 star polygons, Pareto(1.5) 8-8192 vertices, R 0.5-3% of a 2^24 grid; "
+                    f"k=256, cap 2^26; {nq:,} queries per captured-graph batch (2% jitter), "
+                    f"{B} x {R} bands, learned scorer + early-stop refinement",
+        "n_data": D5.n, "n_queries": nq, "k": k, "cap": cap, "bands": B, "rows": R,
+        "rank_F": args.rank_F, "rank_rounds": args.rank_rounds, "scorer_head": args.scorer_head,
+        "binned": {**par5, "lds_edges": cfgb.lds_edges},
+        "candidates_per_query": n_cand / nq, "queries_over_4096_candidates": n_long, "index_ms": 1e3 * t_index,
+        "sign_ms": 1e3 * t_sign, "sign_sig_per_s": D5.n * k / t_sign,
+        "calibration_queries": int(cal.size), "methods": methods, "scorer": learned,
+    }
+    state = {"w5": w5, "D5": D5, "sig5": sig5, "par5": par5, "cfgb": cfgb, "batches": batches,
+             "n_cand": n_cand, "sk": sk, "se": se}
+    return out, state
+
+
+def stage_roofline(state, methods):
+    """Roofline of the dominant stage of the learned step (HIP-event stage
+    times of an instrumented eager run on the batch's stream)."""
+    import torch
+    qb = state["batches"]["scorer"]
+    st = methods["scorer"]["stage_ms"]
+    C = float(qb.cand_off[-1].item())
+    nq, k = qb.nq, qb.k
+    rl = {}
+    # k_rank_jhat_sort: HBM-bound gather: each candidate's data signature
+    # (4k bytes) and id (4 B) read, its score and order written (8 B); per
+    # query its signature and offsets
+    by = C * (4.0 * k + 12.0) + nq * (4.0 * k + 16.0)
+    t = st["jhat_order"] / 1e3
+    rl["k_rank_jhat_sort"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
+                              "frac": by / t / 8e12, "traffic": None, "kernel": "k_rank_jhat_sort",
+                              "launch_ms": 1e3 * t, "bytes_per_launch": by, "candidates": C}
+    return rl
 
 
 def cfg3_pipeline(cfg, dev, bandings=((32, 8), (36, 7), (42, 6), (64, 4)), recall_queries=100):
@@ -226,19 +363,14 @@ def cfg3_pipeline(cfg, dev, bandings=((32, 8), (36, 7), (42, 6), (64, 4)), recal
     return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the signing path has no multi-GPU form; a shard "
-              "of a larger index is measured as one GPU's share", file=sys.stderr)
-        sys.exit(2)
+def secondary(args, hstate):
+    """Workload 2's step (signing, bucket table, 10,000 queries) with the
+    signing and refinement rooflines, and the other measured sections."""
     import torch
 
     from paper_2511_16576_amd import datagen as dg
     from paper_2511_16576_amd import polymh as pm
 
-    torch.cuda.set_device(0)
-    pm.check_device()
     t0 = time.time()
     w = dg.workload(2, n_queries=args.queries)
     log(f"workload 2 generated in {time.time() - t0:.1f}s: {w.data.n} polygons, "
@@ -400,39 +532,24 @@ def main():
         binned = {"workload2": {"walk_ms": None, "binned_ms": 1e3 * t_b2,
                                 "binned_sig_per_s": D.n * k / t_b2, "params": par2}}
         log(f"binned signing, workload 2: {1e3 * t_b2:.3f} ms")
-    if binned is not None and args.binned_cfg5 > 0:
-        w5 = dg.workload(5, n=args.binned_cfg5, n_queries=args.cfg5_queries)
-        D5 = pm.to_device(w5.data)
-        sig5 = torch.empty((D5.n, w5.k), dtype=torch.int32, device=dev)
+    if binned is not None and not args.no_walk5:
+        # Alg. 1's walk of all 4,000,000 workload-5 polygons against the
+        # headline's binned signatures (bit-equality checked here)
+        w5, D5, sig5, par5 = hstate["w5"], hstate["D5"], hstate["sig5"], hstate["par5"]
+        sig5w = torch.empty_like(sig5)
         ws5 = torch.empty(pm.sign_workspace_size(D5.n, cfg), dtype=torch.uint8, device=dev)
-        pm.sign(D5, w5.box, w5.seed, w5.k, w5.cap, config=cfg, out=sig5, ws=ws5)
         e0.record(stream)
-        pm.sign(D5, w5.box, w5.seed, w5.k, w5.cap, config=cfg, out=sig5, ws=ws5)
+        pm.sign(D5, w5.box, w5.seed, w5.k, w5.cap, config=cfg, out=sig5w, ws=ws5)
         e1.record(stream)
         torch.cuda.synchronize()
         t_w5 = e0.elapsed_time(e1) / 1e3
         del ws5
-        sig_b5, t_b5, par5 = time_binned(D5, w5.box, w5.seed, w5.k, w5.cap, 3)
-        if not torch.equal(sig_b5, sig5):
+        if not torch.equal(sig5w, sig5):
             raise RuntimeError("binned and walked signatures disagree (workload 5)")
-        binned["workload5"] = {
-            "polygons": D5.n, "k": w5.k, "cap": w5.cap, "walk_ms": 1e3 * t_w5, "binned_ms": 1e3 * t_b5,
-            "walk_sig_per_s": D5.n * w5.k / t_w5, "binned_sig_per_s": D5.n * w5.k / t_b5,
-            "speedup": t_w5 / t_b5, "params": par5}
-        log(f"binned signing, workload 5 ({D5.n} polygons): walk {1e3 * t_w5:.1f} ms, binned {1e3 * t_b5:.1f} ms")
-        del sig5
-        if args.cfg5_queries > 0:
-            binned["workload5"]["pipeline"] = cfg5_pipeline(w5, D5, sig_b5, par5, cfg, dev)
-            if not args.no_learned:
-                # the learned scorer against the plain pipeline on workload 5
-                # (64 x 4 bands; early stop calibrated to recall@10 >= 0.95)
-                from paper_2511_16576_amd import metrics
-                from paper_2511_16576_amd import scorer as sc
-                binned["workload5"]["learned"] = sc.learned_comparison(
-                    w5, D5, pm.to_device(w5.queries), log, n_pairs=args.train_pairs, epochs=args.epochs,
-                    n_calib=200, n_eval=200, sig=sig_b5,
-                    brute=lambda D_, Q_: metrics.brute_force_topk_mbr(D_, Q_, 10))
-        del sig_b5, D5
+        del sig5w
+        binned["workload5"] = {"polygons": D5.n, "k": w5.k, "cap": w5.cap, "walk_ms": 1e3 * t_w5,
+                               "walk_sig_per_s": D5.n * w5.k / t_w5, "params": par5}
+        log(f"workload 5 ({D5.n} polygons): walk {1e3 * t_w5:.1f} ms")
 
     # polygons with holes and multipolygons: 100,000 shapes of workload 2's
     # sizes (0-2 holes per component, a quarter with two components) joined
@@ -652,39 +769,115 @@ def main():
         log(f"cpu oracle: one thread {cpu['single_thread_sig_per_s']:.3g} sig/s; workload 3 subset "
             f"{cpu['workload3_subset_sig_per_s']:.3g}, workload 5 subset {cpu['workload5_subset_sig_per_s']:.3g} sig/s")
 
-    total_sigs = (D.n + Q.n) * k
+    return {
+        "workload2": {"config": {"workload": "workload 2: 100,000 star polygons, lognormal 8-512 vertices, "
+                                             "R 2-15% of a 2^24 grid; k=128, cap 2^22; 10,000 queries (2% jitter)",
+                                 "n_data": D.n, "n_queries": Q.n, "k": k, "bands": b, "rows": r,
+                                 "sign_config": cfg.as_dict()},
+                      "ms_per_step": ms, "signatures_per_s_step": (D.n + Q.n) * k / (ms / 1e3),
+                      "sign_sig_per_s": D.n * k / (stage_ms["sign"] / 1e3),
+                      "sign_plain_launch_sig_per_s": D.n * k / t_plain,
+                      "queries_per_s": Q.n / (sum(stage_ms[s] for s in names[2:]) / 1e3),
+                      "candidates_per_query": n_cand / Q.n, "recall_at_10": rec,
+                      "recall_queries": rs, "stage_ms": stage_ms},
+        "roofline_kernels": {"k_sign": roof_sign, "k_refine": roof_ref, "k_centre": roof_centre},
+        "cpu_signing": cpu,
+        "autotune": tune,
+        "batched": batched,
+        "learned_workload4": learned,
+        "binned_sign": binned,
+        "rings": rings,
+        "workload3": workload3,
+    }
+
+
+def cpu_baseline_workload5(w5, cand_per_query):
+    """The oracle timed on the host cores on a bounded sample of the
+    headline workload: its Alg. 1 walk signs 2,000 queries (k = 256, cap
+    2^26), and its FP64 fan-clip refinement computes the exact J of 100
+    queries against every data polygon whose MBR meets theirs.  Queries/s =
+    1 / (signing time per query + candidates per query of the headline's
+    lookup x refinement time per pair); band keys, lookup and top-10 are
+    microseconds per query on the host and left out."""
+    import oracle
+    th = oracle.max_threads()
+    S = min(2000, w5.queries.n)
+    t0 = time.perf_counter()
+    oracle.sign(w5.queries.subset(np.arange(S)), w5.box, w5.seed, w5.k, w5.cap, threads=th)
+    t_sign = (time.perf_counter() - t0) / S
+    xy, off = w5.data.xy.reshape(-1, 2), w5.data.offsets
+    lo = np.minimum.reduceat(xy, off[:-1], axis=0)
+    hi = np.maximum.reduceat(xy, off[:-1], axis=0)
+    nq = min(100, w5.queries.n)
+    qoff, qids = [0], []
+    for q in range(nq):
+        p = w5.queries.poly(q)
+        ql, qh = p.min(axis=0), p.max(axis=0)
+        hit = np.flatnonzero((lo[:, 0] <= qh[0]) & (hi[:, 0] >= ql[0]) & (lo[:, 1] <= qh[1]) & (hi[:, 1] >= ql[1]))
+        qids.append(hit.astype(np.int32))
+        qoff.append(qoff[-1] + hit.size)
+    qoff, qids = np.array(qoff, dtype=np.int64), np.concatenate(qids)
+    t0 = time.perf_counter()
+    oracle.jaccard_candidates(w5.data, w5.queries.subset(np.arange(nq)), qoff, qids, threads=th)
+    t_pair = (time.perf_counter() - t0) / max(qids.size, 1)
+    qps = 1.0 / (t_sign + cand_per_query * t_pair)
+    return {"value": qps, "unit": "queries/s", "cores": th, "kind": "oracle",
+            "sample": f"oracle walk signing of {S} workload-5 queries (k=256, cap 2^26: {t_sign * 1e3:.3f} ms a "
+                      f"query on {th} threads) + oracle FP64 exact J of {qids.size} (query, MBR-overlapping polygon) "
+                      f"pairs of {nq} queries ({t_pair * 1e6:.2f} us a pair on {th} threads) x "
+                      f"{cand_per_query:.0f} candidates per query; lookup and top-10 left out",
+            "sign_ms_per_query": 1e3 * t_sign, "refine_us_per_pair": 1e6 * t_pair}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the search path has no multi-GPU form here; a shard "
+              "of a larger index is measured as one GPU's share", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2511_16576_amd import polymh as pm
+
+    torch.cuda.set_device(0)
+    pm.check_device()
+    head, hstate = headline(args)
+    roofs = stage_roofline(hstate, head["methods"])
+    dominant = max(roofs.values(), key=lambda r: r["launch_ms"])
+    for b_ in hstate["batches"].values():
+        del b_
+    hstate["batches"] = None
+    torch.cuda.empty_cache()
+    sec = {} if args.only_headline else secondary(args, hstate)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_workload5(hstate["w5"], head["candidates_per_query"])
+        log(f"cpu oracle: {cpu['value']:.3g} q/s ({cpu['sample']})")
+    m = head["methods"]
     line = {
         "metric": METRIC,
-        "value": total_sigs / (ms / 1e3),
-        "unit": "signatures/s",
+        "value": m["scorer"]["queries_per_s"],
+        "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": m["scorer"]["ms_per_batch"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "workload 2: 100,000 star polygons, lognormal 8-512 vertices, "
-                               "R 2-15% of a 2^24 grid; k=128, cap 2^22; 10,000 queries (2% jitter)",
-                   "n_data": D.n, "n_queries": Q.n, "k": k, "bands": b, "rows": r,
-                   "sign_config": cfg.as_dict()},
-        "sign_sig_per_s": D.n * k / (stage_ms["sign"] / 1e3),
-        "sign_plain_launch_sig_per_s": D.n * k / t_plain,
-        "queries_per_s": Q.n / (sum(stage_ms[s] for s in names[2:]) / 1e3),
-        "candidates_per_query": n_cand / Q.n,
-        "recall_at_10": rec,
-        "stage_ms": stage_ms,
+        "config": {"workload": head["workload"], "n_data": head["n_data"], "n_queries": head["n_queries"],
+                   "k": head["k"], "cap": head["cap"], "bands": head["bands"], "rows": head["rows"]},
+        "recall_at_10": m["scorer"]["recall_at_10"],
+        "queries_per_s": {x: m[x]["queries_per_s"] for x in m},
+        "recall_at_10_by_method": {x: m[x]["recall_at_10"] for x in m},
+        "sign_sig_per_s": head["sign_sig_per_s"],
         "roofline": dominant,
-        "roofline_kernels": {"k_sign": roof_sign, "k_refine": roof_ref, "k_centre": roof_centre},
+        "roofline_kernels": {**roofs, **sec.get("roofline_kernels", {})},
         "cpu_baseline": cpu,
-        "autotune": tune,
-        "batched": batched,
-        "learned": learned,
-        "binned_sign": binned,
-        "rings": rings,
-        "workload3": workload3,
+        "headline": head,
+        "secondary": {x: y for x, y in sec.items() if x != "roofline_kernels"},
     }
     print(json.dumps(line), flush=True)
 

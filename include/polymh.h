@@ -536,10 +536,13 @@ polymh_status polymh_rank_head_fixed(const int64_t *cand_off, const int32_t *can
  * that a whole query batch (signing, lookup, scoring, ordered refinement)
  * can be captured in one graph.  The order comes from the caller
  * (polymh_rank_jhat_order or polymh_rank_order on the same scores); exactly
- * `rounds` rounds of F refinements per active query run (a round with no
- * active query refines nothing), then the finishing pass of
- * polymh_rank_refine completes every query still active, so the result is
- * the same as polymh_rank_refine's with max_rounds = rounds.
+ * `rounds` rounds run: rounds 0 and 1 refine up to F more candidates of each
+ * active query, round r >= 2 up to F * 2^(r-1), so a query still active after
+ * r >= 1 rounds has had F * 2^(r-1) candidates refined (a round with no
+ * active query refines nothing); then the finishing pass of
+ * polymh_rank_refine completes every query still active.  With rounds = 1
+ * the result equals polymh_rank_refine's with max_rounds = 1; the stop test
+ * after each round is the same.
  *   counts [2] int64 device out (nullable): pairs refined, and queries the
  *   finishing pass completed.
  * ws: polymh_rank_workspace_size(nq, n_cand, F) bytes; n_cand is the size

@@ -864,10 +864,16 @@ polymh_status polymh_rank_refine_ordered(const polymh_polys *data, const polymh_
     w.sorted_ok = const_cast<uint8_t *>(sorted_ok);
     if ((st = launch_rank_init(nq, topk, w.cursor, w.active, top_ids, top_j, s))) return st;
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, w.counters);
-    for (int32_t r = 0; r < rounds; r++)
-        if ((st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, F, margin, w, top_ids, top_j,
-                             false, false, s)))
+    // rounds 0 and 1 take up to F candidates of each active query, round
+    // r >= 2 up to F * 2^(r-1): after r rounds a query has visited F * 2^(r-1)
+    // of its list, so a few rounds reach deep while the first stay fine-grained
+    for (int32_t r = 0; r < rounds; r++) {
+        const int sh = r < 2 ? 0 : std::min(r - 1, 20);
+        const int64_t Fr = std::min<int64_t>((int64_t)F << sh, (int64_t)1 << 20);
+        if ((st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, (int32_t)Fr, margin, w, top_ids,
+                             top_j, false, false, s)))
             return st;
+    }
     if ((st = rank_round(data, queries, cand_off, cand_ids, score, nq, topk, F, margin, w, top_ids, top_j, false,
                          true, s)))
         return st;

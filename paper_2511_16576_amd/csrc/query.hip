@@ -2,10 +2,12 @@
 // its buckets).  Each (query, band) key is looked up by binary search in the
 // sorted bucket table; a query's candidate list is the ids of the bucket
 // entries that belong to the same band, in ascending order without repeats.
-// A query whose buckets hold at most kSparseCap entries gathers them in LDS
-// and sorts them there (work in proportion to its entries); a larger one
-// sets its polygons' bits in a bitmap row of the data set's size and reads
-// its set bits in order.  Both give the same list.
+// For large data sets a query's same-band bucket entries are gathered into
+// its own bitmap row (work in proportion to its entries), then sorted and
+// kept without repeats on chip (one wavefront for up to kSparseCap entries,
+// a block for up to kBigCap); a query with more entries sets its polygons'
+// bits in the bitmap row and reads its set bits in order.  Every way gives
+// the same list.
 #include "internal.hpp"
 
 namespace polymh {
@@ -92,61 +94,41 @@ __device__ __forceinline__ void wave_lds_fence()
     __builtin_amdgcn_wave_barrier();
 }
 
-// One wavefront per query (four per block): its bucket entries of the same
-// band gathered in LDS, sorted (bitonic, padded to a power of two with
-// INT32_MAX) and kept without repeats in the query's own bitmap row, which
-// the list leaves unused (rows hold at least kSparseCap words).  dense[q] =
-// 1 when they do not fit (the bitmap takes the query), else 0 and counts[q]
-// = the list's length.
-__global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ skeys,
-                                                const int32_t *__restrict__ sids, int64_t n_entries,
-                                                const uint64_t *__restrict__ qkeys, int64_t nq, int32_t b,
-                                                int32_t *__restrict__ dense, int64_t *__restrict__ counts,
-                                                uint32_t *__restrict__ bitmap, int64_t words)
+// First index in a[0, n) whose value is >= key.  Band keys are SplitMix64
+// outputs, uniform over 64 bits, so a probe placed by linear interpolation
+// between the bracket's end values lands near the answer (about log log n
+// probes); interpolation alternates with bisection, which bounds the probes
+// by about 2 log2 n on any key set (long runs of equal keys included).
+__device__ __forceinline__ int64_t lower_bound_interp(const uint64_t *__restrict__ a, int64_t n, uint64_t key)
 {
-    __shared__ int32_t lists[4][kSparseCap];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
-    if (q >= nq) return;                       // wavefront-uniform; no block barriers below
-    int32_t *L = lists[wave];
-    int cnt = 0;
-    // lane = band: every lane searches its own key, then the lanes walk their
-    // buckets one entry per step
-    for (int32_t t0 = 0; t0 < b && cnt <= kSparseCap; t0 += 64) {
-        const int32_t t = t0 + lane;
-        bool live = t < b && n_entries > 0;
-        const uint64_t key = live ? qkeys[q * b + t] : 0ull;
-        int64_t e = 0;
-        if (live) {
-            int64_t hi = n_entries;
-            while (e < hi) {
-                const int64_t mid = (e + hi) >> 1;
-                if (skeys[mid] < key) e = mid + 1;
-                else hi = mid;
-            }
+    int64_t lo = 0, hi = n;                 // answer in [lo, hi]
+    uint64_t klo = 0, khi = ~0ull;          // a[lo - 1] < key <= a[hi] (or the ends of the key range)
+    bool interp = true;
+    while (lo < hi) {
+        int64_t p = (lo + hi) >> 1;
+        if (interp && khi > klo) {
+            const double f = (double)(key - klo) / (double)(khi - klo);
+            const int64_t g = lo + (int64_t)(f * (double)(hi - lo));
+            p = g < lo ? lo : (g >= hi ? hi - 1 : g);
         }
-        while (__ballot(live) != 0 && cnt <= kSparseCap) {
-            const bool in = live && e < n_entries && skeys[e < n_entries ? e : 0] == key;
-            int32_t id = 0;
-            bool ok = false;
-            if (in) {
-                const int32_t ent = sids[e];          // entry p*b + t'
-                id = ent / b;
-                ok = ent - id * b == t;
-            }
-            const uint64_t om = __ballot(ok);
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
-            if (ok && cnt + rank < kSparseCap) L[cnt + rank] = id;
-            cnt += __popcll(om);
-            live = in;
-            e++;
+        interp = !interp;
+        const uint64_t v = a[p];
+        if (v < key) {
+            lo = p + 1;
+            klo = v;
+        } else {
+            hi = p;
+            khi = v;
         }
     }
-    const bool over = cnt > kSparseCap;
-    if (lane == 0) dense[q] = over ? 1 : 0;
-    if (over) return;
+    return lo;
+}
+
+// Sorts L[0, cnt) in place (bitonic, padded with INT32_MAX to a power of
+// two of at most kSparseCap) and keeps each value once; returns the new
+// length.  One wavefront.
+__device__ int sort_unique(int32_t *L, int cnt, int lane)
+{
     int P = 64;
     while (P < cnt) P <<= 1;
     for (int i = cnt + lane; i < P; i += 64) L[i] = INT32_MAX;
@@ -163,22 +145,320 @@ __global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ ske
             wave_lds_fence();
         }
     }
-    int32_t *row = reinterpret_cast<int32_t *>(bitmap + q * words);
+    // in place: a chunk's values are read before any of its writes, and
+    // writes land at or below the positions already read
     int u = 0;
     for (int i0 = 0; i0 < cnt; i0 += 64) {
         const int i = i0 + lane;
         const bool live = i < cnt;
         const int32_t v = live ? L[i] : 0;
         const bool first = live && (i == 0 || L[i - 1] != v);
+        wave_lds_fence();
         const uint64_t fm = __ballot(first);
         if (first) {
             const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
-            row[u + r] = v;
+            L[u + r] = v;
         }
         u += __popcll(fm);
+        wave_lds_fence();
     }
+    return u;
+}
+
+constexpr int kBigCap = 16384;
+
+// Gather pass, one wavefront per query (four per block): the query's
+// same-band bucket entries, in bucket order with repeats, written to the
+// start of its own bitmap row; raw[q] = their number.  A query with more
+// than min(kBigCap, words) entries gets dense[q] = 1 (the bitmap takes it).
+//
+// Lane t takes band t's key: an interpolation search gives its bucket's
+// first entry, a galloping search (probes 1, 2, 4, ... entries on, then a
+// binary search between the last two) its end.  The bucket lengths' prefix
+// sum then spreads every entry of the 64 buckets over the lanes, 64 entries
+// a step with independent loads, so the walk takes (entries / 64) steps
+// instead of as many as the longest bucket holds.
+__global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ skeys,
+                                                const int32_t *__restrict__ sids, int64_t n_entries,
+                                                const uint64_t *__restrict__ qkeys, int64_t nq, int32_t b,
+                                                int32_t *__restrict__ dense, int64_t *__restrict__ raw,
+                                                uint32_t *__restrict__ bitmap, int64_t words)
+{
+    __shared__ int32_t sbase[4][65];     // exclusive prefix of the bucket lengths, then the total
+    __shared__ int64_t slo[4][64];       // each lane's bucket start
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+    if (q >= nq) return;                       // wavefront-uniform; no block barriers below
+    const int cap = (int)(words < kBigCap ? words : kBigCap);
+    int32_t *row = reinterpret_cast<int32_t *>(bitmap + q * words);
+    int32_t *base = sbase[wave];
+    int64_t *los = slo[wave];
+    int cnt = 0;
+    bool over = false;
+    for (int32_t t0 = 0; t0 < b && !over; t0 += 64) {
+        const int32_t t = t0 + lane;
+        const bool live = t < b && n_entries > 0;
+        const uint64_t key = live ? qkeys[q * b + t] : 0ull;
+        int64_t lo = 0, hi = 0;
+        if (live) {
+            lo = lower_bound_interp(skeys, n_entries, key);
+            hi = lo;
+            if (lo < n_entries && skeys[lo] == key) {
+                // gallop: skeys[last] == key, probe = lo + step is the next test
+                int64_t last = lo, step = 1;
+                while (lo + step < n_entries && skeys[lo + step] == key) {
+                    last = lo + step;
+                    step <<= 1;
+                }
+                int64_t a = last + 1, c = lo + step < n_entries ? lo + step : n_entries;
+                while (a < c) {
+                    const int64_t mid = (a + c) >> 1;
+                    if (skeys[mid] == key) a = mid + 1;
+                    else c = mid;
+                }
+                hi = a;
+            }
+        }
+        // a bucket longer than the list sends the query to the bitmap (which
+        // is exact in every case)
+        const int64_t len64 = hi - lo;
+        if (__ballot(len64 > cap) != 0) {
+            over = true;
+            break;
+        }
+        const int len = (int)len64;
+        // inclusive scan over the wavefront (64 x 16384 fits an int)
+        int inc = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        base[lane] = inc - len;
+        los[lane] = lo;
+        const int total = __shfl(inc, 63, 64);
+        if (lane == 63) base[64] = total;
+        wave_lds_fence();
+        // every entry of the 64 buckets, one per lane per step: band lane
+        // tl of entry j is the last with base[tl] <= j
+        for (int j0 = 0; j0 < total; j0 += 64) {
+            const int j = j0 + lane;
+            bool ok = false;
+            int32_t id = 0;
+            if (j < total) {
+                int l = 0, h = 63;             // base[l] <= j < base[h + 1]
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (base[mid] <= j) l = mid;
+                    else h = mid - 1;
+                }
+                const int32_t ent = sids[los[l] + (j - base[l])];   // entry p*b + t'
+                id = ent / b;
+                ok = ent - id * b == t0 + l;
+            }
+            const uint64_t om = __ballot(ok);
+            const int n_new = __popcll(om);
+            if (cnt + n_new > cap) {
+                over = true;
+                break;
+            }
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+            if (ok) row[cnt + rank] = id;
+            cnt += n_new;
+        }
+        wave_lds_fence();                      // base/los are rewritten by the next band chunk
+    }
+    if (lane == 0) {
+        dense[q] = over ? 1 : 0;
+        raw[q] = over ? 0 : cnt;
+    }
+}
+
+// Multiplicative hash of a polygon id to a slot of a 2^bits table.
+__device__ __forceinline__ int id_slot(int32_t id, int bits)
+{
+    return (int)(((uint32_t)id * 2654435761u) >> (32 - bits));
+}
+
+// Inserts v into an open-addressing set T of 2^bits slots (-1 = empty) by
+// linear probing; returns true if v was not there yet.  Needs an empty slot.
+__device__ __forceinline__ bool set_insert(int32_t *T, int bits, int32_t v)
+{
+    int h = id_slot(v, bits);
+    const int mask = (1 << bits) - 1;
+    for (;;) {
+        const int32_t old = atomicCAS(&T[h], -1, v);
+        if (old == -1) return true;
+        if (old == v) return false;
+        h = (h + 1) & mask;
+    }
+}
+
+constexpr int kSetBits = 12;                 // wavefront pass: 4096 slots
+constexpr int kSetMax = 3072;                // ... filled to at most 3/4
+constexpr int kBigSetBits = 14;              // block pass: 16384 slots
+constexpr int kBigSetMax = 12288;
+static_assert((1 << kSetBits) == kSparseCap && (1 << kBigSetBits) == kBigCap, "set sizes");
+
+// Sort pass for short lists, one wavefront per query (four per block): a
+// query's raw list of at most kSparseCap entries, read from its row 64 at a
+// time, goes into an LDS hash set (each polygon once); the set's members
+// are moved to its front, sorted (bitonic) and written back; counts[q] =
+// the list's length.  A list with more than kSetMax distinct polygons is
+// sorted whole instead (its repeats dropped after the sort).
+__global__ __launch_bounds__(256) void k_sparse_sort(const int32_t *__restrict__ dense, int64_t nq,
+                                                     int64_t *__restrict__ counts, uint32_t *__restrict__ bitmap,
+                                                     int64_t words)
+{
+    __shared__ int32_t lists[4][kSparseCap];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+    if (q >= nq || dense[q]) return;           // wavefront-uniform
+    const int cnt = (int)counts[q];            // the raw count of the gather pass
+    if (cnt > kSparseCap) return;              // the block pass takes it
+    int32_t *T = lists[wave];
+    int32_t *row = reinterpret_cast<int32_t *>(bitmap + q * words);
+    for (int i = lane; i < kSparseCap; i += 64) T[i] = -1;
+    wave_lds_fence();
+    int uniq = 0;
+    bool whole = false;
+    for (int i0 = 0; i0 < cnt; i0 += 64) {
+        if (uniq + 64 > kSetMax) {             // wavefront-uniform: keep the set below 3/4 full
+            whole = true;
+            break;
+        }
+        const int i = i0 + lane;
+        const bool fresh = i < cnt && set_insert(T, kSetBits, row[i]);
+        uniq += __popcll(__ballot(fresh));
+    }
+    wave_lds_fence();
+    int u;
+    if (whole) {
+        for (int i = lane; i < cnt; i += 64) T[i] = row[i];
+        wave_lds_fence();
+        u = sort_unique(T, cnt, lane);
+    } else {
+        // members to the front, in place (a chunk reads before it writes,
+        // and writes land at or below what it read)
+        int m = 0;
+        for (int i0 = 0; i0 < kSparseCap; i0 += 64) {
+            const int32_t v = T[i0 + lane];
+            const bool keep = v != -1;
+            wave_lds_fence();
+            const uint64_t km = __ballot(keep);
+            if (keep) {
+                const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+                T[m + r] = v;
+            }
+            m += __popcll(km);
+            wave_lds_fence();
+        }
+        u = sort_unique(T, m, lane);
+    }
+    for (int i = lane; i < u; i += 64) row[i] = T[i];
     if (lane == 0) counts[q] = u;
+}
+
+// Sort pass for long lists, one block of 1024 threads per query with more
+// than kSparseCap raw entries (at most kBigCap): the same hash set in LDS
+// (16384 slots), its members moved to the front (a block-wide scan places
+// them), a bitonic sort of those, written back.  More than kBigSetMax
+// distinct polygons: the raw list is sorted whole and its repeats dropped.
+__global__ __launch_bounds__(1024) void k_sparse_sort_big(const int32_t *__restrict__ dense,
+                                                          int64_t *__restrict__ counts,
+                                                          uint32_t *__restrict__ bitmap, int64_t words)
+{
+    __shared__ int32_t L[kBigCap];
+    __shared__ int32_t sc[1024];
+    __shared__ int s_uniq;
+    const int64_t q = blockIdx.x;
+    if (dense[q]) return;
+    const int cnt = (int)counts[q];
+    if (cnt <= kSparseCap) return;             // the wavefront pass took it
+    const int tid = threadIdx.x;
+    int32_t *row = reinterpret_cast<int32_t *>(bitmap + q * words);
+    for (int i = tid; i < kBigCap; i += 1024) L[i] = -1;
+    if (tid == 0) s_uniq = 0;
+    __syncthreads();
+    bool whole = false;
+    for (int i0 = 0; i0 < cnt; i0 += 1024) {
+        if (s_uniq + 1024 > kBigSetMax) {     // block-uniform (read after a barrier)
+            whole = true;
+            break;
+        }
+        const int i = i0 + tid;
+        const bool fresh = i < cnt && set_insert(L, kBigSetBits, row[i]);
+        if (fresh) atomicAdd(&s_uniq, 1);
+        __syncthreads();
+    }
+    __syncthreads();
+    int n;                                      // entries to sort at the front of L
+    if (whole) {
+        for (int i = tid; i < cnt; i += 1024) L[i] = row[i];
+        n = cnt;
+    } else {
+        // members to the front: thread tid owns slots [16 tid, 16 tid + 16)
+        int32_t v[16];
+        int mine = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            v[k] = L[16 * tid + k];
+            mine += v[k] != -1;
+        }
+        sc[tid] = mine;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int x = tid >= o ? sc[tid - o] : 0;
+            __syncthreads();
+            sc[tid] += x;
+            __syncthreads();
+        }
+        int at = sc[tid] - mine;
+        n = sc[1023];
+        __syncthreads();                        // every slot read before any is rewritten
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if (v[k] != -1) L[at++] = v[k];
+    }
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = n + tid; i < P; i += 1024) L[i] = INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += 1024) {
+                const int x = i ^ j;
+                if (x > i) {
+                    const int32_t a = L[i], c = L[x];
+                    if ((a > c) == ((i & k) == 0)) { L[i] = c; L[x] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // thread tid owns positions [tid * per, (tid + 1) * per); the first of
+    // each run of equal values is kept
+    const int per = (n + 1023) / 1024;
+    const int i0 = tid * per, i1 = min(n, i0 + per);
+    int mine = 0;
+    for (int i = i0; i < i1; i++) mine += (i == 0 || L[i - 1] != L[i]) ? 1 : 0;
+    sc[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int x = tid >= o ? sc[tid - o] : 0;
+        __syncthreads();
+        sc[tid] += x;
+        __syncthreads();
+    }
+    int u = sc[tid] - mine;
+    for (int i = i0; i < i1; i++)
+        if (i == 0 || L[i - 1] != L[i]) row[u++] = L[i];
+    if (tid == 1023) counts[q] = sc[1023];
 }
 
 // One wavefront per query taken by k_sparse: its list copied from its row to
@@ -204,7 +484,16 @@ __global__ __launch_bounds__(256) void k_count(const uint32_t *__restrict__ bitm
     __shared__ int64_t s[256];
     const uint32_t *row = bitmap + (int64_t)blockIdx.x * words;
     int64_t c = 0;
-    for (int64_t i = threadIdx.x; i < words; i += blockDim.x) c += __popc(row[i]);
+    // eight independent loads in flight a thread
+    int64_t i = threadIdx.x;
+    for (; i + 7 * 256 < words; i += 8 * 256) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = row[i + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; u++) c += __popc(v[u]);
+    }
+    for (; i < words; i += blockDim.x) c += __popc(row[i]);
     s[threadIdx.x] = c;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -238,21 +527,29 @@ __global__ __launch_bounds__(1024) void k_offsets(int64_t *__restrict__ off, int
 }
 
 // One block per dense query: write its set bits in ascending order (nothing
-// when the capacity flag is raised).
+// when the capacity flag is raised).  The row is read in tiles of 4096
+// words, 16 consecutive words a thread: one block-wide scan of the threads'
+// bit counts per tile places every thread's output.
 __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ bitmap, int64_t words,
                                               const int64_t *__restrict__ off,
                                               int32_t *__restrict__ ids, const int32_t *__restrict__ dense,
                                               const int32_t *__restrict__ overflow)
 {
+    constexpr int kPer = 16;
     __shared__ uint32_t s[256];
     const int64_t q = blockIdx.x;
     if (!dense[q] || (overflow && overflow[0])) return;
     const uint32_t *row = bitmap + q * words;
     int64_t base = off[q];
-    for (int64_t w0 = 0; w0 < words; w0 += 256) {
-        const int64_t w = w0 + threadIdx.x;
-        uint32_t bits = w < words ? row[w] : 0u;
-        const uint32_t c = __popc(bits);
+    for (int64_t w0 = 0; w0 < words; w0 += 256 * kPer) {
+        const int64_t w = w0 + (int64_t)threadIdx.x * kPer;
+        uint32_t bits[kPer];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            bits[i] = w + i < words ? row[w + i] : 0u;
+            c += __popc(bits[i]);
+        }
         s[threadIdx.x] = c;
         __syncthreads();
         for (int o = 1; o < 256; o <<= 1) {
@@ -262,10 +559,14 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ bitma
             __syncthreads();
         }
         int64_t pos = base + s[threadIdx.x] - c;
-        while (bits) {
-            const int bit = __builtin_ctz(bits);
-            ids[pos++] = (int32_t)(w * 32 + bit);
-            bits &= bits - 1;
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            uint32_t v = bits[i];
+            while (v) {
+                const int bit = __builtin_ctz(v);
+                ids[pos++] = (int32_t)((w + i) * 32 + bit);
+                v &= v - 1;
+            }
         }
         base += s[255];
         __syncthreads();
@@ -321,6 +622,7 @@ QueryWs carve_query(Carve &cv, int64_t nq, int64_t words)
 constexpr int64_t kSparseMinBytes = (int64_t)1 << 30;
 constexpr int64_t kSparseMinWords = 1 << 12;
 static_assert(kSparseMinWords >= kSparseCap, "a sparse list is kept in its query's bitmap row");
+static_assert(kBigCap <= 16384 && kSparseCap <= kBigCap, "list caps");
 
 __host__ __device__ inline bool use_sparse(int64_t nq, int64_t words)
 {
@@ -337,10 +639,14 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t count, int
 void lookup_counts(const uint64_t *skeys, const int32_t *sids, int64_t n_entries, int64_t words,
                    const uint64_t *qkeys, int64_t nq, int32_t b, const QueryWs &w, int64_t *counts, hipStream_t s)
 {
-    if (use_sparse(nq, words))
+    if (use_sparse(nq, words)) {
         hipLaunchKernelGGL(k_sparse, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, skeys, sids, n_entries,
                            qkeys, nq, b, w.dense, counts, w.bitmap, words);
-    else
+        hipLaunchKernelGGL(k_sparse_sort, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, w.dense, nq, counts,
+                           w.bitmap, words);
+        hipLaunchKernelGGL(k_sparse_sort_big, dim3((unsigned)nq), dim3(1024), 0, s, w.dense, counts, w.bitmap,
+                           words);
+    } else
         hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nq, 256)), dim3(256), 0, s, w.dense, nq, 1);
     if (words > 0) {
         hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)nq), dim3(256), 0, s, w.bitmap, words, w.dense);

@@ -97,7 +97,11 @@ class QueryBatch:
         self.xy[:nv].copy_(torch.from_numpy(np.ascontiguousarray(polys.xy, dtype=np.int32)), non_blocking=False)
         self.off.copy_(torch.from_numpy(np.ascontiguousarray(polys.offsets, dtype=np.int64)))
 
-    def _issue(self):
+    def _issue(self, mark=None):
+        """Enqueue the batch on the current stream; ``mark(name)``, if given,
+        is called after each stage (an instrumented eager run records an
+        event there)."""
+        mark = mark or (lambda name: None)
         s = torch.cuda.current_stream()
         if self.binned is None:
             pm.sign(self.Q, self.box, self.seed, self.k, self.cap, config=self.cfg, out=self.sig,
@@ -110,17 +114,23 @@ class QueryBatch:
                            bin_bits=b["bin_bits"], walk_ratio=b.get("walk_ratio", 300.0), config=self.cfg,
                            out=self.sig, ws=self.ws_sign, stream=s, rebin=not self._binned_ready)
             self._binned_ready = True
+        mark("qsign")
         pm.band(self.sig, self.bands, self.rows, self.seed, out=self.keys, stream=s)
+        mark("qband")
         pm.query_capped(self.sk, self.se, self.D.n, self.keys, self.cand_off, self.cand_ids,
                         self.overflow, self.ws_query, stream=s)
+        mark("lookup")
         if self.method == "plain":
             pm.refine(self.D, self.Q, self.cand_off, self.cand_ids, out=self.cand_j, stream=s,
                       n_cand=self.cand_ids.numel(), ws=self.ws_refine)
+            mark("refine")
             pm.topk(self.cand_off, self.cand_ids, self.cand_j, self.topk, stream=s,
                     out=(self.top_ids, self.top_j))
+            mark("topk")
             return
         pm.rank_jhat_order(self.sig, self.dsig, self.cand_off, self.cand_ids, score=self.score, order=self.order,
                            sorted_ok=self.sorted_ok, stream=s)
+        mark("jhat_order")
         if self.method == "scorer":
             sc = self.scorer
             pm.rank_head_fixed(self.cand_off, self.cand_ids, self.order, self.head,
@@ -128,16 +138,35 @@ class QueryBatch:
             pm.poly_features(self.Q, self.box, out=self.qfeat, stream=s)
             pm.pair_features(self.sig, self.qfeat, self.dsig, self.dfeat, self.hq, self.hid, R_pad=self.R_pad,
                              out=self.X, stream=s)
+            mark("features")
             pm.mlp_forward(self.X, sc.params, sc.wbf16, self.acts, y=self.y, stream=s)
+            mark("mlp")
             pm.scatter_scores(self.hc, self.y[:self.hc.numel()], self.score, stream=s)
             pm.rank_order(self.cand_off, self.score, self.order, self.sorted_ok, stream=s)
+            mark("reorder")
         pm.rank_refine_ordered(self.D, self.Q, self.cand_off, self.cand_ids, self.score, self.order,
                                self.sorted_ok, topk=self.topk, F=self.F, rounds=self.rounds, margin=self.margin,
                                ws=self.ws_rank, out=(self.top_ids, self.top_j), counts=self.counts, stream=s)
+        mark("rank_refine")
 
     def run_eager(self):
         with torch.cuda.stream(self.stream):
             self._issue()
+
+    def run_instrumented(self) -> dict:
+        """One eager run with a HIP event on the batch's stream after every
+        stage: milliseconds per stage."""
+        evs = []
+
+        def mark(name):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(self.stream)
+            evs.append((name, e))
+        with torch.cuda.stream(self.stream):
+            mark("start")
+            self._issue(mark)
+        self.stream.synchronize()
+        return {evs[i][0]: evs[i - 1][1].elapsed_time(evs[i][1]) for i in range(1, len(evs))}
 
     def capture(self):
         pm.check_device()

@@ -11,6 +11,13 @@ Three commands (run from the repository root):
     kernel's average duration from the trace run, against the VALU peak of
     256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 
+``python -m paper_2511_16576_amd.profiling window --trace <kernel_trace.csv> --replays R --out <file.md> --title T --command C``
+    Per-replay kernel table of the dispatches between two marker kernels
+    (torch's ``spin_kernel``; ``bench.py --trace-window m1,m2,..`` puts R
+    replays of each method's captured query batch between consecutive
+    markers; ``--index i`` picks window i), so the benchmark's setup (data
+    generation, training, brute force) stays out.
+
 ``python -m paper_2511_16576_amd.profiling traffic --fetch <counter_collection.csv> --write <counter_collection.csv> --out <file.json> --md <file.md> --command-fetch C1 --command-write C2``
     HBM traffic per dispatch of the hot kernels from one ``--pmc FETCH_SIZE``
     and one ``--pmc WRITE_SIZE`` run.  Both runs include one device-to-device
@@ -72,6 +79,37 @@ def stats_markdown(csv_path: str, title: str, command: str, notes: str = "", top
         nm = nm.split("(")[0].replace("void ", "")
         out.append(f"| {nm} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                    f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def _window_rows(rows, start_key, name_key, index=0, marker="spin_kernel"):
+    """Rows strictly between marker dispatches `index` and `index + 1`
+    (windows are numbered in time order)."""
+    rows = sorted(rows, key=lambda r: int(r[start_key]))
+    idx = [i for i, r in enumerate(rows) if marker in r[name_key]]
+    if len(idx) < index + 2:
+        raise RuntimeError(f"fewer than {index + 2} {marker} dispatches: no window {index}")
+    return rows[idx[index] + 1:idx[index + 1]]
+
+
+def window_markdown(trace_csv: str, replays: int, title: str, command: str, notes: str = "", index: int = 0) -> str:
+    rows = _window_rows(list(csv.DictReader(open(trace_csv))), "Start_Timestamp", "Kernel_Name", index)
+    per = collections.defaultdict(list)
+    for r in rows:
+        per[short_name(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    busy = sum(sum(v) for v in per.values())
+    span = int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"]) if rows else 0
+    out = [f"# {title}", "", "Command (from `/tmp` with `TMPDIR=/tmp`; `<repo>` is the repository root):", "",
+           "```", command, "```", ""]
+    if notes:
+        out += [notes, ""]
+    out += [f"{replays} replays between the marker kernels: {len(rows)} dispatches, GPU busy "
+            f"{busy / 1e6 / replays:.3f} ms and first start to last end {span / 1e6 / replays:.3f} ms per replay.", "",
+            "| kernel | dispatches per replay | avg us | min us | max us | us per replay | % of busy |",
+            "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| {k} | {len(v) / replays:g} | {sum(v) / len(v) / 1e3:.1f} | {min(v) / 1e3:.1f} | "
+                   f"{max(v) / 1e3:.1f} | {sum(v) / replays / 1e3:.1f} | {100.0 * sum(v) / max(busy, 1):.2f} |")
     return "\n".join(out) + "\n"
 
 
@@ -177,6 +215,14 @@ def main():
     v.add_argument("--stats", required=True)
     v.add_argument("--out", required=True)
     v.add_argument("--command", required=True)
+    w = sub.add_parser("window")
+    w.add_argument("--trace", required=True)
+    w.add_argument("--replays", type=int, required=True)
+    w.add_argument("--out", required=True)
+    w.add_argument("--title", required=True)
+    w.add_argument("--command", required=True)
+    w.add_argument("--notes", default="")
+    w.add_argument("--index", type=int, default=0, help="window number (time order)")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -187,6 +233,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "stats":
         open(a.out, "w").write(stats_markdown(a.csv, a.title, a.command, a.notes))
+    elif a.cmd == "window":
+        open(a.out, "w").write(window_markdown(a.trace, a.replays, a.title, a.command, a.notes, a.index))
     elif a.cmd == "valu":
         open(a.out, "w").write(valu_markdown(a.pmc, a.stats, a.command))
     else:

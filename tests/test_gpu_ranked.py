@@ -119,15 +119,19 @@ def test_ordered_refine_inf_margin_is_full(pm, setup):
         assert bool((a_j == tj).all()), rounds
         c = cnt.cpu().numpy()
         assert c[0] == ids.numel(), rounds
-        # queries with more than rounds * F candidates are completed by the finishing pass
-        want_fin = int((np.diff(off.cpu().numpy()) > rounds * 8).sum())
+        # rounds of 8, 8, 16, 32, ...: queries with more than 8 2^(rounds - 1)
+        # candidates (none visited without a round) are completed by the
+        # finishing pass
+        seen = 8 * 2 ** (rounds - 1) if rounds else 0
+        want_fin = int((np.diff(off.cpu().numpy()) > seen).sum())
         assert c[1] == want_fin, (rounds, c[1], want_fin)
 
 
 def test_ordered_refine_exact_scores(pm, setup):
     """With the exact J as scores and margin 0 the early stop returns the
-    exact top-10 (every candidate it skips has a J at most the 10th best),
-    refines fewer pairs, and equals the host-driven rank_refine."""
+    exact top-10 (every candidate it skips has a J at most the 10th best)
+    and refines fewer pairs; one round plus the finishing pass equals the
+    host-driven rank_refine with one round."""
     D, Q, off, ids = setup["D"], setup["Q"], setup["off"], setup["ids"]
     J = pm.refine(D, Q, off, ids)
     ti, tj = pm.topk(off, ids, J, 10)
@@ -135,23 +139,27 @@ def test_ordered_refine_exact_scores(pm, setup):
     order = torch_empty_like_int(ids)
     ok = torch_empty_u8(Q.n)
     pm.rank_order(off, score, order, ok)
-    b_ids, b_j, cnt = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=4, rounds=64, margin=0.0)
+    # rounds of 4, 8, ..., 512 candidates: every list ends inside them
+    b_ids, b_j, cnt = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=4, rounds=8, margin=0.0)
     assert np.allclose(b_j.cpu().numpy(), tj.cpu().numpy(), rtol=0, atol=1e-6)
     c = cnt.cpu().numpy()
     assert c[0] < ids.numel() and c[1] == 0
-    h_ids, h_j, nref, rounds = pm.rank_refine(D, Q, off, ids, score, topk=10, F=4, margin=0.0)
-    assert nref == c[0]
-    assert bool((h_ids == b_ids).all()) and bool((h_j == b_j).all())
-    # too few rounds: the finishing pass completes the active queries
-    f_ids, f_j, cnt1 = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=1, rounds=2,
+    # one round of 3 per query, then the finishing pass
+    f_ids, f_j, cnt1 = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=3, rounds=1,
                                               margin=0.0)
     assert np.allclose(f_j.cpu().numpy(), tj.cpu().numpy(), rtol=0, atol=1e-6)
     assert cnt1.cpu().numpy()[1] > 0
-    # the host-driven call with max_rounds exhausted now finishes too
-    g_ids, g_j, nref1, r1 = pm.rank_refine(D, Q, off, ids, score, topk=10, F=1, margin=0.0, max_rounds=2)
-    assert r1 == 2
-    assert bool((g_ids == f_ids).all())
+    # the host-driven call with its one round exhausted finishes the same way
+    g_ids, g_j, nref1, r1 = pm.rank_refine(D, Q, off, ids, score, topk=10, F=3, margin=0.0, max_rounds=1)
+    assert r1 == 1
+    assert bool((g_ids == f_ids).all()) and bool((g_j == f_j).all())
     assert nref1 == int(cnt1.cpu().numpy()[0])
+    # the schedule F, F, 2F, 4F, ...: three rounds of F = 1 visit 4 candidates
+    # of each query before the finishing pass
+    h_ids, h_j, cnt2 = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=10, F=1, rounds=3,
+                                              margin=float("inf"))
+    nc = np.diff(off.cpu().numpy())
+    assert int(cnt2.cpu().numpy()[1]) == int((nc > 4).sum())
 
 
 def torch_empty_like_int(t):

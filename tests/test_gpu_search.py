@@ -103,6 +103,33 @@ def test_query_large_data_set_sparse_lists(pm, orc):
     assert int(flag.item()) == 1
     assert (coff.cpu().numpy() == 0).all() and (short.cpu().numpy() == -7).all()
 
+def test_query_sparse_lists_band_chunks_and_shared_keys(pm, orc):
+    # the on-chip lists with 80 bands (two chunks of lanes), buckets of about
+    # 1, 50 and 200 entries whose key values recur in other bands (the
+    # band of every entry is checked), and a few queries whose one bucket
+    # holds more than 4,096 entries (the bitmap takes those): sampled lists
+    # equal the oracle's candidates
+    rng = np.random.default_rng(22)
+    nd, b, nq0 = 600_000, 80, 14_996
+    dk = np.empty((nd, b), dtype=np.uint64)
+    dk[:, :60] = rng.integers(0, 600_000, (nd, 60))
+    dk[:, 60:70] = rng.integers(0, 12_000, (nd, 10))
+    dk[:, 70:] = rng.integers(0, 3_000, (nd, 10))
+    big = rng.choice(nd, 5000, replace=False)
+    dk[big, 3] = np.uint64(10 ** 9)
+    qk = dk[rng.integers(0, nd, nq0)].copy()
+    qk = np.concatenate([qk, dk[big[:4]]])
+    nq = qk.shape[0]
+    sample = np.concatenate([np.sort(rng.choice(nq0, 60, replace=False)), np.arange(nq0, nq)])
+    ooff, oids = orc.candidates(dk, qk[sample])
+    sk, si = pm.index_build(_t(dk.view(np.int64)))
+    off, ids = pm.query(sk, si, nd, _t(qk.view(np.int64)))
+    off, ids = off.cpu().numpy(), ids.cpu().numpy()
+    for i, q in enumerate(sample):
+        assert np.array_equal(ids[off[q]:off[q + 1]], oids[ooff[i]:ooff[i + 1]]), q
+    assert np.diff(off)[nq0:].min() > 5000 > np.median(np.diff(off)[:nq0])
+
+
 def _pairs_all(nd, nq):
     off = np.arange(nq + 1, dtype=np.int64) * nd
     ids = np.tile(np.arange(nd, dtype=np.int32), nq)
