@@ -532,6 +532,36 @@ polymh_status polymh_rank_head_fixed(const int64_t *cand_off, const int32_t *can
                                      const int32_t *order, int32_t M, int32_t *head_query,
                                      int64_t *head_cand, int32_t *head_id, void *stream);
 
+/* polymh_rank_reorder_head -- the order after the first min(M, C_q)
+ * candidates of each query's order_in (sorted by the scores they had) were
+ * given new scores in `score` (the rest unchanged): equal to
+ * polymh_rank_order on the new scores, computed by sorting the re-scored
+ * head and merging it with the unchanged rest (work in proportion to the
+ * list, not a full sort).  1 <= M <= 64; order_out must not alias order_in.
+ * Queries with sorted_ok 0 are copied unchanged.  Stream-ordered. */
+polymh_status polymh_rank_reorder_head(const int64_t *cand_off, int64_t nq, const float *score,
+                                      const int32_t *order_in, int32_t M, const uint8_t *sorted_ok,
+                                      int32_t *order_out, void *stream);
+
+/* polymh_mlp_score_pairs -- the scorer's prediction for pairs (li[r], ri[r])
+ * in one launch: each pair's input row (as polymh_pair_features builds it)
+ * assembled on chip, both hidden layers on the matrix cores (BF16 operands,
+ * FP32 accumulation, BF16 activations between the layers, as
+ * polymh_mlp_forward), the output layer and the sigmoid; nothing in between
+ * goes through memory.
+ *   lsig/rsig [.][256] uint32, lfeat/rfeat [.][12] (polymh_poly_features),
+ *   li, ri [R] int32; a row with li[r] < 0 or ri[r] < 0 is skipped.
+ *   out_idx [R] int64 (nullable): the prediction goes to out[out_idx[r]]
+ *   (skipped where out_idx[r] < 0), e.g. into a candidate's score; without
+ *   it to out[r].
+ * Equal to polymh_pair_features + polymh_mlp_forward up to the order of the
+ * FP32 additions of the output layer.  k must be 256; signatures and
+ * weights 16-byte aligned.  Stream-ordered. */
+polymh_status polymh_mlp_score_pairs(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
+                                     const float *rfeat, int32_t k, const int32_t *li, const int32_t *ri,
+                                     const int64_t *out_idx, int64_t R, const float *params,
+                                     const uint16_t *wbf16, float *out, void *stream);
+
 /* polymh_rank_refine_ordered -- polymh_rank_refine without host reads, so
  * that a whole query batch (signing, lookup, scoring, ordered refinement)
  * can be captured in one graph.  The order comes from the caller

@@ -840,6 +840,33 @@ polymh_status polymh_rank_head_fixed(const int64_t *cand_off, const int32_t *can
     return launch_head_fixed(cand_off, cand_ids, nq, order, M, head_query, head_cand, head_id, as_stream(stream));
 }
 
+polymh_status polymh_rank_reorder_head(const int64_t *cand_off, int64_t nq, const float *score,
+                                      const int32_t *order_in, int32_t M, const uint8_t *sorted_ok,
+                                      int32_t *order_out, void *stream)
+{
+    if (nq < 0 || M < 1 || M > 64) return set_error(POLYMH_EINVAL, "rank_reorder_head: bad sizes (1 <= M <= 64)");
+    if (nq == 0) return POLYMH_OK;
+    if (!cand_off || !score || !order_in || !sorted_ok || !order_out)
+        return set_error(POLYMH_EINVAL, "rank_reorder_head: NULL array");
+    if (order_in == order_out) return set_error(POLYMH_EINVAL, "rank_reorder_head: order_out aliases order_in");
+    return launch_reorder_head(cand_off, nq, score, order_in, M, sorted_ok, order_out, as_stream(stream));
+}
+
+polymh_status polymh_mlp_score_pairs(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
+                                     const float *rfeat, int32_t k, const int32_t *li, const int32_t *ri,
+                                     const int64_t *out_idx, int64_t R, const float *params, const uint16_t *wbf16,
+                                     float *out, void *stream)
+{
+    if (k != 256) return set_error(POLYMH_EINVAL, "mlp_score_pairs: the scorer takes k = 256 signatures");
+    if (R < 0) return set_error(POLYMH_EINVAL, "mlp_score_pairs: negative row count");
+    if (R == 0) return POLYMH_OK;
+    if (!lsig || !lfeat || !rsig || !rfeat || !li || !ri || !params || !wbf16 || !out)
+        return set_error(POLYMH_EINVAL, "mlp_score_pairs: NULL array");
+    if ((reinterpret_cast<uintptr_t>(lsig) | reinterpret_cast<uintptr_t>(rsig) | reinterpret_cast<uintptr_t>(wbf16)) & 15)
+        return set_error(POLYMH_EINVAL, "mlp_score_pairs: signatures and weights must be 16-byte aligned");
+    return launch_score_pairs(lsig, lfeat, rsig, rfeat, li, ri, out_idx, R, params, wbf16, out, as_stream(stream));
+}
+
 polymh_status polymh_rank_refine_ordered(const polymh_polys *data, const polymh_polys *queries,
                                          const int64_t *cand_off, const int32_t *cand_ids, const float *score,
                                          const int32_t *order, const uint8_t *sorted_ok, int64_t nq,

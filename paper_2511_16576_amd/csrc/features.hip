@@ -9,6 +9,7 @@
 // MBR intersection-over-union and the collision fraction, zero-padded to 288
 // columns, as BF16.
 #include "internal.hpp"
+#include "scorer_common.hpp"
 
 #include <cmath>
 
@@ -112,26 +113,7 @@ __global__ __launch_bounds__(256) void k_pair_feats(const uint32_t *__restrict__
             cnt += __popcll(__ballot(eq));
         }
         const float *fq = lfeat + q * kFeat, *fp = rfeat + p * kFeat;
-        if (lane < 6) row[kBits + lane] = (__bf16)fq[lane];
-        else if (lane < 12) row[kBits + lane] = (__bf16)fp[lane - 6];
-        else if (lane < 16) {
-            const float aq = fmaxf(fq[6], 0.5f), ap = fmaxf(fp[6], 0.5f);
-            float v;
-            if (lane == 12) v = logf(aq / ap) / 4.f;
-            else if (lane == 13) v = fminf(aq, ap) / fmaxf(aq, ap);
-            else if (lane == 14) {
-                const float ix = fmaxf(0.f, fminf(fq[10], fp[10]) - fmaxf(fq[8], fp[8]));
-                const float iy = fmaxf(0.f, fminf(fq[11], fp[11]) - fmaxf(fq[9], fp[9]));
-                const float in = ix * iy;
-                const float u = (fq[10] - fq[8]) * (fq[11] - fq[9]) + (fp[10] - fp[8]) * (fp[11] - fp[9]) - in;
-                v = u > 0 ? in / u : 0.f;
-            } else {
-                v = (float)cnt / (float)kBits;
-            }
-            row[kBits + lane] = (__bf16)v;
-        } else if (lane < 32) {
-            row[kBits + lane] = (__bf16)0.f;
-        }
+        if (lane < 32) row[kBits + lane] = (__bf16)pair_tail_feature(lane, fq, fp, cnt);
     }
 }
 

@@ -284,6 +284,12 @@ polymh_status launch_round_merge(const int64_t *off, const float *score, const i
                                  const double *rj, int64_t nq, int32_t topk, float margin,
                                  int64_t *cursor, uint8_t *active, int32_t *top_ids, double *top_j,
                                  int32_t *n_active, unsigned long long *counters, int finishing, hipStream_t s);
+polymh_status launch_reorder_head(const int64_t *off, int64_t nq, const float *score, const int32_t *order_in,
+                                 int32_t M, const uint8_t *sorted_ok, int32_t *order_out, hipStream_t s);
+// score.hip
+polymh_status launch_score_pairs(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig, const float *rfeat,
+                                 const int32_t *li, const int32_t *ri, const int64_t *out_idx, int64_t R,
+                                 const float *params, const uint16_t *wbf16, float *out, hipStream_t s);
 polymh_status launch_head_fixed(const int64_t *off, const int32_t *cand_ids, int64_t nq, const int32_t *order,
                                 int32_t M, int32_t *hq, int64_t *hc, int32_t *hid, hipStream_t s);
 polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, int32_t k, const int64_t *off,

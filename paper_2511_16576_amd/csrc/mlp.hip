@@ -11,6 +11,7 @@
 // weight gradient (dZ^T H) share the kernel; when k is the contiguous index
 // a lane reads its 8 values with one 16-byte load.
 #include "internal.hpp"
+#include "scorer_common.hpp"
 
 #include <cmath>
 
@@ -18,22 +19,7 @@ namespace polymh {
 
 namespace {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
-
-constexpr int kIn = 288, kHid = 256;
-constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2 / pi)
-constexpr float kGeluA = 0.044715f;
-
-__device__ __forceinline__ float gelu(float z)
-{
-    return 0.5f * z * (1.0f + tanhf(kGeluC * (z + kGeluA * z * z * z)));
-}
-__device__ __forceinline__ float gelu_grad(float z)
-{
-    const float t = tanhf(kGeluC * (z + kGeluA * z * z * z));
-    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * kGeluC * (1.0f + 3.0f * kGeluA * z * z);
-}
+constexpr int kIn = kScorerIn, kHid = kScorerHid;
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 

@@ -26,6 +26,13 @@ __device__ __forceinline__ bool key_before(float sa, int ia, float sb, int ib)
     return sa > sb || (sa == sb && ia < ib);
 }
 
+// LDS writes of a wavefront visible to its own later reads.
+__device__ __forceinline__ void wave_fence_lds()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One block per query: bitonic sort of (score desc, position asc) in LDS.
 __global__ __launch_bounds__(1024) void k_rank_sort(const int64_t *__restrict__ off,
                                                     const float *__restrict__ score,
@@ -314,6 +321,78 @@ __global__ void k_head_fixed(const int64_t *__restrict__ off, const int32_t *__r
     }
 }
 
+// One wavefront per query: the order after the first h = min(M, C_q)
+// candidates of an order sorted by the old scores were given new scores (the
+// rest keep theirs).  The h re-scored candidates are sorted among themselves
+// (bitonic over the lanes), then merged with the unchanged rest, which is
+// still sorted: a candidate's new place is its place in its own sequence
+// plus the number of the other sequence's candidates ordered before it (a
+// binary search).  The result equals a sort of all candidates by (score
+// desc, position asc).  Queries left unsorted (sorted_ok 0) are copied.
+__global__ __launch_bounds__(256) void k_reorder_head(const int64_t *__restrict__ off, int64_t nq,
+                                                      const float *__restrict__ score,
+                                                      const int32_t *__restrict__ order_in, int32_t M,
+                                                      const uint8_t *__restrict__ sorted_ok,
+                                                      int32_t *__restrict__ order_out)
+{
+    __shared__ float hs[4][64];
+    __shared__ int hp[4][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+    if (q >= nq) return;                       // wavefront-uniform
+    const int64_t a = off[q];
+    const int n = (int)(off[q + 1] - a);
+    if (!sorted_ok[q]) {
+        for (int i = lane; i < n; i += 64) order_out[a + i] = order_in[a + i];
+        return;
+    }
+    const int h = n < M ? n : M;
+    // the re-scored head, one per lane, padded with keys after everything
+    int p = lane < h ? order_in[a + lane] : 0x7fffffff;
+    float sc = lane < h ? score[a + p] : -FLT_MAX;
+    for (int k = 2; k <= 64; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const float so = __shfl_xor(sc, j, 64);
+            const int po = __shfl_xor(p, j, 64);
+            const bool lower = (lane & j) == 0;          // keeps the earlier key of the pair if ascending
+            const bool asc = (lane & k) == 0;
+            const bool other_first = key_before(so, po, sc, p);
+            if (other_first == (lower == asc)) {
+                sc = so;
+                p = po;
+            }
+        }
+    }
+    hs[wave][lane] = sc;
+    hp[wave][lane] = p;
+    wave_fence_lds();
+    const int tail = n - h;
+    // head element `lane`: place = lane + number of tail candidates before it
+    if (lane < h) {
+        int lo = 0, hi = tail;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int pm = order_in[a + h + mid];
+            if (key_before(score[a + pm], pm, sc, p)) lo = mid + 1;
+            else hi = mid;
+        }
+        order_out[a + lane + lo] = p;
+    }
+    // tail element j: place = j + number of head elements before it
+    for (int j = lane; j < tail; j += 64) {
+        const int pt = order_in[a + h + j];
+        const float st = score[a + pt];
+        int lo = 0, hi = h;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (key_before(hs[wave][mid], hp[wave][mid], st, pt)) lo = mid + 1;
+            else hi = mid;
+        }
+        order_out[a + j + lo] = pt;
+    }
+}
+
 __global__ void k_scatter_scores(const int64_t *__restrict__ idx, const float *__restrict__ val,
                                  int64_t n, float *__restrict__ score)
 {
@@ -384,6 +463,15 @@ polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, 
     hipLaunchKernelGGL(k_rank_jhat_sort, dim3((unsigned)nq), dim3(1024), 0, s, qsig, dsig, k, vec, off, cand_ids,
                        score, order, sorted_ok);
     return check_launch("rank_jhat");
+}
+
+polymh_status launch_reorder_head(const int64_t *off, int64_t nq, const float *score, const int32_t *order_in,
+                                 int32_t M, const uint8_t *sorted_ok, int32_t *order_out, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    hipLaunchKernelGGL(k_reorder_head, dim3(g_of(nq, 4)), dim3(256), 0, s, off, nq, score, order_in, M, sorted_ok,
+                       order_out);
+    return check_launch("reorder_head");
 }
 
 polymh_status launch_scatter_scores(const int64_t *idx, const float *val, int64_t n, float *score,

@@ -1,0 +1,174 @@
+// Learned scorer inference in one persistent launch: for a list of pairs,
+// each pair's input row (256 collision bits and 32 feature columns, as
+// k_pair_feats builds it) is assembled on chip, both hidden layers run on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation, the output layer and the
+// sigmoid follow, and the prediction is written where the caller asks (for
+// the ranked search: into the candidate's score).  Nothing between the
+// signatures and the prediction goes through memory.
+//
+// Layout: a workgroup of 8 wavefronts owns the network; wavefront w owns
+// hidden units 32w .. 32w + 31 of both layers and keeps its slices of W1
+// (18 k-steps) and W2 (16 k-steps) in registers for the whole launch.  Pairs
+// are taken 32 at a time (one MFMA row tile): the 32 input rows are built in
+// LDS by the 8 wavefronts (four rows each: a 16-byte load of each signature
+// per lane, all eight in flight together), layer 1 reads its A operand from that tile, writes
+// GELU(z1) as BF16 into a second LDS tile, layer 2 reads it; each wavefront
+// reduces its 32 columns of GELU(z2) * w3 per row, and the 8 partial sums of
+// a row are added in wavefront order.
+//
+// MFMA operand layout (one wavefront, 32 x 32 output tile, k-step 16): lane
+// l supplies row l % 32 of A and column l % 32 of B at k = 8 (l / 32) .. +7;
+// result element r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column
+// l % 32.
+#include "internal.hpp"
+#include "scorer_common.hpp"
+
+#include <algorithm>
+
+namespace polymh {
+
+namespace {
+
+constexpr int kTileRows = 32;
+constexpr int kWaves = kScorerHid / 32;          // 8: one 32-unit slice each
+constexpr int kXStride = kScorerIn + 8;          // LDS row strides in BF16 (16-byte multiples)
+constexpr int kHStride = kScorerHid + 8;
+constexpr int kK1 = kScorerIn / 16, kK2 = kScorerHid / 16;
+
+// Offsets in the FP32 parameter block: W1 [256][288], b1, W2 [256][256], b2, w3, b3.
+constexpr int64_t kPB1 = (int64_t)kScorerHid * kScorerIn;
+constexpr int64_t kPW2 = kPB1 + kScorerHid;
+constexpr int64_t kPB2 = kPW2 + (int64_t)kScorerHid * kScorerHid;
+constexpr int64_t kPW3 = kPB2 + kScorerHid;
+constexpr int64_t kPB3 = kPW3 + kScorerHid;
+
+__global__ __launch_bounds__(512) void k_score_pairs(const uint32_t *__restrict__ lsig,
+                                                     const float *__restrict__ lfeat,
+                                                     const uint32_t *__restrict__ rsig,
+                                                     const float *__restrict__ rfeat,
+                                                     const int32_t *__restrict__ li,
+                                                     const int32_t *__restrict__ ri,
+                                                     const int64_t *__restrict__ out_idx, int64_t R,
+                                                     const float *__restrict__ params,
+                                                     const __bf16 *__restrict__ wbf16,
+                                                     float *__restrict__ out)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 X[kTileRows * kXStride];
+    __shared__ __attribute__((aligned(16))) __bf16 H[kTileRows * kHStride];
+    __shared__ float part[kWaves][kTileRows];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int col = 32 * wave + (lane & 31);    // this lane's hidden unit (B column, output column)
+    const int kl = 8 * (lane >> 5);
+    const __bf16 *W1 = wbf16;
+    const __bf16 *W2 = wbf16 + (int64_t)kScorerHid * kScorerIn;
+    bf16x8 w1[kK1], w2[kK2];
+#pragma unroll
+    for (int ks = 0; ks < kK1; ks++)
+        w1[ks] = *reinterpret_cast<const bf16x8 *>(W1 + (int64_t)col * kScorerIn + 16 * ks + kl);
+#pragma unroll
+    for (int ks = 0; ks < kK2; ks++)
+        w2[ks] = *reinterpret_cast<const bf16x8 *>(W2 + (int64_t)col * kScorerHid + 16 * ks + kl);
+    const float b1c = params[kPB1 + col], b2c = params[kPB2 + col], w3c = params[kPW3 + col];
+    const float b3 = params[kPB3];
+    const int64_t tiles = (R + kTileRows - 1) / kTileRows;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t r0 = t * kTileRows;
+        // -- the tile's input rows: wavefront w builds rows w, w + 8, w + 16,
+        // w + 24; the four rows' indices, then their eight signature slices,
+        // are loaded together so their latencies overlap
+        constexpr int kPer = kTileRows / kWaves;
+        int32_t qi[kPer], pi[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int64_t r = r0 + wave + kWaves * u;
+            qi[u] = r < R ? li[r] : -1;
+            pi[u] = r < R ? ri[r] : -1;
+        }
+        uint4 sa[kPer], sb[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const bool ok = qi[u] >= 0 && pi[u] >= 0;
+            sa[u] = ok ? *reinterpret_cast<const uint4 *>(lsig + (int64_t)qi[u] * kScorerBits + 4 * lane)
+                       : make_uint4(0, 0, 0, 0);
+            sb[u] = ok ? *reinterpret_cast<const uint4 *>(rsig + (int64_t)pi[u] * kScorerBits + 4 * lane)
+                       : make_uint4(1, 1, 1, 1);
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            __bf16 *xr = X + (wave + kWaves * u) * kXStride;
+            const bool ok = qi[u] >= 0 && pi[u] >= 0;   // wavefront-uniform
+            const bool e0 = sa[u].x == sb[u].x, e1 = sa[u].y == sb[u].y, e2 = sa[u].z == sb[u].z,
+                       e3 = sa[u].w == sb[u].w;         // all false on an empty row
+            xr[4 * lane + 0] = (__bf16)(e0 ? 1.f : 0.f);
+            xr[4 * lane + 1] = (__bf16)(e1 ? 1.f : 0.f);
+            xr[4 * lane + 2] = (__bf16)(e2 ? 1.f : 0.f);
+            xr[4 * lane + 3] = (__bf16)(e3 ? 1.f : 0.f);
+            const int cnt = __popcll(__ballot(e0)) + __popcll(__ballot(e1)) + __popcll(__ballot(e2)) +
+                            __popcll(__ballot(e3));
+            if (lane < 32)
+                xr[kScorerBits + lane] = ok ? (__bf16)pair_tail_feature(lane, lfeat + (int64_t)qi[u] * kPolyFeat,
+                                                                        rfeat + (int64_t)pi[u] * kPolyFeat, cnt)
+                                            : (__bf16)0.f;
+        }
+        __syncthreads();
+        // -- layer 1: z1 = X W1^T + b1, H = BF16(GELU(z1))
+        f32x16 acc = {};
+        const __bf16 *xa = X + (lane & 31) * kXStride + kl;
+#pragma unroll
+        for (int ks = 0; ks < kK1; ks++)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8 *>(xa + 16 * ks), w1[ks],
+                                                          acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            const int row = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            H[row * kHStride + col] = (__bf16)gelu(acc[e] + b1c);
+        }
+        __syncthreads();
+        // -- layer 2: z2 = H W2^T + b2; partial output sums of this slice
+        acc = f32x16{};
+        const __bf16 *ha = H + (lane & 31) * kHStride + kl;
+#pragma unroll
+        for (int ks = 0; ks < kK2; ks++)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8 *>(ha + 16 * ks), w2[ks],
+                                                          acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            // h2 is BF16 between the layers, as in the training forward pass
+            float v = (float)(__bf16)gelu(acc[e] + b2c) * w3c;
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);   // the 32 columns of a half
+            if ((lane & 31) == 0) part[wave][8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kTileRows) {
+            const int64_t r = r0 + threadIdx.x;
+            if (r < R && li[r] >= 0 && ri[r] >= 0) {
+                float s = 0.f;
+#pragma unroll
+                for (int w = 0; w < kWaves; w++) s += part[w][threadIdx.x];
+                const float y = 1.0f / (1.0f + expf(-(s + b3)));
+                const int64_t o = out_idx ? out_idx[r] : r;
+                if (o >= 0) out[o] = y;
+            }
+        }
+        // the next tile's rows are written only after every wavefront has
+        // passed the barrier above, i.e. finished reading X, H and part
+    }
+}
+
+}  // namespace
+
+polymh_status launch_score_pairs(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig, const float *rfeat,
+                                 const int32_t *li, const int32_t *ri, const int64_t *out_idx, int64_t R,
+                                 const float *params, const uint16_t *wbf16, float *out, hipStream_t s)
+{
+    if (R == 0) return POLYMH_OK;
+    const int64_t tiles = (R + kTileRows - 1) / kTileRows;
+    const int64_t grid = std::min<int64_t>(tiles, (int64_t)cu_count());
+    hipLaunchKernelGGL(k_score_pairs, dim3((unsigned)grid), dim3(64 * kWaves), 0, s, lsig, lfeat, rsig, rfeat, li, ri,
+                       out_idx, R, params, reinterpret_cast<const __bf16 *>(wbf16), out);
+    return check_launch("score_pairs");
+}
+
+}  // namespace polymh

@@ -78,14 +78,13 @@ class QueryBatch:
                 raise ValueError("the scorer method needs a trained scorer and the data features")
             self.scorer, self.dfeat = scorer, dfeat
             self.qfeat = torch.empty((n_queries, 12), dtype=torch.float32, device=dev)
+            if not 1 <= head <= 64:
+                raise ValueError("the scorer re-scores 1 to 64 candidates per query")
             R = n_queries * head
-            self.R_pad = ((R + 31) // 32) * 32
             self.hq = torch.empty(max(R, 1), dtype=torch.int32, device=dev)
             self.hc = torch.empty(max(R, 1), dtype=torch.int64, device=dev)
             self.hid = torch.empty(max(R, 1), dtype=torch.int32, device=dev)
-            self.X = torch.empty((self.R_pad, 288), dtype=torch.int16, device=dev)
-            self.acts, _ = pm.mlp_buffers(self.R_pad, dev)
-            self.y = torch.empty(self.R_pad, dtype=torch.float32, device=dev)
+            self.order2 = torch.empty(cand_cap, dtype=torch.int32, device=dev)
         self.stream = torch.cuda.Stream()
         self.graph = None
 
@@ -131,20 +130,24 @@ class QueryBatch:
         pm.rank_jhat_order(self.sig, self.dsig, self.cand_off, self.cand_ids, score=self.score, order=self.order,
                            sorted_ok=self.sorted_ok, stream=s)
         mark("jhat_order")
+        order = self.order
         if self.method == "scorer":
+            # the network re-predicts the first `head` candidates of each
+            # query (one fused launch writes into their scores), and the
+            # order is rebuilt by merging them back into the rest
             sc = self.scorer
             pm.rank_head_fixed(self.cand_off, self.cand_ids, self.order, self.head,
                                out=(self.hq, self.hc, self.hid), stream=s)
             pm.poly_features(self.Q, self.box, out=self.qfeat, stream=s)
-            pm.pair_features(self.sig, self.qfeat, self.dsig, self.dfeat, self.hq, self.hid, R_pad=self.R_pad,
-                             out=self.X, stream=s)
-            mark("features")
-            pm.mlp_forward(self.X, sc.params, sc.wbf16, self.acts, y=self.y, stream=s)
-            mark("mlp")
-            pm.scatter_scores(self.hc, self.y[:self.hc.numel()], self.score, stream=s)
-            pm.rank_order(self.cand_off, self.score, self.order, self.sorted_ok, stream=s)
+            mark("head")
+            pm.mlp_score_pairs(self.sig, self.qfeat, self.dsig, self.dfeat, self.hq, self.hid, sc.params,
+                               sc.wbf16, out=self.score, out_idx=self.hc, stream=s)
+            mark("scorer")
+            pm.rank_reorder_head(self.cand_off, self.score, self.order, self.head, self.sorted_ok, self.order2,
+                                 stream=s)
+            order = self.order2
             mark("reorder")
-        pm.rank_refine_ordered(self.D, self.Q, self.cand_off, self.cand_ids, self.score, self.order,
+        pm.rank_refine_ordered(self.D, self.Q, self.cand_off, self.cand_ids, self.score, order,
                                self.sorted_ok, topk=self.topk, F=self.F, rounds=self.rounds, margin=self.margin,
                                ws=self.ws_rank, out=(self.top_ids, self.top_j), counts=self.counts, stream=s)
         mark("rank_refine")

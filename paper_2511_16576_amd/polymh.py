@@ -105,6 +105,8 @@ _SIGNATURES = {
     "polymh_rank_jhat_order": (I32, [P, P, I32, P, P, I64, P, P, P, P]),
     "polymh_rank_order": (I32, [P, I64, P, P, P, P]),
     "polymh_rank_head_fixed": (I32, [P, P, I64, P, I32, P, P, P, P]),
+    "polymh_rank_reorder_head": (I32, [P, I64, P, P, I32, P, P, P]),
+    "polymh_mlp_score_pairs": (I32, [P, P, P, P, I32, P, P, P, I64, P, P, P, P]),
     "polymh_rank_refine_ordered": (I32, [P, P, P, P, P, P, P, I64, I64, I32, I32, I32, ctypes.c_float,
                                          P, SZ, P, P, P, P]),
 }
@@ -676,6 +678,24 @@ def rank_head_fixed(cand_off, cand_ids, order, M, out=None, stream=None):
     _check(lib().polymh_rank_head_fixed(_ptr(cand_off), _ptr(cand_ids), nq, _ptr(order), M, _ptr(hq), _ptr(hc),
                                         _ptr(hid), _stream(stream)))
     return hq, hc, hid
+
+
+def rank_reorder_head(cand_off, score, order_in, M, sorted_ok, order_out, stream=None):
+    """Order after the first M candidates of each query got new scores."""
+    _check(lib().polymh_rank_reorder_head(_ptr(cand_off), cand_off.numel() - 1, _ptr(score), _ptr(order_in), M,
+                                          _ptr(sorted_ok), _ptr(order_out), _stream(stream)))
+
+
+def mlp_score_pairs(lsig, lfeat, rsig, rfeat, li, ri, params, wbf16, out=None, out_idx=None, stream=None):
+    """Fused scorer inference for pairs (li[r], ri[r]): float32 predictions
+    in out[r], or in out[out_idx[r]] when out_idx is given."""
+    R = li.numel()
+    if out is None:
+        out = torch.empty(max(R, 1), dtype=torch.float32, device=li.device)
+    _check(lib().polymh_mlp_score_pairs(_ptr(lsig), _ptr(lfeat), _ptr(rsig), _ptr(rfeat), lsig.shape[1], _ptr(li),
+                                        _ptr(ri), _ptr(out_idx), R, _ptr(params), _ptr(wbf16), _ptr(out),
+                                        _stream(stream)))
+    return out
 
 
 def rank_refine_ordered(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, score, order, sorted_ok,

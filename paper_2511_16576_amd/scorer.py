@@ -72,6 +72,35 @@ def mine_pairs(sorted_keys: torch.Tensor, sorted_ent: torch.Tensor, n: int, band
     return left[perm], right[perm]
 
 
+def mine_head_pairs(D: pm.DevicePolys, sig, sorted_keys, sorted_ent, bands: int, rows: int, band_seed: int,
+                    n_pairs: int, head: int, seed: int = 0, chunk: int = 10_000):
+    """(left, right) polygon ids of the pairs the ranked search scores: a
+    seeded sample of data polygons, each looked up as a query in the bucket
+    table (sorted_keys, sorted_ent) of `bands` x `rows` bands, gives the
+    first `head` of its candidates by collision fraction, itself excluded.
+    Polygons are drawn until n_pairs pairs are found."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(D.n)
+    dev = sig.device
+    left, right, got, at = [], [], 0, 0
+    while got < n_pairs and at < D.n:
+        ids = torch.from_numpy(np.sort(perm[at:at + chunk])).to(dev)
+        at += chunk
+        qs = sig[ids.long()].contiguous()
+        off, cand = pm.query(sorted_keys, sorted_ent, D.n, pm.band(qs, bands, rows, band_seed))
+        _, order, _ = pm.rank_jhat_order(qs, sig, off, cand)
+        hq, _, hid = pm.rank_head_fixed(off, cand, order, head)
+        lq = ids[hq.long()].to(torch.int32)
+        keep = (hid >= 0) & (hid != lq)
+        lq, hid = lq[keep].cpu().numpy(), hid[keep].cpu().numpy()
+        left.append(lq)
+        right.append(hid)
+        got += lq.size
+    left, right = np.concatenate(left)[:n_pairs], np.concatenate(right)[:n_pairs]
+    p = rng.permutation(left.size)
+    return left[p].astype(np.int32), right[p].astype(np.int32)
+
+
 def exact_pair_j(D: pm.DevicePolys, left: np.ndarray, right: np.ndarray) -> torch.Tensor:
     """Exact J of (left[i], right[i]) by the refinement kernel: pairs grouped
     by left polygon as the 'query', so no polygon is copied."""
@@ -163,16 +192,15 @@ def candidate_scores(kind: str, scorer, qsig, qfeat, dsig, dfeat, cand_off, cand
     """Per-candidate predicted J.  'jhat': the collision fraction of the
     signatures (Thm. 1's estimate).  'mlp': a cascade -- the collision
     fraction orders every candidate, then the scorer re-predicts the first
-    `head` candidates of each query (the only ones early stop can reach)."""
-    rows = pm.csr_rows(cand_off, cand_ids.numel())
-    jh = pm.jhat(qsig, dsig, rows, cand_ids)
+    `head` candidates of each query (one fused launch writes into their
+    scores)."""
+    C = cand_ids.numel()
+    score, order, _ = pm.rank_jhat_order(qsig, dsig, cand_off, cand_ids)
     if kind == "jhat":
-        return jh
-    hoff, hq, hc, hid = pm.rank_head(cand_off, cand_ids, jh, head)
-    H = int(hoff[-1].item())
-    pred = predict_pairs(scorer, qsig, qfeat, dsig, dfeat, hq[:H], hid[:H])
-    pm.scatter_scores(hc[:H], pred, jh)
-    return jh
+        return score[:C]
+    hq, hc, hid = pm.rank_head_fixed(cand_off, cand_ids, order, head)
+    pm.mlp_score_pairs(qsig, qfeat, dsig, dfeat, hq, hid, scorer.params, scorer.wbf16, out=score, out_idx=hc)
+    return score[:C]
 
 
 # ------------------------------------------------------------ measurement --

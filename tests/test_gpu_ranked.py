@@ -107,6 +107,34 @@ def test_head_fixed(pm, setup):
                 assert hc[s] == -1 and hid[s] == -1
 
 
+@pytest.mark.parametrize("M", [1, 7, 32, 64])
+def test_reorder_head_equals_full_sort(pm, setup, M):
+    """New scores for the first M of each order (a query with fewer
+    candidates re-scores all of them; one list left unsorted is copied):
+    the merge equals a sort of all candidates by the new scores."""
+    import torch
+    off, ids = setup["off"], setup["ids"]
+    score, order, ok = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
+    hq, hc, hid = pm.rank_head_fixed(off, ids, order, M)
+    rng = np.random.default_rng(M)
+    new = torch.from_numpy(rng.random(hc.numel()).astype(np.float32)).cuda()
+    new[::5] = 0.25                             # ties, broken by position
+    pm.scatter_scores(hc, new, score)
+    ok[3] = 0                                   # an unsorted list: copied as it is
+    out = torch.empty_like(order)
+    pm.rank_reorder_head(off, score, order, M, ok, out)
+    want = order.clone()
+    pm.rank_order(off, score, want, torch.empty_like(ok))
+    o = off.cpu().numpy()
+    got, exp, src = out.cpu().numpy(), want.cpu().numpy(), order.cpu().numpy()
+    for q in range(o.size - 1):
+        a, b = o[q], o[q + 1]
+        if q == 3:
+            assert np.array_equal(got[a:b], src[a:b])
+        else:
+            assert np.array_equal(got[a:b], exp[a:b]), q
+
+
 def test_ordered_refine_inf_margin_is_full(pm, setup):
     D, Q, off, ids = setup["D"], setup["Q"], setup["off"], setup["ids"]
     J = pm.refine(D, Q, off, ids)

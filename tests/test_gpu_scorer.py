@@ -137,6 +137,50 @@ def test_features_match_oracle(pm):
     assert (X[100:] == 0).all()
 
 
+def test_fused_scoring_matches_rows_and_oracle(pm):
+    """polymh_mlp_score_pairs (rows built on chip, both layers fused) against
+    the unfused feature rows + forward pass, and against the FP64 oracle
+    forward pass on the oracle's feature rows; the scatter to out_idx and the
+    skipped rows."""
+    import torch
+    w = dg.workload(2, n=400, n_queries=40)
+    D, Q = pm.to_device(w.data), pm.to_device(w.queries)
+    fd, fq = pm.poly_features(D, w.box), pm.poly_features(Q, w.box)
+    sd = pm.sign(D, w.box, 0, 256, w.cap)
+    sq = pm.sign(Q, w.box, 0, 256, w.cap)
+    rng = np.random.default_rng(5)
+    R = 100                                    # 3 full tiles and a ragged one
+    li = rng.integers(0, 40, R).astype(np.int32)
+    ri = rng.integers(0, 400, R).astype(np.int32)
+    ri[::7] = w.query_source[li[::7]]          # some similar pairs
+    p, _, _, params, wbf16, _, _ = _setup(pm, 32, seed=4)
+    L, Rr = _cuda(li), _cuda(ri)
+    fused = pm.mlp_score_pairs(sq, fq, sd, fd, L, Rr, params, wbf16).cpu().numpy()[:R]
+    X = pm.pair_features(sq, fq, sd, fd, L, Rr, R_pad=128)
+    acts, _ = pm.mlp_buffers(128)
+    y = pm.mlp_forward(X, params, wbf16, acts).cpu().numpy()[:R]
+    assert np.abs(fused - y).max() < 1e-6
+    sdn, sqn, fdn, fqn = sd.cpu().numpy(), sq.cpu().numpy(), fd.cpu().numpy(), fq.cpu().numpy()
+    rows = np.stack([om.bf16_round(om.pair_features(sqn[li[r]], fqn[li[r]].astype(np.float64), sdn[ri[r]],
+                                                    fdn[ri[r]].astype(np.float64)).astype(np.float32))
+                     for r in range(R)]).astype(np.float64)
+    want = om.forward(rows, p)["y"]
+    assert np.abs(fused - want).max() < 2 ** -7 * math.sqrt(om.N_IN) * 0.05
+    # scatter into a score array; negative indices and rows skipped
+    idx = np.arange(R, dtype=np.int64) * 3
+    idx[5] = -1
+    li2 = li.copy()
+    li2[9] = -1
+    score = torch.full((3 * R,), -2.0, dtype=torch.float32, device="cuda")
+    pm.mlp_score_pairs(sq, fq, sd, fd, _cuda(li2), Rr, params, wbf16, out=score, out_idx=_cuda(idx))
+    sc = score.cpu().numpy()
+    keep = np.ones(R, dtype=bool)
+    keep[[5, 9]] = False
+    assert np.array_equal(sc[idx[keep]], fused[keep])
+    untouched = np.setdiff1d(np.arange(3 * R), idx[keep])
+    assert (sc[untouched] == -2.0).all()
+
+
 def test_rank_refine_fallback_and_perfect_scores(pm, orc):
     import torch
     w = dg.workload(1, n=400, n_queries=12)
