@@ -6,6 +6,10 @@ per-polygon shape features and the per-pair input rows.  The scorer is not
 in the paper (it is an added systems form); what pins these functions:
 
 - ``backward``: central finite differences of ``loss`` (tests);
+- ``forward_mixed`` / ``backward_mixed`` (the network as trained: hidden
+  activations BF16 between the layers, the backward products' operands BF16):
+  with the rounding switched off they equal ``forward`` / ``backward``
+  exactly, and with it on they stay within BF16's rounding of them (tests);
 - ``gelu``: the erf form of GELU, which the tanh form approximates to ~1e-3;
 - ``adam_step``: the closed form of the first step, lr * g / (|g| + eps);
 - ``poly_features`` / ``pair_features``: shoelace areas, perimeters and
@@ -90,6 +94,63 @@ def backward(X, params, label):
     g[OFF_W1:OFF_B1] = (dz1.T @ X).reshape(-1)
     g[OFF_B1:OFF_W2] = dz1.sum(axis=0)
     return g
+
+
+def _bf16(x, on=True):
+    """FP64 values rounded as an FP32 computation hands them to BF16 storage
+    (to FP32, then to the nearest BF16, ties to even), back in FP64."""
+    if not on:
+        return x
+    return bf16_round(np.asarray(x, dtype=np.float32)).astype(np.float64)
+
+
+def forward_mixed(X, params, bf16=True):
+    """The network as its matrix-core kernels define it: BF16 weights and
+    inputs (the caller passes BF16-valued ones), the hidden activations
+    GELU(z1) and GELU(z2) stored as BF16 between the layers, everything else
+    exact (FP64 here)."""
+    W1, b1, W2, b2, w3, b3 = unpack(params)
+    z1 = X @ W1.T + b1
+    h1 = _bf16(gelu(z1), bf16)
+    z2 = h1 @ W2.T + b2
+    h2 = _bf16(gelu(z2), bf16)
+    z3 = h2 @ w3 + b3
+    y = 1.0 / (1.0 + np.exp(-z3))
+    return {"z1": z1, "h1": h1, "z2": z2, "h2": h2, "y": y}
+
+
+def backward_mixed(X, params, label, bf16=True, terms=False):
+    """Gradient of the batch MSE through ``forward_mixed`` by the chain rule,
+    each stored activation used where the forward pass used it (a rounding
+    passes the gradient through unchanged), and the operands of the two
+    backward matrix products dz2 and dz1 rounded to BF16 as the matrix cores
+    take them; the bias gradients add the unrounded dz.  With ``terms`` also
+    returns, per gradient entry, the sum of the absolute values of the terms
+    added into it (a scale for rounding bounds)."""
+    W1, b1, W2, b2, w3, b3 = unpack(params)
+    a = forward_mixed(X, params, bf16)
+    B = X.shape[0]
+    y = a["y"]
+    dz3 = 2.0 * (y - label) / B * y * (1.0 - y)
+    g = np.zeros(N_PARAMS)
+    S = np.zeros(N_PARAMS)
+    g[OFF_W3:OFF_B3] = a["h2"].T @ dz3
+    S[OFF_W3:OFF_B3] = np.abs(a["h2"]).T @ np.abs(dz3)
+    g[OFF_B3] = dz3.sum()
+    S[OFF_B3] = np.abs(dz3).sum()
+    dz2 = np.outer(dz3, w3) * gelu_grad(a["z2"])
+    dz2b = _bf16(dz2, bf16)
+    g[OFF_W2:OFF_B2] = (dz2b.T @ a["h1"]).reshape(-1)
+    S[OFF_W2:OFF_B2] = (np.abs(dz2b).T @ np.abs(a["h1"])).reshape(-1)
+    g[OFF_B2:OFF_W3] = dz2.sum(axis=0)
+    S[OFF_B2:OFF_W3] = np.abs(dz2).sum(axis=0)
+    dz1 = (dz2b @ W2) * gelu_grad(a["z1"])
+    dz1b = _bf16(dz1, bf16)
+    g[OFF_W1:OFF_B1] = (dz1b.T @ X).reshape(-1)
+    S[OFF_W1:OFF_B1] = (np.abs(dz1b).T @ np.abs(X)).reshape(-1)
+    g[OFF_B1:OFF_W2] = dz1.sum(axis=0)
+    S[OFF_B1:OFF_W2] = np.abs(dz1).sum(axis=0)
+    return (g, S) if terms else g
 
 
 def adam_step(p, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

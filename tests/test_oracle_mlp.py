@@ -28,6 +28,43 @@ def test_backward_matches_central_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
 
 
+def test_mixed_precision_network_reduces_to_fp64_and_stays_within_bf16():
+    """forward_mixed / backward_mixed with the rounding off are the FP64
+    network and its chain-rule gradient (pinned by finite differences
+    above); with it on, every gradient entry moves by at most a few BF16
+    roundings of its terms, while a real change of the network (a
+    perturbed weight) moves the gradient far more."""
+    rng = np.random.default_rng(3)
+    p = _params(rng, 0.06)
+    X = om.bf16_round(rng.normal(0, 1, (24, om.N_IN)).astype(np.float32)).astype(np.float64)
+    lab = rng.random(24)
+    assert np.array_equal(om.forward_mixed(X, p, bf16=False)["y"], om.forward(X, p)["y"])
+    assert np.array_equal(om.backward_mixed(X, p, lab, bf16=False), om.backward(X, p, lab))
+    g, S = om.backward_mixed(X, p, lab, terms=True)
+    g0 = om.backward(X, p, lab)
+    assert np.all(np.abs(g - g0) <= 2 ** -6 * S + 1e-15)
+    ya, yb = om.forward_mixed(X, p)["y"], om.forward(X, p)["y"]
+    assert np.abs(ya - yb).max() < 2 ** -7 * 0.25 * np.abs(p[om.OFF_W3:om.OFF_B3]).sum()
+    p2 = p.copy()
+    p2[om.OFF_W2 + 5 * om.N_HID + 7] += 0.3        # one weight of W2 changed
+    g2 = om.backward_mixed(X, p2, lab)
+    assert (np.abs(g2 - g) > 2 ** -6 * S + 1e-15).sum() > 100
+
+
+def test_adam_constant_gradient_every_step():
+    """With the same gradient g at every step the bias-corrected moments are
+    exactly g and g^2, so each step moves p by lr g / (|g| + eps): a
+    correction frozen at its first-step value would not."""
+    rng = np.random.default_rng(4)
+    p = rng.normal(size=40)
+    g = rng.normal(size=40)
+    m, v = np.zeros(40), np.zeros(40)
+    for step in range(1, 8):
+        p1, m, v = om.adam_step(p, g, m, v, step, lr=1e-3, eps=1e-8)
+        assert np.allclose(p - p1, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-15), step
+        p = p1
+
+
 def test_gelu_tanh_form_tracks_erf_form():
     z = np.linspace(-6, 6, 2001)
     exact = 0.5 * z * (1 + erf(z / math.sqrt(2)))

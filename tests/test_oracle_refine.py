@@ -116,6 +116,29 @@ def test_fp64_matches_exact_rationals_on_star_pairs(orc):
         assert orc.intersection_area_exact(Q, P[::-1]) == ex
 
 
+def test_fp64_matches_exact_rationals_at_grid_scale(orc):
+    """The FP64 fan clip serves as the reference of the refinement at the
+    workloads' grid sizes, so pin it there too: star pairs centred anywhere
+    on 2^20 and 2^24 grids, radii up to 3% of the grid (workload 5) and 20%
+    (workloads 1 and 3), against exact rational areas."""
+    rng = np.random.default_rng(9)
+    for bits in (20, 24):
+        W = 1 << bits
+        for _ in range(12):
+            R = float(rng.uniform(0.005, 0.2)) * W
+            c = rng.integers(int(R) + 1, W - int(R) - 1, 2)
+            P = dg.star_polygons(rng, [int(rng.integers(4, 10))], [c], [R]).xy
+            Q = dg.star_polygons(rng, [int(rng.integers(4, 10))], [c + rng.integers(-int(R // 2), int(R // 2) + 1, 2)],
+                                 [float(rng.uniform(0.5, 1.5)) * R]).xy
+            assert np.abs(P).max() < W and np.abs(Q).max() < W + 2 * R
+            ex = float(orc.intersection_area_exact(P, Q))
+            got = orc.intersection_area(P, Q)
+            assert abs(got - ex) <= 1e-9 * ex + 1e-6, (bits, got, ex)
+            J = orc.jaccard(P, Q)
+            ej = float(orc.jaccard_exact(P, Q))
+            assert abs(J - ej) <= 1e-9 * ej + 1e-12
+
+
 def test_additivity_over_a_split(orc):
     # area(P n (A u B)) = area(P n A) + area(P n B) for a rectangle split in two
     rng = np.random.default_rng(4)
