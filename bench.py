@@ -32,12 +32,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "polygon-hash signatures/s; queries/s at recall@10≥0.95, learned vs plain"
 PEAK_VALU = 256 * 4 * 16 * 2.4e9      # lane-cycles/s: 256 CUs x 4 SIMD16 x 2.4 GHz
-# VALU issue cycles per lane, counted in the built gfx950 code of the signing
-# kernel: one draw (SplitMix64 with two 64x64-bit products, lattice map, MBR
-# check: 26 full-rate + 6 quarter-rate instructions) and one edge test of the
-# point-in-polygon loop.
-C_DRAW = 26 + 6 * 4
-C_EDGE = 14
+# VALU instructions per lane, counted in the built gfx950 code of the signing
+# kernel's walk: one draw of the tile loop (SplitMix64 with its two 64 x 64-bit
+# products as 4 v_mul_lo_u32 + 2 v_mad_u64_u32, the lattice map, the MBR
+# check and the loop latch: 28 + 3 instructions) and one edge test of the
+# point-in-polygon loop (3 subtractions, 4 conversions, an FP64 product and
+# FMA, 3 compares, 3 index updates: 15).  Each is taken as one lane-cycle:
+# the walk of workload 5 (4.8e12 draws in 3.85 s) would exceed the VALU peak
+# at more than about 32 lane-cycles a draw, so the multiplies issue at full
+# rate on gfx950.
+C_DRAW = 31
+C_EDGE = 15
 # Algorithmic VALU operations of one exact edge-pair test in the refinement:
 # the four orientations from one shared difference r = c - a and X = cross(e, f)
 # (2 subtractions, 3 products with their fused subtractions = 6, 2 additions)
@@ -487,13 +492,6 @@ def secondary(args, hstate):
                 times.setdefault(nmk, []).append(ev[i].elapsed_time(ev[i + 1]))
         return off, ids, ti, tj
 
-    if args.copy_calibration:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
-        src.fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copied 256 MiB device-to-device (counter reference)")
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -600,8 +598,24 @@ def secondary(args, hstate):
         if not torch.equal(sig5w, sig5):
             raise RuntimeError("binned and walked signatures disagree (workload 5)")
         del sig5w
+        # the walk's algorithmic VALU work (every realised draw, the expected
+        # edge tests) over its time: at most the peak if C_DRAW and C_EDGE
+        # are no larger than the instructions the kernel issues
+        s5 = sig5.cpu().numpy().view(np.uint32).astype(np.float64)
+        draws5 = float(s5.sum()) + float((s5 == 0).sum()) * w5.cap
+        mbr5, area5, _ = pm.prepare(D5)
+        mbr5 = mbr5.cpu().numpy().astype(np.float64)
+        a_mbr5 = (mbr5[:, 2] - mbr5[:, 0] + 1) * (mbr5[:, 3] - mbr5[:, 1] + 1)
+        a_p5 = np.maximum(np.abs(area5.cpu().numpy().astype(np.float64)) / 2, 0.5)
+        nv5 = (D5.offsets[1:] - D5.offsets[:-1]).cpu().numpy().astype(np.float64)
+        edges5 = float((w5.k * nv5 * np.minimum(a_mbr5 / a_p5, s5.mean(axis=1))).sum())
+        frac5 = (draws5 * C_DRAW + edges5 * C_EDGE) / t_w5 / PEAK_VALU
         binned["workload5"] = {"polygons": D5.n, "k": w5.k, "cap": w5.cap, "walk_ms": 1e3 * t_w5,
-                               "walk_sig_per_s": D5.n * w5.k / t_w5, "params": par5}
+                               "walk_sig_per_s": D5.n * w5.k / t_w5, "params": par5,
+                               "walk_draws": draws5, "walk_edge_tests": edges5, "walk_valu_frac": frac5,
+                               "check_walk_frac_le_1": bool(frac5 <= 1.0)}
+        if frac5 > 1.0:
+            log(f"CHECK FAILED: the workload-5 walk's algorithmic VALU fraction {frac5:.3f} exceeds 1")
         log(f"workload 5 ({D5.n} polygons): walk {1e3 * t_w5:.1f} ms")
 
     # polygons with holes and multipolygons: 100,000 shapes of workload 2's
@@ -693,7 +707,9 @@ def secondary(args, hstate):
     dw_q, ed_q = sign_work(qsig, Q)
     t_sign_avg = 0.5 * (stage_ms["sign"] + stage_ms["qsign"]) / 1e3
     work_sign = 0.5 * ((dw_d + dw_q) * C_DRAW + (ed_d + ed_q) * C_EDGE)
+    hw_sign = hardware_valu_fraction("k_sign")
     roof_sign = {"bound": "alu", "achieved": work_sign / t_sign_avg / 1e12, "peak": PEAK_VALU / 1e12,
+                 "hardware_valu_frac": hw_sign,
                  "unit": "T lane-cycles/s", "frac": work_sign / t_sign_avg / PEAK_VALU, "traffic": None,
                  "kernel": "k_sign", "launch_ms": 1e3 * t_sign_avg,
                  "draws_per_launch": 0.5 * (dw_d + dw_q), "edge_tests_per_launch": 0.5 * (ed_d + ed_q)}
@@ -731,7 +747,11 @@ def secondary(args, hstate):
             if rec and rec.get("source_hash") == profiling.source_hash(kname):
                 roof["traffic"] = rec["bytes"]
                 roof["traffic_unit"] = "bytes per launch"
-    dominant = roof_ref if t_ref > t_sign_avg * 2 else roof_sign
+    if hw_sign is not None:
+        roof_sign["check_alg_le_hw"] = bool(roof_sign["frac"] <= hw_sign)
+        if roof_sign["frac"] > hw_sign:
+            log(f"CHECK FAILED: k_sign's algorithmic fraction {roof_sign['frac']:.3f} exceeds the issued "
+                f"VALU fraction {hw_sign:.3f}")
     roof_centre = {"bound": "hbm", "achieved": centre_bytes / t_centre / 1e9, "peak": 8000.0, "unit": "GB/s",
                    "frac": centre_bytes / t_centre / 8e12, "traffic": None, "kernel": "k_centre",
                    "launch_ms": 1e3 * t_centre, "bytes_per_launch": centre_bytes}
@@ -844,6 +864,22 @@ def secondary(args, hstate):
     }
 
 
+def hardware_valu_fraction(kernel, path=os.path.join(ROOT, "profiles", "valu_workload2.md")):
+    """The issued VALU fraction of a kernel from the committed counter
+    summary of the workload-2 step (SQ_INSTS_VALU x 64 over its duration), or
+    None."""
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if cells and cells[0] == kernel:
+            try:
+                return float(cells[-1])
+            except ValueError:
+                return None
+    return None
+
+
 def cpu_baseline_workload5(w5, cand_per_query):
     """The oracle timed on the host cores on a bounded sample of the
     headline workload: its Alg. 1 walk signs 2,000 queries (k = 256, cap
@@ -894,6 +930,14 @@ def main():
 
     torch.cuda.set_device(0)
     pm.check_device()
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copied 256 MiB device-to-device (counter reference)")
     head, hstate = headline(args)
     roofs = stage_roofline(hstate, head["methods"])
     dominant = max(roofs.values(), key=lambda r: r["launch_ms"])

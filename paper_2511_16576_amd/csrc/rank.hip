@@ -108,32 +108,62 @@ __global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restr
         const int h = 4 * lane + 256 * t;
         qv[t] = (vec && h < k) ? *reinterpret_cast<const uint4 *>(sq + h) : make_uint4(0, 0, 0, 0);
     }
-    for (int i = wave; i < n; i += nwave) {
-        const uint32_t *sp = dsig + (int64_t)cand_ids[a + i] * k;
-        int cnt = 0;
-        if (vec) {
+    if (vec && k <= 256) {
+        // the common case (k <= 256): a wavefront takes four candidates at a
+        // time, their four 16-byte slices a lane loaded together
+        constexpr int kU = 4;
+        const bool in = 4 * lane < k;
+        for (int i0 = wave * kU; i0 < n; i0 += nwave * kU) {
+            uint4 pv[kU];
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                const int h = 4 * lane + 256 * t;
-                if (256 * t < k) {   // wave-uniform
-                    const bool in = h < k;
-                    const uint4 pv = in ? *reinterpret_cast<const uint4 *>(sp + h) : make_uint4(0, 0, 0, 0);
-                    cnt += __popcll(__ballot(in && pv.x == qv[t].x)) + __popcll(__ballot(in && pv.y == qv[t].y)) +
-                           __popcll(__ballot(in && pv.z == qv[t].z)) + __popcll(__ballot(in && pv.w == qv[t].w));
+            for (int u = 0; u < kU; u++) {
+                const int i = i0 + u < n ? i0 + u : n - 1;
+                const uint32_t *sp = dsig + (int64_t)cand_ids[a + i] * k;
+                pv[u] = in ? *reinterpret_cast<const uint4 *>(sp + 4 * lane) : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                const int i = i0 + u;
+                const int cnt = __popcll(__ballot(in && pv[u].x == qv[0].x)) + __popcll(__ballot(in && pv[u].y == qv[0].y)) +
+                                __popcll(__ballot(in && pv[u].z == qv[0].z)) + __popcll(__ballot(in && pv[u].w == qv[0].w));
+                const float sc = (float)cnt * inv_k;
+                if (lane == 0 && i < n) {
+                    score[a + i] = sc;
+                    if (i < kSortCap) {
+                        ss[i] = sc;
+                        si[i] = i;
+                    }
                 }
             }
-        } else {
-            for (int h0 = 0; h0 < k; h0 += 64) {
-                const int h = h0 + lane;
-                cnt += __popcll(__ballot(h < k && sq[h] == sp[h]));
-            }
         }
-        const float s = (float)cnt * inv_k;
-        if (lane == 0) {
-            score[a + i] = s;
-            if (i < kSortCap) {
-                ss[i] = s;
-                si[i] = i;
+    } else {
+        for (int i = wave; i < n; i += nwave) {
+            const uint32_t *sp = dsig + (int64_t)cand_ids[a + i] * k;
+            int cnt = 0;
+            if (vec) {
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    const int h = 4 * lane + 256 * t;
+                    if (256 * t < k) {   // wave-uniform
+                        const bool in = h < k;
+                        const uint4 pv = in ? *reinterpret_cast<const uint4 *>(sp + h) : make_uint4(0, 0, 0, 0);
+                        cnt += __popcll(__ballot(in && pv.x == qv[t].x)) + __popcll(__ballot(in && pv.y == qv[t].y)) +
+                               __popcll(__ballot(in && pv.z == qv[t].z)) + __popcll(__ballot(in && pv.w == qv[t].w));
+                    }
+                }
+            } else {
+                for (int h0 = 0; h0 < k; h0 += 64) {
+                    const int h = h0 + lane;
+                    cnt += __popcll(__ballot(h < k && sq[h] == sp[h]));
+                }
+            }
+            const float sc = (float)cnt * inv_k;
+            if (lane == 0) {
+                score[a + i] = sc;
+                if (i < kSortCap) {
+                    ss[i] = sc;
+                    si[i] = i;
+                }
             }
         }
     }
