@@ -311,23 +311,94 @@ def headline(args):
     return out, state
 
 
+def _committed_traffic(path, kernel):
+    """HBM bytes per dispatch of `kernel` from a committed counter summary,
+    only while the kernel's sources are the ones the counters were taken on."""
+    from paper_2511_16576_amd import profiling
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if rec and rec.get("source_hash") == profiling.source_hash(kernel):
+        return rec["bytes"]
+    return None
+
+
+def bin_lookup_bytes(Q, qsig, box, horizon, bits, walk_ratio, lds_edges):
+    """Algorithmic bytes of one binned-lookup launch over the query batch:
+    for every (polygon, hash) the lookup settles, each chunk of C samples it
+    visits (up to the chunk of the first hit, the signature value) costs the
+    two 16-bit cell offsets of every grid row under the MBR, the 8-byte
+    records of the samples of those rows' cells (C x cells / 4^bits of them
+    on average) and the 2-byte indices of those inside the MBR; per unit the
+    4-byte signature; per polygon its vertices (8 n) and staging (24 B).
+    Polygons left to the walk (the same rule as the kernel's classification)
+    are not counted."""
+    from paper_2511_16576_amd import polymh as pm
+    mbr, area2, flags = (x.cpu().numpy() for x in pm.prepare(Q))
+    mbr = mbr.astype(np.float64)
+    wx, wy = float(box[2]) - box[0] + 1, float(box[3]) - box[1] + 1
+    lx, ly = int(round(np.log2(wx))), int(round(np.log2(wy)))
+    C = float(1 << int(np.clip(2 * bits, 8, 12)))
+    nchunks = np.ceil(horizon / C)
+    area = np.abs(area2.astype(np.float64)) / 2
+    n = (Q.offsets[1:] - Q.offsets[:-1]).cpu().numpy().astype(np.float64)
+    a_mbr = (mbr[:, 2] - mbr[:, 0] + 1) * (mbr[:, 3] - mbr[:, 1] + 1)
+    deg = (flags & 3) != 0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        walk_cost = 5.0 * wx * wy / area + n * a_mbr / area
+        bin_cost = n * np.maximum(1.0, C * a_mbr / (wx * wy))
+        walk = (~deg) & (area > 0) & ((wx * wy < walk_ratio * area) | (walk_cost < bin_cost) | (n > lds_edges))
+    binned = ~walk & ~deg
+    sx, sy = max(lx - bits, 0), max(ly - bits, 0)
+    cols = (np.floor((mbr[:, 2] - box[0]) / 2 ** sx) - np.floor((mbr[:, 0] - box[0]) / 2 ** sx)) + 1
+    rows = (np.floor((mbr[:, 3] - box[1]) / 2 ** sy) - np.floor((mbr[:, 1] - box[1]) / 2 ** sy)) + 1
+    per_chunk = rows * 4 + C * rows * cols / 4.0 ** bits * 8 + C * a_mbr / (wx * wy) * 2
+    sg = qsig.cpu().numpy().view(np.uint32).astype(np.float64)
+    chunks = np.where(sg > 0, np.minimum(np.ceil(sg / C), nchunks), nchunks).sum(axis=1)
+    k = sg.shape[1]
+    return float(((chunks * per_chunk + 4.0 * k + 8.0 * n + 24.0) * binned).sum())
+
+
 def stage_roofline(state, methods):
-    """Roofline of the dominant stage of the learned step (HIP-event stage
-    times of an instrumented eager run on the batch's stream)."""
-    import torch
+    """Rooflines of the learned step's heaviest stages (HIP-event stage times
+    of an instrumented eager run on the batch's stream)."""
     qb = state["batches"]["scorer"]
     st = methods["scorer"]["stage_ms"]
     C = float(qb.cand_off[-1].item())
     nq, k = qb.nq, qb.k
+    tpath = os.path.join(ROOT, "profiles", "hbm_traffic_workload5.json")
     rl = {}
-    # k_rank_jhat_sort: HBM-bound gather: each candidate's data signature
+    # k_rank_jhat_sort: an HBM-bound gather: each candidate's data signature
     # (4k bytes) and id (4 B) read, its score and order written (8 B); per
     # query its signature and offsets
     by = C * (4.0 * k + 12.0) + nq * (4.0 * k + 16.0)
     t = st["jhat_order"] / 1e3
     rl["k_rank_jhat_sort"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
-                              "frac": by / t / 8e12, "traffic": None, "kernel": "k_rank_jhat_sort",
+                              "frac": by / t / 8e12, "traffic": _committed_traffic(tpath, "k_rank_jhat_sort"),
+                              "traffic_unit": "bytes per launch", "kernel": "k_rank_jhat_sort",
                               "launch_ms": 1e3 * t, "bytes_per_launch": by, "candidates": C}
+    # k_bin_lookup (query signing from the shared binned samples): bytes of
+    # the samples each (query, hash) visits; the stage also holds the walk of
+    # the polygons left to it (k_sign), so its time bounds the kernel's
+    by = bin_lookup_bytes(qb.Q, qb.sig, qb.box, qb.binned["horizon"], qb.binned["bin_bits"],
+                          qb.binned.get("walk_ratio", 300.0), qb.cfg.lds_edges)
+    t = st["qsign"] / 1e3
+    rl["k_bin_lookup"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
+                          "frac": by / t / 8e12, "traffic": _committed_traffic(tpath, "k_bin_lookup"),
+                          "traffic_unit": "bytes per launch", "kernel": "k_bin_lookup",
+                          "stage_ms": 1e3 * t, "bytes_per_launch": by,
+                          "note": "time of the whole query-signing stage (binned lookup and the walk of the "
+                                  "polygons left to it)"}
+    # k_score_pairs (fused scorer inference): matrix-core FLOPs of the two
+    # hidden layers, 2 (288 x 256 + 256 x 256) per pair row, head rows of
+    # every query (empty slots included: whole tiles run)
+    rows = float(nq * qb.head)
+    fl = rows * 2.0 * (288 * 256 + 256 * 256)
+    t = st["scorer"] / 1e3
+    rl["k_score_pairs"] = {"bound": "mfma", "achieved": fl / t / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                           "frac": fl / t / 2.5e15, "traffic": _committed_traffic(tpath, "k_score_pairs"),
+                           "traffic_unit": "bytes per launch", "kernel": "k_score_pairs", "launch_ms": 1e3 * t,
+                           "flops_per_launch": fl, "dtype": "bf16"}
     return rl
 
 
@@ -940,7 +1011,9 @@ def main():
         log("copied 256 MiB device-to-device (counter reference)")
     head, hstate = headline(args)
     roofs = stage_roofline(hstate, head["methods"])
-    dominant = max(roofs.values(), key=lambda r: r["launch_ms"])
+    # the heaviest single kernel of the step (the signing stage's time holds
+    # two kernels and is not a launch time)
+    dominant = max((r for r in roofs.values() if "launch_ms" in r), key=lambda r: r["launch_ms"])
     for b_ in hstate["batches"].values():
         del b_
     hstate["batches"] = None

@@ -18,14 +18,19 @@ Three commands (run from the repository root):
     markers; ``--index i`` picks window i), so the benchmark's setup (data
     generation, training, brute force) stays out.
 
-``python -m paper_2511_16576_amd.profiling traffic --fetch <counter_collection.csv> --write <counter_collection.csv> --out <file.json> --md <file.md> --command-fetch C1 --command-write C2``
+``python -m paper_2511_16576_amd.profiling traffic --fetch <counter_collection.csv> --write <counter_collection.csv> --out <file.json> --md <file.md> --command-fetch C1 --command-write C2 [--window i --kernels k1,k2 --title T]``
     HBM traffic per dispatch of the hot kernels from one ``--pmc FETCH_SIZE``
     and one ``--pmc WRITE_SIZE`` run.  Both runs include one device-to-device
     copy of a known size (``bench.py --copy-calibration``: 256 MiB); each
     counter is scaled by (copy bytes) / (what that counter reads for the copy
     dispatch), so the result is in bytes moved.  The JSON also records a hash
     of each kernel's sources: a reader (``bench.py``) uses the figure only
-    while the kernel is unchanged.
+    while the kernel is unchanged.  ``--window i`` keeps the dispatches
+    between marker kernels i and i + 1 (as ``window``).
+
+``python -m paper_2511_16576_amd.profiling mfma --pmc <counter_collection.csv> --trace <kernel_trace.csv> --replays R --window i --out <file.md> --command C``
+    BF16 matrix-core work and busy cycles per dispatch of the kernels in
+    window i, against the dense BF16 peak.
 """
 from __future__ import annotations
 
@@ -45,6 +50,12 @@ KERNEL_SOURCES = {
     "k_refine": ["refine.hip", "internal.hpp"],
     "k_sign": ["sign.hip", "sign_common.hpp", "internal.hpp"],
     "k_bin_lookup": ["binned.hip", "sign_common.hpp", "internal.hpp"],
+    "k_rank_jhat_sort": ["rank.hip", "internal.hpp"],
+    "k_sparse": ["query.hip", "internal.hpp"],
+    "k_sparse_sort": ["query.hip", "internal.hpp"],
+    "k_sparse_sort_big": ["query.hip", "internal.hpp"],
+    "k_refine_wide": ["refine.hip", "internal.hpp"],
+    "k_score_pairs": ["score.hip", "scorer_common.hpp", "internal.hpp"],
 }
 
 
@@ -113,24 +124,39 @@ def window_markdown(trace_csv: str, replays: int, title: str, command: str, note
     return "\n".join(out) + "\n"
 
 
-def _per_kernel(csv_path: str, counter: str):
-    """kernel short name -> list of per-dispatch counter values (KiB)."""
+def _counter_rows(csv_path: str, window: int | None):
+    rows = list(csv.DictReader(open(csv_path)))
+    if window is None:
+        return rows
+    # dispatches between marker kernels `window` and `window + 1`, in
+    # dispatch order (every dispatch has one row per counter)
+    order = sorted({int(r["Dispatch_Id"]) for r in rows})
+    name = {int(r["Dispatch_Id"]): r["Kernel_Name"] for r in rows}
+    marks = [d for d in order if "spin_kernel" in name[d]]
+    if len(marks) < window + 2:
+        raise RuntimeError(f"fewer than {window + 2} marker dispatches: no window {window}")
+    lo, hi = marks[window], marks[window + 1]
+    return [r for r in rows if lo < int(r["Dispatch_Id"]) < hi]
+
+
+def _per_kernel(csv_path: str, counter: str, window: int | None = None, copies_from: str | None = None):
+    """kernel short name -> list of per-dispatch counter values (KiB), and
+    the values of the copy dispatches (over the whole run)."""
     per = collections.defaultdict(list)
     copies = []
     for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]:
+            copies.append(float(r["Counter_Value"]))
+    for r in _counter_rows(csv_path, window):
         if r["Counter_Name"] != counter:
             continue
-        v = float(r["Counter_Value"])
-        nm = r["Kernel_Name"]
-        if "copyBuffer" in nm:
-            copies.append(v)
-        per[short_name(nm)].append(v)
+        per[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
     return per, copies
 
 
-def traffic(fetch_csv: str, write_csv: str, kernels=("k_refine", "k_sign")) -> dict:
-    fetch, fcopies = _per_kernel(fetch_csv, "FETCH_SIZE")
-    write, wcopies = _per_kernel(write_csv, "WRITE_SIZE")
+def traffic(fetch_csv: str, write_csv: str, kernels=("k_refine", "k_sign"), window: int | None = None) -> dict:
+    fetch, fcopies = _per_kernel(fetch_csv, "FETCH_SIZE", window)
+    write, wcopies = _per_kernel(write_csv, "WRITE_SIZE", window)
     if not fcopies or not wcopies:
         raise RuntimeError("no copy dispatch in the counter runs (run bench.py with --copy-calibration)")
     # the calibration copy is the largest copy dispatch of each run
@@ -153,8 +179,9 @@ def traffic(fetch_csv: str, write_csv: str, kernels=("k_refine", "k_sign")) -> d
     return out
 
 
-def traffic_markdown(t: dict, cmd_fetch: str, cmd_write: str) -> str:
-    out = ["# HBM traffic per dispatch of the hot kernels (workload 2 bench step)", "",
+def traffic_markdown(t: dict, cmd_fetch: str, cmd_write: str,
+                     title: str = "HBM traffic per dispatch of the hot kernels (workload 2 bench step)") -> str:
+    out = [f"# {title}", "",
            "Commands (from `/tmp` with `TMPDIR=/tmp`; `<repo>` is the repository root):", "", "```",
            cmd_fetch, cmd_write, "```", "",
            f"Calibration: a {t['copy_bytes'] >> 20} MiB device-to-device copy reads as "
@@ -201,6 +228,41 @@ def valu_markdown(pmc_csv: str, stats_csv: str, command: str, kernels=("k_refine
     return "\n".join(out) + "\n"
 
 
+PEAK_BF16_FLOPS = 2.5e15
+
+
+def mfma_markdown(pmc_csv: str, trace_csv: str, command: str, replays: int, window: int | None = None,
+                  title: str = "Matrix-core use of the scorer kernels") -> str:
+    """Per kernel: BF16 MFMA operations (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512)
+    and busy cycles per dispatch from a counter run; durations from the
+    windowed kernel trace of the same command."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in _counter_rows(pmc_csv, window):
+        per[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = collections.defaultdict(list)
+    trows = list(csv.DictReader(open(trace_csv)))
+    if window is not None:
+        trows = _window_rows(trows, "Start_Timestamp", "Kernel_Name", window)
+    for r in trows:
+        dur[short_name(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    out = [f"# {title}", "", "Commands (from `/tmp` with `TMPDIR=/tmp`; `<repo>` is the repository root):", "",
+           "```", command, "```", "",
+           "BF16 FLOP per dispatch = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512 (the counter's definition); achieved = "
+           "FLOP / average duration (kernel trace of the same command) against the dense BF16 peak of "
+           f"{PEAK_BF16_FLOPS / 1e15:.1f} PFLOP/s.", "",
+           "| kernel | dispatches | BF16 GFLOP / dispatch | avg duration us | achieved TFLOP/s | fraction of peak |",
+           "|---|---|---|---|---|---|"]
+    for k, d in sorted(per.items()):
+        mops = d.get("SQ_INSTS_VALU_MFMA_MOPS_BF16")
+        if not mops or sum(mops) == 0 or k not in dur:
+            continue
+        flops = sum(mops) / len(mops) * 512
+        t = sum(dur[k]) / len(dur[k])
+        out.append(f"| {k} | {len(mops)} | {flops / 1e9:.3f} | {t * 1e6:.1f} | {flops / t / 1e12:.1f} | "
+                   f"{flops / t / PEAK_BF16_FLOPS:.4f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -230,6 +292,17 @@ def main():
     t.add_argument("--md", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    t.add_argument("--window", type=int, default=None, help="window number (marker kernels)")
+    t.add_argument("--kernels", default="k_refine,k_sign")
+    t.add_argument("--title", default="HBM traffic per dispatch of the hot kernels (workload 2 bench step)")
+    m = sub.add_parser("mfma")
+    m.add_argument("--pmc", required=True)
+    m.add_argument("--trace", required=True)
+    m.add_argument("--replays", type=int, required=True)
+    m.add_argument("--window", type=int, default=None)
+    m.add_argument("--title", default="Matrix-core use of the scorer kernels")
+    m.add_argument("--out", required=True)
+    m.add_argument("--command", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         open(a.out, "w").write(stats_markdown(a.csv, a.title, a.command, a.notes))
@@ -237,10 +310,12 @@ def main():
         open(a.out, "w").write(window_markdown(a.trace, a.replays, a.title, a.command, a.notes, a.index))
     elif a.cmd == "valu":
         open(a.out, "w").write(valu_markdown(a.pmc, a.stats, a.command))
+    elif a.cmd == "mfma":
+        open(a.out, "w").write(mfma_markdown(a.pmc, a.trace, a.command, a.replays, a.window, a.title))
     else:
-        res = traffic(a.fetch, a.write)
+        res = traffic(a.fetch, a.write, tuple(a.kernels.split(",")), a.window)
         json.dump(res, open(a.out, "w"), indent=1)
-        open(a.md, "w").write(traffic_markdown(res, a.command_fetch, a.command_write))
+        open(a.md, "w").write(traffic_markdown(res, a.command_fetch, a.command_write, a.title))
 
 
 if __name__ == "__main__":
