@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--trace-replays", type=int, default=5)
     ap.add_argument("--bands", type=int, default=32)
     ap.add_argument("--rows", type=int, default=4)
-    ap.add_argument("--recall-sample", type=int, default=100)
+    ap.add_argument("--recall-sample", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
@@ -402,7 +402,7 @@ def stage_roofline(state, methods):
     return rl
 
 
-def cfg3_pipeline(cfg, dev, bandings=((32, 8), (36, 7), (42, 6), (64, 4)), recall_queries=100):
+def cfg3_pipeline(cfg, dev, bandings=((32, 8), (36, 7), (42, 6), (64, 4)), recall_queries=1000):
     """Workload 3 end to end: 1,000,000 polygons (20% in near-duplicate
     clusters), k = 256, cap 2^20; the dataset signed by the walk, then per
     banding b x r the bucket table and all 1,000 queries as one batch through

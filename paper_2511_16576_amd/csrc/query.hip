@@ -326,14 +326,23 @@ __global__ __launch_bounds__(256) void k_sparse_sort(const int32_t *__restrict__
     wave_lds_fence();
     int uniq = 0;
     bool whole = false;
-    for (int i0 = 0; i0 < cnt; i0 += 64) {
-        if (uniq + 64 > kSetMax) {             // wavefront-uniform: keep the set below 3/4 full
-            whole = true;
-            break;
+    // eight of a lane's entries are loaded together, then inserted
+    for (int i0 = 0; i0 < cnt && !whole; i0 += 8 * 64) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int i = i0 + 64 * u + lane;
+            v[u] = i < cnt ? row[i] : -1;
         }
-        const int i = i0 + lane;
-        const bool fresh = i < cnt && set_insert(T, kSetBits, row[i]);
-        uniq += __popcll(__ballot(fresh));
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            if (uniq + 64 > kSetMax) {         // wavefront-uniform: keep the set below 3/4 full
+                whole = true;
+                break;
+            }
+            const bool fresh = v[u] >= 0 && set_insert(T, kSetBits, v[u]);
+            uniq += __popcll(__ballot(fresh));
+        }
     }
     wave_lds_fence();
     int u;

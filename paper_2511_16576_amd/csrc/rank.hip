@@ -109,9 +109,9 @@ __global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restr
         qv[t] = (vec && h < k) ? *reinterpret_cast<const uint4 *>(sq + h) : make_uint4(0, 0, 0, 0);
     }
     if (vec && k <= 256) {
-        // the common case (k <= 256): a wavefront takes four candidates at a
-        // time, their four 16-byte slices a lane loaded together
-        constexpr int kU = 4;
+        // the common case (k <= 256): a wavefront takes eight candidates at
+        // a time, their eight 16-byte slices a lane loaded together
+        constexpr int kU = 8;
         const bool in = 4 * lane < k;
         for (int i0 = wave * kU; i0 < n; i0 += nwave * kU) {
             uint4 pv[kU];
