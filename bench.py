@@ -772,10 +772,17 @@ def secondary(args, hstate):
         a_mbr = (mbr[:, 2] - mbr[:, 0] + 1) * (mbr[:, 3] - mbr[:, 1] + 1)
         a_p = np.maximum(np.abs(area2.cpu().numpy().astype(np.float64)) / 2, 0.5)
         nverts = (polys.offsets[1:] - polys.offsets[:-1]).cpu().numpy().astype(np.float64)
-        edges = float((k * nverts * np.minimum(a_mbr / a_p, s_np.mean(axis=1))).sum())
-        return draws, edges
-    dw_d, ed_d = sign_work(sig, D)
-    dw_q, ed_q = sign_work(qsig, Q)
+        tests = k * np.minimum(a_mbr / a_p, s_np.mean(axis=1))
+        edges = float((tests * nverts).sum())
+        # what the 64-sample tiles and the edge-parallel test issue beyond
+        # the algorithmic work: draws past the first hit in its tile, and
+        # lane slots of a test beyond the polygon's edges
+        h = np.where(s_np > 0, s_np, cap)
+        drawn = float((np.ceil(h / 64.0) * 64.0).sum())
+        slots = float((tests * np.ceil(nverts / 64.0) * 64.0).sum())
+        return draws, edges, drawn, slots
+    dw_d, ed_d, dr_d, sl_d = sign_work(sig, D)
+    dw_q, ed_q, dr_q, sl_q = sign_work(qsig, Q)
     t_sign_avg = 0.5 * (stage_ms["sign"] + stage_ms["qsign"]) / 1e3
     work_sign = 0.5 * ((dw_d + dw_q) * C_DRAW + (ed_d + ed_q) * C_EDGE)
     hw_sign = hardware_valu_fraction("k_sign")
@@ -783,7 +790,9 @@ def secondary(args, hstate):
                  "hardware_valu_frac": hw_sign,
                  "unit": "T lane-cycles/s", "frac": work_sign / t_sign_avg / PEAK_VALU, "traffic": None,
                  "kernel": "k_sign", "launch_ms": 1e3 * t_sign_avg,
-                 "draws_per_launch": 0.5 * (dw_d + dw_q), "edge_tests_per_launch": 0.5 * (ed_d + ed_q)}
+                 "draws_per_launch": 0.5 * (dw_d + dw_q), "edge_tests_per_launch": 0.5 * (ed_d + ed_q),
+                 "tile_overshoot_share": 1.0 - (dw_d + dw_q) / (dr_d + dr_q),
+                 "edge_lane_idle_share": 1.0 - (ed_d + ed_q) / (sl_d + sl_q)}
     # -- refinement roofline (k_refine; FP64 VALU bound).  Algorithmic work:
     # the edge pairs the tiled form tests (counted by the kernel: 8 per kept
     # (P chunk, Q edge) unit) times C_PAIR, plus the general form's edge pairs

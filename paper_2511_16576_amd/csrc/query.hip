@@ -166,6 +166,42 @@ __device__ int sort_unique(int32_t *L, int cnt, int lane)
     return u;
 }
 
+// Bitonic sort of 64 R values held R to a lane (element i = R lane + r, a
+// blocked layout), ascending, in registers: steps within a lane swap
+// registers, steps across lanes exchange with __shfl_xor.  R is 16 or 32.
+template <int R>
+__device__ __forceinline__ void sort_regs(int32_t (&v)[R], int lane)
+{
+#pragma unroll
+    for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= R) {
+                const int lj = j / R;                   // partner lane offset
+                const bool lower = (lane & lj) == 0;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const bool up = ((R * lane + r) & k) == 0;
+                    const int32_t o = __shfl_xor(v[r], lj, 64);
+                    const int32_t lo = min(v[r], o), hi = max(v[r], o);
+                    v[r] = (lower == up) ? lo : hi;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if ((r & j) == 0) {
+                        const bool up = ((R * lane + r) & k) == 0;
+                        const int32_t a = v[r], b = v[r | j];
+                        const int32_t lo = min(a, b), hi = max(a, b);
+                        v[r] = up ? lo : hi;
+                        v[r | j] = up ? hi : lo;
+                    }
+                }
+            }
+        }
+    }
+}
+
 constexpr int kBigCap = 16384;
 
 // Gather pass, one wavefront per query (four per block): the query's
@@ -366,6 +402,30 @@ __global__ __launch_bounds__(256) void k_sparse_sort(const int32_t *__restrict__
             }
             m += __popcll(km);
             wave_lds_fence();
+        }
+        // the members are distinct: sorted in registers when they fit
+        // (1,024 or 2,048 of them), else in LDS
+        if (m <= 1024) {
+            int32_t v[16];
+#pragma unroll
+            for (int r = 0; r < 16; r++) v[r] = 16 * lane + r < m ? T[16 * lane + r] : INT32_MAX;
+            sort_regs<16>(v, lane);
+#pragma unroll
+            for (int r = 0; r < 16; r++)
+                if (16 * lane + r < m) row[16 * lane + r] = v[r];
+            if (lane == 0) counts[q] = m;
+            return;
+        }
+        if (m <= 2048) {
+            int32_t v[32];
+#pragma unroll
+            for (int r = 0; r < 32; r++) v[r] = 32 * lane + r < m ? T[32 * lane + r] : INT32_MAX;
+            sort_regs<32>(v, lane);
+#pragma unroll
+            for (int r = 0; r < 32; r++)
+                if (32 * lane + r < m) row[32 * lane + r] = v[r];
+            if (lane == 0) counts[q] = m;
+            return;
         }
         u = sort_unique(T, m, lane);
     }

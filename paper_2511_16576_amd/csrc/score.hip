@@ -11,10 +11,13 @@
 // (18 k-steps) and W2 (16 k-steps) in registers for the whole launch.  Pairs
 // are taken 32 at a time (one MFMA row tile): the 32 input rows are built in
 // LDS by the 8 wavefronts (four rows each: a 16-byte load of each signature
-// per lane, all eight in flight together), layer 1 reads its A operand from that tile, writes
-// GELU(z1) as BF16 into a second LDS tile, layer 2 reads it; each wavefront
-// reduces its 32 columns of GELU(z2) * w3 per row, and the 8 partial sums of
-// a row are added in wavefront order.
+// per lane), layer 1 reads its A operand from that tile, writes GELU(z1) as
+// BF16 into a second LDS tile, layer 2 reads it; each wavefront reduces its
+// 32 columns of GELU(z2) * w3 per row, and the 8 partial sums of a row are
+// added in wavefront order.  The tiles are software-pipelined: while a tile
+// runs on the matrix cores, the next tile's signature slices and features
+// are in flight (and the indices of the one after), and they are written
+// into the other of two input buffers once the tile is done.
 //
 // MFMA operand layout (one wavefront, 32 x 32 output tile, k-step 16): lane
 // l supplies row l % 32 of A and column l % 32 of B at k = 8 (l / 32) .. +7;
@@ -42,6 +45,69 @@ constexpr int64_t kPB2 = kPW2 + (int64_t)kScorerHid * kScorerHid;
 constexpr int64_t kPW3 = kPB2 + kScorerHid;
 constexpr int64_t kPB3 = kPW3 + kScorerHid;
 
+// Pair rows of one tile still in registers: the signature slices of the
+// wavefront's four rows, the rows' 12 + 12 polygon features (lane f < 12
+// holds the left polygon's feature f, lane 12 + f the right one's).
+struct TileRegs {
+    int32_t qi[kTileRows / kWaves], pi[kTileRows / kWaves];
+    uint4 sa[kTileRows / kWaves], sb[kTileRows / kWaves];
+    float fv[kTileRows / kWaves];
+};
+
+__device__ __forceinline__ void load_indices(const int32_t *li, const int32_t *ri, int64_t R, int64_t r0, int wave,
+                                             int32_t *qi, int32_t *pi)
+{
+#pragma unroll
+    for (int u = 0; u < kTileRows / kWaves; u++) {
+        const int64_t r = r0 + wave + kWaves * u;
+        qi[u] = r0 >= 0 && r < R ? li[r] : -1;
+        pi[u] = r0 >= 0 && r < R ? ri[r] : -1;
+    }
+}
+
+__device__ __forceinline__ void load_rows(const uint32_t *lsig, const float *lfeat, const uint32_t *rsig,
+                                          const float *rfeat, int lane, TileRegs &T)
+{
+#pragma unroll
+    for (int u = 0; u < kTileRows / kWaves; u++) {
+        const bool ok = T.qi[u] >= 0 && T.pi[u] >= 0;
+        T.sa[u] = ok ? *reinterpret_cast<const uint4 *>(lsig + (int64_t)T.qi[u] * kScorerBits + 4 * lane)
+                     : make_uint4(0, 0, 0, 0);
+        T.sb[u] = ok ? *reinterpret_cast<const uint4 *>(rsig + (int64_t)T.pi[u] * kScorerBits + 4 * lane)
+                     : make_uint4(1, 1, 1, 1);
+        const float *f = lane < kPolyFeat ? lfeat + (int64_t)T.qi[u] * kPolyFeat + lane
+                                          : rfeat + (int64_t)T.pi[u] * kPolyFeat + (lane - kPolyFeat);
+        T.fv[u] = ok && lane < 2 * kPolyFeat ? *f : 0.f;
+    }
+}
+
+// The wavefront's four rows of the tile into the LDS input buffer X: the
+// collision bits and the 32 feature columns (all zero for an empty row).
+__device__ __forceinline__ void build_rows(const TileRegs &T, __bf16 *X, int wave, int lane)
+{
+#pragma unroll
+    for (int u = 0; u < kTileRows / kWaves; u++) {
+        __bf16 *xr = X + (wave + kWaves * u) * kXStride;
+        const bool ok = T.qi[u] >= 0 && T.pi[u] >= 0;   // wavefront-uniform
+        const bool e0 = T.sa[u].x == T.sb[u].x, e1 = T.sa[u].y == T.sb[u].y, e2 = T.sa[u].z == T.sb[u].z,
+                   e3 = T.sa[u].w == T.sb[u].w;         // all false on an empty row
+        xr[4 * lane + 0] = (__bf16)(e0 ? 1.f : 0.f);
+        xr[4 * lane + 1] = (__bf16)(e1 ? 1.f : 0.f);
+        xr[4 * lane + 2] = (__bf16)(e2 ? 1.f : 0.f);
+        xr[4 * lane + 3] = (__bf16)(e3 ? 1.f : 0.f);
+        const int cnt = __popcll(__ballot(e0)) + __popcll(__ballot(e1)) + __popcll(__ballot(e2)) +
+                        __popcll(__ballot(e3));
+        float fq[kPolyFeat], fp[kPolyFeat];
+#pragma unroll
+        for (int f = 0; f < kPolyFeat; f++) {
+            fq[f] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, T.fv[u]), f));
+            fp[f] = __builtin_bit_cast(float,
+                                       __builtin_amdgcn_readlane(__builtin_bit_cast(int, T.fv[u]), kPolyFeat + f));
+        }
+        if (lane < 32) xr[kScorerBits + lane] = ok ? (__bf16)pair_tail_feature(lane, fq, fp, cnt) : (__bf16)0.f;
+    }
+}
+
 __global__ __launch_bounds__(512) void k_score_pairs(const uint32_t *__restrict__ lsig,
                                                      const float *__restrict__ lfeat,
                                                      const uint32_t *__restrict__ rsig,
@@ -53,13 +119,24 @@ __global__ __launch_bounds__(512) void k_score_pairs(const uint32_t *__restrict_
                                                      const __bf16 *__restrict__ wbf16,
                                                      float *__restrict__ out)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 X[kTileRows * kXStride];
+    __shared__ __attribute__((aligned(16))) __bf16 X[2][kTileRows * kXStride];
     __shared__ __attribute__((aligned(16))) __bf16 H[kTileRows * kHStride];
     __shared__ float part[kWaves][kTileRows];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int col = 32 * wave + (lane & 31);    // this lane's hidden unit (B column, output column)
     const int kl = 8 * (lane >> 5);
+    const int64_t tiles = (R + kTileRows - 1) / kTileRows;
+    const int64_t G = gridDim.x;
+    int64_t t = blockIdx.x;
+    if (t >= tiles) return;                      // workgroup-uniform, before any barrier
+    // the first tile's rows, and the next tile's indices, are requested
+    // before the weights so their latencies overlap
+    TileRegs T;
+    int32_t nqi[kTileRows / kWaves], npi[kTileRows / kWaves];
+    load_indices(li, ri, R, t * kTileRows, wave, T.qi, T.pi);
+    load_rows(lsig, lfeat, rsig, rfeat, lane, T);
+    load_indices(li, ri, R, t + G < tiles ? (t + G) * kTileRows : -1, wave, nqi, npi);
     const __bf16 *W1 = wbf16;
     const __bf16 *W2 = wbf16 + (int64_t)kScorerHid * kScorerIn;
     bf16x8 w1[kK1], w2[kK2];
@@ -71,50 +148,24 @@ __global__ __launch_bounds__(512) void k_score_pairs(const uint32_t *__restrict_
         w2[ks] = *reinterpret_cast<const bf16x8 *>(W2 + (int64_t)col * kScorerHid + 16 * ks + kl);
     const float b1c = params[kPB1 + col], b2c = params[kPB2 + col], w3c = params[kPW3 + col];
     const float b3 = params[kPB3];
-    const int64_t tiles = (R + kTileRows - 1) / kTileRows;
-    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    build_rows(T, X[0], wave, lane);
+    int buf = 0;
+    for (; t < tiles; t += G, buf ^= 1) {
         const int64_t r0 = t * kTileRows;
-        // -- the tile's input rows: wavefront w builds rows w, w + 8, w + 16,
-        // w + 24; the four rows' indices, then their eight signature slices,
-        // are loaded together so their latencies overlap
-        constexpr int kPer = kTileRows / kWaves;
-        int32_t qi[kPer], pi[kPer];
+        // -- the next tile's rows are requested now and land while this
+        // tile runs on the matrix cores; the tile after it, its indices
+        const bool more = t + G < tiles;
 #pragma unroll
-        for (int u = 0; u < kPer; u++) {
-            const int64_t r = r0 + wave + kWaves * u;
-            qi[u] = r < R ? li[r] : -1;
-            pi[u] = r < R ? ri[r] : -1;
+        for (int u = 0; u < kTileRows / kWaves; u++) {
+            T.qi[u] = nqi[u];
+            T.pi[u] = npi[u];
         }
-        uint4 sa[kPer], sb[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; u++) {
-            const bool ok = qi[u] >= 0 && pi[u] >= 0;
-            sa[u] = ok ? *reinterpret_cast<const uint4 *>(lsig + (int64_t)qi[u] * kScorerBits + 4 * lane)
-                       : make_uint4(0, 0, 0, 0);
-            sb[u] = ok ? *reinterpret_cast<const uint4 *>(rsig + (int64_t)pi[u] * kScorerBits + 4 * lane)
-                       : make_uint4(1, 1, 1, 1);
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; u++) {
-            __bf16 *xr = X + (wave + kWaves * u) * kXStride;
-            const bool ok = qi[u] >= 0 && pi[u] >= 0;   // wavefront-uniform
-            const bool e0 = sa[u].x == sb[u].x, e1 = sa[u].y == sb[u].y, e2 = sa[u].z == sb[u].z,
-                       e3 = sa[u].w == sb[u].w;         // all false on an empty row
-            xr[4 * lane + 0] = (__bf16)(e0 ? 1.f : 0.f);
-            xr[4 * lane + 1] = (__bf16)(e1 ? 1.f : 0.f);
-            xr[4 * lane + 2] = (__bf16)(e2 ? 1.f : 0.f);
-            xr[4 * lane + 3] = (__bf16)(e3 ? 1.f : 0.f);
-            const int cnt = __popcll(__ballot(e0)) + __popcll(__ballot(e1)) + __popcll(__ballot(e2)) +
-                            __popcll(__ballot(e3));
-            if (lane < 32)
-                xr[kScorerBits + lane] = ok ? (__bf16)pair_tail_feature(lane, lfeat + (int64_t)qi[u] * kPolyFeat,
-                                                                        rfeat + (int64_t)pi[u] * kPolyFeat, cnt)
-                                            : (__bf16)0.f;
-        }
-        __syncthreads();
+        if (more) load_rows(lsig, lfeat, rsig, rfeat, lane, T);
+        load_indices(li, ri, R, t + 2 * G < tiles ? (t + 2 * G) * kTileRows : -1, wave, nqi, npi);
+        __syncthreads();                          // X[buf] complete
         // -- layer 1: z1 = X W1^T + b1, H = BF16(GELU(z1))
         f32x16 acc = {};
-        const __bf16 *xa = X + (lane & 31) * kXStride + kl;
+        const __bf16 *xa = X[buf] + (lane & 31) * kXStride + kl;
 #pragma unroll
         for (int ks = 0; ks < kK1; ks++)
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8 *>(xa + 16 * ks), w1[ks],
@@ -152,8 +203,9 @@ __global__ __launch_bounds__(512) void k_score_pairs(const uint32_t *__restrict_
                 if (o >= 0) out[o] = y;
             }
         }
-        // the next tile's rows are written only after every wavefront has
-        // passed the barrier above, i.e. finished reading X, H and part
+        // -- the next tile's rows into the other input buffer (its last
+        // readers, layer 1 of the previous tile, are past two barriers)
+        if (more) build_rows(T, X[buf ^ 1], wave, lane);
     }
 }
 
