@@ -728,8 +728,7 @@ polymh_status rank_round(const polymh_polys *data, const polymh_polys *queries, 
                          bool finishing, hipStream_t s)
 {
     polymh_status st;
-    if ((st = launch_round_count(cand_off, nq, w.cursor, w.active, finishing ? 0 : F, w.roff, s))) return st;
-    if ((st = launch_offsets(w.roff, nq, s))) return st;
+    if ((st = launch_round_offsets(cand_off, nq, w.cursor, w.active, finishing ? 0 : F, w.roff, s))) return st;
     if ((st = launch_round_fill(cand_off, cand_ids, w.order, w.cursor, w.roff, nq, w.rids, w.rpos, s))) return st;
     // the pair count lives on the device: the refinement's grid is sized by
     // the round's bound (F per query; one workgroup per query for the

@@ -118,6 +118,7 @@ struct LookupArgs {
     const uint16_t *cell_off;
     uint32_t *sig;
     uint32_t *unresolved;          // [n] 1: a hash needs the walk, 2: the whole polygon is walked
+    const int32_t *order;          // [n] polygons, longest lookups first
     int64_t n;
     int32_t k;
     uint32_t cap, horizon;
@@ -310,7 +311,8 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int per = blockDim.x;
     const int groups = (A.k + per - 1) / per;
-    const int64_t p = blockIdx.x / groups;
+    // workgroups start in order of their index: the order puts the longest first
+    const int64_t p = A.order[blockIdx.x / groups];
     const int i = (int)(blockIdx.x % groups) * per + tid;
     const bool active = i < A.k;
     if (A.unresolved[p] & 2u) return;    // walked (uniform per workgroup, before any barrier)
@@ -363,6 +365,93 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
         if (best != kNone) out[i] = best + 1;
         else if (A.horizon >= A.cap) out[i] = 0u;
         else atomicOr(&A.unresolved[p], 1u);
+    }
+}
+
+// Dispatch order of the polygons for the lookup, longest first.  With
+// h = C x area / |B| expected hits per chunk, a chunk has a hit with
+// probability P = 1 - exp(-h); a workgroup runs until the last of its 256
+// hashes has one, about ln(256) / P chunks (capped at the horizon), each a
+// few round trips to memory, and tests about max(1, m) / P samples a hash
+// (m = C x A_MBR / |B| samples in the MBR per chunk) against its n edges.
+// Started last, the few polygons with the largest such cost set the
+// launch's duration; started first, they overlap the rest.  A counting sort
+// on a quantised estimate (descending; the order within a key is the
+// arrival order, which affects only timing).  Walked and degenerate
+// polygons, whose workgroups return at once, go last.
+constexpr int kOrderCells = 4096;
+
+__global__ __launch_bounds__(256) void k_order_count(const int64_t *__restrict__ area2,
+                                                     const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ mbr,
+                                                     const uint32_t *__restrict__ unresolved, int64_t n,
+                                                     double box_area, double chunk, double nchunks,
+                                                     uint16_t *__restrict__ key, int32_t *__restrict__ counts)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const double area = 0.5 * (double)(area2[p] < 0 ? -area2[p] : area2[p]);
+        int k = kOrderCells - 1;
+        if (!(unresolved[p] & 2u) && area > 0.0) {
+            const int4 b = *reinterpret_cast<const int4 *>(mbr + 4 * p);
+            const double a_mbr = ((double)b.z - (double)b.x + 1.0) * ((double)b.w - (double)b.y + 1.0);
+            const double P = -expm1(-chunk * area / box_area);
+            const double chunks = fmin(nchunks, 5.545 / P);             // ln(256) / P
+            const double tests = fmax(1.0, chunk * a_mbr / box_area) / P;
+            const double est = 16.0 * chunks + tests * (double)(off[p + 1] - off[p]) / 8.0;
+            k = kOrderCells - 1 - (int)fmin(est, (double)(kOrderCells - 1));
+        }
+        key[p] = (uint16_t)k;
+        // the last key (every walked polygon) is counted once a wavefront
+        const bool last = k == kOrderCells - 1;
+        const uint64_t m = __ballot(last);
+        if (!last) atomicAdd(&counts[k], 1);
+        else if ((int)(threadIdx.x & 63) == __builtin_ctzll(m)) atomicAdd(&counts[k], __popcll(m));
+    }
+}
+
+// Exclusive prefix of the kOrderCells counts in place (one block of 1024).
+__global__ __launch_bounds__(1024) void k_order_scan(int32_t *__restrict__ counts)
+{
+    constexpr int kPer = kOrderCells / 1024;
+    __shared__ int sw[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int v[kPer], sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+        v[u] = counts[kPer * tid + u];
+        sum += v[u];
+    }
+    const int incl = wave_incl_scan32(sum);
+    if (lane == 63) sw[wave] = incl;
+    __syncthreads();
+    int pre = incl - sum;
+    for (int w = 0; w < wave; w++) pre += sw[w];
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+        counts[kPer * tid + u] = pre;
+        pre += v[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_order_scatter(const uint16_t *__restrict__ key, int64_t n,
+                                                       int32_t *__restrict__ cursor, int32_t *__restrict__ order)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int k = key[p];
+        // positions of the last key are claimed once a wavefront
+        const bool last = k == kOrderCells - 1;
+        const uint64_t m = __ballot(last);
+        int pos;
+        if (last) {
+            const int leader = __builtin_ctzll(m);
+            int base = 0;
+            if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&cursor[k], __popcll(m));
+            base = __shfl(base, leader, 64);
+            pos = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        } else {
+            pos = atomicAdd(&cursor[k], 1);
+        }
+        order[pos] = (int32_t)p;
     }
 }
 
@@ -443,6 +532,8 @@ struct BinnedWs {
     uint16_t *sj, *cell_off;
     uint32_t *unresolved;
     int32_t *list, *count;
+    int32_t *order, *cell_counts;
+    uint16_t *key;
 };
 
 BinnedWs carve_binned(Carve &c, int32_t k, int64_t nchunks, int32_t bits, int64_t n)
@@ -456,6 +547,9 @@ BinnedWs carve_binned(Carve &c, int32_t k, int64_t nchunks, int32_t bits, int64_
     w.unresolved = c.take<uint32_t>((size_t)n);
     w.list = c.take<int32_t>((size_t)n);
     w.count = c.take<int32_t>(1);
+    w.order = c.take<int32_t>((size_t)n);
+    w.cell_counts = c.take<int32_t>((size_t)kOrderCells);
+    w.key = c.take<uint16_t>((size_t)n);
     return w;
 }
 
@@ -518,6 +612,16 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
                        (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), walk_edges,
                        w.unresolved);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(w.count), (int64_t)1);
+    // the lookup's dispatch order (after the classification: walked polygons last)
+    hipLaunchKernelGGL(k_zero_words, dim3(kOrderCells / 256), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t *>(w.cell_counts), (int64_t)kOrderCells);
+    hipLaunchKernelGGL(k_order_count, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.off, L.mbr, w.unresolved, L.n,
+                       (double)wx * (double)wy, (double)((int64_t)1 << lchunk), (double)nchunks, w.key,
+                       w.cell_counts);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, w.cell_counts);
+    hipLaunchKernelGGL(k_order_scatter, dim3(grid_for(L.n)), dim3(256), 0, s, w.key, L.n, w.cell_counts, w.order);
+    polymh_status st0 = check_launch("sign_binned: order");
+    if (st0) return st0;
     LookupArgs A{};
     A.xy = L.xy;
     A.off = L.off;
@@ -528,6 +632,7 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     A.cell_off = w.cell_off;
     A.sig = L.sig;
     A.unresolved = w.unresolved;
+    A.order = w.order;
     A.n = L.n;
     A.k = L.k;
     A.cap = L.cap;

@@ -274,8 +274,9 @@ polymh_status launch_rank_sort(const int64_t *off, int64_t nq, const float *scor
                                uint8_t *sorted_ok, hipStream_t s);
 polymh_status launch_rank_init(int64_t nq, int32_t topk, int64_t *cursor, uint8_t *active,
                                int32_t *top_ids, double *top_j, hipStream_t s);
-polymh_status launch_round_count(const int64_t *off, int64_t nq, const int64_t *cursor,
-                                 const uint8_t *active, int32_t F, int64_t *counts, hipStream_t s);
+// roff[0..nq]: exclusive prefix of the round's per-query pair counts
+polymh_status launch_round_offsets(const int64_t *off, int64_t nq, const int64_t *cursor,
+                                   const uint8_t *active, int32_t F, int64_t *roff, hipStream_t s);
 polymh_status launch_round_fill(const int64_t *off, const int32_t *cand_ids, const int32_t *order,
                                 const int64_t *cursor, const int64_t *roff, int64_t nq,
                                 int32_t *rids, int32_t *rpos, hipStream_t s);

@@ -433,36 +433,111 @@ __global__ __launch_bounds__(256) void k_sparse_sort(const int32_t *__restrict__
     if (lane == 0) counts[q] = u;
 }
 
+// Bitonic sort of 4096 values over a 1024-thread block, thread t holding
+// positions 4t .. 4t + 3: partners in the same thread are swapped in
+// registers, partners in the same wavefront exchanged by shuffles, and the
+// ten steps whose partners sit in another wavefront go through L (a write,
+// a barrier, a read, a barrier).
+__device__ void sort_block4096(int32_t (&v)[4], int32_t *L, int tid)
+{
+    const int lane = tid & 63;
+    for (int k = 2; k <= 4096; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 256) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) L[4 * tid + r] = v[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = 4 * tid + r;
+                    const int32_t o = L[i ^ j];
+                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                    v[r] = keep_min ? min(v[r], o) : max(v[r], o);
+                }
+                __syncthreads();
+            } else if (j >= 4) {
+                const int lj = j >> 2;
+                const bool lower = (lane & lj) == 0;
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const bool up = ((4 * tid + r) & k) == 0;
+                    const int32_t o = __shfl_xor(v[r], lj, 64);
+                    v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    if ((r & j) == 0) {
+                        const bool up = ((4 * tid + r) & k) == 0;
+                        const int32_t x = v[r], y = v[r | j];
+                        v[r] = up ? min(x, y) : max(x, y);
+                        v[r | j] = up ? max(x, y) : min(x, y);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Block-wide exclusive prefix of one int per thread (1024 threads); *total
+// gets the sum.  sw holds 16 ints.
+__device__ __forceinline__ int block_excl_scan1024(int x, int *sw, int tid, int *total)
+{
+    const int lane = tid & 63, wave = tid >> 6;
+    const int incl = wave_incl_scan32(x);
+    if (lane == 63) sw[wave] = incl;
+    __syncthreads();
+    int pre = incl - x, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; w++) {
+        const int y = sw[w];
+        pre += w < wave ? y : 0;
+        tot += y;
+    }
+    *total = tot;
+    return pre;
+}
+
 // Sort pass for long lists, one block of 1024 threads per query with more
-// than kSparseCap raw entries (at most kBigCap): the same hash set in LDS
-// (16384 slots), its members moved to the front (a block-wide scan places
-// them), a bitonic sort of those, written back.  More than kBigSetMax
-// distinct polygons: the raw list is sorted whole and its repeats dropped.
+// than kSparseCap raw entries (at most kBigCap): the raw list is loaded
+// whole (16 entries a thread, all in flight together), inserted into an LDS
+// hash set of 16384 slots (each polygon once), the set's members moved to
+// the front (a block-wide scan places them) and sorted: up to 4096 of them
+// in registers, more in LDS.  More than kBigSetMax distinct polygons: the
+// raw list is sorted whole in LDS and its repeats dropped.
 __global__ __launch_bounds__(1024) void k_sparse_sort_big(const int32_t *__restrict__ dense,
                                                           int64_t *__restrict__ counts,
                                                           uint32_t *__restrict__ bitmap, int64_t words)
 {
     __shared__ int32_t L[kBigCap];
-    __shared__ int32_t sc[1024];
+    __shared__ int sw[16];
     __shared__ int s_uniq;
     const int64_t q = blockIdx.x;
     if (dense[q]) return;
     const int cnt = (int)counts[q];
     if (cnt <= kSparseCap) return;             // the wavefront pass took it
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     int32_t *row = reinterpret_cast<int32_t *>(bitmap + q * words);
+    int32_t raw[kBigCap / 1024];
+#pragma unroll
+    for (int u = 0; u < kBigCap / 1024; u++) {
+        const int i = u * 1024 + tid;
+        raw[u] = i < cnt ? row[i] : -1;
+    }
     for (int i = tid; i < kBigCap; i += 1024) L[i] = -1;
     if (tid == 0) s_uniq = 0;
     __syncthreads();
     bool whole = false;
-    for (int i0 = 0; i0 < cnt; i0 += 1024) {
+#pragma unroll
+    for (int u = 0; u < kBigCap / 1024; u++) {
+        if (u * 1024 >= cnt) break;             // block-uniform
         if (s_uniq + 1024 > kBigSetMax) {     // block-uniform (read after a barrier)
             whole = true;
             break;
         }
-        const int i = i0 + tid;
-        const bool fresh = i < cnt && set_insert(L, kBigSetBits, row[i]);
-        if (fresh) atomicAdd(&s_uniq, 1);
+        const bool fresh = raw[u] >= 0 && set_insert(L, kBigSetBits, raw[u]);
+        const int nf = __popcll(__ballot(fresh));
+        if (lane == 0 && nf) atomicAdd(&s_uniq, nf);
         __syncthreads();
     }
     __syncthreads();
@@ -479,20 +554,25 @@ __global__ __launch_bounds__(1024) void k_sparse_sort_big(const int32_t *__restr
             v[k] = L[16 * tid + k];
             mine += v[k] != -1;
         }
-        sc[tid] = mine;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const int x = tid >= o ? sc[tid - o] : 0;
-            __syncthreads();
-            sc[tid] += x;
-            __syncthreads();
-        }
-        int at = sc[tid] - mine;
-        n = sc[1023];
+        int at = block_excl_scan1024(mine, sw, tid, &n);
         __syncthreads();                        // every slot read before any is rewritten
 #pragma unroll
         for (int k = 0; k < 16; k++)
             if (v[k] != -1) L[at++] = v[k];
+        __syncthreads();
+        if (n <= 4096) {
+            // distinct ids: sorted in registers and written out as they are
+            int32_t w[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) w[r] = 4 * tid + r < n ? L[4 * tid + r] : INT32_MAX;
+            __syncthreads();                    // L is reused by the sort's cross-wavefront steps
+            sort_block4096(w, L, tid);
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                if (4 * tid + r < n) row[4 * tid + r] = w[r];
+            if (tid == 0) counts[q] = n;
+            return;
+        }
     }
     int P = 1;
     while (P < n) P <<= 1;
@@ -516,18 +596,11 @@ __global__ __launch_bounds__(1024) void k_sparse_sort_big(const int32_t *__restr
     const int i0 = tid * per, i1 = min(n, i0 + per);
     int mine = 0;
     for (int i = i0; i < i1; i++) mine += (i == 0 || L[i - 1] != L[i]) ? 1 : 0;
-    sc[tid] = mine;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int x = tid >= o ? sc[tid - o] : 0;
-        __syncthreads();
-        sc[tid] += x;
-        __syncthreads();
-    }
-    int u = sc[tid] - mine;
+    int total;
+    int u = block_excl_scan1024(mine, sw, tid, &total);
     for (int i = i0; i < i1; i++)
         if (i == 0 || L[i - 1] != L[i]) row[u++] = L[i];
-    if (tid == 1023) counts[q] = sc[1023];
+    if (tid == 0) counts[q] = total;
 }
 
 // One wavefront per query taken by k_sparse: its list copied from its row to
@@ -572,24 +645,40 @@ __global__ __launch_bounds__(256) void k_count(const uint32_t *__restrict__ bitm
     if (threadIdx.x == 0) counts[blockIdx.x] = s[0];
 }
 
-// Exclusive prefix of counts[0..nq) into off[0..nq], single block.
+// Exclusive prefix of counts[0..nq) into off[0..nq], single block, in
+// tiles of 8192: each thread adds 8 consecutive counts, a wavefront scan of
+// those sums and a pass over the 16 wavefront totals place every thread.
 __global__ __launch_bounds__(1024) void k_offsets(int64_t *__restrict__ off, int64_t nq)
 {
-    __shared__ int64_t s[1024];
+    constexpr int kPer = 8;
+    __shared__ int64_t s_w[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nq; c0 += 1024) {
-        const int64_t c = c0 + threadIdx.x;
-        const int64_t v = c < nq ? off[c] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const int64_t t = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
-            __syncthreads();
-            s[threadIdx.x] += t;
-            __syncthreads();
+    for (int64_t t0 = 0; t0 < nq; t0 += 1024 * kPer) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * kPer;
+        int64_t v[kPer];
+        int64_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            v[u] = base + u < nq ? off[base + u] : 0;
+            sum += v[u];
         }
-        if (c < nq) off[c] = carry + s[threadIdx.x] - v;
-        carry += s[1023];
+        const int64_t incl = wave_incl_scan64(sum);
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        int64_t pre = carry + incl - sum, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; w++) {
+            const int64_t x = s_w[w];
+            pre += w < wave ? x : 0;
+            tot += x;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            if (base + u < nq) off[base + u] = pre;
+            pre += v[u];
+        }
+        carry += tot;
         __syncthreads();
     }
     if (threadIdx.x == 0) off[nq] = carry;

@@ -12,6 +12,7 @@
 // their counts on the device and never wait on the host.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cfloat>
 
 namespace polymh {
@@ -214,15 +215,52 @@ __global__ void k_rank_init(int64_t nq, int32_t topk, int64_t *__restrict__ curs
     }
 }
 
-__global__ void k_round_count(const int64_t *__restrict__ off, int64_t nq,
-                              const int64_t *__restrict__ cursor, const uint8_t *__restrict__ active,
-                              int32_t F, int64_t *__restrict__ counts)
+// The round's per-query pair counts (active queries: min(F, left), or all
+// left for F <= 0) and their exclusive prefix into roff[0..nq], in one
+// block: tiles of 8192 queries, 8 consecutive ones a thread, a wavefront
+// scan of the thread sums and a pass over the 16 wavefront totals.
+__global__ __launch_bounds__(1024) void k_round_offsets(const int64_t *__restrict__ off, int64_t nq,
+                                                        const int64_t *__restrict__ cursor,
+                                                        const uint8_t *__restrict__ active, int32_t F,
+                                                        int64_t *__restrict__ roff)
 {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t left = (off[q + 1] - off[q]) - cursor[q];
-        counts[q] = active[q] ? ((F <= 0 || left < F) ? left : F) : 0;
+    constexpr int kPer = 8;
+    __shared__ int64_t s_w[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t carry = 0;
+    for (int64_t t0 = 0; t0 < nq; t0 += 1024 * kPer) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * kPer;
+        int64_t v[kPer];
+        int64_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int64_t q = base + u;
+            v[u] = 0;
+            if (q < nq && active[q]) {
+                const int64_t left = (off[q + 1] - off[q]) - cursor[q];
+                v[u] = (F <= 0 || left < F) ? left : F;
+            }
+            sum += v[u];
+        }
+        const int64_t incl = wave_incl_scan64(sum);
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        int64_t pre = carry + incl - sum, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; w++) {
+            const int64_t x = s_w[w];
+            pre += w < wave ? x : 0;
+            tot += x;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            if (base + u < nq) roff[base + u] = pre;
+            pre += v[u];
+        }
+        carry += tot;
+        __syncthreads();
     }
+    if (threadIdx.x == 0) roff[nq] = carry;
 }
 
 __global__ void k_round_fill(const int64_t *__restrict__ off, const int32_t *__restrict__ cand_ids,
@@ -240,9 +278,12 @@ __global__ void k_round_fill(const int64_t *__restrict__ off, const int32_t *__r
     }
 }
 
-// One thread per query: merge the round's exact results into the top-k and
-// apply the stop test.
-__global__ void k_round_merge(const int64_t *__restrict__ off, const float *__restrict__ score,
+// One wavefront per query: merge the round's exact results into the top-k
+// and apply the stop test.  Lane t holds entry t of the (J desc, id asc)
+// list (topk <= 64); the round's results are read 64 at a time, those that
+// beat the list's last entry are inserted one after another (the first lane
+// they beat takes them, the lanes behind it shift down by one).
+__global__ __launch_bounds__(256) void k_round_merge(const int64_t *__restrict__ off, const float *__restrict__ score,
                               const int32_t *__restrict__ order, const uint8_t *__restrict__ sorted_ok,
                               const int64_t *__restrict__ roff, const int32_t *__restrict__ rids,
                               const double *__restrict__ rj, int64_t nq, int32_t topk, float margin,
@@ -251,45 +292,75 @@ __global__ void k_round_merge(const int64_t *__restrict__ off, const float *__re
                               int32_t *__restrict__ n_active, unsigned long long *__restrict__ counters,
                               int finishing)
 {
+    __shared__ int s_left[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     // counters[0] += pairs refined in this round; counters[1] += queries the
     // finishing pass had to complete
     if (counters && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&counters[0], (unsigned long long)roff[nq]);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        if (!active[q]) continue;
-        if (finishing && counters && roff[q + 1] > roff[q]) atomicAdd(&counters[1], 1ull);
+    int left = 0;                               // queries of this wavefront still active
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + wave; q < nq; q += nw) {
+        if (!active[q]) continue;               // uniform per wavefront
+        const int64_t r0 = roff[q], r1 = roff[q + 1];
+        if (finishing && counters && r1 > r0 && lane == 0) atomicAdd(&counters[1], 1ull);
         int32_t *ti = top_ids + q * topk;
         double *tj = top_j + q * topk;
-        for (int64_t c = roff[q]; c < roff[q + 1]; c++) {
-            const int32_t id = rids[c];
-            const double j = rj[c];
-            // insertion into the (J desc, id asc) list
-            int at = topk;
-            for (int t = 0; t < topk; t++) {
-                if (ti[t] < 0 || j > tj[t] || (j == tj[t] && id < ti[t])) {
-                    at = t;
-                    break;
+        int32_t li = lane < topk ? ti[lane] : -1;
+        double lj = lane < topk ? tj[lane] : 0.0;
+        for (int64_t c0 = r0; c0 < r1; c0 += 64) {
+            const int64_t c = c0 + lane;
+            const int32_t id = c < r1 ? rids[c] : -1;
+            const double j = c < r1 ? rj[c] : 0.0;
+            const int32_t wid = __shfl(li, topk - 1, 64);
+            const double wj = __shfl(lj, topk - 1, 64);
+            uint64_t m = __ballot(c < r1 && (wid < 0 || j > wj || (j == wj && id < wid)));
+            while (m) {
+                const int src = __builtin_ctzll(m);
+                m &= m - 1;
+                const int32_t cid = __shfl(id, src, 64);
+                const double cj = __shfl(j, src, 64);
+                const uint64_t bm = __ballot(lane < topk && (li < 0 || cj > lj || (cj == lj && cid < li)));
+                if (bm == 0) continue;
+                const int at = __builtin_ctzll(bm);
+                const int32_t ui = __shfl_up(li, 1, 64);
+                const double uj = __shfl_up(lj, 1, 64);
+                if (lane == at) {
+                    li = cid;
+                    lj = cj;
+                } else if (lane > at && lane < topk) {
+                    li = ui;
+                    lj = uj;
                 }
-            }
-            if (at < topk) {
-                for (int t = topk - 1; t > at; t--) {
-                    ti[t] = ti[t - 1];
-                    tj[t] = tj[t - 1];
-                }
-                ti[at] = id;
-                tj[at] = j;
             }
         }
-        const int64_t cur = cursor[q] + (roff[q + 1] - roff[q]);
-        cursor[q] = cur;
+        if (lane < topk) {
+            ti[lane] = li;
+            tj[lane] = lj;
+        }
+        const int64_t cur = cursor[q] + (r1 - r0);
         const int64_t nq_c = off[q + 1] - off[q];
         bool stop = cur >= nq_c;
-        if (!stop && sorted_ok[q] && ti[topk - 1] >= 0) {
+        const int32_t last_id = __shfl(li, topk - 1, 64);
+        const double last_j = __shfl(lj, topk - 1, 64);
+        if (!stop && sorted_ok[q] && last_id >= 0) {
             const float next = score[off[q] + order[off[q] + cur]];
-            stop = tj[topk - 1] >= (double)next + (double)margin;
+            stop = last_j >= (double)next + (double)margin;
         }
-        if (stop) active[q] = 0;
-        else if (n_active) atomicAdd(n_active, 1);
+        if (lane == 0) {
+            cursor[q] = cur;
+            if (stop) active[q] = 0;
+        }
+        left += stop ? 0 : 1;
+    }
+    if (n_active) {
+        // one atomic per workgroup
+        if (lane == 0) s_left[wave] = left;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int t = s_left[0] + s_left[1] + s_left[2] + s_left[3];
+            if (t) atomicAdd(n_active, t);
+        }
     }
 }
 
@@ -529,12 +600,11 @@ polymh_status launch_rank_init(int64_t nq, int32_t topk, int64_t *cursor, uint8_
     return check_launch("rank_init");
 }
 
-polymh_status launch_round_count(const int64_t *off, int64_t nq, const int64_t *cursor,
-                                 const uint8_t *active, int32_t F, int64_t *counts, hipStream_t s)
+polymh_status launch_round_offsets(const int64_t *off, int64_t nq, const int64_t *cursor,
+                                   const uint8_t *active, int32_t F, int64_t *roff, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_round_count, dim3(g_of(nq, 256)), dim3(256), 0, s, off, nq, cursor, active,
-                       F, counts);
-    return check_launch("round_count");
+    hipLaunchKernelGGL(k_round_offsets, dim3(1), dim3(1024), 0, s, off, nq, cursor, active, F, roff);
+    return check_launch("round_offsets");
 }
 
 polymh_status launch_round_fill(const int64_t *off, const int32_t *cand_ids, const int32_t *order,
@@ -553,7 +623,8 @@ polymh_status launch_round_merge(const int64_t *off, const float *score, const i
                                  int32_t *n_active, unsigned long long *counters, int finishing, hipStream_t s)
 {
     if (n_active) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, n_active);
-    hipLaunchKernelGGL(k_round_merge, dim3(g_of(nq, 256)), dim3(256), 0, s, off, score, order,
+    const int64_t g = std::min<int64_t>(std::max<int64_t>((nq + 3) / 4, 1), 1024);
+    hipLaunchKernelGGL(k_round_merge, dim3((unsigned)g), dim3(256), 0, s, off, score, order,
                        sorted_ok, roff, rids, rj, nq, topk, margin, cursor, active, top_ids, top_j,
                        n_active, counters, finishing);
     return check_launch("round_merge");

@@ -130,6 +130,51 @@ def test_query_sparse_lists_band_chunks_and_shared_keys(pm, orc):
     assert np.diff(off)[nq0:].min() > 5000 > np.median(np.diff(off)[:nq0])
 
 
+def test_query_sparse_lists_every_sort_branch(pm, orc):
+    # queries built to reach each way a gathered list is sorted: on a
+    # wavefront (hash set with 1,024 / 1,025 / 2,048 / 2,049 members, raw
+    # lists of exactly 4,096 entries, more than 3,008 distinct ids: sorted
+    # whole), on a block (4,096 and 4,097 distinct ids, 2,000 ids met in
+    # eight bands, 7,000 ids, 12,500 distinct ids and 12,200 with repeats:
+    # sorted whole), a list past 16,384 entries (bitmap) and an empty one;
+    # each list equals the oracle's candidates
+    rng = np.random.default_rng(23)
+    nd, b = 600_000, 64
+    dk = rng.integers(0, 600_000, (nd, b)).astype(np.uint64)
+    perm = rng.permutation(nd)
+    groups = [(1024, 2), (1025, 3), (2048, 2), (2049, 1), (3100, 1), (4096, 2), (4097, 2), (2000, 8),
+              (12_500, 1), (7000, 2), (9000, 2)]
+    qrows = []
+    at = 0
+    for g, (size, bands) in enumerate(groups):
+        members = perm[at:at + size]
+        at += size
+        q = np.uint64(2 * 10 ** 12) + np.uint64(100 * g) + np.arange(b, dtype=np.uint64)
+        for t in range(bands):
+            key = np.uint64(10 ** 12 + 1000 * g + t)
+            dk[members, t] = key
+            q[t] = key
+        qrows.append(q)
+    # 6,000 ids in band 0 and 6,500 in band 1, 300 of them in both
+    a_set, b_set = perm[at:at + 6000], np.concatenate([perm[at:at + 300], perm[at + 6000:at + 12_200]])
+    q = np.uint64(3 * 10 ** 12) + np.arange(b, dtype=np.uint64)
+    dk[a_set, 0] = q[0] = np.uint64(4 * 10 ** 12)
+    dk[b_set, 1] = q[1] = np.uint64(4 * 10 ** 12 + 1)
+    qrows.append(q)
+    qrows.append(np.uint64(5 * 10 ** 12) + np.arange(b, dtype=np.uint64))   # matches nothing
+    nq0 = 14_990
+    qk = np.concatenate([dk[rng.integers(0, nd, nq0)], np.stack(qrows)])
+    nq = qk.shape[0]
+    sample = np.concatenate([np.sort(rng.choice(nq0, 20, replace=False)), np.arange(nq0, nq)])
+    ooff, oids = orc.candidates(dk, qk[sample])
+    sizes = np.diff(ooff)[20:]
+    assert list(sizes) == [1024, 1025, 2048, 2049, 3100, 4096, 4097, 2000, 12_500, 7000, 9000, 12_200, 0]
+    sk, si = pm.index_build(_t(dk.view(np.int64)))
+    off, ids = pm.query(sk, si, nd, _t(qk.view(np.int64)))
+    off, ids = off.cpu().numpy(), ids.cpu().numpy()
+    for i, q in enumerate(sample):
+        assert np.array_equal(ids[off[q]:off[q + 1]], oids[ooff[i]:ooff[i + 1]]), (q, i)
+
 def _pairs_all(nd, nq):
     off = np.arange(nq + 1, dtype=np.int64) * nd
     ids = np.tile(np.arange(nd, dtype=np.int32), nq)
