@@ -460,14 +460,18 @@ __global__ __launch_bounds__(256) void k_order_scatter(const uint16_t *__restric
 // area, or when its walk is expected to cost less than its lookup, in edge
 // tests per hash: the walk draws about |B| / area points (kDrawTests edge
 // tests each) and tests the about A_mbr / area of them inside the MBR against
-// its n edges; the lookup tests every sample of the hit's chunk that lies in
-// the MBR, about max(1, C A_mbr / |B|), against its n edges.  Either way the
-// signature is the same.  A polygon beyond the lookup's LDS edge cache
-// (walk_edges) is walked too: the lookup tests up to 64 points a wavefront at
-// a time against its edges one after another, a long serial loop, where the
-// walk splits each test over the lanes.  Degenerate polygons stay with the lookup, which signs them 0 at
-// once.
+// its n edges; the lookup visits chunks until one has a hit (each does with
+// probability P = 1 - exp(-C area / |B|)) and tests every sample of them
+// that lies in the MBR, about max(1, C A_mbr / |B|) a chunk, against its n
+// edges.  Either way the signature is the same.  A polygon beyond the
+// lookup's LDS edge cache (walk_edges), or whose lookup would test more than
+// kLookupTestCap edges a hash, is walked too: one lookup workgroup tests its
+// 256 hashes' points with four wavefronts, a long serial run that sets the
+// launch's duration, where the walk spreads a polygon's hashes over many
+// work items and each test over the lanes.  Degenerate polygons stay with
+// the lookup, which signs them 0 at once.
 constexpr double kDrawTests = 5.0;
+constexpr double kLookupTestCap = 2048.0;
 
 __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ area2,
                                                   const uint32_t *__restrict__ flags,
@@ -485,8 +489,10 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ ar
             const double a_mbr = ((double)m.z - (double)m.x + 1.0) * ((double)m.w - (double)m.y + 1.0);
             const double edges = (double)(off[p + 1] - off[p]);
             const double walk_cost = kDrawTests * box_area / area + edges * a_mbr / area;
-            const double bin_cost = edges * fmax(1.0, chunk * a_mbr / box_area);
-            walk = box_area < walk_ratio * area || walk_cost < bin_cost || edges > walk_edges;
+            const double hit = -expm1(-chunk * area / box_area);         // P(a chunk has a hit)
+            const double bin_cost = edges * fmax(1.0, chunk * a_mbr / box_area) / hit;
+            walk = box_area < walk_ratio * area || walk_cost < bin_cost || edges > walk_edges ||
+                   bin_cost > kLookupTestCap;
         }
         unresolved[p] = walk ? 2u : 0u;
     }
@@ -659,11 +665,11 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     W.n_dev = w.count;
     W.cfg.persistent = 1;
     // in a small launch the few polygons left to the walk are the costly
-    // ones (many edges or deep hits) and set its duration: 16 hashes a work
-    // item spread one polygon's hashes over many workgroups instead of four
-    // wavefronts (in a large launch that only multiplies the staging of the
+    // ones (many edges or deep hits) and set its duration: 8 hashes a work
+    // item (one a wavefront) spread one polygon's hashes over many
+    // workgroups (in a large launch that only multiplies the staging of the
     // many cheap walks of large polygons)
-    if (units < 32768 && (W.cfg.hash_block <= 0 || W.cfg.hash_block > 16)) W.cfg.hash_block = 16;
+    if (units < 32768 && (W.cfg.hash_block <= 0 || W.cfg.hash_block > 8)) W.cfg.hash_block = 8;
     return launch_sign(W, s);
 }
 

@@ -52,11 +52,22 @@ __device__ __forceinline__ bool inside_wave(const int4 *s_edges, const int32_t *
     if constexpr (MODE == kLds) {
         for (int e = lane; e < n; e += 64) odd ^= crosses_fp64(s_edges[e], px, py);
     } else if constexpr (MODE == kStream) {
-        for (int e = lane; e < n; e += 64) {
-            const int f = (e + 1 == n) ? 0 : e + 1;
-            const int2 a = *reinterpret_cast<const int2 *>(pxy + 2 * e);
-            const int2 b = *reinterpret_cast<const int2 *>(pxy + 2 * f);
-            odd ^= crosses_fp64(make_edge(a.x, a.y, b.x, b.y), px, py);
+        // eight 64-edge blocks' vertices are loaded before any is tested, so a
+        // long ring costs n / 512 round trips to memory instead of n / 64
+        constexpr int kU = 8;
+        const int2 *v = reinterpret_cast<const int2 *>(pxy);
+        for (int e0 = 0; e0 < n; e0 += 64 * kU) {
+            int2 a[kU], b[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                const int e = e0 + 64 * u + lane;
+                const int ec = e < n ? e : 0;
+                a[u] = v[ec];
+                b[u] = v[ec + 1 == n ? 0 : ec + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; u++)
+                odd ^= (e0 + 64 * u + lane < n) & crosses_fp64(make_edge(a[u].x, a[u].y, b[u].x, b[u].y), px, py);
         }
     } else {
         for (int e = lane; e < n; e += 64) {

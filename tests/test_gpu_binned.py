@@ -190,3 +190,45 @@ def test_binned_prebinned_reuses_the_bins(pm, orc):
         assert torch.equal(got, pm.sign(P, w.box, w.seed, k, cap)), i
     with pytest.raises(ValueError):
         pm.sign_binned(sets[0], w.box, w.seed, k, cap, horizon=h, bin_bits=b, rebin=False)
+
+
+def _comb(x0, y0, teeth, step, height, tooth):
+    # a base rectangle with rectangular teeth on top: many horizontal edges
+    # and vertices sharing y values
+    pts = [(x0, y0), (x0 + 2 * teeth * step, y0), (x0 + 2 * teeth * step, y0 + height)]
+    for i in reversed(range(teeth)):
+        xa, xb = x0 + (2 * i + 2) * step, x0 + (2 * i + 1) * step
+        pts += [(xa, y0 + height), (xa, y0 + height + tooth), (xb, y0 + height + tooth), (xb, y0 + height)]
+    pts.append((x0, y0 + height))
+    return np.asarray(pts, dtype=np.int64)
+
+
+def _spiky(cx, cy, n, r_out, r_in, seed):
+    # alternating long and short radii: long, steep spikes whose edges each
+    # cross many horizontal slabs
+    rng = np.random.default_rng(seed)
+    ang = np.sort(rng.uniform(0, 2 * np.pi, n))
+    r = np.where(np.arange(n) % 2 == 0, r_out, r_in)
+    return np.stack([np.rint(cx + r * np.cos(ang)), np.rint(cy + r * np.sin(ang))], 1).astype(np.int64)
+
+
+def test_binned_large_polygons_on_lattice_rows(pm, orc):
+    # polygons of 80 to 900 edges in the lookup: a comb (horizontal edges,
+    # vertices on shared rows), a zigzag two units high, a 300-vertex star and
+    # its reverse, and a 900-vertex spiky star whose edges each span much of
+    # its height; on a 1024 x 1024 box the lattice samples fall on vertex rows
+    # and edges often.  Bit-exact against the oracle with every polygon
+    # signed by the lookup (walk_ratio 0), then with the classification on
+    # (the large ones walked)
+    rng = np.random.default_rng(31)
+    zig = [(10 + 4 * i, 700 + (2 if i % 2 else 0)) for i in range(80)] + [(330, 699), (10, 699)]
+    star = dg.star_polygons(rng, [300], [[700, 300]], [200.0]).xy
+    polys = [_comb(40, 40, 60, 3, 100, 37), np.asarray(zig, dtype=np.int64), star, star[::-1],
+             _spiky(500, 600, 900, 380.0, 8.0, 3), _comb(600, 650, 20, 7, 5, 200)]
+    ps = dg.from_list(polys)
+    box = (0, 0, 1023, 1023)
+    k, cap = 64, 1 << 16
+    want = orc.sign(ps, box, 5, k, cap)
+    for horizon, bits, ratio in [(cap, 4, 0.0), (4096, 6, 0.0), (300, 2, 0.0), (4096, 6, 300.0)]:
+        got = _binned(pm, ps, box, 5, k, cap, horizon, bits, ratio, lds_edges=1024)
+        assert _first_diff(got, want) is None, (horizon, bits, ratio, _first_diff(got, want))
