@@ -69,8 +69,8 @@ def parse():
     ap.add_argument("--eval", type=int, default=1000, help="held-out queries for the reported recall")
     ap.add_argument("--rank-F-grid", type=lambda x: [int(v) for v in x.split(",")], default=[8, 10, 12, 16],
                     help="first-round sizes tried for the early stop (comma list)")
-    ap.add_argument("--rank-rounds", type=int, default=5,
-                    help="early-stop rounds (F, F, 2F, 4F, ...) before the finishing pass")
+    ap.add_argument("--rank-rounds-grid", type=lambda x: [int(v) for v in x.split(",")], default=[3, 4, 5],
+                    help="early-stop round counts tried (rounds of F, F, 2F, 4F, ... before the finishing pass)")
     ap.add_argument("--scorer-head", type=int, default=16, help="candidates per query the network re-scores")
     ap.add_argument("--only-headline", action="store_true", help="skip every secondary section")
     ap.add_argument("--trace-window", default=None,
@@ -192,18 +192,18 @@ def headline(args):
     for method in ("plain", "jhat", "scorer"):
         qb = QueryBatch(D5, sk, se, w5.box, w5.seed, k, cap, B, R, nq, w5.queries.xy.shape[0], cand_cap,
                         sign_config=cfgq, binned=par5, method=method, dsig=sig5, scorer=scorer, dfeat=dfeat,
-                        head=args.scorer_head, F=args.rank_F_grid[0], rounds=args.rank_rounds,
+                        head=args.scorer_head, F=args.rank_F_grid[0], rounds=args.rank_rounds_grid[-1],
                         margin=float("inf") if method == "plain" else 0.0)
         qb.load(w5.queries)
         margin, tried = float("inf"), []
         if method != "plain":
-            # per first-round size F: the smallest margin of the grid whose
-            # recall@10 on the calibration queries reaches the target plus a
-            # safety step (two standard errors of a 1,000-query recall near
-            # 0.95); the operating point is the (F, margin) whose captured
-            # batch replays fastest
-            for F in args.rank_F_grid:
-                qb.F = F
+            # per first-round size F and round count: the smallest margin of
+            # the grid whose recall@10 on the calibration queries reaches the
+            # target plus a safety step (two standard errors of a 1,000-query
+            # recall near 0.95); the operating point is the (F, rounds,
+            # margin) whose captured batch replays fastest
+            for F, rounds in [(f, r) for f in args.rank_F_grid for r in args.rank_rounds_grid]:
+                qb.F, qb.rounds = F, rounds
                 m_ok = None
                 for m in MARGINS:
                     qb.margin = m
@@ -223,9 +223,9 @@ def headline(args):
                     qb.run_graph()
                     qb.stream.synchronize()
                     ts.append(time.perf_counter() - t1)
-                tried.append({"F": F, "margin": m_ok, "ms": 1e3 * float(np.median(ts))})
+                tried.append({"F": F, "rounds": rounds, "margin": m_ok, "ms": 1e3 * float(np.median(ts))})
             best = min(tried, key=lambda x: x["ms"])
-            qb.F, margin = best["F"], best["margin"]
+            qb.F, qb.rounds, margin = best["F"], best["rounds"], best["margin"]
             qb.margin = margin
         qb.capture()
         for _ in range(args.warmup):
@@ -241,12 +241,13 @@ def headline(args):
         rec = metrics.recall_at_k(ti[evq], tj[evq], bi[evq], bj[evq], 10)
         cnt = qb.counts.cpu().numpy() if method != "plain" else np.array([n_cand, 0])
         stages = qb.run_instrumented()
-        methods[method] = {"margin": margin, "F": qb.F if method != "plain" else None, "operating_points": tried,
+        methods[method] = {"margin": margin, "F": qb.F if method != "plain" else None,
+                           "rounds": qb.rounds if method != "plain" else None, "operating_points": tried,
                            "recall_at_10": rec, "recall_queries": int(evq.size),
                            "queries_per_s": nq / dt, "ms_per_batch": 1e3 * dt,
                            "refined_pairs_per_query": float(cnt[0]) / nq, "finished_by_fallback": int(cnt[1]),
                            "stage_ms": stages}
-        log(f"{method}: margin {margin}, recall@10 {rec:.4f} on {evq.size} held-out queries, "
+        log(f"{method}: F {qb.F}, rounds {qb.rounds}, margin {margin}, recall@10 {rec:.4f} on {evq.size} held-out queries, "
             f"{1e3 * dt:.2f} ms per {nq}-query graph replay ({nq / dt:.3g} q/s), "
             f"{float(cnt[0]) / nq:.1f} refined pairs/query; stages " +
             ", ".join(f"{a} {b:.3f}" for a, b in stages.items()))
@@ -299,7 +300,7 @@ def headline(args):
                     f"k=256, cap 2^26; {nq:,} queries per captured-graph batch (2% jitter), "
                     f"{B} x {R} bands, learned scorer + early-stop refinement",
         "n_data": D5.n, "n_queries": nq, "k": k, "cap": cap, "bands": B, "rows": R,
-        "rank_rounds": args.rank_rounds, "scorer_head": args.scorer_head,
+        "scorer_head": args.scorer_head,
         "binned": {**par5, "lds_edges": cfgb.lds_edges},
         "candidates_per_query": n_cand / nq, "queries_over_4096_candidates": n_long, "index_ms": 1e3 * t_index,
         "sign_ms": 1e3 * t_sign, "sign_sig_per_s": D5.n * k / t_sign,

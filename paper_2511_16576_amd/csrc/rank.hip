@@ -114,14 +114,23 @@ __global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restr
         // a time, their eight 16-byte slices a lane loaded together
         constexpr int kU = 8;
         const bool in = 4 * lane < k;
+        // the candidate ids of a wavefront's next eight are loaded while the
+        // current eight's signatures are in flight
+        int32_t idn[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int i = min(wave * kU + u, n - 1);
+            idn[u] = n > 0 ? cand_ids[a + i] : 0;
+        }
         for (int i0 = wave * kU; i0 < n; i0 += nwave * kU) {
             uint4 pv[kU];
 #pragma unroll
             for (int u = 0; u < kU; u++) {
-                const int i = i0 + u < n ? i0 + u : n - 1;
-                const uint32_t *sp = dsig + (int64_t)cand_ids[a + i] * k;
+                const uint32_t *sp = dsig + (int64_t)idn[u] * k;
                 pv[u] = in ? *reinterpret_cast<const uint4 *>(sp + 4 * lane) : make_uint4(0, 0, 0, 0);
             }
+#pragma unroll
+            for (int u = 0; u < kU; u++) idn[u] = cand_ids[a + min(i0 + nwave * kU + u, n - 1)];
 #pragma unroll
             for (int u = 0; u < kU; u++) {
                 const int i = i0 + u;
