@@ -277,33 +277,45 @@ __global__ __launch_bounds__(256) void k_sparse(const uint64_t *__restrict__ ske
         const int total = __shfl(inc, 63, 64);
         if (lane == 63) base[64] = total;
         wave_lds_fence();
-        // every entry of the 64 buckets, one per lane per step: band lane
-        // tl of entry j is the last with base[tl] <= j
-        for (int j0 = 0; j0 < total; j0 += 64) {
-            const int j = j0 + lane;
-            bool ok = false;
-            int32_t id = 0;
-            if (j < total) {
-                int l = 0, h = 63;             // base[l] <= j < base[h + 1]
-                while (l < h) {
-                    const int mid = (l + h + 1) >> 1;
-                    if (base[mid] <= j) l = mid;
-                    else h = mid - 1;
+        // every entry of the 64 buckets, one per lane per step (band lane
+        // tl of entry j is the last with base[tl] <= j); the entries of
+        // kWalk steps are loaded before any is used, so the walk costs
+        // total / (64 kWalk) round trips to memory
+        constexpr int kWalk = 8;
+        for (int j00 = 0; j00 < total && !over; j00 += 64 * kWalk) {
+            int32_t ent[kWalk];
+            int band[kWalk];
+#pragma unroll
+            for (int u = 0; u < kWalk; u++) {
+                const int j = j00 + 64 * u + lane;
+                ent[u] = -1;
+                band[u] = 0;
+                if (j < total) {
+                    int l = 0, h = 63;         // base[l] <= j < base[h + 1]
+                    while (l < h) {
+                        const int mid = (l + h + 1) >> 1;
+                        if (base[mid] <= j) l = mid;
+                        else h = mid - 1;
+                    }
+                    ent[u] = sids[los[l] + (j - base[l])];   // entry p*b + t'
+                    band[u] = t0 + l;
                 }
-                const int32_t ent = sids[los[l] + (j - base[l])];   // entry p*b + t'
-                id = ent / b;
-                ok = ent - id * b == t0 + l;
             }
-            const uint64_t om = __ballot(ok);
-            const int n_new = __popcll(om);
-            if (cnt + n_new > cap) {
-                over = true;
-                break;
+#pragma unroll
+            for (int u = 0; u < kWalk; u++) {
+                const int32_t id = ent[u] >= 0 ? ent[u] / b : 0;
+                const bool ok = ent[u] >= 0 && ent[u] - id * b == band[u];
+                const uint64_t om = __ballot(ok);
+                const int n_new = __popcll(om);
+                if (cnt + n_new > cap) {       // wavefront-uniform
+                    over = true;
+                    break;
+                }
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+                if (ok) row[cnt + rank] = id;
+                cnt += n_new;
             }
-            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
-            if (ok) row[cnt + rank] = id;
-            cnt += n_new;
         }
         wave_lds_fence();                      // base/los are rewritten by the next band chunk
     }
