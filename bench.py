@@ -74,8 +74,9 @@ def parse():
     ap.add_argument("--scorer-head", type=int, default=16, help="candidates per query the network re-scores")
     ap.add_argument("--only-headline", action="store_true", help="skip every secondary section")
     ap.add_argument("--trace-window", default=None,
-                    help="comma list of methods (plain, jhat, scorer): after the headline, --trace-replays "
-                         "replays of each method's graph between marker kernels (windowed rocprofv3 summaries)")
+                    help="comma list of methods (plain, jhat, scorer) or dsign (the dataset's binned signing): "
+                         "after the headline, --trace-replays replays of each between marker kernels "
+                         "(windowed rocprofv3 summaries)")
     ap.add_argument("--trace-replays", type=int, default=5)
     ap.add_argument("--bands", type=int, default=32)
     ap.add_argument("--rows", type=int, default=4)
@@ -288,13 +289,24 @@ def headline(args):
         torch.cuda._sleep(1000)              # marker kernel: the first window opens
         torch.cuda.synchronize()
         for name in args.trace_window.split(","):
-            qb = batches[name]
-            for _ in range(args.trace_replays):
-                qb.run_graph()
-            qb.stream.synchronize()
+            if name == "dsign":
+                # the dataset's binned signing (bins drawn each call), as timed above
+                wst = torch.empty(pm.sign_binned_workspace_size(D5.n, k, cap, h5, bb5, cfgb), dtype=torch.uint8,
+                                  device=dev)
+                sgt = torch.empty_like(sig5)    # allocations launch no kernels
+                for _ in range(args.trace_replays):
+                    pm.sign_binned(D5, w5.box, w5.seed, k, cap, horizon=h5, bin_bits=bb5, config=cfgb, out=sgt,
+                                   ws=wst)
+            else:
+                qb = batches[name]
+                for _ in range(args.trace_replays):
+                    qb.run_graph()
+                qb.stream.synchronize()
             torch.cuda._sleep(1000)          # marker kernel: this window closes, the next opens
             torch.cuda.synchronize()
-            log(f"traced {args.trace_replays} replays of the {name} batch between marker kernels")
+            if name == "dsign":
+                del wst, sgt
+            log(f"traced {args.trace_replays} replays of the {name} step between marker kernels")
     out = {
         "workload": "workload 5: 4,000,000 star polygons, Pareto(1.5) 8-8192 vertices, R 0.5-3% of a 2^24 grid; "
                     f"k=256, cap 2^26; {nq:,} queries per captured-graph batch (2% jitter), "

@@ -118,7 +118,7 @@ struct LookupArgs {
     const uint16_t *cell_off;
     uint32_t *sig;
     uint32_t *unresolved;          // [n] 1: a hash needs the walk, 2: the whole polygon is walked
-    const int32_t *order;          // [n] polygons, longest lookups first
+    const int32_t *order;          // [n] polygons, longest lookups first (null: index order)
     int64_t n;
     int32_t k;
     uint32_t cap, horizon;
@@ -311,8 +311,9 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int per = blockDim.x;
     const int groups = (A.k + per - 1) / per;
-    // workgroups start in order of their index: the order puts the longest first
-    const int64_t p = A.order[blockIdx.x / groups];
+    // workgroups start in order of their index: the order (small launches)
+    // puts the longest first
+    const int64_t p = A.order ? (int64_t)A.order[blockIdx.x / groups] : (int64_t)(blockIdx.x / groups);
     const int i = (int)(blockIdx.x % groups) * per + tid;
     const bool active = i < A.k;
     if (A.unresolved[p] & 2u) return;    // walked (uniform per workgroup, before any barrier)
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(256) void k_bin_lookup(LookupArgs A)
 // arrival order, which affects only timing).  Walked and degenerate
 // polygons, whose workgroups return at once, go last.
 constexpr int kOrderCells = 4096;
+constexpr int64_t kOrderMaxPolys = 65536;
 
 __global__ __launch_bounds__(256) void k_order_count(const int64_t *__restrict__ area2,
                                                      const int64_t *__restrict__ off,
@@ -618,14 +620,19 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
                        (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), walk_edges,
                        w.unresolved);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(w.count), (int64_t)1);
-    // the lookup's dispatch order (after the classification: walked polygons last)
-    hipLaunchKernelGGL(k_zero_words, dim3(kOrderCells / 256), dim3(256), 0, s,
-                       reinterpret_cast<uint32_t *>(w.cell_counts), (int64_t)kOrderCells);
-    hipLaunchKernelGGL(k_order_count, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.off, L.mbr, w.unresolved, L.n,
-                       (double)wx * (double)wy, (double)((int64_t)1 << lchunk), (double)nchunks, w.key,
-                       w.cell_counts);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, w.cell_counts);
-    hipLaunchKernelGGL(k_order_scatter, dim3(grid_for(L.n)), dim3(256), 0, s, w.key, L.n, w.cell_counts, w.order);
+    // the lookup's dispatch order (after the classification: walked polygons
+    // last), in small launches only: there a few costly polygons started
+    // late set the duration; a large launch hides them behind the rest
+    const bool ordered = L.n <= kOrderMaxPolys;
+    if (ordered) {
+        hipLaunchKernelGGL(k_zero_words, dim3(kOrderCells / 256), dim3(256), 0, s,
+                           reinterpret_cast<uint32_t *>(w.cell_counts), (int64_t)kOrderCells);
+        hipLaunchKernelGGL(k_order_count, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.off, L.mbr, w.unresolved, L.n,
+                           (double)wx * (double)wy, (double)((int64_t)1 << lchunk), (double)nchunks, w.key,
+                           w.cell_counts);
+        hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, s, w.cell_counts);
+        hipLaunchKernelGGL(k_order_scatter, dim3(grid_for(L.n)), dim3(256), 0, s, w.key, L.n, w.cell_counts, w.order);
+    }
     polymh_status st0 = check_launch("sign_binned: order");
     if (st0) return st0;
     LookupArgs A{};
@@ -638,7 +645,7 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     A.cell_off = w.cell_off;
     A.sig = L.sig;
     A.unresolved = w.unresolved;
-    A.order = w.order;
+    A.order = ordered ? w.order : nullptr;
     A.n = L.n;
     A.k = L.k;
     A.cap = L.cap;
