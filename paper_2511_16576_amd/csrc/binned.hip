@@ -466,12 +466,13 @@ __global__ __launch_bounds__(256) void k_order_scatter(const uint16_t *__restric
 // probability P = 1 - exp(-C area / |B|)) and tests every sample of them
 // that lies in the MBR, about max(1, C A_mbr / |B|) a chunk, against its n
 // edges.  Either way the signature is the same.  A polygon beyond the
-// lookup's LDS edge cache (walk_edges), or whose lookup would test more than
-// kLookupTestCap edges a hash, is walked too: one lookup workgroup tests its
-// 256 hashes' points with four wavefronts, a long serial run that sets the
-// launch's duration, where the walk spreads a polygon's hashes over many
-// work items and each test over the lanes.  Degenerate polygons stay with
-// the lookup, which signs them 0 at once.
+// lookup's LDS edge cache (walk_edges) is walked too, and in a small launch
+// so is one whose lookup would test more than test_cap edges a hash: one
+// lookup workgroup tests its 256 hashes' points with four wavefronts, a
+// long serial run that sets a small launch's duration, where the walk
+// spreads a polygon's hashes over many work items and each test over the
+// lanes.  Degenerate polygons stay with the lookup, which signs them 0 at
+// once.
 constexpr double kDrawTests = 5.0;
 constexpr double kLookupTestCap = 2048.0;
 
@@ -480,7 +481,8 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ ar
                                                   const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ mbr, int64_t n,
                                                   double box_area, double walk_ratio, double chunk,
-                                                  double walk_edges, uint32_t *__restrict__ unresolved)
+                                                  double walk_edges, double test_cap,
+                                                  uint32_t *__restrict__ unresolved)
 {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const bool degenerate = (flags[p] & (kFlagFew | kFlagCollinear)) != 0;
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(256) void k_classify(const int64_t *__restrict__ ar
             const double hit = -expm1(-chunk * area / box_area);         // P(a chunk has a hit)
             const double bin_cost = edges * fmax(1.0, chunk * a_mbr / box_area) / hit;
             walk = box_area < walk_ratio * area || walk_cost < bin_cost || edges > walk_edges ||
-                   bin_cost > kLookupTestCap;
+                   bin_cost > test_cap;
         }
         unresolved[p] = walk ? 2u : 0u;
     }
@@ -616,14 +618,15 @@ polymh_status launch_sign_binned(const SignLaunch &L, const int64_t *area2, uint
     const int64_t per = 64 * waves, groups = (L.k + per - 1) / per;
     const int64_t units = L.n * groups;
     const double walk_edges = (double)L.cfg.lds_edges;
+    // the order and the cap on a lookup's tests serve small launches, where a
+    // few costly polygons set the duration; a large launch hides them
+    const bool ordered = L.n <= kOrderMaxPolys;
     hipLaunchKernelGGL(k_classify, dim3(grid_for(L.n)), dim3(256), 0, s, area2, L.flags, L.off, L.mbr, L.n,
                        (double)wx * (double)wy, walk_ratio, (double)((int64_t)1 << lchunk), walk_edges,
-                       w.unresolved);
+                       ordered ? kLookupTestCap : INFINITY, w.unresolved);
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(w.count), (int64_t)1);
     // the lookup's dispatch order (after the classification: walked polygons
-    // last), in small launches only: there a few costly polygons started
-    // late set the duration; a large launch hides them behind the rest
-    const bool ordered = L.n <= kOrderMaxPolys;
+    // last), in small launches only
     if (ordered) {
         hipLaunchKernelGGL(k_zero_words, dim3(kOrderCells / 256), dim3(256), 0, s,
                            reinterpret_cast<uint32_t *>(w.cell_counts), (int64_t)kOrderCells);
