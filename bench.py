@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--rank-rounds-grid", type=lambda x: [int(v) for v in x.split(",")], default=[3, 4, 5],
                     help="early-stop round counts tried (rounds of F, F, 2F, 4F, ... before the finishing pass)")
     ap.add_argument("--scorer-head", type=int, default=16, help="candidates per query the network re-scores")
+    ap.add_argument("--head-parts", type=int, default=4,
+                    help="sub-batches of the ranked methods' batch run concurrently in its graph (streams forked "
+                         "inside)")
+    ap.add_argument("--plain-parts", type=int, default=1,
+                    help="sub-batches of the plain pipeline's batch (refinement-bound: 1 replays fastest)")
     ap.add_argument("--only-headline", action="store_true", help="skip every secondary section")
     ap.add_argument("--trace-window", default=None,
                     help="comma list of methods (plain, jhat, scorer) or dsign (the dataset's binned signing): "
@@ -111,7 +116,7 @@ def headline(args):
     from paper_2511_16576_amd import metrics
     from paper_2511_16576_amd import polymh as pm
     from paper_2511_16576_amd import scorer as sc
-    from paper_2511_16576_amd.pipeline import QueryBatch
+    from paper_2511_16576_amd.pipeline import SplitBatch
     dev = torch.device("cuda")
     st = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -191,10 +196,11 @@ def headline(args):
     methods = {}
     batches = {}
     for method in ("plain", "jhat", "scorer"):
-        qb = QueryBatch(D5, sk, se, w5.box, w5.seed, k, cap, B, R, nq, w5.queries.xy.shape[0], cand_cap,
-                        sign_config=cfgq, binned=par5, method=method, dsig=sig5, scorer=scorer, dfeat=dfeat,
-                        head=args.scorer_head, F=args.rank_F_grid[0], rounds=args.rank_rounds_grid[-1],
-                        margin=float("inf") if method == "plain" else 0.0)
+        qb = SplitBatch(D5, sk, se, w5.box, w5.seed, k, cap, B, R, nq, w5.queries.xy.shape[0], cand_cap,
+                        parts=args.plain_parts if method == "plain" else args.head_parts, sign_config=cfgq,
+                        binned=par5, method=method, dsig=sig5,
+                        scorer=scorer, dfeat=dfeat, head=args.scorer_head, F=args.rank_F_grid[0],
+                        rounds=args.rank_rounds_grid[-1], margin=float("inf") if method == "plain" else 0.0)
         qb.load(w5.queries)
         margin, tried = float("inf"), []
         if method != "plain":
@@ -257,33 +263,36 @@ def headline(args):
     # exact J of every candidate as its score (a perfect predictor; margin 0
     # then returns the exact top-10 of the candidates), against the
     # collision fraction's, at the collision fraction's first-round size
-    qj = batches["jhat"]
-    qj.run_eager()
-    qj.result()
-    n_c = int(qj.cand_off[-1].item())
-    Jx = pm.refine(D5, qj.Q, qj.cand_off, qj.cand_ids[:n_c])
-    sx = Jx.float().contiguous()
-    ox = torch.empty_like(qj.order)
-    okx = torch.empty_like(qj.sorted_ok)
-    pm.rank_order(qj.cand_off, sx, ox, okx)
-    ceiling = {}
-    for name, (sc_, od_, ok_, mg) in {"collision_fraction": (qj.score, qj.order, qj.sorted_ok, qj.margin),
-                                      "exact_j": (sx, ox, okx, 0.0)}.items():
-        ts = []
-        for _ in range(4):
-            e0, e1 = ev(), ev()
-            e0.record(st)
-            _, _, cnt_ = pm.rank_refine_ordered(D5, qj.Q, qj.cand_off, qj.cand_ids, sc_, od_, ok_, topk=10, F=qj.F,
-                                                rounds=qj.rounds, margin=mg, ws=qj.ws_rank)
-            e1.record(st)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ceiling[name] = {"rank_refine_ms": float(np.median(ts[1:])),
-                         "refined_pairs_per_query": float(cnt_[0].item()) / nq}
+    # (per sub-batch, one after another; times and pairs added)
+    qjs = batches["jhat"]
+    qjs.run_eager()
+    qjs.result()
+    ceiling = {"collision_fraction": {"rank_refine_ms": 0.0, "refined_pairs_per_query": 0.0},
+               "exact_j": {"rank_refine_ms": 0.0, "refined_pairs_per_query": 0.0}}
+    for qj in qjs.parts:
+        n_c = int(qj.cand_off[-1].item())
+        Jx = pm.refine(D5, qj.Q, qj.cand_off, qj.cand_ids[:n_c])
+        sx = Jx.float().contiguous()
+        ox = torch.empty_like(qj.order)
+        okx = torch.empty_like(qj.sorted_ok)
+        pm.rank_order(qj.cand_off, sx, ox, okx)
+        for name, (sc_, od_, ok_, mg) in {"collision_fraction": (qj.score, qj.order, qj.sorted_ok, qj.margin),
+                                          "exact_j": (sx, ox, okx, 0.0)}.items():
+            ts = []
+            for _ in range(4):
+                e0, e1 = ev(), ev()
+                e0.record(st)
+                _, _, cnt_ = pm.rank_refine_ordered(D5, qj.Q, qj.cand_off, qj.cand_ids, sc_, od_, ok_, topk=10,
+                                                    F=qj.F, rounds=qj.rounds, margin=mg, ws=qj.ws_rank)
+                e1.record(st)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ceiling[name]["rank_refine_ms"] += float(np.median(ts[1:]))
+            ceiling[name]["refined_pairs_per_query"] += float(cnt_[0].item()) / nq
+        del Jx, sx, ox, okx
     log("ranked refinement, collision fraction vs exact J as the score: " +
         ", ".join(f"{k} {v['rank_refine_ms']:.3f} ms ({v['refined_pairs_per_query']:.1f} pairs/query)"
                   for k, v in ceiling.items()))
-    del Jx, sx, ox, okx
     if args.trace_window:
         torch.cuda.synchronize()
         torch.cuda._sleep(1000)              # marker kernel: the first window opens
@@ -309,10 +318,11 @@ def headline(args):
             log(f"traced {args.trace_replays} replays of the {name} step between marker kernels")
     out = {
         "workload": "workload 5: 4,000,000 star polygons, Pareto(1.5) 8-8192 vertices, R 0.5-3% of a 2^24 grid; "
-                    f"k=256, cap 2^26; {nq:,} queries per captured-graph batch (2% jitter), "
+                    f"k=256, cap 2^26; {nq:,} queries per captured-graph batch (2% jitter; ranked methods as "
+                    f"{args.head_parts} sub-batches on streams forked inside the graph), "
                     f"{B} x {R} bands, learned scorer + early-stop refinement",
         "n_data": D5.n, "n_queries": nq, "k": k, "cap": cap, "bands": B, "rows": R,
-        "scorer_head": args.scorer_head,
+        "scorer_head": args.scorer_head, "sub_batches": args.head_parts, "plain_sub_batches": args.plain_parts,
         "binned": {**par5, "lds_edges": cfgb.lds_edges},
         "candidates_per_query": n_cand / nq, "queries_over_4096_candidates": n_long, "index_ms": 1e3 * t_index,
         "sign_ms": 1e3 * t_sign, "sign_sig_per_s": D5.n * k / t_sign,
@@ -373,29 +383,33 @@ def bin_lookup_bytes(Q, qsig, box, horizon, bits, walk_ratio, lds_edges):
 
 
 def stage_roofline(state, methods):
-    """Rooflines of the learned step's heaviest stages (HIP-event stage times
-    of an instrumented eager run on the batch's stream)."""
+    """Rooflines of the learned step's heaviest stages.  The batch runs as
+    sub-batches, each with its own launch of every kernel: per launch, the
+    algorithmic work of a sub-batch over its HIP-event stage time (one
+    instrumented eager run of each sub-batch on its stream, alone on the
+    GPU), averaged over the sub-batches."""
     qb = state["batches"]["scorer"]
-    st = methods["scorer"]["stage_ms"]
-    C = float(qb.cand_off[-1].item())
-    nq, k = qb.nq, qb.k
+    parts, sts = qb.parts, qb.parts_stage_ms
+    k = parts[0].k
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic_workload5.json")
     rl = {}
     # k_rank_jhat_sort: an HBM-bound gather: each candidate's data signature
     # (4k bytes) and id (4 B) read, its score and order written (8 B); per
     # query its signature and offsets
-    by = C * (4.0 * k + 12.0) + nq * (4.0 * k + 16.0)
-    t = st["jhat_order"] / 1e3
+    Cs = [float(p.cand_off[-1].item()) for p in parts]
+    by = float(np.mean([c * (4.0 * k + 12.0) + p.nq * (4.0 * k + 16.0) for c, p in zip(Cs, parts)]))
+    t = float(np.mean([st["jhat_order"] for st in sts])) / 1e3
     rl["k_rank_jhat_sort"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
                               "frac": by / t / 8e12, "traffic": _committed_traffic(tpath, "k_rank_jhat_sort"),
                               "traffic_unit": "bytes per launch", "kernel": "k_rank_jhat_sort",
-                              "launch_ms": 1e3 * t, "bytes_per_launch": by, "candidates": C}
+                              "launch_ms": 1e3 * t, "bytes_per_launch": by,
+                              "candidates_per_launch": float(np.mean(Cs)), "launches_per_step": len(parts)}
     # k_bin_lookup (query signing from the shared binned samples): bytes of
     # the samples each (query, hash) visits; the stage also holds the walk of
     # the polygons left to it (k_sign), so its time bounds the kernel's
-    by = bin_lookup_bytes(qb.Q, qb.sig, qb.box, qb.binned["horizon"], qb.binned["bin_bits"],
-                          qb.binned.get("walk_ratio", 300.0), qb.cfg.lds_edges)
-    t = st["qsign"] / 1e3
+    by = float(np.mean([bin_lookup_bytes(p.Q, p.sig, p.box, p.binned["horizon"], p.binned["bin_bits"],
+                                         p.binned.get("walk_ratio", 300.0), p.cfg.lds_edges) for p in parts]))
+    t = float(np.mean([st["qsign"] for st in sts])) / 1e3
     rl["k_bin_lookup"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
                           "frac": by / t / 8e12, "traffic": _committed_traffic(tpath, "k_bin_lookup"),
                           "traffic_unit": "bytes per launch", "kernel": "k_bin_lookup",
@@ -405,9 +419,8 @@ def stage_roofline(state, methods):
     # k_score_pairs (fused scorer inference): matrix-core FLOPs of the two
     # hidden layers, 2 (288 x 256 + 256 x 256) per pair row, head rows of
     # every query (empty slots included: whole tiles run)
-    rows = float(nq * qb.head)
-    fl = rows * 2.0 * (288 * 256 + 256 * 256)
-    t = st["scorer"] / 1e3
+    fl = float(np.mean([p.nq * p.head * 2.0 * (288 * 256 + 256 * 256) for p in parts]))
+    t = float(np.mean([st["scorer"] for st in sts])) / 1e3
     rl["k_score_pairs"] = {"bound": "mfma", "achieved": fl / t / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                            "frac": fl / t / 2.5e15, "traffic": _committed_traffic(tpath, "k_score_pairs"),
                            "traffic_unit": "bytes per launch", "kernel": "k_score_pairs", "launch_ms": 1e3 * t,

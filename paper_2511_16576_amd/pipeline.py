@@ -186,3 +186,98 @@ class QueryBatch:
         if int(self.overflow.item()):
             raise RuntimeError("candidate capacity exceeded; rebuild the batch with a larger cand_cap")
         return self.top_ids, self.top_j
+
+
+class SplitBatch:
+    """A batch of ``n_queries`` queries run as ``parts`` sub-batches of
+    consecutive queries, each a ``QueryBatch`` with its own buffers and
+    stream.  The captured graph forks from the first part's stream onto the
+    others with events and joins back, so the parts' kernels run
+    concurrently: a part's stages are bound by different things (latency
+    chains and their tails in the signing, the lookup's sorts and the
+    refinement rounds; HBM in the collision-fraction order), and the other
+    parts' work fills the gaps.  Every query's result is the one the whole
+    batch gives (the stages treat queries independently); ``result`` and
+    ``counts`` concatenate and add the parts'."""
+
+    def __init__(self, D, sorted_keys, sorted_ent, box, seed, k, cap, bands, rows, n_queries, max_vertices,
+                 cand_cap, parts: int = 4, **kw):
+        if not 1 <= parts <= n_queries:
+            raise ValueError("parts must be between 1 and the number of queries")
+        cuts = np.linspace(0, n_queries, parts + 1).round().astype(np.int64)
+        self.bounds = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]
+        self.parts = [QueryBatch(D, sorted_keys, sorted_ent, box, seed, k, cap, bands, rows, b - a, max_vertices,
+                                 cand_cap, **kw) for a, b in self.bounds]
+        self.nq, self.method = n_queries, self.parts[0].method
+        self.stream = self.parts[0].stream
+        self.graph = None
+
+    # early-stop parameters, set on every part
+    def _get(self, name):
+        return getattr(self.parts[0], name)
+
+    def _set(self, name, v):
+        for p in self.parts:
+            setattr(p, name, v)
+
+    F = property(lambda self: self._get("F"), lambda self, v: self._set("F", v))
+    rounds = property(lambda self: self._get("rounds"), lambda self, v: self._set("rounds", v))
+    margin = property(lambda self: self._get("margin"), lambda self, v: self._set("margin", v))
+
+    def load(self, polys):
+        assert polys.n == self.nq, "a batch has a fixed number of queries"
+        for p, (a, b) in zip(self.parts, self.bounds):
+            p.load(polys.subset(np.arange(a, b)))
+
+    def _wait_all(self):
+        for p in self.parts:
+            p.stream.synchronize()
+
+    def run_eager(self):
+        for p in self.parts:
+            with torch.cuda.stream(p.stream):
+                p._issue()
+        self._wait_all()
+
+    def run_instrumented(self) -> dict:
+        """The parts run one after another with events after every stage:
+        each stage's milliseconds summed over the parts (GPU time, not the
+        concurrent replay's wall time); the parts' own tables are kept in
+        ``parts_stage_ms``."""
+        self.parts_stage_ms = [p.run_instrumented() for p in self.parts]
+        tot = {}
+        for st in self.parts_stage_ms:
+            for name, ms in st.items():
+                tot[name] = tot.get(name, 0.0) + ms
+        return tot
+
+    def capture(self):
+        pm.check_device()
+        self.run_eager()                     # first run outside the graph
+        s0 = self.stream
+
+        def issue():
+            fork = torch.cuda.Event()
+            fork.record(s0)
+            for p in self.parts[1:]:
+                p.stream.wait_event(fork)
+            for p in self.parts:
+                with torch.cuda.stream(p.stream):
+                    p._issue()
+            for p in self.parts[1:]:
+                join = torch.cuda.Event()
+                join.record(p.stream)
+                s0.wait_event(join)
+        self.graph = pm.capture(issue, s0)
+        return self.graph
+
+    def run_graph(self):
+        self.graph.launch()
+
+    def result(self):
+        res = [p.result() for p in self.parts]
+        return torch.cat([r[0] for r in res]), torch.cat([r[1] for r in res])
+
+    @property
+    def counts(self):
+        return sum(p.counts for p in self.parts)

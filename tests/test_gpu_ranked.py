@@ -249,3 +249,45 @@ def test_ranked_batch_graph_equals_eager(pm, setup, method):
                 assert all(lst[x] == y for x, y in got), q
                 assert got == sorted(got, key=lambda t: (-t[1], t[0])), q
         del qb
+
+
+@pytest.mark.parametrize("method,parts", [("plain", 3), ("jhat", 4), ("scorer", 2)])
+def test_split_batch_equals_whole(pm, setup, method, parts):
+    """The batch run as sub-batches of consecutive queries on their own
+    streams, forked inside one captured graph: every replay (eager work of
+    the program between them) and the eager run give the whole batch's
+    top-10, and the early stop's counts add up to the whole batch's."""
+    import torch
+    from paper_2511_16576_amd import scorer as sc
+    from paper_2511_16576_amd.pipeline import QueryBatch, SplitBatch
+    w, D = setup["w"], setup["D"]
+    feats = pm.poly_features(D, w.box)
+    s = sc.init_scorer(0)
+    cap = int(setup["ids"].numel()) * 2 + 1024
+    common = dict(box=w.box, seed=0, k=256, cap=w.cap, bands=64, rows=4, n_queries=w.queries.n,
+                  max_vertices=w.queries.xy.shape[0], cand_cap=cap, method=method, dsig=setup["sig"], scorer=s,
+                  dfeat=feats, head=16, F=4, rounds=3, margin=float("inf") if method == "plain" else 0.02)
+    whole = QueryBatch(D, setup["sk"], setup["se"], **common)
+    whole.load(w.queries)
+    whole.run_eager()
+    w_ids, w_j = (x.clone() for x in whole.result())
+    split = SplitBatch(D, setup["sk"], setup["se"], parts=parts, **common)
+    sizes = [b - a for a, b in split.bounds]
+    assert split.bounds[0][0] == 0 and split.bounds[-1][1] == w.queries.n and max(sizes) - min(sizes) <= 1
+    assert all(split.bounds[i][1] == split.bounds[i + 1][0] for i in range(parts - 1))
+    split.load(w.queries)
+    split.run_eager()
+    e_ids, e_j = split.result()
+    assert torch.equal(e_ids, w_ids) and torch.equal(e_j, w_j)
+    if method != "plain":
+        assert torch.equal(split.counts, whole.counts)
+    split.capture()
+    for rep in range(3):
+        for p in split.parts:
+            p.top_ids.fill_(-7)
+        torch.cuda.synchronize()
+        split.run_graph()
+        g_ids, g_j = split.result()
+        assert torch.equal(g_ids, w_ids) and torch.equal(g_j, w_j), rep
+        pm.refine(D, whole.Q, whole.cand_off, whole.cand_ids, n_cand=whole.cand_ids.numel())
+        torch.cuda.synchronize()
