@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--plain-parts", type=int, default=1,
                     help="sub-batches of the plain pipeline's batch (refinement-bound: 1 replays fastest)")
     ap.add_argument("--only-headline", action="store_true", help="skip every secondary section")
+    ap.add_argument("--only-secondary", action="store_true",
+                    help="skip the headline (profiling runs of the secondary sections; no bench line)")
     ap.add_argument("--trace-window", default=None,
                     help="comma list of methods (plain, jhat, scorer) or dsign (the dataset's binned signing): "
                          "after the headline, --trace-replays replays of each between marker kernels "
@@ -680,7 +682,7 @@ def secondary(args, hstate):
         binned = {"workload2": {"walk_ms": None, "binned_ms": 1e3 * t_b2,
                                 "binned_sig_per_s": D.n * k / t_b2, "params": par2}}
         log(f"binned signing, workload 2: {1e3 * t_b2:.3f} ms")
-    if binned is not None and not args.no_walk5:
+    if binned is not None and not args.no_walk5 and hstate is not None:
         # Alg. 1's walk of all 4,000,000 workload-5 polygons against the
         # headline's binned signatures (bit-equality checked here)
         w5, D5, sig5, par5 = hstate["w5"], hstate["D5"], hstate["sig5"], hstate["par5"]
@@ -1044,6 +1046,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("copied 256 MiB device-to-device (counter reference)")
+    if args.only_secondary:
+        # profiling runs of the secondary sections alone (no headline
+        # dispatches mixed into their kernels' counters)
+        sec = secondary(args, None)
+        print(json.dumps({"secondary": {x: y for x, y in sec.items() if x != "roofline_kernels"},
+                          "roofline_kernels": sec.get("roofline_kernels", {})}), flush=True)
+        return
     head, hstate = headline(args)
     roofs = stage_roofline(hstate, head["methods"])
     # the heaviest single kernel of the step (the signing stage's time holds
