@@ -373,10 +373,16 @@ polymh_status polymh_topk(const int64_t *cand_off, const int32_t *cand_ids, cons
  * Graph capture (batching form): record the stream-ordered libpolymh calls a
  * caller issues on `stream` between polymh_graph_begin and polymh_graph_end
  * into a HIP graph, then replay it with polymh_graph_launch (same buffers,
- * new contents).  Calls that synchronise (polymh_box_of, polymh_query with a
- * capacity check, polymh_rank_refine) must not be captured; use
- * polymh_query_capped and polymh_rank_refine_ordered.  The handle is owned by the caller and released by
- * polymh_graph_destroy. */
+ * new contents).  Other streams join the capture by waiting on an event
+ * recorded on `stream` (and must be joined back the same way before
+ * polymh_graph_end); their branches run concurrently on replay.  The capture
+ * is thread-local: calls from other threads are not recorded.  Calls that
+ * synchronise (polymh_box_of, polymh_query with a capacity check,
+ * polymh_rank_refine) must not be captured; use polymh_query_capped and
+ * polymh_rank_refine_ordered.  The handle is owned by the caller and
+ * released by polymh_graph_destroy.  Errors: POLYMH_EINVAL for a null
+ * stream or output, POLYMH_EDEVICE when HIP refuses the capture, its end or
+ * the instantiation (nothing is then returned). */
 typedef struct polymh_graph_t *polymh_graph;
 polymh_status polymh_graph_begin(void *stream);
 polymh_status polymh_graph_end(void *stream, polymh_graph *out_host);

@@ -1,6 +1,9 @@
-// HIP graph capture of a caller's sequence of libpolymh calls on one stream
+// HIP graph capture of a caller's sequence of libpolymh calls on a stream
 // (the batched query pipeline is captured once and replayed per batch, so
-// the dozens of small launches cost one graph launch).
+// the dozens of small launches cost one graph launch).  Streams that wait
+// on an event recorded on the capturing stream join the capture, so a
+// caller can fork work onto several streams and join it back: their
+// branches run concurrently when the graph is replayed.
 #include "internal.hpp"
 
 #include <new>
@@ -29,7 +32,7 @@ polymh_status polymh_graph_end(void *stream, polymh_graph *out)
     hipError_t e = hipStreamEndCapture(reinterpret_cast<hipStream_t>(stream), &g->graph);
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        if (g->graph) hipGraphDestroy(g->graph);
+        if (g->graph) (void)hipGraphDestroy(g->graph);   // the capture's error is the one reported
         delete g;
         return polymh::set_error(POLYMH_EDEVICE, "graph_end: %s", hipGetErrorString(e));
     }
@@ -48,8 +51,9 @@ polymh_status polymh_graph_launch(polymh_graph g, void *stream)
 void polymh_graph_destroy(polymh_graph g)
 {
     if (!g) return;
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
+    // a destroy call has no caller to report to
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
 }
 
