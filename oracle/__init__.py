@@ -6,6 +6,8 @@ the paper.  Only the test suite, the package's smoke check and the CPU
 baseline leg of the benchmark may import this package.  It shares no code
 with the GPU library, and the GPU library never imports it.
 
-Parity status per function is listed in ``oracle.core``'s docstring.
+Parity status per function is listed in the docstrings of ``oracle.core``,
+``oracle.mlp``, ``oracle.rings``, ``oracle.centre`` and ``oracle.ranked``.
 """
 from .core import *  # noqa: F401,F403
+from .ranked import *  # noqa: F401,F403
