@@ -190,6 +190,79 @@ def test_ordered_refine_exact_scores(pm, setup):
     assert int(cnt2.cpu().numpy()[1]) == int((nc > 4).sum())
 
 
+def _assert_top_equal(got_ids, got_j, want_ids, want_j, ctx):
+    """Top-k rows equal: J within the refinement tolerance, ids exactly
+    except where two candidates' exact J tie within it (either order is
+    correct then)."""
+    assert np.allclose(got_j, want_j, rtol=1e-9, atol=1e-12), ctx
+    k = want_ids.shape[1]
+    for q in range(want_ids.shape[0]):
+        live = got_ids[q][got_ids[q] >= 0]
+        assert np.unique(live).size == live.size, (ctx, q)
+        for t in np.flatnonzero(got_ids[q] != want_ids[q]):
+            tied = np.isclose(want_j[q], want_j[q, t], rtol=1e-9, atol=1e-12).sum()
+            assert want_ids[q, t] >= 0 and (tied >= 2 or t == k - 1), (ctx, q, t)
+
+
+@pytest.fixture(scope="module")
+def oracle_j(setup):
+    """The oracle's exact J of every candidate, its collision fractions (from
+    its own signatures) as FP32 predictions."""
+    o, i = setup["off"].cpu().numpy(), setup["ids"].cpu().numpy()
+    i = i[:o[-1]]
+    w = setup["w"]
+    J = oracle.jaccard_candidates(w.data, w.queries, o, i)
+    pred = np.concatenate([oracle.collision_fraction(setup["oqsig"][q], setup["osig"][i[o[q]:o[q + 1]]])
+                           for q in range(o.size - 1)]).astype(np.float32)
+    return o, i, J, pred
+
+
+@pytest.mark.parametrize("F,rounds,margin", [(4, 3, 0.01), (8, 4, 0.0), (2, 5, -0.02), (16, 2, 0.05),
+                                             (3, 1, 0.0), (1, 0, 0.0)])
+def test_ordered_refine_equals_oracle_early_stop(pm, setup, oracle_j, F, rounds, margin):
+    """The device-driven early stop, ordered by the fused collision fraction,
+    against the oracle's best-first refinement with early stop on its own
+    collision fractions and exact J: top-10 ids and J, pairs refined and
+    queries the finishing pass completed.  Every stop decision of the oracle
+    is at least 1e-6 from the other outcome, so the refinement tolerance
+    cannot flip one."""
+    o, i, J, pred = oracle_j
+    off, ids = setup["off"], setup["ids"]
+    score, order, ok = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
+    assert np.array_equal(score.cpu().numpy()[:i.size], pred)
+    want = oracle.early_stop_topk(o, i, pred, J, 10, F, rounds, margin)
+    assert want["min_gap"] > 1e-6
+    t_ids, t_j, cnt = pm.rank_refine_ordered(setup["D"], setup["Q"], off, ids, score, order, ok, topk=10, F=F,
+                                             rounds=rounds, margin=margin)
+    _assert_top_equal(t_ids.cpu().numpy(), t_j.cpu().numpy(), want["top_ids"], want["top_j"], (F, rounds, margin))
+    c = cnt.cpu().numpy()
+    assert c[0] == want["refined"] and c[1] == want["finished"], (c, want["refined"], want["finished"])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ordered_refine_other_predictions_equals_oracle(pm, setup, oracle_j, seed):
+    """Predictions that are not collision fractions (as the scorer writes
+    them; coarse values, so many ties broken by position): ordered by
+    polymh_rank_order, refined with early stop, against the oracle."""
+    import torch
+    o, i, J, _ = oracle_j
+    off, ids = setup["off"], setup["ids"]
+    rng = np.random.default_rng(seed)
+    pred = (rng.integers(0, 48, i.size) / 64).astype(np.float32)
+    score = torch.from_numpy(pred).cuda()
+    order = torch_empty_like_int(ids)
+    ok = torch_empty_u8(setup["Q"].n)
+    pm.rank_order(off, score, order, ok)
+    for F, rounds, margin in ((4, 3, 0.05), (6, 4, -0.1)):
+        want = oracle.early_stop_topk(o, i, pred, J, 10, F, rounds, margin)
+        assert want["min_gap"] > 1e-6
+        t_ids, t_j, cnt = pm.rank_refine_ordered(setup["D"], setup["Q"], off, ids, score, order, ok, topk=10, F=F,
+                                                 rounds=rounds, margin=margin)
+        _assert_top_equal(t_ids.cpu().numpy(), t_j.cpu().numpy(), want["top_ids"], want["top_j"], (seed, F))
+        c = cnt.cpu().numpy()
+        assert c[0] == want["refined"] and c[1] == want["finished"], (seed, F)
+
+
 def torch_empty_like_int(t):
     import torch
     return torch.empty(max(t.numel(), 1), dtype=torch.int32, device=t.device)
