@@ -145,6 +145,13 @@ def headline(args):
     t_sign = e0.elapsed_time(e1) / 2 / 1e3
     del wsb
     log(f"workload 5: dataset signed (binned) in {1e3 * t_sign:.1f} ms ({D5.n * k / t_sign:.3g} sig/s)")
+    # -- the split table of the signatures the collision fraction reads
+    # (low halves and high-half bits: 17k/8 bytes a row instead of 4k)
+    e0.record(st)
+    dpk5 = pm.sig_pack(sig5)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t_pack = e0.elapsed_time(e1) / 1e3
     # -- bucket table of the query batch's banding
     e0.record(st)
     keys = pm.band(sig5, B, R, w5.seed)
@@ -200,7 +207,7 @@ def headline(args):
     for method in ("plain", "jhat", "scorer"):
         qb = SplitBatch(D5, sk, se, w5.box, w5.seed, k, cap, B, R, nq, w5.queries.xy.shape[0], cand_cap,
                         parts=args.plain_parts if method == "plain" else args.head_parts, sign_config=cfgq,
-                        binned=par5, method=method, dsig=sig5,
+                        binned=par5, method=method, dsig=sig5, dpacked=dpk5,
                         scorer=scorer, dfeat=dfeat, head=args.scorer_head, F=args.rank_F_grid[0],
                         rounds=args.rank_rounds_grid[-1], margin=float("inf") if method == "plain" else 0.0)
         qb.load(w5.queries)
@@ -327,11 +334,12 @@ def headline(args):
         "scorer_head": args.scorer_head, "sub_batches": args.head_parts, "plain_sub_batches": args.plain_parts,
         "binned": {**par5, "lds_edges": cfgb.lds_edges},
         "candidates_per_query": n_cand / nq, "queries_over_4096_candidates": n_long, "index_ms": 1e3 * t_index,
+        "split_table_ms": 1e3 * t_pack,
         "sign_ms": 1e3 * t_sign, "sign_sig_per_s": D5.n * k / t_sign,
         "calibration_queries": int(cal.size), "methods": methods, "scorer": learned,
         "scorer_ceiling": ceiling,
     }
-    state = {"w5": w5, "D5": D5, "sig5": sig5, "par5": par5, "cfgb": cfgb, "batches": batches,
+    state = {"w5": w5, "D5": D5, "sig5": sig5, "dpk5": dpk5, "par5": par5, "cfgb": cfgb, "batches": batches,
              "n_cand": n_cand, "sk": sk, "se": se}
     return out, state
 
@@ -395,17 +403,22 @@ def stage_roofline(state, methods):
     k = parts[0].k
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic_workload5.json")
     rl = {}
-    # k_rank_jhat_sort: an HBM-bound gather: each candidate's data signature
-    # (4k bytes) and id (4 B) read, its score and order written (8 B); per
-    # query its signature and offsets
+    # the collision-fraction order, an HBM-bound gather: each candidate's
+    # data signature row (17k/8 bytes of the split table, or 4k bytes of the
+    # full one) and id (4 B) read, its score and order written (8 B); per
+    # query its signature and offsets.  The split form's reads of full
+    # values (both high halves nonzero, low halves equal) are not counted.
+    packed = parts[0].dpacked is not None
+    kname = "k_rank_jhat_packed" if packed else "k_rank_jhat_sort"
+    row = 17.0 * k / 8.0 if packed else 4.0 * k
     Cs = [float(p.cand_off[-1].item()) for p in parts]
-    by = float(np.mean([c * (4.0 * k + 12.0) + p.nq * (4.0 * k + 16.0) for c, p in zip(Cs, parts)]))
+    by = float(np.mean([c * (row + 12.0) + p.nq * (4.0 * k + 16.0) for c, p in zip(Cs, parts)]))
     t = float(np.mean([st["jhat_order"] for st in sts])) / 1e3
-    rl["k_rank_jhat_sort"] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
-                              "frac": by / t / 8e12, "traffic": _committed_traffic(tpath, "k_rank_jhat_sort"),
-                              "traffic_unit": "bytes per launch", "kernel": "k_rank_jhat_sort",
-                              "launch_ms": 1e3 * t, "bytes_per_launch": by,
-                              "candidates_per_launch": float(np.mean(Cs)), "launches_per_step": len(parts)}
+    rl[kname] = {"bound": "hbm", "achieved": by / t / 1e9, "peak": 8000.0, "unit": "GB/s",
+                 "frac": by / t / 8e12, "traffic": _committed_traffic(tpath, kname),
+                 "traffic_unit": "bytes per launch", "kernel": kname,
+                 "launch_ms": 1e3 * t, "bytes_per_launch": by,
+                 "candidates_per_launch": float(np.mean(Cs)), "launches_per_step": len(parts)}
     # k_bin_lookup (query signing from the shared binned samples): bytes of
     # the samples each (query, hash) visits; the stage also holds the walk of
     # the polygons left to it (k_sign), so its time bounds the kernel's
@@ -1061,6 +1074,7 @@ def main():
     for b_ in hstate["batches"].values():
         del b_
     hstate["batches"] = None
+    hstate["dpk5"] = None
     torch.cuda.empty_cache()
     sec = {} if args.only_headline else secondary(args, hstate)
     cpu = None

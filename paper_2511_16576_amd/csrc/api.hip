@@ -819,6 +819,37 @@ polymh_status polymh_rank_jhat_order(const uint32_t *qsig, const uint32_t *dsig,
     return launch_rank_jhat_sort(qsig, dsig, k, cand_off, cand_ids, nq, score, order, sorted_ok, as_stream(stream));
 }
 
+size_t polymh_sig_pack_stride(int32_t k)
+{
+    return (k >= 64 && k <= 256 && k % 64 == 0) ? (size_t)k * 17 / 8 : 0;
+}
+
+polymh_status polymh_sig_pack(const uint32_t *sig, int64_t n, int32_t k, void *packed, void *stream)
+{
+    if (n < 0 || polymh_sig_pack_stride(k) == 0) return set_error(POLYMH_EINVAL, "sig_pack: bad sizes");
+    if (n == 0) return POLYMH_OK;
+    if (!sig || !packed) return set_error(POLYMH_EINVAL, "sig_pack: NULL array");
+    if ((reinterpret_cast<uintptr_t>(sig) & 15) || (reinterpret_cast<uintptr_t>(packed) & 7))
+        return set_error(POLYMH_EINVAL, "sig_pack: misaligned array");
+    return launch_sig_pack(sig, n, k, static_cast<uint8_t *>(packed), as_stream(stream));
+}
+
+polymh_status polymh_rank_jhat_order_packed(const uint32_t *qsig, const void *packed, const uint32_t *dsig,
+                                            int32_t k, const int64_t *cand_off, const int32_t *cand_ids,
+                                            int64_t nq, float *score, int32_t *order, uint8_t *sorted_ok,
+                                            void *stream)
+{
+    if (nq < 0 || polymh_sig_pack_stride(k) == 0) return set_error(POLYMH_EINVAL, "rank_jhat_order_packed: bad sizes");
+    if (nq == 0) return POLYMH_OK;
+    if (!qsig || !packed || !dsig || !cand_off || !cand_ids || !score || !order || !sorted_ok)
+        return set_error(POLYMH_EINVAL, "rank_jhat_order_packed: NULL array");
+    if ((reinterpret_cast<uintptr_t>(qsig) & 15) || (reinterpret_cast<uintptr_t>(dsig) & 15) ||
+        (reinterpret_cast<uintptr_t>(packed) & 7))
+        return set_error(POLYMH_EINVAL, "rank_jhat_order_packed: misaligned array");
+    return launch_rank_jhat_packed(qsig, static_cast<const uint8_t *>(packed), dsig, k, cand_off, cand_ids, nq,
+                                   score, order, sorted_ok, as_stream(stream));
+}
+
 polymh_status polymh_rank_order(const int64_t *cand_off, int64_t nq, const float *score, int32_t *order,
                                 uint8_t *sorted_ok, void *stream)
 {

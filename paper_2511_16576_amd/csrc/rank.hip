@@ -13,6 +13,7 @@
 #include "internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <cfloat>
 
 namespace polymh {
@@ -78,14 +79,152 @@ __global__ __launch_bounds__(1024) void k_rank_sort(const int64_t *__restrict__ 
 }
 
 
+// The block's (score desc, position asc) order of the n scores it wrote to
+// ss/si (entries below kSortCap), written to order[a..a+n); lists beyond
+// kSortCap keep their given order and get sorted_ok 0.
+__device__ __forceinline__ void order_from_lds(float *ss, int *si, int n, int64_t a, int64_t q,
+                                               int32_t *__restrict__ order, uint8_t *__restrict__ sorted_ok)
+{
+    if (n > kSortCap) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = i;
+        if (threadIdx.x == 0) sorted_ok[q] = 0;
+        return;
+    }
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = n + threadIdx.x; i < np; i += blockDim.x) {
+        ss[i] = -FLT_MAX;
+        si[i] = 0x7fffffff;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= np; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & kk) == 0;
+                    const bool before = key_before(ss[l], si[l], ss[i], si[i]);
+                    if (before == up) {
+                        const float t = ss[i]; ss[i] = ss[l]; ss[l] = t;
+                        const int u = si[i]; si[i] = si[l]; si[l] = u;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = si[i];
+    if (threadIdx.x == 0) sorted_ok[q] = 1;
+}
+
+// For scores that are counts in [0, 256] (agreeing hashes, k <= 256) the
+// same order comes from a stable counting sort.  Per lane, the lanes of its
+// wavefront holding the same count: nine ballots, one per bit.
+__device__ __forceinline__ uint64_t match_count9(int v, bool valid)
+{
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 9; b++) {
+        const bool bit = (v >> b) & 1;
+        const uint64_t bb = __ballot(valid && bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+constexpr int kCountBins = 257;
+
+// LDS of order_from_counts for a block of NW wavefronts.
+template <int NW>
+struct CountSortLds {
+    static_assert(NW % 2 == 0, "the per-wavefront table is cleared as 32-bit words");
+    uint16_t cs[kSortCap];                       // the counts, by position
+    alignas(16) uint16_t wc[NW][kCountBins];     // per wavefront of a chunk: count of each value
+    int bin[kCountBins];                         // running start of each value's slots
+};
+
+// (count desc, position asc) order of the n counts in L.cs, written to
+// order[a..a+n) (n <= kSortCap): a histogram (one LDS atomic per distinct
+// value a wavefront holds), the bins' starts from the largest count down,
+// then, NW * 64 positions at a time, each position's slot: its bin's
+// running start, plus the positions of equal count in earlier wavefronts
+// of the chunk, plus those in earlier lanes of its own.  L.bin must be zero
+// and L.cs complete (a barrier) before the call.
+template <int NW>
+__device__ void order_from_counts(CountSortLds<NW> &L, int n, int64_t a, int32_t *__restrict__ order)
+{
+    constexpr int NT = NW * 64;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = tid >> 6;
+    const uint64_t below = (1ull << lane) - 1;
+    for (int c0 = 0; c0 < n; c0 += NT) {
+        const int p = c0 + tid;
+        const bool valid = p < n;
+        const int v = valid ? L.cs[p] : 0;
+        const uint64_t m = match_count9(v, valid);
+        if (valid && (m & below) == 0) atomicAdd(&L.bin[v], __popcll(m));
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // exclusive prefix over the bins from 256 down, five a lane
+        int h[5], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            const int d = 5 * lane + j;
+            h[j] = d < kCountBins ? L.bin[kCountBins - 1 - d] : 0;
+            sum += h[j];
+        }
+        int pre = wave_incl_scan32(sum) - sum;
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            const int d = 5 * lane + j;
+            if (d < kCountBins) L.bin[kCountBins - 1 - d] = pre;
+            pre += h[j];
+        }
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += NT) {
+        uint32_t *wz = reinterpret_cast<uint32_t *>(&L.wc[0][0]);
+        for (int t = tid; t < NW * kCountBins / 2; t += NT) wz[t] = 0;
+        __syncthreads();
+        const int p = c0 + tid;
+        const bool valid = p < n;
+        const int v = valid ? L.cs[p] : 0;
+        const uint64_t m = match_count9(v, valid);
+        if (valid && (m & below) == 0) L.wc[wave][v] = (uint16_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            int slot = L.bin[v] + __popcll(m & below);
+            for (int w = 0; w < wave; w++) slot += L.wc[w][v];
+            order[a + slot] = p;
+        }
+        __syncthreads();
+        if (c0 + NT < n) {
+            for (int t = tid; t < kCountBins; t += NT) {
+                int s = 0;
+                for (int w = 0; w < NW; w++) s += L.wc[w][t];
+                L.bin[t] += s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // One block per query: the collision fraction of every candidate (the
 // unbiased estimate of J of Thm. 1: the share of the k hashes on which the
 // two signatures agree), written to score[], then the (score desc, position
 // asc) order as k_rank_sort.  One wavefront per candidate; with k a multiple
 // of 4 and at most 1024 and both tables 16-byte aligned (`vec`), a lane keeps
 // its 16-byte slices of the query's signature in registers and reads the
-// candidate's with 16-byte loads.
-__global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restrict__ qsig,
+// candidate's with 16-byte loads.  With k <= 256 (kCount) the order comes
+// from the counting sort, otherwise from the bitonic sort of the scores.
+struct BitonicLds {
+    float ss[kSortCap];
+    int si[kSortCap];
+};
+
+template <bool kCount>
+__global__ __launch_bounds__(1024, 8) void k_rank_jhat_sort(const uint32_t *__restrict__ qsig,
                                                          const uint32_t *__restrict__ dsig, int32_t k,
                                                          int vec, const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ cand_ids,
@@ -93,8 +232,21 @@ __global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restr
                                                          int32_t *__restrict__ order,
                                                          uint8_t *__restrict__ sorted_ok)
 {
-    __shared__ float ss[kSortCap];
-    __shared__ int si[kSortCap];
+    __shared__ typename std::conditional<kCount, CountSortLds<16>, BitonicLds>::type L;
+    // the score of position i, for the sort
+    auto record = [&](int i, int cnt, float sc) {
+        if constexpr (kCount) {
+            if (i < kSortCap) L.cs[i] = (uint16_t)cnt;
+        } else {
+            if (i < kSortCap) {
+                L.ss[i] = sc;
+                L.si[i] = i;
+            }
+        }
+    };
+    if constexpr (kCount) {
+        for (int v = threadIdx.x; v < kCountBins; v += blockDim.x) L.bin[v] = 0;
+    }
     const int64_t q = blockIdx.x;
     const int64_t a = off[q];
     const int n = (int)(off[q + 1] - a);
@@ -139,10 +291,7 @@ __global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restr
                 const float sc = (float)cnt * inv_k;
                 if (lane == 0 && i < n) {
                     score[a + i] = sc;
-                    if (i < kSortCap) {
-                        ss[i] = sc;
-                        si[i] = i;
-                    }
+                    record(i, cnt, sc);
                 }
             }
         }
@@ -170,42 +319,146 @@ __global__ __launch_bounds__(1024) void k_rank_jhat_sort(const uint32_t *__restr
             const float sc = (float)cnt * inv_k;
             if (lane == 0) {
                 score[a + i] = sc;
-                if (i < kSortCap) {
-                    ss[i] = sc;
-                    si[i] = i;
-                }
+                record(i, cnt, sc);
             }
         }
     }
+    if constexpr (kCount) {
+        __syncthreads();
+        if (n > kSortCap) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = i;
+            if (threadIdx.x == 0) sorted_ok[q] = 0;
+            return;
+        }
+        order_from_counts<16>(L, n, a, order);
+        if (threadIdx.x == 0) sorted_ok[q] = 1;
+    } else {
+        order_from_lds(L.ss, L.si, n, a, q, order, sorted_ok);
+    }
+}
+
+// Split signature rows.  Row r of the table holds the low 16 bits of the k
+// values of signature r (k uint16, in hash order), then k/32 words whose bit
+// i is set when value i has nonzero high 16 bits: 17k/8 bytes a row.  Two
+// values are equal exactly when their low halves are equal, their bits are
+// equal and, where both bits are set, their high halves are equal; first
+// hits are mostly below 2^16 (Thm. 2: a polygon of share S_p of B has
+// them at 1/S_p on average), so the last case is rare and reads the full
+// value then.  The collision fraction reads 17k/8 bytes a candidate
+// instead of 4k.
+__device__ __forceinline__ uint32_t hi_bits4(uint4 v)
+{
+    return (uint32_t)((v.x >> 16) != 0) | ((uint32_t)((v.y >> 16) != 0) << 1) |
+           ((uint32_t)((v.z >> 16) != 0) << 2) | ((uint32_t)((v.w >> 16) != 0) << 3);
+}
+
+// One wavefront per row: lane l packs values 4l .. 4l+3.
+__global__ __launch_bounds__(256) void k_sig_pack(const uint32_t *__restrict__ sig, int64_t n, int32_t k,
+                                                  uint8_t *__restrict__ packed)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)k * 17 / 8;
+    const bool in = 4 * lane < k;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nw) {
+        const uint4 v = in ? *reinterpret_cast<const uint4 *>(sig + r * k + 4 * lane) : make_uint4(0, 0, 0, 0);
+        uint8_t *row = packed + r * stride;
+        if (in)
+            *reinterpret_cast<uint2 *>(row + 8 * lane) =
+                make_uint2((v.x & 0xffffu) | (v.y << 16), (v.z & 0xffffu) | (v.w << 16));
+        // lanes 8w .. 8w+7 hold the 32 bits of word w
+        uint32_t bits = hi_bits4(v) << (4 * (lane & 7));
+        bits |= __shfl_xor(bits, 1, 64);
+        bits |= __shfl_xor(bits, 2, 64);
+        bits |= __shfl_xor(bits, 4, 64);
+        if (in && (lane & 7) == 0) *reinterpret_cast<uint32_t *>(row + 2 * k + 4 * (lane >> 3)) = bits;
+    }
+}
+
+// k_rank_jhat_sort on the split rows (k a multiple of 64, at most 256): a
+// lane compares 4 hashes, reading their low halves (8 bytes) and the word
+// of their bits; the full table `dsig` is read only for values whose high
+// halves are both nonzero and whose low halves agree.
+__global__ __launch_bounds__(1024, 8) void k_rank_jhat_packed(const uint32_t *__restrict__ qsig,
+                                                           const uint8_t *__restrict__ packed,
+                                                           const uint32_t *__restrict__ dsig, int32_t k,
+                                                           const int64_t *__restrict__ off,
+                                                           const int32_t *__restrict__ cand_ids,
+                                                           float *__restrict__ score,
+                                                           int32_t *__restrict__ order,
+                                                           uint8_t *__restrict__ sorted_ok)
+{
+    __shared__ CountSortLds<16> L;
+    const int64_t q = blockIdx.x;
+    const int64_t a = off[q];
+    const int n = (int)(off[q + 1] - a);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nwave = (int)(blockDim.x >> 6);
+    for (int v = threadIdx.x; v < kCountBins; v += blockDim.x) L.bin[v] = 0;
+    const int64_t stride = (int64_t)k * 17 / 8;
+    const float inv_k = 1.0f / (float)k;
+    const bool in = 4 * lane < k;
+    const uint4 qv = in ? *reinterpret_cast<const uint4 *>(qsig + q * (int64_t)k + 4 * lane) : make_uint4(0, 0, 0, 0);
+    const uint32_t qlo0 = (qv.x & 0xffffu) | (qv.y << 16), qlo1 = (qv.z & 0xffffu) | (qv.w << 16);
+    const uint32_t qbits = hi_bits4(qv);
+    const int mword = 2 * k + 4 * (lane >> 3), mshift = 4 * (lane & 7);
+    constexpr int kU = 8;
+    int32_t idn[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+        const int i = min(wave * kU + u, n - 1);
+        idn[u] = n > 0 ? cand_ids[a + i] : 0;
+    }
+    for (int i0 = wave * kU; i0 < n; i0 += nwave * kU) {
+        uint2 lo[kU];
+        uint32_t mk[kU];
+        int32_t idc[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const uint8_t *row = packed + (int64_t)idn[u] * stride;
+            lo[u] = in ? *reinterpret_cast<const uint2 *>(row + 8 * lane) : make_uint2(0, 0);
+            mk[u] = in ? *reinterpret_cast<const uint32_t *>(row + mword) : 0u;
+            idc[u] = idn[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) idn[u] = cand_ids[a + min(i0 + nwave * kU + u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int i = i0 + u;
+            const uint32_t cb = (mk[u] >> mshift) & 15u;
+            const uint32_t d0 = lo[u].x ^ qlo0, d1 = lo[u].y ^ qlo1;
+            // equal low halves and equal high-half flags
+            uint32_t eq = (uint32_t)((d0 & 0xffffu) == 0) | ((uint32_t)((d0 >> 16) == 0) << 1) |
+                          ((uint32_t)((d1 & 0xffffu) == 0) << 2) | ((uint32_t)((d1 >> 16) == 0) << 3);
+            eq &= ~(cb ^ qbits) & 15u;
+            if (!in) eq = 0;
+            // both high halves nonzero: compare the full values
+            const uint32_t need = eq & cb;
+            if (__ballot(need != 0)) {
+                if (need) {
+                    const uint4 fv = *reinterpret_cast<const uint4 *>(dsig + (int64_t)idc[u] * k + 4 * lane);
+                    const uint32_t ne = (uint32_t)(fv.x != qv.x) | ((uint32_t)(fv.y != qv.y) << 1) |
+                                        ((uint32_t)(fv.z != qv.z) << 2) | ((uint32_t)(fv.w != qv.w) << 3);
+                    eq &= ~(need & ne);
+                }
+            }
+            const int cnt = __popcll(__ballot(eq & 1u)) + __popcll(__ballot(eq & 2u)) +
+                            __popcll(__ballot(eq & 4u)) + __popcll(__ballot(eq & 8u));
+            if (lane == 0 && i < n) {
+                score[a + i] = (float)cnt * inv_k;
+                if (i < kSortCap) L.cs[i] = (uint16_t)cnt;
+            }
+        }
+    }
+    __syncthreads();
     if (n > kSortCap) {
         for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = i;
         if (threadIdx.x == 0) sorted_ok[q] = 0;
         return;
     }
-    int np = 1;
-    while (np < n) np <<= 1;
-    for (int i = n + threadIdx.x; i < np; i += blockDim.x) {
-        ss[i] = -FLT_MAX;
-        si[i] = 0x7fffffff;
-    }
-    __syncthreads();
-    for (int kk = 2; kk <= np; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < np; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const bool up = (i & kk) == 0;
-                    const bool before = key_before(ss[l], si[l], ss[i], si[i]);
-                    if (before == up) {
-                        const float t = ss[i]; ss[i] = ss[l]; ss[l] = t;
-                        const int u = si[i]; si[i] = si[l]; si[l] = u;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) order[a + i] = si[i];
+    // scores are counts over k <= 256: the same order by counting
+    order_from_counts<16>(L, n, a, order);
     if (threadIdx.x == 0) sorted_ok[q] = 1;
 }
 
@@ -570,9 +823,32 @@ polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, 
     if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "rank_jhat: too many queries");
     const int vec = (k & 3) == 0 && k <= 1024 && (reinterpret_cast<uintptr_t>(qsig) & 15) == 0 &&
                     (reinterpret_cast<uintptr_t>(dsig) & 15) == 0;
-    hipLaunchKernelGGL(k_rank_jhat_sort, dim3((unsigned)nq), dim3(1024), 0, s, qsig, dsig, k, vec, off, cand_ids,
-                       score, order, sorted_ok);
+    if (k <= 256)   // counts of at most 256 agreeing hashes: the counting sort
+        hipLaunchKernelGGL(k_rank_jhat_sort<true>, dim3((unsigned)nq), dim3(1024), 0, s, qsig, dsig, k, vec, off,
+                           cand_ids, score, order, sorted_ok);
+    else
+        hipLaunchKernelGGL(k_rank_jhat_sort<false>, dim3((unsigned)nq), dim3(1024), 0, s, qsig, dsig, k, vec, off,
+                           cand_ids, score, order, sorted_ok);
     return check_launch("rank_jhat");
+}
+
+polymh_status launch_sig_pack(const uint32_t *sig, int64_t n, int32_t k, uint8_t *packed, hipStream_t s)
+{
+    if (n == 0) return POLYMH_OK;
+    const int64_t blocks = std::min<int64_t>((n + 3) / 4, 1 << 20);
+    hipLaunchKernelGGL(k_sig_pack, dim3((unsigned)blocks), dim3(256), 0, s, sig, n, k, packed);
+    return check_launch("sig_pack");
+}
+
+polymh_status launch_rank_jhat_packed(const uint32_t *qsig, const uint8_t *packed, const uint32_t *dsig, int32_t k,
+                                      const int64_t *off, const int32_t *cand_ids, int64_t nq, float *score,
+                                      int32_t *order, uint8_t *sorted_ok, hipStream_t s)
+{
+    if (nq == 0) return POLYMH_OK;
+    if (nq > 0x7fffffffLL) return set_error(POLYMH_EINVAL, "rank_jhat_packed: too many queries");
+    hipLaunchKernelGGL(k_rank_jhat_packed, dim3((unsigned)nq), dim3(1024), 0, s, qsig, packed, dsig, k, off,
+                       cand_ids, score, order, sorted_ok);
+    return check_launch("rank_jhat_packed");
 }
 
 polymh_status launch_reorder_head(const int64_t *off, int64_t nq, const float *score, const int32_t *order_in,

@@ -26,13 +26,16 @@ class QueryBatch:
     def __init__(self, D: pm.DevicePolys, sorted_keys, sorted_ent, box, seed: int, k: int, cap: int,
                  bands: int, rows: int, n_queries: int, max_vertices: int, cand_cap: int,
                  sign_config=None, topk: int = 10, binned=None, method: str = "plain", dsig=None,
-                 scorer=None, dfeat=None, head: int = 32, F: int = 8, rounds: int = 4, margin: float = 0.0):
+                 scorer=None, dfeat=None, head: int = 32, F: int = 8, rounds: int = 4, margin: float = 0.0,
+                 dpacked=None):
         """``binned``: None signs the queries by the walk; a dict with
         horizon, bin_bits and walk_ratio signs them from binned samples
         (``polymh_sign_binned``, the same bits).  ``method`` "jhat" and
         "scorer" need the data signatures ``dsig`` ([N][k]); "scorer" also
         the trained ``scorer`` (params, BF16 weights) and the data shape
-        features ``dfeat``."""
+        features ``dfeat``.  ``dpacked`` (``pm.sig_pack(dsig)``, optional)
+        lets the collision fraction read the split table of the data
+        signatures (the same scores and order, fewer bytes a candidate)."""
         dev = D.offsets.device
         self.D, self.sk, self.se = D, sorted_keys, sorted_ent
         self.box, self.seed, self.k, self.cap = box, seed, k, cap
@@ -67,7 +70,7 @@ class QueryBatch:
         if method != "plain":
             if dsig is None or dsig.shape[1] != k:
                 raise ValueError("ranked methods need the data signatures at the batch's k")
-            self.dsig = dsig
+            self.dsig, self.dpacked = dsig, dpacked
             self.score = torch.empty(cand_cap, dtype=torch.float32, device=dev)
             self.order = torch.empty(cand_cap, dtype=torch.int32, device=dev)
             self.sorted_ok = torch.empty(n_queries, dtype=torch.uint8, device=dev)
@@ -128,7 +131,7 @@ class QueryBatch:
             mark("topk")
             return
         pm.rank_jhat_order(self.sig, self.dsig, self.cand_off, self.cand_ids, score=self.score, order=self.order,
-                           sorted_ok=self.sorted_ok, stream=s)
+                           sorted_ok=self.sorted_ok, stream=s, packed=self.dpacked)
         mark("jhat_order")
         order = self.order
         if self.method == "scorer":

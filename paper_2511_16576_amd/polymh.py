@@ -104,6 +104,9 @@ _SIGNATURES = {
                                  P, P, P, P, P]),
     "polymh_rank_jhat_order": (I32, [P, P, I32, P, P, I64, P, P, P, P]),
     "polymh_rank_order": (I32, [P, I64, P, P, P, P]),
+    "polymh_sig_pack_stride": (SZ, [I32]),
+    "polymh_sig_pack": (I32, [P, I64, I32, P, P]),
+    "polymh_rank_jhat_order_packed": (I32, [P, P, P, I32, P, P, I64, P, P, P, P]),
     "polymh_rank_head_fixed": (I32, [P, P, I64, P, I32, P, P, P, P]),
     "polymh_rank_reorder_head": (I32, [P, I64, P, P, I32, P, P, P]),
     "polymh_mlp_score_pairs": (I32, [P, P, P, P, I32, P, P, P, I64, P, P, P, P]),
@@ -645,17 +648,39 @@ def rank_refine(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, sco
     return ids[:nq], js[:nq], int(nref.value), int(rounds.value)
 
 
-def rank_jhat_order(qsig, dsig, cand_off, cand_ids, score=None, order=None, sorted_ok=None, stream=None):
+def sig_pack(sig, out=None, stream=None):
+    """The split signature table of sig [n][k] (k a multiple of 64 up to
+    256): uint8 [n][17k/8], per row the k low 16-bit halves, then the bits
+    of the values of 2^16 and more."""
+    n, k = sig.shape
+    stride = int(lib().polymh_sig_pack_stride(k))
+    if stride == 0:
+        raise ValueError("the split signature table needs k a multiple of 64 in [64, 256]")
+    out = torch.empty((max(n, 1), stride), dtype=torch.uint8, device=sig.device) if out is None else out
+    _check(lib().polymh_sig_pack(_ptr(sig), n, k, _ptr(out), _stream(stream)))
+    return out
+
+
+def rank_jhat_order(qsig, dsig, cand_off, cand_ids, score=None, order=None, sorted_ok=None, stream=None,
+                    packed=None):
     """Collision fraction of every candidate and each query's best-first
-    order: (score float32 [C], order int32 [C], sorted_ok uint8 [nq])."""
+    order: (score float32 [C], order int32 [C], sorted_ok uint8 [nq]).  With
+    ``packed`` (``sig_pack(dsig)``) the candidates are read from the split
+    table; the result is the same."""
     nq = cand_off.numel() - 1
     dev = cand_off.device
     C = cand_ids.numel()
     score = torch.empty(max(C, 1), dtype=torch.float32, device=dev) if score is None else score
     order = torch.empty(max(C, 1), dtype=torch.int32, device=dev) if order is None else order
     sorted_ok = torch.empty(max(nq, 1), dtype=torch.uint8, device=dev) if sorted_ok is None else sorted_ok
-    _check(lib().polymh_rank_jhat_order(_ptr(qsig), _ptr(dsig), qsig.shape[1], _ptr(cand_off), _ptr(cand_ids),
-                                        nq, _ptr(score), _ptr(order), _ptr(sorted_ok), _stream(stream)))
+    if packed is not None:
+        _check(lib().polymh_rank_jhat_order_packed(_ptr(qsig), _ptr(packed), _ptr(dsig), qsig.shape[1],
+                                                   _ptr(cand_off), _ptr(cand_ids), nq, _ptr(score), _ptr(order),
+                                                   _ptr(sorted_ok), _stream(stream)))
+    else:
+        _check(lib().polymh_rank_jhat_order(_ptr(qsig), _ptr(dsig), qsig.shape[1], _ptr(cand_off),
+                                            _ptr(cand_ids), nq, _ptr(score), _ptr(order), _ptr(sorted_ok),
+                                            _stream(stream)))
     return score, order, sorted_ok
 
 

@@ -51,6 +51,7 @@ KERNEL_SOURCES = {
     "k_sign": ["sign.hip", "sign_common.hpp", "internal.hpp"],
     "k_bin_lookup": ["binned.hip", "sign_common.hpp", "internal.hpp"],
     "k_rank_jhat_sort": ["rank.hip", "internal.hpp"],
+    "k_rank_jhat_packed": ["rank.hip", "internal.hpp"],
     "k_sparse": ["query.hip", "internal.hpp"],
     "k_sparse_sort": ["query.hip", "internal.hpp"],
     "k_sparse_sort_big": ["query.hip", "internal.hpp"],

@@ -1,0 +1,142 @@
+"""Workload 5's query batch at full size, in the launch configuration the
+benchmark times: 4,000,000 polygons signed from binned samples, 64 x 4
+bands, 10,000 queries signed from binned samples, looked up and refined as
+four sub-batches on streams forked inside one captured graph, ordered by
+the collision fraction (read from the split signature table) with early
+stop (first rounds of 16, 4 rounds, margin 0.01), and beside it the plain
+batch (every candidate refined, one graph).  For five sampled queries of
+every sub-batch (its first and last among them, and one of 257 to 2,048
+vertices) the oracle recomputes, one by one: the query's signature and
+band keys; the signatures of all its candidates (bit-exact against the
+indexed rows and their rows of the split table; each shares a band key
+with the query, the list is ascending and free of repeats, and none of
+2,000 random other polygons shares a key); every candidate's collision
+fraction and the best-first order; the early stop's top-10 from its own
+exact J of the candidates it refines; and the plain batch's top-10 from the
+exact J of the whole list."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_16576_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+BANDS, ROWS, PARTS = 64, 4, 4
+F, ROUNDS, MARGIN = 16, 4, 0.01
+REL, ABS = 1e-9, 1e-12
+
+
+def _assert_top_equal(got_ids, got_j, want_ids, want_j, ctx):
+    """One top-k row: J within the refinement tolerance, ids exactly except
+    where exact J values tie within it (either order is correct then)."""
+    assert np.allclose(got_j, want_j, rtol=REL, atol=ABS), ctx
+    live = got_ids[got_ids >= 0]
+    assert np.unique(live).size == live.size, ctx
+    for t in np.flatnonzero(got_ids != want_ids):
+        tied = np.isclose(want_j, want_j[t], rtol=REL, atol=ABS).sum()
+        assert want_ids[t] >= 0 and (tied >= 2 or t == want_ids.size - 1), (ctx, t)
+
+
+def test_query_batch_workload5_full_size(orc):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_16576_amd import polymh as pm
+    from paper_2511_16576_amd.pipeline import SplitBatch
+    pm.check_device()
+    t0 = time.time()
+    w = dg.workload(5, n_queries=10000)
+    nq, k, cap = w.queries.n, w.k, w.cap
+    print(f"workload 5: {w.data.n} polygons, {nq} queries, generated in {time.time() - t0:.1f}s", flush=True)
+    D = pm.to_device(w.data)
+    h, bb = pm.binned_params(D, w.box, k, cap)
+    sig = pm.sign_binned(D, w.box, w.seed, k, cap, horizon=h, bin_bits=bb, config=pm.binned_config(D))
+    sk, se = pm.index_build(pm.band(sig, BANDS, ROWS, w.seed))
+    Qd = pm.to_device(w.queries)
+    binned = {"horizon": h, "bin_bits": bb, "walk_ratio": 300.0}
+    qs = pm.sign_binned(Qd, w.box, w.seed, k, cap, horizon=h, bin_bits=bb)
+    off, _ = pm.query(sk, se, D.n, pm.band(qs, BANDS, ROWS, w.seed))
+    cand_cap = int(1.25 * int(off[-1].item())) + 65536
+    del qs, off
+    common = dict(sign_config=pm.binned_config(Qd), binned=binned, dsig=sig)
+    args = (D, sk, se, w.box, w.seed, k, cap, BANDS, ROWS, nq, w.queries.xy.shape[0], cand_cap)
+    packed = pm.sig_pack(sig)
+    jb = SplitBatch(*args, parts=PARTS, method="jhat", F=F, rounds=ROUNDS, margin=MARGIN, dpacked=packed,
+                    **common)
+    jb.load(w.queries)
+    jb.capture()
+    pb = SplitBatch(*args, parts=1, method="plain", **common)
+    pb.load(w.queries)
+    pb.capture()
+    for _ in range(2):
+        jb.run_graph()
+        pb.run_graph()
+    j_ids, j_j = (x.cpu().numpy() for x in jb.result())
+    p_ids, p_j = (x.cpu().numpy() for x in pb.result())
+    print(f"batches replayed: {cand_cap} candidate slots a part", flush=True)
+
+    rng = np.random.default_rng(51)
+    nv = np.diff(w.queries.offsets)
+    # per sub-batch its first and last query, two at random and one at
+    # random among those of 257 to 2,048 vertices (the longest rings are
+    # left out so the oracle's fan clipping of whole lists stays short; they
+    # have refinement tests of their own)
+    sample = []
+    for a, b in jb.bounds:
+        pool = np.arange(a + 1, b - 1)
+        sample += [a, b - 1] + rng.choice(pool, 2, replace=False).tolist()
+        long_ = pool[(nv[pool] > 256) & (nv[pool] <= 2048)]
+        if long_.size:
+            sample.append(int(rng.choice(long_)))
+    others = np.sort(rng.choice(w.data.n, 2000, replace=False))
+    okeys = orc.band(orc.sign(w.data.subset(others), w.box, w.seed, k, cap), BANDS, ROWS, w.seed)
+    gsig = sig.cpu().numpy().view(np.uint32)
+    gpk = packed.cpu().numpy()
+    assert ((gsig >> 16) != 0).any(), "values of 2^16 and more: the split comparison reads full values"
+    for q in sample:
+        t1 = time.time()
+        p = int(np.searchsorted([b for _, b in jb.bounds], q, side="right"))
+        part, lq = jb.parts[p], q - jb.bounds[p][0]
+        o = part.cand_off.cpu().numpy()
+        a, b = int(o[lq]), int(o[lq + 1])
+        cand = part.cand_ids[a:b].cpu().numpy()
+        oq = orc.sign(w.queries.subset([q]), w.box, w.seed, k, cap)
+        assert np.array_equal(part.sig[lq].cpu().numpy().view(np.uint32), oq[0]), q
+        oqk = orc.band(oq, BANDS, ROWS, w.seed)[0]
+        assert np.array_equal(part.keys[lq].cpu().numpy().view(np.uint64), oqk), q
+        # the candidate list: sound, ascending without repeats, sampled complete
+        assert cand.size > 0 and np.all(np.diff(cand) > 0), q
+        osig = orc.sign(w.data.subset(cand), w.box, w.seed, k, cap)
+        assert np.array_equal(gsig[cand], osig), q
+        # their rows of the split table: low halves, then high-half bits
+        assert np.array_equal(gpk[cand, :2 * k].copy().view("<u2"), (osig & 0xFFFF).astype(np.uint16)), q
+        words = gpk[cand, 2 * k:].copy().view("<u4")
+        bits = ((words[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(cand.size, k)
+        assert np.array_equal(bits, (osig >> 16) != 0), q
+        assert (orc.band(osig, BANDS, ROWS, w.seed) == oqk[None, :]).any(axis=1).all(), q
+        outside = ~np.isin(others, cand)
+        assert not (okeys[outside] == oqk[None, :]).any(), q
+        pl = pb.parts[0]
+        po = pl.cand_off.cpu().numpy()
+        assert np.array_equal(pl.cand_ids[int(po[q]):int(po[q + 1])].cpu().numpy(), cand), q
+        # collision fractions and the best-first order
+        pred = oracle.collision_fraction(oq[0], osig).astype(np.float32)
+        assert np.array_equal(part.score[a:b].cpu().numpy(), pred), q
+        order, is_sorted = oracle.best_first(pred)
+        assert bool(part.sorted_ok[lq].item()) == is_sorted, q
+        assert np.array_equal(part.order[a:b].cpu().numpy(), order), q
+        # the early stop from the oracle's exact J of the candidates it refines
+        one = w.queries.subset([q])
+        jf = lambda pos: orc.jaccard_candidates(w.data, one, np.array([0, pos.size]), cand[pos])
+        r = oracle.early_stop_query(cand, pred, jf, 10, F, ROUNDS, MARGIN)
+        assert min(r["gaps"], default=1.0) > 1e-6, q
+        _assert_top_equal(j_ids[q], j_j[q], r["top_ids"], r["top_j"], ("early stop", q))
+        # the plain batch: the top-10 of the whole list
+        Jall = orc.jaccard_candidates(w.data, one, np.array([0, cand.size]), cand)
+        ti, tj = oracle.topk(np.array([0, cand.size]), cand, Jall, 10)
+        _assert_top_equal(p_ids[q], p_j[q], ti[0], tj[0], ("plain", q))
+        print(f"query {q} (sub-batch {p}, {nv[q]} vertices): {cand.size} candidates, {r['refined']} refined by "
+              f"the early stop; checked in {time.time() - t1:.1f}s", flush=True)

@@ -89,6 +89,62 @@ def test_jhat_order_other_k(pm, k):
     _check_order(want, off, order.cpu().numpy()[:ids.size])
 
 
+def test_sig_pack_layout(pm, setup):
+    """The split table: per row the k low 16-bit halves, then k/32 words
+    whose bit i % 32 of word i / 32 marks a value of 2^16 or more."""
+    osig = setup["osig"]
+    got = pm.sig_pack(setup["sig"]).cpu().numpy()
+    n, k = osig.shape
+    assert got.shape == (n, 17 * k // 8)
+    lo = got[:, :2 * k].copy().view("<u2")
+    assert np.array_equal(lo, (osig & 0xFFFF).astype(np.uint16))
+    words = got[:, 2 * k:].copy().view("<u4")
+    bits = ((words[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(n, k)
+    assert np.array_equal(bits, (osig >> 16) != 0)
+
+
+def test_jhat_order_packed_equals_unpacked(pm, setup):
+    off, ids = setup["off"], setup["ids"]
+    packed = pm.sig_pack(setup["sig"])
+    a = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
+    b = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids, packed=packed)
+    C = int(off[-1].item())
+    assert np.array_equal(a[0].cpu().numpy()[:C], b[0].cpu().numpy()[:C])
+    assert np.array_equal(a[1].cpu().numpy()[:C], b[1].cpu().numpy()[:C])
+    assert np.array_equal(a[2].cpu().numpy(), b[2].cpu().numpy())
+
+
+@pytest.mark.parametrize("k", [64, 128, 192, 256])
+def test_jhat_order_packed_high_halves(pm, k):
+    """Values built to share low halves with different high halves (and
+    the reverse), so that every branch of the split comparison is taken:
+    scores equal the share of equal values, the order is the oracle's."""
+    import torch
+    rng = np.random.default_rng(k)
+    vals = (rng.integers(1, 6, 64) + (rng.integers(0, 4, 64) << 16)).astype(np.uint32)
+    vals[:4] = (7, 7 + (1 << 16), 7 + (5 << 16), 5 << 16)
+    qs = vals[rng.integers(0, 12, (6, k))]
+    ds = vals[rng.integers(0, 12, (120, k))]
+    ds[:6] = qs                                  # candidates equal to their query
+    counts = np.array([0, 3, 120, 1, 40, 77])
+    off = np.zeros(7, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    ids = np.concatenate([rng.choice(120, c, replace=False) for c in counts]).astype(np.int32)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    dsig = t(ds.view(np.int32))
+    packed = pm.sig_pack(dsig)
+    score, order, ok = pm.rank_jhat_order(t(qs.view(np.int32)), dsig, t(off), t(ids), packed=packed)
+    rows = np.repeat(np.arange(6), counts)
+    cnt = np.concatenate([oracle.collision_counts(qs[q], ds[ids[off[q]:off[q + 1]]]) for q in range(6)])
+    assert np.array_equal(score.cpu().numpy()[:ids.size], cnt.astype(np.float32) * np.float32(1.0 / k))
+    for q in range(6):
+        a, b = off[q], off[q + 1]
+        od, srt = oracle.best_first(score.cpu().numpy()[a:b])
+        assert srt and np.array_equal(order.cpu().numpy()[a:b], od), q
+    assert (ok.cpu().numpy() == 1).all()
+    assert (cnt == (qs[rows] == ds[ids]).sum(axis=1)).all()
+
+
 def test_head_fixed(pm, setup):
     off, ids = setup["off"], setup["ids"]
     score, order, ok = pm.rank_jhat_order(setup["qsig"], setup["sig"], off, ids)
@@ -344,7 +400,9 @@ def test_split_batch_equals_whole(pm, setup, method, parts):
     whole.load(w.queries)
     whole.run_eager()
     w_ids, w_j = (x.clone() for x in whole.result())
-    split = SplitBatch(D, setup["sk"], setup["se"], parts=parts, **common)
+    # the collision fraction of the sub-batches reads the split table
+    packed = pm.sig_pack(setup["sig"]) if method == "jhat" else None
+    split = SplitBatch(D, setup["sk"], setup["se"], parts=parts, dpacked=packed, **common)
     sizes = [b - a for a, b in split.bounds]
     assert split.bounds[0][0] == 0 and split.bounds[-1][1] == w.queries.n and max(sizes) - min(sizes) <= 1
     assert all(split.bounds[i][1] == split.bounds[i + 1][0] for i in range(parts - 1))
