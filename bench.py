@@ -145,8 +145,8 @@ def headline(args):
     t_sign = e0.elapsed_time(e1) / 2 / 1e3
     del wsb
     log(f"workload 5: dataset signed (binned) in {1e3 * t_sign:.1f} ms ({D5.n * k / t_sign:.3g} sig/s)")
-    # -- the split table of the signatures the collision fraction reads
-    # (low halves and high-half bits: 17k/8 bytes a row instead of 4k)
+    # -- the saturated 16-bit table of the signatures the collision fraction
+    # reads (2k bytes a row instead of 4k)
     e0.record(st)
     dpk5 = pm.sig_pack(sig5)
     e1.record(st)
@@ -334,7 +334,7 @@ def headline(args):
         "scorer_head": args.scorer_head, "sub_batches": args.head_parts, "plain_sub_batches": args.plain_parts,
         "binned": {**par5, "lds_edges": cfgb.lds_edges},
         "candidates_per_query": n_cand / nq, "queries_over_4096_candidates": n_long, "index_ms": 1e3 * t_index,
-        "split_table_ms": 1e3 * t_pack,
+        "saturated_table_ms": 1e3 * t_pack,
         "sign_ms": 1e3 * t_sign, "sign_sig_per_s": D5.n * k / t_sign,
         "calibration_queries": int(cal.size), "methods": methods, "scorer": learned,
         "scorer_ceiling": ceiling,
@@ -404,13 +404,13 @@ def stage_roofline(state, methods):
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic_workload5.json")
     rl = {}
     # the collision-fraction order, an HBM-bound gather: each candidate's
-    # data signature row (17k/8 bytes of the split table, or 4k bytes of the
-    # full one) and id (4 B) read, its score and order written (8 B); per
-    # query its signature and offsets.  The split form's reads of full
-    # values (both high halves nonzero, low halves equal) are not counted.
+    # data signature row (2k bytes of the saturated table, or 4k bytes of
+    # the full one) and id (4 B) read, its score and order written (8 B);
+    # per query its signature and offsets.  The saturated form's reads of
+    # full values (both entries 65535) are not counted.
     packed = parts[0].dpacked is not None
     kname = "k_rank_jhat_packed" if packed else "k_rank_jhat_sort"
-    row = 17.0 * k / 8.0 if packed else 4.0 * k
+    row = 2.0 * k if packed else 4.0 * k
     Cs = [float(p.cand_off[-1].item()) for p in parts]
     by = float(np.mean([c * (row + 12.0) + p.nq * (4.0 * k + 16.0) for c, p in zip(Cs, parts)]))
     t = float(np.mean([st["jhat_order"] for st in sts])) / 1e3

@@ -521,33 +521,31 @@ polymh_status polymh_rank_jhat_order(const uint32_t *qsig, const uint32_t *dsig,
                                      const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                                      float *score, int32_t *order, uint8_t *sorted_ok, void *stream);
 
-/* polymh_sig_pack_stride -- bytes a row of the split signature table takes
- * for k hashes (17k/8), or 0 when k is not a multiple of 64 in [64, 256]. */
+/* polymh_sig_pack_stride -- bytes a row of the saturated signature table
+ * takes for k hashes (2k), or 0 when k is not a multiple of 4 in [4, 256]. */
 size_t polymh_sig_pack_stride(int32_t k);
 
-/* polymh_sig_pack -- the split signature table of sig [n][k], the layout
- * polymh_rank_jhat_order_packed reads.  Row r (polymh_sig_pack_stride(k)
- * bytes) holds the low 16 bits of the k values of signature r (uint16, hash
- * order), then k/32 uint32 words in which bit i % 32 of word i / 32 is set
- * when value i is 2^16 or more.  Lossless together with sig: two values are
- * equal exactly when their low halves and bits are equal and, where both
- * bits are set, their high halves are.  First hits (Def. 2) average 1/S_p
- * draws (Thm. 2), so at the shares of the configured data sets almost
- * every value is below 2^16.
- *   sig: device, 16-byte aligned; packed: device, n * stride bytes, 8-byte
+/* polymh_sig_pack -- the saturated signature table of sig [n][k], the layout
+ * polymh_rank_jhat_order_packed reads: uint16 [n][k], entry i of row r =
+ * min(sig[r][i], 65535).  With sig it decides equality exactly: two values
+ * are equal when their entries are equal and below 65535, or both entries
+ * are 65535 and the values themselves are equal.  First hits (Def. 2)
+ * average 1/S_p draws (Thm. 2), so at the configured data sets' shares
+ * almost every value lies below 65535.
+ *   sig: device, 16-byte aligned; packed: device, n * 2k bytes, 8-byte
  *   aligned, owned by the caller.  Errors: POLYMH_EINVAL for k not a
- *   multiple of 64 in [64, 256], n < 0, or NULL or misaligned arrays.
+ *   multiple of 4 in [4, 256], n < 0, or NULL or misaligned arrays.
  *   Stream-ordered. */
 polymh_status polymh_sig_pack(const uint32_t *sig, int64_t n, int32_t k, void *packed, void *stream);
 
 /* polymh_rank_jhat_order_packed -- polymh_rank_jhat_order (the same score,
  * order and sorted_ok, bit for bit) reading the indexed signatures as the
- * split table `packed` that polymh_sig_pack made from dsig: a candidate
- * costs 17k/8 bytes instead of 4k, and dsig is read only where both high
- * halves are nonzero and the low halves agree.  k a multiple of 64 in
- * [64, 256]; qsig and dsig 16-byte aligned, packed 8-byte aligned.  Errors
- * as polymh_rank_jhat_order, and POLYMH_EINVAL for another k or a
- * misaligned array.  Stream-ordered, no host reads (graph-capturable). */
+ * saturated table `packed` that polymh_sig_pack made from dsig: a candidate
+ * costs 2k bytes instead of 4k, and dsig is read only where the query's and
+ * the candidate's entries are both 65535.  k a multiple of 4 in [4, 256];
+ * qsig and dsig 16-byte aligned, packed 8-byte aligned.  Errors as
+ * polymh_rank_jhat_order, and POLYMH_EINVAL for another k or a misaligned
+ * array.  Stream-ordered, no host reads (graph-capturable). */
 polymh_status polymh_rank_jhat_order_packed(const uint32_t *qsig, const void *packed, const uint32_t *dsig,
                                             int32_t k, const int64_t *cand_off, const int32_t *cand_ids,
                                             int64_t nq, float *score, int32_t *order, uint8_t *sorted_ok,

@@ -821,7 +821,7 @@ polymh_status polymh_rank_jhat_order(const uint32_t *qsig, const uint32_t *dsig,
 
 size_t polymh_sig_pack_stride(int32_t k)
 {
-    return (k >= 64 && k <= 256 && k % 64 == 0) ? (size_t)k * 17 / 8 : 0;
+    return (k >= 4 && k <= 256 && k % 4 == 0) ? (size_t)k * 2 : 0;
 }
 
 polymh_status polymh_sig_pack(const uint32_t *sig, int64_t n, int32_t k, void *packed, void *stream)
@@ -831,7 +831,7 @@ polymh_status polymh_sig_pack(const uint32_t *sig, int64_t n, int32_t k, void *p
     if (!sig || !packed) return set_error(POLYMH_EINVAL, "sig_pack: NULL array");
     if ((reinterpret_cast<uintptr_t>(sig) & 15) || (reinterpret_cast<uintptr_t>(packed) & 7))
         return set_error(POLYMH_EINVAL, "sig_pack: misaligned array");
-    return launch_sig_pack(sig, n, k, static_cast<uint8_t *>(packed), as_stream(stream));
+    return launch_sig_pack(sig, n, k, static_cast<uint16_t *>(packed), as_stream(stream));
 }
 
 polymh_status polymh_rank_jhat_order_packed(const uint32_t *qsig, const void *packed, const uint32_t *dsig,
@@ -846,7 +846,7 @@ polymh_status polymh_rank_jhat_order_packed(const uint32_t *qsig, const void *pa
     if ((reinterpret_cast<uintptr_t>(qsig) & 15) || (reinterpret_cast<uintptr_t>(dsig) & 15) ||
         (reinterpret_cast<uintptr_t>(packed) & 7))
         return set_error(POLYMH_EINVAL, "rank_jhat_order_packed: misaligned array");
-    return launch_rank_jhat_packed(qsig, static_cast<const uint8_t *>(packed), dsig, k, cand_off, cand_ids, nq,
+    return launch_rank_jhat_packed(qsig, static_cast<const uint16_t *>(packed), dsig, k, cand_off, cand_ids, nq,
                                    score, order, sorted_ok, as_stream(stream));
 }
 

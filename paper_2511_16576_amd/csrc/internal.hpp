@@ -296,8 +296,8 @@ polymh_status launch_head_fixed(const int64_t *off, const int32_t *cand_ids, int
 polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, int32_t k, const int64_t *off,
                                     const int32_t *cand_ids, int64_t nq, float *score, int32_t *order,
                                     uint8_t *sorted_ok, hipStream_t s);
-polymh_status launch_sig_pack(const uint32_t *sig, int64_t n, int32_t k, uint8_t *packed, hipStream_t s);
-polymh_status launch_rank_jhat_packed(const uint32_t *qsig, const uint8_t *packed, const uint32_t *dsig, int32_t k,
+polymh_status launch_sig_pack(const uint32_t *sig, int64_t n, int32_t k, uint16_t *packed, hipStream_t s);
+polymh_status launch_rank_jhat_packed(const uint32_t *qsig, const uint16_t *packed, const uint32_t *dsig, int32_t k,
                                       const int64_t *off, const int32_t *cand_ids, int64_t nq, float *score,
                                       int32_t *order, uint8_t *sorted_ok, hipStream_t s);
 polymh_status launch_jhat(const uint32_t *lsig, const uint32_t *rsig, const int32_t *li,

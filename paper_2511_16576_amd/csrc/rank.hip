@@ -337,56 +337,43 @@ __global__ __launch_bounds__(1024, 8) void k_rank_jhat_sort(const uint32_t *__re
     }
 }
 
-// Split signature rows.  Row r of the table holds the low 16 bits of the k
-// values of signature r (k uint16, in hash order), then k/32 words whose bit
-// i is set when value i has nonzero high 16 bits: 17k/8 bytes a row.  Two
-// values are equal exactly when their low halves are equal, their bits are
-// equal and, where both bits are set, their high halves are equal; first
-// hits are mostly below 2^16 (Thm. 2: a polygon of share S_p of B has
-// them at 1/S_p on average), so the last case is rare and reads the full
-// value then.  The collision fraction reads 17k/8 bytes a candidate
-// instead of 4k.
-__device__ __forceinline__ uint32_t hi_bits4(uint4 v)
-{
-    return (uint32_t)((v.x >> 16) != 0) | ((uint32_t)((v.y >> 16) != 0) << 1) |
-           ((uint32_t)((v.z >> 16) != 0) << 2) | ((uint32_t)((v.w >> 16) != 0) << 3);
-}
+// Saturated signature table: value i of signature r as min(value, 65535),
+// 16 bits, so 2k bytes a row (whole 128-byte lines at k = 256) instead of
+// 4k.  Two values are equal exactly when their saturated copies are equal
+// and below 65535, or both copies are 65535 and the full values are equal;
+// first hits average 1/S_p draws (Thm. 2), so at the configured data sets'
+// shares almost every value lies below 65535 and the full table is read
+// only for the rare hashes where both the query's and the candidate's value
+// saturate.
+__device__ __forceinline__ uint32_t sat16(uint32_t v) { return v < 0xffffu ? v : 0xffffu; }
 
-// One wavefront per row: lane l packs values 4l .. 4l+3.
+// Lane l saturates values 4l .. 4l+3 of a row; a wavefront takes a row.
 __global__ __launch_bounds__(256) void k_sig_pack(const uint32_t *__restrict__ sig, int64_t n, int32_t k,
-                                                  uint8_t *__restrict__ packed)
+                                                  uint16_t *__restrict__ packed)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)k * 17 / 8;
     const bool in = 4 * lane < k;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nw) {
-        const uint4 v = in ? *reinterpret_cast<const uint4 *>(sig + r * k + 4 * lane) : make_uint4(0, 0, 0, 0);
-        uint8_t *row = packed + r * stride;
-        if (in)
-            *reinterpret_cast<uint2 *>(row + 8 * lane) =
-                make_uint2((v.x & 0xffffu) | (v.y << 16), (v.z & 0xffffu) | (v.w << 16));
-        // lanes 8w .. 8w+7 hold the 32 bits of word w
-        uint32_t bits = hi_bits4(v) << (4 * (lane & 7));
-        bits |= __shfl_xor(bits, 1, 64);
-        bits |= __shfl_xor(bits, 2, 64);
-        bits |= __shfl_xor(bits, 4, 64);
-        if (in && (lane & 7) == 0) *reinterpret_cast<uint32_t *>(row + 2 * k + 4 * (lane >> 3)) = bits;
+        if (!in) continue;
+        const uint4 v = *reinterpret_cast<const uint4 *>(sig + r * k + 4 * lane);
+        *reinterpret_cast<uint2 *>(packed + r * k + 4 * lane) =
+            make_uint2(sat16(v.x) | (sat16(v.y) << 16), sat16(v.z) | (sat16(v.w) << 16));
     }
 }
 
-// k_rank_jhat_sort on the split rows (k a multiple of 64, at most 256): a
-// lane compares 4 hashes, reading their low halves (8 bytes) and the word
-// of their bits; the full table `dsig` is read only for values whose high
-// halves are both nonzero and whose low halves agree.
+// k_rank_jhat_sort on the saturated table (k a multiple of 4, at most 256):
+// a lane compares 4 hashes from 8 bytes of the candidate's row; the full
+// table `dsig` is read only where the query's and the candidate's copies
+// both saturate.
 __global__ __launch_bounds__(1024, 8) void k_rank_jhat_packed(const uint32_t *__restrict__ qsig,
-                                                           const uint8_t *__restrict__ packed,
-                                                           const uint32_t *__restrict__ dsig, int32_t k,
-                                                           const int64_t *__restrict__ off,
-                                                           const int32_t *__restrict__ cand_ids,
-                                                           float *__restrict__ score,
-                                                           int32_t *__restrict__ order,
-                                                           uint8_t *__restrict__ sorted_ok)
+                                                              const uint16_t *__restrict__ packed,
+                                                              const uint32_t *__restrict__ dsig, int32_t k,
+                                                              const int64_t *__restrict__ off,
+                                                              const int32_t *__restrict__ cand_ids,
+                                                              float *__restrict__ score,
+                                                              int32_t *__restrict__ order,
+                                                              uint8_t *__restrict__ sorted_ok)
 {
     __shared__ CountSortLds<16> L;
     const int64_t q = blockIdx.x;
@@ -396,13 +383,13 @@ __global__ __launch_bounds__(1024, 8) void k_rank_jhat_packed(const uint32_t *__
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nwave = (int)(blockDim.x >> 6);
     for (int v = threadIdx.x; v < kCountBins; v += blockDim.x) L.bin[v] = 0;
-    const int64_t stride = (int64_t)k * 17 / 8;
     const float inv_k = 1.0f / (float)k;
     const bool in = 4 * lane < k;
     const uint4 qv = in ? *reinterpret_cast<const uint4 *>(qsig + q * (int64_t)k + 4 * lane) : make_uint4(0, 0, 0, 0);
-    const uint32_t qlo0 = (qv.x & 0xffffu) | (qv.y << 16), qlo1 = (qv.z & 0xffffu) | (qv.w << 16);
-    const uint32_t qbits = hi_bits4(qv);
-    const int mword = 2 * k + 4 * (lane >> 3), mshift = 4 * (lane & 7);
+    const uint32_t qs0 = sat16(qv.x) | (sat16(qv.y) << 16), qs1 = sat16(qv.z) | (sat16(qv.w) << 16);
+    // hashes whose query value saturates: equal copies need the full values
+    const uint32_t qsat = (uint32_t)(qv.x >= 0xffffu) | ((uint32_t)(qv.y >= 0xffffu) << 1) |
+                          ((uint32_t)(qv.z >= 0xffffu) << 2) | ((uint32_t)(qv.w >= 0xffffu) << 3);
     constexpr int kU = 8;
     int32_t idn[kU];
 #pragma unroll
@@ -411,14 +398,11 @@ __global__ __launch_bounds__(1024, 8) void k_rank_jhat_packed(const uint32_t *__
         idn[u] = n > 0 ? cand_ids[a + i] : 0;
     }
     for (int i0 = wave * kU; i0 < n; i0 += nwave * kU) {
-        uint2 lo[kU];
-        uint32_t mk[kU];
+        uint2 cv[kU];
         int32_t idc[kU];
 #pragma unroll
         for (int u = 0; u < kU; u++) {
-            const uint8_t *row = packed + (int64_t)idn[u] * stride;
-            lo[u] = in ? *reinterpret_cast<const uint2 *>(row + 8 * lane) : make_uint2(0, 0);
-            mk[u] = in ? *reinterpret_cast<const uint32_t *>(row + mword) : 0u;
+            cv[u] = in ? *reinterpret_cast<const uint2 *>(packed + (int64_t)idn[u] * k + 4 * lane) : make_uint2(0, 0);
             idc[u] = idn[u];
         }
 #pragma unroll
@@ -426,15 +410,12 @@ __global__ __launch_bounds__(1024, 8) void k_rank_jhat_packed(const uint32_t *__
 #pragma unroll
         for (int u = 0; u < kU; u++) {
             const int i = i0 + u;
-            const uint32_t cb = (mk[u] >> mshift) & 15u;
-            const uint32_t d0 = lo[u].x ^ qlo0, d1 = lo[u].y ^ qlo1;
-            // equal low halves and equal high-half flags
+            const uint32_t d0 = cv[u].x ^ qs0, d1 = cv[u].y ^ qs1;
             uint32_t eq = (uint32_t)((d0 & 0xffffu) == 0) | ((uint32_t)((d0 >> 16) == 0) << 1) |
                           ((uint32_t)((d1 & 0xffffu) == 0) << 2) | ((uint32_t)((d1 >> 16) == 0) << 3);
-            eq &= ~(cb ^ qbits) & 15u;
             if (!in) eq = 0;
-            // both high halves nonzero: compare the full values
-            const uint32_t need = eq & cb;
+            // both copies saturated: compare the full values
+            const uint32_t need = eq & qsat;
             if (__ballot(need != 0)) {
                 if (need) {
                     const uint4 fv = *reinterpret_cast<const uint4 *>(dsig + (int64_t)idc[u] * k + 4 * lane);
@@ -832,7 +813,7 @@ polymh_status launch_rank_jhat_sort(const uint32_t *qsig, const uint32_t *dsig, 
     return check_launch("rank_jhat");
 }
 
-polymh_status launch_sig_pack(const uint32_t *sig, int64_t n, int32_t k, uint8_t *packed, hipStream_t s)
+polymh_status launch_sig_pack(const uint32_t *sig, int64_t n, int32_t k, uint16_t *packed, hipStream_t s)
 {
     if (n == 0) return POLYMH_OK;
     const int64_t blocks = std::min<int64_t>((n + 3) / 4, 1 << 20);
@@ -840,7 +821,7 @@ polymh_status launch_sig_pack(const uint32_t *sig, int64_t n, int32_t k, uint8_t
     return check_launch("sig_pack");
 }
 
-polymh_status launch_rank_jhat_packed(const uint32_t *qsig, const uint8_t *packed, const uint32_t *dsig, int32_t k,
+polymh_status launch_rank_jhat_packed(const uint32_t *qsig, const uint16_t *packed, const uint32_t *dsig, int32_t k,
                                       const int64_t *off, const int32_t *cand_ids, int64_t nq, float *score,
                                       int32_t *order, uint8_t *sorted_ok, hipStream_t s)
 {

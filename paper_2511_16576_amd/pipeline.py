@@ -34,8 +34,9 @@ class QueryBatch:
         "scorer" need the data signatures ``dsig`` ([N][k]); "scorer" also
         the trained ``scorer`` (params, BF16 weights) and the data shape
         features ``dfeat``.  ``dpacked`` (``pm.sig_pack(dsig)``, optional)
-        lets the collision fraction read the split table of the data
-        signatures (the same scores and order, fewer bytes a candidate)."""
+        lets the collision fraction read the saturated 16-bit table of the
+        data signatures (the same scores and order, half the bytes a
+        candidate)."""
         dev = D.offsets.device
         self.D, self.sk, self.se = D, sorted_keys, sorted_ent
         self.box, self.seed, self.k, self.cap = box, seed, k, cap

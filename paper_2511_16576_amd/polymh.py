@@ -649,14 +649,12 @@ def rank_refine(data: DevicePolys, queries: DevicePolys, cand_off, cand_ids, sco
 
 
 def sig_pack(sig, out=None, stream=None):
-    """The split signature table of sig [n][k] (k a multiple of 64 up to
-    256): uint8 [n][17k/8], per row the k low 16-bit halves, then the bits
-    of the values of 2^16 and more."""
+    """The saturated signature table of sig [n][k] (k a multiple of 4 up to
+    256): uint16 bit patterns in an int16 tensor [n][k], min(value, 65535)."""
     n, k = sig.shape
-    stride = int(lib().polymh_sig_pack_stride(k))
-    if stride == 0:
-        raise ValueError("the split signature table needs k a multiple of 64 in [64, 256]")
-    out = torch.empty((max(n, 1), stride), dtype=torch.uint8, device=sig.device) if out is None else out
+    if int(lib().polymh_sig_pack_stride(k)) == 0:
+        raise ValueError("the saturated signature table needs k a multiple of 4 in [4, 256]")
+    out = torch.empty((max(n, 1), k), dtype=torch.int16, device=sig.device) if out is None else out
     _check(lib().polymh_sig_pack(_ptr(sig), n, k, _ptr(out), _stream(stream)))
     return out
 
@@ -665,8 +663,8 @@ def rank_jhat_order(qsig, dsig, cand_off, cand_ids, score=None, order=None, sort
                     packed=None):
     """Collision fraction of every candidate and each query's best-first
     order: (score float32 [C], order int32 [C], sorted_ok uint8 [nq]).  With
-    ``packed`` (``sig_pack(dsig)``) the candidates are read from the split
-    table; the result is the same."""
+    ``packed`` (``sig_pack(dsig)``) the candidates are read from the
+    saturated table; the result is the same."""
     nq = cand_off.numel() - 1
     dev = cand_off.device
     C = cand_ids.numel()

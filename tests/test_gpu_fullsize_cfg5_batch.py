@@ -2,13 +2,13 @@
 benchmark times: 4,000,000 polygons signed from binned samples, 64 x 4
 bands, 10,000 queries signed from binned samples, looked up and refined as
 four sub-batches on streams forked inside one captured graph, ordered by
-the collision fraction (read from the split signature table) with early
+the collision fraction (read from the saturated signature table) with early
 stop (first rounds of 16, 4 rounds, margin 0.01), and beside it the plain
 batch (every candidate refined, one graph).  For five sampled queries of
 every sub-batch (its first and last among them, and one of 257 to 2,048
 vertices) the oracle recomputes, one by one: the query's signature and
 band keys; the signatures of all its candidates (bit-exact against the
-indexed rows and their rows of the split table; each shares a band key
+indexed rows and their rows of the saturated table; each shares a band key
 with the query, the list is ascending and free of repeats, and none of
 2,000 random other polygons shares a key); every candidate's collision
 fraction and the best-first order; the early stop's top-10 from its own
@@ -94,8 +94,8 @@ def test_query_batch_workload5_full_size(orc):
     others = np.sort(rng.choice(w.data.n, 2000, replace=False))
     okeys = orc.band(orc.sign(w.data.subset(others), w.box, w.seed, k, cap), BANDS, ROWS, w.seed)
     gsig = sig.cpu().numpy().view(np.uint32)
-    gpk = packed.cpu().numpy()
-    assert ((gsig >> 16) != 0).any(), "values of 2^16 and more: the split comparison reads full values"
+    gpk = packed.cpu().numpy().view(np.uint16)
+    assert (gsig >= 65535).any(), "values of 65535 and more: the comparison reads full values"
     for q in sample:
         t1 = time.time()
         p = int(np.searchsorted([b for _, b in jb.bounds], q, side="right"))
@@ -111,11 +111,8 @@ def test_query_batch_workload5_full_size(orc):
         assert cand.size > 0 and np.all(np.diff(cand) > 0), q
         osig = orc.sign(w.data.subset(cand), w.box, w.seed, k, cap)
         assert np.array_equal(gsig[cand], osig), q
-        # their rows of the split table: low halves, then high-half bits
-        assert np.array_equal(gpk[cand, :2 * k].copy().view("<u2"), (osig & 0xFFFF).astype(np.uint16)), q
-        words = gpk[cand, 2 * k:].copy().view("<u4")
-        bits = ((words[:, :, None] >> np.arange(32, dtype=np.uint32)) & 1).reshape(cand.size, k)
-        assert np.array_equal(bits, (osig >> 16) != 0), q
+        # their rows of the saturated table
+        assert np.array_equal(gpk[cand], np.minimum(osig, 65535).astype(np.uint16)), q
         assert (orc.band(osig, BANDS, ROWS, w.seed) == oqk[None, :]).any(axis=1).all(), q
         outside = ~np.isin(others, cand)
         assert not (okeys[outside] == oqk[None, :]).any(), q
