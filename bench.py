@@ -67,9 +67,9 @@ def parse():
     ap.add_argument("--head-rows", type=int, default=4)
     ap.add_argument("--calib", type=int, default=1000, help="calibration queries (recall of the early stop)")
     ap.add_argument("--eval", type=int, default=1000, help="held-out queries for the reported recall")
-    ap.add_argument("--rank-F-grid", type=lambda x: [int(v) for v in x.split(",")], default=[8, 10, 12, 16],
+    ap.add_argument("--rank-F-grid", type=lambda x: [int(v) for v in x.split(",")], default=[12, 16, 20, 22, 24, 28],
                     help="first-round sizes tried for the early stop (comma list)")
-    ap.add_argument("--rank-rounds-grid", type=lambda x: [int(v) for v in x.split(",")], default=[3, 4, 5],
+    ap.add_argument("--rank-rounds-grid", type=lambda x: [int(v) for v in x.split(",")], default=[1, 2, 3, 4],
                     help="early-stop round counts tried (rounds of F, F, 2F, 4F, ... before the finishing pass)")
     ap.add_argument("--scorer-head", type=int, default=16, help="candidates per query the network re-scores")
     ap.add_argument("--head-parts", type=int, default=4,
@@ -107,7 +107,7 @@ def parse():
 # early-stop margins tried in order (the first reaching the recall target
 # on the calibration queries is kept); a negative margin stops before the
 # next candidate's predicted J falls below the 10th exact J
-MARGINS = [-0.12, -0.1, -0.08, -0.07, -0.06, -0.05, -0.04, -0.03, -0.025, -0.02, -0.015, -0.01, -0.005, 0.0, 0.005, 0.01, 0.015, 0.02, 0.025,
+MARGINS = [-0.3, -0.2, -0.15, -0.12, -0.1, -0.08, -0.07, -0.06, -0.05, -0.04, -0.03, -0.025, -0.02, -0.015, -0.01, -0.005, 0.0, 0.005, 0.01, 0.015, 0.02, 0.025,
            0.03, 0.04, 0.05, 0.06, 0.08, 0.1, 0.15, 0.2, 0.3, 0.5]
 
 
