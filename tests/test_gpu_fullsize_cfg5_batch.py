@@ -40,12 +40,13 @@ def _assert_top_equal(got_ids, got_j, want_ids, want_j, ctx):
         assert want_ids[t] >= 0 and (tied >= 2 or t == want_ids.size - 1), (ctx, t)
 
 
-def test_query_batch_workload5_full_size(orc):
+@pytest.fixture(scope="module")
+def state(orc):
+    """Workload 5 in full: the indexed data set and the batch's setup."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2511_16576_amd import polymh as pm
-    from paper_2511_16576_amd.pipeline import SplitBatch
     pm.check_device()
     t0 = time.time()
     w = dg.workload(5, n_queries=10000)
@@ -64,6 +65,15 @@ def test_query_batch_workload5_full_size(orc):
     common = dict(sign_config=pm.binned_config(Qd), binned=binned, dsig=sig)
     args = (D, sk, se, w.box, w.seed, k, cap, BANDS, ROWS, nq, w.queries.xy.shape[0], cand_cap)
     packed = pm.sig_pack(sig)
+    yield dict(w=w, D=D, sig=sig, packed=packed, common=common, args=args, cand_cap=cand_cap)
+    torch.cuda.empty_cache()
+
+
+def test_query_batch_workload5_full_size(orc, state):
+    from paper_2511_16576_amd.pipeline import SplitBatch
+    w, sig, packed, common, args = state["w"], state["sig"], state["packed"], state["common"], state["args"]
+    nq, k, cap = w.queries.n, w.k, w.cap
+    cand_cap = state["cand_cap"]
     jb = SplitBatch(*args, parts=PARTS, method="jhat", F=F, rounds=ROUNDS, margin=MARGIN, dpacked=packed,
                     **common)
     jb.load(w.queries)
@@ -137,3 +147,90 @@ def test_query_batch_workload5_full_size(orc):
         _assert_top_equal(p_ids[q], p_j[q], ti[0], tj[0], ("plain", q))
         print(f"query {q} (sub-batch {p}, {nv[q]} vertices): {cand.size} candidates, {r['refined']} refined by "
               f"the early stop; checked in {time.time() - t1:.1f}s", flush=True)
+    del jb, pb
+
+
+# the learned batch as the benchmark runs it: the network re-scores each
+# query's first 16 candidates by collision fraction, the order is rebuilt,
+# then rounds of 24 (two rounds, margin -0.3)
+HEAD, F_L, ROUNDS_L, MARGIN_L = 16, 24, 2, -0.3
+
+
+def test_learned_batch_workload5_full_size(orc, state):
+    """The learned batch in the benchmark's launch configuration (a seeded
+    network: its arithmetic, not its training, is under test).  For sampled
+    queries: the head slots are the collision-fraction order's first 16; their
+    new scores are the oracle's FP64 network on the oracle's feature rows
+    (within the BF16 rounding between the layers), the other scores the
+    oracle's collision fractions exactly; the rebuilt order sorts the final
+    scores (desc, position asc); and the top-10 is the exact top-10 (the
+    oracle's J) of the first 24 or 48 candidates of that order, or of the
+    whole list."""
+    import torch
+    from oracle import mlp as om
+    from paper_2511_16576_amd import polymh as pm
+    from paper_2511_16576_amd import scorer as sc
+    from paper_2511_16576_amd.pipeline import SplitBatch
+    w, D, sig, packed = state["w"], state["D"], state["sig"], state["packed"]
+    k, cap = w.k, w.cap
+    net = sc.init_scorer(5)
+    dfeat = pm.poly_features(D, w.box)
+    lb = SplitBatch(*state["args"], parts=PARTS, method="scorer", scorer=net, dfeat=dfeat, head=HEAD, F=F_L,
+                    rounds=ROUNDS_L, margin=MARGIN_L, dpacked=packed, **state["common"])
+    lb.load(w.queries)
+    lb.capture()
+    for _ in range(2):
+        lb.run_graph()
+    l_ids, l_j = (x.cpu().numpy() for x in lb.result())
+    p = net.params.cpu().numpy()
+    p[om.OFF_W1:om.OFF_B1] = om.bf16_round(p[om.OFF_W1:om.OFF_B1])
+    p[om.OFF_W2:om.OFF_B2] = om.bf16_round(p[om.OFF_W2:om.OFF_B2])
+    p = p.astype(np.float64)
+    rng = np.random.default_rng(61)
+    sample = []
+    for a, b in lb.bounds:
+        sample += [a, b - 1] + rng.choice(np.arange(a + 1, b - 1), 2, replace=False).tolist()
+    for q in sample:
+        t1 = time.time()
+        pi = int(np.searchsorted([b for _, b in lb.bounds], q, side="right"))
+        part, lq = lb.parts[pi], q - lb.bounds[pi][0]
+        o = part.cand_off.cpu().numpy()
+        a, b = int(o[lq]), int(o[lq + 1])
+        cand = part.cand_ids[a:b].cpu().numpy()
+        oq = orc.sign(w.queries.subset([q]), w.box, w.seed, k, cap)
+        osig = orc.sign(w.data.subset(cand), w.box, w.seed, k, cap)
+        pred = oracle.collision_fraction(oq[0], osig).astype(np.float32)
+        jorder, _ = oracle.best_first(pred)
+        assert np.array_equal(part.order[a:b].cpu().numpy(), jorder), q
+        # the head slots: the first 16 of the collision-fraction order
+        nh = min(HEAD, cand.size)
+        hc = part.hc[lq * HEAD:(lq + 1) * HEAD].cpu().numpy()
+        hid = part.hid[lq * HEAD:(lq + 1) * HEAD].cpu().numpy()
+        assert np.array_equal(hc[:nh], a + jorder[:nh]) and (hc[nh:] == -1).all(), q
+        assert np.array_equal(hid[:nh], cand[jorder[:nh]]), q
+        # final scores: the network on the head, the collision fraction elsewhere
+        score = part.score[a:b].cpu().numpy()
+        rest = np.setdiff1d(np.arange(cand.size), jorder[:nh])
+        assert np.array_equal(score[rest], pred[rest]), q
+        qf = om.poly_features(w.queries.poly(q), w.box)
+        rows = np.stack([om.pair_features(oq[0], qf, osig[j], om.poly_features(w.data.poly(cand[j]), w.box))
+                         for j in jorder[:nh]])
+        want = om.forward(om.bf16_round(rows.astype(np.float32)).astype(np.float64), p)["y"]
+        assert np.abs(score[jorder[:nh]] - want).max() < 2 ** -6, q
+        # the rebuilt order sorts the final scores
+        forder, srt = oracle.best_first(score)
+        assert srt and np.array_equal(part.order2[a:b].cpu().numpy(), forder), q
+        # the top-10: the exact top-10 of the candidates a round reached
+        one = w.queries.subset([q])
+        Jall = orc.jaccard_candidates(w.data, one, np.array([0, cand.size]), cand)
+        fits = []
+        for r in (F_L, 2 * F_L, cand.size):
+            sel = forder[:r]
+            ti, tj = oracle.topk(np.array([0, sel.size]), cand[sel], Jall[sel], 10)
+            if np.allclose(l_j[q], tj[0], rtol=REL, atol=ABS):
+                fits.append(r)
+                _assert_top_equal(l_ids[q], l_j[q], ti[0], tj[0], ("learned", q, r))
+        assert fits, q
+        print(f"query {q} (sub-batch {pi}): {cand.size} candidates, top-10 of the first {fits[0]} refined; "
+              f"checked in {time.time() - t1:.1f}s", flush=True)
+    del lb
