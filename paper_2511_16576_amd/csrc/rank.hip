@@ -681,6 +681,7 @@ __global__ __launch_bounds__(256) void k_reorder_head(const int64_t *__restrict_
 {
     __shared__ float hs[4][64];
     __shared__ int hp[4][64];
+    __shared__ int hc[4][65];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
@@ -710,31 +711,49 @@ __global__ __launch_bounds__(256) void k_reorder_head(const int64_t *__restrict_
     }
     hs[wave][lane] = sc;
     hp[wave][lane] = p;
+    hc[wave][lane] = 0;
+    if (lane == 0) hc[wave][64] = 0;
     wave_fence_lds();
     const int tail = n - h;
-    // head element `lane`: place = lane + number of tail candidates before it
-    if (lane < h) {
-        int lo = 0, hi = tail;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            const int pm = order_in[a + h + mid];
-            if (key_before(score[a + pm], pm, sc, p)) lo = mid + 1;
-            else hi = mid;
+    // tail element j (the unchanged, sorted rest) goes to j + lo_j, lo_j the
+    // head elements before it (a search of the head in LDS); its order
+    // entries and scores are loaded eight a lane ahead, so a list costs a few
+    // round trips to memory.  Head element i goes to i + the tail elements
+    // before it, those with lo_j <= i: counted per lo_j, then summed.
+    constexpr int kU = 8;
+    for (int j0 = 0; j0 < tail; j0 += 64 * kU) {
+        int pt[kU];
+        float st[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int j = j0 + 64 * u + lane;
+            pt[u] = j < tail ? order_in[a + h + j] : 0;
         }
-        order_out[a + lane + lo] = p;
-    }
-    // tail element j: place = j + number of head elements before it
-    for (int j = lane; j < tail; j += 64) {
-        const int pt = order_in[a + h + j];
-        const float st = score[a + pt];
-        int lo = 0, hi = h;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (key_before(hs[wave][mid], hp[wave][mid], st, pt)) lo = mid + 1;
-            else hi = mid;
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int j = j0 + 64 * u + lane;
+            st[u] = j < tail ? score[a + pt[u]] : 0.0f;
         }
-        order_out[a + j + lo] = pt;
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const int j = j0 + 64 * u + lane;
+            if (j < tail) {
+                int lo = 0, hi = h;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (key_before(hs[wave][mid], hp[wave][mid], st[u], pt[u])) lo = mid + 1;
+                    else hi = mid;
+                }
+                order_out[a + j + lo] = pt[u];
+                atomicAdd(&hc[wave][lo], 1);
+            }
+        }
     }
+    wave_fence_lds();
+    // head element `lane`: lane + (tail elements with lo_j <= lane)
+    const int c = hc[wave][lane];
+    const int before = wave_incl_scan32(c);
+    if (lane < h) order_out[a + lane + before] = p;
 }
 
 __global__ void k_scatter_scores(const int64_t *__restrict__ idx, const float *__restrict__ val,
