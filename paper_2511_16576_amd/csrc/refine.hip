@@ -852,15 +852,17 @@ constexpr int kWideListCap = 1 << 20;
 
 // A pair that spans more than two window pairs (of kWideCap edges a side) is
 // split into units of one wavefront each: P windows of plen edges (the
-// shortest of 256, 512 and kWideCap that keeps the units within
-// kMultiUnits), each walking Q's windows, or, when Q has more than two
-// windows, each (P window, Q window) alone.  Every unit writes its partial
-// sums, all linear in the crossing signs, and k_refine_multi_finish adds them
-// in window order.  Up to kMultiCap such pairs per call (the rest take all
-// their windows on one wavefront).
+// shortest of 256, 512 and kWideCap that keeps the units within half of
+// kMultiUnits; in the small calls of the early-stop rounds, where the
+// longest unit sets the launch's end, within kMultiUnits, and 128 for a
+// staged polygon of kSplitFineP edges or more), each walking Q's windows,
+// or, when Q has more than two windows, each (P window, Q window) alone.
+// Every unit writes its partial sums, all linear in the crossing signs, and
+// k_refine_multi_finish adds them in window order.  Up to kMultiCap such
+// pairs per call (the rest take all their windows on one wavefront).
 constexpr int kMultiCap = 4096;
-constexpr int kMultiUnits = 256;
-constexpr int kSplitMinP = 256;
+constexpr int kMultiUnits = 512;
+constexpr int kSplitFineP = 4096;
 
 struct SplitShape {
     int plen;             // P window length of the units
@@ -870,20 +872,22 @@ struct SplitShape {
 
 // The split of a pair whose staged polygon (P's role) has np edges and the
 // other nq; deterministic, so the wide kernel and the finish recompute it.
-__device__ __forceinline__ int split_plen(int np, int qs)
+__device__ __forceinline__ int split_plen(int np, int qs, bool fine)
 {
-    return ((np + 255) >> 8) * qs <= kMultiUnits ? 256
-         : ((np + 511) >> 9) * qs <= kMultiUnits ? 512
-         : ((np + 1023) >> 10) * qs <= kMultiUnits ? 1024 : 0;
+    const int cap = fine ? kMultiUnits : kMultiUnits / 2;
+    return (fine && np >= kSplitFineP && ((np + 127) >> 7) * qs <= cap) ? 128
+         : ((np + 255) >> 8) * qs <= cap ? 256
+         : ((np + 511) >> 9) * qs <= cap ? 512
+         : ((np + 1023) >> 10) * qs <= cap ? 1024 : 0;
 }
 
-__device__ __forceinline__ SplitShape split_shape(int np, int nq)
+__device__ __forceinline__ SplitShape split_shape(int np, int nq, bool fine)
 {
     const int npw = (np + kWideCap - 1) / kWideCap, nqw = (nq + kWideCap - 1) / kWideCap;
     if (npw * nqw <= 2) return {kWideCap, 1, 1};
     int qs = nqw > 2 ? nqw : 1;
-    int plen = split_plen(np, qs);
-    if (plen == 0 && qs > 1) plen = split_plen(np, qs = 1);
+    int plen = split_plen(np, qs, fine);
+    if (plen == 0 && qs > 1) plen = split_plen(np, qs = 1, fine);
     if (plen == 0) return {kWideCap, 1, 1};
     return {plen, qs, (np + plen - 1) / plen * qs};
 }
@@ -921,6 +925,7 @@ struct HeavyWs {
     WidePair *wide;       // [kWideListCap]
     MultiPair *multi;     // [kMultiCap]
     MultiUnit *units;     // [kMultiCap][kMultiUnits]
+    int32_t fine;         // the call's split rule (split_plen)
 };
 
 // Records a pair for k_refine_wide as one list entry (k_expand splits the
@@ -1280,7 +1285,7 @@ __global__ __launch_bounds__(256) void k_expand(const int64_t *__restrict__ qoff
         const WidePair w = hw.wide[i];
         const int mq = (int)(qoff[w.q + 1] - qoff[w.q]);
         const bool swap = w.n > kWideCap && w.n > mq;
-        const SplitShape sh = split_shape(swap ? mq : w.n, swap ? w.n : mq);
+        const SplitShape sh = split_shape(swap ? mq : w.n, swap ? w.n : mq, hw.fine != 0);
         if (sh.units <= 1) continue;
         const int ms = atomicAdd(hw.count + 2, 1);
         if (ms >= kMultiCap) continue;
@@ -1350,7 +1355,7 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
         const int64_t ox = Qg[0], oy = Qg[1];
         // windows of this entry: all, or one P window (and one Q window) of
         // a split pair
-        const SplitShape sh = split_shape(n, m);
+        const SplitShape sh = split_shape(n, m, hw.fine != 0);
         const int pfirst = w.pw < 0 ? 0 : w.pw * sh.plen;
         const int pend = w.pw < 0 ? n : min(n, pfirst + sh.plen);
         const int qfirst = w.qw < 0 ? 0 : w.qw * kWideCap;
@@ -1483,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__re
             }
             if (kq < 0) wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
             const int sp = a2p > 0 ? 1 : -1, sq = a2q > 0 ? 1 : -1;
-            const SplitShape sh = split_shape(n, m);
+            const SplitShape sh = split_shape(n, m, hw.fine != 0);
             const int pk = kp / sh.plen;
             // lanes take the P windows, 64 at a time; the carry of crossing
             // signs into each is a scan in window order
@@ -1614,13 +1619,14 @@ size_t refine_workspace_bytes()
 polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, hipStream_t s,
-                            unsigned long long *stats, void *ws, size_t ws_bytes)
+                            unsigned long long *stats, void *ws, size_t ws_bytes, bool fine_split)
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
     HeavyWs hw{};
     if (ws) {
         Carve cv{static_cast<char *>(ws), ws_bytes};
         hw = carve_heavy(cv);
+        hw.fine = fine_split ? 1 : 0;
         if (!cv.ok) return set_error(POLYMH_ECAPACITY, "refine: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
         hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(kStatSlots * 4), 0, s, hw.count, hw.stat_slots);
     }

@@ -459,6 +459,43 @@ def _subdivided_rect(x0, y0, x1, y1, k):
                            np.stack([np.full(k, x0), y1 - h * i // k], 1)]).astype(np.int64)
 
 
+def test_ranked_rounds_split_large_pairs_finer(pm):
+    """The early-stop rounds split pairs with very large polygons finer (P
+    windows of 128 edges for a staged polygon of 4,096 edges or more, up to
+    512 units a pair): 6,000-vertex squares (128-edge P windows, each with
+    one of the 6 Q windows), 9,000-vertex squares (256-edge windows) and
+    20,000-vertex squares (1,024-edge windows, each with one of the 20 Q
+    windows) give the exact J, as refine's coarser split does."""
+    import torch
+    L6, L9, L20 = 6000, 9000, 20000
+    a6 = _subdivided_rect(0, 0, L6, L6, 1500)
+    a9 = _subdivided_rect(0, 0, L9, L9, 2250)
+    a20 = _subdivided_rect(0, 0, L20, L20, 5000)
+    cases = [
+        (a6, a6, Fraction(1)), (a6, _subdivided_rect(L6 // 2, 0, L6 // 2 + L6, L6, 1500), Fraction(1, 3)),
+        (a6[::-1], a6, Fraction(1)),
+        (a9, a9, Fraction(1)), (a9, _subdivided_rect(L9 // 2, 0, L9 // 2 + L9, L9, 2250), Fraction(1, 3)),
+        (a20, _subdivided_rect(L20 // 2, 0, L20 // 2 + L20, L20, 5000), Fraction(1, 3)),
+    ]
+    D = pm.to_device(dg.from_list([c[0] for c in cases]))
+    Q = pm.to_device(dg.from_list([c[1] for c in cases]))
+    n = len(cases)
+    off = torch.arange(n + 1, dtype=torch.int64, device="cuda")
+    ids = torch.arange(n, dtype=torch.int32, device="cuda")
+    score = torch.zeros(n, dtype=torch.float32, device="cuda")
+    order = torch.empty(n, dtype=torch.int32, device="cuda")
+    ok = torch.empty(n, dtype=torch.uint8, device="cuda")
+    pm.rank_order(off, score, order, ok)
+    t_ids, t_j, cnt = pm.rank_refine_ordered(D, Q, off, ids, score, order, ok, topk=1, F=1, rounds=1,
+                                             margin=float("inf"))
+    got = t_j.cpu().numpy()[:, 0]
+    for j, (_, _, want) in enumerate(cases):
+        assert abs(got[j] - float(want)) <= 1e-12, (j, got[j], want)
+    assert (t_ids.cpu().numpy()[:, 0] == np.arange(n)).all()
+    coarse = pm.refine(D, Q, off, ids).cpu().numpy()
+    assert np.allclose(got, coarse, rtol=1e-12, atol=1e-12)
+
+
 def test_refine_wide_tiled_degenerate_contacts(pm, orc):
     # the degenerate contacts of the small cases at 513 to 1024 edges: every
     # side of a 400 x 400 square carries 200 (or 150) vertices, so edges
@@ -561,20 +598,24 @@ def test_refine_windowed_degenerate_contacts(pm, orc):
 
 
 def test_refine_split_units_exact(pm):
-    # exact J for pairs split into units of each shape: 9,000-vertex squares
-    # (P windows of 512 edges, each with one of the 9 Q windows: windows of
-    # 256 would give more than 256 units), 20,000-vertex squares (P windows
-    # of 256 edges walking all 20 Q windows: a unit per Q window would
-    # exceed the cap) and a 4-vertex rectangle against a 20,000-vertex
-    # square, either way round (one P window, each of the 20 Q windows a
-    # unit of its own); collinear overlaps, shared edges and a reversed ring
-    # included
+    # exact J for pairs split into units of each shape: 6,000-vertex squares
+    # (P windows of 256 edges, each with one of the 6 Q windows), 9,000-vertex
+    # squares (P windows of 512 edges, each with one of the 9 Q windows:
+    # windows of 256 would give more than 256 units), 20,000-vertex squares
+    # (P windows of 256 edges walking all 20 Q windows: a unit per Q window
+    # would exceed the cap) and a 4-vertex rectangle against a 20,000-vertex
+    # square, either way round (one P window, each of the 20 Q windows a unit
+    # of its own); collinear overlaps, shared edges and a reversed ring
+    # included.  (The early-stop rounds split finer: see
+    # test_ranked_rounds_split_large_pairs_finer.)
     import torch
-    L9, L20 = 9000, 20000
+    L6, L9, L20 = 6000, 9000, 20000
+    a6 = _subdivided_rect(0, 0, L6, L6, 1500)
     a9 = _subdivided_rect(0, 0, L9, L9, 2250)
     a20 = _subdivided_rect(0, 0, L20, L20, 5000)
     small = dg.rectangle(1000, 1000, 3000, 5000)
     cases = [
+        (a6, a6, Fraction(1)), (a6, _subdivided_rect(L6 // 2, 0, L6 // 2 + L6, L6, 1500), Fraction(1, 3)),
         (a9, a9, Fraction(1)), (a9, a9[::-1], Fraction(1)),
         (a9, _subdivided_rect(L9 // 2, 0, L9 // 2 + L9, L9, 2250), Fraction(1, 3)),
         (a9, _subdivided_rect(L9, 0, 2 * L9, L9, 2250), Fraction(0)),
