@@ -734,10 +734,8 @@ polymh_status rank_round(const polymh_polys *data, const polymh_polys *queries, 
     // the round's bound (F per query; one workgroup per query for the
     // finishing pass), and workgroups of queries without pairs return at once
     const int64_t hint = finishing ? nq : nq * (int64_t)F;
-    // a round's call is small: the finer split of very large pairs shortens
-    // its longest unit
     if ((st = launch_refine(data, queries, w.roff, w.rids, nq, hint, w.rj, s, nullptr, w.refine_ws,
-                            refine_workspace_bytes(), true)))
+                            refine_workspace_bytes())))
         return st;
     return launch_round_merge(cand_off, score, w.order, w.sorted_ok, w.roff, w.rids, w.rj, nq, topk,
                               finishing ? INFINITY : margin, w.cursor, w.active, top_ids, top_j,

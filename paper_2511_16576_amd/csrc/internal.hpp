@@ -233,8 +233,7 @@ size_t refine_workspace_bytes();
 polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, hipStream_t s,
-                            unsigned long long *stats = nullptr, void *ws = nullptr, size_t ws_bytes = 0,
-                            bool fine_split = false);
+                            unsigned long long *stats = nullptr, void *ws = nullptr, size_t ws_bytes = 0);
 
 // topk.hip
 polymh_status launch_topk(const int64_t *off, const int32_t *ids, const double *js, int64_t nq,

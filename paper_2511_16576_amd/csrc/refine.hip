@@ -468,19 +468,24 @@ __device__ void chunk_boxes_p(RingLds R, int n, int lane)
     }
 }
 
-// One edge's parity term in the membership of point a + sh*delta in a ring
-// (half-open crossing rule with the perturbation): sh = -1 tests a - delta
-// (a vertex of P against Q + delta), sh = +1 tests a + delta (a vertex of
-// Q + delta against P).  A straddling edge is never horizontal.
-__device__ __forceinline__ bool member_edge(const int2 *v, int e, int2 a, int sh)
+// Edge (c, d)'s parity term in the membership of point a + sh*delta in a
+// ring (half-open crossing rule with the perturbation): sh = -1 tests
+// a - delta (a vertex of P against Q + delta), sh = +1 tests a + delta (a
+// vertex of Q + delta against P).  A straddling edge is never horizontal.
+__device__ __forceinline__ bool flips_parity(int2 c, int2 d, int2 a, int sh)
 {
-    const int2 c = v[e], d = v[e + 1];
     const bool st = sh < 0 ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
     const int up = d.y > c.y ? 1 : -1;
     const int tb = sh < 0 ? up : -up;   // sign of orient(c, d, a + sh*delta) when orient(c, d, a) = 0
     const double o = orient_d(c, d, a);
     const int so = o > 0 ? 1 : (o < 0 ? -1 : tb);
     return st & (so == up);
+}
+
+// The same for edge e of a ring in LDS.
+__device__ __forceinline__ bool member_edge(const int2 *v, int e, int2 a, int sh)
+{
+    return flips_parity(v[e], v[e + 1], a, sh);
 }
 
 // Ring-start memberships of both rings in one pass: w0p for P's vertex 0
@@ -851,15 +856,15 @@ constexpr int kWideRing = kWideCap + 16;   // ring vertices incl. padding
 constexpr int kWideListCap = 1 << 20;
 
 // A pair that spans more than two window pairs (of kWideCap edges a side) is
-// split into units of one wavefront each: P windows of plen edges (the
-// shortest of 256, 512 and kWideCap that keeps the units within half of
-// kMultiUnits; in the small calls of the early-stop rounds, where the
-// longest unit sets the launch's end, within kMultiUnits, and 128 for a
-// staged polygon of kSplitFineP edges or more), each walking Q's windows,
-// or, when Q has more than two windows, each (P window, Q window) alone.
-// Every unit writes its partial sums, all linear in the crossing signs, and
-// k_refine_multi_finish adds them in window order.  Up to kMultiCap such
-// pairs per call (the rest take all their windows on one wavefront).
+// split into units of one wavefront each: P windows of plen edges (128 for a
+// staged polygon of kSplitFineP edges or more, else the shortest of 256, 512
+// and kWideCap that keeps the units within kMultiUnits), each walking Q's
+// windows, or, when Q has more than two windows, each (P window, Q window)
+// alone.  k_wide_meta finds the pair's own quantities once (areas, anchors,
+// Q's window carries), every unit writes its partial sums, all linear in the
+// crossing signs, and k_refine_multi_finish adds them in window order.  Up
+// to kMultiCap such pairs per call (the rest take all their windows on one
+// wavefront).
 constexpr int kMultiCap = 4096;
 constexpr int kMultiUnits = 512;
 constexpr int kSplitFineP = 4096;
@@ -872,22 +877,21 @@ struct SplitShape {
 
 // The split of a pair whose staged polygon (P's role) has np edges and the
 // other nq; deterministic, so the wide kernel and the finish recompute it.
-__device__ __forceinline__ int split_plen(int np, int qs, bool fine)
+__device__ __forceinline__ int split_plen(int np, int qs)
 {
-    const int cap = fine ? kMultiUnits : kMultiUnits / 2;
-    return (fine && np >= kSplitFineP && ((np + 127) >> 7) * qs <= cap) ? 128
-         : ((np + 255) >> 8) * qs <= cap ? 256
-         : ((np + 511) >> 9) * qs <= cap ? 512
-         : ((np + 1023) >> 10) * qs <= cap ? 1024 : 0;
+    return (np >= kSplitFineP && ((np + 127) >> 7) * qs <= kMultiUnits) ? 128
+         : ((np + 255) >> 8) * qs <= kMultiUnits ? 256
+         : ((np + 511) >> 9) * qs <= kMultiUnits ? 512
+         : ((np + 1023) >> 10) * qs <= kMultiUnits ? 1024 : 0;
 }
 
-__device__ __forceinline__ SplitShape split_shape(int np, int nq, bool fine)
+__device__ __forceinline__ SplitShape split_shape(int np, int nq)
 {
     const int npw = (np + kWideCap - 1) / kWideCap, nqw = (nq + kWideCap - 1) / kWideCap;
     if (npw * nqw <= 2) return {kWideCap, 1, 1};
     int qs = nqw > 2 ? nqw : 1;
-    int plen = split_plen(np, qs, fine);
-    if (plen == 0 && qs > 1) plen = split_plen(np, qs = 1, fine);
+    int plen = split_plen(np, qs);
+    if (plen == 0 && qs > 1) plen = split_plen(np, qs = 1);
     if (plen == 0) return {kWideCap, 1, 1};
     return {plen, qs, (np + plen - 1) / plen * qs};
 }
@@ -906,6 +910,11 @@ struct MultiPair {
     int64_t c;            // candidate slot (-1: the pair was not deferred)
     int64_t pa;
     int32_t n, q, units, pad;
+    // the pair's own quantities, written by k_wide_meta for its units and
+    // the finish (P and Q in k_refine_wide's roles)
+    int64_t a2p, a2q;     // exact doubled areas
+    int32_t kp, kq;       // anchors (0 where a membership pass stands in)
+    int32_t wkp, wkq;     // memberships of P's vertex 0 in Q, of Q's vertex 0 in P (0 when anchored)
 };
 
 struct MultiUnit {
@@ -913,6 +922,7 @@ struct MultiUnit {
     double cr;            // sum of the P window's cross products (first Q window's unit only)
     int32_t stot;         // sum of the window's crossing signs
     int32_t kloc;         // exclusive prefix of crossing signs at the anchor, if in this window
+    int64_t qpre;         // in: Q's cross-product sum before the unit's Q window (k_wide_meta)
 };
 
 struct HeavyWs {
@@ -925,7 +935,6 @@ struct HeavyWs {
     WidePair *wide;       // [kWideListCap]
     MultiPair *multi;     // [kMultiCap]
     MultiUnit *units;     // [kMultiCap][kMultiUnits]
-    int32_t fine;         // the call's split rule (split_plen)
 };
 
 // Records a pair for k_refine_wide as one list entry (k_expand splits the
@@ -1199,15 +1208,7 @@ __device__ int member_point_global(const int32_t *V, int m, int64_t ox, int64_t 
             dv[k] = ring_vertex(V, m, e + 1, ox, oy);
         }
 #pragma unroll
-        for (int k = 0; k < kPassU; k++) {
-            const int2 c = cv[k], d = dv[k];
-            const bool st = sh < 0 ? ((c.y >= a.y) != (d.y >= a.y)) : ((c.y > a.y) != (d.y > a.y));
-            const int up = d.y > c.y ? 1 : -1;
-            const int tb = sh < 0 ? up : -up;
-            const double o = orient_d(c, d, a);
-            const int so = o > 0 ? 1 : (o < 0 ? -1 : tb);
-            odd ^= (base + 64 * k + lane < m) & st & (so == up);
-        }
+        for (int k = 0; k < kPassU; k++) odd ^= (base + 64 * k + lane < m) & flips_parity(cv[k], dv[k], a, sh);
     }
     return __popcll(__ballot(odd)) & 1;
 }
@@ -1272,6 +1273,181 @@ __device__ int first_outside_global(const int32_t *V, int n, const int32_t *b, i
     return -1;
 }
 
+// The quantities of a split pair that all its units share, found once per
+// pair by one workgroup (a unit used to find them itself, in four passes over
+// both whole rings read from memory, and the finish again): both rings' MBRs
+// and exact doubled areas, the anchors (P's first vertex strictly outside
+// Q's MBR, Q's extreme vertex outside P's MBR), the memberships of the ring
+// starts where there is no anchor, and Q's cross-product sum before each Q
+// window, written into the units' slots as their suffix-sum carry.  All are
+// exact integers, the same as the per-unit passes gave.  Rings of up to
+// kMetaThreads x kMetaU vertices take one round trip to memory a pass.
+constexpr int kMetaThreads = 512;
+constexpr int kMetaU = 8;
+
+__global__ __launch_bounds__(kMetaThreads) void k_wide_meta(const int32_t *__restrict__ dxy,
+                                                          const int32_t *__restrict__ qxy,
+                                                          const int64_t *__restrict__ qoff, HeavyWs hw)
+{
+    __shared__ unsigned long long sWin[kMultiUnits];   // Q's cross products per window of kWideCap edges
+    __shared__ unsigned long long sA[2];               // doubled areas of Q and P
+    __shared__ int32_t sBox[8];                        // MBRs of Q and P: min x, min y, max x, max y
+    __shared__ int32_t sIdx[5];                        // Q's extreme vertices, P's first vertex outside
+    __shared__ int32_t sOdd[2];                        // crossings of the two membership passes
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t count = min((int64_t)hw.count[2], (int64_t)kMultiCap);
+    for (int64_t s = blockIdx.x; s < count; s += gridDim.x) {
+        const MultiPair mp = hw.multi[s];
+        if (mp.c < 0) continue;
+        // the roles of k_refine_wide
+        const int64_t qa = qoff[mp.q];
+        const int mq = (int)(qoff[mp.q + 1] - qa);
+        const bool swap = mp.n > kWideCap && mp.n > mq;
+        const int2 *PW = reinterpret_cast<const int2 *>(swap ? qxy + 2 * qa : dxy + 2 * mp.pa);
+        const int2 *QW = reinterpret_cast<const int2 *>(swap ? dxy + 2 * mp.pa : qxy + 2 * qa);
+        const int n = swap ? mq : mp.n, m = swap ? mp.n : mq;
+        const int2 o = QW[0];
+        const SplitShape sh = split_shape(n, m);
+        const int len = max(n, m);
+        for (int i = tid; i < kMultiUnits; i += kMetaThreads) sWin[i] = 0;
+        if (tid < 2) { sA[tid] = 0; sOdd[tid] = 0; }
+        if (tid < 8) sBox[tid] = (tid & 3) < 2 ? INT32_MAX : INT32_MIN;
+        if (tid < 5) sIdx[tid] = INT32_MAX;
+        __syncthreads();
+        // MBRs, areas and Q's window sums (a wavefront's 64 edges lie in one window)
+        {
+            int32_t b[8] = {INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN};
+            int64_t aq = 0, ap = 0;
+            for (int base = 0; base < len; base += kMetaThreads * kMetaU) {
+                int2 qv[kMetaU], qw[kMetaU], pv[kMetaU], pw[kMetaU];
+#pragma unroll
+                for (int k = 0; k < kMetaU; k++) {
+                    const int i = base + k * kMetaThreads + tid;
+                    const int iq = min(i, m - 1), ip = min(i, n - 1);
+                    qv[k] = QW[iq]; qw[k] = QW[iq + 1 == m ? 0 : iq + 1];
+                    pv[k] = PW[ip]; pw[k] = PW[ip + 1 == n ? 0 : ip + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < kMetaU; k++) {
+                    const int i = base + k * kMetaThreads + tid;
+                    int64_t cq = 0;
+                    if (i < m) {
+                        b[0] = min(b[0], qv[k].x); b[1] = min(b[1], qv[k].y);
+                        b[2] = max(b[2], qv[k].x); b[3] = max(b[3], qv[k].y);
+                        cq = (int64_t)(qv[k].x - o.x) * (qw[k].y - o.y) - (int64_t)(qw[k].x - o.x) * (qv[k].y - o.y);
+                    }
+                    if (i < n) {
+                        b[4] = min(b[4], pv[k].x); b[5] = min(b[5], pv[k].y);
+                        b[6] = max(b[6], pv[k].x); b[7] = max(b[7], pv[k].y);
+                        ap += (int64_t)(pv[k].x - o.x) * (pw[k].y - o.y) - (int64_t)(pw[k].x - o.x) * (pv[k].y - o.y);
+                    }
+                    aq += cq;
+                    const int w0 = base + k * kMetaThreads + (tid & ~63);   // the wavefront's first edge
+                    if (sh.qs > 1 && w0 < m) {
+                        const int64_t ws = wave_sum_i64(cq);
+                        if (lane == 0) atomicAdd(&sWin[w0 / kWideCap], (unsigned long long)ws);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) b[j] = (j & 3) < 2 ? wmin(b[j]) : wmax(b[j]);
+            aq = wave_sum_i64(aq);
+            ap = wave_sum_i64(ap);
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    if ((j & 3) < 2) atomicMin(&sBox[j], b[j]);
+                    else atomicMax(&sBox[j], b[j]);
+                }
+                atomicAdd(&sA[0], (unsigned long long)aq);
+                atomicAdd(&sA[1], (unsigned long long)ap);
+            }
+        }
+        __syncthreads();
+        const int32_t qm[4] = {sBox[0], sBox[1], sBox[2], sBox[3]}, pm[4] = {sBox[4], sBox[5], sBox[6], sBox[7]};
+        const int64_t a2q = (int64_t)sA[0], a2p = (int64_t)sA[1];
+        int kp = 0, kq = 0, wkp = 0, wkq = 0;
+        if (a2p != 0 && a2q != 0) {
+            // Q's extreme vertices (the first of each side) and P's first
+            // vertex strictly outside Q's MBR
+            int32_t e[5] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+            for (int base = 0; base < len; base += kMetaThreads * kMetaU) {
+                int2 qv[kMetaU], pv[kMetaU];
+#pragma unroll
+                for (int k = 0; k < kMetaU; k++) {
+                    const int i = base + k * kMetaThreads + tid;
+                    qv[k] = QW[min(i, m - 1)];
+                    pv[k] = PW[min(i, n - 1)];
+                }
+#pragma unroll
+                for (int k = 0; k < kMetaU; k++) {
+                    const int i = base + k * kMetaThreads + tid;
+                    if (i < m) {
+                        if (qv[k].x == qm[0]) e[0] = min(e[0], i);
+                        if (qv[k].x == qm[2]) e[1] = min(e[1], i);
+                        if (qv[k].y == qm[1]) e[2] = min(e[2], i);
+                        if (qv[k].y == qm[3]) e[3] = min(e[3], i);
+                    }
+                    const bool out = (pv[k].x < qm[0]) | (pv[k].x > qm[2]) | (pv[k].y < qm[1]) | (pv[k].y > qm[3]);
+                    if (i < n && out) e[4] = min(e[4], i);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 5; j++) e[j] = wmin(e[j]);
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < 5; j++) atomicMin(&sIdx[j], e[j]);
+            }
+            __syncthreads();
+            const int ext[4] = {sIdx[0], sIdx[1], sIdx[2], sIdx[3]};
+            kq = anchor_q(qm, pm, ext);
+            kp = sIdx[4] == INT32_MAX ? -1 : sIdx[4];
+            if (kp < 0 || kq < 0) {
+                // without an anchor: P's vertex 0 (against Q + delta) and Q's
+                // vertex 0, the origin (plus delta, against P), by the
+                // crossing rule over the other ring's edges
+                const int2 p0 = make_int2(PW[0].x - o.x, PW[0].y - o.y), q0 = make_int2(0, 0);
+                bool op = false, oq = false;
+                for (int base = 0; base < len; base += kMetaThreads * kMetaU) {
+                    int2 qv[kMetaU], qw[kMetaU], pv[kMetaU], pw[kMetaU];
+#pragma unroll
+                    for (int k = 0; k < kMetaU; k++) {
+                        const int i = base + k * kMetaThreads + tid;
+                        const int iq = min(i, m - 1), ip = min(i, n - 1);
+                        qv[k] = QW[iq]; qw[k] = QW[iq + 1 == m ? 0 : iq + 1];
+                        pv[k] = PW[ip]; pw[k] = PW[ip + 1 == n ? 0 : ip + 1];
+                    }
+#pragma unroll
+                    for (int k = 0; k < kMetaU; k++) {
+                        const int i = base + k * kMetaThreads + tid;
+                        const int2 c = make_int2(qv[k].x - o.x, qv[k].y - o.y), d = make_int2(qw[k].x - o.x, qw[k].y - o.y);
+                        const int2 f = make_int2(pv[k].x - o.x, pv[k].y - o.y), g = make_int2(pw[k].x - o.x, pw[k].y - o.y);
+                        op ^= kp < 0 && i < m && flips_parity(c, d, p0, -1);
+                        oq ^= kq < 0 && i < n && flips_parity(f, g, q0, +1);
+                    }
+                }
+                const int cp = __popcll(__ballot(op)), cq = __popcll(__ballot(oq));
+                if (lane == 0) { atomicAdd(&sOdd[0], cp); atomicAdd(&sOdd[1], cq); }
+                __syncthreads();
+                if (kp < 0) { wkp = sOdd[0] & 1; kp = 0; }
+                if (kq < 0) { wkq = sOdd[1] & 1; kq = 0; }
+            }
+        }
+        if (tid == 0) {
+            MultiPair &out = hw.multi[s];
+            out.a2p = a2p; out.a2q = a2q; out.kp = kp; out.kq = kq; out.wkp = wkp; out.wkq = wkq;
+        }
+        for (int u = tid; u < mp.units; u += kMetaThreads) {
+            const int qw = sh.qs > 1 ? u % sh.qs : 0;
+            int64_t pre = 0;
+            for (int j = 0; j < qw; j++) pre += (int64_t)sWin[j];
+            hw.units[s * kMultiUnits + u].qpre = pre;
+        }
+        // every thread is done with the LDS before the next pair clears it
+        __syncthreads();
+    }
+}
+
 // Splits the recorded wide entries that split_shape splits, one thread per
 // entry: a split slot, then the units appended after the recorded entries
 // (the recorded entry is then marked unused).  A pair stays whole when the
@@ -1285,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_expand(const int64_t *__restrict__ qoff
         const WidePair w = hw.wide[i];
         const int mq = (int)(qoff[w.q + 1] - qoff[w.q]);
         const bool swap = w.n > kWideCap && w.n > mq;
-        const SplitShape sh = split_shape(swap ? mq : w.n, swap ? w.n : mq, hw.fine != 0);
+        const SplitShape sh = split_shape(swap ? mq : w.n, swap ? w.n : mq);
         if (sh.units <= 1) continue;
         const int ms = atomicAdd(hw.count + 2, 1);
         if (ms >= kMultiCap) continue;
@@ -1355,37 +1531,47 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
         const int64_t ox = Qg[0], oy = Qg[1];
         // windows of this entry: all, or one P window (and one Q window) of
         // a split pair
-        const SplitShape sh = split_shape(n, m, hw.fine != 0);
+        const SplitShape sh = split_shape(n, m);
         const int pfirst = w.pw < 0 ? 0 : w.pw * sh.plen;
         const int pend = w.pw < 0 ? n : min(n, pfirst + sh.plen);
         const int qfirst = w.qw < 0 ? 0 : w.qw * kWideCap;
         const int qend = w.qw < 0 ? m : min(m, qfirst + kWideCap);
-        int32_t qm[4], pm[4];
-        int64_t a2q, a2p, qpre, ppre;
-        ring_sums_global(Qg, m, ox, oy, qfirst, lane, qm, a2q, qpre);
-        ring_sums_global(Pg, n, ox, oy, 0, lane, pm, a2p, ppre);
+        const int u = w.qw < 0 ? w.pw : w.pw * sh.qs + w.qw;   // a split pair's unit slot
+        int64_t a2q, a2p, qpre;
+        int kp = 0, kq = 0, wkp = 0, wkq = 0;
+        if (w.pw >= 0) {
+            // a split pair's unit: the pair's own quantities from k_wide_meta
+            // (its ring starts' memberships are the finish's)
+            const MultiPair &mp = hw.multi[w.slot];
+            a2p = mp.a2p; a2q = mp.a2q; kp = mp.kp; kq = mp.kq;
+            qpre = hw.units[(int64_t)w.slot * kMultiUnits + u].qpre;
+        } else {
+            int32_t qm[4], pm[4];
+            int64_t ppre;
+            ring_sums_global(Qg, m, ox, oy, 0, lane, qm, a2q, qpre);
+            ring_sums_global(Pg, n, ox, oy, 0, lane, pm, a2p, ppre);
+            if (a2p != 0 && a2q != 0) {
+                // anchors: a vertex outside the other polygon's MBR has
+                // membership 0; without one, a crossing-number pass
+                int qext[4];
+                extremes_global(Qg, m, qm, lane, qext);
+                kq = anchor_q(qm, pm, qext);
+                kp = first_outside_global(Pg, n, qm, lane);
+                if (kp < 0) {
+                    const int2 p0 = make_int2((int)((int64_t)Pg[0] - ox), (int)((int64_t)Pg[1] - oy));
+                    wkp = member_point_global(Qg, m, ox, oy, p0, -1, lane);
+                    kp = 0;
+                }
+                if (kq < 0) {
+                    // Q's vertex 0 is the origin
+                    wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
+                    kq = 0;
+                }
+            }
+        }
         double J = 0.0;
-        MultiUnit unit{0.0, 0.0, 0, 0};
+        MultiUnit unit{0.0, 0.0, 0, 0, 0};
         if (a2p != 0 && a2q != 0) {
-            // anchors: a vertex outside the other polygon's MBR has
-            // membership 0; without one, a crossing-number pass (by the
-            // finish for a split pair)
-            int qext[4];
-            extremes_global(Qg, m, qm, lane, qext);
-            int kq = anchor_q(qm, pm, qext);
-            int kp = first_outside_global(Pg, n, qm, lane);
-            int wkp = 0, wkq = 0;
-            if (kp < 0 && w.pw < 0) {
-                const int2 p0 = make_int2((int)((int64_t)Pg[0] - ox), (int)((int64_t)Pg[1] - oy));
-                wkp = member_point_global(Qg, m, ox, oy, p0, -1, lane);
-                kp = 0;
-            }
-            if (kq < 0 && w.pw < 0) {
-                // Q's vertex 0 is the origin
-                wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
-            }
-            kp = max(kp, 0);
-            kq = max(kq, 0);
             RingLds Qs{sQv, sQbox, nullptr, sQsuf};
             RingLds Ps{sPv, sPbox, sPS, nullptr};
             double accP = 0.0, accQ = 0.0, accM = 0.0, accK = 0.0, T = 0.0, crs = 0.0;
@@ -1433,7 +1619,6 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
         }
         st_pairs += (w.pw <= 0) & (w.qw <= 0);
         if (lane == 0) {
-            const int u = w.qw < 0 ? w.pw : w.pw * sh.qs + w.qw;
             if (w.pw < 0) cand_j[w.c] = J;
             else hw.units[(int64_t)w.slot * kMultiUnits + u] = unit;
         }
@@ -1447,13 +1632,11 @@ __global__ __launch_bounds__(64) void k_refine_wide(const int32_t *__restrict__ 
     }
 }
 
-// One wavefront per split pair: the anchors' memberships, then the P
-// windows' sums (each the sum of its Q windows' units, one window a lane)
+// One wavefront per split pair: the P windows' sums (each the sum of its Q
+// windows' units, one window a lane)
 // with the crossing signs of the earlier windows carried into each, added in
 // a fixed order (deterministic), then J.
-__global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__restrict__ dxy,
-                                                            const int32_t *__restrict__ qxy,
-                                                            const int64_t *__restrict__ qoff,
+__global__ __launch_bounds__(256) void k_refine_multi_finish(const int64_t *__restrict__ qoff,
                                                             double *__restrict__ cand_j, HeavyWs hw)
 {
     const int lane = threadIdx.x & 63;
@@ -1462,33 +1645,16 @@ __global__ __launch_bounds__(256) void k_refine_multi_finish(const int32_t *__re
     for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; s < count; s += nw) {
         const MultiPair mp = hw.multi[s];
         if (mp.c < 0) continue;
-        // the roles of k_refine_wide
-        const int64_t qa = qoff[mp.q];
-        const int mq = (int)(qoff[mp.q + 1] - qa);
+        // the roles of k_refine_wide; the pair's own quantities from k_wide_meta
+        const int mq = (int)(qoff[mp.q + 1] - qoff[mp.q]);
         const bool swap = mp.n > kWideCap && mp.n > mq;
-        const int32_t *Pg = swap ? qxy + 2 * qa : dxy + 2 * mp.pa;
-        const int32_t *Qg = swap ? dxy + 2 * mp.pa : qxy + 2 * qa;
         const int n = swap ? mq : mp.n, m = swap ? mp.n : mq;
-        const int64_t ox = Qg[0], oy = Qg[1];
-        int32_t qm[4], pm[4];
-        int64_t a2q, a2p, pre;
-        ring_sums_global(Qg, m, ox, oy, 0, lane, qm, a2q, pre);
-        ring_sums_global(Pg, n, ox, oy, 0, lane, pm, a2p, pre);
+        const int64_t a2q = mp.a2q, a2p = mp.a2p;
         double J = 0.0;
         if (a2p != 0 && a2q != 0) {
-            int qext[4];
-            extremes_global(Qg, m, qm, lane, qext);
-            const int kq = anchor_q(qm, pm, qext);
-            int kp = first_outside_global(Pg, n, qm, lane);
-            int wkp = 0, wkq = 0;
-            if (kp < 0) {
-                const int2 p0 = make_int2((int)((int64_t)Pg[0] - ox), (int)((int64_t)Pg[1] - oy));
-                wkp = member_point_global(Qg, m, ox, oy, p0, -1, lane);
-                kp = 0;
-            }
-            if (kq < 0) wkq = member_point_global(Pg, n, ox, oy, make_int2(0, 0), +1, lane);
+            const int kp = mp.kp, wkp = mp.wkp, wkq = mp.wkq;
             const int sp = a2p > 0 ? 1 : -1, sq = a2q > 0 ? 1 : -1;
-            const SplitShape sh = split_shape(n, m, hw.fine != 0);
+            const SplitShape sh = split_shape(n, m);
             const int pk = kp / sh.plen;
             // lanes take the P windows, 64 at a time; the carry of crossing
             // signs into each is a scan in window order
@@ -1619,14 +1785,13 @@ size_t refine_workspace_bytes()
 polymh_status launch_refine(const polymh_polys *data, const polymh_polys *queries,
                             const int64_t *cand_off, const int32_t *cand_ids, int64_t nq,
                             int64_t n_cand, double *cand_j, hipStream_t s,
-                            unsigned long long *stats, void *ws, size_t ws_bytes, bool fine_split)
+                            unsigned long long *stats, void *ws, size_t ws_bytes)
 {
     if (n_cand == 0 || nq == 0) return POLYMH_OK;
     HeavyWs hw{};
     if (ws) {
         Carve cv{static_cast<char *>(ws), ws_bytes};
         hw = carve_heavy(cv);
-        hw.fine = fine_split ? 1 : 0;
         if (!cv.ok) return set_error(POLYMH_ECAPACITY, "refine: workspace of %zu bytes, need %zu", ws_bytes, cv.used);
         hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(kStatSlots * 4), 0, s, hw.count, hw.stat_slots);
     }
@@ -1649,12 +1814,14 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
     if (st || !ws) return st;
     hipLaunchKernelGGL(k_expand, dim3(64), dim3(256), 0, s, queries->offsets, hw);
     if ((st = check_launch("refine: split wide pairs"))) return st;
+    hipLaunchKernelGGL(k_wide_meta, dim3(512), dim3(kMetaThreads), 0, s, data->xy, queries->xy, queries->offsets,
+                       hw);
+    if ((st = check_launch("refine: split wide pairs"))) return st;
     // deferred wide tiled pairs: four one-wavefront workgroups per CU
     hipLaunchKernelGGL(k_refine_wide, dim3(1024), dim3(64), 0, s, data->xy, queries->xy, queries->offsets, cand_j,
                        hw, stats ? 1 : 0);
     if ((st = check_launch("refine: wide pairs"))) return st;
-    hipLaunchKernelGGL(k_refine_multi_finish, dim3(64), dim3(256), 0, s, data->xy, queries->xy, queries->offsets,
-                       cand_j, hw);
+    hipLaunchKernelGGL(k_refine_multi_finish, dim3(64), dim3(256), 0, s, queries->offsets, cand_j, hw);
     if ((st = check_launch("refine: split wide pairs"))) return st;
     // deferred heavy pairs: a grid that covers every (pair, side, slice) of a
     // full list in a few rounds, then the per-pair sums

@@ -459,13 +459,14 @@ def _subdivided_rect(x0, y0, x1, y1, k):
                            np.stack([np.full(k, x0), y1 - h * i // k], 1)]).astype(np.int64)
 
 
-def test_ranked_rounds_split_large_pairs_finer(pm):
-    """The early-stop rounds split pairs with very large polygons finer (P
-    windows of 128 edges for a staged polygon of 4,096 edges or more, up to
-    512 units a pair): 6,000-vertex squares (128-edge P windows, each with
-    one of the 6 Q windows), 9,000-vertex squares (256-edge windows) and
-    20,000-vertex squares (1,024-edge windows, each with one of the 20 Q
-    windows) give the exact J, as refine's coarser split does."""
+def test_ranked_rounds_split_large_pairs(pm):
+    """The early-stop rounds' refinement splits pairs with very large
+    polygons as refine does (P windows of 128 edges for a staged polygon of
+    4,096 edges or more, up to 512 units a pair): 6,000-vertex squares
+    (128-edge P windows, each with one of the 6 Q windows), 9,000-vertex
+    squares (256-edge windows) and 20,000-vertex squares (1,024-edge
+    windows, each with one of the 20 Q windows) give the exact J through
+    the ranked rounds, equal to refine's."""
     import torch
     L6, L9, L20 = 6000, 9000, 20000
     a6 = _subdivided_rect(0, 0, L6, L6, 1500)
@@ -599,20 +600,21 @@ def test_refine_windowed_degenerate_contacts(pm, orc):
 
 def test_refine_split_units_exact(pm):
     # exact J for pairs split into units of each shape: 6,000-vertex squares
-    # (P windows of 256 edges, each with one of the 6 Q windows), 9,000-vertex
-    # squares (P windows of 512 edges, each with one of the 9 Q windows:
-    # windows of 256 would give more than 256 units), 20,000-vertex squares
-    # (P windows of 256 edges walking all 20 Q windows: a unit per Q window
-    # would exceed the cap) and a 4-vertex rectangle against a 20,000-vertex
-    # square, either way round (one P window, each of the 20 Q windows a unit
-    # of its own); collinear overlaps, shared edges and a reversed ring
-    # included.  (The early-stop rounds split finer: see
-    # test_ranked_rounds_split_large_pairs_finer.)
+    # (P windows of 128 edges, each with one of the 6 Q windows), 9,000-vertex
+    # squares (P windows of 256 edges, each with one of the 9 Q windows:
+    # windows of 128 would give more than 512 units), 20,000-vertex squares
+    # (P windows of 1,024 edges, each with one of the 20 Q windows),
+    # 30,000-vertex squares (P windows of 128 edges walking all 30 Q windows:
+    # a unit per Q window would exceed the cap at any window length) and a
+    # 4-vertex rectangle against a 20,000-vertex square, either way round
+    # (one P window, each of the 20 Q windows a unit of its own); collinear
+    # overlaps, shared edges and a reversed ring included
     import torch
-    L6, L9, L20 = 6000, 9000, 20000
+    L6, L9, L20, L30 = 6000, 9000, 20000, 30000
     a6 = _subdivided_rect(0, 0, L6, L6, 1500)
     a9 = _subdivided_rect(0, 0, L9, L9, 2250)
     a20 = _subdivided_rect(0, 0, L20, L20, 5000)
+    a30 = _subdivided_rect(0, 0, L30, L30, 7500)
     small = dg.rectangle(1000, 1000, 3000, 5000)
     cases = [
         (a6, a6, Fraction(1)), (a6, _subdivided_rect(L6 // 2, 0, L6 // 2 + L6, L6, 1500), Fraction(1, 3)),
@@ -621,6 +623,7 @@ def test_refine_split_units_exact(pm):
         (a9, _subdivided_rect(L9, 0, 2 * L9, L9, 2250), Fraction(0)),
         (a20, a20, Fraction(1)),
         (a20, _subdivided_rect(L20 // 2, 0, L20 // 2 + L20, L20, 5000), Fraction(1, 3)),
+        (a30, _subdivided_rect(L30 // 2, 0, L30 // 2 + L30, L30, 7500), Fraction(1, 3)),
         (small, a20, Fraction(2000 * 4000, L20 * L20)),
         (a20, small, Fraction(2000 * 4000, L20 * L20)),
     ]
