@@ -909,7 +909,8 @@ struct WidePair {
 struct MultiPair {
     int64_t c;            // candidate slot (-1: the pair was not deferred)
     int64_t pa;
-    int32_t n, q, units, pad;
+    int32_t n, q, units;
+    int32_t first;        // list position of its first unit (k_wide_meta writes the units there)
     // the pair's own quantities, written by k_wide_meta for its units and
     // the finish (P and Q in k_refine_wide's roles)
     int64_t a2p, a2q;     // exact doubled areas
@@ -1281,8 +1282,11 @@ __device__ int first_outside_global(const int32_t *V, int n, const int32_t *b, i
 // starts where there is no anchor, and Q's cross-product sum before each Q
 // window, written into the units' slots as their suffix-sum carry.  All are
 // exact integers, the same as the per-unit passes gave.  Rings of up to
-// kMetaThreads x kMetaU vertices take one round trip to memory a pass.
-constexpr int kMetaThreads = 512;
+// kMetaThreads x kMetaU vertices take one round trip to memory a pass.  The
+// workgroup also writes the pair's unit entries at the list positions
+// k_expand reserved (one thread each, where a thread of k_expand wrote them
+// all in turn).
+constexpr int kMetaThreads = 1024;
 constexpr int kMetaU = 8;
 
 __global__ __launch_bounds__(kMetaThreads) void k_wide_meta(const int32_t *__restrict__ dxy,
@@ -1442,6 +1446,12 @@ __global__ __launch_bounds__(kMetaThreads) void k_wide_meta(const int32_t *__res
             int64_t pre = 0;
             for (int j = 0; j < qw; j++) pre += (int64_t)sWin[j];
             hw.units[s * kMultiUnits + u].qpre = pre;
+            WidePair e;
+            e.c = mp.c; e.pa = mp.pa; e.n = mp.n; e.q = mp.q;
+            e.pw = (int16_t)(u / sh.qs);
+            e.qw = (int16_t)(sh.qs == 1 ? -1 : qw);
+            e.slot = (int32_t)s;
+            hw.wide[mp.first + u] = e;
         }
         // every thread is done with the LDS before the next pair clears it
         __syncthreads();
@@ -1449,8 +1459,9 @@ __global__ __launch_bounds__(kMetaThreads) void k_wide_meta(const int32_t *__res
 }
 
 // Splits the recorded wide entries that split_shape splits, one thread per
-// entry: a split slot, then the units appended after the recorded entries
-// (the recorded entry is then marked unused).  A pair stays whole when the
+// entry: a split slot and the list positions of its units, appended after the
+// recorded entries (k_wide_meta writes the units there; the recorded entry is
+// then marked unused).  A pair stays whole when the
 // split slots run out; when its units do not fit the list, the positions it
 // claimed are marked unused and its slot is dropped.
 __global__ __launch_bounds__(256) void k_expand(const int64_t *__restrict__ qoff, HeavyWs hw)
@@ -1472,14 +1483,7 @@ __global__ __launch_bounds__(256) void k_expand(const int64_t *__restrict__ qoff
             mp.c = -1;
             continue;
         }
-        mp.c = w.c; mp.pa = w.pa; mp.n = w.n; mp.q = w.q; mp.units = sh.units; mp.pad = 0;
-        for (int u = 0; u < sh.units; u++) {
-            WidePair e = w;
-            e.pw = (int16_t)(u / sh.qs);
-            e.qw = (int16_t)(sh.qs == 1 ? -1 : u % sh.qs);
-            e.slot = ms;
-            hw.wide[base + u] = e;
-        }
+        mp.c = w.c; mp.pa = w.pa; mp.n = w.n; mp.q = w.q; mp.units = sh.units; mp.first = (int32_t)base;
         hw.wide[i].c = -1;
     }
 }
@@ -1814,7 +1818,7 @@ polymh_status launch_refine(const polymh_polys *data, const polymh_polys *querie
     if (st || !ws) return st;
     hipLaunchKernelGGL(k_expand, dim3(64), dim3(256), 0, s, queries->offsets, hw);
     if ((st = check_launch("refine: split wide pairs"))) return st;
-    hipLaunchKernelGGL(k_wide_meta, dim3(512), dim3(kMetaThreads), 0, s, data->xy, queries->xy, queries->offsets,
+    hipLaunchKernelGGL(k_wide_meta, dim3(256), dim3(kMetaThreads), 0, s, data->xy, queries->xy, queries->offsets,
                        hw);
     if ((st = check_launch("refine: split wide pairs"))) return st;
     // deferred wide tiled pairs: four one-wavefront workgroups per CU
