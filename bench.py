@@ -71,7 +71,7 @@ def parse():
                     help="first-round sizes tried for the early stop (comma list)")
     ap.add_argument("--rank-rounds-grid", type=lambda x: [int(v) for v in x.split(",")], default=[1, 2, 3, 4],
                     help="early-stop round counts tried (rounds of F, F, 2F, 4F, ... before the finishing pass)")
-    ap.add_argument("--scorer-head", type=int, default=16, help="candidates per query the network re-scores")
+    ap.add_argument("--scorer-head", type=int, default=8, help="candidates per query the network re-scores")
     ap.add_argument("--head-parts", type=int, default=4,
                     help="sub-batches of the ranked methods' batch run concurrently in its graph (streams forked "
                          "inside)")
