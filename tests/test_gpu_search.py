@@ -608,7 +608,9 @@ def test_refine_split_units_exact(pm):
     # a unit per Q window would exceed the cap at any window length) and a
     # 4-vertex rectangle against a 20,000-vertex square, either way round
     # (one P window, each of the 20 Q windows a unit of its own); collinear
-    # overlaps, shared edges and a reversed ring included
+    # overlaps, shared edges and a reversed ring included; and flat chains
+    # (zero area, J = 0) of 6,000 and 9,000 vertices inside a square's MBR,
+    # the data polygon staged as P in the first and as Q in the second
     import torch
     L6, L9, L20, L30 = 6000, 9000, 20000, 30000
     a6 = _subdivided_rect(0, 0, L6, L6, 1500)
@@ -616,6 +618,10 @@ def test_refine_split_units_exact(pm):
     a20 = _subdivided_rect(0, 0, L20, L20, 5000)
     a30 = _subdivided_rect(0, 0, L30, L30, 7500)
     small = dg.rectangle(1000, 1000, 3000, 5000)
+
+    def flat(n):
+        x = np.concatenate([2 * np.arange(n // 2), 2 * (n // 2) - 1 - 2 * np.arange(n // 2)])
+        return np.stack([x, np.full(n, 3000)], 1).astype(np.int64)
     cases = [
         (a6, a6, Fraction(1)), (a6, _subdivided_rect(L6 // 2, 0, L6 // 2 + L6, L6, 1500), Fraction(1, 3)),
         (a9, a9, Fraction(1)), (a9, a9[::-1], Fraction(1)),
@@ -626,6 +632,7 @@ def test_refine_split_units_exact(pm):
         (a30, _subdivided_rect(L30 // 2, 0, L30 // 2 + L30, L30, 7500), Fraction(1, 3)),
         (small, a20, Fraction(2000 * 4000, L20 * L20)),
         (a20, small, Fraction(2000 * 4000, L20 * L20)),
+        (flat(6000), a6, Fraction(0)), (flat(9000), a6, Fraction(0)),
     ]
     D = pm.to_device(dg.from_list([c[0] for c in cases]))
     Q = pm.to_device(dg.from_list([c[1] for c in cases]))
