@@ -332,11 +332,12 @@ polymh_status polymh_refine(const polymh_polys *data, const polymh_polys *querie
  *   - with coordinate spans below 2^26, it takes the tiled form of the
  *     smaller pairs (only edges whose boxes meet are tested), both polygons
  *     passing through on-chip memory in windows of 1024 edges; a pair
- *     spanning more than two window pairs is split into up to 256 units of
- *     one wavefront each (windows of 256 to 1024 edges of the staged
+ *     spanning more than two window pairs is split into up to 512 units of
+ *     one wavefront each (windows of 128 to 1024 edges of the staged
  *     polygon, each against the other's windows together or one at a
- *     time), and the partial sums are added in window order (up to 2^20
- *     list entries and 4096 split pairs per call);
+ *     time), whose shared quantities (areas, anchors, carries) are found
+ *     once per pair, and the partial sums are added in window order (up to
+ *     2^20 list entries and 4096 split pairs per call);
  *   - with wider spans (128-bit signs), a pair with n m >= 2^17 edge pairs
  *     is split over 128 wavefronts of the general form (up to 8192 pairs),
  * so the few large pairs of a batch no longer set the call's duration.  The
