@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--rank-rounds-grid", type=lambda x: [int(v) for v in x.split(",")], default=[1, 2, 3, 4],
                     help="early-stop round counts tried (rounds of F, F, 2F, 4F, ... before the finishing pass)")
     ap.add_argument("--scorer-head", type=int, default=8, help="candidates per query the network re-scores")
+    ap.add_argument("--query-order", choices=("morton", "given"), default="morton",
+                    help="order the headline batches run their queries in (results come back in the given order)")
     ap.add_argument("--head-parts", type=int, default=4,
                     help="sub-batches of the ranked methods' batch run concurrently in its graph (streams forked "
                          "inside)")
@@ -209,7 +211,8 @@ def headline(args):
                         parts=args.plain_parts if method == "plain" else args.head_parts, sign_config=cfgq,
                         binned=par5, method=method, dsig=sig5, dpacked=dpk5,
                         scorer=scorer, dfeat=dfeat, head=args.scorer_head, F=args.rank_F_grid[0],
-                        rounds=args.rank_rounds_grid[-1], margin=float("inf") if method == "plain" else 0.0)
+                        rounds=args.rank_rounds_grid[-1], margin=float("inf") if method == "plain" else 0.0,
+                        query_order=args.query_order)
         qb.load(w5.queries)
         margin, tried = float("inf"), []
         if method != "plain":
@@ -257,15 +260,34 @@ def headline(args):
         rec = metrics.recall_at_k(ti[evq], tj[evq], bi[evq], bj[evq], 10)
         cnt = qb.counts.cpu().numpy() if method != "plain" else np.array([n_cand, 0])
         stages = qb.run_instrumented()
+        given_ms = None
+        if args.query_order != "given":
+            # the same captured batch with the queries in their given order
+            # (reloaded into the same buffers, so the graph stays valid)
+            qb.query_order = "given"
+            qb.load(w5.queries)
+            for _ in range(args.warmup):
+                qb.run_graph()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                qb.run_graph()
+            torch.cuda.synchronize()
+            given_ms = 1e3 * (time.perf_counter() - t1) / args.steps
+            qb.query_order = args.query_order
+            qb.load(w5.queries)
+            qb.run_graph()
+            qb.result()
         methods[method] = {"margin": margin, "F": qb.F if method != "plain" else None,
                            "rounds": qb.rounds if method != "plain" else None, "operating_points": tried,
                            "recall_at_10": rec, "recall_queries": int(evq.size),
                            "queries_per_s": nq / dt, "ms_per_batch": 1e3 * dt,
                            "refined_pairs_per_query": float(cnt[0]) / nq, "finished_by_fallback": int(cnt[1]),
-                           "stage_ms": stages}
+                           "stage_ms": stages, "ms_per_batch_given_order": given_ms}
         log(f"{method}: F {qb.F}, rounds {qb.rounds}, margin {margin}, recall@10 {rec:.4f} on {evq.size} held-out queries, "
             f"{1e3 * dt:.2f} ms per {nq}-query graph replay ({nq / dt:.3g} q/s), "
-            f"{float(cnt[0]) / nq:.1f} refined pairs/query; stages " +
+            f"{float(cnt[0]) / nq:.1f} refined pairs/query" +
+            (f" ({given_ms:.2f} ms in the given query order)" if given_ms is not None else "") + "; stages " +
             ", ".join(f"{a} {b:.3f}" for a, b in stages.items()))
         batches[method] = qb
     # -- what any scorer could gain here: the same ranked refinement with the
@@ -328,10 +350,13 @@ def headline(args):
     out = {
         "workload": "workload 5: 4,000,000 star polygons, Pareto(1.5) 8-8192 vertices, R 0.5-3% of a 2^24 grid; "
                     f"k=256, cap 2^26; {nq:,} queries per captured-graph batch (2% jitter; ranked methods as "
-                    f"{args.head_parts} sub-batches on streams forked inside the graph), "
+                    f"{args.head_parts} sub-batches on streams forked inside the graph"
+                    + ("; queries run in the Morton order of their MBR centres, set when the batch is loaded, "
+                       "results returned in the given order" if args.query_order == "morton" else "") + "), "
                     f"{B} x {R} bands, learned scorer + early-stop refinement",
         "n_data": D5.n, "n_queries": nq, "k": k, "cap": cap, "bands": B, "rows": R,
         "scorer_head": args.scorer_head, "sub_batches": args.head_parts, "plain_sub_batches": args.plain_parts,
+        "query_order": args.query_order,
         "binned": {**par5, "lds_edges": cfgb.lds_edges},
         "candidates_per_query": n_cand / nq, "queries_over_4096_candidates": n_long, "index_ms": 1e3 * t_index,
         "saturated_table_ms": 1e3 * t_pack,

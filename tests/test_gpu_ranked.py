@@ -375,6 +375,50 @@ def test_ranked_batch_graph_equals_eager(pm, setup, method):
         del qb
 
 
+@pytest.mark.parametrize("method,parts", [("plain", 1), ("jhat", 4), ("scorer", 2)])
+def test_split_batch_morton_order_equals_given(pm, setup, method, parts):
+    """The batch run in the Morton order of its queries (the parts hold
+    stretches of the curve) returns every query's top-10 in the given order,
+    equal to the given-order batch's, eagerly and on graph replays, and the
+    early stop's counts are the same."""
+    import torch
+    from paper_2511_16576_amd import scorer as sc
+    from paper_2511_16576_amd.pipeline import SplitBatch, spatial_order
+    w, D = setup["w"], setup["D"]
+    feats = pm.poly_features(D, w.box)
+    s = sc.init_scorer(0)
+    cap = int(setup["ids"].numel()) * 2 + 1024
+    packed = pm.sig_pack(setup["sig"]) if method != "plain" else None
+    common = dict(box=w.box, seed=0, k=256, cap=w.cap, bands=64, rows=4, n_queries=w.queries.n,
+                  max_vertices=w.queries.xy.shape[0], cand_cap=cap, method=method, dsig=setup["sig"], scorer=s,
+                  dfeat=feats, head=8, F=4, rounds=3, margin=float("inf") if method == "plain" else 0.02,
+                  dpacked=packed, parts=parts)
+    given = SplitBatch(D, setup["sk"], setup["se"], **common)
+    given.load(w.queries)
+    given.run_eager()
+    w_ids, w_j = (x.clone() for x in given.result())
+    z = SplitBatch(D, setup["sk"], setup["se"], query_order="morton", **common)
+    z.load(w.queries)
+    perm = spatial_order(w.queries)
+    assert np.array_equal(z.perm, perm) and not np.array_equal(perm, np.arange(w.queries.n))
+    # the first part holds the queries the curve visits first
+    first = w.queries.subset(perm[:z.bounds[0][1]])
+    assert np.array_equal(z.parts[0].off.cpu().numpy(), first.offsets)
+    z.run_eager()
+    e_ids, e_j = z.result()
+    assert torch.equal(e_ids, w_ids) and torch.equal(e_j, w_j)
+    if method != "plain":
+        assert torch.equal(z.counts, given.counts)
+    z.capture()
+    for rep in range(2):
+        for p in z.parts:
+            p.top_ids.fill_(-7)
+        torch.cuda.synchronize()
+        z.run_graph()
+        g_ids, g_j = z.result()
+        assert torch.equal(g_ids, w_ids) and torch.equal(g_j, w_j), rep
+
+
 @pytest.mark.parametrize("method,parts", [("plain", 3), ("jhat", 4), ("scorer", 2)])
 def test_split_batch_equals_whole(pm, setup, method, parts):
     """The batch run as sub-batches of consecutive queries on their own
