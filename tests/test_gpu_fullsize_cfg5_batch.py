@@ -1,12 +1,13 @@
 """Workload 5's query batch at full size, in the launch configuration the
 benchmark times: 4,000,000 polygons signed from binned samples, 64 x 4
-bands, 10,000 queries signed from binned samples, looked up and refined as
-four sub-batches on streams forked inside one captured graph, ordered by
+bands, 10,000 queries in the Morton order of their MBR centres signed from
+binned samples, looked up and refined as four sub-batches (stretches of the
+curve) on streams forked inside one captured graph, ordered by
 the collision fraction (read from the saturated signature table) with early
 stop (first rounds of 16, 4 rounds, margin 0.01), and beside it the plain
-batch (every candidate refined, one graph).  For five sampled queries of
-every sub-batch (its first and last among them, and one of 257 to 2,048
-vertices) the oracle recomputes, one by one: the query's signature and
+batch (every candidate refined, one graph, the same order).  For five
+sampled queries of every sub-batch (its first and last among them, and one
+of 257 to 2,048 vertices) the oracle recomputes, one by one: the query's signature and
 band keys; the signatures of all its candidates (bit-exact against the
 indexed rows and their rows of the saturated table; each shares a band key
 with the query, the list is ascending and free of repeats, and none of
@@ -75,12 +76,15 @@ def test_query_batch_workload5_full_size(orc, state):
     nq, k, cap = w.queries.n, w.k, w.cap
     cand_cap = state["cand_cap"]
     jb = SplitBatch(*args, parts=PARTS, method="jhat", F=F, rounds=ROUNDS, margin=MARGIN, dpacked=packed,
-                    **common)
+                    query_order="morton", **common)
     jb.load(w.queries)
     jb.capture()
-    pb = SplitBatch(*args, parts=1, method="plain", **common)
+    pb = SplitBatch(*args, parts=1, method="plain", query_order="morton", **common)
     pb.load(w.queries)
     pb.capture()
+    # both batches hold query perm[r] in row r; results come back in the given order
+    perm = jb.perm
+    assert np.array_equal(pb.perm, perm) and np.array_equal(np.sort(perm), np.arange(nq))
     for _ in range(2):
         jb.run_graph()
         pb.run_graph()
@@ -90,15 +94,15 @@ def test_query_batch_workload5_full_size(orc, state):
 
     rng = np.random.default_rng(51)
     nv = np.diff(w.queries.offsets)
-    # per sub-batch its first and last query, two at random and one at
-    # random among those of 257 to 2,048 vertices (the longest rings are
+    # rows of each sub-batch: its first and last, two at random and one at
+    # random among queries of 257 to 2,048 vertices (the longest rings are
     # left out so the oracle's fan clipping of whole lists stays short; they
     # have refinement tests of their own)
     sample = []
     for a, b in jb.bounds:
         pool = np.arange(a + 1, b - 1)
         sample += [a, b - 1] + rng.choice(pool, 2, replace=False).tolist()
-        long_ = pool[(nv[pool] > 256) & (nv[pool] <= 2048)]
+        long_ = pool[(nv[perm[pool]] > 256) & (nv[perm[pool]] <= 2048)]
         if long_.size:
             sample.append(int(rng.choice(long_)))
     others = np.sort(rng.choice(w.data.n, 2000, replace=False))
@@ -106,10 +110,11 @@ def test_query_batch_workload5_full_size(orc, state):
     gsig = sig.cpu().numpy().view(np.uint32)
     gpk = packed.cpu().numpy().view(np.uint16)
     assert (gsig >= 65535).any(), "values of 65535 and more: the comparison reads full values"
-    for q in sample:
+    for row in sample:
         t1 = time.time()
-        p = int(np.searchsorted([b for _, b in jb.bounds], q, side="right"))
-        part, lq = jb.parts[p], q - jb.bounds[p][0]
+        q = int(perm[row])
+        p = int(np.searchsorted([b for _, b in jb.bounds], row, side="right"))
+        part, lq = jb.parts[p], row - jb.bounds[p][0]
         o = part.cand_off.cpu().numpy()
         a, b = int(o[lq]), int(o[lq + 1])
         cand = part.cand_ids[a:b].cpu().numpy()
@@ -128,7 +133,7 @@ def test_query_batch_workload5_full_size(orc, state):
         assert not (okeys[outside] == oqk[None, :]).any(), q
         pl = pb.parts[0]
         po = pl.cand_off.cpu().numpy()
-        assert np.array_equal(pl.cand_ids[int(po[q]):int(po[q + 1])].cpu().numpy(), cand), q
+        assert np.array_equal(pl.cand_ids[int(po[row]):int(po[row + 1])].cpu().numpy(), cand), q
         # collision fractions and the best-first order
         pred = oracle.collision_fraction(oq[0], osig).astype(np.float32)
         assert np.array_equal(part.score[a:b].cpu().numpy(), pred), q
@@ -145,27 +150,28 @@ def test_query_batch_workload5_full_size(orc, state):
         Jall = orc.jaccard_candidates(w.data, one, np.array([0, cand.size]), cand)
         ti, tj = oracle.topk(np.array([0, cand.size]), cand, Jall, 10)
         _assert_top_equal(p_ids[q], p_j[q], ti[0], tj[0], ("plain", q))
-        print(f"query {q} (sub-batch {p}, {nv[q]} vertices): {cand.size} candidates, {r['refined']} refined by "
+        print(f"query {q} (row {row}, sub-batch {p}, {nv[q]} vertices): {cand.size} candidates, {r['refined']} refined by "
               f"the early stop; checked in {time.time() - t1:.1f}s", flush=True)
     del jb, pb
 
 
 # the learned batch as the benchmark runs it: the network re-scores each
-# query's first 16 candidates by collision fraction, the order is rebuilt,
-# then rounds of 24 (two rounds, margin -0.3)
-HEAD, F_L, ROUNDS_L, MARGIN_L = 16, 24, 2, -0.3
+# query's first 8 candidates by collision fraction, the order is rebuilt,
+# then one round of 22 (margin -0.3) and the finishing pass
+HEAD, F_L, ROUNDS_L, MARGIN_L = 8, 22, 1, -0.3
 
 
 def test_learned_batch_workload5_full_size(orc, state):
-    """The learned batch in the benchmark's launch configuration (a seeded
-    network: its arithmetic, not its training, is under test).  For sampled
-    queries: the head slots are the collision-fraction order's first 16; their
+    """The learned batch in the benchmark's launch configuration (queries in
+    Morton order; a seeded network: its arithmetic, not its training, is
+    under test).  For sampled queries: the head slots are the
+    collision-fraction order's first 8; their
     new scores are the oracle's FP64 network on the oracle's feature rows
     (within the BF16 rounding between the layers), the other scores the
     oracle's collision fractions exactly; the rebuilt order sorts the final
     scores (desc, position asc); and the top-10 is the exact top-10 (the
-    oracle's J) of the first 24 or 48 candidates of that order, or of the
-    whole list."""
+    oracle's J) of the first 22 candidates of that order (every query that
+    stops after its round), or of the whole list (the finishing pass)."""
     import torch
     from oracle import mlp as om
     from paper_2511_16576_amd import polymh as pm
@@ -176,8 +182,9 @@ def test_learned_batch_workload5_full_size(orc, state):
     net = sc.init_scorer(5)
     dfeat = pm.poly_features(D, w.box)
     lb = SplitBatch(*state["args"], parts=PARTS, method="scorer", scorer=net, dfeat=dfeat, head=HEAD, F=F_L,
-                    rounds=ROUNDS_L, margin=MARGIN_L, dpacked=packed, **state["common"])
+                    rounds=ROUNDS_L, margin=MARGIN_L, dpacked=packed, query_order="morton", **state["common"])
     lb.load(w.queries)
+    perm = lb.perm
     lb.capture()
     for _ in range(2):
         lb.run_graph()
@@ -190,10 +197,11 @@ def test_learned_batch_workload5_full_size(orc, state):
     sample = []
     for a, b in lb.bounds:
         sample += [a, b - 1] + rng.choice(np.arange(a + 1, b - 1), 2, replace=False).tolist()
-    for q in sample:
+    for row in sample:
         t1 = time.time()
-        pi = int(np.searchsorted([b for _, b in lb.bounds], q, side="right"))
-        part, lq = lb.parts[pi], q - lb.bounds[pi][0]
+        q = int(perm[row])
+        pi = int(np.searchsorted([b for _, b in lb.bounds], row, side="right"))
+        part, lq = lb.parts[pi], row - lb.bounds[pi][0]
         o = part.cand_off.cpu().numpy()
         a, b = int(o[lq]), int(o[lq + 1])
         cand = part.cand_ids[a:b].cpu().numpy()
@@ -202,7 +210,7 @@ def test_learned_batch_workload5_full_size(orc, state):
         pred = oracle.collision_fraction(oq[0], osig).astype(np.float32)
         jorder, _ = oracle.best_first(pred)
         assert np.array_equal(part.order[a:b].cpu().numpy(), jorder), q
-        # the head slots: the first 16 of the collision-fraction order
+        # the head slots: the first 8 of the collision-fraction order
         nh = min(HEAD, cand.size)
         hc = part.hc[lq * HEAD:(lq + 1) * HEAD].cpu().numpy()
         hid = part.hid[lq * HEAD:(lq + 1) * HEAD].cpu().numpy()
@@ -224,13 +232,15 @@ def test_learned_batch_workload5_full_size(orc, state):
         one = w.queries.subset([q])
         Jall = orc.jaccard_candidates(w.data, one, np.array([0, cand.size]), cand)
         fits = []
-        for r in (F_L, 2 * F_L, cand.size):
+        # candidates refined after each round (F, then F 2^(r-1)), or all
+        reach = np.cumsum([F_L if r < 2 else F_L << (r - 1) for r in range(ROUNDS_L)]).tolist()
+        for r in reach + [cand.size]:
             sel = forder[:r]
             ti, tj = oracle.topk(np.array([0, sel.size]), cand[sel], Jall[sel], 10)
             if np.allclose(l_j[q], tj[0], rtol=REL, atol=ABS):
                 fits.append(r)
                 _assert_top_equal(l_ids[q], l_j[q], ti[0], tj[0], ("learned", q, r))
         assert fits, q
-        print(f"query {q} (sub-batch {pi}): {cand.size} candidates, top-10 of the first {fits[0]} refined; "
+        print(f"query {q} (row {row}, sub-batch {pi}): {cand.size} candidates, top-10 of the first {fits[0]} refined; "
               f"checked in {time.time() - t1:.1f}s", flush=True)
     del lb
