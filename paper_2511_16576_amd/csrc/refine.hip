@@ -415,9 +415,12 @@ __device__ void stage_ring_mbr(const int32_t *src, int n, int pad_to, int64_t ox
         const bool live = i < pad_to, edge = i < n;
         const int2 p = base == 0 ? pf.p[0] : base == 64 ? pf.p[1] : v[edge ? i : 0];
         const int2 q = base == 0 ? pf.q[0] : base == 64 ? pf.q[1] : v[i + 1 < n ? i + 1 : 0];
-        const int64_t px = (int64_t)p.x - ox, py = (int64_t)p.y - oy;
-        if (live) R.v[i] = make_int2((int)px, (int)py);
-        a2 += edge ? px * ((int64_t)q.y - oy) - ((int64_t)q.x - ox) * py : 0;
+        // relative coordinates in 32 bits (wrapping): exact unless the pair
+        // spans 2^26 or more, whose area the caller takes from elsewhere
+        const int px = (int)((uint32_t)p.x - (uint32_t)ox), py = (int)((uint32_t)p.y - (uint32_t)oy);
+        const int qx = (int)((uint32_t)q.x - (uint32_t)ox), qy = (int)((uint32_t)q.y - (uint32_t)oy);
+        if (live) R.v[i] = make_int2(px, py);
+        a2 += edge ? (int64_t)px * qy - (int64_t)qx * py : 0;
         x0 = min(x0, p.x); y0 = min(y0, p.y); x1 = max(x1, p.x); y1 = max(y1, p.y);
         const bool out = edge & ((p.x < qb[0]) | (p.x > qb[2]) | (p.y < qb[1]) | (p.y > qb[3]));
         const uint64_t mk = __ballot(out);
