@@ -455,7 +455,11 @@ __device__ void chunk_boxes_p(RingLds R, int n, int lane)
     const int nc = (n + 7) >> 3;
 #pragma unroll
     for (int c0 = 0; c0 < MAXC; c0 += 64) {
-        const int c = c0 + lane;
+        int c = c0 + lane;
+        // recomputed here rather than hoisted out of a caller's loop over
+        // pairs, where the compiler would keep 8 c + 1 and 8 c + 8 live in
+        // registers (or spill them) across the whole pair
+        asm volatile("" : "+v"(c));
         if (c < nc) {
             const int e1 = min(n, 8 * c + 8);
             int2 p[9];
@@ -644,6 +648,10 @@ __device__ __forceinline__ void sweep_units(RingLds P, RingLds Q, int entry, int
     for (int i = 0; i < 9; i++) pv[i] = P.v[e0 + i];
     double ax = (double)pv[0].x, ay = (double)pv[0].y;
     double rx = cx - ax, ry = cy - ay;
+    // orient(c, d, a) of the chunk's first vertex; each edge's end value
+    // orient(c, d, b) = that - X is the next edge's start value (all exact
+    // integers below 2^53, so carrying it equals recomputing it)
+    double oa = __fma_rn(fy, rx, -(fx * ry));
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         const int2 b = pv[i + 1];
@@ -651,7 +659,6 @@ __device__ __forceinline__ void sweep_units(RingLds P, RingLds Q, int entry, int
         const double ex = bx - ax, ey = by - ay;
         const double thr = p_edge_threshold(ex, ey);
         const double oc = __fma_rn(ex, ry, -(ey * rx));
-        const double oa = __fma_rn(fy, rx, -(fx * ry));
         const double X = __fma_rn(ex, fy, -(ey * fx));
         const double od = oc + X, ob = oa - X;
         const bool p1 = oc > thr, p2 = od > thr;
@@ -672,6 +679,7 @@ __device__ __forceinline__ void sweep_units(RingLds P, RingLds Q, int entry, int
         }
         ax = bx; ay = by;
         rx = cx - bx; ry = cy - by;
+        oa = ob;
     }
 }
 
