@@ -236,12 +236,14 @@ def headline(args):
                 qb.margin = m_ok
                 qb.capture()
                 ts = []
-                for _ in range(5):
+                # two untimed replays, then the median of ten
+                for r in range(12):
                     torch.cuda.synchronize()
                     t1 = time.perf_counter()
                     qb.run_graph()
                     qb.stream.synchronize()
-                    ts.append(time.perf_counter() - t1)
+                    if r >= 2:
+                        ts.append(time.perf_counter() - t1)
                 tried.append({"F": F, "rounds": rounds, "margin": m_ok, "ms": 1e3 * float(np.median(ts))})
             best = min(tried, key=lambda x: x["ms"])
             qb.F, qb.rounds, margin = best["F"], best["rounds"], best["margin"]
