@@ -13,6 +13,7 @@
 #include "internal.hpp"
 #include "scorer_common.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace polymh {
@@ -90,6 +91,49 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
             g.outf[o] = d;
             g.outb[o] = to_bf16(d);
         }
+    }
+}
+
+// Split-K form of the product for the weight gradients, whose M x N output
+// is a few dozen tiles while K is the whole batch (one wavefront a tile
+// would leave the chip nearly idle): split s (blockIdx.y) reduces over
+// [s kc, min(K, (s + 1) kc)) and writes its partial tile to part[s][M][N];
+// k_split_sum then adds the splits in order, so the result is deterministic.
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_part(GemmArgs g, int64_t kc, float *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t tiles_n = g.N / 32;
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (tile >= (g.M / 32) * tiles_n) return;
+    const int64_t i0 = (tile / tiles_n) * 32, j0 = (tile % tiles_n) * 32;
+    const int64_t row = i0 + (lane & 31), col = j0 + (lane & 31);
+    const int64_t kl = 8 * (lane >> 5);
+    const int64_t k_lo = (int64_t)blockIdx.y * kc, k_hi = min(g.K, k_lo + kc);
+    f32x16 acc = {};
+    for (int64_t k0 = k_lo; k0 < k_hi; k0 += 16) {
+        const bf16x8 a = frag<AKC>(g.A, row, k0 + kl);
+        const bf16x8 b = frag<BKC>(g.B, col, k0 + kl);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    float *out = part + (int64_t)blockIdx.y * g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int64_t i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        out[i * g.N + col] = acc[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_split_sum(const float *__restrict__ part, int nsplit, int64_t M,
+                                                   int64_t N, float *__restrict__ out, int64_t ldo)
+{
+    const int64_t mn = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int s = 0; s < nsplit; s++) v += part[s * mn + e];
+        const int64_t i = e / N;
+        out[i * ldo + (e - i * N)] = v;
     }
 }
 
@@ -222,6 +266,31 @@ polymh_status gemm(const GemmArgs &g, hipStream_t s)
     return check_launch("mlp gemm");
 }
 
+// At most kMaxSplit splits of at least kMinSplitK reduction steps each.
+constexpr int kMaxSplit = 64, kMinSplitK = 256;
+
+// The product as split-K with plain FP32 stores (the weight gradients);
+// part holds kMaxSplit x M x N floats.
+polymh_status gemm_split(const GemmArgs &g, float *part, hipStream_t s)
+{
+    const int64_t tiles = (g.M / 32) * (g.N / 32);
+    if (tiles == 0) return POLYMH_OK;
+    int64_t kc = (g.K + kMaxSplit - 1) / kMaxSplit;
+    kc = std::max<int64_t>(kMinSplitK, (kc + 15) / 16 * 16);
+    const int nsplit = (int)std::max<int64_t>(1, (g.K + kc - 1) / kc);
+    const dim3 grid((unsigned)((tiles + 3) / 4), (unsigned)nsplit), block(256);
+    const bool akc = g.A.sk == 1, bkc = g.B.sk == 1;
+    if (akc && bkc) hipLaunchKernelGGL((k_gemm_part<true, true>), grid, block, 0, s, g, kc, part);
+    else if (akc) hipLaunchKernelGGL((k_gemm_part<true, false>), grid, block, 0, s, g, kc, part);
+    else if (bkc) hipLaunchKernelGGL((k_gemm_part<false, true>), grid, block, 0, s, g, kc, part);
+    else hipLaunchKernelGGL((k_gemm_part<false, false>), grid, block, 0, s, g, kc, part);
+    polymh_status st = check_launch("mlp gemm (split)");
+    if (st) return st;
+    hipLaunchKernelGGL(k_split_sum, dim3(grid_of(g.M * g.N, 256)), dim3(256), 0, s, part, nsplit, g.M, g.N,
+                       g.outf, g.ldo);
+    return check_launch("mlp gemm (split sum)");
+}
+
 }  // namespace
 
 // Parameter block (FP32 master): W1[256][288], b1[256], W2[256][256], b2[256], w3[256], b3.
@@ -305,11 +374,12 @@ polymh_status launch_mlp_forward(const uint16_t *X, int64_t B, const float *para
 
 // Loss and parameter gradient of one batch (the forward must have run on the
 // same X and acts).  grad [kNParams] is overwritten; loss (device float) is
-// overwritten with the batch MSE.  scratch: dz3 [B], dz2/dz1 fp32 and bf16.
+// overwritten with the batch MSE.  scratch: dz3 [B], dz2/dz1 fp32 and bf16,
+// the weight gradients' split-K partials.
 size_t mlp_backward_scratch_bytes(int64_t B)
 {
     return align_up((size_t)B * 4, 256) + 2 * align_up((size_t)B * kHid * 4, 256) +
-           2 * align_up((size_t)B * kHid * 2, 256) + 256;
+           2 * align_up((size_t)B * kHid * 2, 256) + align_up((size_t)kMaxSplit * kHid * kIn * 4, 256) + 256;
 }
 
 polymh_status launch_mlp_backward(const uint16_t *X, int64_t B, const float *params,
@@ -323,7 +393,8 @@ polymh_status launch_mlp_backward(const uint16_t *X, int64_t B, const float *par
     float *dz2f = reinterpret_cast<float *>(c); c += align_up((size_t)B * kHid * 4, 256);
     float *dz1f = reinterpret_cast<float *>(c); c += align_up((size_t)B * kHid * 4, 256);
     __bf16 *dz2b = reinterpret_cast<__bf16 *>(c); c += align_up((size_t)B * kHid * 2, 256);
-    __bf16 *dz1b = reinterpret_cast<__bf16 *>(c);
+    __bf16 *dz1b = reinterpret_cast<__bf16 *>(c); c += align_up((size_t)B * kHid * 2, 256);
+    float *part = reinterpret_cast<float *>(c);
     const __bf16 *x = reinterpret_cast<const __bf16 *>(X);
     const __bf16 *w2 = reinterpret_cast<const __bf16 *>(wbf16) + (int64_t)kHid * kIn;
 
@@ -341,7 +412,7 @@ polymh_status launch_mlp_backward(const uint16_t *X, int64_t B, const float *par
     g.A = Operand{dz2b, 1, kHid};
     g.B = Operand{a.h1, 1, kHid};
     g.M = kHid; g.N = kHid; g.K = B; g.epi = kStoreF32; g.outf = grad + kOffW2; g.ldo = kHid;
-    if ((st = gemm(g, s))) return st;
+    if ((st = gemm_split(g, part, s))) return st;
     hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, dz2f, B, kHid, grad + kOffB2);
     // dz1 = (dz2 W2) * gelu'(z1)
     g.A = Operand{dz2b, kHid, 1};
@@ -353,7 +424,7 @@ polymh_status launch_mlp_backward(const uint16_t *X, int64_t B, const float *par
     g.A = Operand{dz1b, 1, kHid};
     g.B = Operand{x, 1, kIn};
     g.M = kHid; g.N = kIn; g.K = B; g.epi = kStoreF32; g.outf = grad + kOffW1; g.ldo = kIn;
-    if ((st = gemm(g, s))) return st;
+    if ((st = gemm_split(g, part, s))) return st;
     hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, dz1f, B, kHid, grad + kOffB1);
     return check_launch("mlp backward");
 }

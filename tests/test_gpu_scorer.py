@@ -78,15 +78,17 @@ def test_forward_matches_oracle(pm):
     assert np.all(np.abs(y - a["y"]) <= 0.25 * 2 ** -7 * S3 + 1e-6)
 
 
-def test_backward_matches_oracle(pm):
+@pytest.mark.parametrize("B", [128, 2048])
+def test_backward_matches_oracle(pm, B):
     """Every gradient entry against the oracle's chain rule through the
     mixed-precision network (BF16 activations and backward operands where
     the kernels store them): FP32 accumulation and an occasional BF16
     rounding that falls the other way (the GPU rounds FP32 values, the
     oracle FP64 ones) move an entry by at most a BF16 rounding (2^-7) of the
-    sum of the absolute values of its terms."""
+    sum of the absolute values of its terms.  At 2,048 rows the weight
+    gradients' reduction over the batch runs as eight splits added in
+    order."""
     import torch
-    B = 128
     p, X, lab, params, wbf16, Xg, labg = _setup(pm, B, seed=1)
     acts, scratch = pm.mlp_buffers(B)
     pm.mlp_forward(Xg, params, wbf16, acts)
@@ -103,6 +105,10 @@ def test_backward_matches_oracle(pm):
     assert bad.size == 0, (bad[:10], err[bad[:10]], tol[bad[:10]])
     # the bound is tight enough to matter: typical entries agree far closer
     assert np.median(err / np.maximum(S, 1e-30)) < 2 ** -12
+    # the splits are added in a fixed order: a second call gives the same bits
+    grad2 = torch.empty_like(params)
+    pm.mlp_backward(Xg, params, wbf16, acts, labg, grad2, loss, scratch)
+    assert torch.equal(grad2, grad)
 
 
 def test_adam_matches_oracle(pm):
